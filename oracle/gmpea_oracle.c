@@ -298,11 +298,12 @@ static double orc_clip(double v, double lo, double hi) {
   return v;
 }
 
-/* R8: bounded polynomial mutation of y in [lo, hi] when wB < tpm (integer test);
- * the conditional uniform is floor(wB 2^24 / tpm) 2^-24 (exact in both precisions). */
+/* R8: bounded polynomial mutation of y in [lo, hi] when wB < tpm (integer test,
+ * bit-exact on both sides); given that, wB is uniform on [0, tpm) and the
+ * conditional uniform is u = wB / tpm in the working precision. */
 double orc_pm_dim(double y, double lo, double hi, uint32_t wB, uint64_t tpm, double eta_m) {
   if ((uint64_t)wB >= tpm) return y;
-  double u = (double)((((uint64_t)wB) << 24) / tpm) * (1.0 / 16777216.0);
+  double u = (double)wB / (double)tpm;
   double span = hi - lo;
   double mpow = 1.0 / (eta_m + 1.0);
   double dq;

@@ -79,7 +79,7 @@ def _python_offspring(o, k):
                     c = (1 + beta) / 2 * a[l] + (1 - beta) / 2 * b[l]
                 c = min(max(c, lb[l]), ub[l])
                 if wB < tpm:
-                    u = ((wB << 24) // tpm) / 2.0**24
+                    u = wB / tpm
                     span = ub[l] - lb[l]
                     if u < 0.5:
                         dq = (2 * u + (1 - 2 * u) * (1 - (c - lb[l]) / span) ** (eta_m + 1)) ** (1 / (eta_m + 1)) - 1

@@ -60,9 +60,8 @@ def test_pm_identity_when_probability_zero(oracle_core):
 
 
 def test_pm_zero_step_at_half(oracle_core):
-    tpm = int(math.floor(0.1 * 2**32))
-    wB = (tpm + 1) // 2  # floor(wB 2^24 / tpm) = 2^23, so u = 0.5
-    assert ((wB << 24) // tpm) == 1 << 23
+    tpm = 2 * 214748364  # even, so wB = tpm / 2 gives u = 0.5 exactly
+    wB = tpm // 2
     for y in (0.0, 0.2, 0.5, 0.999, 1.0):
         assert oracle_core.pm_dim(y, 0.0, 1.0, wB, tpm, 20.0) == y
 
