@@ -1,0 +1,175 @@
+"""Throughput of full GMPEA generations on one MI355X.
+
+A step is one generation of the whole hot path over both populations of the
+large synthetic workload: m = 3, d = 100, N = 100,128 reference vectors per
+population (Das-Dennis, H = 446), T = 32 (t1 = 16, t2 = 64), four ring
+constraints plus the equality x1 + x2 = 1 (tolerance 1e-4), FP32 on device.
+Inputs are resident in HBM before timing starts; the timed region is K
+generations enqueued back to back (hipGraph replay of generation chunks)
+between two device synchronisations.
+
+Prints one JSON line with the value (offspring evaluated + selected per
+second = 2 N K / t), the roofline of the dominant kernel (per-kernel HIP-event
+timing on the stream the kernels run on, algorithmic bytes from the bytes
+model), and the CPU oracle timed on a bounded sample on this host.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "offspring evaluated+selected/sec (FP32) and % HBM roofline; batched vs plain speedup at equal IGD"
+HBM_PEAK_GBS = 8000.0
+KERNEL_SRC = os.path.join(ROOT, "paper_2509_19821_amd", "csrc", "gmpea_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_large.json")
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def bytes_model(n, m, d, t, rho):
+    """Algorithmic bytes per launch of each kernel (FP32 / int32 words; each item
+    counted once at the level the method must move it).
+      vary:   parent row (d, each row read once per generation), offspring row
+              write (d), offspring F/CV write (m + 1), two mating picks
+      op1:    both offspring F/CV read (2 (m + 1)), weight (m), both new
+              offspring F/CV written (2 (m + 1)) -- per subproblem
+      select: parent F/CV (m + 1), weight (m), reverse list (t_p entries),
+              candidate F/CV once per offspring (m + 1); winners: offspring row
+              read + parent row write (2 d) and F/CV write (m + 1), times rho_p"""
+    vary = sum(n * 4 * (2 * d + (m + 1) + 2) for _ in range(2))
+    op1 = n * 4 * (4 * (m + 1) + m)
+    select = sum(n * 4 * ((m + 1) + m + t[p] + (m + 1)) + rho[p] * n * 4 * (2 * d + (m + 1))
+                 for p in range(2))
+    return {"vary": vary, "op1": op1, "select": select}
+
+
+def kernel_hash():
+    with open(KERNEL_SRC, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch from committed rocprofv3 FETCH_SIZE / WRITE_SIZE runs,
+    only if they were taken on the kernel source as it is now."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_src_sha256_16") != kernel_hash():
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("bytes_per_launch")
+
+
+def cpu_baseline(target_s=12.0):
+    """The oracle as it stands, on the large workload's shape at a bounded
+    population (N = 50,086 per population), timed over whole generations."""
+    import cmop_inputs as ci
+    from oracle import core
+    prob, cfg, _ = ci.workload_large(0)
+    cfg = dict(cfg, n_req=50000)
+    cores = core.set_threads(0)
+    o = core.Oracle(prob, cfg)
+    o.step()  # first generation off the clock
+    gens, t0 = 0, time.perf_counter()
+    while True:
+        o.step()
+        gens += 1
+        el = time.perf_counter() - t0
+        if el >= target_s or gens >= 200:
+            break
+    return {"value": 2.0 * o.N * gens / el, "unit": "offspring/s", "cores": int(cores),
+            "kind": "oracle",
+            "sample": "large-workload shape (m=3, d=100, T=32, 4 rings + equality) at N=%d per "
+                      "population, %d generations after one warm-up, FP64, OpenMP over "
+                      "subproblems" % (o.N, gens)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--profile-gens", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build runs each instance on a single "
+              "MI355X (instances shard across GPUs without communication); run with --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import cmop_inputs as ci
+    import paper_2509_19821_amd as g
+
+    torch.cuda.set_device(0)
+    prob, cfg, K_total = ci.workload_large(0)
+    log("bench: init large workload")
+    t0 = time.perf_counter()
+    gp = g.Gmpea(prob, cfg)
+    torch.cuda.synchronize()
+    log("bench: init %.2f s, N=%d t=%s" % (time.perf_counter() - t0, gp.n, gp.t))
+    n, m, d = gp.n, gp.m, gp.d
+
+    gp.step(args.warmup)
+    torch.cuda.synchronize()
+    log("bench: warmup done")
+    r0 = gp.info()["replaced"]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gp.step(args.steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    r1 = gp.info()["replaced"]
+    value = 2.0 * n * args.steps / el
+    rho = [(r1[p] - r0[p]) / (n * args.steps) for p in range(2)]
+    log("bench: %d generations in %.3f s (%.1f us/gen), rho=%s" % (args.steps, el,
+                                                                   1e6 * el / args.steps, rho))
+
+    ms = gp.profile(args.profile_gens)
+    model = bytes_model(n, m, d, gp.t, rho)
+    dom = max(ms, key=ms.get)
+    achieved = model[dom] / (ms[dom] * 1e-3) / 1e9
+    traffic = measured_traffic(dom)
+    log("bench: per-kernel ms %s; model bytes %s" % (ms, model))
+    gen_bytes = sum(model.values())
+    roof = {"bound": "hbm", "kernel": "k_" + dom, "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic, "algorithmic_bytes_per_launch": int(model[dom]),
+            "avg_launch_ms": round(ms[dom], 5),
+            "per_kernel_ms": {k: round(v, 5) for k, v in ms.items()},
+            "generation_gbs": round(gen_bytes / (sum(ms.values()) * 1e-3) / 1e9, 1),
+            "rho": [round(r, 4) for r in rho]}
+    gp.close()
+
+    out = {"metric": METRIC, "value": round(value, 1), "unit": "offspring/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": round(1e3 * el / args.steps, 5), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "large: m=3, d=100, N=%d per population (2 populations), "
+                                  "T=32 (t1=16, t2=64), 4 rings + equality x1+x2=1 (tol 1e-4), "
+                                  "%d generations in the full solve" % (n, K_total),
+                      "global_batch": 2 * n, "parallelism": "single GPU"},
+           "roofline": roof}
+    if not args.no_cpu_baseline:
+        log("bench: timing the CPU oracle")
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,226 @@
+/*
+ * gmpea.h — C ABI of the MI355X (gfx950) GMPEA library.
+ *
+ * GMPEA is the decomposition-based, two-population constrained multiobjective
+ * evolutionary algorithm of Huang et al., arXiv 2509.19821. One generation
+ * (Alg. 1 loop body and Alg. 2) runs on the GPU for every subproblem of both
+ * populations: neighbourhood mating, SBX + polynomial mutation, evaluation of
+ * F and CV, the ideal-point update, OP1 offspring cooperation and the OP2/OP3
+ * constraint-aware neighbour replacement.
+ *
+ * Conventions shared by every call:
+ *  - Every call returns gmpea_status; no exception crosses the ABI. On an
+ *    error, outputs are left unchanged and gmpea_last_error() explains.
+ *  - Host pointers are plain C arrays owned by the caller. Device memory is
+ *    owned by the handle and obtained through the caller's allocator hook
+ *    (hipMalloc when none is given).
+ *  - The device computes in FP32; FP64 problem constants are rounded once.
+ *  - Population rows are in ascending subproblem order. Subproblem i is the
+ *    i-th Das-Dennis reference vector in lexicographic order.
+ *  - A handle is used by one host thread at a time; separate handles are
+ *    independent and may share a stream.
+ */
+#ifndef GMPEA_H
+#define GMPEA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gmpea_s *gmpea_t; /* opaque; owns the device memory of one instance */
+
+typedef enum {
+  GMPEA_OK = 0,
+  GMPEA_EINVAL = -1,      /* invalid argument (sizes, bounds, NULL where required) */
+  GMPEA_ENOMEM = -2,      /* the allocator hook (or hipMalloc) returned no memory */
+  GMPEA_EHIP = -3,        /* a HIP runtime call failed */
+  GMPEA_ECAPACITY = -4,   /* an output buffer is too small; *count holds the need */
+  GMPEA_ESTATE = -5,      /* handle destroyed or not in a usable state */
+  GMPEA_EUNSUPPORTED = -6 /* valid request outside what this build implements */
+} gmpea_status;
+
+/* Problem families (objective functions of the synthetic CMOPs). */
+enum {
+  GMPEA_FAMILY_CURVE = 0, /* m = 2: f1 = x1, g = 1 + 9 mean(x2..xd), f2 = g (1 - sqrt(f1/g)) */
+  GMPEA_FAMILY_SPHERE = 1 /* m in {2, 3}: F = (1 + g) s(angles pi x_l / 2, l < m),
+                             g = sum_{l >= m} (x_l - 0.5)^2; s is the unit sphere octant */
+};
+
+/* Aggregation (Eq. (7) and its Tchebycheff alternative named beside it). */
+enum {
+  GMPEA_AGG_PBI = 0, /* d1 + theta d2 with a unit reference direction; theta = 5 by default */
+  GMPEA_AGG_TCHE = 1 /* max_k w_k |f_k - z_k| */
+};
+
+/* What gmpea_front returns. */
+enum {
+  GMPEA_FRONT_FEASIBLE_ND = 0, /* feasible (CV = 0) non-dominated rows of population 1 (Eq. (5)) */
+  GMPEA_FRONT_POP1 = 1,        /* every row of population 1 (the output of Alg. 1) */
+  GMPEA_FRONT_POP2 = 2         /* every row of population 2 */
+};
+
+/* Buffers reachable through gmpea_read / gmpea_write. Host layouts:
+ *   X      N x d  float   decision vectors of population `pop`
+ *   F      N x m  float   objectives
+ *   CV     N      float   total constraint violation (Eq. (3))
+ *   XOFF, FOFF, CVOFF     the last generation's offspring of population `pop`
+ *                         (before OP1), same layouts; read only
+ *   Z      m      float   ideal point (shared by both populations); pop ignored
+ *   GEN    1      int64   generations completed; pop ignored
+ *   W      N x m  float   reference vectors (read only; pop ignored)
+ *   B      N x t  int32   neighbourhood of population `pop` (read only)
+ *   MATE   N x 2  int32   last generation's parent rows of population `pop`
+ *   OP1    N      uint8   1 if population `pop`'s new offspring i came from the
+ *                         other population in OP1 (Eq. (11))
+ *   WIN    N      int32   last generation's winner per parent slot (offspring
+ *                         index, -1 = parent kept)
+ *   MATE and WIN exist only when gmpea_config.record is nonzero. */
+enum {
+  GMPEA_BUF_X = 0,
+  GMPEA_BUF_F = 1,
+  GMPEA_BUF_CV = 2,
+  GMPEA_BUF_XOFF = 3,
+  GMPEA_BUF_FOFF = 4,
+  GMPEA_BUF_CVOFF = 5,
+  GMPEA_BUF_Z = 6,
+  GMPEA_BUF_GEN = 7,
+  GMPEA_BUF_W = 8,
+  GMPEA_BUF_B = 9,
+  GMPEA_BUF_MATE = 10,
+  GMPEA_BUF_OP1 = 11,
+  GMPEA_BUF_WIN = 12
+};
+
+#define GMPEA_MAX_M 3     /* objectives supported by this build */
+#define GMPEA_MAX_RING 8  /* ring constraints supported by this build */
+
+/* A CMOP instance (Eq. (1)): minimise F(x) over the box [lb, ub]^d subject to
+ *   ring:     r_j^2 - ||F(x) - a_j||^2 <= 0          (j < n_ring)
+ *   linear:   sum_lower - sum_k f_k(x) <= 0         (if has_sum_lower)
+ *   equality: x1 + x2 - 1 = 0, violation max(0, |h| - eq_tol)  (if n_eq = 1; Eq. (2))
+ * CV is the sum of the violations (Eq. (3)). All pointers are host memory,
+ * read during gmpea_init only. */
+typedef struct {
+  int32_t family, m, d;
+  const double *lb, *ub;      /* d each; NULL means [0, 1]^d; need lb < ub */
+  int32_t n_ring;             /* 0 .. GMPEA_MAX_RING */
+  const double *ring_center;  /* n_ring x m, row-major */
+  const double *ring_radius;  /* n_ring */
+  int32_t has_sum_lower;
+  double sum_lower;
+  int32_t n_eq;               /* 0 or 1 */
+  double eq_tol;              /* delta of Eq. (2); the paper's typical value is 1e-6 */
+} gmpea_problem;
+
+/* Method parameters (Alg. 1 inputs and the experimental settings). Zero means
+ * the paper's default where one exists. */
+typedef struct {
+  int32_t n_req;   /* requested reference vectors per population; the library uses
+                      the smallest Das-Dennis count N >= n_req (needs n_req >= 2) */
+  int32_t T;       /* base neighbourhood size: t1 = T/2, t2 = 2T unless set below */
+  int32_t t1, t2;  /* population 1 (small) and population 2 (large) neighbourhoods */
+  int32_t agg;     /* GMPEA_AGG_PBI (default) or GMPEA_AGG_TCHE */
+  double theta;    /* PBI penalty; 0 means 5 */
+  double eta_c;    /* SBX distribution index; 0 means 20 */
+  double eta_m;    /* PM distribution index; 0 means 20 */
+  double pc;       /* SBX probability per offspring; 0 means 1 */
+  double pm;       /* PM probability per variable; 0 means 1/d */
+  uint64_t seed;   /* key of the counter RNG: every random draw is a function of
+                      (seed, generation, population, subproblem, variable) */
+  int32_t record;  /* nonzero: keep MATE and WIN of the last generation */
+} gmpea_config;
+
+/* Device allocator hook. alloc returns device memory (or NULL), free releases
+ * it; ctx is passed through. A handle frees everything it allocated with the
+ * same hook. */
+typedef struct {
+  void *(*alloc)(size_t bytes, void *ctx);
+  void (*free)(void *ptr, void *ctx);
+  void *ctx;
+} gmpea_allocator;
+
+typedef struct {
+  int32_t n;          /* N, rows per population */
+  int32_t m, d;
+  int32_t t1, t2;
+  int32_t H;          /* Das-Dennis divisions */
+  int64_t generation; /* generations completed */
+  float z[GMPEA_MAX_M];
+  int64_t replaced[2];   /* parent slots replaced, summed over all generations */
+  double feasible_frac;  /* share of population 1 with CV = 0 */
+  size_t device_bytes;   /* device memory held by the handle */
+} gmpea_info;
+
+/* Create an instance: build the reference vectors W (Das-Dennis lattice), the
+ * neighbourhoods B1/B2 (t nearest reference vectors, self first, ties by index)
+ * and their reverse lists, draw the two initial populations uniformly in the box,
+ * evaluate them and set the ideal point to their minimum (Alg. 1 initialisation).
+ * hip_stream: a hipStream_t, or NULL for a stream owned by the handle. Work is
+ * enqueued on that stream; the call returns once the handle is ready.
+ * Errors: EINVAL (bad sizes: m, d < 2 for the curve family, lb >= ub, t > N,
+ * n_ring out of range, ...), EUNSUPPORTED (m > GMPEA_MAX_M), ENOMEM, EHIP. */
+gmpea_status gmpea_init(const gmpea_problem *problem, const gmpea_config *config,
+                        const gmpea_allocator *allocator, void *hip_stream, gmpea_t *out);
+
+/* Enqueue n_gen generations (Alg. 1 loop body) on the handle's stream and
+ * return without waiting. n_gen = 0 is a no-op. Errors: EINVAL (n_gen < 0), EHIP. */
+gmpea_status gmpea_step(gmpea_t h, int32_t n_gen);
+
+/* Run up to max_gen generations, stopping at the first generation boundary at
+ * or after time_limit_s seconds of wall time (the paper's fixed-time protocol;
+ * <= 0 means no limit), then synchronise. *gens_done (may be NULL) receives the
+ * generations run by this call. A limit already reached runs none. */
+gmpea_status gmpea_run(gmpea_t h, int32_t max_gen, double time_limit_s, int32_t *gens_done);
+
+/* Copy rows of the current populations to the host (synchronises). For
+ * GMPEA_FRONT_FEASIBLE_ND: the feasible rows of population 1 that no other
+ * feasible row dominates (Eq. (5)); identical objective vectors are all kept.
+ * x: capacity x d, f: capacity x m, cv: capacity, idx: capacity (subproblem
+ * indices, ascending); any of them may be NULL. *count receives the row count;
+ * if it exceeds capacity nothing is copied and ECAPACITY is returned. */
+gmpea_status gmpea_front(gmpea_t h, int32_t what, int32_t capacity, float *x, float *f,
+                         float *cv, int32_t *idx, int32_t *count);
+
+/* Sizes, generation count, ideal point and counters (synchronises). */
+gmpea_status gmpea_get_info(gmpea_t h, gmpea_info *info);
+
+/* Copy a buffer (see GMPEA_BUF_*) to host memory of `count` elements of its
+ * host type; count must equal the buffer's element count. Synchronises. */
+gmpea_status gmpea_read(gmpea_t h, int32_t buffer, int32_t pop, void *host, int64_t count);
+
+/* Overwrite X, F, CV (of population `pop`), Z or GEN from host memory, e.g. to
+ * resume from a checkpoint taken with gmpea_read: since every random draw is a
+ * function of (seed, generation, ...), restoring X, F, CV of both populations,
+ * Z and GEN resumes the run bit-exactly. Synchronises. Other buffers: EINVAL. */
+gmpea_status gmpea_write(gmpea_t h, int32_t buffer, int32_t pop, const void *host,
+                         int64_t count);
+
+/* Release the handle and its device memory (waits for its work). NULL is a no-op. */
+void gmpea_destroy(gmpea_t h);
+
+/* Message of the last error on this host thread (library-owned string). */
+const char *gmpea_last_error(void);
+
+/* Run n_gen generations one launch at a time with HIP events recorded on the
+ * handle's stream around every kernel, and return each kernel's mean duration in
+ * milliseconds: ms[0] variation + evaluation + ideal point, ms[1] offspring
+ * cooperation (OP1), ms[2] neighbour replacement (OP2 + OP3). The generations
+ * are real (the state advances). Synchronises. */
+gmpea_status gmpea_profile(gmpea_t h, int32_t n_gen, float *ms);
+
+/* The counter RNG every draw of the method uses (reading R5 of the design
+ * notes): Philox4x32-10 of Salmon et al. (SC'11). n blocks: out[4i..4i+3] =
+ * Philox(ctr[4i..4i+3], key = (seed low word, seed high word)). ctr and out are
+ * device pointers; the call enqueues on hip_stream (NULL: legacy default) and
+ * synchronises. */
+gmpea_status gmpea_philox(const uint32_t *ctr, int64_t n, uint64_t seed, uint32_t *out,
+                          void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GMPEA_H */

@@ -1,0 +1,10 @@
+"""MI355X-native GMPEA (arXiv 2509.19821): one generation of the two-population
+constrained multiobjective evolutionary algorithm in hand-written HIP for gfx950,
+behind the C ABI declared in include/gmpea.h.
+
+The Python module is a thin ctypes binding: every step of the generation runs
+in the library's kernels. Importing fails loudly when the library is not built
+(run ``python -m paper_2509_19821_amd.build`` or ``__graft_entry__.build()``).
+"""
+from .gmpea import (AGG_PBI, AGG_TCHE, BUF, FAMILY_CURVE, FAMILY_SPHERE, FRONT_FEASIBLE_ND,  # noqa: F401
+                    FRONT_POP1, FRONT_POP2, Gmpea, GmpeaError, lib, lib_path, philox)

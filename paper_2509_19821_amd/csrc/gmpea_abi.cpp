@@ -1,0 +1,721 @@
+// Host runtime of the GMPEA library: handle, device memory through the caller's
+// allocator hook, stream, hipGraph replay of generation chunks, and the C ABI
+// declared in include/gmpea.h.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdlib>
+#include <mutex>
+#include <string>
+#include <unordered_set>
+#include <vector>
+
+#include "gmpea.h"
+#include "gmpea_internal.hpp"
+
+using namespace gmpea;
+
+namespace {
+
+thread_local std::string g_err;
+
+gmpea_status fail(gmpea_status s, const std::string &msg) {
+  g_err = msg;
+  return s;
+}
+
+gmpea_status hip_fail(hipError_t e, const char *what) {
+  return fail(GMPEA_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+}  // namespace
+
+struct gmpea_s {
+  gmpea_allocator al{};
+  bool hook = false;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  DevState st{};
+  int32_t H = 0;
+  bool record = false;
+  std::vector<std::pair<void *, size_t>> allocs;
+  size_t bytes = 0;
+  std::vector<float> w_raw;      // N x m reference vectors (host copy)
+  std::vector<int32_t> b_host[2];
+  // graph replay of `gchunk` generations
+  hipGraphExec_t gexec = nullptr;
+  int32_t gchunk = 0;
+  int32_t graph_chunk_cfg = 16;
+};
+
+namespace {
+
+void *dev_alloc(gmpea_s *h, size_t bytes) {
+  void *p = nullptr;
+  bytes = std::max<size_t>(bytes, 256);
+  if (h->hook) {
+    p = h->al.alloc(bytes, h->al.ctx);
+  } else if (hipMalloc(&p, bytes) != hipSuccess) {
+    p = nullptr;
+  }
+  if (p) {
+    h->allocs.emplace_back(p, bytes);
+    h->bytes += bytes;
+  }
+  return p;
+}
+
+void dev_free(gmpea_s *h, void *p) {
+  for (size_t q = 0; q < h->allocs.size(); ++q) {
+    if (h->allocs[q].first == p) {
+      h->bytes -= h->allocs[q].second;
+      h->allocs.erase(h->allocs.begin() + static_cast<long>(q));
+      break;
+    }
+  }
+  if (h->hook)
+    h->al.free(p, h->al.ctx);
+  else
+    (void)hipFree(p);
+}
+
+void release_all(gmpea_s *h) {
+  if (h->gexec) {
+    (void)hipGraphExecDestroy(h->gexec);
+    h->gexec = nullptr;
+  }
+  while (!h->allocs.empty()) dev_free(h, h->allocs.back().first);
+  if (h->own_stream && h->stream) {
+    (void)hipStreamDestroy(h->stream);
+    h->stream = nullptr;
+  }
+}
+
+// Live handles: a destroyed (or never created) handle is rejected with ESTATE
+// without touching freed memory.
+std::mutex g_live_mu;
+std::unordered_set<const gmpea_s *> g_live;
+
+bool valid(gmpea_t h) {
+  std::lock_guard<std::mutex> lk(g_live_mu);
+  return h != nullptr && g_live.count(h) != 0;
+}
+
+void register_live(gmpea_s *h, bool on) {
+  std::lock_guard<std::mutex> lk(g_live_mu);
+  if (on)
+    g_live.insert(h);
+  else
+    g_live.erase(h);
+}
+
+template <class T>
+T *alloc_n(gmpea_s *h, size_t n) {
+  return static_cast<T *>(dev_alloc(h, n * sizeof(T)));
+}
+
+gmpea_status sync(gmpea_s *h, const char *what) {
+  hipError_t e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_fail(e, what);
+  return GMPEA_OK;
+}
+
+gmpea_status validate(const gmpea_problem *P, const gmpea_config *C) {
+  if (!P || !C) return fail(GMPEA_EINVAL, "gmpea_init: problem and config are required");
+  if (P->m < 2) return fail(GMPEA_EINVAL, "gmpea_init: m must be at least 2");
+  if (P->m > GMPEA_MAX_M) return fail(GMPEA_EUNSUPPORTED, "gmpea_init: m above GMPEA_MAX_M");
+  if (P->family != GMPEA_FAMILY_CURVE && P->family != GMPEA_FAMILY_SPHERE)
+    return fail(GMPEA_EINVAL, "gmpea_init: unknown problem family");
+  if (P->family == GMPEA_FAMILY_CURVE && (P->m != 2 || P->d < 2))
+    return fail(GMPEA_EINVAL, "gmpea_init: the curve family needs m = 2 and d >= 2");
+  if (P->family == GMPEA_FAMILY_SPHERE && P->d < P->m - 1)
+    return fail(GMPEA_EINVAL, "gmpea_init: the sphere family needs d >= m - 1");
+  if (P->d < 1 || P->d > (1 << 20)) return fail(GMPEA_EINVAL, "gmpea_init: d out of range");
+  if (P->n_eq && P->d < 2) return fail(GMPEA_EINVAL, "gmpea_init: the equality needs d >= 2");
+  if (P->n_ring < 0 || P->n_ring > GMPEA_MAX_RING)
+    return fail(GMPEA_EINVAL, "gmpea_init: n_ring out of range");
+  if (P->n_ring > 0 && (!P->ring_center || !P->ring_radius))
+    return fail(GMPEA_EINVAL, "gmpea_init: ring constants missing");
+  if (P->n_eq != 0 && P->n_eq != 1) return fail(GMPEA_EINVAL, "gmpea_init: n_eq must be 0 or 1");
+  if (P->n_eq && !(P->eq_tol >= 0.0)) return fail(GMPEA_EINVAL, "gmpea_init: eq_tol must be >= 0");
+  if ((P->lb == nullptr) != (P->ub == nullptr))
+    return fail(GMPEA_EINVAL, "gmpea_init: give both lb and ub or neither");
+  if (P->lb)
+    for (int32_t l = 0; l < P->d; ++l)
+      if (!(P->lb[l] < P->ub[l]) || !std::isfinite(P->lb[l]) || !std::isfinite(P->ub[l]))
+        return fail(GMPEA_EINVAL, "gmpea_init: need finite lb < ub in every variable");
+  if (C->n_req < 2) return fail(GMPEA_EINVAL, "gmpea_init: n_req must be at least 2");
+  if (C->n_req > (1 << 26)) return fail(GMPEA_EUNSUPPORTED, "gmpea_init: n_req too large");
+  if (C->agg != GMPEA_AGG_PBI && C->agg != GMPEA_AGG_TCHE)
+    return fail(GMPEA_EINVAL, "gmpea_init: unknown aggregation");
+  if (C->T < 0 || C->t1 < 0 || C->t2 < 0) return fail(GMPEA_EINVAL, "gmpea_init: negative size");
+  if (C->pc < 0 || C->pc > 1 || C->pm < 0 || C->pm > 1)
+    return fail(GMPEA_EINVAL, "gmpea_init: probabilities must lie in [0, 1]");
+  if (C->eta_c < 0 || C->eta_m < 0 || C->theta < 0)
+    return fail(GMPEA_EINVAL, "gmpea_init: negative distribution index or penalty");
+  return GMPEA_OK;
+}
+
+gmpea_status build_graph(gmpea_s *h, int32_t chunk) {
+  if (h->gexec && h->gchunk == chunk) return GMPEA_OK;
+  if (h->gexec) {
+    (void)hipGraphExecDestroy(h->gexec);
+    h->gexec = nullptr;
+  }
+  hipStream_t cap;
+  hipError_t e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+  if (e != hipSuccess) return hip_fail(e, "graph stream");
+  e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    for (int32_t g = 0; g < chunk && e == hipSuccess; ++g) e = launch_generation(h->st, cap);
+    hipGraph_t graph = nullptr;
+    hipError_t e2 = hipStreamEndCapture(cap, &graph);
+    if (e == hipSuccess) e = e2;
+    if (e == hipSuccess) e = hipGraphInstantiate(&h->gexec, graph, nullptr, nullptr, 0);
+    if (graph) (void)hipGraphDestroy(graph);
+  }
+  (void)hipStreamDestroy(cap);
+  if (e != hipSuccess) {
+    h->gexec = nullptr;
+    return hip_fail(e, "graph capture");
+  }
+  h->gchunk = chunk;
+  return GMPEA_OK;
+}
+
+gmpea_status enqueue(gmpea_s *h, int32_t n) {
+  const int32_t G = h->graph_chunk_cfg;
+  if (G >= 2 && n >= G) {
+    gmpea_status s = build_graph(h, G);
+    if (s != GMPEA_OK) return s;
+    while (n >= G) {
+      hipError_t e = hipGraphLaunch(h->gexec, h->stream);
+      if (e != hipSuccess) return hip_fail(e, "graph launch");
+      n -= G;
+    }
+  }
+  for (int32_t g = 0; g < n; ++g) {
+    hipError_t e = launch_generation(h->st, h->stream);
+    if (e != hipSuccess) return hip_fail(e, "generation launch");
+  }
+  return GMPEA_OK;
+}
+
+template <class T>
+gmpea_status d2h(gmpea_s *h, T *dst, const void *src, size_t n, const char *what) {
+  hipError_t e = hipMemcpyAsync(dst, src, n * sizeof(T), hipMemcpyDeviceToHost, h->stream);
+  if (e != hipSuccess) return hip_fail(e, what);
+  return sync(h, what);
+}
+
+template <class T>
+gmpea_status h2d(gmpea_s *h, void *dst, const T *src, size_t n, const char *what) {
+  hipError_t e = hipMemcpyAsync(dst, src, n * sizeof(T), hipMemcpyHostToDevice, h->stream);
+  if (e != hipSuccess) return hip_fail(e, what);
+  return sync(h, what);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *gmpea_last_error(void) { return g_err.c_str(); }
+
+gmpea_status gmpea_init(const gmpea_problem *P, const gmpea_config *C, const gmpea_allocator *A,
+                        void *hip_stream, gmpea_t *out) {
+  if (!out) return fail(GMPEA_EINVAL, "gmpea_init: out is NULL");
+  gmpea_status s = validate(P, C);
+  if (s != GMPEA_OK) return s;
+  if (A && (!A->alloc || !A->free)) return fail(GMPEA_EINVAL, "gmpea_init: incomplete allocator");
+
+  const int32_t m = P->m, d = P->d;
+  const int32_t H = dd_divisions(m, C->n_req);
+  const int64_t n64 = dd_count(m, H);
+  if (n64 > (1 << 27)) return fail(GMPEA_EUNSUPPORTED, "gmpea_init: population too large");
+  const int32_t N = static_cast<int32_t>(n64);
+  const int32_t T = C->T;
+  const int32_t t1 = C->t1 > 0 ? C->t1 : T / 2;
+  const int32_t t2 = C->t2 > 0 ? C->t2 : 2 * T;
+  if (t1 < 1 || t2 < 1 || t1 > N || t2 > N)
+    return fail(GMPEA_EINVAL, "gmpea_init: need 1 <= t1, t2 <= N (population " + std::to_string(N) +
+                                  ", t1 " + std::to_string(t1) + ", t2 " + std::to_string(t2) + ")");
+
+  gmpea_s *h = new gmpea_s();
+  if (A) {
+    h->al = *A;
+    h->hook = true;
+  }
+  if (const char *g = std::getenv("GMPEA_GRAPH_CHUNK")) h->graph_chunk_cfg = std::atoi(g);
+  if (hip_stream) {
+    h->stream = static_cast<hipStream_t>(hip_stream);
+  } else {
+    hipError_t e = hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      delete h;
+      return hip_fail(e, "gmpea_init: stream");
+    }
+    h->own_stream = true;
+  }
+  h->H = H;
+  h->record = C->record != 0;
+
+  // ---- host-side structures: W, B1, B2, reverse lists ----
+  std::vector<int32_t> K;
+  dd_lattice(m, H, K);
+  h->w_raw.resize(static_cast<size_t>(N) * m);
+  std::vector<float4> wdev(static_cast<size_t>(N));
+  for (int32_t i = 0; i < N; ++i) {
+    double w[3] = {0, 0, 0}, nrm = 0;
+    for (int32_t a = 0; a < m; ++a) {
+      w[a] = static_cast<double>(K[static_cast<size_t>(i) * m + a]) / H;
+      h->w_raw[static_cast<size_t>(i) * m + a] = static_cast<float>(w[a]);
+      nrm += w[a] * w[a];
+    }
+    nrm = std::sqrt(nrm);
+    double v[3];
+    for (int32_t a = 0; a < 3; ++a) v[a] = (C->agg == GMPEA_AGG_PBI) ? w[a] / nrm : w[a];
+    wdev[i] = make_float4(static_cast<float>(v[0]), static_cast<float>(v[1]),
+                          static_cast<float>(v[2]), 0.0f);
+  }
+  std::vector<int32_t> roff[2], ridx[2];
+  const int32_t ts[2] = {t1, t2};
+  for (int p = 0; p < 2; ++p) {
+    if (p == 1 && t2 == t1) {
+      h->b_host[1] = h->b_host[0];
+    } else {
+      lattice_knn(K, m, H, ts[p], h->b_host[p]);
+    }
+    reverse_lists(h->b_host[p], N, ts[p], roff[p], ridx[p]);
+  }
+
+  // ---- device state ----
+  DevState &st = h->st;
+  st.n = N;
+  st.m = m;
+  st.d = d;
+  st.stride = (d + 3) & ~3;
+  st.nblk = (N + kBlock - 1) / kBlock;
+  st.t[0] = t1;
+  st.t[1] = t2;
+  st.agg = C->agg;
+  st.theta = static_cast<float>(C->theta > 0 ? C->theta : 5.0);
+  const double eta_c = C->eta_c > 0 ? C->eta_c : 20.0, eta_m = C->eta_m > 0 ? C->eta_m : 20.0;
+  const double pc = C->pc > 0 ? C->pc : 1.0, pm = C->pm > 0 ? C->pm : 1.0 / d;
+  st.sbx_e = static_cast<float>(1.0 / (eta_c + 1.0));
+  st.pm_p = static_cast<float>(eta_m + 1.0);
+  st.pm_e = static_cast<float>(1.0 / (eta_m + 1.0));
+  st.tpm = static_cast<uint64_t>(std::floor(pm * 4294967296.0));
+  st.tpc = static_cast<uint64_t>(std::floor(pc * 4294967296.0));
+  st.key0 = static_cast<uint32_t>(C->seed & 0xFFFFFFFFull);
+  st.key1 = static_cast<uint32_t>(C->seed >> 32);
+  DevProblem &dp = st.prob;
+  dp.family = P->family;
+  dp.m = m;
+  dp.d = d;
+  dp.n_ring = P->n_ring;
+  dp.has_sum_lower = P->has_sum_lower ? 1 : 0;
+  dp.n_eq = P->n_eq;
+  for (int32_t j = 0; j < P->n_ring; ++j) {
+    for (int32_t a = 0; a < m; ++a)
+      dp.ring_c[j * m + a] = static_cast<float>(P->ring_center[static_cast<size_t>(j) * m + a]);
+    dp.ring_r2[j] = static_cast<float>(P->ring_radius[j] * P->ring_radius[j]);
+  }
+  dp.sum_lower = static_cast<float>(P->sum_lower);
+  dp.eq_tol = static_cast<float>(P->eq_tol);
+  dp.g_scale = d > 1 ? static_cast<float>(9.0 / (d - 1)) : 0.0f;
+
+  const size_t rows = static_cast<size_t>(st.nblk) * kBlock;
+  bool ok = true;
+  float *lb = alloc_n<float>(h, d), *ub = alloc_n<float>(h, d);
+  ok = ok && lb && ub;
+  for (int p = 0; p < 2 && ok; ++p) {
+    st.X[p] = alloc_n<float>(h, rows * st.stride);
+    st.XO[p] = alloc_n<float>(h, rows * st.stride);
+    st.FC[p] = alloc_n<float4>(h, rows);
+    st.FCO[p] = alloc_n<float4>(h, rows);
+    st.FCN[p] = alloc_n<float4>(h, rows);
+    int32_t *b = alloc_n<int32_t>(h, static_cast<size_t>(N) * ts[p]);
+    int32_t *ro = alloc_n<int32_t>(h, static_cast<size_t>(N) + 1);
+    int32_t *ri = alloc_n<int32_t>(h, static_cast<size_t>(N) * ts[p]);
+    st.B[p] = b;
+    st.roff[p] = ro;
+    st.ridx[p] = ri;
+    st.mate[p] = h->record ? alloc_n<int32_t>(h, rows * 2) : nullptr;
+    st.win[p] = h->record ? alloc_n<int32_t>(h, rows) : nullptr;
+    ok = st.X[p] && st.XO[p] && st.FC[p] && st.FCO[p] && st.FCN[p] && b && ro && ri &&
+         (!h->record || (st.mate[p] && st.win[p]));
+  }
+  if (ok) {
+    st.W = alloc_n<float4>(h, rows);
+    st.src = alloc_n<uint8_t>(h, rows);
+    st.zkey = alloc_n<uint32_t>(h, 4);
+    st.gen = alloc_n<uint32_t>(h, 4);
+    st.repl = alloc_n<unsigned long long>(h, 2);
+    ok = st.W && st.src && st.zkey && st.gen && st.repl;
+  }
+  if (!ok) {
+    release_all(h);
+    delete h;
+    return fail(GMPEA_ENOMEM, "gmpea_init: device allocation failed");
+  }
+  dp.lb = lb;
+  dp.ub = ub;
+
+  std::vector<float> lbf(d), ubf(d);
+  for (int32_t l = 0; l < d; ++l) {
+    lbf[l] = P->lb ? static_cast<float>(P->lb[l]) : 0.0f;
+    ubf[l] = P->ub ? static_cast<float>(P->ub[l]) : 1.0f;
+  }
+  hipError_t e = hipSuccess;
+  auto cp = [&](void *dst, const void *src, size_t bytes) {
+    if (e == hipSuccess) e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, h->stream);
+  };
+  auto zero = [&](void *dst, int v, size_t bytes) {
+    if (e == hipSuccess) e = hipMemsetAsync(dst, v, bytes, h->stream);
+  };
+  cp(lb, lbf.data(), d * sizeof(float));
+  cp(ub, ubf.data(), d * sizeof(float));
+  cp(st.W, wdev.data(), N * sizeof(float4));
+  for (int p = 0; p < 2; ++p) {
+    cp(const_cast<int32_t *>(st.B[p]), h->b_host[p].data(), h->b_host[p].size() * sizeof(int32_t));
+    cp(const_cast<int32_t *>(st.roff[p]), roff[p].data(), roff[p].size() * sizeof(int32_t));
+    cp(const_cast<int32_t *>(st.ridx[p]), ridx[p].data(), ridx[p].size() * sizeof(int32_t));
+    zero(st.X[p], 0, rows * st.stride * sizeof(float));
+    zero(st.XO[p], 0, rows * st.stride * sizeof(float));
+    zero(st.FC[p], 0, rows * sizeof(float4));
+    zero(st.FCO[p], 0, rows * sizeof(float4));
+    zero(st.FCN[p], 0, rows * sizeof(float4));
+    if (h->record) {
+      zero(st.mate[p], 0xFF, rows * 2 * sizeof(int32_t));
+      zero(st.win[p], 0xFF, rows * sizeof(int32_t));
+    }
+  }
+  zero(st.src, 0, rows);
+  zero(st.zkey, 0xFF, 4 * sizeof(uint32_t));
+  zero(st.gen, 0, 4 * sizeof(uint32_t));
+  zero(st.repl, 0, 2 * sizeof(unsigned long long));
+  if (e == hipSuccess) e = launch_init(st, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) {
+    gmpea_status r = hip_fail(e, "gmpea_init");
+    release_all(h);
+    delete h;
+    return r;
+  }
+  register_live(h, true);
+  *out = h;
+  return GMPEA_OK;
+}
+
+gmpea_status gmpea_step(gmpea_t h, int32_t n_gen) {
+  if (!valid(h)) return fail(GMPEA_ESTATE, "gmpea_step: invalid handle");
+  if (n_gen < 0) return fail(GMPEA_EINVAL, "gmpea_step: n_gen < 0");
+  return enqueue(h, n_gen);
+}
+
+gmpea_status gmpea_run(gmpea_t h, int32_t max_gen, double time_limit_s, int32_t *gens_done) {
+  if (!valid(h)) return fail(GMPEA_ESTATE, "gmpea_run: invalid handle");
+  if (max_gen < 0) return fail(GMPEA_EINVAL, "gmpea_run: max_gen < 0");
+  using clk = std::chrono::steady_clock;
+  const auto t0 = clk::now();
+  auto elapsed = [&] { return std::chrono::duration<double>(clk::now() - t0).count(); };
+  int32_t done = 0;
+  gmpea_status s = GMPEA_OK;
+  if (!(time_limit_s > 0.0)) {
+    s = enqueue(h, max_gen);
+    if (s == GMPEA_OK) s = sync(h, "gmpea_run");
+    if (s == GMPEA_OK) done = max_gen;
+  } else {
+    // chunks sized from the measured time per generation so that each chunk is
+    // expected to end before half of the remaining time has passed
+    int32_t chunk = 1;
+    while (done < max_gen && s == GMPEA_OK) {
+      const double now = elapsed();
+      if (now >= time_limit_s) break;
+      const int32_t c = std::min(chunk, max_gen - done);
+      const double c0 = elapsed();
+      s = enqueue(h, c);
+      if (s == GMPEA_OK) s = sync(h, "gmpea_run");
+      if (s != GMPEA_OK) break;
+      done += c;
+      const double per = std::max(1e-7, (elapsed() - c0) / c);
+      const double left = time_limit_s - elapsed();
+      chunk = static_cast<int32_t>(std::clamp(left / per * 0.5, 1.0, 4096.0));
+    }
+  }
+  if (gens_done) *gens_done = done;
+  return s;
+}
+
+gmpea_status gmpea_front(gmpea_t h, int32_t what, int32_t capacity, float *x, float *f, float *cv,
+                         int32_t *idx, int32_t *count) {
+  if (!valid(h)) return fail(GMPEA_ESTATE, "gmpea_front: invalid handle");
+  if (!count) return fail(GMPEA_EINVAL, "gmpea_front: count is NULL");
+  if (what != GMPEA_FRONT_FEASIBLE_ND && what != GMPEA_FRONT_POP1 && what != GMPEA_FRONT_POP2)
+    return fail(GMPEA_EINVAL, "gmpea_front: unknown selector");
+  if (capacity < 0) return fail(GMPEA_EINVAL, "gmpea_front: negative capacity");
+  const DevState &st = h->st;
+  const int pop = what == GMPEA_FRONT_POP2 ? 1 : 0;
+  std::vector<int32_t> rows;
+  if (what == GMPEA_FRONT_FEASIBLE_ND) {
+    uint8_t *keep = alloc_n<uint8_t>(h, st.n);
+    if (!keep) return fail(GMPEA_ENOMEM, "gmpea_front: scratch allocation failed");
+    hipError_t e = launch_front_flags(st, pop, keep, h->stream);
+    std::vector<uint8_t> hk(st.n);
+    gmpea_status s = e == hipSuccess ? d2h(h, hk.data(), keep, st.n, "gmpea_front") : hip_fail(e, "gmpea_front");
+    dev_free(h, keep);
+    if (s != GMPEA_OK) return s;
+    for (int32_t i = 0; i < st.n; ++i)
+      if (hk[i]) rows.push_back(i);
+  } else {
+    gmpea_status s = sync(h, "gmpea_front");
+    if (s != GMPEA_OK) return s;
+    rows.resize(st.n);
+    for (int32_t i = 0; i < st.n; ++i) rows[i] = i;
+  }
+  const int32_t cnt = static_cast<int32_t>(rows.size());
+  *count = cnt;
+  if (cnt > capacity) return fail(GMPEA_ECAPACITY, "gmpea_front: capacity below the row count");
+  if (cnt == 0) return GMPEA_OK;
+  if (idx) std::copy(rows.begin(), rows.end(), idx);
+  int32_t *didx = alloc_n<int32_t>(h, cnt);
+  float *dx = alloc_n<float>(h, static_cast<size_t>(cnt) * st.d);
+  float4 *dfc = alloc_n<float4>(h, cnt);
+  gmpea_status s = GMPEA_OK;
+  if (!didx || !dx || !dfc) s = fail(GMPEA_ENOMEM, "gmpea_front: scratch allocation failed");
+  std::vector<float4> hfc;
+  if (s == GMPEA_OK) s = h2d(h, didx, rows.data(), cnt, "gmpea_front");
+  if (s == GMPEA_OK) {
+    hipError_t e = launch_gather(st, pop, didx, cnt, dx, dfc, h->stream);
+    if (e != hipSuccess) s = hip_fail(e, "gmpea_front gather");
+  }
+  if (s == GMPEA_OK && x) s = d2h(h, x, dx, static_cast<size_t>(cnt) * st.d, "gmpea_front");
+  if (s == GMPEA_OK) {
+    hfc.resize(cnt);
+    s = d2h(h, hfc.data(), dfc, cnt, "gmpea_front");
+  }
+  if (s == GMPEA_OK) {
+    for (int32_t r = 0; r < cnt; ++r) {
+      const float v[4] = {hfc[r].x, hfc[r].y, hfc[r].z, hfc[r].w};
+      if (f)
+        for (int32_t a = 0; a < st.m; ++a) f[static_cast<size_t>(r) * st.m + a] = v[a];
+      if (cv) cv[r] = v[3];
+    }
+  }
+  if (didx) dev_free(h, didx);
+  if (dx) dev_free(h, dx);
+  if (dfc) dev_free(h, dfc);
+  return s;
+}
+
+gmpea_status gmpea_get_info(gmpea_t h, gmpea_info *info) {
+  if (!valid(h)) return fail(GMPEA_ESTATE, "gmpea_get_info: invalid handle");
+  if (!info) return fail(GMPEA_EINVAL, "gmpea_get_info: info is NULL");
+  const DevState &st = h->st;
+  uint32_t gen = 0, zk[4];
+  unsigned long long rep[2];
+  std::vector<float4> fc(st.n);
+  gmpea_status s = d2h(h, &gen, st.gen, 1, "gmpea_get_info");
+  if (s == GMPEA_OK) s = d2h(h, zk, st.zkey, 4, "gmpea_get_info");
+  if (s == GMPEA_OK) s = d2h(h, rep, st.repl, 2, "gmpea_get_info");
+  if (s == GMPEA_OK) s = d2h(h, fc.data(), st.FC[0], st.n, "gmpea_get_info");
+  if (s != GMPEA_OK) return s;
+  info->n = st.n;
+  info->m = st.m;
+  info->d = st.d;
+  info->t1 = st.t[0];
+  info->t2 = st.t[1];
+  info->H = h->H;
+  info->generation = gen;
+  for (int a = 0; a < GMPEA_MAX_M; ++a) info->z[a] = a < st.m ? key_float(zk[a]) : 0.0f;
+  info->replaced[0] = static_cast<int64_t>(rep[0]);
+  info->replaced[1] = static_cast<int64_t>(rep[1]);
+  int64_t feas = 0;
+  for (int32_t i = 0; i < st.n; ++i) feas += fc[i].w == 0.0f;
+  info->feasible_frac = static_cast<double>(feas) / st.n;
+  info->device_bytes = h->bytes;
+  return GMPEA_OK;
+}
+
+gmpea_status gmpea_read(gmpea_t h, int32_t buffer, int32_t pop, void *host, int64_t count) {
+  if (!valid(h)) return fail(GMPEA_ESTATE, "gmpea_read: invalid handle");
+  if (!host) return fail(GMPEA_EINVAL, "gmpea_read: host is NULL");
+  if (pop != 0 && pop != 1) return fail(GMPEA_EINVAL, "gmpea_read: pop must be 0 or 1");
+  const DevState &st = h->st;
+  const int64_t n = st.n, m = st.m, d = st.d;
+  auto need = [&](int64_t want) { return count == want; };
+  switch (buffer) {
+    case GMPEA_BUF_X:
+    case GMPEA_BUF_XOFF: {
+      if (!need(n * d)) return fail(GMPEA_EINVAL, "gmpea_read: count must be N * d");
+      const float *src = buffer == GMPEA_BUF_X ? st.X[pop] : st.XO[pop];
+      hipError_t e = hipMemcpy2DAsync(host, d * sizeof(float), src, st.stride * sizeof(float),
+                                      d * sizeof(float), n, hipMemcpyDeviceToHost, h->stream);
+      if (e != hipSuccess) return hip_fail(e, "gmpea_read");
+      return sync(h, "gmpea_read");
+    }
+    case GMPEA_BUF_F:
+    case GMPEA_BUF_CV:
+    case GMPEA_BUF_FOFF:
+    case GMPEA_BUF_CVOFF: {
+      const bool isf = buffer == GMPEA_BUF_F || buffer == GMPEA_BUF_FOFF;
+      if (!need(isf ? n * m : n)) return fail(GMPEA_EINVAL, "gmpea_read: wrong count");
+      std::vector<float4> fc(n);
+      const float4 *src = (buffer == GMPEA_BUF_F || buffer == GMPEA_BUF_CV) ? st.FC[pop] : st.FCO[pop];
+      gmpea_status s = d2h(h, fc.data(), src, n, "gmpea_read");
+      if (s != GMPEA_OK) return s;
+      float *o = static_cast<float *>(host);
+      for (int64_t i = 0; i < n; ++i) {
+        const float v[4] = {fc[i].x, fc[i].y, fc[i].z, fc[i].w};
+        if (isf)
+          for (int64_t a = 0; a < m; ++a) o[i * m + a] = v[a];
+        else
+          o[i] = v[3];
+      }
+      return GMPEA_OK;
+    }
+    case GMPEA_BUF_Z: {
+      if (!need(m)) return fail(GMPEA_EINVAL, "gmpea_read: count must be m");
+      uint32_t zk[4];
+      gmpea_status s = d2h(h, zk, st.zkey, 4, "gmpea_read");
+      if (s != GMPEA_OK) return s;
+      for (int64_t a = 0; a < m; ++a) static_cast<float *>(host)[a] = key_float(zk[a]);
+      return GMPEA_OK;
+    }
+    case GMPEA_BUF_GEN: {
+      if (!need(1)) return fail(GMPEA_EINVAL, "gmpea_read: count must be 1");
+      uint32_t g = 0;
+      gmpea_status s = d2h(h, &g, st.gen, 1, "gmpea_read");
+      if (s == GMPEA_OK) *static_cast<int64_t *>(host) = g;
+      return s;
+    }
+    case GMPEA_BUF_W: {
+      if (!need(n * m)) return fail(GMPEA_EINVAL, "gmpea_read: count must be N * m");
+      std::copy(h->w_raw.begin(), h->w_raw.end(), static_cast<float *>(host));
+      return GMPEA_OK;
+    }
+    case GMPEA_BUF_B: {
+      if (!need(n * st.t[pop])) return fail(GMPEA_EINVAL, "gmpea_read: count must be N * t");
+      std::copy(h->b_host[pop].begin(), h->b_host[pop].end(), static_cast<int32_t *>(host));
+      return GMPEA_OK;
+    }
+    case GMPEA_BUF_MATE:
+      if (!h->record) return fail(GMPEA_EINVAL, "gmpea_read: MATE needs config.record");
+      if (!need(n * 2)) return fail(GMPEA_EINVAL, "gmpea_read: count must be N * 2");
+      return d2h(h, static_cast<int32_t *>(host), st.mate[pop], n * 2, "gmpea_read");
+    case GMPEA_BUF_WIN:
+      if (!h->record) return fail(GMPEA_EINVAL, "gmpea_read: WIN needs config.record");
+      if (!need(n)) return fail(GMPEA_EINVAL, "gmpea_read: count must be N");
+      return d2h(h, static_cast<int32_t *>(host), st.win[pop], n, "gmpea_read");
+    case GMPEA_BUF_OP1: {
+      if (!need(n)) return fail(GMPEA_EINVAL, "gmpea_read: count must be N");
+      std::vector<uint8_t> sw(n);
+      gmpea_status s = d2h(h, sw.data(), st.src, n, "gmpea_read");
+      if (s != GMPEA_OK) return s;
+      for (int64_t i = 0; i < n; ++i) static_cast<uint8_t *>(host)[i] = (sw[i] >> pop) & 1u;
+      return GMPEA_OK;
+    }
+    default:
+      return fail(GMPEA_EINVAL, "gmpea_read: unknown buffer");
+  }
+}
+
+gmpea_status gmpea_write(gmpea_t h, int32_t buffer, int32_t pop, const void *host, int64_t count) {
+  if (!valid(h)) return fail(GMPEA_ESTATE, "gmpea_write: invalid handle");
+  if (!host) return fail(GMPEA_EINVAL, "gmpea_write: host is NULL");
+  if (pop != 0 && pop != 1) return fail(GMPEA_EINVAL, "gmpea_write: pop must be 0 or 1");
+  DevState &st = h->st;
+  const int64_t n = st.n, m = st.m, d = st.d;
+  switch (buffer) {
+    case GMPEA_BUF_X: {
+      if (count != n * d) return fail(GMPEA_EINVAL, "gmpea_write: count must be N * d");
+      hipError_t e = hipMemcpy2DAsync(st.X[pop], st.stride * sizeof(float), host, d * sizeof(float),
+                                      d * sizeof(float), n, hipMemcpyHostToDevice, h->stream);
+      if (e != hipSuccess) return hip_fail(e, "gmpea_write");
+      return sync(h, "gmpea_write");
+    }
+    case GMPEA_BUF_F:
+    case GMPEA_BUF_CV: {
+      const bool isf = buffer == GMPEA_BUF_F;
+      if (count != (isf ? n * m : n)) return fail(GMPEA_EINVAL, "gmpea_write: wrong count");
+      std::vector<float4> fc(n);
+      gmpea_status s = d2h(h, fc.data(), st.FC[pop], n, "gmpea_write");
+      if (s != GMPEA_OK) return s;
+      const float *in = static_cast<const float *>(host);
+      for (int64_t i = 0; i < n; ++i) {
+        if (isf) {
+          fc[i].x = in[i * m];
+          fc[i].y = in[i * m + 1];
+          fc[i].z = m > 2 ? in[i * m + 2] : 0.0f;
+        } else {
+          fc[i].w = in[i];
+        }
+      }
+      return h2d(h, st.FC[pop], fc.data(), n, "gmpea_write");
+    }
+    case GMPEA_BUF_Z: {
+      if (count != m) return fail(GMPEA_EINVAL, "gmpea_write: count must be m");
+      uint32_t zk[4] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu};
+      for (int64_t a = 0; a < m; ++a) zk[a] = float_key(static_cast<const float *>(host)[a]);
+      return h2d(h, st.zkey, zk, 4, "gmpea_write");
+    }
+    case GMPEA_BUF_GEN: {
+      if (count != 1) return fail(GMPEA_EINVAL, "gmpea_write: count must be 1");
+      const int64_t g = *static_cast<const int64_t *>(host);
+      if (g < 0 || g > 0xFFFFFFFFll) return fail(GMPEA_EINVAL, "gmpea_write: generation out of range");
+      const uint32_t g32 = static_cast<uint32_t>(g);
+      return h2d(h, st.gen, &g32, 1, "gmpea_write");
+    }
+    default:
+      return fail(GMPEA_EINVAL, "gmpea_write: buffer is not writable");
+  }
+}
+
+void gmpea_destroy(gmpea_t h) {
+  if (!valid(h)) return;
+  register_live(h, false);
+  if (h->stream) (void)hipStreamSynchronize(h->stream);
+  release_all(h);
+  delete h;
+}
+
+gmpea_status gmpea_profile(gmpea_t h, int32_t n_gen, float *ms) {
+  if (!valid(h)) return fail(GMPEA_ESTATE, "gmpea_profile: invalid handle");
+  if (n_gen < 1 || !ms) return fail(GMPEA_EINVAL, "gmpea_profile: need n_gen >= 1 and ms");
+  hipEvent_t ev[kPhases + 1];
+  int made = 0;
+  hipError_t e = hipSuccess;
+  for (; made <= kPhases && e == hipSuccess; ++made) e = hipEventCreate(&ev[made]);
+  if (e != hipSuccess) --made;
+  double acc[kPhases] = {0.0, 0.0, 0.0};
+  for (int32_t g = 0; g < n_gen && e == hipSuccess; ++g) {
+    e = hipEventRecord(ev[0], h->stream);
+    for (int ph = 0; ph < kPhases && e == hipSuccess; ++ph) {
+      e = launch_phase(h->st, ph, h->stream);
+      if (e == hipSuccess) e = hipEventRecord(ev[ph + 1], h->stream);
+    }
+    if (e == hipSuccess) e = hipEventSynchronize(ev[kPhases]);
+    for (int ph = 0; ph < kPhases && e == hipSuccess; ++ph) {
+      float t = 0.0f;
+      e = hipEventElapsedTime(&t, ev[ph], ev[ph + 1]);
+      acc[ph] += t;
+    }
+  }
+  for (int q = 0; q < made; ++q) (void)hipEventDestroy(ev[q]);
+  if (e != hipSuccess) return hip_fail(e, "gmpea_profile");
+  for (int ph = 0; ph < kPhases; ++ph) ms[ph] = static_cast<float>(acc[ph] / n_gen);
+  return GMPEA_OK;
+}
+
+gmpea_status gmpea_philox(const uint32_t *ctr, int64_t n, uint64_t seed, uint32_t *out,
+                          void *hip_stream) {
+  if (n < 0 || (n > 0 && (!ctr || !out))) return fail(GMPEA_EINVAL, "gmpea_philox: bad arguments");
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  hipError_t e = launch_philox(ctr, n, static_cast<uint32_t>(seed & 0xFFFFFFFFull),
+                               static_cast<uint32_t>(seed >> 32), out, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "gmpea_philox");
+  return GMPEA_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,98 @@
+// Internal declarations of the GMPEA HIP library: kernel argument blocks and
+// launchers shared by the kernels (gmpea_kernels.hip) and the host runtime
+// (gmpea_abi.cpp, lattice.cpp). Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+
+namespace gmpea {
+
+constexpr int kMaxM = 3;
+constexpr int kMaxRing = 8;
+constexpr int kBlock = 256;  // threads per block of the per-subproblem kernels
+
+// Stream tags of the counter RNG (top byte of counter word 3).
+constexpr uint32_t kTagInit = 1u;
+constexpr uint32_t kTagMate = 2u;
+constexpr uint32_t kTagVar = 3u;
+
+// Problem constants in the device precision, passed by value to every kernel
+// that evaluates F and CV.
+struct DevProblem {
+  int32_t family, m, d, n_ring, has_sum_lower, n_eq;
+  float ring_c[kMaxRing * kMaxM];  // centres, row-major
+  float ring_r2[kMaxRing];         // squared radii
+  float sum_lower, eq_tol;
+  float g_scale;                   // 9 / (d - 1) for the curve family
+  const float *lb, *ub;            // device, d each
+};
+
+// Device state of one instance. Rows of X are `stride` floats (d rounded up to a
+// multiple of 4 so that every row starts 16-byte aligned); F and CV of one
+// individual share a float4 (f0, f1, f2, cv) with unused objective lanes 0.
+struct DevState {
+  int32_t n, m, d, stride, nblk;  // nblk: blocks of kBlock rows per population
+  int32_t t[2];
+  int32_t agg;
+  float theta;
+  float *X[2], *XO[2];
+  float4 *FC[2], *FCO[2], *FCN[2];
+  float4 *W;                 // unit direction (PBI) or raw weight (Tchebycheff)
+  const int32_t *B[2];       // n x t_p
+  const int32_t *roff[2];    // reverse lists, CSR: offsets n + 1
+  const int32_t *ridx[2];    //                     indices n t_p, ascending per row
+  uint8_t *src;              // OP1 switches: bit p set = population p took the other's offspring
+  uint32_t *zkey;            // ideal point as order-preserving keys (atomic min)
+  uint32_t *gen;             // generations completed
+  unsigned long long *repl;  // replaced-slot counters per population
+  int32_t *mate[2];          // optional record of parent rows (n x 2)
+  int32_t *win[2];           // optional record of winners (n)
+  uint32_t key0, key1;       // RNG key
+  uint64_t tpm, tpc;         // mutation / crossover thresholds floor(p 2^32)
+  float sbx_e;               // 1 / (eta_c + 1)
+  float pm_p, pm_e;          // eta_m + 1, 1 / (eta_m + 1)
+  DevProblem prob;
+};
+
+// Launchers (gmpea_kernels.hip). Each enqueues on `s` and returns the launch status.
+hipError_t launch_init(const DevState &st, hipStream_t s);
+// A generation is kPhases launches: 0 variation + evaluation + ideal point,
+// 1 offspring cooperation, 2 neighbour replacement.
+constexpr int kPhases = 3;
+hipError_t launch_phase(const DevState &st, int phase, hipStream_t s);
+hipError_t launch_generation(const DevState &st, hipStream_t s);
+hipError_t launch_front_flags(const DevState &st, int pop, uint8_t *keep, hipStream_t s);
+hipError_t launch_gather(const DevState &st, int pop, const int32_t *idx, int32_t count,
+                         float *x, float4 *fc, hipStream_t s);
+hipError_t launch_philox(const uint32_t *ctr, int64_t n, uint32_t k0, uint32_t k1, uint32_t *out,
+                         hipStream_t s);
+
+// Order-preserving map between floats and unsigned keys (host copies of the
+// device helpers, used to read and write the ideal point).
+inline uint32_t float_key(float f) {
+  uint32_t b;
+  std::memcpy(&b, &f, 4);
+  return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+inline float key_float(uint32_t k) {
+  uint32_t b = (k & 0x80000000u) ? (k & 0x7FFFFFFFu) : ~k;
+  float f;
+  std::memcpy(&f, &b, 4);
+  return f;
+}
+
+// Reference vectors and neighbourhoods (lattice.cpp).
+int32_t dd_divisions(int32_t m, int64_t n_req);            // smallest H with count >= n_req
+int64_t dd_count(int32_t m, int32_t H);                     // C(H + m - 1, m - 1)
+void dd_lattice(int32_t m, int32_t H, std::vector<int32_t> &K);
+void lattice_knn(const std::vector<int32_t> &K, int32_t m, int32_t H, int32_t t,
+                 std::vector<int32_t> &B);
+void reverse_lists(const std::vector<int32_t> &B, int32_t n, int32_t t, std::vector<int32_t> &off,
+                   std::vector<int32_t> &idx);
+
+}  // namespace gmpea

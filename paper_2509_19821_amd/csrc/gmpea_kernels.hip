@@ -1,0 +1,553 @@
+// GMPEA generation kernels for gfx950 (CDNA4, wave64).
+//
+// One generation (Alg. 1 loop body + Alg. 2) is three launches:
+//   k_vary    one lane per offspring (p, i): Philox draws, neighbourhood mating,
+//             SBX + polynomial mutation, evaluation of F and CV, and the block's
+//             share of the ideal-point minimum (one atomic per block and
+//             objective, skipped when it cannot lower z).
+//   k_op1     one lane per subproblem i: OP1 offspring cooperation at w_i with
+//             the updated ideal point; writes the new offspring's F/CV and the
+//             source switch (X is not copied).
+//   k_select  one lane per parent slot (p, j): OP2 + OP3 as a pull over the
+//             reverse neighbour list of j (every offspring i with j in B_p(i)),
+//             lexicographic minimum of the qualifiers; winners' rows are then
+//             copied by the whole block with 16-byte accesses.
+// The ideal point is a grid-wide dependency between k_vary and k_op1, and OP1
+// must finish for every i before any slot can be decided; kernel boundaries
+// provide both.
+//
+// Layout: X rows are `stride` floats (16-byte aligned), so a row copy is a run
+// of float4 moves; F and CV share one float4 per individual.
+// Blocks are remapped so that consecutive row tiles run on the same XCD (the
+// hardware deals blocks to the 8 XCDs round-robin): neighbouring subproblems
+// share parents and candidates, and then share that XCD's L2.
+#include "gmpea_internal.hpp"
+
+namespace gmpea {
+
+// ----------------------------------------------------------------------------
+// Counter RNG: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ uint4 philox10(uint4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint32_t hi0 = __umulhi(0xD2511F53u, c.x), lo0 = 0xD2511F53u * c.x;
+    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c.z), lo1 = 0xCD9E8D57u * c.z;
+    c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return c;
+}
+
+__device__ __forceinline__ float u24(uint32_t w) {
+  return static_cast<float>(w >> 8) * (1.0f / 16777216.0f);
+}
+
+__device__ __forceinline__ uint32_t fkey(float f) {
+  const uint32_t b = __float_as_uint(f);
+  return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+__device__ __forceinline__ float keyf(uint32_t k) {
+  return __uint_as_float((k & 0x80000000u) ? (k & 0x7FFFFFFFu) : ~k);
+}
+
+__device__ __forceinline__ float nan_inf(float v) { return (v != v) ? __builtin_huge_valf() : v; }
+
+// Block index -> tile such that each XCD receives a contiguous run of tiles.
+__device__ __forceinline__ int xcd_tile(int b, int G) {
+  const int x = b & 7, q = G >> 3, r = G & 7;
+  return x * q + min(x, r) + (b >> 3);
+}
+
+__device__ __forceinline__ float powpos(float x, float e) {
+  // x^e for x >= 0 (x = 0 gives 0 for e > 0 and +inf for e < 0)
+  return exp2f(e * log2f(x));
+}
+
+// ----------------------------------------------------------------------------
+// Variation of one variable: SBX (one child kept; per-variable crossing bit,
+// sign bit, 24-bit uniform) then clip, then bounded polynomial mutation.
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ float vary1(float a, float b, uint32_t wA, uint32_t wB, float lo, float hi,
+                                       bool cross, const DevState &st) {
+  float c = a;
+  if (cross && (wA & 1u)) {
+    const float u = u24(wA);
+    float beta = (u <= 0.5f) ? powpos(2.0f * u, st.sbx_e) : powpos(2.0f * (1.0f - u), -st.sbx_e);
+    if (wA & 2u) beta = -beta;
+    c = 0.5f * ((a + b) + beta * (a - b));
+  }
+  c = fminf(fmaxf(c, lo), hi);
+  if (static_cast<uint64_t>(wB) < st.tpm) {
+    const float u = static_cast<float>(wB) / static_cast<float>(st.tpm);
+    const float span = hi - lo;
+    float dq;
+    if (u < 0.5f) {
+      const float xy = 1.0f - (c - lo) / span;
+      const float val = 2.0f * u + (1.0f - 2.0f * u) * powpos(xy, st.pm_p);
+      dq = powpos(val, st.pm_e) - 1.0f;
+    } else {
+      const float xy = 1.0f - (hi - c) / span;
+      const float val = 2.0f * (1.0f - u) + 2.0f * (u - 0.5f) * powpos(xy, st.pm_p);
+      dq = 1.0f - powpos(val, st.pm_e);
+    }
+    c = fminf(fmaxf(c + dq * span, lo), hi);
+  }
+  return c;
+}
+
+// Running sums of the evaluation, filled variable by variable.
+struct EvalAcc {
+  float s;       // curve: sum x_2..x_d; sphere: sum over non-angle variables of (x - 0.5)^2
+  float x0, x1;  // first two variables (angles, f1, equality)
+};
+
+template <int M, int FAM>
+__device__ __forceinline__ void eval_add(EvalAcc &e, int l, float x) {
+  if (l == 0) e.x0 = x;
+  if (l == 1) e.x1 = x;
+  if (FAM == 0) {
+    if (l >= 1) e.s += x;
+  } else {
+    if (l >= M - 1) e.s += (x - 0.5f) * (x - 0.5f);
+  }
+}
+
+// F and CV from the sums (Eqs. (1)-(3)); returns (f0, f1, f2, cv).
+template <int M, int FAM>
+__device__ __forceinline__ float4 eval_finish(const EvalAcc &e, const DevProblem &P) {
+  float f[3] = {0.0f, 0.0f, 0.0f};
+  if (FAM == 0) {
+    const float g = 1.0f + P.g_scale * e.s;
+    f[0] = e.x0;
+    f[1] = g * (1.0f - sqrtf(e.x0 / g));
+  } else {
+    const float r = 1.0f + e.s;
+    float s0, c0;
+    sincospif(0.5f * e.x0, &s0, &c0);
+    if (M == 2) {
+      f[0] = r * c0;
+      f[1] = r * s0;
+    } else {
+      float s1, c1;
+      sincospif(0.5f * e.x1, &s1, &c1);
+      f[0] = r * c0 * c1;
+      f[1] = r * c0 * s1;
+      f[2] = r * s0;
+    }
+  }
+  float cv = 0.0f;
+  for (int j = 0; j < P.n_ring; ++j) {
+    float q = 0.0f;
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+      const float df = f[k] - P.ring_c[j * M + k];
+      q += df * df;
+    }
+    const float c = P.ring_r2[j] - q;
+    cv += (c > 0.0f) ? c : 0.0f;
+  }
+  if (P.has_sum_lower) {
+    float sum = 0.0f;
+#pragma unroll
+    for (int k = 0; k < M; ++k) sum += f[k];
+    const float c = P.sum_lower - sum;
+    cv += (c > 0.0f) ? c : 0.0f;
+  }
+  if (P.n_eq) {
+    const float c = fabsf(e.x0 + e.x1 - 1.0f) - P.eq_tol;
+    cv += (c > 0.0f) ? c : 0.0f;
+  }
+  return make_float4(f[0], f[1], f[2], cv);
+}
+
+// Block-wide minimum of each objective, then one atomic per objective when the
+// block's value can lower the ideal point. NaN never lowers it.
+template <int M>
+__device__ __forceinline__ void block_zmin(float (&v)[M], uint32_t *zkey) {
+  __shared__ float red[M][kBlock / 64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < M; ++k) {
+    float x = v[k];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x = fminf(x, __shfl_xor(x, o));
+    if (lane == 0) red[k][wv] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x < M) {
+    const int k = threadIdx.x;
+    float x = red[k][0];
+#pragma unroll
+    for (int w = 1; w < kBlock / 64; ++w) x = fminf(x, red[k][w]);
+    if (x == x) {
+      const uint32_t kk = fkey(x);
+      if (kk < __atomic_load_n(&zkey[k], __ATOMIC_RELAXED)) atomicMin(&zkey[k], kk);
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------
+// Initialisation (Alg. 1): X uniform in the box from the INIT stream,
+// evaluation, ideal point.
+// ----------------------------------------------------------------------------
+template <int M, int FAM>
+__global__ __launch_bounds__(kBlock) void k_init(DevState st) {
+  const int L = xcd_tile(blockIdx.x, gridDim.x);
+  const int p = L >= st.nblk ? 1 : 0;
+  const int i = (L - p * st.nblk) * kBlock + threadIdx.x;
+  float zv[M];
+#pragma unroll
+  for (int k = 0; k < M; ++k) zv[k] = __builtin_huge_valf();
+  if (i < st.n) {
+    float *row = st.X[p] + static_cast<size_t>(i) * st.stride;
+    EvalAcc e{0.0f, 0.0f, 0.0f};
+    uint4 w = make_uint4(0, 0, 0, 0);
+    for (int l = 0; l < st.stride; ++l) {
+      float x = 0.0f;
+      if (l < st.d) {
+        if ((l & 3) == 0)
+          w = philox10(make_uint4(l >> 2, i, 0u, (kTagInit << 24) | (p << 16)), st.key0, st.key1);
+        const uint32_t word = (l & 3) == 0 ? w.x : (l & 3) == 1 ? w.y : (l & 3) == 2 ? w.z : w.w;
+        const float lo = st.prob.lb[l], hi = st.prob.ub[l];
+        x = lo + (hi - lo) * u24(word);
+        eval_add<M, FAM>(e, l, x);
+      }
+      row[l] = x;
+    }
+    const float4 fc = eval_finish<M, FAM>(e, st.prob);
+    st.FC[p][i] = fc;
+    zv[0] = fc.x;
+    if (M > 1) zv[1] = fc.y;
+    if (M > 2) zv[M - 1] = fc.z;
+  }
+  block_zmin<M>(zv, st.zkey);
+}
+
+// ----------------------------------------------------------------------------
+// k_vary: reproduction + evaluation + ideal-point update.
+// Draws (reading R5/R6 of the design notes): MATE block (0, i, k, MATE|p) gives
+// the two neighbourhood positions and the per-offspring crossing draw; VAR block
+// (l >> 1, i, k, VAR|p) gives (wA, wB) for variables l, l + 1.
+// ----------------------------------------------------------------------------
+template <int M, int FAM>
+__global__ __launch_bounds__(kBlock) void k_vary(DevState st) {
+  const int L = xcd_tile(blockIdx.x, gridDim.x);
+  const int p = L >= st.nblk ? 1 : 0;
+  const int i = (L - p * st.nblk) * kBlock + threadIdx.x;
+  const uint32_t k = *st.gen + 1u;
+  const uint32_t tagp = (p << 16);
+  float zv[M];
+#pragma unroll
+  for (int q = 0; q < M; ++q) zv[q] = __builtin_huge_valf();
+  if (i < st.n) {
+    const int t = st.t[p];
+    const uint4 w = philox10(make_uint4(0u, i, k, (kTagMate << 24) | tagp), st.key0, st.key1);
+    const uint32_t r1 = __umulhi(w.x, static_cast<uint32_t>(t));
+    uint32_t r2 = r1;
+    if (t > 1) {
+      r2 = __umulhi(w.y, static_cast<uint32_t>(t - 1));
+      r2 += (r2 >= r1) ? 1u : 0u;
+    }
+    const int32_t *Bi = st.B[p] + static_cast<size_t>(i) * t;
+    const int pa = Bi[r1], pb = Bi[r2];
+    if (st.mate[p]) {
+      st.mate[p][2 * i] = pa;
+      st.mate[p][2 * i + 1] = pb;
+    }
+    const bool cross = static_cast<uint64_t>(w.z) < st.tpc;
+    const float4 *ra = reinterpret_cast<const float4 *>(st.X[p] + static_cast<size_t>(pa) * st.stride);
+    const float4 *rb = reinterpret_cast<const float4 *>(st.X[p] + static_cast<size_t>(pb) * st.stride);
+    float4 *ro = reinterpret_cast<float4 *>(st.XO[p] + static_cast<size_t>(i) * st.stride);
+    const uint32_t tagv = (kTagVar << 24) | tagp;
+    EvalAcc e{0.0f, 0.0f, 0.0f};
+    const int nq = st.stride >> 2;
+    for (int q = 0; q < nq; ++q) {
+      const int l0 = q << 2;
+      const float4 va = ra[q], vb = rb[q];
+      const uint4 r0 = philox10(make_uint4(2 * q, i, k, tagv), st.key0, st.key1);
+      uint4 r1w = make_uint4(0, 0, 0, 0);
+      if (l0 + 2 < st.d) r1w = philox10(make_uint4(2 * q + 1, i, k, tagv), st.key0, st.key1);
+      float4 o = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      if (l0 < st.d) {
+        o.x = vary1(va.x, vb.x, r0.x, r0.y, st.prob.lb[l0], st.prob.ub[l0], cross, st);
+        eval_add<M, FAM>(e, l0, o.x);
+      }
+      if (l0 + 1 < st.d) {
+        o.y = vary1(va.y, vb.y, r0.z, r0.w, st.prob.lb[l0 + 1], st.prob.ub[l0 + 1], cross, st);
+        eval_add<M, FAM>(e, l0 + 1, o.y);
+      }
+      if (l0 + 2 < st.d) {
+        o.z = vary1(va.z, vb.z, r1w.x, r1w.y, st.prob.lb[l0 + 2], st.prob.ub[l0 + 2], cross, st);
+        eval_add<M, FAM>(e, l0 + 2, o.z);
+      }
+      if (l0 + 3 < st.d) {
+        o.w = vary1(va.w, vb.w, r1w.z, r1w.w, st.prob.lb[l0 + 3], st.prob.ub[l0 + 3], cross, st);
+        eval_add<M, FAM>(e, l0 + 3, o.w);
+      }
+      ro[q] = o;
+    }
+    const float4 fc = eval_finish<M, FAM>(e, st.prob);
+    st.FCO[p][i] = fc;
+    zv[0] = fc.x;
+    if (M > 1) zv[1] = fc.y;
+    if (M > 2) zv[M - 1] = fc.z;
+  }
+  block_zmin<M>(zv, st.zkey);
+}
+
+// ----------------------------------------------------------------------------
+// Aggregation. PBI (Eq. (7)) with the unit direction u = w / ||w|| stored in W:
+// d1 = |(F - z) . u|, d2 = ||F - z - d1 u||, g = d1 + theta d2. Tchebycheff:
+// max_k w_k |f_k - z_k| with the raw weight stored in W. NaN reads as +inf.
+// ----------------------------------------------------------------------------
+template <int M>
+__device__ __forceinline__ float aggregate(float4 f, float4 w, const float (&z)[M], int agg,
+                                           float theta) {
+  const float df[3] = {f.x - z[0], f.y - (M > 1 ? z[1] : 0.0f), f.z - (M > 2 ? z[M - 1] : 0.0f)};
+  const float ww[3] = {w.x, w.y, w.z};
+  float g;
+  if (agg == 1) {
+    // fmaxf drops NaN operands, so a NaN term is tracked on the side
+    g = -__builtin_huge_valf();
+    bool nan = false;
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+      const float v = ww[k] * fabsf(df[k]);
+      nan = nan || (v != v);
+      g = fmaxf(g, v);
+    }
+    if (nan) g = __builtin_huge_valf();
+  } else {
+    float dot = 0.0f;
+#pragma unroll
+    for (int k = 0; k < M; ++k) dot += df[k] * ww[k];
+    const float d1 = fabsf(dot);
+    float d2 = 0.0f;
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+      const float e = df[k] - d1 * ww[k];
+      d2 += e * e;
+    }
+    g = d1 + theta * sqrtf(d2);
+  }
+  return nan_inf(g);
+}
+
+template <int M>
+__device__ __forceinline__ void load_z(const uint32_t *zkey, float (&z)[M]) {
+#pragma unroll
+  for (int k = 0; k < M; ++k) z[k] = keyf(zkey[k]);
+}
+
+// ----------------------------------------------------------------------------
+// k_op1: offspring cooperation (Alg. 2 OP1, Eq. (11)) at w_i.
+// Population 1 takes off2_i if it is better by the feasibility priority rule
+// (Eq. (8)); population 2 takes off1_i if its aggregation is lower.
+// ----------------------------------------------------------------------------
+template <int M>
+__global__ __launch_bounds__(kBlock) void k_op1(DevState st) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= st.n) return;
+  float z[M];
+  load_z<M>(st.zkey, z);
+  const float4 o1 = st.FCO[0][i], o2 = st.FCO[1][i], w = st.W[i];
+  const float g1 = aggregate<M>(o1, w, z, st.agg, st.theta);
+  const float g2 = aggregate<M>(o2, w, z, st.agg, st.theta);
+  const float c1 = nan_inf(o1.w), c2 = nan_inf(o2.w);
+  const bool s1 = (c2 < c1) || (c2 == c1 && g2 < g1);
+  const bool s2 = g1 < g2;
+  st.FCN[0][i] = s1 ? o2 : o1;
+  st.FCN[1][i] = s2 ? o1 : o2;
+  st.src[i] = static_cast<uint8_t>((s1 ? 1u : 0u) | (s2 ? 2u : 0u));
+}
+
+// ----------------------------------------------------------------------------
+// k_select: OP2 + OP3 (Eqs. (12)-(13)) as a pull over parent slot j of
+// population p. Offspring i qualifies iff j is in B_p(i) and its new offspring
+// is strictly better than parent j at w_j (population 1: lower CV, or equal CV
+// and lower aggregation; population 2: lower aggregation). The winner is the
+// lexicographic minimum over the qualifiers with the first index on ties; every
+// decision uses generation-k parents, and replacements land after all reads of
+// the slot they overwrite.
+// ----------------------------------------------------------------------------
+template <int M>
+__global__ __launch_bounds__(kBlock) void k_select(DevState st) {
+  __shared__ int s_cnt;
+  __shared__ int s_dst[kBlock];
+  __shared__ const float4 *s_srcrow[kBlock];
+  const int L = xcd_tile(blockIdx.x, gridDim.x);
+  const int p = L >= st.nblk ? 1 : 0;
+  const int j = (L - p * st.nblk) * kBlock + threadIdx.x;
+  if (threadIdx.x == 0) s_cnt = 0;
+  __syncthreads();
+  if (j < st.n) {
+    float z[M];
+    load_z<M>(st.zkey, z);
+    const float4 par = st.FC[p][j];
+    const float4 w = st.W[j];
+    float best_g = aggregate<M>(par, w, z, st.agg, st.theta);
+    float best_c = (p == 0) ? nan_inf(par.w) : 0.0f;
+    int win = -1;
+    const int q0 = st.roff[p][j], q1 = st.roff[p][j + 1];
+    const int32_t *rl = st.ridx[p];
+    const float4 *cand = st.FCN[p];
+    for (int q = q0; q < q1; ++q) {
+      const int i = rl[q];
+      const float4 c = cand[i];
+      const float g = aggregate<M>(c, w, z, st.agg, st.theta);
+      const float cv = (p == 0) ? nan_inf(c.w) : 0.0f;
+      const bool better = (cv < best_c) || (cv == best_c && g < best_g);
+      if (better) {
+        best_c = cv;
+        best_g = g;
+        win = i;
+      }
+    }
+    if (st.win[p]) st.win[p][j] = win;
+    if (win >= 0) {
+      st.FC[p][j] = cand[win];
+      const int sp = p ^ ((st.src[win] >> p) & 1);
+      const int slot = atomicAdd(&s_cnt, 1);
+      s_dst[slot] = j;
+      s_srcrow[slot] = reinterpret_cast<const float4 *>(st.XO[sp] + static_cast<size_t>(win) * st.stride);
+    }
+  }
+  __syncthreads();
+  const int n = s_cnt;
+  if (n > 0) {
+    const int nq = st.stride >> 2;
+    float4 *base = reinterpret_cast<float4 *>(st.X[p]);
+    for (int f = threadIdx.x; f < n * nq; f += kBlock) {
+      const int r = f / nq, c = f - r * nq;
+      base[static_cast<size_t>(s_dst[r]) * nq + c] = s_srcrow[r][c];
+    }
+    if (threadIdx.x == 0) atomicAdd(&st.repl[p], static_cast<unsigned long long>(n));
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    // generations completed; next read by the following generation's k_vary
+    st.gen[0] = st.gen[0] + 1u;
+  }
+}
+
+// ----------------------------------------------------------------------------
+// Front: feasible rows of population `pop` that no feasible row dominates
+// (Eq. (5)); candidates staged through LDS tiles.
+// ----------------------------------------------------------------------------
+template <int M>
+__global__ __launch_bounds__(kBlock) void k_front(DevState st, int pop, uint8_t *keep) {
+  __shared__ float4 tile[kBlock];
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  float4 me = make_float4(0, 0, 0, 1);
+  bool alive = false;
+  if (i < st.n) {
+    me = st.FC[pop][i];
+    alive = (me.w == 0.0f);
+  }
+  for (int t0 = 0; t0 < st.n; t0 += kBlock) {
+    if (!__syncthreads_or(alive)) break;
+    const int jj = t0 + threadIdx.x;
+    tile[threadIdx.x] = jj < st.n ? st.FC[pop][jj] : make_float4(0, 0, 0, 1);
+    __syncthreads();
+    const int lim = min(kBlock, st.n - t0);
+    if (alive) {
+      for (int q = 0; q < lim; ++q) {
+        const float4 o = tile[q];
+        if (o.w != 0.0f) continue;
+        bool le = o.x <= me.x, lt = o.x < me.x;
+        if (M > 1) { le = le && o.y <= me.y; lt = lt || o.y < me.y; }
+        if (M > 2) { le = le && o.z <= me.z; lt = lt || o.z < me.z; }
+        if (le && lt) {
+          alive = false;
+          break;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (i < st.n) keep[i] = alive ? 1 : 0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_gather(DevState st, int pop, const int32_t *idx,
+                                                   int32_t count, float *x, float4 *fc) {
+  const int r = blockIdx.x;
+  if (r >= count) return;
+  const int row = idx[r];
+  const float *srcx = st.X[pop] + static_cast<size_t>(row) * st.stride;
+  for (int l = threadIdx.x; l < st.d; l += blockDim.x) x[static_cast<size_t>(r) * st.d + l] = srcx[l];
+  if (threadIdx.x == 0) fc[r] = st.FC[pop][row];
+}
+
+__global__ __launch_bounds__(kBlock) void k_philox(const uint4 *ctr, int64_t n, uint32_t k0,
+                                                   uint32_t k1, uint4 *out) {
+  const int64_t q = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (q < n) out[q] = philox10(ctr[q], k0, k1);
+}
+
+// ----------------------------------------------------------------------------
+// Launchers
+// ----------------------------------------------------------------------------
+#define GMPEA_DISPATCH_MF(KER, GRID, ST, S)                                          \
+  do {                                                                               \
+    if ((ST).m == 2 && (ST).prob.family == 0)                                        \
+      hipLaunchKernelGGL((KER<2, 0>), dim3(GRID), dim3(kBlock), 0, (S), (ST));       \
+    else if ((ST).m == 2)                                                            \
+      hipLaunchKernelGGL((KER<2, 1>), dim3(GRID), dim3(kBlock), 0, (S), (ST));       \
+    else                                                                             \
+      hipLaunchKernelGGL((KER<3, 1>), dim3(GRID), dim3(kBlock), 0, (S), (ST));       \
+  } while (0)
+
+#define GMPEA_DISPATCH_M(KER, GRID, S, ...)                                          \
+  do {                                                                               \
+    if (st.m == 2)                                                                   \
+      hipLaunchKernelGGL((KER<2>), dim3(GRID), dim3(kBlock), 0, (S), __VA_ARGS__);   \
+    else                                                                             \
+      hipLaunchKernelGGL((KER<3>), dim3(GRID), dim3(kBlock), 0, (S), __VA_ARGS__);   \
+  } while (0)
+
+hipError_t launch_init(const DevState &st, hipStream_t s) {
+  GMPEA_DISPATCH_MF(k_init, 2 * st.nblk, st, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_phase(const DevState &st, int phase, hipStream_t s) {
+  if (phase == 0)
+    GMPEA_DISPATCH_MF(k_vary, 2 * st.nblk, st, s);
+  else if (phase == 1)
+    GMPEA_DISPATCH_M(k_op1, st.nblk, s, st);
+  else
+    GMPEA_DISPATCH_M(k_select, 2 * st.nblk, s, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_generation(const DevState &st, hipStream_t s) {
+  for (int phase = 0; phase < kPhases; ++phase) {
+    hipError_t e = launch_phase(st, phase, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_front_flags(const DevState &st, int pop, uint8_t *keep, hipStream_t s) {
+  GMPEA_DISPATCH_M(k_front, st.nblk, s, st, pop, keep);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather(const DevState &st, int pop, const int32_t *idx, int32_t count, float *x,
+                         float4 *fc, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather, dim3(count), dim3(64), 0, s, st, pop, idx, count, x, fc);
+  return hipGetLastError();
+}
+
+hipError_t launch_philox(const uint32_t *ctr, int64_t n, uint32_t k0, uint32_t k1, uint32_t *out,
+                         hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int64_t grid = (n + kBlock - 1) / kBlock;
+  hipLaunchKernelGGL(k_philox, dim3(static_cast<unsigned>(grid)), dim3(kBlock), 0, s,
+                     reinterpret_cast<const uint4 *>(ctr), n, k0, k1, reinterpret_cast<uint4 *>(out));
+  return hipGetLastError();
+}
+
+}  // namespace gmpea

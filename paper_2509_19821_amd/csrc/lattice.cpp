@@ -1,0 +1,156 @@
+// Reference vectors, neighbourhoods and reverse neighbourhood lists (host side).
+//
+// W: the Das-Dennis simplex lattice (the "uniform reference vectors" input of
+// Alg. 1). Rows are k / H for every k in N^m with sum H, enumerated in ascending
+// lexicographic order of (k_1 .. k_{m-1}); H is the smallest value whose count
+// C(H + m - 1, m - 1) reaches the requested population size.
+//
+// B: the t nearest reference vectors of each subproblem (Alg. 1 "neighbours
+// initialization"; t1 = T/2 and t2 = 2T in the parameter settings), ordered by
+// exact integer lattice distance sum_a (k_i,a - k_j,a)^2 with ties broken by
+// ascending index, so subproblem i itself comes first.
+//
+// Instead of scanning all N points per subproblem, the search walks the lattice:
+// it enumerates the points whose leading m - 1 coordinates lie within a box of
+// half-width R around k_i, ranks them directly, and grows R until the t-th
+// nearest found lies within distance R. Every lattice point within distance R
+// lies inside the box, so no closer point (or equal-distance point with a
+// smaller index) can be missed. O(N (2R + 1)^(m-1) log) instead of O(N^2).
+#include <algorithm>
+#include <cmath>
+#include <thread>
+
+#include "gmpea_internal.hpp"
+
+namespace gmpea {
+
+int64_t dd_count(int32_t m, int32_t H) {
+  // C(H + m - 1, m - 1), exact in 64-bit for the supported sizes
+  int64_t c = 1;
+  for (int32_t j = 1; j <= m - 1; ++j) c = c * (H + j) / j;
+  return c;
+}
+
+int32_t dd_divisions(int32_t m, int64_t n_req) {
+  int32_t H = 1;
+  while (dd_count(m, H) < n_req) ++H;
+  return H;
+}
+
+void dd_lattice(int32_t m, int32_t H, std::vector<int32_t> &K) {
+  const int64_t n = dd_count(m, H);
+  K.assign(static_cast<size_t>(n) * m, 0);
+  std::vector<int32_t> cur(m, 0);
+  // odometer over (k_1 .. k_{m-1}) in lexicographic order; k_m takes the rest
+  cur[m - 1] = H;
+  for (int64_t row = 0; row < n; ++row) {
+    for (int32_t a = 0; a < m; ++a) K[row * m + a] = cur[a];
+    // advance: increase the last leading coordinate that still has room
+    int32_t a = m - 2;
+    while (a >= 0) {
+      int32_t used = 0;
+      for (int32_t b = 0; b <= a; ++b) used += cur[b];
+      if (used < H) break;
+      --a;
+    }
+    if (a < 0) break;
+    cur[a] += 1;
+    for (int32_t b = a + 1; b < m - 1; ++b) cur[b] = 0;
+    int32_t used = 0;
+    for (int32_t b = 0; b < m - 1; ++b) used += cur[b];
+    cur[m - 1] = H - used;
+  }
+}
+
+// Position of composition k in the enumeration above.
+static int64_t dd_rank(const int32_t *k, int32_t m, int32_t H) {
+  int64_t r = 0;
+  int32_t left = H;
+  for (int32_t a = 0; a < m - 1; ++a) {
+    for (int32_t v = 0; v < k[a]; ++v) r += dd_count(m - a - 1, left - v);
+    left -= k[a];
+  }
+  return r;
+}
+
+namespace {
+struct Cand {
+  int64_t dist;
+  int32_t idx;
+  bool operator<(const Cand &o) const { return dist < o.dist || (dist == o.dist && idx < o.idx); }
+};
+}  // namespace
+
+static void knn_rows(const std::vector<int32_t> &K, int32_t m, int32_t H, int32_t t, int64_t lo,
+                     int64_t hi, std::vector<int32_t> &B) {
+  std::vector<Cand> cand;
+  std::vector<int32_t> kk(m), off(m > 1 ? m - 1 : 1);
+  const int32_t lead = m - 1;
+  for (int64_t i = lo; i < hi; ++i) {
+    const int32_t *ki = &K[i * m];
+    int32_t R = 1;
+    while (R * R < t) ++R;
+    for (;;) {
+      cand.clear();
+      // enumerate offsets in [-R, R]^(m-1)
+      for (int32_t a = 0; a < lead; ++a) off[a] = -R;
+      for (;;) {
+        int32_t sum = 0;
+        bool ok = true;
+        for (int32_t a = 0; a < lead; ++a) {
+          kk[a] = ki[a] + off[a];
+          if (kk[a] < 0 || kk[a] > H) ok = false;
+          sum += kk[a];
+        }
+        kk[m - 1] = H - sum;
+        if (ok && kk[m - 1] >= 0 && kk[m - 1] <= H) {
+          int64_t dist = 0;
+          for (int32_t a = 0; a < m; ++a) {
+            int64_t df = int64_t(kk[a]) - ki[a];
+            dist += df * df;
+          }
+          cand.push_back({dist, static_cast<int32_t>(dd_rank(kk.data(), m, H))});
+        }
+        int32_t a = lead - 1;
+        while (a >= 0 && off[a] == R) off[a--] = -R;
+        if (a < 0) break;
+        ++off[a];
+      }
+      if (static_cast<int32_t>(cand.size()) >= t) {
+        std::partial_sort(cand.begin(), cand.begin() + t, cand.end());
+        if (cand[t - 1].dist <= int64_t(R) * R) {
+          for (int32_t r = 0; r < t; ++r) B[i * t + r] = cand[r].idx;
+          break;
+        }
+      }
+      ++R;
+    }
+  }
+}
+
+void lattice_knn(const std::vector<int32_t> &K, int32_t m, int32_t H, int32_t t,
+                 std::vector<int32_t> &B) {
+  const int64_t n = static_cast<int64_t>(K.size()) / m;
+  B.assign(static_cast<size_t>(n) * t, 0);
+  unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  if (n < 4096) nt = 1;
+  std::vector<std::thread> pool;
+  for (unsigned w = 0; w < nt; ++w) {
+    int64_t lo = n * w / nt, hi = n * (w + 1) / nt;
+    pool.emplace_back([&, lo, hi] { knn_rows(K, m, H, t, lo, hi, B); });
+  }
+  for (auto &th : pool) th.join();
+}
+
+void reverse_lists(const std::vector<int32_t> &B, int32_t n, int32_t t, std::vector<int32_t> &off,
+                   std::vector<int32_t> &idx) {
+  off.assign(static_cast<size_t>(n) + 1, 0);
+  for (size_t q = 0; q < static_cast<size_t>(n) * t; ++q) off[B[q] + 1]++;
+  for (int32_t j = 0; j < n; ++j) off[j + 1] += off[j];
+  idx.assign(static_cast<size_t>(n) * t, 0);
+  std::vector<int32_t> fill(off.begin(), off.end() - 1);
+  for (int32_t i = 0; i < n; ++i)  // ascending i keeps every list sorted
+    for (int32_t r = 0; r < t; ++r) idx[fill[B[static_cast<size_t>(i) * t + r]]++] = i;
+}
+
+}  // namespace gmpea

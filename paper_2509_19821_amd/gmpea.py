@@ -1,0 +1,281 @@
+"""ctypes binding of libgmpea.so (include/gmpea.h). Argument marshalling only.
+
+PyTorch supplies device memory (its caching allocator, through the library's
+allocator hook) and the stream the work is enqueued on; nothing else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_PKG, "_build", "libgmpea.so")
+
+FAMILY_CURVE, FAMILY_SPHERE = 0, 1
+AGG_PBI, AGG_TCHE = 0, 1
+FRONT_FEASIBLE_ND, FRONT_POP1, FRONT_POP2 = 0, 1, 2
+BUF = {"X": 0, "F": 1, "CV": 2, "XOFF": 3, "FOFF": 4, "CVOFF": 5, "Z": 6, "GEN": 7, "W": 8,
+       "B": 9, "MATE": 10, "OP1": 11, "WIN": 12}
+STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ECAPACITY", -5: "ESTATE",
+          -6: "EUNSUPPORTED"}
+EXPORTS = ["gmpea_init", "gmpea_step", "gmpea_run", "gmpea_front", "gmpea_get_info", "gmpea_read",
+           "gmpea_write", "gmpea_destroy", "gmpea_last_error", "gmpea_profile", "gmpea_philox"]
+PHASES = ("vary", "op1", "select")
+
+
+class GmpeaError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__("%s (%d): %s" % (STATUS.get(status, "?"), status, message))
+        self.status = status
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("family", ctypes.c_int32), ("m", ctypes.c_int32), ("d", ctypes.c_int32),
+                ("lb", ctypes.c_void_p), ("ub", ctypes.c_void_p), ("n_ring", ctypes.c_int32),
+                ("ring_center", ctypes.c_void_p), ("ring_radius", ctypes.c_void_p),
+                ("has_sum_lower", ctypes.c_int32), ("sum_lower", ctypes.c_double),
+                ("n_eq", ctypes.c_int32), ("eq_tol", ctypes.c_double)]
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("n_req", ctypes.c_int32), ("T", ctypes.c_int32), ("t1", ctypes.c_int32),
+                ("t2", ctypes.c_int32), ("agg", ctypes.c_int32), ("theta", ctypes.c_double),
+                ("eta_c", ctypes.c_double), ("eta_m", ctypes.c_double), ("pc", ctypes.c_double),
+                ("pm", ctypes.c_double), ("seed", ctypes.c_uint64), ("record", ctypes.c_int32)]
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class Allocator(ctypes.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("ctx", ctypes.c_void_p)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("m", ctypes.c_int32), ("d", ctypes.c_int32),
+                ("t1", ctypes.c_int32), ("t2", ctypes.c_int32), ("H", ctypes.c_int32),
+                ("generation", ctypes.c_int64), ("z", ctypes.c_float * 3),
+                ("replaced", ctypes.c_int64 * 2), ("feasible_frac", ctypes.c_double),
+                ("device_bytes", ctypes.c_size_t)]
+
+
+_lib = None
+
+
+def lib_path() -> str:
+    return _LIB_PATH
+
+
+def lib():
+    """The loaded HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise ImportError("libgmpea.so is not built (expected at %s); run "
+                              "`python -m paper_2509_19821_amd.build`" % _LIB_PATH)
+        L = ctypes.CDLL(_LIB_PATH)
+        vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+        L.gmpea_init.argtypes = [ctypes.POINTER(Problem), ctypes.POINTER(Config),
+                                 ctypes.POINTER(Allocator), vp, ctypes.POINTER(vp)]
+        L.gmpea_step.argtypes = [vp, i32]
+        L.gmpea_run.argtypes = [vp, i32, ctypes.c_double, ctypes.POINTER(i32)]
+        L.gmpea_front.argtypes = [vp, i32, i32, vp, vp, vp, vp, ctypes.POINTER(i32)]
+        L.gmpea_get_info.argtypes = [vp, ctypes.POINTER(Info)]
+        L.gmpea_read.argtypes = [vp, i32, i32, vp, i64]
+        L.gmpea_write.argtypes = [vp, i32, i32, vp, i64]
+        L.gmpea_destroy.argtypes = [vp]
+        L.gmpea_destroy.restype = None
+        L.gmpea_last_error.restype = ctypes.c_char_p
+        L.gmpea_philox.argtypes = [vp, i64, ctypes.c_uint64, vp, vp]
+        L.gmpea_profile.argtypes = [vp, i32, vp]
+        for name in EXPORTS:
+            if name not in ("gmpea_destroy", "gmpea_last_error"):
+                getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != 0:
+        raise GmpeaError(status, lib().gmpea_last_error().decode(errors="replace"))
+
+
+def _torch_allocator():
+    """Allocator hook over torch's caching allocator (device memory only)."""
+    import torch
+
+    def _alloc(nbytes, ctx):
+        try:
+            return int(torch.cuda.caching_allocator_alloc(int(nbytes)))
+        except Exception:  # out of memory -> NULL -> GMPEA_ENOMEM
+            return None
+
+    def _free(ptr, ctx):
+        torch.cuda.caching_allocator_delete(int(ptr))
+
+    fa, ff = ALLOC_FN(_alloc), FREE_FN(_free)
+    return Allocator(fa, ff, None), (fa, ff)
+
+
+def _f64(a, n=None):
+    arr = np.ascontiguousarray(np.asarray(a, dtype=np.float64).reshape(-1))
+    if n is not None and arr.size != n:
+        raise ValueError("expected %d values, got %d" % (n, arr.size))
+    return arr
+
+
+class Gmpea:
+    """One GMPEA instance resident on the GPU.
+
+    problem: dict with family, m, d, lb, ub, ring_center (n_ring x m),
+             ring_radius, has_sum_lower, sum_lower, n_eq, eq_tol.
+    config:  dict with n_req, T, t1, t2, agg, theta, eta_c, eta_m, pc, pm, seed
+             (and optionally record).
+    stream:  a torch.cuda.Stream, a raw hipStream_t integer, or None for torch's
+             current stream.
+    """
+
+    def __init__(self, problem: dict, config: dict, stream=None, use_torch_allocator=True,
+                 record: bool = False):
+        L = lib()
+        self._h = None
+        m, d = int(problem["m"]), int(problem["d"])
+        nr = int(np.asarray(problem["ring_radius"]).size)
+        self._keep = [_f64(problem["lb"], d), _f64(problem["ub"], d),
+                      _f64(problem["ring_center"], nr * m), _f64(problem["ring_radius"], nr)]
+        lb, ub, rc, rr = self._keep
+        self._prob = Problem(int(problem["family"]), m, d, lb.ctypes.data, ub.ctypes.data, nr,
+                             rc.ctypes.data if nr else None, rr.ctypes.data if nr else None,
+                             int(problem["has_sum_lower"]), float(problem["sum_lower"]),
+                             int(problem["n_eq"]), float(problem["eq_tol"]))
+        c = config
+        self._cfg = Config(int(c["n_req"]), int(c["T"]), int(c.get("t1", 0)), int(c.get("t2", 0)),
+                           int(c.get("agg", 0)), float(c.get("theta", 0.0)),
+                           float(c.get("eta_c", 0.0)), float(c.get("eta_m", 0.0)),
+                           float(c.get("pc", 0.0)), float(c.get("pm", 0.0)),
+                           int(c["seed"]) & 0xFFFFFFFFFFFFFFFF,
+                           1 if (record or c.get("record", 0)) else 0)
+        self._alloc = None
+        if use_torch_allocator:
+            self._alloc, self._cb = _torch_allocator()
+        self.stream = self._stream_handle(stream)
+        h = ctypes.c_void_p()
+        _check(L.gmpea_init(ctypes.byref(self._prob), ctypes.byref(self._cfg),
+                            ctypes.byref(self._alloc) if self._alloc else None,
+                            ctypes.c_void_p(self.stream) if self.stream else None, ctypes.byref(h)))
+        self._h = h
+        inf = self.info()
+        self.n, self.m, self.d = inf["n"], inf["m"], inf["d"]
+        self.t = (inf["t1"], inf["t2"])
+
+    @staticmethod
+    def _stream_handle(stream):
+        if stream is None:
+            import torch
+            return int(torch.cuda.current_stream().cuda_stream)
+        if isinstance(stream, int):
+            return stream
+        return int(stream.cuda_stream)
+
+    # -- lifecycle ----------------------------------------------------------
+    def close(self):
+        if self._h is not None:
+            lib().gmpea_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    @property
+    def handle(self):
+        return self._h
+
+    # -- calls ----------------------------------------------------------------
+    def step(self, n_gen: int = 1):
+        _check(lib().gmpea_step(self._h, int(n_gen)))
+
+    def run(self, max_gen: int, time_limit_s: float = 0.0) -> int:
+        done = ctypes.c_int32(0)
+        _check(lib().gmpea_run(self._h, int(max_gen), float(time_limit_s), ctypes.byref(done)))
+        return int(done.value)
+
+    def front(self, what: int = FRONT_FEASIBLE_ND) -> dict:
+        cnt = ctypes.c_int32(0)
+        st = lib().gmpea_front(self._h, int(what), 0, None, None, None, None, ctypes.byref(cnt))
+        if st not in (0, -4):
+            _check(st)
+        n = int(cnt.value)
+        x = np.empty((n, self.d), dtype=np.float32)
+        f = np.empty((n, self.m), dtype=np.float32)
+        cv = np.empty(n, dtype=np.float32)
+        idx = np.empty(n, dtype=np.int32)
+        if n:
+            _check(lib().gmpea_front(self._h, int(what), n, x.ctypes.data, f.ctypes.data,
+                                     cv.ctypes.data, idx.ctypes.data, ctypes.byref(cnt)))
+        return {"x": x, "f": f, "cv": cv, "idx": idx}
+
+    def profile(self, n_gen: int) -> dict:
+        """Mean per-kernel durations (ms) over n_gen generations, HIP events on
+        the handle's stream."""
+        ms = np.zeros(3, dtype=np.float32)
+        _check(lib().gmpea_profile(self._h, int(n_gen), ms.ctypes.data))
+        return dict(zip(PHASES, (float(v) for v in ms)))
+
+    def info(self) -> dict:
+        inf = Info()
+        _check(lib().gmpea_get_info(self._h, ctypes.byref(inf)))
+        return {"n": inf.n, "m": inf.m, "d": inf.d, "t1": inf.t1, "t2": inf.t2, "H": inf.H,
+                "generation": int(inf.generation), "z": np.array(inf.z[:inf.m], dtype=np.float32),
+                "replaced": (int(inf.replaced[0]), int(inf.replaced[1])),
+                "feasible_frac": float(inf.feasible_frac), "device_bytes": int(inf.device_bytes)}
+
+    def _shape(self, name: str, pop: int):
+        n, m, d = self.n, self.m, self.d
+        return {"X": ((n, d), np.float32), "XOFF": ((n, d), np.float32), "F": ((n, m), np.float32),
+                "FOFF": ((n, m), np.float32), "CV": ((n,), np.float32), "CVOFF": ((n,), np.float32),
+                "Z": ((m,), np.float32), "GEN": ((1,), np.int64), "W": ((n, m), np.float32),
+                "B": ((n, self.t[pop]), np.int32), "MATE": ((n, 2), np.int32),
+                "OP1": ((n,), np.uint8), "WIN": ((n,), np.int32)}[name]
+
+    def read(self, name: str, pop: int = 0) -> np.ndarray:
+        shape, dt = self._shape(name, pop)
+        out = np.empty(shape, dtype=dt)
+        _check(lib().gmpea_read(self._h, BUF[name], int(pop), out.ctypes.data, int(out.size)))
+        return out
+
+    def write(self, name: str, arr, pop: int = 0):
+        shape, dt = self._shape(name, pop)
+        a = np.ascontiguousarray(np.asarray(arr, dtype=dt).reshape(shape))
+        _check(lib().gmpea_write(self._h, BUF[name], int(pop), a.ctypes.data, int(a.size)))
+
+    def state(self) -> dict:
+        """Snapshot of both populations, the ideal point and the generation count."""
+        return {"X": [self.read("X", p) for p in range(2)], "F": [self.read("F", p) for p in range(2)],
+                "CV": [self.read("CV", p) for p in range(2)], "z": self.read("Z"),
+                "gen": int(self.read("GEN")[0])}
+
+    def load_state(self, s: dict):
+        for p in range(2):
+            self.write("X", s["X"][p], p)
+            self.write("F", s["F"][p], p)
+            self.write("CV", s["CV"][p], p)
+        self.write("Z", s["z"])
+        self.write("GEN", np.array([s["gen"]], dtype=np.int64))
+
+
+def philox(ctr_dev_ptr: int, n: int, seed: int, out_dev_ptr: int, stream: int = 0):
+    """Philox4x32-10 blocks on the device (pointers to n x 4 uint32 each)."""
+    _check(lib().gmpea_philox(ctypes.c_void_p(ctr_dev_ptr), int(n), int(seed) & 0xFFFFFFFFFFFFFFFF,
+                              ctypes.c_void_p(out_dev_ptr), ctypes.c_void_p(stream) if stream else None))

@@ -1,0 +1,91 @@
+"""The C-ABI library loads, exports every function include/gmpea.h declares, and
+rejects invalid input before any GPU work (no compute calls: CPU only)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import cmop_inputs as ci
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "gmpea.h")
+
+
+@pytest.fixture(scope="module")
+def glib():
+    from paper_2509_19821_amd import build as B
+    if not os.path.exists(B.LIB):
+        B.build()
+    import paper_2509_19821_amd as g
+    return g
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(gmpea_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for want in ("gmpea_init", "gmpea_step", "gmpea_run", "gmpea_front"):
+        assert want in names
+
+
+def test_library_exports_every_declared_symbol(glib):
+    L = ctypes.CDLL(glib.lib_path())
+    for name in _declared():
+        assert hasattr(L, name), name
+
+
+def _init(glib, prob, cfg):
+    """Call gmpea_init directly; validation errors return before any HIP call."""
+    from paper_2509_19821_amd import gmpea as G
+    L = G.lib()
+    m, d = prob["m"], prob["d"]
+    keep = [np.ascontiguousarray(prob["lb"], dtype=np.float64),
+            np.ascontiguousarray(prob["ub"], dtype=np.float64),
+            np.ascontiguousarray(prob["ring_center"], dtype=np.float64).reshape(-1),
+            np.ascontiguousarray(prob["ring_radius"], dtype=np.float64)]
+    nr = keep[3].size
+    P = G.Problem(prob["family"], m, d, keep[0].ctypes.data, keep[1].ctypes.data, nr,
+                  keep[2].ctypes.data if nr else None, keep[3].ctypes.data if nr else None,
+                  prob["has_sum_lower"], prob["sum_lower"], prob["n_eq"], prob["eq_tol"])
+    C = G.Config(cfg["n_req"], cfg["T"], cfg["t1"], cfg["t2"], cfg["agg"], cfg["theta"],
+                 cfg["eta_c"], cfg["eta_m"], cfg["pc"], cfg["pm"], cfg["seed"], 0)
+    h = ctypes.c_void_p()
+    st = L.gmpea_init(ctypes.byref(P), ctypes.byref(C), None, None, ctypes.byref(h))
+    return st, L.gmpea_last_error().decode()
+
+
+@pytest.mark.parametrize("mutate,code", [
+    (lambda p, c: c.update(T=400), -1),                      # t2 = 800 > N = 100
+    (lambda p, c: c.update(t1=101), -1),                     # t1 > N
+    (lambda p, c: c.update(n_req=1), -1),                    # fewer than two subproblems
+    (lambda p, c: p.update(ub=np.zeros(10)), -1),            # lb >= ub
+    (lambda p, c: p.update(m=4), -6),                        # beyond the objectives supported
+    (lambda p, c: p.update(family=7), -1),                   # unknown family
+    (lambda p, c: c.update(agg=5), -1),                      # unknown aggregation
+    (lambda p, c: c.update(pm=1.5), -1),                     # probability above 1
+    (lambda p, c: p.update(ring_center=np.zeros((9, 2)), ring_radius=np.zeros(9)), -1),
+])
+def test_init_rejects_invalid_input(glib, mutate, code):
+    prob, cfg, _ = ci.workload_small(0)
+    mutate(prob, cfg)
+    st, msg = _init(glib, prob, cfg)
+    assert st == code, msg
+    assert msg
+
+
+def test_calls_on_dead_handles_are_rejected(glib):
+    from paper_2509_19821_amd import gmpea as G
+    L = G.lib()
+    bogus = ctypes.c_void_p(0x1234)
+    assert L.gmpea_step(bogus, 1) == -5
+    assert L.gmpea_step(None, 1) == -5
+    cnt = ctypes.c_int32(0)
+    assert L.gmpea_front(bogus, 0, 0, None, None, None, None, ctypes.byref(cnt)) == -5
+    L.gmpea_destroy(bogus)  # no-op
+    L.gmpea_destroy(None)

@@ -1,0 +1,310 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Per generation the comparison is teacher-forced: the oracle runs generation k
+from the GPU's own pre-state (FP32 values, exact in FP64) and both sides'
+results are compared.
+  - RNG words, initial decision vectors (unit box) and mating picks: bit-exact.
+  - Offspring X, F, CV and the ideal point: |gpu - ref| <= 1e-5 max(1, |ref|).
+  - OP1 switches and the winner of each parent slot: identical wherever the
+    oracle marks the decision robust (FP64 margin above 1e-4 relative, exact
+    CV zeros with slack); every other decision must still be a valid one.
+  - The population after replacement: within tolerance on robust slots.
+Sizes span several 256-row tiles with ragged tails (N = 100, 1035, ...), d not
+a multiple of 4, both aggregations, the equality constraint, unit
+neighbourhoods, and the full large workload once.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import cmop_inputs as ci
+from oracle import core
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+def _log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _err(gpu, ref):
+    gpu = np.asarray(gpu, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    if gpu.size == 0:
+        return 0.0
+    return float(np.max(np.abs(gpu - ref) / np.maximum(1.0, np.abs(ref))))
+
+
+@pytest.fixture(scope="module")
+def G():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible MI355X"
+    import paper_2509_19821_amd as g
+    return g
+
+
+def _pair(prob, cfg, record=True):
+    import paper_2509_19821_amd as g
+    gp = g.Gmpea(prob, cfg, record=record)
+    o = core.Oracle(prob, cfg, init=False)
+    assert gp.n == o.N
+    return gp, o
+
+
+def _teacher_forced(gp, o, gens, label):
+    """Run `gens` teacher-forced generations; returns the ambiguous-slot share."""
+    amb_total, slots = 0, 0
+    for _ in range(gens):
+        S = gp.state()
+        o.set_state(S["X"][0], S["X"][1], S["z"].astype(np.float64), gen=S["gen"])
+        gp.step(1)
+        dbg = o.step(debug=True)
+        N = o.N
+        for p in range(2):
+            mate = gp.read("MATE", p)
+            assert np.array_equal(mate, dbg["mate"][p]), (label, "mate", p)
+            assert _err(gp.read("XOFF", p), dbg["Xo"][p]) <= TOL, (label, "Xo", p)
+            assert _err(gp.read("FOFF", p), dbg["Fo"][p]) <= TOL, (label, "Fo", p)
+            assert _err(gp.read("CVOFF", p), dbg["CVo"][p]) <= TOL, (label, "CVo", p)
+        assert _err(gp.read("Z"), o.z) <= TOL, (label, "z")
+        for p in range(2):
+            sw = gp.read("OP1", p)
+            rob = dbg["op1_rob"][p].astype(bool)
+            assert np.array_equal(sw[rob], dbg["op1"][p][rob]), (label, "op1", p)
+            win = gp.read("WIN", p)
+            wr = dbg["win_rob"][p].astype(bool)
+            bad = np.nonzero(win[wr] != dbg["win"][p][wr])[0]
+            assert bad.size == 0, (label, "win", p, np.nonzero(wr)[0][bad[:5]])
+            # every decision, robust or not, is a valid one: -1 or a reverse neighbour
+            B = o.B[p]
+            for j in np.nonzero(~wr)[0]:
+                i = win[j]
+                assert i == -1 or j in B[i], (label, "invalid winner", p, j, i)
+            X = gp.read("X", p)
+            F = gp.read("F", p)
+            CV = gp.read("CV", p)
+            assert _err(X[wr], o.X[p][wr]) <= TOL, (label, "X after", p)
+            assert _err(F[wr], o.F[p][wr]) <= TOL, (label, "F after", p)
+            assert _err(CV[wr], o.CV[p][wr]) <= TOL, (label, "CV after", p)
+            amb_total += int((~wr).sum())
+            slots += N
+    frac = amb_total / max(1, slots)
+    _log("%s: ambiguous slot decisions %d of %d (%.4f%%)" % (label, amb_total, slots, 100 * frac))
+    return frac
+
+
+def test_philox_device_bit_exact(G):
+    import torch
+    n = 1 << 20
+    rng = np.random.default_rng(0)
+    ctr = rng.integers(0, 2**32, size=(n, 4), dtype=np.uint64).astype(np.uint32)
+    seed = 0x0123456789ABCDEF
+    want = core.philox(ctr, np.array([seed & 0xFFFFFFFF, seed >> 32], dtype=np.uint32))
+    dctr = torch.from_numpy(ctr.view(np.int32)).cuda()
+    dout = torch.empty_like(dctr)
+    G.philox(dctr.data_ptr(), n, seed, dout.data_ptr(), 0)
+    got = dout.cpu().numpy().view(np.uint32)
+    assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("which", ["small", "medium"])
+def test_structures_and_init(G, which):
+    prob, cfg, _ = ci.WORKLOADS[which](0)
+    gp, o = _pair(prob, cfg, record=False)
+    try:
+        assert np.array_equal(gp.read("W"), o.W.astype(np.float32))
+        for p in range(2):
+            assert np.array_equal(gp.read("B", p), o.B[p]), p
+        o.set_state(o.init_x(0), o.init_x(1), None, gen=0)
+        for p in range(2):
+            # the unit box makes X = U exactly in both precisions
+            assert np.array_equal(gp.read("X", p), o.X[p].astype(np.float32)), p
+            assert _err(gp.read("F", p), o.F[p]) <= TOL
+            assert _err(gp.read("CV", p), o.CV[p]) <= TOL
+        assert _err(gp.read("Z"), o.z) <= TOL
+        assert gp.read("GEN")[0] == 0
+    finally:
+        gp.close()
+
+
+def test_neighbourhoods_full_size_sampled(G):
+    prob, cfg, _ = ci.workload_large(0)
+    import paper_2509_19821_amd as g
+    gp = g.Gmpea(prob, cfg, record=False)
+    try:
+        assert gp.n == 100128 and gp.t == (16, 64)
+        H = core.dd_H(3, cfg["n_req"])
+        K = core.dd_lattice(3, H).astype(np.int64)
+        rng = np.random.default_rng(1)
+        rows = np.concatenate([[0, 1, 445, 446, gp.n - 1], rng.integers(0, gp.n, 60)])
+        for p, t in ((0, 16), (1, 64)):
+            B = gp.read("B", p)
+            for i in rows:
+                dist = ((K - K[i]) ** 2).sum(1)
+                order = np.lexsort((np.arange(len(K)), dist))[:t]
+                assert np.array_equal(B[i], order), (p, i)
+    finally:
+        gp.close()
+
+
+@pytest.mark.parametrize("which,agg,seed", [("small", 0, 0), ("small", 1, 1), ("medium", 0, 0),
+                                            ("medium", 1, 2)])
+def test_generation_teacher_forced(G, which, agg, seed):
+    prob, cfg, _ = ci.WORKLOADS[which](seed)
+    cfg["agg"] = agg
+    gp, o = _pair(prob, cfg)
+    try:
+        gp.step(4)
+        frac = _teacher_forced(gp, o, 3, "%s agg=%d seed=%d" % (which, agg, seed))
+        assert frac < 0.02
+    finally:
+        gp.close()
+
+
+def test_generation_equality_and_wide_rows(G):
+    """Large-workload shape (m = 3, d = 100, T = 32, four rings, x1 + x2 = 1 with
+    tolerance 1e-4) at a population the oracle steps quickly."""
+    prob = ci.make_problem(ci.FAMILY_SPHERE, 3, 100, 4, False, True, 5, eq_tol=1e-4)
+    cfg = ci.method_config(3000, 32, 5)
+    gp, o = _pair(prob, cfg)
+    try:
+        gp.step(3)
+        frac = _teacher_forced(gp, o, 2, "d100 equality")
+        assert frac < 0.02
+    finally:
+        gp.close()
+
+
+def test_generation_odd_shapes(G):
+    """Unit neighbourhoods, d = 7 (ragged rows), m = 2 sphere family, pc < 1."""
+    prob = ci.make_problem(ci.FAMILY_SPHERE, 2, 7, 3, True, False, 3)
+    cfg = ci.method_config(300, 2, 3, t1=1, t2=1, pc=0.7)
+    gp, o = _pair(prob, cfg)
+    try:
+        gp.step(2)
+        _teacher_forced(gp, o, 2, "unit neighbourhoods")
+    finally:
+        gp.close()
+    prob = ci.make_problem(ci.FAMILY_CURVE, 2, 7, 1, False, False, 4)
+    cfg = ci.method_config(700, 10, 4, t2=700)  # population 2 sees everyone
+    gp, o = _pair(prob, cfg)
+    try:
+        gp.step(2)
+        _teacher_forced(gp, o, 1, "full neighbourhood")
+    finally:
+        gp.close()
+
+
+def test_generation_full_size_large(G):
+    """One teacher-forced generation of the large workload at full size
+    (N = 100,128 per population, d = 100, t1 = 16, t2 = 64) in the launch
+    configuration the benchmark times."""
+    prob, cfg, _ = ci.workload_large(0)
+    _log("full size: building oracle neighbourhoods")
+    gp, o = _pair(prob, cfg)
+    try:
+        gp.step(2)
+        frac = _teacher_forced(gp, o, 1, "large full size")
+        assert frac < 0.01
+    finally:
+        gp.close()
+
+
+def test_front_matches_bruteforce(G):
+    prob, cfg, K = ci.workload_medium(1)
+    import paper_2509_19821_amd as g
+    gp = g.Gmpea(prob, cfg)
+    try:
+        gp.step(60)
+        fr = gp.front()
+        F = gp.read("F", 0).astype(np.float64)
+        CV = gp.read("CV", 0).astype(np.float64)
+        keep = core.front_mask(F, CV)
+        assert np.array_equal(fr["idx"], np.nonzero(keep)[0])
+        assert np.array_equal(fr["f"], F[keep].astype(np.float32))
+        assert np.array_equal(fr["x"], gp.read("X", 0)[keep])
+        assert np.all(fr["cv"] == 0)
+        allp = gp.front(g.FRONT_POP2)
+        assert np.array_equal(allp["x"], gp.read("X", 1))
+    finally:
+        gp.close()
+
+
+def test_graph_replay_equals_eager(G):
+    import paper_2509_19821_amd as g
+    prob, cfg, _ = ci.workload_medium(3)
+    out = []
+    for chunk in ("0", "16"):
+        os.environ["GMPEA_GRAPH_CHUNK"] = chunk
+        gp = g.Gmpea(prob, cfg)
+        try:
+            gp.step(40)
+            gp.step(7)
+            out.append(gp.state())
+        finally:
+            gp.close()
+    os.environ.pop("GMPEA_GRAPH_CHUNK", None)
+    a, b = out
+    assert a["gen"] == b["gen"] == 47
+    for p in range(2):
+        assert np.array_equal(a["X"][p], b["X"][p])
+        assert np.array_equal(a["F"][p], b["F"][p])
+    assert np.array_equal(a["z"], b["z"])
+
+
+def test_checkpoint_resume_bit_exact(G):
+    import paper_2509_19821_amd as g
+    prob, cfg, _ = ci.workload_small(5)
+    gp = g.Gmpea(prob, cfg)
+    try:
+        gp.step(10)
+        snap = gp.state()
+        gp.step(15)
+        ref = gp.state()
+    finally:
+        gp.close()
+    gp = g.Gmpea(prob, cfg)
+    try:
+        gp.load_state(snap)
+        gp.step(15)
+        got = gp.state()
+    finally:
+        gp.close()
+    assert got["gen"] == ref["gen"] == 25
+    for p in range(2):
+        assert np.array_equal(got["X"][p], ref["X"][p])
+        assert np.array_equal(got["CV"][p], ref["CV"][p])
+
+
+def test_run_time_limit(G):
+    import paper_2509_19821_amd as g
+    prob, cfg, _ = ci.workload_medium(0)
+    gp = g.Gmpea(prob, cfg)
+    try:
+        assert gp.run(50) == 50
+        assert gp.read("GEN")[0] == 50
+        assert gp.run(10**6, time_limit_s=1e-9) == 0   # deadline already passed
+        assert gp.read("GEN")[0] == 50
+        n = gp.run(10**6, time_limit_s=0.05)
+        assert 1 <= n < 10**6
+        assert gp.read("GEN")[0] == 50 + n
+    finally:
+        gp.close()
+
+
+def test_record_disabled_rejects_decision_reads(G):
+    import paper_2509_19821_amd as g
+    prob, cfg, _ = ci.workload_small(0)
+    gp = g.Gmpea(prob, cfg, record=False)
+    try:
+        with pytest.raises(g.GmpeaError):
+            gp.read("WIN", 0)
+        cnt = gp.front()
+        assert cnt["x"].shape[1] == 10
+    finally:
+        gp.close()
