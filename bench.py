@@ -111,28 +111,25 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
-    import torch
-
     import cmop_inputs as ci
     import paper_2509_19821_amd as g
 
-    torch.cuda.set_device(0)
     prob, cfg, K_total = ci.workload_large(0)
     log("bench: init large workload")
     t0 = time.perf_counter()
     gp = g.Gmpea(prob, cfg)
-    torch.cuda.synchronize()
+    gp.sync()
     log("bench: init %.2f s, N=%d t=%s" % (time.perf_counter() - t0, gp.n, gp.t))
     n, m, d = gp.n, gp.m, gp.d
 
     gp.step(args.warmup)
-    torch.cuda.synchronize()
+    gp.sync()
     log("bench: warmup done")
     r0 = gp.info()["replaced"]
-    torch.cuda.synchronize()
+    gp.sync()  # one process, one GPU: the barrier is this device synchronisation
     t0 = time.perf_counter()
     gp.step(args.steps)
-    torch.cuda.synchronize()
+    gp.sync()
     el = time.perf_counter() - t0
     r1 = gp.info()["replaced"]
     value = 2.0 * n * args.steps / el

@@ -160,6 +160,8 @@ typedef struct {
  * evaluate them and set the ideal point to their minimum (Alg. 1 initialisation).
  * hip_stream: a hipStream_t, or NULL for a stream owned by the handle. Work is
  * enqueued on that stream; the call returns once the handle is ready.
+ * The HIP runtime in the process must be at least as new as the HIP toolchain
+ * the library was built with; otherwise EUNSUPPORTED (nothing is launched).
  * Errors: EINVAL (bad sizes: m, d < 2 for the curve family, lb >= ub, t > N,
  * n_ring out of range, ...), EUNSUPPORTED (m > GMPEA_MAX_M), ENOMEM, EHIP. */
 gmpea_status gmpea_init(const gmpea_problem *problem, const gmpea_config *config,
@@ -183,6 +185,9 @@ gmpea_status gmpea_run(gmpea_t h, int32_t max_gen, double time_limit_s, int32_t 
  * if it exceeds capacity nothing is copied and ECAPACITY is returned. */
 gmpea_status gmpea_front(gmpea_t h, int32_t what, int32_t capacity, float *x, float *f,
                          float *cv, int32_t *idx, int32_t *count);
+
+/* Wait until every generation enqueued on the handle's stream has finished. */
+gmpea_status gmpea_sync(gmpea_t h);
 
 /* Sizes, generation count, ideal point and counters (synchronises). */
 gmpea_status gmpea_get_info(gmpea_t h, gmpea_info *info);

@@ -1,6 +1,7 @@
 """Build the HIP library (gfx950) in-tree: paper_2509_19821_amd/_build/libgmpea.so."""
 from __future__ import annotations
 
+import json
 import os
 import shutil
 import subprocess
@@ -51,7 +52,23 @@ def build(verbose: bool = False, jobs: int = 3) -> str:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
+    with open(os.path.join(OUT_DIR, "build_info.json"), "w") as fh:
+        json.dump({"hip_version": hip_version(), "arch": ARCH}, fh)
     return LIB
+
+
+def hip_version() -> str:
+    """major.minor.patch of the HIP toolchain (from hip_version.h)."""
+    inc = os.path.join(os.path.dirname(os.path.dirname(hipcc())), "include", "hip", "hip_version.h")
+    vals = {}
+    with open(inc) as fh:
+        for line in fh:
+            parts = line.split()
+            if len(parts) == 3 and parts[0] == "#define" and parts[1] in (
+                    "HIP_VERSION_MAJOR", "HIP_VERSION_MINOR", "HIP_VERSION_PATCH"):
+                vals[parts[1]] = parts[2]
+    return "%s.%s.%s" % (vals["HIP_VERSION_MAJOR"], vals["HIP_VERSION_MINOR"],
+                         vals["HIP_VERSION_PATCH"])
 
 
 def _wait(pr):

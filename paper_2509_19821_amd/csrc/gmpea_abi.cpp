@@ -10,6 +10,8 @@
 #include <unordered_set>
 #include <vector>
 
+#include <hip/hip_version.h>
+
 #include "gmpea.h"
 #include "gmpea_internal.hpp"
 
@@ -215,11 +217,36 @@ gmpea_status h2d(gmpea_s *h, void *dst, const T *src, size_t n, const char *what
   return sync(h, what);
 }
 
+// The library must run on a HIP runtime at least as new as the toolchain it was
+// built with (HIP keeps old binaries working on newer runtimes, not the reverse).
+// A process that already loaded an older runtime under the same soname (for
+// example one bundled with a framework) is refused instead of crashing later.
+gmpea_status check_runtime(const char *who) {
+  int rt = 0;
+  hipError_t e = hipRuntimeGetVersion(&rt);
+  if (e != hipSuccess) return hip_fail(e, who);
+  const int built = HIP_VERSION_MAJOR * 100 + HIP_VERSION_MINOR;
+  const int have = (rt / 10000000) * 100 + (rt / 100000) % 100;
+  if (have < built)
+    return fail(GMPEA_EUNSUPPORTED,
+                std::string(who) + ": HIP runtime " + std::to_string(have / 100) + "." +
+                    std::to_string(have % 100) + " is older than the HIP " +
+                    std::to_string(HIP_VERSION_MAJOR) + "." + std::to_string(HIP_VERSION_MINOR) +
+                    " toolchain this library was built with; load it in a process whose HIP "
+                    "runtime is the toolchain's (or newer)");
+  return GMPEA_OK;
+}
+
 }  // namespace
 
 extern "C" {
 
 const char *gmpea_last_error(void) { return g_err.c_str(); }
+
+gmpea_status gmpea_sync(gmpea_t h) {
+  if (!valid(h)) return fail(GMPEA_ESTATE, "gmpea_sync: invalid handle");
+  return sync(h, "gmpea_sync");
+}
 
 gmpea_status gmpea_init(const gmpea_problem *P, const gmpea_config *C, const gmpea_allocator *A,
                         void *hip_stream, gmpea_t *out) {
@@ -239,6 +266,8 @@ gmpea_status gmpea_init(const gmpea_problem *P, const gmpea_config *C, const gmp
   if (t1 < 1 || t2 < 1 || t1 > N || t2 > N)
     return fail(GMPEA_EINVAL, "gmpea_init: need 1 <= t1, t2 <= N (population " + std::to_string(N) +
                                   ", t1 " + std::to_string(t1) + ", t2 " + std::to_string(t2) + ")");
+  s = check_runtime("gmpea_init");
+  if (s != GMPEA_OK) return s;
 
   gmpea_s *h = new gmpea_s();
   if (A) {
@@ -710,6 +739,8 @@ gmpea_status gmpea_profile(gmpea_t h, int32_t n_gen, float *ms) {
 gmpea_status gmpea_philox(const uint32_t *ctr, int64_t n, uint64_t seed, uint32_t *out,
                           void *hip_stream) {
   if (n < 0 || (n > 0 && (!ctr || !out))) return fail(GMPEA_EINVAL, "gmpea_philox: bad arguments");
+  gmpea_status st = check_runtime("gmpea_philox");
+  if (st != GMPEA_OK) return st;
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   hipError_t e = launch_philox(ctr, n, static_cast<uint32_t>(seed & 0xFFFFFFFFull),
                                static_cast<uint32_t>(seed >> 32), out, s);

@@ -1,17 +1,25 @@
 """ctypes binding of libgmpea.so (include/gmpea.h). Argument marshalling only.
 
-PyTorch supplies device memory (its caching allocator, through the library's
-allocator hook) and the stream the work is enqueued on; nothing else.
+By default the library allocates its device memory with hipMalloc and enqueues
+on a stream it owns, so nothing beyond the HIP runtime it was built against is
+loaded. A caller may instead hand in a PyTorch stream and PyTorch's caching
+allocator (device memory and streams only) when that PyTorch build's HIP
+runtime is at least as new as the library's toolchain; the binding refuses a
+process whose already-loaded PyTorch carries an older HIP runtime, because
+both runtimes share one soname and the older one would serve the library.
 """
 from __future__ import annotations
 
 import ctypes
+import json
 import os
+import sys
 
 import numpy as np
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_PKG, "_build", "libgmpea.so")
+_BUILD_INFO = os.path.join(_PKG, "_build", "build_info.json")
 
 FAMILY_CURVE, FAMILY_SPHERE = 0, 1
 AGG_PBI, AGG_TCHE = 0, 1
@@ -21,7 +29,8 @@ BUF = {"X": 0, "F": 1, "CV": 2, "XOFF": 3, "FOFF": 4, "CVOFF": 5, "Z": 6, "GEN":
 STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ECAPACITY", -5: "ESTATE",
           -6: "EUNSUPPORTED"}
 EXPORTS = ["gmpea_init", "gmpea_step", "gmpea_run", "gmpea_front", "gmpea_get_info", "gmpea_read",
-           "gmpea_write", "gmpea_destroy", "gmpea_last_error", "gmpea_profile", "gmpea_philox"]
+           "gmpea_write", "gmpea_destroy", "gmpea_last_error", "gmpea_sync", "gmpea_profile",
+           "gmpea_philox"]
 PHASES = ("vary", "op1", "select")
 
 
@@ -69,6 +78,31 @@ def lib_path() -> str:
     return _LIB_PATH
 
 
+def _version_tuple(text):
+    parts = [int(p) for p in str(text).split(".")[:2] if p.isdigit()]
+    return tuple(parts) if len(parts) == 2 else None
+
+
+def _check_process_runtime():
+    """Refuse to load next to an already-imported PyTorch whose bundled HIP
+    runtime is older than the library's toolchain (same soname: that runtime
+    would serve the library)."""
+    torch = sys.modules.get("torch")
+    if torch is None:
+        return
+    have = _version_tuple(getattr(getattr(torch, "version", None), "hip", None) or "")
+    try:
+        with open(_BUILD_INFO) as fh:
+            built = _version_tuple(json.load(fh)["hip_version"])
+    except (OSError, ValueError, KeyError):
+        built = None
+    if have is not None and built is not None and have < built:
+        raise ImportError(
+            "libgmpea.so was built with HIP %d.%d but this process already imported a PyTorch "
+            "that bundles HIP %d.%d; load the library in a process without that PyTorch "
+            "(or rebuild it with a matching toolchain)" % (built + have))
+
+
 def lib():
     """The loaded HIP library; raises if it has not been built."""
     global _lib
@@ -76,6 +110,7 @@ def lib():
         if not os.path.exists(_LIB_PATH):
             raise ImportError("libgmpea.so is not built (expected at %s); run "
                               "`python -m paper_2509_19821_amd.build`" % _LIB_PATH)
+        _check_process_runtime()
         L = ctypes.CDLL(_LIB_PATH)
         vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
         L.gmpea_init.argtypes = [ctypes.POINTER(Problem), ctypes.POINTER(Config),
@@ -91,6 +126,7 @@ def lib():
         L.gmpea_last_error.restype = ctypes.c_char_p
         L.gmpea_philox.argtypes = [vp, i64, ctypes.c_uint64, vp, vp]
         L.gmpea_profile.argtypes = [vp, i32, vp]
+        L.gmpea_sync.argtypes = [vp]
         for name in EXPORTS:
             if name not in ("gmpea_destroy", "gmpea_last_error"):
                 getattr(L, name).restype = ctypes.c_int
@@ -134,11 +170,13 @@ class Gmpea:
              ring_radius, has_sum_lower, sum_lower, n_eq, eq_tol.
     config:  dict with n_req, T, t1, t2, agg, theta, eta_c, eta_m, pc, pm, seed
              (and optionally record).
-    stream:  a torch.cuda.Stream, a raw hipStream_t integer, or None for torch's
-             current stream.
+    stream:  None (a stream owned by the instance), a raw hipStream_t integer,
+             or a torch.cuda.Stream.
+    use_torch_allocator: take device memory from PyTorch's caching allocator
+             instead of hipMalloc.
     """
 
-    def __init__(self, problem: dict, config: dict, stream=None, use_torch_allocator=True,
+    def __init__(self, problem: dict, config: dict, stream=None, use_torch_allocator=False,
                  record: bool = False):
         L = lib()
         self._h = None
@@ -174,8 +212,7 @@ class Gmpea:
     @staticmethod
     def _stream_handle(stream):
         if stream is None:
-            import torch
-            return int(torch.cuda.current_stream().cuda_stream)
+            return 0
         if isinstance(stream, int):
             return stream
         return int(stream.cuda_stream)
@@ -205,6 +242,9 @@ class Gmpea:
     # -- calls ----------------------------------------------------------------
     def step(self, n_gen: int = 1):
         _check(lib().gmpea_step(self._h, int(n_gen)))
+
+    def sync(self):
+        _check(lib().gmpea_sync(self._h))
 
     def run(self, max_gen: int, time_limit_s: float = 0.0) -> int:
         done = ctypes.c_int32(0)
@@ -279,3 +319,53 @@ def philox(ctr_dev_ptr: int, n: int, seed: int, out_dev_ptr: int, stream: int = 
     """Philox4x32-10 blocks on the device (pointers to n x 4 uint32 each)."""
     _check(lib().gmpea_philox(ctypes.c_void_p(ctr_dev_ptr), int(n), int(seed) & 0xFFFFFFFFFFFFFFFF,
                               ctypes.c_void_p(out_dev_ptr), ctypes.c_void_p(stream) if stream else None))
+
+
+class DeviceBuffer:
+    """Raw device memory from the HIP runtime that serves the library (for
+    handing device pointers to gmpea_philox without another framework)."""
+
+    def __init__(self, nbytes: int):
+        lib()
+        self._hip = ctypes.CDLL("libamdhip64.so.7")
+        self._hip.hipMalloc.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_size_t]
+        self._hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                        ctypes.c_int]
+        self._hip.hipFree.argtypes = [ctypes.c_void_p]
+        self.ptr = ctypes.c_void_p()
+        self.nbytes = int(nbytes)
+        if self._hip.hipMalloc(ctypes.byref(self.ptr), self.nbytes) != 0:
+            raise MemoryError("hipMalloc(%d) failed" % self.nbytes)
+
+    def upload(self, arr: np.ndarray):
+        a = np.ascontiguousarray(arr)
+        assert a.nbytes <= self.nbytes
+        if self._hip.hipMemcpy(self.ptr, a.ctypes.data, a.nbytes, 1) != 0:  # host to device
+            raise RuntimeError("hipMemcpy to device failed")
+
+    def download(self, out: np.ndarray):
+        assert out.flags["C_CONTIGUOUS"] and out.nbytes <= self.nbytes
+        if self._hip.hipMemcpy(out.ctypes.data, self.ptr, out.nbytes, 2) != 0:  # device to host
+            raise RuntimeError("hipMemcpy to host failed")
+        return out
+
+    def free(self):
+        if self.ptr:
+            self._hip.hipFree(self.ptr)
+            self.ptr = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def device_count() -> int:
+    """GPUs visible to the HIP runtime that serves the library."""
+    lib()
+    hip = ctypes.CDLL("libamdhip64.so.7")
+    n = ctypes.c_int(0)
+    if hip.hipGetDeviceCount(ctypes.byref(n)) != 0:
+        return 0
+    return int(n.value)

@@ -89,3 +89,27 @@ def test_calls_on_dead_handles_are_rejected(glib):
     assert L.gmpea_front(bogus, 0, 0, None, None, None, None, ctypes.byref(cnt)) == -5
     L.gmpea_destroy(bogus)  # no-op
     L.gmpea_destroy(None)
+
+
+def test_refuses_older_framework_runtime_in_process(glib):
+    """A process that imported a PyTorch bundling an older HIP runtime than the
+    library's toolchain is refused before the library is loaded."""
+    import json
+    import subprocess
+    import sys
+    info = json.load(open(os.path.join(os.path.dirname(glib.lib_path()), "build_info.json")))
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "import torch\n"
+            "from paper_2509_19821_amd import gmpea as G\n"
+            "have = G._version_tuple(torch.version.hip or '')\n"
+            "built = G._version_tuple(%r)\n"
+            "try:\n"
+            "    G.lib(); print('loaded', have, built)\n"
+            "except ImportError as e:\n"
+            "    print('refused', have, built)\n") % (ROOT, info["hip_version"])
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr
+    words = out.stdout.split()
+    have = tuple(int(x) for x in "".join(words[1:3]).strip("()").split(","))
+    built = tuple(int(x) for x in "".join(words[3:5]).strip("()").split(","))
+    assert words[0] == ("refused" if have < built else "loaded")
