@@ -47,7 +47,8 @@ class Cfg(ctypes.Structure):
                 ("agg", ctypes.c_int32), ("theta", ctypes.c_double),
                 ("eta_c", ctypes.c_double), ("eta_m", ctypes.c_double),
                 ("tpm", ctypes.c_uint64), ("tpc", ctypes.c_uint64),
-                ("key", ctypes.c_uint32 * 2)]
+                ("key", ctypes.c_uint32 * 2), ("n_eq", ctypes.c_int32), ("eq_tol", ctypes.c_double),
+                ("f32", ctypes.c_int32)]
 
 
 def lib():
@@ -77,10 +78,10 @@ def lib():
                                      ctypes.c_uint64, ctypes.c_double]
             L.orc_pm_dim.restype = ctypes.c_double
             L.orc_mate.argtypes = [u32, u32, i32, vp, vp]
-            L.orc_select.argtypes = [vp] + [vp] * 14
+            L.orc_select.argtypes = [vp] * 18
             L.orc_reproduce.argtypes = [vp, vp, u32, vp, vp, vp, vp, vp, vp, vp]
             L.orc_ideal.argtypes = [i64, i32, vp, vp]
-            L.orc_generation.argtypes = [vp, vp, u32] + [vp] * 16
+            L.orc_generation.argtypes = [vp, vp, u32] + [vp] * 17
             L.orc_generation.restype = i64
             L.orc_init_x.argtypes = [vp, i32, vp, i32, vp]
             L.orc_front.argtypes = [i64, i32, vp, vp, vp]
@@ -157,7 +158,8 @@ class _ProblemHolder:
 
 
 def evaluate(prob: dict, X: np.ndarray):
-    """F, CV, CMAX of the rows of X (Eqs. (1)-(3))."""
+    """F, CV and the largest objective-space constraint value of the rows of X
+    (Eqs. (1)-(3))."""
     ph = _ProblemHolder(prob)
     X = np.ascontiguousarray(X, dtype=np.float64).reshape(-1, ph.d)
     n = X.shape[0]
@@ -246,7 +248,8 @@ class Oracle:
         self._cfg = Cfg(self.m, self.d, self.N, (ctypes.c_int32 * 2)(*dv["t"]),
                         (ctypes.c_void_p * 2)(_p(self.B[0]), _p(self.B[1])), _p(self.W),
                         dv["agg"], dv["theta"], dv["eta_c"], dv["eta_m"], dv["tpm"], dv["tpc"],
-                        (ctypes.c_uint32 * 2)(*dv["key"]))
+                        (ctypes.c_uint32 * 2)(*dv["key"]), int(prob["n_eq"]),
+                        float(prob["eq_tol"]), 0)
         self.gen = 0
         if init:
             X = [self.init_x(0), self.init_x(1)]
@@ -304,9 +307,15 @@ class Oracle:
         for _ in range(K):
             self.step()
 
-    def select(self, F, CV, CM, Fo, CVo, CMo, z):
-        """Selection alone (Alg. 2) on explicit parents/offspring (population-major)."""
-        N, m = self.N, self.m
+    def select(self, X, F, CV, CM, Xo, Fo, CVo, CMo, z, f32: bool = False):
+        """Selection alone (Alg. 2) on explicit parents/offspring (population-major).
+        X / Xo and CM / CMo only inform the robustness flags. With f32 the
+        aggregation (and so every decision) is taken in FP32 arithmetic on
+        FP32-rounded inputs, the device's precision; violations are compared as
+        given."""
+        N, m, d = self.N, self.m, self.d
+        Xp = [np.ascontiguousarray(X[p], dtype=np.float64).reshape(N, d) for p in range(2)]
+        Xo = np.ascontiguousarray(Xo, dtype=np.float64).reshape(2 * N, d)
         Fp = [np.ascontiguousarray(F[p], dtype=np.float64) for p in range(2)]
         CVp = [np.ascontiguousarray(CV[p], dtype=np.float64) for p in range(2)]
         CMp = [np.ascontiguousarray(CM[p], dtype=np.float64) for p in range(2)]
@@ -318,9 +327,13 @@ class Oracle:
         swr = np.empty(2 * N, dtype=np.uint8)
         win = np.empty(2 * N, dtype=np.int32)
         winr = np.empty(2 * N, dtype=np.uint8)
-        lib().orc_select(ctypes.byref(self._cfg), _p(Fp[0]), _p(Fp[1]), _p(CVp[0]), _p(CVp[1]),
-                         _p(CMp[0]), _p(CMp[1]), _p(Fo), _p(CVo), _p(CMo), _p(z), _p(sw),
-                         _p(swr), _p(win), _p(winr))
+        self._cfg.f32 = 1 if f32 else 0
+        try:
+            lib().orc_select(ctypes.byref(self._cfg), _p(Xp[0]), _p(Xp[1]), _p(Fp[0]), _p(Fp[1]),
+                             _p(CVp[0]), _p(CVp[1]), _p(CMp[0]), _p(CMp[1]), _p(Xo), _p(Fo),
+                             _p(CVo), _p(CMo), _p(z), _p(sw), _p(swr), _p(win), _p(winr))
+        finally:
+            self._cfg.f32 = 0
         return (sw.reshape(2, N), swr.reshape(2, N), win.reshape(2, N), winr.reshape(2, N))
 
     def front(self, pop: int = 0):

@@ -195,7 +195,8 @@ static void orc_objectives(const orc_problem *P, const double *x, double *f) {
 /* Constraint values c (<= 0 means satisfied) for one individual, in order:
  * rings r_j^2 - ||F - a_j||^2, then the linear bound sum_lower - sum F, then the
  * equality |x1 + x2 - 1| - tol (Eq. (2) turns h = 0 into |h| - delta <= 0).
- * Returns CV = sum max(0, c) (Eq. (3)); *cmax gets max c (-inf when none). */
+ * Returns CV = sum max(0, c) (Eq. (3)); *cmax gets the largest objective-space
+ * constraint value (rings, linear bound; -inf when there are none). */
 static double orc_constraints(const orc_problem *P, const double *x, const double *f,
                               double *cmax) {
   const int32_t m = P->m;
@@ -220,7 +221,6 @@ static double orc_constraints(const orc_problem *P, const double *x, const doubl
   if (P->n_eq) {
     double c = fabs(x[0] + x[1] - 1.0) - P->eq_tol;
     cv += (c > 0.0) ? c : 0.0;
-    if (c > mx) mx = c;
   }
   if (cmax) *cmax = mx;
   return cv;
@@ -345,6 +345,9 @@ typedef struct {
   uint64_t tpm; /* floor(pm 2^32) */
   uint64_t tpc; /* floor(pc 2^32) */
   uint32_t key[2];
+  int32_t n_eq;  /* the equality x1 + x2 = 1 is active (robustness bookkeeping only) */
+  double eq_tol;
+  int32_t f32;   /* selection only: take the decisions in FP32 on FP32 inputs (below) */
 } orc_cfg;
 
 /* Robustness threshold for parity (R24). */
@@ -352,83 +355,216 @@ typedef struct {
 
 static double orc_nan_inf(double v) { return isnan(v) ? INFINITY : v; }
 
-/* Three-way comparison a <=> b (-1, 0, +1). *rob = 0 when FP32 rounding on the
- * device side could flip the outcome: the FP64 margin is at most
- * 1e-4 max(1, |a|, |b|), or both are infinite and equal (R24). */
+/* Absolute rounding bound of a total violation computed in FP32: constraints
+ * only count while violated, which for the ring and linear constraints happens
+ * at objective values of order one, and the equality reads two variables. */
+#define ORC_CV_ABS 2e-5
+
+/* Three-way comparison of two total violations a <=> b (-1, 0, +1). *rob = 0
+ * when FP32 rounding on the device side could flip the outcome: the FP64
+ * margin is at most 1e-4 max(|a|, |b|) + ORC_CV_ABS, or both are infinite and
+ * equal (R24). */
 static int orc_cmp(double a, double b, int *rob) {
   int c = (a < b) ? -1 : ((a > b) ? 1 : 0);
   if (isinf(a) || isinf(b)) {
     *rob = (a != b);
     return c;
   }
-  double s = fmax(1.0, fmax(fabs(a), fabs(b)));
-  *rob = fabs(a - b) > ORC_REL * s;
+  *rob = fabs(a - b) > ORC_REL * fmax(fabs(a), fabs(b)) + ORC_CV_ABS;
   return c;
 }
 
-/* What the selection compares for one individual at one weight. */
+/* What the selection compares for one individual at one weight. f points at
+ * the objective vector the key was computed from (used only to recognise exact
+ * copies when judging robustness). */
 typedef struct {
-  double cv, cmax, g;
+  int f32;            /* key evaluated in FP32 (orc_cfg.f32) */
+  double cv, cmax, g; /* cmax: largest objective-space constraint value */
+  const double *f;
+  const double *x;
+  double ceq; /* equality slack |x1 + x2 - 1| - tol (-inf without the equality) */
+  int tk;     /* Tchebycheff: index of the term that sets g with a clear margin, else -1 */
+  double fs;  /* max(1, |f|_inf, |z|_inf): the scale of g's absolute rounding error */
 } orc_key;
+
+/* Aggregation values: FP32 rounding moves g by a few units of 1e-7 relative to
+ * g and to the objective scale, so a decision on g is robust when the FP64
+ * margin exceeds 1e-4 max(|a|, |b|) + 1e-5 max(fs_a, fs_b) (R24). */
+static int orc_cmp_g(double a, double b, double fs, int f32, int *rob) {
+  int c = (a < b) ? -1 : ((a > b) ? 1 : 0);
+  if (isinf(a) || isinf(b)) {
+    *rob = (a != b);
+    return c;
+  }
+  if (f32) /* both sides in FP32 on the same inputs: only operation order differs */
+    *rob = fabs(a - b) > 2e-6 * (fmax(fabs(a), fabs(b)) + fs);
+  else
+    *rob = fabs(a - b) > ORC_REL * fmax(fabs(a), fabs(b)) + 1e-5 * fs;
+  return c;
+}
+
+/* Index of the Tchebycheff term that attains the maximum with a margin above
+ * 1e-4 max(1, term) over every other term (-1 when no term is that clear). */
+static int orc_tche_arg(int32_t m, const double *f, const double *w, const double *z) {
+  int best = -1;
+  double v1 = -INFINITY, v2 = -INFINITY;
+  for (int32_t k = 0; k < m; ++k) {
+    double v = w[k] * fabs(f[k] - z[k]);
+    if (isnan(v)) return -1;
+    if (v > v1) {
+      v2 = v1;
+      v1 = v;
+      best = k;
+    } else if (v > v2) {
+      v2 = v;
+    }
+  }
+  if (m > 1 && !(v1 - v2 > ORC_REL * fmax(1.0, v1))) return -1;
+  return best;
+}
+
+/* The equality reads x1 and x2 only: bitwise-equal pairs give bitwise-equal
+ * violations in any precision (the sum commutes). */
+static int orc_same_eq(orc_key a, orc_key b) {
+  if (!a.x || !b.x || isinf(a.ceq) || isinf(b.ceq)) return 0;
+  return (memcmp(&a.x[0], &b.x[0], sizeof(double)) == 0 &&
+          memcmp(&a.x[1], &b.x[1], sizeof(double)) == 0) ||
+         (memcmp(&a.x[0], &b.x[1], sizeof(double)) == 0 &&
+          memcmp(&a.x[1], &b.x[0], sizeof(double)) == 0);
+}
 
 /* "a is strictly better than b". pop 0 (population 1) uses the feasibility
  * priority rule of Eq. (8): lower CV wins, equal CV falls back to the lower
  * aggregation. pop 1 (population 2) ignores constraints and compares the
  * aggregation alone. NaN is read as +inf, so it never wins. *rob receives the
- * robustness of the decision (R24): equal CVs count as robustly equal only when
- * both are exactly feasible with every constraint below -1e-4. */
+ * robustness of the decision (R24). */
 static int orc_better(int pop, orc_key a, orc_key b, int *rob) {
   double ga = orc_nan_inf(a.g), gb = orc_nan_inf(b.g);
+  double fs = fmax(a.fs, b.fs);
   if (pop == 1) {
-    return orc_cmp(ga, gb, rob) < 0;
+    return orc_cmp_g(ga, gb, fs, a.f32, rob) < 0;
   }
   double ca = orc_nan_inf(a.cv), cb = orc_nan_inf(b.cv);
   int rcv;
   int c = orc_cmp(ca, cb, &rcv);
+  if (a.f32) rcv = 1; /* the same FP32 violations are compared on both sides */
   if (c != 0) {
     *rob = rcv;
     return c < 0;
   }
-  int eq_rob = (ca == 0.0 && cb == 0.0 && a.cmax < -ORC_REL && b.cmax < -ORC_REL);
+  /* equal CVs tie on both sides when nothing near a constraint boundary can
+   * move: every objective-space constraint holds with slack, and either both
+   * are feasible with slack on the equality too, or both violate only the
+   * equality, read from bitwise-equal variables */
+  int obj_free = a.cmax < -ORC_CV_ABS && b.cmax < -ORC_CV_ABS;
+  int eq_rob = obj_free && ((ca == 0.0 && cb == 0.0 && a.ceq < -ORC_CV_ABS && b.ceq < -ORC_CV_ABS) ||
+                            (ca > 0.0 && orc_same_eq(a, b)));
+  if (a.f32) eq_rob = 1;
   int rg;
-  int cg = orc_cmp(ga, gb, &rg);
+  int cg = orc_cmp_g(ga, gb, fs, a.f32, &rg);
   *rob = eq_rob && rg;
   return cg < 0;
 }
 
+/* Keys that tie exactly on both sides of a parity check, whatever the
+ * precision: exact copies (bitwise-equal objectives, and CV for population 1),
+ * or, for Tchebycheff, the same clearly dominant term evaluated on a bitwise-
+ * equal objective (e.g. a variable copied unchanged by SBX). */
+static int orc_same(int pop, int m, orc_key a, orc_key b) {
+  if (pop == 0 && memcmp(&a.cv, &b.cv, sizeof(double)) != 0) return 0;
+  if (memcmp(a.f, b.f, sizeof(double) * (size_t)m) == 0) return 1;
+  return a.tk >= 0 && a.tk == b.tk && memcmp(&a.f[a.tk], &b.f[b.tk], sizeof(double)) == 0;
+}
+
+/* The aggregation in FP32 arithmetic on FP32-rounded operands: the same
+ * formulas as orc_agg, for decisions taken in the device's precision. */
+static double orc_agg_f32(int32_t agg, double theta, int32_t m, const double *f, const double *w,
+                          const double *z) {
+  float ff[64], zz[64], ww[64];
+  for (int32_t k = 0; k < m; ++k) {
+    ff[k] = (float)f[k];
+    zz[k] = (float)z[k];
+  }
+  if (agg == 1) {
+    for (int32_t k = 0; k < m; ++k) ww[k] = (float)w[k];
+    float g = -INFINITY;
+    int nan = 0;
+    for (int32_t k = 0; k < m; ++k) {
+      float v = ww[k] * fabsf(ff[k] - zz[k]);
+      if (isnan(v)) nan = 1;
+      if (v > g) g = v;
+    }
+    return nan ? NAN : (double)g;
+  }
+  double wn = 0.0; /* unit direction computed in FP64, then rounded once */
+  for (int32_t k = 0; k < m; ++k) wn += w[k] * w[k];
+  wn = sqrt(wn);
+  for (int32_t k = 0; k < m; ++k) ww[k] = (float)(w[k] / wn);
+  float dot = 0.0f;
+  for (int32_t k = 0; k < m; ++k) dot += (ff[k] - zz[k]) * ww[k];
+  float d1 = fabsf(dot), d2 = 0.0f;
+  for (int32_t k = 0; k < m; ++k) {
+    float e = (ff[k] - zz[k]) - d1 * ww[k];
+    d2 += e * e;
+  }
+  return (double)(d1 + (float)theta * sqrtf(d2));
+}
+
+/* Key of an individual (decision vector x, objectives f, CV and the largest
+ * objective-space constraint value given) at weight w. */
+static orc_key orc_mk(const orc_cfg *C, double cv, double cmax, const double *x, const double *f,
+                      const double *w, const double *z) {
+  double g = C->f32 ? orc_agg_f32(C->agg, C->theta, C->m, f, w, z)
+                    : orc_agg(C->agg, C->theta, C->m, f, w, z);
+  orc_key k = {C->f32 != 0, cv, cmax, g, f, x, -INFINITY, -1, 1.0};
+  if (C->n_eq) k.ceq = fabs(x[0] + x[1] - 1.0) - C->eq_tol;
+  if (C->agg == 1) k.tk = orc_tche_arg(C->m, f, w, z);
+  for (int32_t a = 0; a < C->m; ++a) {
+    if (fabs(f[a]) > k.fs) k.fs = fabs(f[a]);
+    if (fabs(z[a]) > k.fs) k.fs = fabs(z[a]);
+  }
+  return k;
+}
+
 /* Environmental selection of one generation (Alg. 2) on given parents and
  * offspring, with z already updated.
- *   F[p], CV[p], CM[p]   parents of population p (N x m, N, N)
- *   Fo, CVo, CMo         offspring, population-major (2N x m, 2N, 2N)
+ *   X[p], F[p], CV[p], CM[p]   parents of population p (N x d, N x m, N, N)
+ *   Xo, Fo, CVo, CMo           offspring, population-major (2N x d, 2N x m, 2N, 2N)
+ * (X and CM serve only the robustness flags.)
  * Outputs (all 2N, population-major):
  *   sw[p N + i]   OP1: 1 if population p's new offspring at i is the other
  *                 population's offspring; swr = robustness of that switch
  *   win[p N + j]  winner offspring index for parent slot j (-1: parent kept);
- *                 winr = robustness of the whole slot decision.
+ *                 winr = robustness of the slot's outcome (R24): the winner is
+ *                 robustly better than the parent and than every other
+ *                 candidate, or, when the parent stays, no candidate can be
+ *                 better than it; a candidate whose OP1 switch is not robust is
+ *                 judged under both of its possible offspring.
  * OP1 (Eq. (11)): at w_i, population 1 takes off2 if it is FPR-better than
  * off1; population 2 takes off1 if its aggregation is lower (R14, R15).
  * OP2 + OP3 (Eqs. (12)-(13)), as a pull over parent slot j: offspring i with
  * j in B_p(i) qualifies iff its new offspring is strictly better than parent j
  * at w_j; the winner is the lexicographic minimum over the qualifiers, first
  * index on ties (R17-R19). Decisions all use generation-k parents. */
-void orc_select(const orc_cfg *C, const double *F0, const double *F1, const double *CV0,
-                const double *CV1, const double *CM0, const double *CM1, const double *Fo,
-                const double *CVo, const double *CMo, const double *z, uint8_t *sw,
-                uint8_t *swr, int32_t *win, uint8_t *winr) {
-  const int32_t m = C->m, N = C->N;
-  const double *F[2] = {F0, F1}, *CV[2] = {CV0, CV1}, *CM[2] = {CM0, CM1};
+void orc_select(const orc_cfg *C, const double *X0, const double *X1, const double *F0,
+                const double *F1, const double *CV0, const double *CV1, const double *CM0,
+                const double *CM1, const double *Xo, const double *Fo, const double *CVo,
+                const double *CMo, const double *z, uint8_t *sw, uint8_t *swr, int32_t *win,
+                uint8_t *winr) {
+  const int32_t m = C->m, N = C->N, d = C->d;
+  const double *X[2] = {X0, X1}, *F[2] = {F0, F1}, *CV[2] = {CV0, CV1}, *CM[2] = {CM0, CM1};
 
 #pragma omp parallel for schedule(static)
   for (int32_t i = 0; i < N; ++i) {
     const double *w = C->W + (size_t)i * m;
-    orc_key k1 = {CVo[i], CMo[i], orc_agg(C->agg, C->theta, m, Fo + (size_t)i * m, w, z)};
-    orc_key k2 = {CVo[N + i], CMo[N + i],
-                  orc_agg(C->agg, C->theta, m, Fo + ((size_t)N + i) * m, w, z)};
+    orc_key k1 = orc_mk(C, CVo[i], CMo[i], Xo + (size_t)i * d, Fo + (size_t)i * m, w, z);
+    orc_key k2 = orc_mk(C, CVo[N + i], CMo[N + i], Xo + ((size_t)N + i) * d,
+                        Fo + ((size_t)N + i) * m, w, z);
     int r1, r2;
     sw[i] = (uint8_t)orc_better(0, k2, k1, &r1);     /* S1: population 1 takes off2 */
     sw[N + i] = (uint8_t)orc_better(1, k1, k2, &r2); /* S2: population 2 takes off1 */
-    swr[i] = (uint8_t)r1;
-    swr[N + i] = (uint8_t)r2;
+    swr[i] = (uint8_t)(r1 || orc_same(0, m, k1, k2));
+    swr[N + i] = (uint8_t)(r2 || orc_same(1, m, k1, k2));
   }
 
   for (int p = 0; p < 2; ++p) {
@@ -449,27 +585,51 @@ void orc_select(const orc_cfg *C, const double *F0, const double *F1, const doub
 #pragma omp parallel for schedule(static)
     for (int32_t j = 0; j < N; ++j) {
       const double *w = C->W + (size_t)j * m;
-      orc_key par = {CV[p][j], CM[p][j], orc_agg(C->agg, C->theta, m, F[p] + (size_t)j * m, w, z)};
+      orc_key par = orc_mk(C, CV[p][j], CM[p][j], X[p] + (size_t)j * d, F[p] + (size_t)j * m, w, z);
+      /* the decision: lexicographic minimum over qualifiers, first index on ties */
       orc_key best = par;
       int32_t bi = -1;
-      int robust = 1;
       for (int32_t q = roff[j]; q < roff[j + 1]; ++q) {
         int32_t i = ridx[q];
         size_t src = (size_t)(p ^ sw[(size_t)p * N + i]) * N + i;
-        if (!swr[(size_t)p * N + i]) robust = 0;
-        orc_key ck = {CVo[src], CMo[src], orc_agg(C->agg, C->theta, m, Fo + src * m, w, z)};
-        int rp, rb;
-        int bp = orc_better(p, ck, par, &rp);
-        if (!rp) robust = 0;
-        if (!bp) continue;
-        int bb = orc_better(p, ck, best, &rb);
-        if (bi >= 0 && !rb) robust = 0;
-        if (bb) {
+        orc_key ck = orc_mk(C, CVo[src], CMo[src], Xo + src * d, Fo + src * m, w, z);
+        int r;
+        if (orc_better(p, ck, par, &r) && orc_better(p, ck, best, &r)) {
           best = ck;
           bi = i;
         }
       }
       win[(size_t)p * N + j] = bi;
+
+      /* robustness of that outcome */
+      int robust = 1;
+      if (bi >= 0) {
+        int r;
+        if (!swr[(size_t)p * N + bi]) robust = 0;
+        if (!orc_better(p, best, par, &r) || !r) robust = 0;
+      }
+      for (int32_t q = roff[j]; q < roff[j + 1] && robust; ++q) {
+        int32_t i = ridx[q];
+        if (i == bi) continue;
+        int nalt = swr[(size_t)p * N + i] ? 1 : 2;
+        for (int a = 0; a < nalt && robust; ++a) {
+          int other = sw[(size_t)p * N + i] ^ a;
+          size_t src = (size_t)(p ^ other) * N + i;
+          orc_key ck = orc_mk(C, CVo[src], CMo[src], Xo + src * d, Fo + src * m, w, z);
+          int r;
+          if (bi >= 0) {
+            /* the winner must stay ahead of this candidate */
+            if (orc_same(p, m, ck, best)) {
+              if (i < bi) robust = 0;
+            } else if (!orc_better(p, best, ck, &r) || !r) {
+              robust = 0;
+            }
+          } else {
+            /* no candidate may overtake the parent */
+            if (!orc_same(p, m, ck, par) && (orc_better(p, ck, par, &r) || !r)) robust = 0;
+          }
+        }
+      }
       winr[(size_t)p * N + j] = (uint8_t)robust;
     }
     free(roff);
@@ -554,7 +714,7 @@ int64_t orc_generation(const orc_problem *P, const orc_cfg *C, uint32_t k, doubl
 
   orc_reproduce(P, C, k, X0, X1, xo, fo, cvo, cmo, mate);
   orc_ideal(2 * (int64_t)N, m, fo, z);
-  orc_select(C, F0, F1, CV0, CV1, CM0, CM1, fo, cvo, cmo, z, sw, swr, wn, wr);
+  orc_select(C, X0, X1, F0, F1, CV0, CV1, CM0, CM1, xo, fo, cvo, cmo, z, sw, swr, wn, wr);
 
   int64_t replaced = 0;
   for (int p = 0; p < 2; ++p) {

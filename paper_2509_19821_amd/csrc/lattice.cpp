@@ -16,6 +16,7 @@
 // nearest found lies within distance R. Every lattice point within distance R
 // lies inside the box, so no closer point (or equal-distance point with a
 // smaller index) can be missed. O(N (2R + 1)^(m-1) log) instead of O(N^2).
+// The radius grows geometrically: the result does not depend on the final R.
 #include <algorithm>
 #include <cmath>
 #include <thread>
@@ -62,12 +63,15 @@ void dd_lattice(int32_t m, int32_t H, std::vector<int32_t> &K) {
   }
 }
 
-// Position of composition k in the enumeration above.
+// Position of composition k in the enumeration above. The compositions placed
+// before k at coordinate a are those with a smaller value there:
+// sum_{v < k_a} C(left - v + r - 1, r - 1) with r = m - a - 1 parts left, which
+// the hockey-stick identity turns into C(left + r, r) - C(left - k_a + r, r).
 static int64_t dd_rank(const int32_t *k, int32_t m, int32_t H) {
   int64_t r = 0;
   int32_t left = H;
   for (int32_t a = 0; a < m - 1; ++a) {
-    for (int32_t v = 0; v < k[a]; ++v) r += dd_count(m - a - 1, left - v);
+    r += dd_count(m - a, left) - dd_count(m - a, left - k[a]);
     left -= k[a];
   }
   return r;
@@ -123,7 +127,7 @@ static void knn_rows(const std::vector<int32_t> &K, int32_t m, int32_t H, int32_
           break;
         }
       }
-      ++R;
+      R += std::max(1, R / 2);  // any R that passes the test above is exact
     }
   }
 }

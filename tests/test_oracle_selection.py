@@ -45,7 +45,9 @@ def _random_state(o, rng, tie_frac=0.3, dup_frac=0.2):
     z = np.minimum(np.min(np.concatenate([F[0], F[1], Fo]), 0), 0.0) - rng.uniform(0, 0.1, m)
     CM = [np.where(c == 0, -1.0, c) for c in CV]
     CMo = np.where(CVo == 0, -1.0, CVo)
-    return F, CV, CM, Fo, CVo, CMo, z
+    X = [rng.uniform(0, 1, (N, o.d)) for _ in range(2)]
+    Xo = rng.uniform(0, 1, (2 * N, o.d))
+    return F, CV, CM, Fo, CVo, CMo, z, X, Xo
 
 
 @pytest.mark.parametrize("m,n_req,T,kind", [(2, 20, 6, 0), (2, 24, 10, 1), (3, 28, 8, 0),
@@ -54,8 +56,8 @@ def test_pull_equals_dense_alg2(m, n_req, T, kind):
     o = _tiny_oracle(m, n_req, T, kind)
     rng = np.random.default_rng(100 + m * 7 + T)
     for trial in range(12):
-        F, CV, CM, Fo, CVo, CMo, z = _random_state(o, rng)
-        sw, _, win, _ = o.select(F, CV, CM, Fo, CVo, CMo, z)
+        F, CV, CM, Fo, CVo, CMo, z, X, Xo = _random_state(o, rng)
+        sw, _, win, _ = o.select(X, F, CV, CM, Xo, Fo, CVo, CMo, z)
         Fo2 = Fo.reshape(2, o.N, m)
         CVo2 = CVo.reshape(2, o.N)
         dsw, dwin = dense_select(F, CV, Fo2, CVo2, o.W, z, o.B, kind=kind, theta=5.0)
@@ -66,12 +68,12 @@ def test_pull_equals_dense_alg2(m, n_req, T, kind):
 def test_pull_equals_dense_with_nan():
     o = _tiny_oracle(3, 28, 8)
     rng = np.random.default_rng(77)
-    F, CV, CM, Fo, CVo, CMo, z = _random_state(o, rng)
+    F, CV, CM, Fo, CVo, CMo, z, X, Xo = _random_state(o, rng)
     Fo[3, 0] = np.nan
     Fo[o.N + 5, 1] = np.nan
     F[0][2, 2] = np.nan
     CVo[7] = np.nan
-    sw, _, win, _ = o.select(F, CV, CM, Fo, CVo, CMo, z)
+    sw, _, win, _ = o.select(X, F, CV, CM, Xo, Fo, CVo, CMo, z)
     dsw, dwin = dense_select(F, CV, Fo.reshape(2, o.N, 3), CVo.reshape(2, o.N), o.W, z, o.B)
     assert np.array_equal(sw, dsw) and np.array_equal(win, dwin)
     # a NaN offspring never wins a slot
@@ -92,8 +94,8 @@ def test_unit_neighbourhood_is_pairwise():
     """t1 = t2 = 1: each slot only meets its own subproblem's new offspring."""
     o = _tiny_oracle(3, 28, 2, t1=1, t2=1)
     rng = np.random.default_rng(5)
-    F, CV, CM, Fo, CVo, CMo, z = _random_state(o, rng)
-    sw, _, win, _ = o.select(F, CV, CM, Fo, CVo, CMo, z)
+    F, CV, CM, Fo, CVo, CMo, z, X, Xo = _random_state(o, rng)
+    sw, _, win, _ = o.select(X, F, CV, CM, Xo, Fo, CVo, CMo, z)
     from oracle.dense_alg2 import agg_rows
     for p in range(2):
         for j in range(o.N):
@@ -112,13 +114,13 @@ def test_unconstrained_population_rules_coincide():
     feasibility rule reduces to population 2's aggregation rule."""
     o = _tiny_oracle(3, 36, 10, t1=10, t2=10)
     rng = np.random.default_rng(6)
-    F, CV, CM, Fo, CVo, CMo, z = _random_state(o, rng, dup_frac=0.0)
+    F, CV, CM, Fo, CVo, CMo, z, X, Xo = _random_state(o, rng, dup_frac=0.0)
     F = [F[0], F[0].copy()]
     CV = [np.zeros(o.N), np.zeros(o.N)]
     CM = [np.full(o.N, -1.0), np.full(o.N, -1.0)]
     CVo = np.zeros(2 * o.N)
     CMo = np.full(2 * o.N, -1.0)
-    sw, _, win, _ = o.select(F, CV, CM, Fo, CVo, CMo, z)
+    sw, _, win, _ = o.select(X, F, CV, CM, Xo, Fo, CVo, CMo, z)
     # same chosen offspring content and same winners
     for i in range(o.N):
         assert (0 ^ sw[0, i]) * o.N + i == (1 ^ sw[1, i]) * o.N + i
@@ -157,3 +159,49 @@ def test_ideal_point_is_running_minimum():
         d = o.step(debug=True)
         seen = np.minimum(seen, d["Fo"].reshape(-1, o.m).min(0))
         assert np.array_equal(o.z, seen)
+
+
+def _dense_f32(F, CV, Fo, CVo, W, z, B, kind):
+    """The dense transcription fed FP32 operands with its aggregation in FP32."""
+    import oracle.dense_alg2 as D
+    orig = D.agg_rows
+
+    def agg32(kind_, theta, Fr, Wr, zr):
+        Fr = np.atleast_2d(Fr).astype(np.float32)
+        Wr = np.atleast_2d(Wr)
+        zr = np.asarray(zr).astype(np.float32)
+        if kind_ == 1:
+            return np.max(Wr.astype(np.float32) * np.abs(Fr - zr), axis=1).astype(np.float64)
+        u = (Wr / np.linalg.norm(Wr, axis=1, keepdims=True)).astype(np.float32)
+        diff = Fr - zr
+        d1 = np.abs(np.sum(diff * u, axis=1, dtype=np.float32))
+        e = diff - d1[:, None] * u
+        d2 = np.sqrt(np.sum(e * e, axis=1, dtype=np.float32))
+        return (d1 + np.float32(theta) * d2).astype(np.float64)
+
+    D.agg_rows = agg32
+    try:
+        return D.dense_select(F, CV, Fo, CVo, W, z, B, kind=kind, theta=5.0)
+    finally:
+        D.agg_rows = orig
+
+
+@pytest.mark.parametrize("m,kind", [(2, 0), (3, 0), (3, 1)])
+def test_fp32_decisions_equal_dense_alg2_in_fp32(m, kind):
+    """The FP32 decision mode (used to compare with the device) takes the same
+    decisions as the dense transcription evaluated in FP32, wherever it marks
+    them robust; its CV comparisons are exact."""
+    o = _tiny_oracle(m, 28 if m == 3 else 24, 8, kind)
+    rng = np.random.default_rng(200 + m + 10 * kind)
+    for trial in range(10):
+        F, CV, CM, Fo, CVo, CMo, z, X, Xo = _random_state(o, rng)
+        F = [f.astype(np.float32).astype(np.float64) for f in F]
+        CV = [c.astype(np.float32).astype(np.float64) for c in CV]
+        Fo = Fo.astype(np.float32).astype(np.float64)
+        CVo = CVo.astype(np.float32).astype(np.float64)
+        z = z.astype(np.float32).astype(np.float64)
+        sw, swr, win, winr = o.select(X, F, CV, CM, Xo, Fo, CVo, CMo, z, f32=True)
+        dsw, dwin = _dense_f32(F, CV, Fo.reshape(2, o.N, m), CVo.reshape(2, o.N), o.W, z, o.B, kind)
+        assert np.array_equal(sw[swr.astype(bool)], dsw[swr.astype(bool)]), trial
+        assert np.array_equal(win[winr.astype(bool)], dwin[winr.astype(bool)]), trial
+        assert winr.mean() > 0.9
