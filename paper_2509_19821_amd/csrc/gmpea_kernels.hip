@@ -79,17 +79,26 @@ __device__ __forceinline__ float vary1(float a, float b, uint32_t wA, uint32_t w
     c = 0.5f * ((a + b) + beta * (a - b));
   }
   c = fminf(fmaxf(c, lo), hi);
-  if (static_cast<uint64_t>(wB) < st.tpm) {
-    const float u = static_cast<float>(wB) / static_cast<float>(st.tpm);
+  const uint64_t w = wB;
+  if (w < st.tpm) {
+    // u = wB / tpm. Every coefficient of the mutation step (2u, 1 - 2u, 2(1 - u),
+    // 2(u - 1/2)) comes from an exact integer numerator over tpm, and 1 - delta
+    // from the distance to the far bound: in FP32, 1 - u itself cancels
+    // catastrophically as u -> 1 and val^(1/(eta+1)) magnifies that error.
+    const float tp = static_cast<float>(st.tpm);
     const float span = hi - lo;
     float dq;
-    if (u < 0.5f) {
-      const float xy = 1.0f - (c - lo) / span;
-      const float val = 2.0f * u + (1.0f - 2.0f * u) * powpos(xy, st.pm_p);
+    if (2u * w < st.tpm) {
+      const float u2 = static_cast<float>(2u * w) / tp;
+      const float om = static_cast<float>(st.tpm - 2u * w) / tp;
+      const float xy = (hi - c) / span;
+      const float val = u2 + om * powpos(xy, st.pm_p);
       dq = powpos(val, st.pm_e) - 1.0f;
     } else {
-      const float xy = 1.0f - (hi - c) / span;
-      const float val = 2.0f * (1.0f - u) + 2.0f * (u - 0.5f) * powpos(xy, st.pm_p);
+      const float a2 = static_cast<float>(2u * (st.tpm - w)) / tp;
+      const float b2 = static_cast<float>(2u * w - st.tpm) / tp;
+      const float xy = (c - lo) / span;
+      const float val = a2 + b2 * powpos(xy, st.pm_p);
       dq = 1.0f - powpos(val, st.pm_e);
     }
     c = fminf(fmaxf(c + dq * span, lo), hi);

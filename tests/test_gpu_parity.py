@@ -55,6 +55,28 @@ def _pair(prob, cfg, record=True):
     return gp, o
 
 
+def _diag(label, S, Xo, Fo, CVo, dbg, ok):
+    """On a tolerance failure, keep the worst rows (inputs and outputs) for a
+    replay on the CPU (only when GMPEA_DIAG_DIR names a directory)."""
+    out = os.environ.get("GMPEA_DIAG_DIR")
+    if ok or not out:
+        return
+    os.makedirs(out, exist_ok=True)
+    keep = {"gen": np.array([S["gen"]]), "z_pre": S["z"]}
+    for p in range(2):
+        ex = np.abs(Xo[p].astype(np.float64) - dbg["Xo"][p]).max(1)
+        ef = np.abs(Fo[p].astype(np.float64) - dbg["Fo"][p]).max(1)
+        rows = np.unique(np.concatenate([np.argsort(ex)[-16:], np.argsort(ef)[-16:]]))
+        mate = dbg["mate"][p][rows]
+        keep.update({"rows_%d" % p: rows, "mate_%d" % p: mate,
+                     "pa_%d" % p: S["X"][p][mate[:, 0]], "pb_%d" % p: S["X"][p][mate[:, 1]],
+                     "gpu_x_%d" % p: Xo[p][rows], "ref_x_%d" % p: dbg["Xo"][p][rows],
+                     "gpu_f_%d" % p: Fo[p][rows], "ref_f_%d" % p: dbg["Fo"][p][rows],
+                     "gpu_cv_%d" % p: CVo[p][rows], "ref_cv_%d" % p: dbg["CVo"][p][rows]})
+    name = "".join(ch if ch.isalnum() else "_" for ch in label)
+    np.savez(os.path.join(out, "diag_%s.npz" % name), **keep)
+
+
 def _teacher_forced(gp, o, gens, label):
     """Run `gens` teacher-forced generations, each checked in two stages.
 
@@ -79,6 +101,9 @@ def _teacher_forced(gp, o, gens, label):
         Xo = [gp.read("XOFF", p) for p in range(2)]
         Fo = [gp.read("FOFF", p) for p in range(2)]
         CVo = [gp.read("CVOFF", p) for p in range(2)]
+        _diag(label, S=S, Xo=Xo, Fo=Fo, CVo=CVo, dbg=dbg, ok=all(
+            _err(a[p], dbg[k][p]) <= TOL for a, k in ((Xo, "Xo"), (Fo, "Fo"), (CVo, "CVo"))
+            for p in range(2)))
         for p in range(2):
             assert np.array_equal(gp.read("MATE", p), dbg["mate"][p]), (label, "mate", p)
             assert _err(Xo[p], dbg["Xo"][p]) <= TOL, (label, "Xo", p)
