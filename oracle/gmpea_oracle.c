@@ -378,7 +378,7 @@ static int orc_cmp(double a, double b, int *rob) {
  * the objective vector the key was computed from (used only to recognise exact
  * copies when judging robustness). */
 typedef struct {
-  int f32;            /* key evaluated in FP32 (orc_cfg.f32) */
+  int f32;            /* key evaluated in FP32 (orc_cfg.f32); 2 = bitwise reproducible */
   double cv, cmax, g; /* cmax: largest objective-space constraint value */
   const double *f;
   const double *x;
@@ -396,7 +396,9 @@ static int orc_cmp_g(double a, double b, double fs, int f32, int *rob) {
     *rob = (a != b);
     return c;
   }
-  if (f32) /* both sides in FP32 on the same inputs: only operation order differs */
+  if (f32 == 2) /* every operation is one correctly rounded FP32 step on both sides */
+    *rob = 1;
+  else if (f32) /* FP32 on the same inputs: only contraction and order of sums differ */
     *rob = fabs(a - b) > 2e-6 * (fmax(fabs(a), fabs(b)) + fs);
   else
     *rob = fabs(a - b) > ORC_REL * fmax(fabs(a), fabs(b)) + 1e-5 * fs;
@@ -516,7 +518,11 @@ static orc_key orc_mk(const orc_cfg *C, double cv, double cmax, const double *x,
                       const double *w, const double *z) {
   double g = C->f32 ? orc_agg_f32(C->agg, C->theta, C->m, f, w, z)
                     : orc_agg(C->agg, C->theta, C->m, f, w, z);
-  orc_key k = {C->f32 != 0, cv, cmax, g, f, x, -INFINITY, -1, 1.0};
+  /* In FP32, Tchebycheff is max_k w_k |f_k - z_k|: a subtraction, an absolute
+   * value and a product per term, none of which a compiler can fuse, so equal
+   * FP32 inputs give the bitwise-equal value on every IEEE device. */
+  int mode = C->f32 ? (C->agg == 1 ? 2 : 1) : 0;
+  orc_key k = {mode, cv, cmax, g, f, x, -INFINITY, -1, 1.0};
   if (C->n_eq) k.ceq = fabs(x[0] + x[1] - 1.0) - C->eq_tol;
   if (C->agg == 1) k.tk = orc_tche_arg(C->m, f, w, z);
   for (int32_t a = 0; a < C->m; ++a) {
