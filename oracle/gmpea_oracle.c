@@ -512,6 +512,14 @@ static double orc_agg_f32(int32_t agg, double theta, int32_t m, const double *f,
   return (double)(d1 + (float)theta * sqrtf(d2));
 }
 
+/* Keys that compare equal and are computed bitwise-reproducibly on both sides
+ * (the exact FP32 mode): the tie itself is reproduced, and the index decides. */
+static int orc_exact_tie(int pop, orc_key a, orc_key b) {
+  if (a.f32 != 2 || b.f32 != 2) return 0;
+  if (pop == 0 && !(orc_nan_inf(a.cv) == orc_nan_inf(b.cv))) return 0;
+  return orc_nan_inf(a.g) == orc_nan_inf(b.g);
+}
+
 /* Key of an individual (decision vector x, objectives f, CV and the largest
  * objective-space constraint value given) at weight w. */
 static orc_key orc_mk(const orc_cfg *C, double cv, double cmax, const double *x, const double *f,
@@ -625,14 +633,16 @@ void orc_select(const orc_cfg *C, const double *X0, const double *X1, const doub
           int r;
           if (bi >= 0) {
             /* the winner must stay ahead of this candidate */
-            if (orc_same(p, m, ck, best)) {
+            if (orc_same(p, m, ck, best) || orc_exact_tie(p, ck, best)) {
               if (i < bi) robust = 0;
             } else if (!orc_better(p, best, ck, &r) || !r) {
               robust = 0;
             }
           } else {
             /* no candidate may overtake the parent */
-            if (!orc_same(p, m, ck, par) && (orc_better(p, ck, par, &r) || !r)) robust = 0;
+            if (!orc_same(p, m, ck, par) && !orc_exact_tie(p, ck, par) &&
+                (orc_better(p, ck, par, &r) || !r))
+              robust = 0;
           }
         }
       }
