@@ -96,6 +96,22 @@ def cpu_baseline(target_s=12.0):
                       "subproblems" % (o.N, gens)}
 
 
+def copy_probe(g, nbytes=512 << 20, reps=5):
+    """Bandwidth of the library's streaming copy kernel (read + write bytes per
+    second, best of `reps`); also the reference launch for counter calibration."""
+    src, dst = g.DeviceBuffer(nbytes), g.DeviceBuffer(nbytes)
+    try:
+        best = float("inf")
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            g.copy(src.ptr.value, dst.ptr.value, nbytes)
+            best = min(best, time.perf_counter() - t0)
+    finally:
+        src.free()
+        dst.free()
+    return 2.0 * nbytes / best / 1e9
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -144,12 +160,15 @@ def main():
     traffic = measured_traffic(dom)
     log("bench: per-kernel ms %s; model bytes %s" % (ms, model))
     gen_bytes = sum(model.values())
+    copy_gbs = copy_probe(g)
+    log("bench: streaming copy %.0f GB/s" % copy_gbs)
     roof = {"bound": "hbm", "kernel": "k_" + dom, "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic, "algorithmic_bytes_per_launch": int(model[dom]),
             "avg_launch_ms": round(ms[dom], 5),
             "per_kernel_ms": {k: round(v, 5) for k, v in ms.items()},
             "generation_gbs": round(gen_bytes / (sum(ms.values()) * 1e-3) / 1e9, 1),
+            "copy_probe_gbs": round(copy_gbs, 1),
             "rho": [round(r, 4) for r in rho]}
     gp.close()
 

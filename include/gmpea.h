@@ -224,6 +224,13 @@ gmpea_status gmpea_profile(gmpea_t h, int32_t n_gen, float *ms);
 gmpea_status gmpea_philox(const uint32_t *ctr, int64_t n, uint64_t seed, uint32_t *out,
                           void *hip_stream);
 
+/* Streaming device-to-device copy of `bytes` (a multiple of 16; both pointers
+ * 16-byte aligned device memory) with the library's own kernel: every byte read
+ * once and written once. It serves as the reference for measured bandwidth and
+ * for calibrating hardware byte counters against a known transfer. Enqueues on
+ * hip_stream (NULL: legacy default) and synchronises. */
+gmpea_status gmpea_copy(const void *src, void *dst, size_t bytes, void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

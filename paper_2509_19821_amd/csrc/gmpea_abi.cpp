@@ -736,6 +736,19 @@ gmpea_status gmpea_profile(gmpea_t h, int32_t n_gen, float *ms) {
   return GMPEA_OK;
 }
 
+gmpea_status gmpea_copy(const void *src, void *dst, size_t bytes, void *hip_stream) {
+  if (bytes % 16 != 0 || (bytes > 0 && (!src || !dst)) ||
+      (reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) % 16 != 0)
+    return fail(GMPEA_EINVAL, "gmpea_copy: need 16-byte aligned pointers and size");
+  gmpea_status st = check_runtime("gmpea_copy");
+  if (st != GMPEA_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  hipError_t e = launch_copy(src, dst, static_cast<int64_t>(bytes / 16), s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "gmpea_copy");
+  return GMPEA_OK;
+}
+
 gmpea_status gmpea_philox(const uint32_t *ctr, int64_t n, uint64_t seed, uint32_t *out,
                           void *hip_stream) {
   if (n < 0 || (n > 0 && (!ctr || !out))) return fail(GMPEA_EINVAL, "gmpea_philox: bad arguments");

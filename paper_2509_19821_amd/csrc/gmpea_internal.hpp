@@ -69,6 +69,7 @@ hipError_t launch_generation(const DevState &st, hipStream_t s);
 hipError_t launch_front_flags(const DevState &st, int pop, uint8_t *keep, hipStream_t s);
 hipError_t launch_gather(const DevState &st, int pop, const int32_t *idx, int32_t count,
                          float *x, float4 *fc, hipStream_t s);
+hipError_t launch_copy(const void *src, void *dst, int64_t n16, hipStream_t s);
 hipError_t launch_philox(const uint32_t *ctr, int64_t n, uint32_t k0, uint32_t k1, uint32_t *out,
                          hipStream_t s);
 

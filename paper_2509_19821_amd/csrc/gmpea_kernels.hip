@@ -21,6 +21,8 @@
 // Blocks are remapped so that consecutive row tiles run on the same XCD (the
 // hardware deals blocks to the 8 XCDs round-robin): neighbouring subproblems
 // share parents and candidates, and then share that XCD's L2.
+#include <algorithm>
+
 #include "gmpea_internal.hpp"
 
 namespace gmpea {
@@ -494,6 +496,15 @@ __global__ __launch_bounds__(kBlock) void k_philox(const uint4 *ctr, int64_t n, 
   if (q < n) out[q] = philox10(ctr[q], k0, k1);
 }
 
+// Streaming copy of n16 16-byte words: the reference kernel for bandwidth and
+// for calibrating hardware byte counters (each word read once, written once).
+__global__ __launch_bounds__(kBlock) void k_copy(const uint4 *__restrict__ src,
+                                                 uint4 *__restrict__ dst, int64_t n16) {
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
+  for (int64_t q = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; q < n16; q += stride)
+    dst[q] = src[q];
+}
+
 // ----------------------------------------------------------------------------
 // Launchers
 // ----------------------------------------------------------------------------
@@ -547,6 +558,14 @@ hipError_t launch_gather(const DevState &st, int pop, const int32_t *idx, int32_
                          float4 *fc, hipStream_t s) {
   if (count <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_gather, dim3(count), dim3(64), 0, s, st, pop, idx, count, x, fc);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(const void *src, void *dst, int64_t n16, hipStream_t s) {
+  if (n16 <= 0) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>((n16 + kBlock - 1) / kBlock, 256 * 16);
+  hipLaunchKernelGGL(k_copy, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, s,
+                     static_cast<const uint4 *>(src), static_cast<uint4 *>(dst), n16);
   return hipGetLastError();
 }
 

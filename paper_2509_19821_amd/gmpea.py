@@ -30,7 +30,7 @@ STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ECAPACITY", -5: 
           -6: "EUNSUPPORTED"}
 EXPORTS = ["gmpea_init", "gmpea_step", "gmpea_run", "gmpea_front", "gmpea_get_info", "gmpea_read",
            "gmpea_write", "gmpea_destroy", "gmpea_last_error", "gmpea_sync", "gmpea_profile",
-           "gmpea_philox"]
+           "gmpea_philox", "gmpea_copy"]
 PHASES = ("vary", "op1", "select")
 
 
@@ -127,6 +127,7 @@ def lib():
         L.gmpea_philox.argtypes = [vp, i64, ctypes.c_uint64, vp, vp]
         L.gmpea_profile.argtypes = [vp, i32, vp]
         L.gmpea_sync.argtypes = [vp]
+        L.gmpea_copy.argtypes = [vp, vp, ctypes.c_size_t, vp]
         for name in EXPORTS:
             if name not in ("gmpea_destroy", "gmpea_last_error"):
                 getattr(L, name).restype = ctypes.c_int
@@ -313,6 +314,12 @@ class Gmpea:
             self.write("CV", s["CV"][p], p)
         self.write("Z", s["z"])
         self.write("GEN", np.array([s["gen"]], dtype=np.int64))
+
+
+def copy(src_dev_ptr: int, dst_dev_ptr: int, nbytes: int, stream: int = 0):
+    """The library's streaming copy kernel (bandwidth reference)."""
+    _check(lib().gmpea_copy(ctypes.c_void_p(src_dev_ptr), ctypes.c_void_p(dst_dev_ptr), int(nbytes),
+                            ctypes.c_void_p(stream) if stream else None))
 
 
 def philox(ctr_dev_ptr: int, n: int, seed: int, out_dev_ptr: int, stream: int = 0):

@@ -167,6 +167,22 @@ def test_philox_device_bit_exact(G):
     assert np.array_equal(got, want)
 
 
+def test_copy_probe(G):
+    n = (3 << 20) + 16 * 7  # ragged against the block size
+    data = np.random.default_rng(3).integers(0, 2**32, size=n // 4, dtype=np.uint64).astype(np.uint32)
+    src, dst = G.DeviceBuffer(n), G.DeviceBuffer(n)
+    try:
+        src.upload(data)
+        G.copy(src.ptr.value, dst.ptr.value, n)
+        got = dst.download(np.empty_like(data))
+    finally:
+        src.free()
+        dst.free()
+    assert np.array_equal(got, data)
+    with pytest.raises(G.GmpeaError):
+        G.copy(0, 0, 17)
+
+
 @pytest.mark.parametrize("which", ["small", "medium"])
 def test_structures_and_init(G, which):
     prob, cfg, _ = ci.WORKLOADS[which](0)
