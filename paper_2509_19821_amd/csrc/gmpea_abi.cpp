@@ -335,6 +335,7 @@ gmpea_status gmpea_init(const gmpea_problem *P, const gmpea_config *C, const gmp
   st.pm_e = static_cast<float>(1.0 / (eta_m + 1.0));
   st.tpm = static_cast<uint64_t>(std::floor(pm * 4294967296.0));
   st.tpc = static_cast<uint64_t>(std::floor(pc * 4294967296.0));
+  st.inv_tpm = st.tpm > 0 ? static_cast<float>(1.0 / static_cast<double>(st.tpm)) : 0.0f;
   st.key0 = static_cast<uint32_t>(C->seed & 0xFFFFFFFFull);
   st.key1 = static_cast<uint32_t>(C->seed >> 32);
   DevProblem &dp = st.prob;
@@ -355,8 +356,9 @@ gmpea_status gmpea_init(const gmpea_problem *P, const gmpea_config *C, const gmp
 
   const size_t rows = static_cast<size_t>(st.nblk) * kBlock;
   bool ok = true;
-  float *lb = alloc_n<float>(h, d), *ub = alloc_n<float>(h, d);
-  ok = ok && lb && ub;
+  float *lb = alloc_n<float>(h, st.stride), *ub = alloc_n<float>(h, st.stride);
+  float *inv_span = alloc_n<float>(h, st.stride);
+  ok = ok && lb && ub && inv_span;
   for (int p = 0; p < 2 && ok; ++p) {
     st.X[p] = alloc_n<float>(h, rows * st.stride);
     st.XO[p] = alloc_n<float>(h, rows * st.stride);
@@ -389,11 +391,15 @@ gmpea_status gmpea_init(const gmpea_problem *P, const gmpea_config *C, const gmp
   }
   dp.lb = lb;
   dp.ub = ub;
+  dp.inv_span = inv_span;
 
-  std::vector<float> lbf(d), ubf(d);
+  // bounds padded to the row stride; padding lanes get [0, 1]
+  std::vector<float> lbf(st.stride, 0.0f), ubf(st.stride, 1.0f), isf(st.stride, 1.0f);
   for (int32_t l = 0; l < d; ++l) {
-    lbf[l] = P->lb ? static_cast<float>(P->lb[l]) : 0.0f;
-    ubf[l] = P->ub ? static_cast<float>(P->ub[l]) : 1.0f;
+    const double lo = P->lb ? P->lb[l] : 0.0, hi = P->ub ? P->ub[l] : 1.0;
+    lbf[l] = static_cast<float>(lo);
+    ubf[l] = static_cast<float>(hi);
+    isf[l] = static_cast<float>(1.0 / (static_cast<double>(ubf[l]) - static_cast<double>(lbf[l])));
   }
   hipError_t e = hipSuccess;
   auto cp = [&](void *dst, const void *src, size_t bytes) {
@@ -402,8 +408,9 @@ gmpea_status gmpea_init(const gmpea_problem *P, const gmpea_config *C, const gmp
   auto zero = [&](void *dst, int v, size_t bytes) {
     if (e == hipSuccess) e = hipMemsetAsync(dst, v, bytes, h->stream);
   };
-  cp(lb, lbf.data(), d * sizeof(float));
-  cp(ub, ubf.data(), d * sizeof(float));
+  cp(lb, lbf.data(), st.stride * sizeof(float));
+  cp(ub, ubf.data(), st.stride * sizeof(float));
+  cp(inv_span, isf.data(), st.stride * sizeof(float));
   cp(st.W, wdev.data(), N * sizeof(float4));
   for (int p = 0; p < 2; ++p) {
     cp(const_cast<int32_t *>(st.B[p]), h->b_host[p].data(), h->b_host[p].size() * sizeof(int32_t));

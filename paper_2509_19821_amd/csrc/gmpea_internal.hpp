@@ -29,7 +29,8 @@ struct DevProblem {
   float ring_r2[kMaxRing];         // squared radii
   float sum_lower, eq_tol;
   float g_scale;                   // 9 / (d - 1) for the curve family
-  const float *lb, *ub;            // device, d each
+  const float *lb, *ub;            // device, stride each (padding: 0 and 1)
+  const float *inv_span;           // device, 1 / (ub - lb), stride each
 };
 
 // Device state of one instance. Rows of X are `stride` floats (d rounded up to a
@@ -54,6 +55,7 @@ struct DevState {
   int32_t *win[2];           // optional record of winners (n)
   uint32_t key0, key1;       // RNG key
   uint64_t tpm, tpc;         // mutation / crossover thresholds floor(p 2^32)
+  float inv_tpm;             // 1 / tpm
   float sbx_e;               // 1 / (eta_c + 1)
   float pm_p, pm_e;          // eta_m + 1, 1 / (eta_m + 1)
   DevProblem prob;

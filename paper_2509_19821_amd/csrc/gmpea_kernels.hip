@@ -30,12 +30,15 @@ namespace gmpea {
 // ----------------------------------------------------------------------------
 // Counter RNG: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).
 // ----------------------------------------------------------------------------
+// Each round's two 32 x 32 -> 64-bit products are written as 64-bit multiplies
+// so that each becomes one v_mad_u64_u32 (high and low words together).
 __device__ __forceinline__ uint4 philox10(uint4 c, uint32_t k0, uint32_t k1) {
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
-    const uint32_t hi0 = __umulhi(0xD2511F53u, c.x), lo0 = 0xD2511F53u * c.x;
-    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c.z), lo1 = 0xCD9E8D57u * c.z;
-    c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+    const uint64_t p0 = static_cast<uint64_t>(0xD2511F53u) * c.x;
+    const uint64_t p1 = static_cast<uint64_t>(0xCD9E8D57u) * c.z;
+    c = make_uint4(static_cast<uint32_t>(p1 >> 32) ^ c.y ^ k0, static_cast<uint32_t>(p1),
+                   static_cast<uint32_t>(p0 >> 32) ^ c.w ^ k1, static_cast<uint32_t>(p0));
     k0 += 0x9E3779B9u;
     k1 += 0xBB67AE85u;
   }
@@ -62,9 +65,11 @@ __device__ __forceinline__ int xcd_tile(int b, int G) {
   return x * q + min(x, r) + (b >> 3);
 }
 
+// x^e for x >= 0 with the hardware log2/exp2 (about 1 ulp each). Every base
+// used here is either exactly 0 (giving 0 for e > 0) or a normal number; a
+// result below the normal range flushes to 0, which no caller can tell apart.
 __device__ __forceinline__ float powpos(float x, float e) {
-  // x^e for x >= 0 (x = 0 gives 0 for e > 0 and +inf for e < 0)
-  return exp2f(e * log2f(x));
+  return __builtin_amdgcn_exp2f(e * __builtin_amdgcn_logf(x));
 }
 
 // ----------------------------------------------------------------------------
@@ -72,7 +77,7 @@ __device__ __forceinline__ float powpos(float x, float e) {
 // sign bit, 24-bit uniform) then clip, then bounded polynomial mutation.
 // ----------------------------------------------------------------------------
 __device__ __forceinline__ float vary1(float a, float b, uint32_t wA, uint32_t wB, float lo, float hi,
-                                       bool cross, const DevState &st) {
+                                       float inv_span, bool cross, const DevState &st) {
   float c = a;
   if (cross && (wA & 1u)) {
     const float u = u24(wA);
@@ -87,19 +92,18 @@ __device__ __forceinline__ float vary1(float a, float b, uint32_t wA, uint32_t w
     // 2(u - 1/2)) comes from an exact integer numerator over tpm, and 1 - delta
     // from the distance to the far bound: in FP32, 1 - u itself cancels
     // catastrophically as u -> 1 and val^(1/(eta+1)) magnifies that error.
-    const float tp = static_cast<float>(st.tpm);
     const float span = hi - lo;
     float dq;
     if (2u * w < st.tpm) {
-      const float u2 = static_cast<float>(2u * w) / tp;
-      const float om = static_cast<float>(st.tpm - 2u * w) / tp;
-      const float xy = (hi - c) / span;
+      const float u2 = static_cast<float>(2u * w) * st.inv_tpm;
+      const float om = static_cast<float>(st.tpm - 2u * w) * st.inv_tpm;
+      const float xy = (hi - c) * inv_span;
       const float val = u2 + om * powpos(xy, st.pm_p);
       dq = powpos(val, st.pm_e) - 1.0f;
     } else {
-      const float a2 = static_cast<float>(2u * (st.tpm - w)) / tp;
-      const float b2 = static_cast<float>(2u * w - st.tpm) / tp;
-      const float xy = (c - lo) / span;
+      const float a2 = static_cast<float>(2u * (st.tpm - w)) * st.inv_tpm;
+      const float b2 = static_cast<float>(2u * w - st.tpm) * st.inv_tpm;
+      const float xy = (c - lo) * inv_span;
       const float val = a2 + b2 * powpos(xy, st.pm_p);
       dq = 1.0f - powpos(val, st.pm_e);
     }
@@ -241,18 +245,28 @@ __global__ __launch_bounds__(kBlock) void k_init(DevState st) {
 // Draws (reading R5/R6 of the design notes): MATE block (0, i, k, MATE|p) gives
 // the two neighbourhood positions and the per-offspring crossing draw; VAR block
 // (l >> 1, i, k, VAR|p) gives (wA, wB) for variables l, l + 1.
+// A group of LPO consecutive lanes builds one offspring: lane g of the group
+// takes the float4 chunks g, g + LPO, ... of the row, so with LPO = 8 the group
+// reads each parent row and writes the offspring row as whole 128-byte lines.
+// The group shares the mating draw (each lane computes it; the cost is one
+// Philox block either way) and reduces the evaluation sums with butterflies.
 // ----------------------------------------------------------------------------
-template <int M, int FAM>
+template <int M, int FAM, int LPO>
 __global__ __launch_bounds__(kBlock) void k_vary(DevState st) {
+  constexpr int kPer = kBlock / LPO;  // offspring per block
+  const int half = gridDim.x >> 1;    // blocks per population
   const int L = xcd_tile(blockIdx.x, gridDim.x);
-  const int p = L >= st.nblk ? 1 : 0;
-  const int i = (L - p * st.nblk) * kBlock + threadIdx.x;
+  const int p = L >= half ? 1 : 0;
+  const int g = threadIdx.x & (LPO - 1);
+  const int i = (L - p * half) * kPer + threadIdx.x / LPO;
   const uint32_t k = *st.gen + 1u;
   const uint32_t tagp = (p << 16);
   float zv[M];
 #pragma unroll
   for (int q = 0; q < M; ++q) zv[q] = __builtin_huge_valf();
-  if (i < st.n) {
+  const bool live = i < st.n;
+  EvalAcc e{0.0f, 0.0f, 0.0f};
+  if (live) {
     const int t = st.t[p];
     const uint4 w = philox10(make_uint4(0u, i, k, (kTagMate << 24) | tagp), st.key0, st.key1);
     const uint32_t r1 = __umulhi(w.x, static_cast<uint32_t>(t));
@@ -263,7 +277,7 @@ __global__ __launch_bounds__(kBlock) void k_vary(DevState st) {
     }
     const int32_t *Bi = st.B[p] + static_cast<size_t>(i) * t;
     const int pa = Bi[r1], pb = Bi[r2];
-    if (st.mate[p]) {
+    if (st.mate[p] && g == 0) {
       st.mate[p][2 * i] = pa;
       st.mate[p][2 * i + 1] = pb;
     }
@@ -271,34 +285,43 @@ __global__ __launch_bounds__(kBlock) void k_vary(DevState st) {
     const float4 *ra = reinterpret_cast<const float4 *>(st.X[p] + static_cast<size_t>(pa) * st.stride);
     const float4 *rb = reinterpret_cast<const float4 *>(st.X[p] + static_cast<size_t>(pb) * st.stride);
     float4 *ro = reinterpret_cast<float4 *>(st.XO[p] + static_cast<size_t>(i) * st.stride);
+    const float4 *lb4 = reinterpret_cast<const float4 *>(st.prob.lb);
+    const float4 *ub4 = reinterpret_cast<const float4 *>(st.prob.ub);
+    const float4 *is4 = reinterpret_cast<const float4 *>(st.prob.inv_span);
     const uint32_t tagv = (kTagVar << 24) | tagp;
-    EvalAcc e{0.0f, 0.0f, 0.0f};
     const int nq = st.stride >> 2;
-    for (int q = 0; q < nq; ++q) {
+    for (int q = g; q < nq; q += LPO) {
       const int l0 = q << 2;
-      const float4 va = ra[q], vb = rb[q];
+      const float4 va = ra[q], vb = rb[q], lo = lb4[q], hi = ub4[q], is = is4[q];
       const uint4 r0 = philox10(make_uint4(2 * q, i, k, tagv), st.key0, st.key1);
       uint4 r1w = make_uint4(0, 0, 0, 0);
       if (l0 + 2 < st.d) r1w = philox10(make_uint4(2 * q + 1, i, k, tagv), st.key0, st.key1);
       float4 o = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-      if (l0 < st.d) {
-        o.x = vary1(va.x, vb.x, r0.x, r0.y, st.prob.lb[l0], st.prob.ub[l0], cross, st);
-        eval_add<M, FAM>(e, l0, o.x);
-      }
+      o.x = vary1(va.x, vb.x, r0.x, r0.y, lo.x, hi.x, is.x, cross, st);
+      eval_add<M, FAM>(e, l0, o.x);
       if (l0 + 1 < st.d) {
-        o.y = vary1(va.y, vb.y, r0.z, r0.w, st.prob.lb[l0 + 1], st.prob.ub[l0 + 1], cross, st);
+        o.y = vary1(va.y, vb.y, r0.z, r0.w, lo.y, hi.y, is.y, cross, st);
         eval_add<M, FAM>(e, l0 + 1, o.y);
       }
       if (l0 + 2 < st.d) {
-        o.z = vary1(va.z, vb.z, r1w.x, r1w.y, st.prob.lb[l0 + 2], st.prob.ub[l0 + 2], cross, st);
+        o.z = vary1(va.z, vb.z, r1w.x, r1w.y, lo.z, hi.z, is.z, cross, st);
         eval_add<M, FAM>(e, l0 + 2, o.z);
       }
       if (l0 + 3 < st.d) {
-        o.w = vary1(va.w, vb.w, r1w.z, r1w.w, st.prob.lb[l0 + 3], st.prob.ub[l0 + 3], cross, st);
+        o.w = vary1(va.w, vb.w, r1w.z, r1w.w, lo.w, hi.w, is.w, cross, st);
         eval_add<M, FAM>(e, l0 + 3, o.w);
       }
       ro[q] = o;
     }
+  }
+  // Group reduction: the sums over the group's chunks, and x1, x2 from chunk 0
+  // (lane g = 0). Every lane of a wave takes part (no lane has left early).
+#pragma unroll
+  for (int o = 1; o < LPO; o <<= 1) e.s += __shfl_xor(e.s, o);
+  const int base = (threadIdx.x & 63) & ~(LPO - 1);
+  e.x0 = __shfl(e.x0, base);
+  e.x1 = __shfl(e.x1, base);
+  if (live && g == 0) {
     const float4 fc = eval_finish<M, FAM>(e, st.prob);
     st.FCO[p][i] = fc;
     zv[0] = fc.x;
@@ -531,10 +554,33 @@ hipError_t launch_init(const DevState &st, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <int LPO>
+static void launch_vary_lpo(const DevState &st, hipStream_t s) {
+  constexpr int per = kBlock / LPO;
+  const int grid = 2 * ((st.n + per - 1) / per);
+  if (st.m == 2 && st.prob.family == 0)
+    hipLaunchKernelGGL((k_vary<2, 0, LPO>), dim3(grid), dim3(kBlock), 0, s, st);
+  else if (st.m == 2)
+    hipLaunchKernelGGL((k_vary<2, 1, LPO>), dim3(grid), dim3(kBlock), 0, s, st);
+  else
+    hipLaunchKernelGGL((k_vary<3, 1, LPO>), dim3(grid), dim3(kBlock), 0, s, st);
+}
+
+// Lanes per offspring: enough that each lane keeps two to four float4 chunks.
+static int vary_lanes(const DevState &st) {
+  const int nq = st.stride >> 2;
+  return nq >= 16 ? 8 : nq >= 6 ? 4 : nq >= 3 ? 2 : 1;
+}
+
 hipError_t launch_phase(const DevState &st, int phase, hipStream_t s) {
-  if (phase == 0)
-    GMPEA_DISPATCH_MF(k_vary, 2 * st.nblk, st, s);
-  else if (phase == 1)
+  if (phase == 0) {
+    switch (vary_lanes(st)) {
+      case 8: launch_vary_lpo<8>(st, s); break;
+      case 4: launch_vary_lpo<4>(st, s); break;
+      case 2: launch_vary_lpo<2>(st, s); break;
+      default: launch_vary_lpo<1>(st, s); break;
+    }
+  } else if (phase == 1)
     GMPEA_DISPATCH_M(k_op1, st.nblk, s, st);
   else
     GMPEA_DISPATCH_M(k_select, 2 * st.nblk, s, st);
