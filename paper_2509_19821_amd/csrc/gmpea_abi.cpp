@@ -326,6 +326,13 @@ gmpea_status gmpea_init(const gmpea_problem *P, const gmpea_config *C, const gmp
   st.nblk = (N + kBlock - 1) / kBlock;
   st.t[0] = t1;
   st.t[1] = t2;
+  for (int p = 0; p < 2; ++p) {
+    int l = 1;
+    while (l < st.t[p] && l < 64) l <<= 1;
+    st.lps[p] = l;
+  }
+  st.sel_blocks0 = (N + kBlock / st.lps[0] - 1) / (kBlock / st.lps[0]);
+  st.sel_blocks1 = (N + kBlock / st.lps[1] - 1) / (kBlock / st.lps[1]);
   st.agg = C->agg;
   st.theta = static_cast<float>(C->theta > 0 ? C->theta : 5.0);
   const double eta_c = C->eta_c > 0 ? C->eta_c : 20.0, eta_m = C->eta_m > 0 ? C->eta_m : 20.0;

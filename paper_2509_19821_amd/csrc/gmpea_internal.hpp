@@ -39,6 +39,8 @@ struct DevProblem {
 struct DevState {
   int32_t n, m, d, stride, nblk;  // nblk: blocks of kBlock rows per population
   int32_t t[2];
+  int32_t lps[2];                  // lanes per slot in k_select (power of two <= 64)
+  int32_t sel_blocks0, sel_blocks1;  // k_select blocks of each population
   int32_t agg;
   float theta;
   float *X[2], *XO[2];

@@ -405,47 +405,68 @@ __global__ __launch_bounds__(kBlock) void k_op1(DevState st) {
 // lexicographic minimum over the qualifiers with the first index on ties; every
 // decision uses generation-k parents, and replacements land after all reads of
 // the slot they overwrite.
+// A group of lps lanes (lps = t_p rounded up to a power of two, at most 64)
+// decides one slot: lane g scans entries g, g + lps, ... of the slot's reverse
+// list (coalesced reads) keeping its lexicographic minimum of (CV, g, index),
+// and a butterfly over the group yields the minimum over all candidates. That
+// minimum qualifies exactly when some candidate qualifies, since qualifying
+// means being below the parent in the same order.
 // ----------------------------------------------------------------------------
+struct SelKey {
+  float c, g;
+  int i;
+};
+
+__device__ __forceinline__ bool sel_less(const SelKey &a, const SelKey &b) {
+  return a.c < b.c || (a.c == b.c && (a.g < b.g || (a.g == b.g && a.i < b.i)));
+}
+
 template <int M>
 __global__ __launch_bounds__(kBlock) void k_select(DevState st) {
   __shared__ int s_cnt;
   __shared__ int s_dst[kBlock];
   __shared__ const float4 *s_srcrow[kBlock];
   const int L = xcd_tile(blockIdx.x, gridDim.x);
-  const int p = L >= st.nblk ? 1 : 0;
-  const int j = (L - p * st.nblk) * kBlock + threadIdx.x;
+  const int p = L >= st.sel_blocks0 ? 1 : 0;
+  const int lps = st.lps[p];
+  const int g = threadIdx.x & (lps - 1);
+  const int j = (L - p * st.sel_blocks0) * (kBlock / lps) + threadIdx.x / lps;
   if (threadIdx.x == 0) s_cnt = 0;
   __syncthreads();
-  if (j < st.n) {
-    float z[M];
-    load_z<M>(st.zkey, z);
-    const float4 par = st.FC[p][j];
-    const float4 w = st.W[j];
-    float best_g = aggregate<M>(par, w, z, st.agg, st.theta);
-    float best_c = (p == 0) ? nan_inf(par.w) : 0.0f;
-    int win = -1;
-    const int q0 = st.roff[p][j], q1 = st.roff[p][j + 1];
+  const bool live = j < st.n;
+  SelKey best{__builtin_huge_valf(), __builtin_huge_valf(), 0x7FFFFFFF};
+  float4 w = make_float4(0, 0, 0, 0);
+  float z[M];
+  load_z<M>(st.zkey, z);
+  if (live) {
+    w = st.W[j];
+    const int q1 = st.roff[p][j + 1];
     const int32_t *rl = st.ridx[p];
     const float4 *cand = st.FCN[p];
-    for (int q = q0; q < q1; ++q) {
+    for (int q = st.roff[p][j] + g; q < q1; q += lps) {
       const int i = rl[q];
       const float4 c = cand[i];
-      const float g = aggregate<M>(c, w, z, st.agg, st.theta);
-      const float cv = (p == 0) ? nan_inf(c.w) : 0.0f;
-      const bool better = (cv < best_c) || (cv == best_c && g < best_g);
-      if (better) {
-        best_c = cv;
-        best_g = g;
-        win = i;
-      }
+      const SelKey k{(p == 0) ? nan_inf(c.w) : 0.0f, aggregate<M>(c, w, z, st.agg, st.theta), i};
+      if (sel_less(k, best)) best = k;
     }
-    if (st.win[p]) st.win[p][j] = win;
-    if (win >= 0) {
-      st.FC[p][j] = cand[win];
-      const int sp = p ^ ((st.src[win] >> p) & 1);
+  }
+  for (int o = 1; o < lps; o <<= 1) {
+    SelKey other{__shfl_xor(best.c, o), __shfl_xor(best.g, o), __shfl_xor(best.i, o)};
+    if (sel_less(other, best)) best = other;
+  }
+  if (live && g == 0) {
+    const float4 par = st.FC[p][j];
+    const float pc = (p == 0) ? nan_inf(par.w) : 0.0f;
+    const float pg = aggregate<M>(par, w, z, st.agg, st.theta);
+    const bool win = best.i != 0x7FFFFFFF && (best.c < pc || (best.c == pc && best.g < pg));
+    if (st.win[p]) st.win[p][j] = win ? best.i : -1;
+    if (win) {
+      st.FC[p][j] = st.FCN[p][best.i];
+      const int sp = p ^ ((st.src[best.i] >> p) & 1);
       const int slot = atomicAdd(&s_cnt, 1);
       s_dst[slot] = j;
-      s_srcrow[slot] = reinterpret_cast<const float4 *>(st.XO[sp] + static_cast<size_t>(win) * st.stride);
+      s_srcrow[slot] =
+          reinterpret_cast<const float4 *>(st.XO[sp] + static_cast<size_t>(best.i) * st.stride);
     }
   }
   __syncthreads();
@@ -580,10 +601,11 @@ hipError_t launch_phase(const DevState &st, int phase, hipStream_t s) {
       case 2: launch_vary_lpo<2>(st, s); break;
       default: launch_vary_lpo<1>(st, s); break;
     }
-  } else if (phase == 1)
+  } else if (phase == 1) {
     GMPEA_DISPATCH_M(k_op1, st.nblk, s, st);
-  else
-    GMPEA_DISPATCH_M(k_select, 2 * st.nblk, s, st);
+  } else {
+    GMPEA_DISPATCH_M(k_select, st.sel_blocks0 + st.sel_blocks1, s, st);
+  }
   return hipGetLastError();
 }
 
