@@ -31,6 +31,7 @@ extern "C" {
 #endif
 
 typedef struct gmpea_s *gmpea_t; /* opaque; owns the device memory of one instance */
+typedef struct gmpea_pool_s *gmpea_pool_t; /* opaque; a set of resident instances */
 
 typedef enum {
   GMPEA_OK = 0,
@@ -223,6 +224,54 @@ gmpea_status gmpea_profile(gmpea_t h, int32_t n_gen, float *ms);
  * synchronises. */
 gmpea_status gmpea_philox(const uint32_t *ctr, int64_t n, uint64_t seed, uint32_t *out,
                           void *hip_stream);
+
+/* ---------------------------------------------------------------------------
+ * Pools: many independent instances (uneven N, d, m, constraint counts) stay
+ * resident on the device and advance together. A batched generation is one
+ * launch per phase over every active instance; each instance computes exactly
+ * what it computes alone (same kernels, lane grouping and random streams), so
+ * results are bit-identical to gmpea_step on that instance by itself.
+ * ------------------------------------------------------------------------- */
+
+/* Create a pool whose instances may hold at most budget_bytes of device memory
+ * in total (the allocator hook, or hipMalloc, provides it). hip_stream: the
+ * stream every instance of the pool uses, or NULL for one the pool owns. */
+gmpea_status gmpea_pool_create(size_t budget_bytes, const gmpea_allocator *allocator,
+                               void *hip_stream, gmpea_pool_t *out);
+
+/* Initialise an instance inside the pool (as gmpea_init) and return its slot.
+ * ENOMEM when its footprint does not fit the remaining budget (nothing is kept). */
+gmpea_status gmpea_pool_admit(gmpea_pool_t pool, const gmpea_problem *problem,
+                              const gmpea_config *config, int32_t *slot);
+
+/* Enqueue n_gen batched generations of every active instance; asynchronous. */
+gmpea_status gmpea_pool_step(gmpea_pool_t pool, int32_t n_gen);
+
+/* Run n_gen batched generations while choosing the launch schedule (instance
+ * blocks grouped per XCD or in order) and the graph chunk length by timing the
+ * first generations; the choice stays for later steps. Results do not depend
+ * on it. *gens_done (may be NULL) receives the generations run. Synchronises. */
+gmpea_status gmpea_pool_tune(gmpea_pool_t pool, int32_t n_gen, int32_t *gens_done);
+
+/* The handle of a slot, for gmpea_front, gmpea_read, gmpea_write,
+ * gmpea_get_info and gmpea_step on that instance alone. The pool owns it: do
+ * not pass it to gmpea_destroy (use gmpea_pool_release). */
+gmpea_status gmpea_pool_handle(gmpea_pool_t pool, int32_t slot, gmpea_t *handle);
+
+/* Free a slot and its device memory (waits for the pool's work). */
+gmpea_status gmpea_pool_release(gmpea_pool_t pool, int32_t slot);
+
+/* Active instances, device bytes in use and the budget, and the launch policy
+ * (schedule 0: grouped per XCD, 1: in order; graph chunk length). Any output
+ * may be NULL. */
+gmpea_status gmpea_pool_query(gmpea_pool_t pool, int32_t *active, size_t *used_bytes,
+                              size_t *budget_bytes, int32_t *schedule, int32_t *chunk);
+
+/* Wait for all work enqueued on the pool's stream. */
+gmpea_status gmpea_pool_sync(gmpea_pool_t pool);
+
+/* Release every instance and the pool. NULL is a no-op. */
+void gmpea_pool_destroy(gmpea_pool_t pool);
 
 /* Streaming device-to-device copy of `bytes` (a multiple of 16; both pointers
  * 16-byte aligned device memory) with the library's own kernel: every byte read

@@ -116,11 +116,13 @@ T *alloc_n(gmpea_s *h, size_t n) {
   return static_cast<T *>(dev_alloc(h, n * sizeof(T)));
 }
 
-gmpea_status sync(gmpea_s *h, const char *what) {
-  hipError_t e = hipStreamSynchronize(h->stream);
+gmpea_status sync_stream(hipStream_t s, const char *what) {
+  hipError_t e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_fail(e, what);
   return GMPEA_OK;
 }
+
+gmpea_status sync(gmpea_s *h, const char *what) { return sync_stream(h->stream, what); }
 
 gmpea_status validate(const gmpea_problem *P, const gmpea_config *C) {
   if (!P || !C) return fail(GMPEA_EINVAL, "gmpea_init: problem and config are required");
@@ -774,6 +776,398 @@ gmpea_status gmpea_philox(const uint32_t *ctr, int64_t n, uint64_t seed, uint32_
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_fail(e, "gmpea_philox");
   return GMPEA_OK;
+}
+
+}  // extern "C"
+
+// ============================================================================
+// Pools: many resident instances advanced together (batched generations).
+// ============================================================================
+#include <unordered_map>
+
+struct gmpea_pool_s {
+  gmpea_allocator user{};
+  bool user_hook = false;
+  gmpea_allocator hook{};  // budget-enforcing hook handed to every instance
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  size_t budget = 0, used = 0;
+  std::unordered_map<void *, size_t> sizes;
+  std::vector<gmpea_t> slots;  // nullptr = free
+  // device tables
+  DevState *d_states = nullptr;
+  int32_t state_cap = 0;
+  int2 *d_work[kPhases] = {nullptr, nullptr, nullptr};
+  int32_t work_cap[kPhases] = {0, 0, 0};
+  int32_t nwork[kPhases] = {0, 0, 0};
+  bool dirty = true;
+  // launch policy (the autotuner may change both; results do not depend on them)
+  int32_t schedule = 0;  // 0: instance blocks grouped per XCD, 1: linear
+  int32_t chunk = 16;    // generations per graph replay
+  hipGraphExec_t gexec = nullptr;
+  int32_t gchunk = 0;
+};
+
+namespace {
+
+std::mutex g_pool_mu;
+std::unordered_set<const gmpea_pool_s *> g_pools;
+
+bool pool_valid(gmpea_pool_t q) {
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  return q != nullptr && g_pools.count(q) != 0;
+}
+
+void *pool_raw_alloc(gmpea_pool_s *q, size_t bytes) {
+  void *p = nullptr;
+  if (q->user_hook) {
+    p = q->user.alloc(bytes, q->user.ctx);
+  } else if (hipMalloc(&p, bytes) != hipSuccess) {
+    p = nullptr;
+  }
+  return p;
+}
+
+void pool_raw_free(gmpea_pool_s *q, void *p) {
+  if (q->user_hook)
+    q->user.free(p, q->user.ctx);
+  else
+    (void)hipFree(p);
+}
+
+// Allocator hook of the pool's instances: refuses what would exceed the budget.
+void *pool_hook_alloc(size_t bytes, void *ctx) {
+  gmpea_pool_s *q = static_cast<gmpea_pool_s *>(ctx);
+  if (q->used + bytes > q->budget) return nullptr;
+  void *p = pool_raw_alloc(q, bytes);
+  if (p) {
+    q->used += bytes;
+    q->sizes[p] = bytes;
+  }
+  return p;
+}
+
+void pool_hook_free(void *p, void *ctx) {
+  gmpea_pool_s *q = static_cast<gmpea_pool_s *>(ctx);
+  auto it = q->sizes.find(p);
+  if (it != q->sizes.end()) {
+    q->used -= it->second;
+    q->sizes.erase(it);
+  }
+  pool_raw_free(q, p);
+}
+
+template <class T>
+gmpea_status pool_table(gmpea_pool_s *q, T **ptr, int32_t *cap, int32_t need) {
+  if (need <= *cap) return GMPEA_OK;
+  int32_t ncap = std::max(need, 2 * *cap);
+  void *p = pool_raw_alloc(q, sizeof(T) * static_cast<size_t>(ncap));
+  if (!p) return fail(GMPEA_ENOMEM, "pool: table allocation failed");
+  if (*ptr) pool_raw_free(q, *ptr);
+  *ptr = static_cast<T *>(p);
+  *cap = ncap;
+  return GMPEA_OK;
+}
+
+int32_t phase_blocks(const DevState &st, int phase) {
+  if (phase == 0) return vary_blocks_of(st.n, vary_lanes_of(st.stride));
+  if (phase == 1) return st.nblk;
+  return st.sel_blocks0 + st.sel_blocks1;
+}
+
+// Work list of one phase. Schedule 0 keeps each instance's consecutive blocks
+// on one XCD (instances placed largest first on the least-loaded XCD, large
+// ones split into contiguous runs) so neighbouring subproblems share an L2;
+// the hardware deals block b to XCD b mod 8, hence the interleaving at the end.
+void build_work(const gmpea_pool_s *q, int phase, int schedule, std::vector<int2> &out) {
+  out.clear();
+  std::vector<std::pair<int32_t, int32_t>> inst;  // (blocks, slot)
+  int64_t total = 0;
+  for (int32_t s = 0; s < static_cast<int32_t>(q->slots.size()); ++s)
+    if (q->slots[s]) {
+      inst.emplace_back(phase_blocks(q->slots[s]->st, phase), s);
+      total += inst.back().first;
+    }
+  if (schedule == 1) {
+    for (auto &e : inst)
+      for (int32_t b = 0; b < e.first; ++b) out.push_back(make_int2(e.second, b));
+    return;
+  }
+  constexpr int kX = 8;
+  std::vector<std::vector<int2>> lane(kX);
+  std::vector<int64_t> load(kX, 0);
+  const int64_t share = (total + kX - 1) / kX;
+  std::sort(inst.begin(), inst.end(), [](const std::pair<int32_t, int32_t> &a,
+                                         const std::pair<int32_t, int32_t> &b) {
+    return a.first > b.first || (a.first == b.first && a.second < b.second);
+  });
+  for (auto &e : inst) {
+    int32_t b = 0;
+    while (b < e.first) {
+      const int x = static_cast<int>(std::min_element(load.begin(), load.end()) - load.begin());
+      const int64_t room = std::max<int64_t>(share - load[x], 1);
+      const int32_t take = static_cast<int32_t>(std::min<int64_t>(e.first - b, room));
+      for (int32_t k = 0; k < take; ++k) lane[x].push_back(make_int2(e.second, b + k));
+      load[x] += take;
+      b += take;
+    }
+  }
+  size_t len = 0;
+  for (auto &l : lane) len = std::max(len, l.size());
+  for (size_t j = 0; j < len; ++j)
+    for (int x = 0; x < kX; ++x) out.push_back(j < lane[x].size() ? lane[x][j] : make_int2(-1, -1));
+}
+
+gmpea_status pool_rebuild(gmpea_pool_s *q) {
+  if (!q->dirty) return GMPEA_OK;
+  if (q->gexec) {
+    (void)hipGraphExecDestroy(q->gexec);
+    q->gexec = nullptr;
+  }
+  gmpea_status s = sync_stream(q->stream, "pool");
+  if (s != GMPEA_OK) return s;
+  const int32_t ns = static_cast<int32_t>(q->slots.size());
+  s = pool_table(q, &q->d_states, &q->state_cap, std::max(ns, 1));
+  if (s != GMPEA_OK) return s;
+  std::vector<DevState> host(static_cast<size_t>(std::max(ns, 1)));
+  for (int32_t k = 0; k < ns; ++k)
+    if (q->slots[k]) host[k] = q->slots[k]->st;
+  hipError_t e = hipMemcpyAsync(q->d_states, host.data(), sizeof(DevState) * host.size(),
+                                hipMemcpyHostToDevice, q->stream);
+  std::vector<int2> w;
+  for (int ph = 0; ph < kPhases && e == hipSuccess; ++ph) {
+    build_work(q, ph, q->schedule, w);
+    s = pool_table(q, &q->d_work[ph], &q->work_cap[ph], std::max<int32_t>(1, static_cast<int32_t>(w.size())));
+    if (s != GMPEA_OK) return s;
+    q->nwork[ph] = static_cast<int32_t>(w.size());
+    if (!w.empty())
+      e = hipMemcpyAsync(q->d_work[ph], w.data(), sizeof(int2) * w.size(), hipMemcpyHostToDevice,
+                         q->stream);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(q->stream);
+  if (e != hipSuccess) return hip_fail(e, "pool rebuild");
+  q->dirty = false;
+  return GMPEA_OK;
+}
+
+hipError_t pool_generation(const gmpea_pool_s *q, hipStream_t s) {
+  for (int ph = 0; ph < kPhases; ++ph) {
+    hipError_t e = launch_batch_phase(q->d_states, q->d_work[ph], q->nwork[ph], ph, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+gmpea_status pool_enqueue(gmpea_pool_s *q, int32_t n) {
+  gmpea_status s = pool_rebuild(q);
+  if (s != GMPEA_OK) return s;
+  if (q->nwork[0] == 0) return GMPEA_OK;
+  const int32_t G = q->chunk;
+  if (G >= 2 && n >= G) {
+    if (!q->gexec || q->gchunk != G) {
+      if (q->gexec) {
+        (void)hipGraphExecDestroy(q->gexec);
+        q->gexec = nullptr;
+      }
+      hipStream_t cap;
+      hipError_t e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+      if (e != hipSuccess) return hip_fail(e, "pool graph stream");
+      e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+      if (e == hipSuccess) {
+        for (int32_t g = 0; g < G && e == hipSuccess; ++g) e = pool_generation(q, cap);
+        hipGraph_t graph = nullptr;
+        hipError_t e2 = hipStreamEndCapture(cap, &graph);
+        if (e == hipSuccess) e = e2;
+        if (e == hipSuccess) e = hipGraphInstantiate(&q->gexec, graph, nullptr, nullptr, 0);
+        if (graph) (void)hipGraphDestroy(graph);
+      }
+      (void)hipStreamDestroy(cap);
+      if (e != hipSuccess) {
+        q->gexec = nullptr;
+        return hip_fail(e, "pool graph capture");
+      }
+      q->gchunk = G;
+    }
+    while (n >= G) {
+      hipError_t e = hipGraphLaunch(q->gexec, q->stream);
+      if (e != hipSuccess) return hip_fail(e, "pool graph launch");
+      n -= G;
+    }
+  }
+  for (int32_t g = 0; g < n; ++g) {
+    hipError_t e = pool_generation(q, q->stream);
+    if (e != hipSuccess) return hip_fail(e, "pool generation launch");
+  }
+  return GMPEA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+gmpea_status gmpea_pool_create(size_t budget_bytes, const gmpea_allocator *A, void *hip_stream,
+                               gmpea_pool_t *out) {
+  if (!out) return fail(GMPEA_EINVAL, "gmpea_pool_create: out is NULL");
+  if (A && (!A->alloc || !A->free)) return fail(GMPEA_EINVAL, "gmpea_pool_create: incomplete allocator");
+  gmpea_status s = check_runtime("gmpea_pool_create");
+  if (s != GMPEA_OK) return s;
+  gmpea_pool_s *q = new gmpea_pool_s();
+  if (A) {
+    q->user = *A;
+    q->user_hook = true;
+  }
+  q->hook.alloc = pool_hook_alloc;
+  q->hook.free = pool_hook_free;
+  q->hook.ctx = q;
+  q->budget = budget_bytes;
+  if (const char *g = std::getenv("GMPEA_GRAPH_CHUNK")) q->chunk = std::atoi(g);
+  if (hip_stream) {
+    q->stream = static_cast<hipStream_t>(hip_stream);
+  } else {
+    hipError_t e = hipStreamCreateWithFlags(&q->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      delete q;
+      return hip_fail(e, "gmpea_pool_create: stream");
+    }
+    q->own_stream = true;
+  }
+  {
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    g_pools.insert(q);
+  }
+  *out = q;
+  return GMPEA_OK;
+}
+
+gmpea_status gmpea_pool_admit(gmpea_pool_t q, const gmpea_problem *P, const gmpea_config *C,
+                              int32_t *slot) {
+  if (!pool_valid(q)) return fail(GMPEA_ESTATE, "gmpea_pool_admit: invalid pool");
+  if (!slot) return fail(GMPEA_EINVAL, "gmpea_pool_admit: slot is NULL");
+  gmpea_t h = nullptr;
+  gmpea_status s = gmpea_init(P, C, &q->hook, q->stream, &h);
+  if (s == GMPEA_ENOMEM)
+    return fail(GMPEA_ENOMEM, "gmpea_pool_admit: the instance does not fit the pool's budget");
+  if (s != GMPEA_OK) return s;
+  int32_t k = 0;
+  while (k < static_cast<int32_t>(q->slots.size()) && q->slots[k]) ++k;
+  if (k == static_cast<int32_t>(q->slots.size())) q->slots.push_back(nullptr);
+  q->slots[k] = h;
+  q->dirty = true;
+  *slot = k;
+  return GMPEA_OK;
+}
+
+gmpea_status gmpea_pool_step(gmpea_pool_t q, int32_t n_gen) {
+  if (!pool_valid(q)) return fail(GMPEA_ESTATE, "gmpea_pool_step: invalid pool");
+  if (n_gen < 0) return fail(GMPEA_EINVAL, "gmpea_pool_step: n_gen < 0");
+  return pool_enqueue(q, n_gen);
+}
+
+gmpea_status gmpea_pool_tune(gmpea_pool_t q, int32_t n_gen, int32_t *gens_done) {
+  if (!pool_valid(q)) return fail(GMPEA_ESTATE, "gmpea_pool_tune: invalid pool");
+  if (n_gen < 0) return fail(GMPEA_EINVAL, "gmpea_pool_tune: n_gen < 0");
+  // Each candidate (schedule, chunk) runs real generations, timed with events;
+  // the fastest per generation is kept. The state advances by the generations
+  // run, whatever the choice, and results do not depend on it.
+  const int32_t cand[4][2] = {{0, 16}, {1, 16}, {0, 64}, {1, 64}};
+  hipEvent_t a, b;
+  if (hipEventCreate(&a) != hipSuccess) return fail(GMPEA_EHIP, "gmpea_pool_tune: event");
+  if (hipEventCreate(&b) != hipSuccess) {
+    (void)hipEventDestroy(a);
+    return fail(GMPEA_EHIP, "gmpea_pool_tune: event");
+  }
+  int32_t done = 0;
+  float best = 1e30f;
+  int32_t bs = q->schedule, bc = q->chunk;
+  gmpea_status s = GMPEA_OK;
+  for (int c = 0; c < 4 && s == GMPEA_OK; ++c) {
+    const int32_t gens = cand[c][1];
+    if (done + 2 * gens > n_gen) break;
+    if (q->schedule != cand[c][0]) q->dirty = true;
+    q->schedule = cand[c][0];
+    q->chunk = cand[c][1];
+    s = pool_rebuild(q);
+    if (s != GMPEA_OK) break;
+    s = pool_enqueue(q, gens);  // first replay also builds the graph; time the second half
+    if (s != GMPEA_OK) break;
+    (void)hipEventRecord(a, q->stream);
+    s = pool_enqueue(q, gens);
+    (void)hipEventRecord(b, q->stream);
+    if (s != GMPEA_OK) break;
+    (void)hipEventSynchronize(b);
+    float ms = 0.0f;
+    (void)hipEventElapsedTime(&ms, a, b);
+    done += 2 * gens;
+    if (ms / gens < best) {
+      best = ms / gens;
+      bs = cand[c][0];
+      bc = cand[c][1];
+    }
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (q->schedule != bs) q->dirty = true;
+  q->schedule = bs;
+  q->chunk = bc;
+  if (s == GMPEA_OK && done < n_gen) {
+    s = pool_enqueue(q, n_gen - done);
+    if (s == GMPEA_OK) done = n_gen;
+  }
+  if (gens_done) *gens_done = done;
+  return s;
+}
+
+gmpea_status gmpea_pool_handle(gmpea_pool_t q, int32_t slot, gmpea_t *h) {
+  if (!pool_valid(q)) return fail(GMPEA_ESTATE, "gmpea_pool_handle: invalid pool");
+  if (!h || slot < 0 || slot >= static_cast<int32_t>(q->slots.size()) || !q->slots[slot])
+    return fail(GMPEA_EINVAL, "gmpea_pool_handle: no such slot");
+  *h = q->slots[slot];
+  return GMPEA_OK;
+}
+
+gmpea_status gmpea_pool_release(gmpea_pool_t q, int32_t slot) {
+  if (!pool_valid(q)) return fail(GMPEA_ESTATE, "gmpea_pool_release: invalid pool");
+  if (slot < 0 || slot >= static_cast<int32_t>(q->slots.size()) || !q->slots[slot])
+    return fail(GMPEA_EINVAL, "gmpea_pool_release: no such slot");
+  gmpea_destroy(q->slots[slot]);
+  q->slots[slot] = nullptr;
+  q->dirty = true;
+  return GMPEA_OK;
+}
+
+gmpea_status gmpea_pool_query(gmpea_pool_t q, int32_t *active, size_t *used_bytes,
+                              size_t *budget_bytes, int32_t *schedule, int32_t *chunk) {
+  if (!pool_valid(q)) return fail(GMPEA_ESTATE, "gmpea_pool_query: invalid pool");
+  int32_t n = 0;
+  for (auto *h : q->slots) n += h != nullptr;
+  if (active) *active = n;
+  if (used_bytes) *used_bytes = q->used;
+  if (budget_bytes) *budget_bytes = q->budget;
+  if (schedule) *schedule = q->schedule;
+  if (chunk) *chunk = q->chunk;
+  return GMPEA_OK;
+}
+
+gmpea_status gmpea_pool_sync(gmpea_pool_t q) {
+  if (!pool_valid(q)) return fail(GMPEA_ESTATE, "gmpea_pool_sync: invalid pool");
+  return sync_stream(q->stream, "gmpea_pool_sync");
+}
+
+void gmpea_pool_destroy(gmpea_pool_t q) {
+  if (!pool_valid(q)) return;
+  {
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    g_pools.erase(q);
+  }
+  (void)hipStreamSynchronize(q->stream);
+  for (auto &h : q->slots)
+    if (h) gmpea_destroy(h);
+  if (q->gexec) (void)hipGraphExecDestroy(q->gexec);
+  if (q->d_states) pool_raw_free(q, q->d_states);
+  for (int ph = 0; ph < kPhases; ++ph)
+    if (q->d_work[ph]) pool_raw_free(q, q->d_work[ph]);
+  if (q->own_stream) (void)hipStreamDestroy(q->stream);
+  delete q;
 }
 
 }  // extern "C"

@@ -63,6 +63,20 @@ struct DevState {
   DevProblem prob;
 };
 
+// Launch geometry shared by host and device (plain and batched launches must
+// agree on it, since it fixes the lane grouping and so the rounding order).
+// Lanes per offspring in k_vary: enough that each lane keeps two to four float4
+// chunks of the row.
+__host__ __device__ inline int vary_lanes_of(int stride) {
+  const int nq = stride >> 2;
+  return nq >= 16 ? 8 : nq >= 6 ? 4 : nq >= 3 ? 2 : 1;
+}
+// k_vary blocks of one instance (both populations).
+__host__ __device__ inline int vary_blocks_of(int n, int lanes) {
+  const int per = kBlock / lanes;
+  return 2 * ((n + per - 1) / per);
+}
+
 // Launchers (gmpea_kernels.hip). Each enqueues on `s` and returns the launch status.
 hipError_t launch_init(const DevState &st, hipStream_t s);
 // A generation is kPhases launches: 0 variation + evaluation + ideal point,
@@ -70,6 +84,9 @@ hipError_t launch_init(const DevState &st, hipStream_t s);
 constexpr int kPhases = 3;
 hipError_t launch_phase(const DevState &st, int phase, hipStream_t s);
 hipError_t launch_generation(const DevState &st, hipStream_t s);
+// One phase of a batched generation over a pool: work[b] = (instance, block).
+hipError_t launch_batch_phase(const DevState *states, const int2 *work, int nwork, int phase,
+                              hipStream_t s);
 hipError_t launch_front_flags(const DevState &st, int pop, uint8_t *keep, hipStream_t s);
 hipError_t launch_gather(const DevState &st, int pop, const int32_t *idx, int32_t count,
                          float *x, float4 *fc, hipStream_t s);

@@ -252,10 +252,9 @@ __global__ __launch_bounds__(kBlock) void k_init(DevState st) {
 // Philox block either way) and reduces the evaluation sums with butterflies.
 // ----------------------------------------------------------------------------
 template <int M, int FAM, int LPO>
-__global__ __launch_bounds__(kBlock) void k_vary(DevState st) {
+__device__ __forceinline__ void vary_body(const DevState &st, int L, int G) {
   constexpr int kPer = kBlock / LPO;  // offspring per block
-  const int half = gridDim.x >> 1;    // blocks per population
-  const int L = xcd_tile(blockIdx.x, gridDim.x);
+  const int half = G >> 1;            // blocks per population
   const int p = L >= half ? 1 : 0;
   const int g = threadIdx.x & (LPO - 1);
   const int i = (L - p * half) * kPer + threadIdx.x / LPO;
@@ -331,6 +330,11 @@ __global__ __launch_bounds__(kBlock) void k_vary(DevState st) {
   block_zmin<M>(zv, st.zkey);
 }
 
+template <int M, int FAM, int LPO>
+__global__ __launch_bounds__(kBlock) void k_vary(DevState st) {
+  vary_body<M, FAM, LPO>(st, xcd_tile(blockIdx.x, gridDim.x), gridDim.x);
+}
+
 // ----------------------------------------------------------------------------
 // Aggregation. PBI (Eq. (7)) with the unit direction u = w / ||w|| stored in W:
 // d1 = |(F - z) . u|, d2 = ||F - z - d1 u||, g = d1 + theta d2. Tchebycheff:
@@ -381,8 +385,8 @@ __device__ __forceinline__ void load_z(const uint32_t *zkey, float (&z)[M]) {
 // (Eq. (8)); population 2 takes off1_i if its aggregation is lower.
 // ----------------------------------------------------------------------------
 template <int M>
-__global__ __launch_bounds__(kBlock) void k_op1(DevState st) {
-  const int i = blockIdx.x * kBlock + threadIdx.x;
+__device__ __forceinline__ void op1_body(const DevState &st, int b) {
+  const int i = b * kBlock + threadIdx.x;
   if (i >= st.n) return;
   float z[M];
   load_z<M>(st.zkey, z);
@@ -395,6 +399,11 @@ __global__ __launch_bounds__(kBlock) void k_op1(DevState st) {
   st.FCN[0][i] = s1 ? o2 : o1;
   st.FCN[1][i] = s2 ? o1 : o2;
   st.src[i] = static_cast<uint8_t>((s1 ? 1u : 0u) | (s2 ? 2u : 0u));
+}
+
+template <int M>
+__global__ __launch_bounds__(kBlock) void k_op1(DevState st) {
+  op1_body<M>(st, blockIdx.x);
 }
 
 // ----------------------------------------------------------------------------
@@ -422,11 +431,10 @@ __device__ __forceinline__ bool sel_less(const SelKey &a, const SelKey &b) {
 }
 
 template <int M>
-__global__ __launch_bounds__(kBlock) void k_select(DevState st) {
+__device__ __forceinline__ void select_body(const DevState &st, int L) {
   __shared__ int s_cnt;
   __shared__ int s_dst[kBlock];
   __shared__ const float4 *s_srcrow[kBlock];
-  const int L = xcd_tile(blockIdx.x, gridDim.x);
   const int p = L >= st.sel_blocks0 ? 1 : 0;
   const int lps = st.lps[p];
   const int g = threadIdx.x & (lps - 1);
@@ -480,10 +488,67 @@ __global__ __launch_bounds__(kBlock) void k_select(DevState st) {
     }
     if (threadIdx.x == 0) atomicAdd(&st.repl[p], static_cast<unsigned long long>(n));
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  if (L == 0 && threadIdx.x == 0) {
     // generations completed; next read by the following generation's k_vary
     st.gen[0] = st.gen[0] + 1u;
   }
+}
+
+template <int M>
+__global__ __launch_bounds__(kBlock) void k_select(DevState st) {
+  select_body<M>(st, xcd_tile(blockIdx.x, gridDim.x));
+}
+
+// ----------------------------------------------------------------------------
+// Batched generations: one launch per phase covers every instance of a pool.
+// Block b runs work item work[b] = (instance, block of that instance's plain
+// launch), on the instance's state in S; padding items (instance -1) idle.
+// Each item runs the very device function, template and lane grouping of the
+// plain launch, so every instance computes bit-identically to running alone.
+// ----------------------------------------------------------------------------
+template <int M, int FAM>
+__device__ __forceinline__ void vary_any_lanes(const DevState &st, int L) {
+  switch (vary_lanes_of(st.stride)) {
+    case 8: vary_body<M, FAM, 8>(st, L, vary_blocks_of(st.n, 8)); break;
+    case 4: vary_body<M, FAM, 4>(st, L, vary_blocks_of(st.n, 4)); break;
+    case 2: vary_body<M, FAM, 2>(st, L, vary_blocks_of(st.n, 2)); break;
+    default: vary_body<M, FAM, 1>(st, L, vary_blocks_of(st.n, 1)); break;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_vary_batch(const DevState *__restrict__ S,
+                                                      const int2 *__restrict__ work) {
+  const int2 wi = work[blockIdx.x];
+  if (wi.x < 0) return;
+  const DevState &st = S[wi.x];
+  if (st.m == 2 && st.prob.family == 0)
+    vary_any_lanes<2, 0>(st, wi.y);
+  else if (st.m == 2)
+    vary_any_lanes<2, 1>(st, wi.y);
+  else
+    vary_any_lanes<3, 1>(st, wi.y);
+}
+
+__global__ __launch_bounds__(kBlock) void k_op1_batch(const DevState *__restrict__ S,
+                                                     const int2 *__restrict__ work) {
+  const int2 wi = work[blockIdx.x];
+  if (wi.x < 0) return;
+  const DevState &st = S[wi.x];
+  if (st.m == 2)
+    op1_body<2>(st, wi.y);
+  else
+    op1_body<3>(st, wi.y);
+}
+
+__global__ __launch_bounds__(kBlock) void k_select_batch(const DevState *__restrict__ S,
+                                                        const int2 *__restrict__ work) {
+  const int2 wi = work[blockIdx.x];
+  if (wi.x < 0) return;
+  const DevState &st = S[wi.x];
+  if (st.m == 2)
+    select_body<2>(st, wi.y);
+  else
+    select_body<3>(st, wi.y);
 }
 
 // ----------------------------------------------------------------------------
@@ -577,8 +642,7 @@ hipError_t launch_init(const DevState &st, hipStream_t s) {
 
 template <int LPO>
 static void launch_vary_lpo(const DevState &st, hipStream_t s) {
-  constexpr int per = kBlock / LPO;
-  const int grid = 2 * ((st.n + per - 1) / per);
+  const int grid = vary_blocks_of(st.n, LPO);
   if (st.m == 2 && st.prob.family == 0)
     hipLaunchKernelGGL((k_vary<2, 0, LPO>), dim3(grid), dim3(kBlock), 0, s, st);
   else if (st.m == 2)
@@ -587,15 +651,9 @@ static void launch_vary_lpo(const DevState &st, hipStream_t s) {
     hipLaunchKernelGGL((k_vary<3, 1, LPO>), dim3(grid), dim3(kBlock), 0, s, st);
 }
 
-// Lanes per offspring: enough that each lane keeps two to four float4 chunks.
-static int vary_lanes(const DevState &st) {
-  const int nq = st.stride >> 2;
-  return nq >= 16 ? 8 : nq >= 6 ? 4 : nq >= 3 ? 2 : 1;
-}
-
 hipError_t launch_phase(const DevState &st, int phase, hipStream_t s) {
   if (phase == 0) {
-    switch (vary_lanes(st)) {
+    switch (vary_lanes_of(st.stride)) {
       case 8: launch_vary_lpo<8>(st, s); break;
       case 4: launch_vary_lpo<4>(st, s); break;
       case 2: launch_vary_lpo<2>(st, s); break;
@@ -606,6 +664,18 @@ hipError_t launch_phase(const DevState &st, int phase, hipStream_t s) {
   } else {
     GMPEA_DISPATCH_M(k_select, st.sel_blocks0 + st.sel_blocks1, s, st);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_phase(const DevState *states, const int2 *work, int nwork, int phase,
+                              hipStream_t s) {
+  if (nwork <= 0) return hipSuccess;
+  if (phase == 0)
+    hipLaunchKernelGGL(k_vary_batch, dim3(nwork), dim3(kBlock), 0, s, states, work);
+  else if (phase == 1)
+    hipLaunchKernelGGL(k_op1_batch, dim3(nwork), dim3(kBlock), 0, s, states, work);
+  else
+    hipLaunchKernelGGL(k_select_batch, dim3(nwork), dim3(kBlock), 0, s, states, work);
   return hipGetLastError();
 }
 

@@ -30,7 +30,9 @@ STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ECAPACITY", -5: 
           -6: "EUNSUPPORTED"}
 EXPORTS = ["gmpea_init", "gmpea_step", "gmpea_run", "gmpea_front", "gmpea_get_info", "gmpea_read",
            "gmpea_write", "gmpea_destroy", "gmpea_last_error", "gmpea_sync", "gmpea_profile",
-           "gmpea_philox", "gmpea_copy"]
+           "gmpea_philox", "gmpea_copy", "gmpea_pool_create", "gmpea_pool_admit",
+           "gmpea_pool_step", "gmpea_pool_tune", "gmpea_pool_handle", "gmpea_pool_release",
+           "gmpea_pool_query", "gmpea_pool_sync", "gmpea_pool_destroy"]
 PHASES = ("vary", "op1", "select")
 
 
@@ -128,8 +130,22 @@ def lib():
         L.gmpea_profile.argtypes = [vp, i32, vp]
         L.gmpea_sync.argtypes = [vp]
         L.gmpea_copy.argtypes = [vp, vp, ctypes.c_size_t, vp]
+        L.gmpea_pool_create.argtypes = [ctypes.c_size_t, ctypes.POINTER(Allocator), vp,
+                                        ctypes.POINTER(vp)]
+        L.gmpea_pool_admit.argtypes = [vp, ctypes.POINTER(Problem), ctypes.POINTER(Config),
+                                       ctypes.POINTER(i32)]
+        L.gmpea_pool_step.argtypes = [vp, i32]
+        L.gmpea_pool_tune.argtypes = [vp, i32, ctypes.POINTER(i32)]
+        L.gmpea_pool_handle.argtypes = [vp, i32, ctypes.POINTER(vp)]
+        L.gmpea_pool_release.argtypes = [vp, i32]
+        L.gmpea_pool_query.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_size_t),
+                                       ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(i32),
+                                       ctypes.POINTER(i32)]
+        L.gmpea_pool_sync.argtypes = [vp]
+        L.gmpea_pool_destroy.argtypes = [vp]
+        L.gmpea_pool_destroy.restype = None
         for name in EXPORTS:
-            if name not in ("gmpea_destroy", "gmpea_last_error"):
+            if name not in ("gmpea_destroy", "gmpea_last_error", "gmpea_pool_destroy"):
                 getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -181,6 +197,7 @@ class Gmpea:
                  record: bool = False):
         L = lib()
         self._h = None
+        self._owned = True
         m, d = int(problem["m"]), int(problem["d"])
         nr = int(np.asarray(problem["ring_radius"]).size)
         self._keep = [_f64(problem["lb"], d), _f64(problem["ub"], d),
@@ -206,9 +223,22 @@ class Gmpea:
                             ctypes.byref(self._alloc) if self._alloc else None,
                             ctypes.c_void_p(self.stream) if self.stream else None, ctypes.byref(h)))
         self._h = h
+        self._describe()
+
+    def _describe(self):
         inf = self.info()
         self.n, self.m, self.d = inf["n"], inf["m"], inf["d"]
         self.t = (inf["t1"], inf["t2"])
+
+    @classmethod
+    def _borrow(cls, handle, keep):
+        """View of a handle owned elsewhere (a pool slot); never destroyed here."""
+        obj = cls.__new__(cls)
+        obj._h = handle
+        obj._owned = False
+        obj._keep = keep
+        obj._describe()
+        return obj
 
     @staticmethod
     def _stream_handle(stream):
@@ -221,7 +251,8 @@ class Gmpea:
     # -- lifecycle ----------------------------------------------------------
     def close(self):
         if self._h is not None:
-            lib().gmpea_destroy(self._h)
+            if getattr(self, "_owned", True):
+                lib().gmpea_destroy(self._h)
             self._h = None
 
     def __del__(self):
@@ -326,6 +357,108 @@ def philox(ctr_dev_ptr: int, n: int, seed: int, out_dev_ptr: int, stream: int = 
     """Philox4x32-10 blocks on the device (pointers to n x 4 uint32 each)."""
     _check(lib().gmpea_philox(ctypes.c_void_p(ctr_dev_ptr), int(n), int(seed) & 0xFFFFFFFFFFFFFFFF,
                               ctypes.c_void_p(out_dev_ptr), ctypes.c_void_p(stream) if stream else None))
+
+
+def _structs(problem: dict, config: dict, record: bool = False):
+    m, d = int(problem["m"]), int(problem["d"])
+    nr = int(np.asarray(problem["ring_radius"]).size)
+    keep = [_f64(problem["lb"], d), _f64(problem["ub"], d),
+            _f64(problem["ring_center"], nr * m), _f64(problem["ring_radius"], nr)]
+    lb, ub, rc, rr = keep
+    P = Problem(int(problem["family"]), m, d, lb.ctypes.data, ub.ctypes.data, nr,
+                rc.ctypes.data if nr else None, rr.ctypes.data if nr else None,
+                int(problem["has_sum_lower"]), float(problem["sum_lower"]), int(problem["n_eq"]),
+                float(problem["eq_tol"]))
+    c = config
+    C = Config(int(c["n_req"]), int(c["T"]), int(c.get("t1", 0)), int(c.get("t2", 0)),
+               int(c.get("agg", 0)), float(c.get("theta", 0.0)), float(c.get("eta_c", 0.0)),
+               float(c.get("eta_m", 0.0)), float(c.get("pc", 0.0)), float(c.get("pm", 0.0)),
+               int(c["seed"]) & 0xFFFFFFFFFFFFFFFF, 1 if (record or c.get("record", 0)) else 0)
+    return P, C, keep
+
+
+class Pool:
+    """Resident instances advanced together by batched generations.
+    Results per instance are bit-identical to running that instance alone."""
+
+    def __init__(self, budget_bytes: int, stream=None):
+        L = lib()
+        self._q = None
+        h = ctypes.c_void_p()
+        _check(L.gmpea_pool_create(int(budget_bytes), None,
+                                   ctypes.c_void_p(stream) if stream else None, ctypes.byref(h)))
+        self._q = h
+        self._views = {}
+
+    def admit(self, problem: dict, config: dict, record: bool = False) -> int:
+        P, C, keep = _structs(problem, config, record)
+        slot = ctypes.c_int32(-1)
+        _check(lib().gmpea_pool_admit(self._q, ctypes.byref(P), ctypes.byref(C), ctypes.byref(slot)))
+        return int(slot.value)
+
+    def try_admit(self, problem: dict, config: dict, record: bool = False):
+        """Slot index, or None when the instance does not fit the budget."""
+        try:
+            return self.admit(problem, config, record)
+        except GmpeaError as e:
+            if e.status == -2:
+                return None
+            raise
+
+    def step(self, n_gen: int = 1):
+        _check(lib().gmpea_pool_step(self._q, int(n_gen)))
+
+    def tune(self, n_gen: int) -> int:
+        done = ctypes.c_int32(0)
+        _check(lib().gmpea_pool_tune(self._q, int(n_gen), ctypes.byref(done)))
+        return int(done.value)
+
+    def sync(self):
+        _check(lib().gmpea_pool_sync(self._q))
+
+    def instance(self, slot: int) -> "Gmpea":
+        """Borrowed view of one slot (front, read, write, info, step)."""
+        v = self._views.get(slot)
+        if v is None:
+            h = ctypes.c_void_p()
+            _check(lib().gmpea_pool_handle(self._q, int(slot), ctypes.byref(h)))
+            v = Gmpea._borrow(h, self)
+            self._views[slot] = v
+        return v
+
+    def release(self, slot: int):
+        v = self._views.pop(slot, None)
+        if v is not None:
+            v._h = None
+        _check(lib().gmpea_pool_release(self._q, int(slot)))
+
+    def query(self) -> dict:
+        a, s, c = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_int32(0)
+        u, b = ctypes.c_size_t(0), ctypes.c_size_t(0)
+        _check(lib().gmpea_pool_query(self._q, ctypes.byref(a), ctypes.byref(u), ctypes.byref(b),
+                                      ctypes.byref(s), ctypes.byref(c)))
+        return {"active": a.value, "used_bytes": u.value, "budget_bytes": b.value,
+                "schedule": s.value, "chunk": c.value}
+
+    def close(self):
+        if self._q is not None:
+            for v in self._views.values():
+                v._h = None
+            self._views.clear()
+            lib().gmpea_pool_destroy(self._q)
+            self._q = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
 
 class DeviceBuffer:
