@@ -80,11 +80,20 @@ def test_tuning_does_not_change_results(G):
 def test_admission_by_budget_and_release(G):
     small = ci.workload_small(0)[:2]
     medium = ci.workload_medium(0)[:2]
-    pool = G.Pool(3 << 20)  # room for a few small instances, not for a medium one
+    probe = G.Pool(1 << 30)
+    try:
+        probe.admit(*small)
+        one = probe.query()["used_bytes"]
+        probe.admit(*medium)
+        med = probe.query()["used_bytes"] - one
+    finally:
+        probe.close()
+    assert med > 2 * one
+    pool = G.Pool(int(2.5 * one))  # two small instances, never a medium one
     try:
         a = pool.admit(*small)
         used = pool.query()["used_bytes"]
-        assert 0 < used <= 3 << 20
+        assert used == one
         assert pool.try_admit(*medium) is None          # footprint above what is left
         assert pool.query()["used_bytes"] == used        # nothing kept from the refusal
         b = pool.admit(*small)
