@@ -22,6 +22,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -112,6 +114,72 @@ def copy_probe(g, nbytes=512 << 20, reps=5):
     return 2.0 * nbytes / best / 1e9
 
 
+def batched_vs_plain(g, ci, count=256, gens=300):
+    """Instance throughput of one pool (batched generations) against the same
+    instances solved one after another with plain launches, plus a bitwise
+    comparison of every instance's final population 1 (equal fronts, so equal
+    IGD, by construction)."""
+    insts = ci.batch_instances(count=count, master_seed=0)
+    plain_s, plain_f = 0.0, []
+    t_init = time.perf_counter()
+    for p, c in insts:
+        gp = g.Gmpea(p, c)
+        gp.sync()
+        t0 = time.perf_counter()
+        gp.step(gens)
+        gp.sync()
+        plain_s += time.perf_counter() - t0
+        plain_f.append((gp.read("F", 0), gp.read("CV", 0)))
+        gp.close()
+    log("bench: plain %d instances x %d generations: %.3f s solving (%.1f s total)"
+        % (count, gens, plain_s, time.perf_counter() - t_init))
+    pool = g.Pool(200 << 30)
+    try:
+        slots = [pool.admit(p, c) for p, c in insts]
+        pool.sync()
+        t0 = time.perf_counter()
+        pool.tune(gens)
+        pool.sync()
+        batched_s = time.perf_counter() - t0
+        q = pool.query()
+        same = all(np.array_equal(pool.instance(s).read("F", 0), f) and
+                   np.array_equal(pool.instance(s).read("CV", 0), cv)
+                   for s, (f, cv) in zip(slots, plain_f))
+        offspring = sum(2 * pool.instance(s).n for s in slots) * gens
+    finally:
+        pool.close()
+    log("bench: batched: %.3f s (schedule %d, chunk %d), identical=%s"
+        % (batched_s, q["schedule"], q["chunk"], same))
+    return {"instances": count, "generations": gens,
+            "plain_instances_per_s": round(count / plain_s, 2),
+            "batched_instances_per_s": round(count / batched_s, 2),
+            "speedup": round(plain_s / batched_s, 2),
+            "batched_offspring_per_s": round(offspring / batched_s, 1),
+            "final_fronts_identical": bool(same), "device_bytes": int(q["used_bytes"]),
+            "schedule": "xcd-grouped" if q["schedule"] == 0 else "linear",
+            "graph_chunk": q["chunk"]}
+
+
+def serving(g, ci, window_s=5.0, rate=200.0):
+    """Poisson arrivals at `rate` per second over `window_s`, deadlines
+    log-uniform in [10 ms, 1 s], problems from the batched-instance
+    distribution; continuous batching over one pool."""
+    from paper_2509_19821_amd.serve import Request, Server, summarize
+    arr = ci.serve_arrivals(rate=rate, window_s=window_s, master_seed=0)
+    inst = ci.batch_instances(count=len(arr), master_seed=1)
+    reqs = [Request(k, p, c, dl, t) for k, ((t, dl), (p, c)) in enumerate(zip(arr, inst))]
+    srv = Server(200 << 30, keep_fronts=False)
+    try:
+        t0 = time.perf_counter()
+        res = srv.run(reqs)
+        wall = time.perf_counter() - t0
+        out = summarize(res, wall, srv.offspring)
+        out.update({"window_s": window_s, "rate_per_s": rate, "batched_steps": srv.steps})
+    finally:
+        srv.close()
+    return {k: (round(v, 5) if isinstance(v, float) else v) for k, v in out.items()}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -119,6 +187,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--profile-gens", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serve-window", type=float, default=5.0)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -181,6 +252,12 @@ def main():
                                   "%d generations in the full solve" % (n, K_total),
                       "global_batch": 2 * n, "parallelism": "single GPU"},
            "roofline": roof}
+    if not args.no_batched:
+        log("bench: batched instances")
+        out["batched"] = batched_vs_plain(g, ci)
+    if not args.no_serving:
+        log("bench: serving")
+        out["serving"] = serving(g, ci, window_s=args.serve_window)
     if not args.no_cpu_baseline:
         log("bench: timing the CPU oracle")
         out["cpu_baseline"] = cpu_baseline()

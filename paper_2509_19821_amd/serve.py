@@ -1,0 +1,147 @@
+"""Continuous-batching solve server over a pool of resident GMPEA instances.
+
+Requests (a CMOP, method parameters and a deadline) arrive over time. A request
+is admitted into the pool as soon as its device-memory footprint fits the
+budget; until then it waits in arrival order. Every loop iteration advances all
+resident solves by one batched generation (one launch per phase for all of
+them). When a solve's deadline has passed, the loop stops it at that
+generation boundary, as in the paper's fixed-time protocol (a run reaching its
+time limit outputs its current set), takes its feasible non-dominated front
+(population 1) and frees its slot for waiting requests.
+
+Each delivered result records how many generations the solve received, so it
+can be reproduced exactly: an instance advanced alone for that many generations
+computes the same front bit for bit.
+"""
+from __future__ import annotations
+
+import collections
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from .gmpea import Pool
+
+
+@dataclass
+class Request:
+    rid: int
+    problem: dict
+    config: dict
+    deadline_s: float          # time allowed after arrival
+    arrival: float = 0.0       # wall-clock arrival (seconds since the server started)
+
+
+@dataclass
+class Result:
+    rid: int
+    arrival: float
+    admitted: float
+    delivered: float
+    deadline: float            # absolute deadline (arrival + deadline_s)
+    generations: int
+    n: int
+    front_f: np.ndarray = field(repr=False)
+    front_x: np.ndarray = field(repr=False)
+
+    @property
+    def latency(self):
+        return self.delivered - self.arrival
+
+    @property
+    def lateness(self):
+        return self.delivered - self.deadline
+
+
+class Server:
+    """Single-threaded serving loop on one GPU (one pool, one stream)."""
+
+    def __init__(self, budget_bytes: int, clock=time.perf_counter, keep_fronts: bool = True):
+        self.pool = Pool(budget_bytes)
+        self.clock = clock
+        self.t0 = None
+        self.waiting = collections.deque()
+        self.active = {}       # slot -> (request, admitted time, start generation)
+        self.results = []
+        self.offspring = 0     # offspring evaluated and selected so far
+        self.steps = 0
+        self.keep_fronts = keep_fronts
+
+    def now(self) -> float:
+        if self.t0 is None:
+            self.t0 = self.clock()
+        return self.clock() - self.t0
+
+    def submit(self, req: Request):
+        self.waiting.append(req)
+
+    def _admit(self):
+        while self.waiting:
+            req = self.waiting[0]
+            slot = self.pool.try_admit(req.problem, req.config)
+            if slot is None:
+                if not self.active:
+                    raise MemoryError("request %d does not fit an empty pool" % req.rid)
+                return  # wait for a slot to free up
+            self.waiting.popleft()
+            inst = self.pool.instance(slot)
+            self.active[slot] = (req, self.now(), inst.n)
+
+    def _harvest(self, force: bool = False):
+        t = self.now()
+        for slot in list(self.active):
+            req, admitted, n = self.active[slot]
+            if force or t >= req.arrival + req.deadline_s:
+                inst = self.pool.instance(slot)
+                fr = inst.front()
+                gens = int(inst.read("GEN")[0])
+                delivered = self.now()
+                self.results.append(Result(req.rid, req.arrival, admitted, delivered,
+                                           req.arrival + req.deadline_s, gens, n,
+                                           fr["f"] if self.keep_fronts else fr["f"][:0],
+                                           fr["x"] if self.keep_fronts else fr["x"][:0]))
+                self.pool.release(slot)
+                del self.active[slot]
+
+    def step(self):
+        """Admit what fits, advance every resident solve one generation, deliver
+        the solves whose deadline has passed."""
+        self._admit()
+        if self.active:
+            self.pool.step(1)
+            self.pool.sync()
+            self.steps += 1
+            self.offspring += sum(2 * n for (_, _, n) in self.active.values())
+        self._harvest()
+
+    def run(self, requests, idle_sleep: float = 2e-4):
+        """Serve requests, each with its arrival time (seconds from start),
+        until every one has been delivered. Returns the results."""
+        pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
+        self.now()
+        while pending or self.waiting or self.active:
+            t = self.now()
+            while pending and pending[0].arrival <= t:
+                self.submit(pending.popleft())
+            if not self.waiting and not self.active:
+                time.sleep(min(idle_sleep, max(0.0, pending[0].arrival - t)) if pending else 0)
+                continue
+            self.step()
+        return self.results
+
+    def close(self):
+        self.pool.close()
+
+
+def summarize(results, wall_s: float, offspring: int) -> dict:
+    lat = np.array([r.latency for r in results])
+    late = np.array([r.lateness for r in results])
+    return {"requests": len(results),
+            "p50_time_to_front_s": float(np.percentile(lat, 50)) if len(lat) else None,
+            "p99_time_to_front_s": float(np.percentile(lat, 99)) if len(lat) else None,
+            "p50_past_deadline_s": float(np.percentile(late, 50)) if len(late) else None,
+            "p99_past_deadline_s": float(np.percentile(late, 99)) if len(late) else None,
+            "mean_generations": float(np.mean([r.generations for r in results])) if results else 0,
+            "offspring_per_s": offspring / wall_s if wall_s > 0 else None,
+            "wall_s": wall_s}

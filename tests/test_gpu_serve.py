@@ -1,0 +1,74 @@
+"""Continuous-batching server: results are the same alone and in the mix (at
+the generation count each solve received), and requests wait for memory."""
+import numpy as np
+import pytest
+
+import cmop_inputs as ci
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def G():
+    import paper_2509_19821_amd as g
+    assert g.device_count() >= 1, "GPU tests need a visible MI355X"
+    return g
+
+
+def _requests(n, seed, d_lo=0.02, d_hi=0.15, rate=400.0):
+    from paper_2509_19821_amd.serve import Request
+    arr = ci.serve_arrivals(rate=rate, window_s=n / rate * 1.5, master_seed=seed,
+                            d_lo=d_lo, d_hi=d_hi)[:n]
+    inst = ci.batch_instances(count=n, master_seed=seed, n_hi=3000, d_hi=40)
+    return [Request(k, p, c, dl, t) for k, ((t, dl), (p, c)) in enumerate(zip(arr, inst))]
+
+
+def test_served_results_equal_alone(G):
+    from paper_2509_19821_amd.serve import Server, summarize
+    reqs = _requests(24, seed=5)
+    srv = Server(4 << 30)
+    try:
+        res = srv.run(reqs)
+    finally:
+        srv.close()
+    assert sorted(r.rid for r in res) == list(range(len(reqs)))
+    s = summarize(res, max(r.delivered for r in res), srv.offspring)
+    assert s["p99_time_to_front_s"] is not None
+    by = {r.rid: r for r in res}
+    for rid in (0, 5, 11, 17, 23):
+        r, q = by[rid], reqs[rid]
+        assert r.generations >= 1
+        gp = G.Gmpea(q.problem, q.config)
+        try:
+            gp.step(r.generations)
+            fr = gp.front()
+        finally:
+            gp.close()
+        assert np.array_equal(fr["f"], r.front_f), rid
+        assert np.array_equal(fr["x"], r.front_x), rid
+
+
+def test_requests_wait_for_memory(G):
+    from paper_2509_19821_amd.serve import Request, Server
+    prob, cfg, _ = ci.workload_medium(0)
+    probe = G.Pool(1 << 30)
+    try:
+        probe.admit(prob, cfg)
+        one = probe.query()["used_bytes"]
+    finally:
+        probe.close()
+    reqs = [Request(k, prob, dict(cfg, seed=k), 0.03, 0.0) for k in range(5)]
+    srv = Server(int(2.2 * one))
+    peak = 0
+    try:
+        for r in reqs:
+            srv.submit(r)
+        srv.now()
+        while srv.waiting or srv.active:
+            srv.step()
+            peak = max(peak, len(srv.active))
+    finally:
+        srv.close()
+    assert peak == 2
+    assert len(srv.results) == 5
+    assert all(r.generations >= 1 for r in srv.results)
