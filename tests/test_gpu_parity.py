@@ -379,3 +379,45 @@ def test_record_disabled_rejects_decision_reads(G):
         assert cnt["x"].shape[1] == 10
     finally:
         gp.close()
+
+
+def test_front_capacity_reports_required_count(G):
+    """An undersized output reports GMPEA_ECAPACITY and the required row count."""
+    import ctypes
+    import paper_2509_19821_amd as g
+    from paper_2509_19821_amd import gmpea as GM
+    prob, cfg, _ = ci.workload_small(2)
+    gp = g.Gmpea(prob, cfg)
+    try:
+        gp.step(20)
+        n = gp.front()["x"].shape[0]
+        assert n >= 2
+        cap = n - 1
+        x = np.empty((cap, gp.d), dtype=np.float32)
+        f = np.empty((cap, gp.m), dtype=np.float32)
+        cv = np.empty(cap, dtype=np.float32)
+        idx = np.empty(cap, dtype=np.int32)
+        cnt = ctypes.c_int32(-7)
+        st = GM.lib().gmpea_front(gp.handle, g.FRONT_FEASIBLE_ND, cap, x.ctypes.data,
+                                  f.ctypes.data, cv.ctypes.data, idx.ctypes.data, ctypes.byref(cnt))
+        assert st == -4 and cnt.value == n
+        assert GM.lib().gmpea_last_error()
+    finally:
+        gp.close()
+
+
+def test_generation_nan_constraint_constant(G):
+    """A NaN ring radius makes that constraint's value NaN; the clamp max(0, .)
+    of Eq. (2) reads it as satisfied on both sides (comparisons with NaN are
+    false), and the generation matches the oracle as usual."""
+    prob, cfg, _ = ci.workload_small(6)
+    prob["ring_radius"] = np.array(prob["ring_radius"], dtype=np.float64)
+    prob["ring_radius"][0] = np.nan
+    gp, o = _pair(prob, cfg)
+    try:
+        gp.step(2)
+        frac = _teacher_forced(gp, o, 2, "nan ring radius")
+        assert frac < 0.005
+        assert np.all(np.isfinite(gp.read("CV", 0)))
+    finally:
+        gp.close()
