@@ -173,7 +173,8 @@ def serving(g, ci, window_s=5.0, rate=200.0):
         t0 = time.perf_counter()
         res = srv.run(reqs)
         wall = time.perf_counter() - t0
-        out = summarize(res, wall, srv.offspring)
+        out = summarize(res, wall, srv.offspring, srv.host_s)
+        out["host_s"] = {k: round(v, 3) for k, v in out["host_s"].items()}
         out.update({"window_s": window_s, "rate_per_s": rate, "batched_steps": srv.steps})
     finally:
         srv.close()

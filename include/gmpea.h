@@ -217,13 +217,28 @@ const char *gmpea_last_error(void);
  * are real (the state advances). Synchronises. */
 gmpea_status gmpea_profile(gmpea_t h, int32_t n_gen, float *ms);
 
-/* The counter RNG every draw of the method uses (reading R5 of the design
- * notes): Philox4x32-10 of Salmon et al. (SC'11). n blocks: out[4i..4i+3] =
+/* The counter RNG every draw of the method uses (the paper names none):
+ * Philox4x32-10 of Salmon et al. (SC'11). n blocks: out[4i..4i+3] =
  * Philox(ctr[4i..4i+3], key = (seed low word, seed high word)). ctr and out are
  * device pointers; the call enqueues on hip_stream (NULL: legacy default) and
  * synchronises. */
 gmpea_status gmpea_philox(const uint32_t *ctr, int64_t n, uint64_t seed, uint32_t *out,
                           void *hip_stream);
+
+/* Reference vectors and neighbourhoods of Alg. 1 ("uniform reference vectors"
+ * and "neighbours initialization"), computed on the host with no GPU work, as
+ * gmpea_init builds them. H is the smallest number of divisions whose
+ * Das-Dennis count C(H + m - 1, m - 1) reaches n_req, and N is that count.
+ * K (N x m, row-major, caller-owned; may be NULL): the lattice rows k with
+ * k_1 + ... + k_m = H in ascending lexicographic order of (k_1 .. k_{m-1});
+ * the reference vectors are W = K / H. B (N x t, caller-owned; may be NULL):
+ * for each row i the t rows nearest by squared lattice distance, ties by
+ * ascending index, so row i itself comes first. *H_out and *n_out (may be
+ * NULL) receive H and N. EINVAL for m outside [2, GMPEA_MAX_M], n_req < 2 or
+ * t outside [1, N]; ECAPACITY (with *n_out set) when cap_rows < N and K or B
+ * is given. */
+gmpea_status gmpea_lattice(int32_t m, int32_t n_req, int32_t t, int32_t cap_rows, int32_t *K,
+                           int32_t *B, int32_t *H_out, int32_t *n_out);
 
 /* ---------------------------------------------------------------------------
  * Pools: many independent instances (uneven N, d, m, constraint counts) stay
@@ -233,9 +248,12 @@ gmpea_status gmpea_philox(const uint32_t *ctr, int64_t n, uint64_t seed, uint32_
  * results are bit-identical to gmpea_step on that instance by itself.
  * ------------------------------------------------------------------------- */
 
-/* Create a pool whose instances may hold at most budget_bytes of device memory
- * in total (the allocator hook, or hipMalloc, provides it). hip_stream: the
- * stream every instance of the pool uses, or NULL for one the pool owns. */
+/* Create a pool that may reserve at most budget_bytes of device memory in
+ * total, for its instances and its own tables. Memory is reserved in chunks of
+ * up to 256 MiB from the allocator hook (or hipMalloc) as instances are
+ * admitted, carved into blocks, and recycled when instances are released; the
+ * chunks are returned only by gmpea_pool_destroy. hip_stream: the stream every
+ * instance of the pool uses, or NULL for one the pool owns. */
 gmpea_status gmpea_pool_create(size_t budget_bytes, const gmpea_allocator *allocator,
                                void *hip_stream, gmpea_pool_t *out);
 

@@ -9,7 +9,8 @@
  * this file shares no code, header or table with the product path.
  *
  * Every function cites the passage of the paper it follows. Where the paper is
- * silent, the reading taken is named R<n> and listed with the design notes.
+ * silent, the reading taken is stated where it applies and tagged R<n>; the same
+ * tag marks the same reading in the kernels and the tests.
  *
  * Plain loops throughout; OpenMP only spreads independent subproblems over
  * threads (results are identical for any thread count).

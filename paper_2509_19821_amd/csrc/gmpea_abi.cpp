@@ -5,6 +5,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdlib>
+#include <map>
 #include <mutex>
 #include <string>
 #include <unordered_set>
@@ -43,6 +44,11 @@ struct gmpea_s {
   std::vector<std::pair<void *, size_t>> allocs;
   size_t bytes = 0;
   std::vector<float> w_raw;      // N x m reference vectors (host copy)
+  // gmpea_front scratch (flags, row list, gathered rows), allocated on first use
+  uint8_t *f_keep = nullptr;
+  int32_t *f_idx = nullptr;
+  float *f_x = nullptr;
+  float4 *f_fc = nullptr;
   std::vector<int32_t> b_host[2];
   // graph replay of `gchunk` generations
   hipGraphExec_t gexec = nullptr;
@@ -111,10 +117,19 @@ void register_live(gmpea_s *h, bool on) {
     g_live.erase(h);
 }
 
-template <class T>
-T *alloc_n(gmpea_s *h, size_t n) {
-  return static_cast<T *>(dev_alloc(h, n * sizeof(T)));
-}
+// Several device arrays carved out of one allocation (256-byte aligned pieces):
+// a first pass with no base sizes the block, a second hands out the pointers.
+struct Carve {
+  char *base = nullptr;
+  size_t off = 0;
+  template <class T>
+  T *take(size_t n) {
+    off = (off + 255) & ~static_cast<size_t>(255);
+    T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+    off += std::max<size_t>(n * sizeof(T), 1);
+    return p;
+  }
+};
 
 gmpea_status sync_stream(hipStream_t s, const char *what) {
   hipError_t e = hipStreamSynchronize(s);
@@ -329,8 +344,9 @@ gmpea_status gmpea_init(const gmpea_problem *P, const gmpea_config *C, const gmp
   st.t[0] = t1;
   st.t[1] = t2;
   for (int p = 0; p < 2; ++p) {
+    // lanes per slot in k_select: about four reverse-list entries per lane
     int l = 1;
-    while (l < st.t[p] && l < 64) l <<= 1;
+    while (4 * l < st.t[p] && l < 64) l <<= 1;
     st.lps[p] = l;
   }
   st.sel_blocks0 = (N + kBlock / st.lps[0] - 1) / (kBlock / st.lps[0]);
@@ -364,40 +380,39 @@ gmpea_status gmpea_init(const gmpea_problem *P, const gmpea_config *C, const gmp
   dp.g_scale = d > 1 ? static_cast<float>(9.0 / (d - 1)) : 0.0f;
 
   const size_t rows = static_cast<size_t>(st.nblk) * kBlock;
-  bool ok = true;
-  float *lb = alloc_n<float>(h, st.stride), *ub = alloc_n<float>(h, st.stride);
-  float *inv_span = alloc_n<float>(h, st.stride);
-  ok = ok && lb && ub && inv_span;
-  for (int p = 0; p < 2 && ok; ++p) {
-    st.X[p] = alloc_n<float>(h, rows * st.stride);
-    st.XO[p] = alloc_n<float>(h, rows * st.stride);
-    st.FC[p] = alloc_n<float4>(h, rows);
-    st.FCO[p] = alloc_n<float4>(h, rows);
-    st.FCN[p] = alloc_n<float4>(h, rows);
-    int32_t *b = alloc_n<int32_t>(h, static_cast<size_t>(N) * ts[p]);
-    int32_t *ro = alloc_n<int32_t>(h, static_cast<size_t>(N) + 1);
-    int32_t *ri = alloc_n<int32_t>(h, static_cast<size_t>(N) * ts[p]);
-    st.B[p] = b;
-    st.roff[p] = ro;
-    st.ridx[p] = ri;
-    st.mate[p] = h->record ? alloc_n<int32_t>(h, rows * 2) : nullptr;
-    st.win[p] = h->record ? alloc_n<int32_t>(h, rows) : nullptr;
-    ok = st.X[p] && st.XO[p] && st.FC[p] && st.FCO[p] && st.FCN[p] && b && ro && ri &&
-         (!h->record || (st.mate[p] && st.win[p]));
-  }
-  if (ok) {
-    st.W = alloc_n<float4>(h, rows);
-    st.src = alloc_n<uint8_t>(h, rows);
-    st.zkey = alloc_n<uint32_t>(h, 4);
-    st.gen = alloc_n<uint32_t>(h, 4);
-    st.repl = alloc_n<unsigned long long>(h, 2);
-    ok = st.W && st.src && st.zkey && st.gen && st.repl;
-  }
-  if (!ok) {
+  float *lb = nullptr, *ub = nullptr, *inv_span = nullptr;
+  auto layout = [&](Carve &c) {
+    lb = c.take<float>(st.stride);
+    ub = c.take<float>(st.stride);
+    inv_span = c.take<float>(st.stride);
+    for (int p = 0; p < 2; ++p) {
+      st.X[p] = c.take<float>(rows * st.stride);
+      st.XO[p] = c.take<float>(rows * st.stride);
+      st.FC[p] = c.take<float4>(rows);
+      st.FCO[p] = c.take<float4>(rows);
+      st.FCN[p] = c.take<float4>(rows);
+      st.B[p] = c.take<int32_t>(static_cast<size_t>(N) * ts[p]);
+      st.roff[p] = c.take<int32_t>(static_cast<size_t>(N) + 1);
+      st.ridx[p] = c.take<int32_t>(static_cast<size_t>(N) * ts[p]);
+      st.mate[p] = h->record ? c.take<int32_t>(rows * 2) : nullptr;
+      st.win[p] = h->record ? c.take<int32_t>(rows) : nullptr;
+    }
+    st.W = c.take<float4>(rows);
+    st.src = c.take<uint8_t>(rows);
+    st.zkey = c.take<uint32_t>(4);
+    st.gen = c.take<uint32_t>(4);
+    st.repl = c.take<unsigned long long>(2);
+  };
+  Carve sizing;
+  layout(sizing);
+  Carve carve;
+  carve.base = static_cast<char *>(dev_alloc(h, sizing.off));
+  if (!carve.base) {
     release_all(h);
     delete h;
     return fail(GMPEA_ENOMEM, "gmpea_init: device allocation failed");
   }
+  layout(carve);
   dp.lb = lb;
   dp.ub = ub;
   dp.inv_span = inv_span;
@@ -501,14 +516,29 @@ gmpea_status gmpea_front(gmpea_t h, int32_t what, int32_t capacity, float *x, fl
   if (capacity < 0) return fail(GMPEA_EINVAL, "gmpea_front: negative capacity");
   const DevState &st = h->st;
   const int pop = what == GMPEA_FRONT_POP2 ? 1 : 0;
+  if (!h->f_keep) {
+    auto layout = [&](Carve &c) {
+      h->f_keep = c.take<uint8_t>(st.n);
+      h->f_idx = c.take<int32_t>(st.n);
+      h->f_x = c.take<float>(static_cast<size_t>(st.n) * st.d);
+      h->f_fc = c.take<float4>(st.n);
+    };
+    Carve sizing;
+    layout(sizing);
+    Carve carve;
+    carve.base = static_cast<char *>(dev_alloc(h, sizing.off));
+    if (!carve.base) {
+      h->f_keep = nullptr;
+      return fail(GMPEA_ENOMEM, "gmpea_front: scratch allocation failed");
+    }
+    layout(carve);
+  }
   std::vector<int32_t> rows;
   if (what == GMPEA_FRONT_FEASIBLE_ND) {
-    uint8_t *keep = alloc_n<uint8_t>(h, st.n);
-    if (!keep) return fail(GMPEA_ENOMEM, "gmpea_front: scratch allocation failed");
-    hipError_t e = launch_front_flags(st, pop, keep, h->stream);
+    hipError_t e = launch_front_flags(st, pop, h->f_keep, h->stream);
     std::vector<uint8_t> hk(st.n);
-    gmpea_status s = e == hipSuccess ? d2h(h, hk.data(), keep, st.n, "gmpea_front") : hip_fail(e, "gmpea_front");
-    dev_free(h, keep);
+    gmpea_status s =
+        e == hipSuccess ? d2h(h, hk.data(), h->f_keep, st.n, "gmpea_front") : hip_fail(e, "gmpea_front");
     if (s != GMPEA_OK) return s;
     for (int32_t i = 0; i < st.n; ++i)
       if (hk[i]) rows.push_back(i);
@@ -523,11 +553,10 @@ gmpea_status gmpea_front(gmpea_t h, int32_t what, int32_t capacity, float *x, fl
   if (cnt > capacity) return fail(GMPEA_ECAPACITY, "gmpea_front: capacity below the row count");
   if (cnt == 0) return GMPEA_OK;
   if (idx) std::copy(rows.begin(), rows.end(), idx);
-  int32_t *didx = alloc_n<int32_t>(h, cnt);
-  float *dx = alloc_n<float>(h, static_cast<size_t>(cnt) * st.d);
-  float4 *dfc = alloc_n<float4>(h, cnt);
+  int32_t *didx = h->f_idx;
+  float *dx = h->f_x;
+  float4 *dfc = h->f_fc;
   gmpea_status s = GMPEA_OK;
-  if (!didx || !dx || !dfc) s = fail(GMPEA_ENOMEM, "gmpea_front: scratch allocation failed");
   std::vector<float4> hfc;
   if (s == GMPEA_OK) s = h2d(h, didx, rows.data(), cnt, "gmpea_front");
   if (s == GMPEA_OK) {
@@ -547,9 +576,6 @@ gmpea_status gmpea_front(gmpea_t h, int32_t what, int32_t capacity, float *x, fl
       if (cv) cv[r] = v[3];
     }
   }
-  if (didx) dev_free(h, didx);
-  if (dx) dev_free(h, dx);
-  if (dfc) dev_free(h, dfc);
   return s;
 }
 
@@ -785,14 +811,31 @@ gmpea_status gmpea_philox(const uint32_t *ctr, int64_t n, uint64_t seed, uint32_
 // ============================================================================
 #include <unordered_map>
 
+// Device memory of a pool: chunks reserved from hipMalloc (or the caller's
+// allocator) and carved first-fit into 256-byte aligned blocks, with freed
+// blocks merged with free neighbours. Chunks stay reserved until the pool is
+// destroyed, so admitting and releasing instances costs no runtime allocation
+// once the pool has grown. The budget bounds the bytes reserved.
+struct PoolArena {
+  struct Chunk {
+    char *base = nullptr;
+    size_t size = 0;
+    std::map<size_t, size_t> free;  // offset -> length, non-adjacent
+  };
+  std::vector<Chunk> chunks;
+  std::unordered_map<void *, std::pair<size_t, size_t>> live;  // ptr -> (chunk, length)
+  size_t reserved = 0, used = 0;
+  static constexpr size_t kChunk = size_t(256) << 20;
+};
+
 struct gmpea_pool_s {
   gmpea_allocator user{};
   bool user_hook = false;
-  gmpea_allocator hook{};  // budget-enforcing hook handed to every instance
+  gmpea_allocator hook{};  // arena-backed hook handed to every instance
   hipStream_t stream = nullptr;
   bool own_stream = false;
-  size_t budget = 0, used = 0;
-  std::unordered_map<void *, size_t> sizes;
+  size_t budget = 0;
+  PoolArena arena;
   std::vector<gmpea_t> slots;  // nullptr = free
   // device tables
   DevState *d_states = nullptr;
@@ -818,7 +861,7 @@ bool pool_valid(gmpea_pool_t q) {
   return q != nullptr && g_pools.count(q) != 0;
 }
 
-void *pool_raw_alloc(gmpea_pool_s *q, size_t bytes) {
+void *pool_chunk_alloc(gmpea_pool_s *q, size_t bytes) {
   void *p = nullptr;
   if (q->user_hook) {
     p = q->user.alloc(bytes, q->user.ctx);
@@ -828,34 +871,83 @@ void *pool_raw_alloc(gmpea_pool_s *q, size_t bytes) {
   return p;
 }
 
-void pool_raw_free(gmpea_pool_s *q, void *p) {
+void pool_chunk_free(gmpea_pool_s *q, void *p) {
   if (q->user_hook)
     q->user.free(p, q->user.ctx);
   else
     (void)hipFree(p);
 }
 
-// Allocator hook of the pool's instances: refuses what would exceed the budget.
-void *pool_hook_alloc(size_t bytes, void *ctx) {
-  gmpea_pool_s *q = static_cast<gmpea_pool_s *>(ctx);
-  if (q->used + bytes > q->budget) return nullptr;
-  void *p = pool_raw_alloc(q, bytes);
-  if (p) {
-    q->used += bytes;
-    q->sizes[p] = bytes;
+void *arena_take(gmpea_pool_s *q, size_t c, size_t bytes) {
+  PoolArena::Chunk &ch = q->arena.chunks[c];
+  for (auto it = ch.free.begin(); it != ch.free.end(); ++it) {
+    if (it->second < bytes) continue;
+    const size_t off = it->first, len = it->second;
+    ch.free.erase(it);
+    if (len > bytes) ch.free.emplace(off + bytes, len - bytes);
+    void *p = ch.base + off;
+    q->arena.live.emplace(p, std::make_pair(c, bytes));
+    q->arena.used += bytes;
+    return p;
   }
-  return p;
+  return nullptr;
 }
 
-void pool_hook_free(void *p, void *ctx) {
-  gmpea_pool_s *q = static_cast<gmpea_pool_s *>(ctx);
-  auto it = q->sizes.find(p);
-  if (it != q->sizes.end()) {
-    q->used -= it->second;
-    q->sizes.erase(it);
-  }
-  pool_raw_free(q, p);
+void *pool_raw_alloc(gmpea_pool_s *q, size_t bytes) {
+  PoolArena &A = q->arena;
+  bytes = (std::max<size_t>(bytes, 1) + 255) & ~static_cast<size_t>(255);
+  for (size_t c = 0; c < A.chunks.size(); ++c)
+    if (void *p = arena_take(q, c, bytes)) return p;
+  if (A.reserved + bytes > q->budget) return nullptr;
+  const size_t size = std::max(bytes, std::min(PoolArena::kChunk, q->budget - A.reserved));
+  void *base = pool_chunk_alloc(q, size);
+  if (!base) return nullptr;
+  PoolArena::Chunk ch;
+  ch.base = static_cast<char *>(base);
+  ch.size = size;
+  ch.free.emplace(0, size);
+  A.chunks.push_back(std::move(ch));
+  A.reserved += size;
+  return arena_take(q, A.chunks.size() - 1, bytes);
 }
+
+void pool_raw_free(gmpea_pool_s *q, void *p) {
+  PoolArena &A = q->arena;
+  auto it = A.live.find(p);
+  if (it == A.live.end()) return;
+  const size_t c = it->second.first, len = it->second.second;
+  A.live.erase(it);
+  A.used -= len;
+  PoolArena::Chunk &ch = A.chunks[c];
+  size_t off = static_cast<size_t>(static_cast<char *>(p) - ch.base), n = len;
+  auto next = ch.free.lower_bound(off);
+  if (next != ch.free.end() && off + n == next->first) {  // merge with the following block
+    n += next->second;
+    next = ch.free.erase(next);
+  }
+  if (next != ch.free.begin()) {  // merge with the preceding block
+    auto prev = std::prev(next);
+    if (prev->first + prev->second == off) {
+      off = prev->first;
+      n += prev->second;
+      ch.free.erase(prev);
+    }
+  }
+  ch.free.emplace(off, n);
+}
+
+void pool_arena_destroy(gmpea_pool_s *q) {
+  for (auto &ch : q->arena.chunks) pool_chunk_free(q, ch.base);
+  q->arena = PoolArena();
+}
+
+// Allocator hook of the pool's instances: blocks of the pool's arena (NULL when
+// the budget cannot hold the request).
+void *pool_hook_alloc(size_t bytes, void *ctx) {
+  return pool_raw_alloc(static_cast<gmpea_pool_s *>(ctx), bytes);
+}
+
+void pool_hook_free(void *p, void *ctx) { pool_raw_free(static_cast<gmpea_pool_s *>(ctx), p); }
 
 template <class T>
 gmpea_status pool_table(gmpea_pool_s *q, T **ptr, int32_t *cap, int32_t need) {
@@ -1005,6 +1097,32 @@ gmpea_status pool_enqueue(gmpea_pool_s *q, int32_t n) {
 
 extern "C" {
 
+gmpea_status gmpea_lattice(int32_t m, int32_t n_req, int32_t t, int32_t cap_rows, int32_t *K,
+                           int32_t *B, int32_t *H_out, int32_t *n_out) {
+  if (m < 2 || m > GMPEA_MAX_M) return fail(GMPEA_EINVAL, "gmpea_lattice: m out of range");
+  if (n_req < 2 || n_req > (1 << 26)) return fail(GMPEA_EINVAL, "gmpea_lattice: n_req out of range");
+  const int32_t H = dd_divisions(m, n_req);
+  const int64_t n = dd_count(m, H);
+  if (n > (int64_t(1) << 27)) return fail(GMPEA_EUNSUPPORTED, "gmpea_lattice: lattice too large");
+  if (t < 1 || t > n) return fail(GMPEA_EINVAL, "gmpea_lattice: t must lie in [1, N]");
+  if (H_out) *H_out = H;
+  if (n_out) *n_out = static_cast<int32_t>(n);
+  if (!K && !B) return GMPEA_OK;
+  if (cap_rows < n) return fail(GMPEA_ECAPACITY, "gmpea_lattice: cap_rows below N");
+  try {
+    std::vector<int32_t> KK, BB;
+    dd_lattice(m, H, KK);
+    if (K) std::memcpy(K, KK.data(), KK.size() * sizeof(int32_t));
+    if (B) {
+      lattice_knn(KK, m, H, t, BB);
+      std::memcpy(B, BB.data(), BB.size() * sizeof(int32_t));
+    }
+  } catch (const std::bad_alloc &) {
+    return fail(GMPEA_ENOMEM, "gmpea_lattice: host memory");
+  }
+  return GMPEA_OK;
+}
+
 gmpea_status gmpea_pool_create(size_t budget_bytes, const gmpea_allocator *A, void *hip_stream,
                                gmpea_pool_t *out) {
   if (!out) return fail(GMPEA_EINVAL, "gmpea_pool_create: out is NULL");
@@ -1141,7 +1259,7 @@ gmpea_status gmpea_pool_query(gmpea_pool_t q, int32_t *active, size_t *used_byte
   int32_t n = 0;
   for (auto *h : q->slots) n += h != nullptr;
   if (active) *active = n;
-  if (used_bytes) *used_bytes = q->used;
+  if (used_bytes) *used_bytes = q->arena.used;
   if (budget_bytes) *budget_bytes = q->budget;
   if (schedule) *schedule = q->schedule;
   if (chunk) *chunk = q->chunk;
@@ -1166,6 +1284,7 @@ void gmpea_pool_destroy(gmpea_pool_t q) {
   if (q->d_states) pool_raw_free(q, q->d_states);
   for (int ph = 0; ph < kPhases; ++ph)
     if (q->d_work[ph]) pool_raw_free(q, q->d_work[ph]);
+  pool_arena_destroy(q);
   if (q->own_stream) (void)hipStreamDestroy(q->stream);
   delete q;
 }

@@ -242,9 +242,11 @@ __global__ __launch_bounds__(kBlock) void k_init(DevState st) {
 
 // ----------------------------------------------------------------------------
 // k_vary: reproduction + evaluation + ideal-point update.
-// Draws (reading R5/R6 of the design notes): MATE block (0, i, k, MATE|p) gives
-// the two neighbourhood positions and the per-offspring crossing draw; VAR block
-// (l >> 1, i, k, VAR|p) gives (wA, wB) for variables l, l + 1.
+// Draws (the paper fixes no RNG; this counter layout is the library's): Philox
+// counter (c0, i, k, tag << 24 | p << 16) for offspring i of population p in
+// generation k. The MATE block (c0 = 0) gives the two neighbourhood positions
+// and the per-offspring crossing draw; VAR block c0 = l >> 1 gives (wA, wB) for
+// variables l and l + 1.
 // A group of LPO consecutive lanes builds one offspring: lane g of the group
 // takes the float4 chunks g, g + LPO, ... of the row, so with LPO = 8 the group
 // reads each parent row and writes the offspring row as whole 128-byte lines.
@@ -414,12 +416,15 @@ __global__ __launch_bounds__(kBlock) void k_op1(DevState st) {
 // lexicographic minimum over the qualifiers with the first index on ties; every
 // decision uses generation-k parents, and replacements land after all reads of
 // the slot they overwrite.
-// A group of lps lanes (lps = t_p rounded up to a power of two, at most 64)
-// decides one slot: lane g scans entries g, g + lps, ... of the slot's reverse
-// list (coalesced reads) keeping its lexicographic minimum of (CV, g, index),
-// and a butterfly over the group yields the minimum over all candidates. That
+// A group of lps lanes decides one slot (lps = t_p / 4 rounded up to a power of
+// two, at most 64: about four reverse-list entries per lane). Lane g takes
+// entries g, g + lps, ... of the slot's list, four at a time with independent
+// loads (index, then candidate F/CV), and keeps its lexicographic minimum of
+// (CV, g, index). The group minimum follows from DPP moves inside 16-lane rows
+// (quad swaps, half-row mirror, row mirror) and lane permutes beyond. That
 // minimum qualifies exactly when some candidate qualifies, since qualifying
-// means being below the parent in the same order.
+// means being below the parent in the same order; a minimum over a total order
+// does not depend on how the candidates were split among lanes.
 // ----------------------------------------------------------------------------
 struct SelKey {
   float c, g;
@@ -428,6 +433,34 @@ struct SelKey {
 
 __device__ __forceinline__ bool sel_less(const SelKey &a, const SelKey &b) {
   return a.c < b.c || (a.c == b.c && (a.g < b.g || (a.g == b.g && a.i < b.i)));
+}
+
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int v) {
+  return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, false);
+}
+
+template <int CTRL>
+__device__ __forceinline__ void sel_step_dpp(SelKey &best) {
+  const SelKey o{__int_as_float(dpp_i<CTRL>(__float_as_int(best.c))),
+                 __int_as_float(dpp_i<CTRL>(__float_as_int(best.g))), dpp_i<CTRL>(best.i)};
+  if (sel_less(o, best)) best = o;
+}
+
+__device__ __forceinline__ void sel_step_xor(SelKey &best, int o) {
+  const SelKey k{__shfl_xor(best.c, o), __shfl_xor(best.g, o), __shfl_xor(best.i, o)};
+  if (sel_less(k, best)) best = k;
+}
+
+// Minimum over each aligned group of lps lanes, left in every lane of the group.
+// Every lane of the wave must be active.
+__device__ __forceinline__ void sel_group_min(SelKey &best, int lps) {
+  if (lps > 1) sel_step_dpp<0xB1>(best);   // quad_perm [1, 0, 3, 2]
+  if (lps > 2) sel_step_dpp<0x4E>(best);   // quad_perm [2, 3, 0, 1]
+  if (lps > 4) sel_step_dpp<0x141>(best);  // row_half_mirror: quad q <-> the other quad of its 8
+  if (lps > 8) sel_step_dpp<0x140>(best);  // row_mirror: half-row <-> the other half of its 16
+  if (lps > 16) sel_step_xor(best, 16);
+  if (lps > 32) sel_step_xor(best, 32);
 }
 
 template <int M>
@@ -443,34 +476,46 @@ __device__ __forceinline__ void select_body(const DevState &st, int L) {
   __syncthreads();
   const bool live = j < st.n;
   SelKey best{__builtin_huge_valf(), __builtin_huge_valf(), 0x7FFFFFFF};
-  float4 w = make_float4(0, 0, 0, 0);
+  float4 w = make_float4(0, 0, 0, 0), par = make_float4(0, 0, 0, 0);
   float z[M];
   load_z<M>(st.zkey, z);
   if (live) {
     w = st.W[j];
-    const int q1 = st.roff[p][j + 1];
+    par = st.FC[p][j];
+    const int q0 = st.roff[p][j], q1 = st.roff[p][j + 1];
     const int32_t *rl = st.ridx[p];
     const float4 *cand = st.FCN[p];
-    for (int q = st.roff[p][j] + g; q < q1; q += lps) {
-      const int i = rl[q];
-      const float4 c = cand[i];
-      const SelKey k{(p == 0) ? nan_inf(c.w) : 0.0f, aggregate<M>(c, w, z, st.agg, st.theta), i};
-      if (sel_less(k, best)) best = k;
+    for (int q = q0 + g; q < q1; q += 4 * lps) {
+      int ii[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int qq = q + u * lps;
+        ii[u] = qq < q1 ? rl[qq] : -1;
+      }
+      float4 cc[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) cc[u] = ii[u] >= 0 ? cand[ii[u]] : make_float4(0, 0, 0, 0);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (ii[u] >= 0) {
+          const SelKey k{(p == 0) ? nan_inf(cc[u].w) : 0.0f,
+                         aggregate<M>(cc[u], w, z, st.agg, st.theta), ii[u]};
+          if (sel_less(k, best)) best = k;
+        }
+      }
     }
   }
-  for (int o = 1; o < lps; o <<= 1) {
-    SelKey other{__shfl_xor(best.c, o), __shfl_xor(best.g, o), __shfl_xor(best.i, o)};
-    if (sel_less(other, best)) best = other;
-  }
+  sel_group_min(best, lps);
   if (live && g == 0) {
-    const float4 par = st.FC[p][j];
     const float pc = (p == 0) ? nan_inf(par.w) : 0.0f;
     const float pg = aggregate<M>(par, w, z, st.agg, st.theta);
     const bool win = best.i != 0x7FFFFFFF && (best.c < pc || (best.c == pc && best.g < pg));
     if (st.win[p]) st.win[p][j] = win ? best.i : -1;
     if (win) {
-      st.FC[p][j] = st.FCN[p][best.i];
-      const int sp = p ^ ((st.src[best.i] >> p) & 1);
+      const float4 fnew = st.FCN[p][best.i];
+      const uint32_t sb = st.src[best.i];
+      st.FC[p][j] = fnew;
+      const int sp = p ^ static_cast<int>((sb >> p) & 1u);
       const int slot = atomicAdd(&s_cnt, 1);
       s_dst[slot] = j;
       s_srcrow[slot] =

@@ -10,13 +10,17 @@
 // exact integer lattice distance sum_a (k_i,a - k_j,a)^2 with ties broken by
 // ascending index, so subproblem i itself comes first.
 //
-// Instead of scanning all N points per subproblem, the search walks the lattice:
-// it enumerates the points whose leading m - 1 coordinates lie within a box of
-// half-width R around k_i, ranks them directly, and grows R until the t-th
-// nearest found lies within distance R. Every lattice point within distance R
-// lies inside the box, so no closer point (or equal-distance point with a
-// smaller index) can be missed. O(N (2R + 1)^(m-1) log) instead of O(N^2).
-// The radius grows geometrically: the result does not depend on the final R.
+// Rank order among lattice points equals the lexicographic order of their leading
+// m - 1 coordinates, so for any point i the candidates j = i + delta sort by
+// (distance of delta, lexicographic order of delta), the same for every i. The
+// search therefore walks one offset list, sorted once, holding every offset
+// within distance R, and keeps the first t offsets that land inside the lattice.
+// A point with fewer than t lattice neighbours in that list (only possible near
+// corners) falls back to a box walk: it enumerates the points whose leading
+// coordinates lie within a box of half-width R around k_i, ranks them directly,
+// and grows R until the t-th nearest found lies within distance R. Every lattice
+// point within distance R lies inside the box, so neither method can miss a
+// closer point (or an equal-distance point with a smaller index).
 #include <algorithm>
 #include <cmath>
 #include <thread>
@@ -68,6 +72,13 @@ void dd_lattice(int32_t m, int32_t H, std::vector<int32_t> &K) {
 // sum_{v < k_a} C(left - v + r - 1, r - 1) with r = m - a - 1 parts left, which
 // the hockey-stick identity turns into C(left + r, r) - C(left - k_a + r, r).
 static int64_t dd_rank(const int32_t *k, int32_t m, int32_t H) {
+  // m = 2: the rank is k_1. m = 3: C(H + 2, 2) - C(H - k_1 + 2, 2) + k_2, where
+  // C(x + 2, 2) = (x + 2)(x + 1) / 2 is exact (a product of consecutive integers).
+  if (m == 2) return k[0];
+  if (m == 3) {
+    const int64_t a = H, b = H - k[0];
+    return ((a + 2) * (a + 1) - (b + 2) * (b + 1)) / 2 + k[1];
+  }
   int64_t r = 0;
   int32_t left = H;
   for (int32_t a = 0; a < m - 1; ++a) {
@@ -85,50 +96,115 @@ struct Cand {
 };
 }  // namespace
 
-static void knn_rows(const std::vector<int32_t> &K, int32_t m, int32_t H, int32_t t, int64_t lo,
-                     int64_t hi, std::vector<int32_t> &B) {
+// Box walk for row i (exact; used where the offset list runs out).
+static void knn_row_box(const std::vector<int32_t> &K, int32_t m, int32_t H, int32_t t, int64_t i,
+                        int32_t *out) {
   std::vector<Cand> cand;
   std::vector<int32_t> kk(m), off(m > 1 ? m - 1 : 1);
   const int32_t lead = m - 1;
+  const int32_t *ki = &K[i * m];
+  int32_t R = 1;
+  while (R * R < t) ++R;
+  for (;;) {
+    cand.clear();
+    // enumerate offsets in [-R, R]^(m-1)
+    for (int32_t a = 0; a < lead; ++a) off[a] = -R;
+    for (;;) {
+      int32_t sum = 0;
+      bool ok = true;
+      for (int32_t a = 0; a < lead; ++a) {
+        kk[a] = ki[a] + off[a];
+        if (kk[a] < 0 || kk[a] > H) ok = false;
+        sum += kk[a];
+      }
+      kk[m - 1] = H - sum;
+      if (ok && kk[m - 1] >= 0 && kk[m - 1] <= H) {
+        int64_t dist = 0;
+        for (int32_t a = 0; a < m; ++a) {
+          int64_t df = int64_t(kk[a]) - ki[a];
+          dist += df * df;
+        }
+        cand.push_back({dist, static_cast<int32_t>(dd_rank(kk.data(), m, H))});
+      }
+      int32_t a = lead - 1;
+      while (a >= 0 && off[a] == R) off[a--] = -R;
+      if (a < 0) break;
+      ++off[a];
+    }
+    if (static_cast<int32_t>(cand.size()) >= t) {
+      std::partial_sort(cand.begin(), cand.begin() + t, cand.end());
+      if (cand[t - 1].dist <= int64_t(R) * R) {
+        for (int32_t r = 0; r < t; ++r) out[r] = cand[r].idx;
+        return;
+      }
+    }
+    R += std::max(1, R / 2);  // any R that passes the test above is exact
+  }
+}
+
+namespace {
+struct Offset {
+  int64_t dist;
+  int32_t d[kMaxM];  // leading m - 1 components
+};
+}  // namespace
+
+// Every offset of the leading coordinates within distance R (last coordinate
+// -sum of the others), sorted by (distance, lexicographic order).
+static std::vector<Offset> sorted_offsets(int32_t m, int32_t R) {
+  std::vector<Offset> out;
+  const int32_t lead = m - 1;
+  int32_t off[kMaxM] = {0, 0, 0};
+  for (int32_t a = 0; a < lead; ++a) off[a] = -R;
+  for (;;) {
+    int64_t dist = 0, sum = 0;
+    for (int32_t a = 0; a < lead; ++a) {
+      dist += int64_t(off[a]) * off[a];
+      sum += off[a];
+    }
+    dist += sum * sum;
+    if (dist <= int64_t(R) * R) {
+      Offset o{dist, {0, 0, 0}};
+      for (int32_t a = 0; a < lead; ++a) o.d[a] = off[a];
+      out.push_back(o);
+    }
+    int32_t a = lead - 1;
+    while (a >= 0 && off[a] == R) off[a--] = -R;
+    if (a < 0) break;
+    ++off[a];
+  }
+  std::sort(out.begin(), out.end(), [lead](const Offset &x, const Offset &y) {
+    if (x.dist != y.dist) return x.dist < y.dist;
+    for (int32_t a = 0; a < lead; ++a)
+      if (x.d[a] != y.d[a]) return x.d[a] < y.d[a];
+    return false;
+  });
+  return out;
+}
+
+static void knn_rows(const std::vector<int32_t> &K, int32_t m, int32_t H, int32_t t,
+                     const std::vector<Offset> &offs, int64_t lo, int64_t hi,
+                     std::vector<int32_t> &B) {
+  const int32_t lead = m - 1;
+  int32_t kk[kMaxM];
   for (int64_t i = lo; i < hi; ++i) {
     const int32_t *ki = &K[i * m];
-    int32_t R = 1;
-    while (R * R < t) ++R;
-    for (;;) {
-      cand.clear();
-      // enumerate offsets in [-R, R]^(m-1)
-      for (int32_t a = 0; a < lead; ++a) off[a] = -R;
-      for (;;) {
-        int32_t sum = 0;
-        bool ok = true;
-        for (int32_t a = 0; a < lead; ++a) {
-          kk[a] = ki[a] + off[a];
-          if (kk[a] < 0 || kk[a] > H) ok = false;
-          sum += kk[a];
-        }
-        kk[m - 1] = H - sum;
-        if (ok && kk[m - 1] >= 0 && kk[m - 1] <= H) {
-          int64_t dist = 0;
-          for (int32_t a = 0; a < m; ++a) {
-            int64_t df = int64_t(kk[a]) - ki[a];
-            dist += df * df;
-          }
-          cand.push_back({dist, static_cast<int32_t>(dd_rank(kk.data(), m, H))});
-        }
-        int32_t a = lead - 1;
-        while (a >= 0 && off[a] == R) off[a--] = -R;
-        if (a < 0) break;
-        ++off[a];
+    int32_t *out = &B[i * t];
+    int32_t cnt = 0;
+    for (const Offset &o : offs) {
+      int32_t sum = 0;
+      bool ok = true;
+      for (int32_t a = 0; a < lead; ++a) {
+        kk[a] = ki[a] + o.d[a];
+        ok = ok && kk[a] >= 0 && kk[a] <= H;
+        sum += kk[a];
       }
-      if (static_cast<int32_t>(cand.size()) >= t) {
-        std::partial_sort(cand.begin(), cand.begin() + t, cand.end());
-        if (cand[t - 1].dist <= int64_t(R) * R) {
-          for (int32_t r = 0; r < t; ++r) B[i * t + r] = cand[r].idx;
-          break;
-        }
-      }
-      R += std::max(1, R / 2);  // any R that passes the test above is exact
+      kk[lead] = H - sum;
+      if (!ok || kk[lead] < 0 || kk[lead] > H) continue;
+      out[cnt++] = static_cast<int32_t>(dd_rank(kk, m, H));
+      if (cnt == t) break;
     }
+    if (cnt < t) knn_row_box(K, m, H, t, i, out);
   }
 }
 
@@ -136,12 +212,16 @@ void lattice_knn(const std::vector<int32_t> &K, int32_t m, int32_t H, int32_t t,
                  std::vector<int32_t> &B) {
   const int64_t n = static_cast<int64_t>(K.size()) / m;
   B.assign(static_cast<size_t>(n) * t, 0);
+  // radius whose offset list holds about 8 t entries (interior points need t)
+  int32_t R = 1;
+  while (R < H && static_cast<int64_t>(sorted_offsets(m, R).size()) < 8 * int64_t(t)) R += 1 + R / 4;
+  const std::vector<Offset> offs = sorted_offsets(m, R);
   unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-  if (n < 4096) nt = 1;
+  if (n * t < (1 << 18)) nt = 1;
   std::vector<std::thread> pool;
   for (unsigned w = 0; w < nt; ++w) {
     int64_t lo = n * w / nt, hi = n * (w + 1) / nt;
-    pool.emplace_back([&, lo, hi] { knn_rows(K, m, H, t, lo, hi, B); });
+    pool.emplace_back([&, lo, hi] { knn_rows(K, m, H, t, offs, lo, hi, B); });
   }
   for (auto &th : pool) th.join();
 }

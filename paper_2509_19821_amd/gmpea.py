@@ -32,7 +32,7 @@ EXPORTS = ["gmpea_init", "gmpea_step", "gmpea_run", "gmpea_front", "gmpea_get_in
            "gmpea_write", "gmpea_destroy", "gmpea_last_error", "gmpea_sync", "gmpea_profile",
            "gmpea_philox", "gmpea_copy", "gmpea_pool_create", "gmpea_pool_admit",
            "gmpea_pool_step", "gmpea_pool_tune", "gmpea_pool_handle", "gmpea_pool_release",
-           "gmpea_pool_query", "gmpea_pool_sync", "gmpea_pool_destroy"]
+           "gmpea_pool_query", "gmpea_pool_sync", "gmpea_pool_destroy", "gmpea_lattice"]
 PHASES = ("vary", "op1", "select")
 
 
@@ -144,6 +144,8 @@ def lib():
         L.gmpea_pool_sync.argtypes = [vp]
         L.gmpea_pool_destroy.argtypes = [vp]
         L.gmpea_pool_destroy.restype = None
+        L.gmpea_lattice.argtypes = [i32, i32, i32, i32, vp, vp, ctypes.POINTER(i32),
+                                    ctypes.POINTER(i32)]
         for name in EXPORTS:
             if name not in ("gmpea_destroy", "gmpea_last_error", "gmpea_pool_destroy"):
                 getattr(L, name).restype = ctypes.c_int
@@ -284,19 +286,17 @@ class Gmpea:
         return int(done.value)
 
     def front(self, what: int = FRONT_FEASIBLE_ND) -> dict:
+        # one call with room for the whole population (the front is a subset)
         cnt = ctypes.c_int32(0)
-        st = lib().gmpea_front(self._h, int(what), 0, None, None, None, None, ctypes.byref(cnt))
-        if st not in (0, -4):
-            _check(st)
-        n = int(cnt.value)
+        n = self.n
         x = np.empty((n, self.d), dtype=np.float32)
         f = np.empty((n, self.m), dtype=np.float32)
         cv = np.empty(n, dtype=np.float32)
         idx = np.empty(n, dtype=np.int32)
-        if n:
-            _check(lib().gmpea_front(self._h, int(what), n, x.ctypes.data, f.ctypes.data,
-                                     cv.ctypes.data, idx.ctypes.data, ctypes.byref(cnt)))
-        return {"x": x, "f": f, "cv": cv, "idx": idx}
+        _check(lib().gmpea_front(self._h, int(what), n, x.ctypes.data, f.ctypes.data,
+                                 cv.ctypes.data, idx.ctypes.data, ctypes.byref(cnt)))
+        k = int(cnt.value)
+        return {"x": x[:k].copy(), "f": f[:k].copy(), "cv": cv[:k].copy(), "idx": idx[:k].copy()}
 
     def profile(self, n_gen: int) -> dict:
         """Mean per-kernel durations (ms) over n_gen generations, HIP events on
@@ -357,6 +357,19 @@ def philox(ctr_dev_ptr: int, n: int, seed: int, out_dev_ptr: int, stream: int = 
     """Philox4x32-10 blocks on the device (pointers to n x 4 uint32 each)."""
     _check(lib().gmpea_philox(ctypes.c_void_p(ctr_dev_ptr), int(n), int(seed) & 0xFFFFFFFFFFFFFFFF,
                               ctypes.c_void_p(out_dev_ptr), ctypes.c_void_p(stream) if stream else None))
+
+
+def lattice(m: int, n_req: int, t: int):
+    """(H, K, B) of gmpea_lattice: Das-Dennis lattice rows (N x m) and the t
+    nearest rows of each (N x t), computed on the host."""
+    H, n = ctypes.c_int32(0), ctypes.c_int32(0)
+    _check(lib().gmpea_lattice(int(m), int(n_req), int(t), 0, None, None, ctypes.byref(H),
+                               ctypes.byref(n)))
+    K = np.empty((n.value, int(m)), dtype=np.int32)
+    B = np.empty((n.value, int(t)), dtype=np.int32)
+    _check(lib().gmpea_lattice(int(m), int(n_req), int(t), n.value, K.ctypes.data, B.ctypes.data,
+                               ctypes.byref(H), ctypes.byref(n)))
+    return int(H.value), K, B
 
 
 def _structs(problem: dict, config: dict, record: bool = False):

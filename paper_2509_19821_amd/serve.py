@@ -67,6 +67,7 @@ class Server:
         self.offspring = 0     # offspring evaluated and selected so far
         self.steps = 0
         self.keep_fronts = keep_fronts
+        self.host_s = {"admit": 0.0, "step": 0.0, "harvest": 0.0}  # wall time per activity
 
     def now(self) -> float:
         if self.t0 is None:
@@ -105,15 +106,27 @@ class Server:
                 del self.active[slot]
 
     def step(self):
-        """Admit what fits, advance every resident solve one generation, deliver
+        """Advance every resident solve one generation, admit what fits while the
+        GPU works (new solves join from the next generation on), then deliver
         the solves whose deadline has passed."""
-        self._admit()
-        if self.active:
+        c = self.clock
+        t0 = c()
+        stepped = bool(self.active)
+        if stepped:
             self.pool.step(1)
-            self.pool.sync()
             self.steps += 1
             self.offspring += sum(2 * n for (_, _, n) in self.active.values())
+        t1 = c()
+        self._admit()
+        t2 = c()
+        if stepped:
+            self.pool.sync()
+        t3 = c()
         self._harvest()
+        t4 = c()
+        self.host_s["step"] += (t1 - t0) + (t3 - t2)
+        self.host_s["admit"] += t2 - t1
+        self.host_s["harvest"] += t4 - t3
 
     def run(self, requests, idle_sleep: float = 2e-4):
         """Serve requests, each with its arrival time (seconds from start),
@@ -134,7 +147,7 @@ class Server:
         self.pool.close()
 
 
-def summarize(results, wall_s: float, offspring: int) -> dict:
+def summarize(results, wall_s: float, offspring: int, host_s: dict | None = None) -> dict:
     lat = np.array([r.latency for r in results])
     late = np.array([r.lateness for r in results])
     return {"requests": len(results),
@@ -144,4 +157,5 @@ def summarize(results, wall_s: float, offspring: int) -> dict:
             "p99_past_deadline_s": float(np.percentile(late, 99)) if len(late) else None,
             "mean_generations": float(np.mean([r.generations for r in results])) if results else 0,
             "offspring_per_s": offspring / wall_s if wall_s > 0 else None,
-            "wall_s": wall_s}
+            "wall_s": wall_s,
+            "host_s": dict(host_s) if host_s else None}

@@ -113,3 +113,32 @@ def test_refuses_older_framework_runtime_in_process(glib):
     have = tuple(int(x) for x in "".join(words[1:3]).strip("()").split(","))
     built = tuple(int(x) for x in "".join(words[3:5]).strip("()").split(","))
     assert words[0] == ("refused" if have < built else "loaded")
+
+
+@pytest.mark.parametrize("m,n_req,t", [(2, 100, 10), (2, 100, 40), (2, 700, 700), (2, 5, 1),
+                                       (3, 1000, 10), (3, 1000, 40), (3, 300, 64), (3, 3000, 64),
+                                       (3, 50, 55), (2, 20000, 40)])
+def test_host_lattice_matches_bruteforce(glib, m, n_req, t):
+    """The library's host lattice and neighbourhoods (the sorted-offset walk with
+    its box-walk fallback) equal the oracle's brute-force search (Alg. 1
+    initialisation: Das-Dennis rows, t nearest by squared lattice distance with
+    ties by index)."""
+    from oracle import core
+    H, K, B = glib.lattice(m, n_req, t)
+    assert H == core.dd_H(m, n_req)
+    Ko = core.dd_lattice(m, H)
+    assert np.array_equal(K, Ko)
+    assert np.array_equal(B, core.knn(Ko, t))
+    assert np.all(B[:, 0] == np.arange(K.shape[0]))
+
+
+def test_host_lattice_rejects_invalid(glib):
+    from paper_2509_19821_amd import gmpea as G
+    with pytest.raises(G.GmpeaError):
+        glib.lattice(4, 100, 10)
+    with pytest.raises(G.GmpeaError):
+        glib.lattice(2, 100, 101)
+    H, n = ctypes.c_int32(0), ctypes.c_int32(0)
+    K = np.empty((2, 2), dtype=np.int32)
+    st = G.lib().gmpea_lattice(2, 100, 3, 2, K.ctypes.data, None, ctypes.byref(H), ctypes.byref(n))
+    assert st == -4 and n.value == 100 and H.value == 99
