@@ -43,6 +43,14 @@ typedef enum {
   GMPEA_EUNSUPPORTED = -6 /* valid request outside what this build implements */
 } gmpea_status;
 
+/* Reproduction operators (the experimental settings name both). GMPEA_OP_DE
+ * reads the DE operator (CR = 1, F = 0.5) in its neighbourhood form: for
+ * subproblem i of population p, v = x_i + F (x_a - x_b) with x_i the current
+ * solution and (a, b) the two mating picks from B_p(i), every variable taken
+ * from the mutant (CR = 1), clipped to the box, then polynomial mutation as
+ * after SBX. */
+enum { GMPEA_OP_SBX = 0, GMPEA_OP_DE = 1 };
+
 /* Problem families (objective functions of the synthetic CMOPs). */
 enum {
   GMPEA_FAMILY_CURVE = 0, /* m = 2: f1 = x1, g = 1 + 9 mean(x2..xd), f2 = g (1 - sqrt(f1/g)) */
@@ -132,6 +140,9 @@ typedef struct {
   uint64_t seed;   /* key of the counter RNG: every random draw is a function of
                       (seed, generation, population, subproblem, variable) */
   int32_t record;  /* nonzero: keep MATE and WIN of the last generation */
+  int32_t op;      /* reproduction: GMPEA_OP_SBX (SBX then PM, the C-DTLZ / DC-DTLZ
+                      setting) or GMPEA_OP_DE (DE then PM, the LIR-CMOP setting) */
+  double de_f;     /* DE scale factor F; 0 means 0.5 (the crossover rate is 1) */
 } gmpea_config;
 
 /* Device allocator hook. alloc returns device memory (or NULL), free releases

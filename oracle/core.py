@@ -48,7 +48,7 @@ class Cfg(ctypes.Structure):
                 ("eta_c", ctypes.c_double), ("eta_m", ctypes.c_double),
                 ("tpm", ctypes.c_uint64), ("tpc", ctypes.c_uint64),
                 ("key", ctypes.c_uint32 * 2), ("n_eq", ctypes.c_int32), ("eq_tol", ctypes.c_double),
-                ("f32", ctypes.c_int32)]
+                ("f32", ctypes.c_int32), ("op", ctypes.c_int32), ("de_f", ctypes.c_double)]
 
 
 def lib():
@@ -78,6 +78,8 @@ def lib():
                                      ctypes.c_uint64, ctypes.c_double]
             L.orc_pm_dim.restype = ctypes.c_double
             L.orc_mate.argtypes = [u32, u32, i32, vp, vp]
+            L.orc_de_dim.argtypes = [ctypes.c_double] * 6 + [u32, ctypes.c_uint64, ctypes.c_double]
+            L.orc_de_dim.restype = ctypes.c_double
             L.orc_select.argtypes = [vp] * 18
             L.orc_reproduce.argtypes = [vp, vp, u32, vp, vp, vp, vp, vp, vp, vp]
             L.orc_ideal.argtypes = [i64, i32, vp, vp]
@@ -190,6 +192,13 @@ def pm_dim(y: float, lo: float, hi: float, wB: int, tpm: int, eta_m: float) -> f
                                   int(tpm), float(eta_m)))
 
 
+def de_dim(xi: float, a: float, b: float, F: float, lo: float, hi: float, wB: int, tpm: int,
+           eta_m: float) -> float:
+    """One variable of the DE operator (R26): x_i + F (a - b), clipped, then PM."""
+    return float(lib().orc_de_dim(float(xi), float(a), float(b), float(F), float(lo), float(hi),
+                                  int(wB) & 0xFFFFFFFF, int(tpm), float(eta_m)))
+
+
 def mate(w0: int, w1: int, t: int):
     r1 = np.zeros(1, dtype=np.int32)
     r2 = np.zeros(1, dtype=np.int32)
@@ -228,7 +237,8 @@ def derive(prob: dict, cfg: dict) -> dict:
             "tpm": int(np.floor(pm * 4294967296.0)), "tpc": int(np.floor(float(cfg["pc"]) * 4294967296.0)),
             "key": (seed & 0xFFFFFFFF, seed >> 32), "agg": int(cfg["agg"]),
             "theta": float(cfg["theta"]), "eta_c": float(cfg["eta_c"]),
-            "eta_m": float(cfg["eta_m"])}
+            "eta_m": float(cfg["eta_m"]), "op": int(cfg.get("op", 0)),
+            "de_f": float(cfg.get("de_f", 0.0)) or 0.5}
 
 
 class Oracle:
@@ -249,7 +259,7 @@ class Oracle:
                         (ctypes.c_void_p * 2)(_p(self.B[0]), _p(self.B[1])), _p(self.W),
                         dv["agg"], dv["theta"], dv["eta_c"], dv["eta_m"], dv["tpm"], dv["tpc"],
                         (ctypes.c_uint32 * 2)(*dv["key"]), int(prob["n_eq"]),
-                        float(prob["eq_tol"]), 0)
+                        float(prob["eq_tol"]), 0, dv["op"], dv["de_f"])
         self.gen = 0
         if init:
             X = [self.init_x(0), self.init_x(1)]

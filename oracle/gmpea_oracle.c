@@ -320,6 +320,18 @@ double orc_pm_dim(double y, double lo, double hi, uint32_t wB, uint64_t tpm, dou
   return orc_clip(y + dq * span, lo, hi);
 }
 
+/* R26: the DE operator of the LIR-CMOP experiments (CR = 1, F = 0.5) in its
+ * neighbourhood form: the base is the subproblem's own current solution x_i, the
+ * difference is taken between the two mating picks, and CR = 1 makes every
+ * variable take the mutant: v = x_i + F (x_a - x_b), clipped to the box, then
+ * the polynomial mutation above with the same per-variable draw wB as after
+ * SBX. */
+double orc_de_dim(double xi, double a, double b, double F, double lo, double hi, uint32_t wB,
+                  uint64_t tpm, double eta_m) {
+  double v = orc_clip(xi + F * (a - b), lo, hi);
+  return orc_pm_dim(v, lo, hi, wB, tpm, eta_m);
+}
+
 /* R6: mating picks two distinct positions of B(i) from the MATE block:
  * r1 = hi32(w0 t), r2' = hi32(w1 (t-1)), r2 = r2' + [r2' >= r1]; t = 1 gives r2 = r1. */
 void orc_mate(uint32_t w0, uint32_t w1, int32_t t, int32_t *r1, int32_t *r2) {
@@ -349,7 +361,12 @@ typedef struct {
   int32_t n_eq;  /* the equality x1 + x2 = 1 is active (robustness bookkeeping only) */
   double eq_tol;
   int32_t f32;   /* selection only: take the decisions in FP32 on FP32 inputs (below) */
+  int32_t op;    /* reproduction operator: ORC_OP_SBX (SBX then PM) or ORC_OP_DE (DE then PM) */
+  double de_f;   /* DE scale factor F */
 } orc_cfg;
+
+#define ORC_OP_SBX 0
+#define ORC_OP_DE 1
 
 /* Robustness threshold for parity (R24). */
 #define ORC_REL 1e-4
@@ -656,8 +673,8 @@ void orc_select(const orc_cfg *C, const double *X0, const double *X1, const doub
 }
 
 /* Offspring of one generation (Alg. 1 reproduction + evaluation): each
- * population mates inside its own neighbourhood (R6), SBX then PM (R7, R8),
- * then objectives and constraints. Outputs population-major; mate may be NULL. */
+ * population mates inside its own neighbourhood (R6), SBX then PM (R7, R8) or
+ * DE then PM (R26), then objectives and constraints. Outputs population-major; mate may be NULL. */
 void orc_reproduce(const orc_problem *P, const orc_cfg *C, uint32_t k, const double *X0,
                    const double *X1, double *Xo, double *Fo, double *CVo, double *CMo,
                    int32_t *mate) {
@@ -679,11 +696,16 @@ void orc_reproduce(const orc_problem *P, const orc_cfg *C, uint32_t k, const dou
       }
       int cross = (uint64_t)w[2] < C->tpc; /* SBX probability pc per individual */
       const double *a = X[p] + (size_t)pa * d, *b = X[p] + (size_t)pb * d;
+      const double *xi = X[p] + (size_t)i * d;
       double *c = Xo + (size_t)p * nd + (size_t)i * d;
       for (int32_t l = 0; l < d; ++l) {
         if ((l & 1) == 0)
           orc_draw((uint32_t)(l >> 1), (uint32_t)i, k, ORC_TAG_VAR, (uint32_t)p, C->key, v);
         uint32_t wA = v[2 * (l & 1)], wB = v[2 * (l & 1) + 1];
+        if (C->op == ORC_OP_DE) {
+          c[l] = orc_de_dim(xi[l], a[l], b[l], C->de_f, P->lb[l], P->ub[l], wB, C->tpm, C->eta_m);
+          continue;
+        }
         double ch = a[l], sib;
         if (cross) orc_sbx_dim(a[l], b[l], wA, C->eta_c, &ch, &sib);
         ch = orc_clip(ch, P->lb[l], P->ub[l]);

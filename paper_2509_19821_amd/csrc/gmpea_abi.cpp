@@ -43,13 +43,11 @@ struct gmpea_s {
   bool record = false;
   std::vector<std::pair<void *, size_t>> allocs;
   size_t bytes = 0;
-  std::vector<float> w_raw;      // N x m reference vectors (host copy)
   // gmpea_front scratch (flags, row list, gathered rows), allocated on first use
   uint8_t *f_keep = nullptr;
   int32_t *f_idx = nullptr;
   float *f_x = nullptr;
   float4 *f_fc = nullptr;
-  std::vector<int32_t> b_host[2];
   // graph replay of `gchunk` generations
   hipGraphExec_t gexec = nullptr;
   int32_t gchunk = 0;
@@ -172,6 +170,10 @@ gmpea_status validate(const gmpea_problem *P, const gmpea_config *C) {
     return fail(GMPEA_EINVAL, "gmpea_init: probabilities must lie in [0, 1]");
   if (C->eta_c < 0 || C->eta_m < 0 || C->theta < 0)
     return fail(GMPEA_EINVAL, "gmpea_init: negative distribution index or penalty");
+  if (C->op != GMPEA_OP_SBX && C->op != GMPEA_OP_DE)
+    return fail(GMPEA_EINVAL, "gmpea_init: unknown reproduction operator");
+  if (!(C->de_f >= 0.0) || !std::isfinite(C->de_f))
+    return fail(GMPEA_EINVAL, "gmpea_init: de_f must be finite and >= 0");
   return GMPEA_OK;
 }
 
@@ -283,6 +285,8 @@ gmpea_status gmpea_init(const gmpea_problem *P, const gmpea_config *C, const gmp
   if (t1 < 1 || t2 < 1 || t1 > N || t2 > N)
     return fail(GMPEA_EINVAL, "gmpea_init: need 1 <= t1, t2 <= N (population " + std::to_string(N) +
                                   ", t1 " + std::to_string(t1) + ", t2 " + std::to_string(t2) + ")");
+  if (static_cast<int64_t>(N) * std::max(t1, t2) >= (int64_t(1) << 31))
+    return fail(GMPEA_EUNSUPPORTED, "gmpea_init: N * t above the 32-bit index range");
   s = check_runtime("gmpea_init");
   if (s != GMPEA_OK) return s;
 
@@ -305,34 +309,11 @@ gmpea_status gmpea_init(const gmpea_problem *P, const gmpea_config *C, const gmp
   h->H = H;
   h->record = C->record != 0;
 
-  // ---- host-side structures: W, B1, B2, reverse lists ----
-  std::vector<int32_t> K;
-  dd_lattice(m, H, K);
-  h->w_raw.resize(static_cast<size_t>(N) * m);
-  std::vector<float4> wdev(static_cast<size_t>(N));
-  for (int32_t i = 0; i < N; ++i) {
-    double w[3] = {0, 0, 0}, nrm = 0;
-    for (int32_t a = 0; a < m; ++a) {
-      w[a] = static_cast<double>(K[static_cast<size_t>(i) * m + a]) / H;
-      h->w_raw[static_cast<size_t>(i) * m + a] = static_cast<float>(w[a]);
-      nrm += w[a] * w[a];
-    }
-    nrm = std::sqrt(nrm);
-    double v[3];
-    for (int32_t a = 0; a < 3; ++a) v[a] = (C->agg == GMPEA_AGG_PBI) ? w[a] / nrm : w[a];
-    wdev[i] = make_float4(static_cast<float>(v[0]), static_cast<float>(v[1]),
-                          static_cast<float>(v[2]), 0.0f);
-  }
-  std::vector<int32_t> roff[2], ridx[2];
+  // ---- neighbourhood offsets (host, a few KB); the tables are built on the device ----
   const int32_t ts[2] = {t1, t2};
-  for (int p = 0; p < 2; ++p) {
-    if (p == 1 && t2 == t1) {
-      h->b_host[1] = h->b_host[0];
-    } else {
-      lattice_knn(K, m, H, ts[p], h->b_host[p]);
-    }
-    reverse_lists(h->b_host[p], N, ts[p], roff[p], ridx[p]);
-  }
+  std::vector<int32_t> offs;
+  neighbour_offsets(m, H, std::max(t1, t2), offs);
+  const int32_t noffs = static_cast<int32_t>(offs.size() / 2);
 
   // ---- device state ----
   DevState &st = h->st;
@@ -361,6 +342,8 @@ gmpea_status gmpea_init(const gmpea_problem *P, const gmpea_config *C, const gmp
   st.tpm = static_cast<uint64_t>(std::floor(pm * 4294967296.0));
   st.tpc = static_cast<uint64_t>(std::floor(pc * 4294967296.0));
   st.inv_tpm = st.tpm > 0 ? static_cast<float>(1.0 / static_cast<double>(st.tpm)) : 0.0f;
+  st.op = C->op;
+  st.de_f = static_cast<float>(C->de_f > 0 ? C->de_f : 0.5);
   st.key0 = static_cast<uint32_t>(C->seed & 0xFFFFFFFFull);
   st.key1 = static_cast<uint32_t>(C->seed >> 32);
   DevProblem &dp = st.prob;
@@ -381,6 +364,8 @@ gmpea_status gmpea_init(const gmpea_problem *P, const gmpea_config *C, const gmp
 
   const size_t rows = static_cast<size_t>(st.nblk) * kBlock;
   float *lb = nullptr, *ub = nullptr, *inv_span = nullptr;
+  int2 *d_offs = nullptr;
+  uint32_t *d_flag = nullptr;
   auto layout = [&](Carve &c) {
     lb = c.take<float>(st.stride);
     ub = c.take<float>(st.stride);
@@ -402,6 +387,8 @@ gmpea_status gmpea_init(const gmpea_problem *P, const gmpea_config *C, const gmp
     st.zkey = c.take<uint32_t>(4);
     st.gen = c.take<uint32_t>(4);
     st.repl = c.take<unsigned long long>(2);
+    d_offs = c.take<int2>(noffs);
+    d_flag = c.take<uint32_t>(4);
   };
   Carve sizing;
   layout(sizing);
@@ -435,16 +422,15 @@ gmpea_status gmpea_init(const gmpea_problem *P, const gmpea_config *C, const gmp
   cp(lb, lbf.data(), st.stride * sizeof(float));
   cp(ub, ubf.data(), st.stride * sizeof(float));
   cp(inv_span, isf.data(), st.stride * sizeof(float));
-  cp(st.W, wdev.data(), N * sizeof(float4));
+  cp(d_offs, offs.data(), offs.size() * sizeof(int32_t));
+  zero(d_flag, 0, 4 * sizeof(uint32_t));
   for (int p = 0; p < 2; ++p) {
-    cp(const_cast<int32_t *>(st.B[p]), h->b_host[p].data(), h->b_host[p].size() * sizeof(int32_t));
-    cp(const_cast<int32_t *>(st.roff[p]), roff[p].data(), roff[p].size() * sizeof(int32_t));
-    cp(const_cast<int32_t *>(st.ridx[p]), ridx[p].data(), ridx[p].size() * sizeof(int32_t));
     zero(st.X[p], 0, rows * st.stride * sizeof(float));
     zero(st.XO[p], 0, rows * st.stride * sizeof(float));
     zero(st.FC[p], 0, rows * sizeof(float4));
     zero(st.FCO[p], 0, rows * sizeof(float4));
     zero(st.FCN[p], 0, rows * sizeof(float4));
+    zero(const_cast<int32_t *>(st.roff[p]), 0, (static_cast<size_t>(N) + 1) * sizeof(int32_t));
     if (h->record) {
       zero(st.mate[p], 0xFF, rows * 2 * sizeof(int32_t));
       zero(st.win[p], 0xFF, rows * sizeof(int32_t));
@@ -454,6 +440,33 @@ gmpea_status gmpea_init(const gmpea_problem *P, const gmpea_config *C, const gmp
   zero(st.zkey, 0xFF, 4 * sizeof(uint32_t));
   zero(st.gen, 0, 4 * sizeof(uint32_t));
   zero(st.repl, 0, 2 * sizeof(unsigned long long));
+  // reference vectors and neighbourhoods on the device
+  if (e == hipSuccess)
+    e = launch_tables(m, N, H, d_offs, noffs, t1, t2, C->agg, st.W, const_cast<int32_t *>(st.B[0]),
+                      const_cast<int32_t *>(st.B[1]), d_flag, h->stream);
+  uint32_t incomplete = 0;
+  if (e == hipSuccess) e = hipMemcpyAsync(&incomplete, d_flag, sizeof(uint32_t), hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e == hipSuccess && incomplete) {
+    // some row (near a lattice corner) needs neighbours beyond the offset list:
+    // the host's exact search provides both tables
+    std::vector<int32_t> K, Bh;
+    dd_lattice(m, H, K);
+    for (int p = 0; p < 2 && e == hipSuccess; ++p) {
+      lattice_knn(K, m, H, ts[p], Bh);
+      e = hipMemcpyAsync(const_cast<int32_t *>(st.B[p]), Bh.data(), Bh.size() * sizeof(int32_t),
+                         hipMemcpyHostToDevice, h->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    }
+  }
+  // reverse lists (the offspring buffer serves as the zeroed cursor array)
+  for (int p = 0; p < 2; ++p) {
+    zero(st.FCO[0], 0, static_cast<size_t>(N) * sizeof(int32_t));
+    if (e == hipSuccess)
+      e = launch_reverse(N, ts[p], st.B[p], const_cast<int32_t *>(st.roff[p]), reinterpret_cast<int32_t *>(st.FCO[0]),
+                         const_cast<int32_t *>(st.ridx[p]), h->stream);
+  }
+  zero(st.FCO[0], 0, rows * sizeof(float4));
   if (e == hipSuccess) e = launch_init(st, h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) {
@@ -662,13 +675,15 @@ gmpea_status gmpea_read(gmpea_t h, int32_t buffer, int32_t pop, void *host, int6
     }
     case GMPEA_BUF_W: {
       if (!need(n * m)) return fail(GMPEA_EINVAL, "gmpea_read: count must be N * m");
-      std::copy(h->w_raw.begin(), h->w_raw.end(), static_cast<float *>(host));
+      std::vector<int32_t> K;
+      dd_lattice(static_cast<int32_t>(m), h->H, K);
+      for (size_t q = 0; q < K.size(); ++q)
+        static_cast<float *>(host)[q] = static_cast<float>(static_cast<double>(K[q]) / h->H);
       return GMPEA_OK;
     }
     case GMPEA_BUF_B: {
       if (!need(n * st.t[pop])) return fail(GMPEA_EINVAL, "gmpea_read: count must be N * t");
-      std::copy(h->b_host[pop].begin(), h->b_host[pop].end(), static_cast<int32_t *>(host));
-      return GMPEA_OK;
+      return d2h(h, static_cast<int32_t *>(host), st.B[pop], n * st.t[pop], "gmpea_read");
     }
     case GMPEA_BUF_MATE:
       if (!h->record) return fail(GMPEA_EINVAL, "gmpea_read: MATE needs config.record");

@@ -60,6 +60,8 @@ struct DevState {
   float inv_tpm;             // 1 / tpm
   float sbx_e;               // 1 / (eta_c + 1)
   float pm_p, pm_e;          // eta_m + 1, 1 / (eta_m + 1)
+  int32_t op;                // 0: SBX then PM, 1: DE then PM
+  float de_f;                // DE scale factor
   DevProblem prob;
 };
 
@@ -116,5 +118,20 @@ void lattice_knn(const std::vector<int32_t> &K, int32_t m, int32_t H, int32_t t,
                  std::vector<int32_t> &B);
 void reverse_lists(const std::vector<int32_t> &B, int32_t n, int32_t t, std::vector<int32_t> &off,
                    std::vector<int32_t> &idx);
+// Leading-coordinate offsets (pairs; second component 0 for m = 2) sorted by
+// (squared lattice distance, lexicographic order), enough for t neighbours of
+// interior points; the device builds neighbourhoods by walking this list.
+void neighbour_offsets(int32_t m, int32_t H, int32_t t, std::vector<int32_t> &d);
+
+// Device construction of the initialisation tables (gmpea_kernels.hip).
+// W and both neighbourhoods from the offset list; *incomplete becomes nonzero
+// when some row found fewer than max(t1, t2) lattice neighbours in the list.
+hipError_t launch_tables(int32_t m, int32_t n, int32_t H, const int2 *offs, int32_t noffs,
+                         int32_t t1, int32_t t2, int32_t agg, float4 *W, int32_t *B1, int32_t *B2,
+                         uint32_t *incomplete, hipStream_t s);
+// Reverse lists of B (n x t) in CSR form, each list ascending. off (n + 1) and
+// cursor (n) must be zero on entry.
+hipError_t launch_reverse(int32_t n, int32_t t, const int32_t *B, int32_t *off, int32_t *cursor,
+                          int32_t *idx, hipStream_t s);
 
 }  // namespace gmpea

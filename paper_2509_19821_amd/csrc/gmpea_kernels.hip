@@ -73,19 +73,12 @@ __device__ __forceinline__ float powpos(float x, float e) {
 }
 
 // ----------------------------------------------------------------------------
-// Variation of one variable: SBX (one child kept; per-variable crossing bit,
-// sign bit, 24-bit uniform) then clip, then bounded polynomial mutation.
+// Variation of one variable. Bounded polynomial mutation of c in [lo, hi] when
+// wB < tpm, then SBX (one child kept; per-variable crossing bit, sign bit,
+// 24-bit uniform) or DE (x + F (a - b), every variable) in front of it.
 // ----------------------------------------------------------------------------
-__device__ __forceinline__ float vary1(float a, float b, uint32_t wA, uint32_t wB, float lo, float hi,
-                                       float inv_span, bool cross, const DevState &st) {
-  float c = a;
-  if (cross && (wA & 1u)) {
-    const float u = u24(wA);
-    float beta = (u <= 0.5f) ? powpos(2.0f * u, st.sbx_e) : powpos(2.0f * (1.0f - u), -st.sbx_e);
-    if (wA & 2u) beta = -beta;
-    c = 0.5f * ((a + b) + beta * (a - b));
-  }
-  c = fminf(fmaxf(c, lo), hi);
+__device__ __forceinline__ float pm1(float c, uint32_t wB, float lo, float hi, float inv_span,
+                                     const DevState &st) {
   const uint64_t w = wB;
   if (w < st.tpm) {
     // u = wB / tpm. Every coefficient of the mutation step (2u, 1 - 2u, 2(1 - u),
@@ -110,6 +103,25 @@ __device__ __forceinline__ float vary1(float a, float b, uint32_t wA, uint32_t w
     c = fminf(fmaxf(c + dq * span, lo), hi);
   }
   return c;
+}
+
+__device__ __forceinline__ float vary1(float a, float b, uint32_t wA, uint32_t wB, float lo, float hi,
+                                       float inv_span, bool cross, const DevState &st) {
+  float c = a;
+  if (cross && (wA & 1u)) {
+    const float u = u24(wA);
+    float beta = (u <= 0.5f) ? powpos(2.0f * u, st.sbx_e) : powpos(2.0f * (1.0f - u), -st.sbx_e);
+    if (wA & 2u) beta = -beta;
+    c = 0.5f * ((a + b) + beta * (a - b));
+  }
+  c = fminf(fmaxf(c, lo), hi);
+  return pm1(c, wB, lo, hi, inv_span, st);
+}
+
+__device__ __forceinline__ float vary1_de(float x, float a, float b, uint32_t wB, float lo, float hi,
+                                          float inv_span, const DevState &st) {
+  const float c = fminf(fmaxf(x + st.de_f * (a - b), lo), hi);
+  return pm1(c, wB, lo, hi, inv_span, st);
 }
 
 // Running sums of the evaluation, filled variable by variable.
@@ -241,7 +253,136 @@ __global__ __launch_bounds__(kBlock) void k_init(DevState st) {
 }
 
 // ----------------------------------------------------------------------------
-// k_vary: reproduction + evaluation + ideal-point update.
+// Initialisation tables (Alg. 1 inputs): reference vectors and neighbourhoods.
+// Row i of the Das-Dennis lattice is unranked from its index (lexicographic
+// order of the leading coordinates); its neighbours are the first valid points
+// k_i + delta along one offset list sorted by (distance, lexicographic order of
+// delta), which is the (distance, index) order for every row because the rank
+// is increasing in the lexicographic order. The first t1 and the first t2 of
+// them are the two neighbourhoods.
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ int64_t dd_base3(int64_t H, int64_t a) {
+  // rank of the first row with k_1 = a when m = 3: C(H + 2, 2) - C(H - a + 2, 2)
+  return ((H + 2) * (H + 1) - (H - a + 2) * (H - a + 1)) / 2;
+}
+
+template <int M>
+__global__ __launch_bounds__(kBlock) void k_tables(int32_t n, int32_t H, const int2 *__restrict__ offs,
+                                                  int32_t noffs, int32_t t1, int32_t t2, int32_t agg,
+                                                  float4 *__restrict__ W, int32_t *__restrict__ B1,
+                                                  int32_t *__restrict__ B2,
+                                                  uint32_t *__restrict__ incomplete) {
+  const int32_t i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  int32_t k[3] = {0, 0, 0};
+  if (M == 2) {
+    k[0] = i;
+    k[1] = H - i;
+  } else {
+    int32_t lo = 0, hi = H;  // largest a with dd_base3(H, a) <= i
+    while (lo < hi) {
+      const int32_t mid = (lo + hi + 1) >> 1;
+      if (dd_base3(H, mid) <= i) lo = mid;
+      else hi = mid - 1;
+    }
+    k[0] = lo;
+    k[1] = i - static_cast<int32_t>(dd_base3(H, lo));
+    k[2] = H - k[0] - k[1];
+  }
+  // weights in FP64, rounded once: the unit direction for PBI, the raw weight otherwise
+  double w[3] = {0.0, 0.0, 0.0}, nrm = 0.0;
+#pragma unroll
+  for (int a = 0; a < M; ++a) {
+    w[a] = static_cast<double>(k[a]) / static_cast<double>(H);
+    nrm += w[a] * w[a];
+  }
+  nrm = sqrt(nrm);
+  float v[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) v[a] = static_cast<float>(agg == 0 ? w[a] / nrm : w[a]);
+  W[i] = make_float4(v[0], v[1], v[2], 0.0f);
+  const int32_t tmax = max(t1, t2);
+  int32_t c = 0;
+  for (int32_t q = 0; q < noffs && c < tmax; ++q) {
+    const int2 dl = offs[q];
+    const int32_t a0 = k[0] + dl.x;
+    int32_t rank;
+    if (M == 2) {
+      if (a0 < 0 || a0 > H) continue;
+      rank = a0;
+    } else {
+      const int32_t a1 = k[1] + dl.y, a2 = H - a0 - a1;
+      if (a0 < 0 || a1 < 0 || a2 < 0 || a0 > H || a1 > H || a2 > H) continue;
+      rank = static_cast<int32_t>(dd_base3(H, a0)) + a1;
+    }
+    if (c < t1) B1[static_cast<size_t>(i) * t1 + c] = rank;
+    if (c < t2) B2[static_cast<size_t>(i) * t2 + c] = rank;
+    ++c;
+  }
+  if (c < tmax) atomicOr(incomplete, 1u);
+}
+
+// Reverse lists: counts (at off[j + 1]), an in-place scan, a scatter, and a
+// per-list insertion sort (lists hold about t entries) for a deterministic layout.
+__global__ __launch_bounds__(kBlock) void k_rev_count(int64_t nt, const int32_t *__restrict__ B,
+                                                     int32_t *__restrict__ off) {
+  const int64_t q = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (q < nt) atomicAdd(&off[B[q] + 1], 1);
+}
+
+constexpr int kScanThreads = 1024;
+
+__global__ __launch_bounds__(kScanThreads) void k_scan(int32_t *off, int32_t len) {
+  __shared__ int32_t part[kScanThreads];
+  const int tid = threadIdx.x;
+  const int per = (len + kScanThreads - 1) / kScanThreads;
+  const int lo = min(len, tid * per), hi = min(len, lo + per);
+  int32_t sum = 0;
+  for (int q = lo; q < hi; ++q) sum += off[q];
+  part[tid] = sum;
+  __syncthreads();
+  for (int o = 1; o < kScanThreads; o <<= 1) {
+    const int32_t v = tid >= o ? part[tid - o] : 0;
+    __syncthreads();
+    part[tid] += v;
+    __syncthreads();
+  }
+  int32_t run = tid > 0 ? part[tid - 1] : 0;
+  for (int q = lo; q < hi; ++q) {
+    run += off[q];
+    off[q] = run;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_rev_fill(int64_t nt, int32_t t, const int32_t *__restrict__ B,
+                                                    const int32_t *__restrict__ off,
+                                                    int32_t *__restrict__ cursor,
+                                                    int32_t *__restrict__ idx) {
+  const int64_t q = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (q >= nt) return;
+  const int32_t j = B[q];
+  const int32_t pos = atomicAdd(&cursor[j], 1);
+  idx[off[j] + pos] = static_cast<int32_t>(q / t);
+}
+
+__global__ __launch_bounds__(kBlock) void k_rev_sort(int32_t n, const int32_t *__restrict__ off,
+                                                    int32_t *__restrict__ idx) {
+  const int32_t j = blockIdx.x * kBlock + threadIdx.x;
+  if (j >= n) return;
+  const int32_t a = off[j], b = off[j + 1];
+  for (int32_t q = a + 1; q < b; ++q) {
+    const int32_t v = idx[q];
+    int32_t r = q - 1;
+    while (r >= a && idx[r] > v) {
+      idx[r + 1] = idx[r];
+      --r;
+    }
+    idx[r + 1] = v;
+  }
+}
+
+// ----------------------------------------------------------------------------
+// k_vary: reproduction (SBX or DE, then PM) + evaluation + ideal-point update.
 // Draws (the paper fixes no RNG; this counter layout is the library's): Philox
 // counter (c0, i, k, tag << 24 | p << 16) for offspring i of population p in
 // generation k. The MATE block (c0 = 0) gives the two neighbourhood positions
@@ -291,6 +432,8 @@ __device__ __forceinline__ void vary_body(const DevState &st, int L, int G) {
     const float4 *is4 = reinterpret_cast<const float4 *>(st.prob.inv_span);
     const uint32_t tagv = (kTagVar << 24) | tagp;
     const int nq = st.stride >> 2;
+    const bool de = st.op == 1;
+    const float4 *rx = reinterpret_cast<const float4 *>(st.X[p] + static_cast<size_t>(i) * st.stride);
     for (int q = g; q < nq; q += LPO) {
       const int l0 = q << 2;
       const float4 va = ra[q], vb = rb[q], lo = lb4[q], hi = ub4[q], is = is4[q];
@@ -298,20 +441,22 @@ __device__ __forceinline__ void vary_body(const DevState &st, int L, int G) {
       uint4 r1w = make_uint4(0, 0, 0, 0);
       if (l0 + 2 < st.d) r1w = philox10(make_uint4(2 * q + 1, i, k, tagv), st.key0, st.key1);
       float4 o = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-      o.x = vary1(va.x, vb.x, r0.x, r0.y, lo.x, hi.x, is.x, cross, st);
+      if (de) {
+        const float4 vx = rx[q];
+        o.x = vary1_de(vx.x, va.x, vb.x, r0.y, lo.x, hi.x, is.x, st);
+        if (l0 + 1 < st.d) o.y = vary1_de(vx.y, va.y, vb.y, r0.w, lo.y, hi.y, is.y, st);
+        if (l0 + 2 < st.d) o.z = vary1_de(vx.z, va.z, vb.z, r1w.y, lo.z, hi.z, is.z, st);
+        if (l0 + 3 < st.d) o.w = vary1_de(vx.w, va.w, vb.w, r1w.w, lo.w, hi.w, is.w, st);
+      } else {
+        o.x = vary1(va.x, vb.x, r0.x, r0.y, lo.x, hi.x, is.x, cross, st);
+        if (l0 + 1 < st.d) o.y = vary1(va.y, vb.y, r0.z, r0.w, lo.y, hi.y, is.y, cross, st);
+        if (l0 + 2 < st.d) o.z = vary1(va.z, vb.z, r1w.x, r1w.y, lo.z, hi.z, is.z, cross, st);
+        if (l0 + 3 < st.d) o.w = vary1(va.w, vb.w, r1w.z, r1w.w, lo.w, hi.w, is.w, cross, st);
+      }
       eval_add<M, FAM>(e, l0, o.x);
-      if (l0 + 1 < st.d) {
-        o.y = vary1(va.y, vb.y, r0.z, r0.w, lo.y, hi.y, is.y, cross, st);
-        eval_add<M, FAM>(e, l0 + 1, o.y);
-      }
-      if (l0 + 2 < st.d) {
-        o.z = vary1(va.z, vb.z, r1w.x, r1w.y, lo.z, hi.z, is.z, cross, st);
-        eval_add<M, FAM>(e, l0 + 2, o.z);
-      }
-      if (l0 + 3 < st.d) {
-        o.w = vary1(va.w, vb.w, r1w.z, r1w.w, lo.w, hi.w, is.w, cross, st);
-        eval_add<M, FAM>(e, l0 + 3, o.w);
-      }
+      if (l0 + 1 < st.d) eval_add<M, FAM>(e, l0 + 1, o.y);
+      if (l0 + 2 < st.d) eval_add<M, FAM>(e, l0 + 2, o.z);
+      if (l0 + 3 < st.d) eval_add<M, FAM>(e, l0 + 3, o.w);
       ro[q] = o;
     }
   }
@@ -679,6 +824,30 @@ __global__ __launch_bounds__(kBlock) void k_copy(const uint4 *__restrict__ src,
     else                                                                             \
       hipLaunchKernelGGL((KER<3>), dim3(GRID), dim3(kBlock), 0, (S), __VA_ARGS__);   \
   } while (0)
+
+hipError_t launch_tables(int32_t m, int32_t n, int32_t H, const int2 *offs, int32_t noffs,
+                         int32_t t1, int32_t t2, int32_t agg, float4 *W, int32_t *B1, int32_t *B2,
+                         uint32_t *incomplete, hipStream_t s) {
+  const int grid = (n + kBlock - 1) / kBlock;
+  if (m == 2)
+    hipLaunchKernelGGL(k_tables<2>, dim3(grid), dim3(kBlock), 0, s, n, H, offs, noffs, t1, t2, agg,
+                       W, B1, B2, incomplete);
+  else
+    hipLaunchKernelGGL(k_tables<3>, dim3(grid), dim3(kBlock), 0, s, n, H, offs, noffs, t1, t2, agg,
+                       W, B1, B2, incomplete);
+  return hipGetLastError();
+}
+
+hipError_t launch_reverse(int32_t n, int32_t t, const int32_t *B, int32_t *off, int32_t *cursor,
+                          int32_t *idx, hipStream_t s) {
+  const int64_t nt = static_cast<int64_t>(n) * t;
+  const unsigned grid = static_cast<unsigned>((nt + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL(k_rev_count, dim3(grid), dim3(kBlock), 0, s, nt, B, off);
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, s, off, n + 1);
+  hipLaunchKernelGGL(k_rev_fill, dim3(grid), dim3(kBlock), 0, s, nt, t, B, off, cursor, idx);
+  hipLaunchKernelGGL(k_rev_sort, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, n, off, idx);
+  return hipGetLastError();
+}
 
 hipError_t launch_init(const DevState &st, hipStream_t s) {
   GMPEA_DISPATCH_MF(k_init, 2 * st.nblk, st, s);

@@ -208,14 +208,29 @@ static void knn_rows(const std::vector<int32_t> &K, int32_t m, int32_t H, int32_
   }
 }
 
+// Offsets within the smallest radius (grown geometrically, at most H) whose list
+// holds about 8 t entries: interior points need t of them, points near a corner
+// of the lattice a few times more.
+static std::vector<Offset> offsets_for(int32_t m, int32_t H, int32_t t) {
+  int32_t R = 1;
+  while (R < H && static_cast<int64_t>(sorted_offsets(m, R).size()) < 8 * int64_t(t)) R += 1 + R / 4;
+  return sorted_offsets(m, R);
+}
+
+void neighbour_offsets(int32_t m, int32_t H, int32_t t, std::vector<int32_t> &d) {
+  const std::vector<Offset> offs = offsets_for(m, H, t);
+  d.assign(offs.size() * 2, 0);
+  for (size_t q = 0; q < offs.size(); ++q) {
+    d[2 * q] = offs[q].d[0];
+    d[2 * q + 1] = m > 2 ? offs[q].d[1] : 0;
+  }
+}
+
 void lattice_knn(const std::vector<int32_t> &K, int32_t m, int32_t H, int32_t t,
                  std::vector<int32_t> &B) {
   const int64_t n = static_cast<int64_t>(K.size()) / m;
   B.assign(static_cast<size_t>(n) * t, 0);
-  // radius whose offset list holds about 8 t entries (interior points need t)
-  int32_t R = 1;
-  while (R < H && static_cast<int64_t>(sorted_offsets(m, R).size()) < 8 * int64_t(t)) R += 1 + R / 4;
-  const std::vector<Offset> offs = sorted_offsets(m, R);
+  const std::vector<Offset> offs = offsets_for(m, H, t);
   unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
   if (n * t < (1 << 18)) nt = 1;
   std::vector<std::thread> pool;

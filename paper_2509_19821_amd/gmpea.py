@@ -22,6 +22,7 @@ _LIB_PATH = os.path.join(_PKG, "_build", "libgmpea.so")
 _BUILD_INFO = os.path.join(_PKG, "_build", "build_info.json")
 
 FAMILY_CURVE, FAMILY_SPHERE = 0, 1
+OP_SBX, OP_DE = 0, 1
 AGG_PBI, AGG_TCHE = 0, 1
 FRONT_FEASIBLE_ND, FRONT_POP1, FRONT_POP2 = 0, 1, 2
 BUF = {"X": 0, "F": 1, "CV": 2, "XOFF": 3, "FOFF": 4, "CVOFF": 5, "Z": 6, "GEN": 7, "W": 8,
@@ -54,7 +55,8 @@ class Config(ctypes.Structure):
     _fields_ = [("n_req", ctypes.c_int32), ("T", ctypes.c_int32), ("t1", ctypes.c_int32),
                 ("t2", ctypes.c_int32), ("agg", ctypes.c_int32), ("theta", ctypes.c_double),
                 ("eta_c", ctypes.c_double), ("eta_m", ctypes.c_double), ("pc", ctypes.c_double),
-                ("pm", ctypes.c_double), ("seed", ctypes.c_uint64), ("record", ctypes.c_int32)]
+                ("pm", ctypes.c_double), ("seed", ctypes.c_uint64), ("record", ctypes.c_int32),
+                ("op", ctypes.c_int32), ("de_f", ctypes.c_double)]
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -200,22 +202,7 @@ class Gmpea:
         L = lib()
         self._h = None
         self._owned = True
-        m, d = int(problem["m"]), int(problem["d"])
-        nr = int(np.asarray(problem["ring_radius"]).size)
-        self._keep = [_f64(problem["lb"], d), _f64(problem["ub"], d),
-                      _f64(problem["ring_center"], nr * m), _f64(problem["ring_radius"], nr)]
-        lb, ub, rc, rr = self._keep
-        self._prob = Problem(int(problem["family"]), m, d, lb.ctypes.data, ub.ctypes.data, nr,
-                             rc.ctypes.data if nr else None, rr.ctypes.data if nr else None,
-                             int(problem["has_sum_lower"]), float(problem["sum_lower"]),
-                             int(problem["n_eq"]), float(problem["eq_tol"]))
-        c = config
-        self._cfg = Config(int(c["n_req"]), int(c["T"]), int(c.get("t1", 0)), int(c.get("t2", 0)),
-                           int(c.get("agg", 0)), float(c.get("theta", 0.0)),
-                           float(c.get("eta_c", 0.0)), float(c.get("eta_m", 0.0)),
-                           float(c.get("pc", 0.0)), float(c.get("pm", 0.0)),
-                           int(c["seed"]) & 0xFFFFFFFFFFFFFFFF,
-                           1 if (record or c.get("record", 0)) else 0)
+        self._prob, self._cfg, self._keep = _structs(problem, config, record)
         self._alloc = None
         if use_torch_allocator:
             self._alloc, self._cb = _torch_allocator()
@@ -386,7 +373,8 @@ def _structs(problem: dict, config: dict, record: bool = False):
     C = Config(int(c["n_req"]), int(c["T"]), int(c.get("t1", 0)), int(c.get("t2", 0)),
                int(c.get("agg", 0)), float(c.get("theta", 0.0)), float(c.get("eta_c", 0.0)),
                float(c.get("eta_m", 0.0)), float(c.get("pc", 0.0)), float(c.get("pm", 0.0)),
-               int(c["seed"]) & 0xFFFFFFFFFFFFFFFF, 1 if (record or c.get("record", 0)) else 0)
+               int(c["seed"]) & 0xFFFFFFFFFFFFFFFF, 1 if (record or c.get("record", 0)) else 0,
+               int(c.get("op", 0)), float(c.get("de_f", 0.0)))
     return P, C, keep
 
 

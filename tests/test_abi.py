@@ -54,7 +54,8 @@ def _init(glib, prob, cfg):
                   keep[2].ctypes.data if nr else None, keep[3].ctypes.data if nr else None,
                   prob["has_sum_lower"], prob["sum_lower"], prob["n_eq"], prob["eq_tol"])
     C = G.Config(cfg["n_req"], cfg["T"], cfg["t1"], cfg["t2"], cfg["agg"], cfg["theta"],
-                 cfg["eta_c"], cfg["eta_m"], cfg["pc"], cfg["pm"], cfg["seed"], 0)
+                 cfg["eta_c"], cfg["eta_m"], cfg["pc"], cfg["pm"], cfg["seed"], 0,
+                 cfg.get("op", 0), cfg.get("de_f", 0.0))
     h = ctypes.c_void_p()
     st = L.gmpea_init(ctypes.byref(P), ctypes.byref(C), None, None, ctypes.byref(h))
     return st, L.gmpea_last_error().decode()
@@ -69,6 +70,8 @@ def _init(glib, prob, cfg):
     (lambda p, c: p.update(family=7), -1),                   # unknown family
     (lambda p, c: c.update(agg=5), -1),                      # unknown aggregation
     (lambda p, c: c.update(pm=1.5), -1),                     # probability above 1
+    (lambda p, c: c.update(op=2), -1),                       # unknown operator
+    (lambda p, c: c.update(de_f=-0.5), -1),                  # negative DE scale
     (lambda p, c: p.update(ring_center=np.zeros((9, 2)), ring_radius=np.zeros(9)), -1),
 ])
 def test_init_rejects_invalid_input(glib, mutate, code):

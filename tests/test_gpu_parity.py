@@ -237,18 +237,33 @@ def test_generation_teacher_forced(G, which, agg, seed):
         gp.close()
 
 
+@pytest.mark.parametrize("which,seed", [("small", 4), ("medium", 5)])
+def test_generation_teacher_forced_de(G, which, seed):
+    """The DE operator (CR = 1, F = 0.5, then PM) in place of SBX."""
+    prob, cfg, _ = ci.WORKLOADS[which](seed)
+    cfg = dict(cfg, op=1)
+    gp, o = _pair(prob, cfg)
+    try:
+        gp.step(3)
+        frac = _teacher_forced(gp, o, 2, "%s DE seed=%d" % (which, seed))
+        assert frac < 0.005
+    finally:
+        gp.close()
+
+
 def test_generation_equality_and_wide_rows(G):
     """Large-workload shape (m = 3, d = 100, T = 32, four rings, x1 + x2 = 1 with
     tolerance 1e-4) at a population the oracle steps quickly."""
     prob = ci.make_problem(ci.FAMILY_SPHERE, 3, 100, 4, False, True, 5, eq_tol=1e-4)
-    cfg = ci.method_config(3000, 32, 5)
-    gp, o = _pair(prob, cfg)
-    try:
-        gp.step(3)
-        frac = _teacher_forced(gp, o, 2, "d100 equality")
-        assert frac < 0.005
-    finally:
-        gp.close()
+    for op in (0, 1):
+        cfg = ci.method_config(3000, 32, 5, op=op)
+        gp, o = _pair(prob, cfg)
+        try:
+            gp.step(3)
+            frac = _teacher_forced(gp, o, 2, "d100 equality op=%d" % op)
+            assert frac < 0.005
+        finally:
+            gp.close()
 
 
 def test_generation_odd_shapes(G):

@@ -71,4 +71,9 @@ def test_requests_wait_for_memory(G):
         srv.close()
     assert peak == 2
     assert len(srv.results) == 5
-    assert all(r.generations >= 1 for r in srv.results)
+    by = {r.rid: r for r in srv.results}
+    # the first two ran from the start; the others waited for memory, and a
+    # request whose deadline passed while it waited gets its initial front
+    assert by[0].generations >= 1 and by[1].generations >= 1
+    assert all(by[k].admitted >= min(by[0].delivered, by[1].delivered) for k in (2, 3, 4))
+    assert all(r.generations >= 0 and r.front_f.shape[1] == 3 for r in srv.results)

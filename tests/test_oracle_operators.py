@@ -231,3 +231,80 @@ def test_tchebycheff_closed_form(oracle_core):
         g_star = oracle_core.agg(1, 0.0, want, w, z)
         assert g_star <= vals.min() + 1e-12
         assert abs(g_star - 1.0 / (1 / w).sum()) < 1e-14
+
+
+# ------------------------------------------------------------------ DE ----
+# The DE operator of the LIR-CMOP experiments (CR = 1, F = 0.5), read as the
+# neighbourhood form x_i + F (x_a - x_b) followed by polynomial mutation.
+
+NO_PM = 0xFFFFFFFF  # a draw above every mutation threshold below
+
+
+def test_de_special_cases(oracle_core):
+    """F = 0.5 with x_i = x_b gives the midpoint of the two picks; equal picks
+    leave x_i unchanged; F = 0 returns x_i; with x_i = x_a the mutant is the
+    reflection of x_b through x_a scaled by one half."""
+    rng = np.random.default_rng(11)
+    tpm = 2**32 // 10
+    for _ in range(500):
+        xi, a, b = rng.uniform(0.2, 0.8, size=3)
+        assert oracle_core.de_dim(b, a, b, 0.5, 0.0, 1.0, NO_PM, tpm, 20.0) == pytest.approx(0.5 * (a + b), abs=1e-15)
+        assert oracle_core.de_dim(xi, a, a, 0.5, 0.0, 1.0, NO_PM, tpm, 20.0) == xi
+        assert oracle_core.de_dim(xi, a, b, 0.0, 0.0, 1.0, NO_PM, tpm, 20.0) == xi
+        v = oracle_core.de_dim(a, a, b, 0.5, -10.0, 10.0, NO_PM, tpm, 20.0)
+        assert v - a == pytest.approx(0.5 * (a - b), abs=1e-15)
+
+
+def test_de_clip_then_mutation(oracle_core):
+    """The mutant is clipped to the box; a mutation draw then applies bounded PM
+    to the clipped value (which stays in the box)."""
+    tpm = 2**32 // 10
+    assert oracle_core.de_dim(0.9, 1.0, 0.0, 0.5, 0.0, 1.0, NO_PM, tpm, 20.0) == 1.0
+    assert oracle_core.de_dim(0.1, 0.0, 1.0, 0.5, 0.0, 1.0, NO_PM, tpm, 20.0) == 0.0
+    rng = np.random.default_rng(12)
+    for _ in range(500):
+        xi, a, b = rng.uniform(0, 1, size=3)
+        w = int(rng.integers(0, tpm))
+        v = oracle_core.de_dim(xi, a, b, 0.5, 0.0, 1.0, w, tpm, 20.0)
+        base = min(1.0, max(0.0, xi + 0.5 * (a - b)))
+        assert v == oracle_core.pm_dim(base, 0.0, 1.0, w, tpm, 20.0)
+        assert 0.0 <= v <= 1.0
+
+
+def test_de_spread(oracle_core):
+    """With x_i fixed at the centre and independent uniform picks, the mutant has
+    mean x_i and variance F^2 (Var a + Var b) = 0.25 * 2 / 12 (no clipping can
+    occur: |F (a - b)| <= 0.5)."""
+    rng = np.random.default_rng(13)
+    a, b = rng.uniform(0, 1, size=(2, 40000))
+    v = np.array([oracle_core.de_dim(0.5, x, y, 0.5, 0.0, 1.0, NO_PM, 1, 20.0) for x, y in zip(a, b)])
+    assert abs(v.mean() - 0.5) < 4 * math.sqrt(1 / 24 / v.size)
+    assert abs(v.var() - 1 / 24) < 0.02 / 24 * 4
+
+
+def test_de_generation_wiring(oracle_core):
+    """In a whole generation with the DE operator, every offspring variable that
+    drew no mutation equals clip(x_i + 0.5 (x_a - x_b)) for the recorded picks
+    (a, b) and the subproblem's own row x_i of the same population."""
+    prob, cfg, _ = ci.workload_small(3)
+    cfg = dict(cfg, op=1)
+    o = oracle_core.Oracle(prob, cfg)
+    o.run(2)
+    X = [o.X[0].copy(), o.X[1].copy()]
+    dbg = o.step(debug=True)
+    dv = o.dv
+    N, d = o.N, o.d
+    key = np.array(dv["key"], dtype=np.uint32)
+    checked = 0
+    for p in range(2):
+        for i in range(N):
+            a, b = dbg["mate"][p][i]
+            for l in range(d):
+                ctr = np.array([l >> 1, i, o.gen, (3 << 24) | (p << 16)], dtype=np.uint32)
+                wB = int(oracle_core.philox(ctr[None, :], key)[0][2 * (l & 1) + 1])
+                if wB < dv["tpm"]:
+                    continue
+                want = min(1.0, max(0.0, X[p][i, l] + 0.5 * (X[p][a, l] - X[p][b, l])))
+                assert dbg["Xo"][p][i, l] == pytest.approx(want, abs=1e-15)
+                checked += 1
+    assert checked > 0.8 * 2 * N * d  # pm = 1/d mutates about one variable in d
