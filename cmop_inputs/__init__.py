@@ -61,14 +61,15 @@ def make_problem(family: int, m: int, d: int, n_ring: int, linear: bool, equalit
 
 def method_config(n_req: int, T: int, seed: int, agg: int = 0, theta: float = 5.0,
                   t1: int = 0, t2: int = 0, eta_c: float = 20.0, eta_m: float = 20.0,
-                  pc: float = 1.0, pm: float = 0.0, op: int = 0, de_f: float = 0.5) -> dict:
+                  pc: float = 1.0, pm: float = 0.0, op: int = 0, de_f: float = 0.5,
+                  op1_rule: int = 0) -> dict:
     """Raw method parameters (the paper's settings: theta = 5, eta = 20, pc = 1,
     pm = 1/d written as 0, t1 = T/2 and t2 = 2T written as 0; op 0 = SBX, op 1 =
     DE with F = 0.5 and CR = 1)."""
     return {"n_req": int(n_req), "T": int(T), "t1": int(t1), "t2": int(t2), "agg": int(agg),
             "theta": float(theta), "eta_c": float(eta_c), "eta_m": float(eta_m),
             "pc": float(pc), "pm": float(pm), "seed": int(seed), "op": int(op),
-            "de_f": float(de_f)}
+            "de_f": float(de_f), "op1_rule": int(op1_rule)}
 
 
 # --------------------------------------------------------------------------

@@ -143,7 +143,13 @@ typedef struct {
   int32_t op;      /* reproduction: GMPEA_OP_SBX (SBX then PM, the C-DTLZ / DC-DTLZ
                       setting) or GMPEA_OP_DE (DE then PM, the LIR-CMOP setting) */
   double de_f;     /* DE scale factor F; 0 means 0.5 (the crossover rate is 1) */
+  int32_t op1_rule; /* population 1's test in offspring cooperation (OP1):
+                       GMPEA_OP1_FPR (Alg. 2: lower CV, then lower aggregation) or
+                       GMPEA_OP1_FEASIBLE_FIRST (its prose: a feasible offspring
+                       wins, otherwise the lower aggregation) */
 } gmpea_config;
+
+enum { GMPEA_OP1_FPR = 0, GMPEA_OP1_FEASIBLE_FIRST = 1 };
 
 /* Device allocator hook. alloc returns device memory (or NULL), free releases
  * it; ctx is passed through. A handle frees everything it allocated with the

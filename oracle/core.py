@@ -48,7 +48,8 @@ class Cfg(ctypes.Structure):
                 ("eta_c", ctypes.c_double), ("eta_m", ctypes.c_double),
                 ("tpm", ctypes.c_uint64), ("tpc", ctypes.c_uint64),
                 ("key", ctypes.c_uint32 * 2), ("n_eq", ctypes.c_int32), ("eq_tol", ctypes.c_double),
-                ("f32", ctypes.c_int32), ("op", ctypes.c_int32), ("de_f", ctypes.c_double)]
+                ("f32", ctypes.c_int32), ("op", ctypes.c_int32), ("de_f", ctypes.c_double),
+                ("op1_rule", ctypes.c_int32)]
 
 
 def lib():
@@ -238,7 +239,7 @@ def derive(prob: dict, cfg: dict) -> dict:
             "key": (seed & 0xFFFFFFFF, seed >> 32), "agg": int(cfg["agg"]),
             "theta": float(cfg["theta"]), "eta_c": float(cfg["eta_c"]),
             "eta_m": float(cfg["eta_m"]), "op": int(cfg.get("op", 0)),
-            "de_f": float(cfg.get("de_f", 0.0)) or 0.5}
+            "de_f": float(cfg.get("de_f", 0.0)) or 0.5, "op1_rule": int(cfg.get("op1_rule", 0))}
 
 
 class Oracle:
@@ -259,7 +260,7 @@ class Oracle:
                         (ctypes.c_void_p * 2)(_p(self.B[0]), _p(self.B[1])), _p(self.W),
                         dv["agg"], dv["theta"], dv["eta_c"], dv["eta_m"], dv["tpm"], dv["tpc"],
                         (ctypes.c_uint32 * 2)(*dv["key"]), int(prob["n_eq"]),
-                        float(prob["eq_tol"]), 0, dv["op"], dv["de_f"])
+                        float(prob["eq_tol"]), 0, dv["op"], dv["de_f"], dv["op1_rule"])
         self.gen = 0
         if init:
             X = [self.init_x(0), self.init_x(1)]

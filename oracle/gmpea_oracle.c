@@ -363,6 +363,8 @@ typedef struct {
   int32_t f32;   /* selection only: take the decisions in FP32 on FP32 inputs (below) */
   int32_t op;    /* reproduction operator: ORC_OP_SBX (SBX then PM) or ORC_OP_DE (DE then PM) */
   double de_f;   /* DE scale factor F */
+  int32_t op1_rule; /* population 1's OP1 test: 0 the pseudocode's FPR, 1 the prose's
+                       feasibility-first rule (R27) */
 } orc_cfg;
 
 #define ORC_OP_SBX 0
@@ -486,6 +488,34 @@ static int orc_better(int pop, orc_key a, orc_key b, int *rob) {
   return cg < 0;
 }
 
+/* Robust feasibility status for parity: clearly violated (CV above the FP32
+ * rounding bound) or feasible with slack on every constraint; always robust
+ * when the decision is taken on given FP32 values. */
+static int orc_feas_rob(orc_key a) {
+  if (a.f32) return 1;
+  double ca = orc_nan_inf(a.cv);
+  if (ca > ORC_CV_ABS) return 1;
+  return ca == 0.0 && a.cmax < -ORC_CV_ABS && a.ceq < -ORC_CV_ABS;
+}
+
+/* R27: OP1 for population 1 as its prose describes it (a reading kept as a
+ * variant; the pseudocode's FPR is the default): a feasible offspring beats an
+ * infeasible one; when both are feasible or both infeasible the aggregation
+ * decides. True iff a is strictly better than b. */
+static int orc_better_feasfirst(orc_key a, orc_key b, int *rob) {
+  double ca = orc_nan_inf(a.cv), cb = orc_nan_inf(b.cv);
+  int fa = ca == 0.0, fb = cb == 0.0;
+  int rs = orc_feas_rob(a) && orc_feas_rob(b);
+  if (fa != fb) {
+    *rob = rs;
+    return fa;
+  }
+  int rg;
+  int cg = orc_cmp_g(orc_nan_inf(a.g), orc_nan_inf(b.g), fmax(a.fs, b.fs), a.f32, &rg);
+  *rob = rs && rg;
+  return cg < 0;
+}
+
 /* Keys that tie exactly on both sides of a parity check, whatever the
  * precision: exact copies (bitwise-equal objectives, and CV for population 1),
  * or, for Tchebycheff, the same clearly dominant term evaluated on a bitwise-
@@ -593,7 +623,10 @@ void orc_select(const orc_cfg *C, const double *X0, const double *X1, const doub
     orc_key k2 = orc_mk(C, CVo[N + i], CMo[N + i], Xo + ((size_t)N + i) * d,
                         Fo + ((size_t)N + i) * m, w, z);
     int r1, r2;
-    sw[i] = (uint8_t)orc_better(0, k2, k1, &r1);     /* S1: population 1 takes off2 */
+    if (C->op1_rule == 1)
+      sw[i] = (uint8_t)orc_better_feasfirst(k2, k1, &r1); /* S1 under the prose rule */
+    else
+      sw[i] = (uint8_t)orc_better(0, k2, k1, &r1);     /* S1: population 1 takes off2 */
     sw[N + i] = (uint8_t)orc_better(1, k1, k2, &r2); /* S2: population 2 takes off1 */
     swr[i] = (uint8_t)(r1 || orc_same(0, m, k1, k2));
     swr[N + i] = (uint8_t)(r2 || orc_same(1, m, k1, k2));

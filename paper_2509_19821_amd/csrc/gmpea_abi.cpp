@@ -174,6 +174,8 @@ gmpea_status validate(const gmpea_problem *P, const gmpea_config *C) {
     return fail(GMPEA_EINVAL, "gmpea_init: unknown reproduction operator");
   if (!(C->de_f >= 0.0) || !std::isfinite(C->de_f))
     return fail(GMPEA_EINVAL, "gmpea_init: de_f must be finite and >= 0");
+  if (C->op1_rule != GMPEA_OP1_FPR && C->op1_rule != GMPEA_OP1_FEASIBLE_FIRST)
+    return fail(GMPEA_EINVAL, "gmpea_init: unknown OP1 rule");
   return GMPEA_OK;
 }
 
@@ -343,6 +345,7 @@ gmpea_status gmpea_init(const gmpea_problem *P, const gmpea_config *C, const gmp
   st.tpc = static_cast<uint64_t>(std::floor(pc * 4294967296.0));
   st.inv_tpm = st.tpm > 0 ? static_cast<float>(1.0 / static_cast<double>(st.tpm)) : 0.0f;
   st.op = C->op;
+  st.op1_rule = C->op1_rule;
   st.de_f = static_cast<float>(C->de_f > 0 ? C->de_f : 0.5);
   st.key0 = static_cast<uint32_t>(C->seed & 0xFFFFFFFFull);
   st.key1 = static_cast<uint32_t>(C->seed >> 32);

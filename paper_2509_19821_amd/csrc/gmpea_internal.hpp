@@ -62,6 +62,7 @@ struct DevState {
   float pm_p, pm_e;          // eta_m + 1, 1 / (eta_m + 1)
   int32_t op;                // 0: SBX then PM, 1: DE then PM
   float de_f;                // DE scale factor
+  int32_t op1_rule;          // OP1 for population 1: 0 FPR, 1 feasibility first
   DevProblem prob;
 };
 

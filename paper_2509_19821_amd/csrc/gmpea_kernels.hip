@@ -529,7 +529,9 @@ __device__ __forceinline__ void load_z(const uint32_t *zkey, float (&z)[M]) {
 // ----------------------------------------------------------------------------
 // k_op1: offspring cooperation (Alg. 2 OP1, Eq. (11)) at w_i.
 // Population 1 takes off2_i if it is better by the feasibility priority rule
-// (Eq. (8)); population 2 takes off1_i if its aggregation is lower.
+// (Eq. (8)), or, as a variant, by the prose's feasibility-first rule (a feasible
+// offspring wins; otherwise the lower aggregation); population 2 takes off1_i
+// if its aggregation is lower.
 // ----------------------------------------------------------------------------
 template <int M>
 __device__ __forceinline__ void op1_body(const DevState &st, int b) {
@@ -541,7 +543,8 @@ __device__ __forceinline__ void op1_body(const DevState &st, int b) {
   const float g1 = aggregate<M>(o1, w, z, st.agg, st.theta);
   const float g2 = aggregate<M>(o2, w, z, st.agg, st.theta);
   const float c1 = nan_inf(o1.w), c2 = nan_inf(o2.w);
-  const bool s1 = (c2 < c1) || (c2 == c1 && g2 < g1);
+  const bool s1 = st.op1_rule == 0 ? ((c2 < c1) || (c2 == c1 && g2 < g1))
+                                    : ((c2 == 0.0f) != (c1 == 0.0f) ? c2 == 0.0f : g2 < g1);
   const bool s2 = g1 < g2;
   st.FCN[0][i] = s1 ? o2 : o1;
   st.FCN[1][i] = s2 ? o1 : o2;

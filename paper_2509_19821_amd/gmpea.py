@@ -23,6 +23,7 @@ _BUILD_INFO = os.path.join(_PKG, "_build", "build_info.json")
 
 FAMILY_CURVE, FAMILY_SPHERE = 0, 1
 OP_SBX, OP_DE = 0, 1
+OP1_FPR, OP1_FEASIBLE_FIRST = 0, 1
 AGG_PBI, AGG_TCHE = 0, 1
 FRONT_FEASIBLE_ND, FRONT_POP1, FRONT_POP2 = 0, 1, 2
 BUF = {"X": 0, "F": 1, "CV": 2, "XOFF": 3, "FOFF": 4, "CVOFF": 5, "Z": 6, "GEN": 7, "W": 8,
@@ -56,7 +57,7 @@ class Config(ctypes.Structure):
                 ("t2", ctypes.c_int32), ("agg", ctypes.c_int32), ("theta", ctypes.c_double),
                 ("eta_c", ctypes.c_double), ("eta_m", ctypes.c_double), ("pc", ctypes.c_double),
                 ("pm", ctypes.c_double), ("seed", ctypes.c_uint64), ("record", ctypes.c_int32),
-                ("op", ctypes.c_int32), ("de_f", ctypes.c_double)]
+                ("op", ctypes.c_int32), ("de_f", ctypes.c_double), ("op1_rule", ctypes.c_int32)]
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -374,7 +375,7 @@ def _structs(problem: dict, config: dict, record: bool = False):
                int(c.get("agg", 0)), float(c.get("theta", 0.0)), float(c.get("eta_c", 0.0)),
                float(c.get("eta_m", 0.0)), float(c.get("pc", 0.0)), float(c.get("pm", 0.0)),
                int(c["seed"]) & 0xFFFFFFFFFFFFFFFF, 1 if (record or c.get("record", 0)) else 0,
-               int(c.get("op", 0)), float(c.get("de_f", 0.0)))
+               int(c.get("op", 0)), float(c.get("de_f", 0.0)), int(c.get("op1_rule", 0)))
     return P, C, keep
 
 

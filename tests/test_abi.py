@@ -55,7 +55,7 @@ def _init(glib, prob, cfg):
                   prob["has_sum_lower"], prob["sum_lower"], prob["n_eq"], prob["eq_tol"])
     C = G.Config(cfg["n_req"], cfg["T"], cfg["t1"], cfg["t2"], cfg["agg"], cfg["theta"],
                  cfg["eta_c"], cfg["eta_m"], cfg["pc"], cfg["pm"], cfg["seed"], 0,
-                 cfg.get("op", 0), cfg.get("de_f", 0.0))
+                 cfg.get("op", 0), cfg.get("de_f", 0.0), cfg.get("op1_rule", 0))
     h = ctypes.c_void_p()
     st = L.gmpea_init(ctypes.byref(P), ctypes.byref(C), None, None, ctypes.byref(h))
     return st, L.gmpea_last_error().decode()
@@ -72,6 +72,7 @@ def _init(glib, prob, cfg):
     (lambda p, c: c.update(pm=1.5), -1),                     # probability above 1
     (lambda p, c: c.update(op=2), -1),                       # unknown operator
     (lambda p, c: c.update(de_f=-0.5), -1),                  # negative DE scale
+    (lambda p, c: c.update(op1_rule=3), -1),                 # unknown OP1 rule
     (lambda p, c: p.update(ring_center=np.zeros((9, 2)), ring_radius=np.zeros(9)), -1),
 ])
 def test_init_rejects_invalid_input(glib, mutate, code):

@@ -237,15 +237,16 @@ def test_generation_teacher_forced(G, which, agg, seed):
         gp.close()
 
 
-@pytest.mark.parametrize("which,seed", [("small", 4), ("medium", 5)])
-def test_generation_teacher_forced_de(G, which, seed):
-    """The DE operator (CR = 1, F = 0.5, then PM) in place of SBX."""
+@pytest.mark.parametrize("which,seed,rule", [("small", 4, 0), ("medium", 5, 0), ("medium", 6, 1)])
+def test_generation_teacher_forced_de(G, which, seed, rule):
+    """The DE operator (CR = 1, F = 0.5, then PM) in place of SBX; also with
+    OP1's feasibility-first variant for population 1."""
     prob, cfg, _ = ci.WORKLOADS[which](seed)
-    cfg = dict(cfg, op=1)
+    cfg = dict(cfg, op=1, op1_rule=rule)
     gp, o = _pair(prob, cfg)
     try:
         gp.step(3)
-        frac = _teacher_forced(gp, o, 2, "%s DE seed=%d" % (which, seed))
+        frac = _teacher_forced(gp, o, 2, "%s DE seed=%d op1_rule=%d" % (which, seed, rule))
         assert frac < 0.005
     finally:
         gp.close()

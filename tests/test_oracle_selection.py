@@ -205,3 +205,53 @@ def test_fp32_decisions_equal_dense_alg2_in_fp32(m, kind):
         assert np.array_equal(sw[swr.astype(bool)], dsw[swr.astype(bool)]), trial
         assert np.array_equal(win[winr.astype(bool)], dwin[winr.astype(bool)]), trial
         assert winr.mean() > 0.9
+
+
+def _op1_oracle(rule):
+    fam = ci.FAMILY_CURVE
+    prob = ci.make_problem(fam, 2, 6, 2, False, False, 0)
+    cfg = dict(ci.method_config(20, 6, 0), op1_rule=rule)
+    return core.Oracle(prob, cfg, init=False)
+
+
+@pytest.mark.parametrize("rule", [0, 1])
+def test_op1_rules_worked_cases(rule):
+    """Population 1's OP1 switch (S1: take population 2's offspring) on cases
+    that separate the pseudocode's FPR (lower CV, then lower aggregation) from
+    the prose's feasibility-first rule (feasible first; otherwise the lower
+    aggregation), with population 2's rule (lower aggregation) alongside."""
+    o = _op1_oracle(rule)
+    N, m, d = o.N, o.m, o.d
+    z = np.zeros(m)
+    w = o.W
+    # offspring on each subproblem's own direction at distance s: g = s (PBI, d2 = 0)
+    def on_ray(i, s):
+        u = w[i] / np.linalg.norm(w[i])
+        return s * u
+    cases = {  # (cv1, g1, cv2, g2) -> (S1 under FPR, S1 under prose, S2)
+        0: ((1.0, 0.2, 0.5, 0.9), (1, 0, 1)),   # both infeasible: FPR by CV, prose by g
+        1: ((0.0, 0.9, 0.0, 0.2), (1, 1, 0)),   # both feasible: g decides everywhere
+        2: ((0.3, 0.1, 0.0, 0.9), (1, 1, 1)),   # only off2 feasible: both rules take it
+        3: ((0.0, 0.9, 0.4, 0.1), (0, 0, 0)),   # only off1 feasible: both keep it
+        4: ((0.7, 0.5, 0.7, 0.5), (0, 0, 0)),   # exact copy: no switch
+    }
+    Fo = np.zeros((2 * N, m))
+    CVo = np.full(2 * N, 2.0)
+    for i, ((c1, g1, c2, g2), _) in cases.items():
+        Fo[i], CVo[i] = on_ray(i + 1, g1), c1
+        Fo[N + i], CVo[N + i] = on_ray(i + 1, g2), c2
+    # evaluate at subproblem i + 1 by placing the cases there
+    Fo2 = np.zeros_like(Fo)
+    CVo2 = np.full(2 * N, 2.0)
+    for i in cases:
+        Fo2[i + 1], CVo2[i + 1] = Fo[i], CVo[i]
+        Fo2[N + i + 1], CVo2[N + i + 1] = Fo[N + i], CVo[N + i]
+    F = [np.full((N, m), 5.0), np.full((N, m), 5.0)]
+    CV = [np.full(N, 9.0), np.full(N, 9.0)]
+    CM = [CV[0].copy(), CV[1].copy()]
+    X = [np.zeros((N, d)), np.zeros((N, d))]
+    Xo = np.zeros((2 * N, d))
+    sw, _, _, _ = o.select(X, F, CV, CM, Xo, Fo2, CVo2, np.where(CVo2 == 0, -1.0, CVo2), z)
+    for i, (_, want) in cases.items():
+        assert sw[0, i + 1] == want[rule], (i, rule)
+        assert sw[1, i + 1] == want[2], i
