@@ -405,6 +405,7 @@ typedef struct {
   double ceq; /* equality slack |x1 + x2 - 1| - tol (-inf without the equality) */
   int tk;     /* Tchebycheff: index of the term that sets g with a clear margin, else -1 */
   double fs;  /* max(1, |f|_inf, |z|_inf): the scale of g's absolute rounding error */
+  int copy_ties; /* bitwise-equal keys here are bitwise equal on the device too */
 } orc_key;
 
 /* Aggregation values: FP32 rounding moves g by a few units of 1e-7 relative to
@@ -521,6 +522,7 @@ static int orc_better_feasfirst(orc_key a, orc_key b, int *rob) {
  * or, for Tchebycheff, the same clearly dominant term evaluated on a bitwise-
  * equal objective (e.g. a variable copied unchanged by SBX). */
 static int orc_same(int pop, int m, orc_key a, orc_key b) {
+  if (!a.copy_ties || !b.copy_ties) return 0;
   if (pop == 0 && memcmp(&a.cv, &b.cv, sizeof(double)) != 0) return 0;
   if (memcmp(a.f, b.f, sizeof(double) * (size_t)m) == 0) return 1;
   return a.tk >= 0 && a.tk == b.tk && memcmp(&a.f[a.tk], &b.f[b.tk], sizeof(double)) == 0;
@@ -578,7 +580,12 @@ static orc_key orc_mk(const orc_cfg *C, double cv, double cmax, const double *x,
    * value and a product per term, none of which a compiler can fuse, so equal
    * FP32 inputs give the bitwise-equal value on every IEEE device. */
   int mode = C->f32 ? (C->agg == 1 ? 2 : 1) : 0;
-  orc_key k = {mode, cv, cmax, g, f, x, -INFINITY, -1, 1.0};
+  /* FP64-equal offspring are device-equal when they are copies of equal values
+   * (SBX leaves variables uncrossed; decisions on given FP32 values). DE
+   * offspring are recomputed in every variable, and different triples can meet
+   * exactly in FP64 (x_b + F (x_a - x_b) and x_a + F (x_b - x_a) at F = 1/2)
+   * while their FP32 roundings differ: such ties are not robust (R24, R26). */
+  orc_key k = {mode, cv, cmax, g, f, x, -INFINITY, -1, 1.0, C->f32 || C->op != ORC_OP_DE};
   if (C->n_eq) k.ceq = fabs(x[0] + x[1] - 1.0) - C->eq_tol;
   if (C->agg == 1) k.tk = orc_tche_arg(C->m, f, w, z);
   for (int32_t a = 0; a < C->m; ++a) {

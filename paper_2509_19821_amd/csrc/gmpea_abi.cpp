@@ -380,8 +380,8 @@ gmpea_status gmpea_init(const gmpea_problem *P, const gmpea_config *C, const gmp
       st.FCO[p] = c.take<float4>(rows);
       st.FCN[p] = c.take<float4>(rows);
       st.B[p] = c.take<int32_t>(static_cast<size_t>(N) * ts[p]);
-      st.roff[p] = c.take<int32_t>(static_cast<size_t>(N) + 1);
-      st.ridx[p] = c.take<int32_t>(static_cast<size_t>(N) * ts[p]);
+      st.rhead[p] = c.take<int32_t>(static_cast<size_t>(N) * ts[p]);
+      st.rtoff[p] = c.take<int32_t>(static_cast<size_t>(N) + 1);
       st.mate[p] = h->record ? c.take<int32_t>(rows * 2) : nullptr;
       st.win[p] = h->record ? c.take<int32_t>(rows) : nullptr;
     }
@@ -433,7 +433,8 @@ gmpea_status gmpea_init(const gmpea_problem *P, const gmpea_config *C, const gmp
     zero(st.FC[p], 0, rows * sizeof(float4));
     zero(st.FCO[p], 0, rows * sizeof(float4));
     zero(st.FCN[p], 0, rows * sizeof(float4));
-    zero(const_cast<int32_t *>(st.roff[p]), 0, (static_cast<size_t>(N) + 1) * sizeof(int32_t));
+    zero(const_cast<int32_t *>(st.rtoff[p]), 0, (static_cast<size_t>(N) + 1) * sizeof(int32_t));
+    zero(const_cast<int32_t *>(st.rhead[p]), 0xFF, static_cast<size_t>(N) * ts[p] * sizeof(int32_t));
     if (h->record) {
       zero(st.mate[p], 0xFF, rows * 2 * sizeof(int32_t));
       zero(st.win[p], 0xFF, rows * sizeof(int32_t));
@@ -462,12 +463,37 @@ gmpea_status gmpea_init(const gmpea_problem *P, const gmpea_config *C, const gmp
       if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     }
   }
-  // reverse lists (the offspring buffer serves as the zeroed cursor array)
+  // reverse lists (the offspring buffer serves as the zeroed cursor array); the
+  // tail, sized by the count pass, gets an allocation of its own
+  int32_t *cursor = reinterpret_cast<int32_t *>(st.FCO[0]);
+  int32_t tail_n[2] = {0, 0};
   for (int p = 0; p < 2; ++p) {
-    zero(st.FCO[0], 0, static_cast<size_t>(N) * sizeof(int32_t));
+    zero(cursor, 0, static_cast<size_t>(N) * sizeof(int32_t));
     if (e == hipSuccess)
-      e = launch_reverse(N, ts[p], st.B[p], const_cast<int32_t *>(st.roff[p]), reinterpret_cast<int32_t *>(st.FCO[0]),
-                         const_cast<int32_t *>(st.ridx[p]), h->stream);
+      e = launch_reverse_count(N, ts[p], st.B[p], cursor, const_cast<int32_t *>(st.rtoff[p]), h->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(&tail_n[p], st.rtoff[p] + N, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e == hipSuccess) {
+    Carve sizing;
+    sizing.take<int32_t>(static_cast<size_t>(tail_n[0]));
+    sizing.take<int32_t>(static_cast<size_t>(tail_n[1]));
+    Carve carve;
+    carve.base = static_cast<char *>(dev_alloc(h, sizing.off));
+    if (!carve.base) {
+      release_all(h);
+      delete h;
+      return fail(GMPEA_ENOMEM, "gmpea_init: device allocation failed");
+    }
+    st.rtail[0] = carve.take<int32_t>(static_cast<size_t>(tail_n[0]));
+    st.rtail[1] = carve.take<int32_t>(static_cast<size_t>(tail_n[1]));
+  }
+  for (int p = 0; p < 2; ++p) {
+    zero(cursor, 0, static_cast<size_t>(N) * sizeof(int32_t));
+    if (e == hipSuccess)
+      e = launch_reverse_fill(N, ts[p], st.B[p], st.rtoff[p], cursor, const_cast<int32_t *>(st.rhead[p]),
+                              const_cast<int32_t *>(st.rtail[p]), h->stream);
   }
   zero(st.FCO[0], 0, rows * sizeof(float4));
   if (e == hipSuccess) e = launch_init(st, h->stream);

@@ -47,9 +47,14 @@ struct DevState {
   float4 *FC[2], *FCO[2], *FCN[2];
   float4 *W;                 // unit direction (PBI) or raw weight (Tchebycheff)
   const int32_t *B[2];       // n x t_p
-  const int32_t *roff[2];    // reverse lists, CSR: offsets n + 1
-  const int32_t *ridx[2];    //                     indices n t_p, ascending per row
+  // Reverse lists rev_p(j) = {i : j in B_p(i)}, ascending: the first t_p entries
+  // of each list in a padded head (n x t_p, -1 after the list's end), the rest
+  // (lists longer than t_p, a few percent of slots) in a CSR tail.
+  const int32_t *rhead[2];   // n x t_p
+  const int32_t *rtoff[2];   // tail offsets, n + 1
+  const int32_t *rtail[2];   // tail entries
   uint8_t *src;              // OP1 switches: bit p set = population p took the other's offspring
+                             // (also carried in the sign of FCN's CV, for k_select)
   uint32_t *zkey;            // ideal point as order-preserving keys (atomic min)
   uint32_t *gen;             // generations completed
   unsigned long long *repl;  // replaced-slot counters per population
@@ -130,9 +135,14 @@ void neighbour_offsets(int32_t m, int32_t H, int32_t t, std::vector<int32_t> &d)
 hipError_t launch_tables(int32_t m, int32_t n, int32_t H, const int2 *offs, int32_t noffs,
                          int32_t t1, int32_t t2, int32_t agg, float4 *W, int32_t *B1, int32_t *B2,
                          uint32_t *incomplete, hipStream_t s);
-// Reverse lists of B (n x t) in CSR form, each list ascending. off (n + 1) and
-// cursor (n) must be zero on entry.
-hipError_t launch_reverse(int32_t n, int32_t t, const int32_t *B, int32_t *off, int32_t *cursor,
-                          int32_t *idx, hipStream_t s);
+// Reverse lists of B (n x t), in two launches around a host read of the tail
+// size. launch_reverse_count: cursor (n, zero on entry) receives each list's
+// length and toff (n + 1, zero on entry) the exclusive scan of the lengths in
+// excess of t, so toff[n] is the tail size. launch_reverse_fill: head (n x t)
+// and tail receive the lists, each ascending (cursor must be zero again).
+hipError_t launch_reverse_count(int32_t n, int32_t t, const int32_t *B, int32_t *cursor,
+                                int32_t *toff, hipStream_t s);
+hipError_t launch_reverse_fill(int32_t n, int32_t t, const int32_t *B, const int32_t *toff,
+                               int32_t *cursor, int32_t *head, int32_t *tail, hipStream_t s);
 
 }  // namespace gmpea

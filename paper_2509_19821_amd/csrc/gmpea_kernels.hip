@@ -8,7 +8,7 @@
 //   k_op1     one lane per subproblem i: OP1 offspring cooperation at w_i with
 //             the updated ideal point; writes the new offspring's F/CV and the
 //             source switch (X is not copied).
-//   k_select  one lane per parent slot (p, j): OP2 + OP3 as a pull over the
+//   k_select  a lane group per parent slot (p, j): OP2 + OP3 as a pull over the
 //             reverse neighbour list of j (every offspring i with j in B_p(i)),
 //             lexicographic minimum of the qualifiers; winners' rows are then
 //             copied by the whole block with 16-byte accesses.
@@ -322,16 +322,24 @@ __global__ __launch_bounds__(kBlock) void k_tables(int32_t n, int32_t H, const i
   if (c < tmax) atomicOr(incomplete, 1u);
 }
 
-// Reverse lists: counts (at off[j + 1]), an in-place scan, a scatter, and a
-// per-list insertion sort (lists hold about t entries) for a deterministic layout.
+// Reverse lists: lengths, the scan of their excess over t, a scatter into the
+// padded head and the tail, and a per-list insertion sort (lists hold about t
+// entries) so that every list is ascending.
 __global__ __launch_bounds__(kBlock) void k_rev_count(int64_t nt, const int32_t *__restrict__ B,
-                                                     int32_t *__restrict__ off) {
+                                                     int32_t *__restrict__ cnt) {
   const int64_t q = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
-  if (q < nt) atomicAdd(&off[B[q] + 1], 1);
+  if (q < nt) atomicAdd(&cnt[B[q]], 1);
+}
+
+__global__ __launch_bounds__(kBlock) void k_rev_excess(int32_t n, int32_t t, const int32_t *__restrict__ cnt,
+                                                      int32_t *__restrict__ toff) {
+  const int32_t j = blockIdx.x * kBlock + threadIdx.x;
+  if (j < n) toff[j + 1] = max(cnt[j] - t, 0);
 }
 
 constexpr int kScanThreads = 1024;
 
+// In-place inclusive scan of off[0 .. len) by one block.
 __global__ __launch_bounds__(kScanThreads) void k_scan(int32_t *off, int32_t len) {
   __shared__ int32_t part[kScanThreads];
   const int tid = threadIdx.x;
@@ -355,29 +363,42 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(int32_t *off, int32_t len
 }
 
 __global__ __launch_bounds__(kBlock) void k_rev_fill(int64_t nt, int32_t t, const int32_t *__restrict__ B,
-                                                    const int32_t *__restrict__ off,
+                                                    const int32_t *__restrict__ toff,
                                                     int32_t *__restrict__ cursor,
-                                                    int32_t *__restrict__ idx) {
+                                                    int32_t *__restrict__ head,
+                                                    int32_t *__restrict__ tail) {
   const int64_t q = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
   if (q >= nt) return;
   const int32_t j = B[q];
   const int32_t pos = atomicAdd(&cursor[j], 1);
-  idx[off[j] + pos] = static_cast<int32_t>(q / t);
+  const int32_t i = static_cast<int32_t>(q / t);
+  if (pos < t)
+    head[static_cast<size_t>(j) * t + pos] = i;
+  else
+    tail[toff[j] + pos - t] = i;
 }
 
-__global__ __launch_bounds__(kBlock) void k_rev_sort(int32_t n, const int32_t *__restrict__ off,
-                                                    int32_t *__restrict__ idx) {
+__global__ __launch_bounds__(kBlock) void k_rev_sort(int32_t n, int32_t t, const int32_t *__restrict__ toff,
+                                                    int32_t *__restrict__ head,
+                                                    int32_t *__restrict__ tail) {
   const int32_t j = blockIdx.x * kBlock + threadIdx.x;
   if (j >= n) return;
-  const int32_t a = off[j], b = off[j + 1];
-  for (int32_t q = a + 1; q < b; ++q) {
-    const int32_t v = idx[q];
+  int32_t *h = head + static_cast<size_t>(j) * t;
+  int32_t *tl = tail + toff[j];
+  const int32_t ext = toff[j + 1] - toff[j];
+  int32_t len = 0;
+  while (len < t && h[len] >= 0) ++len;
+  len += ext;
+  // element k of the list: head for k < t, tail beyond
+  auto at = [&](int32_t k) -> int32_t & { return k < t ? h[k] : tl[k - t]; };
+  for (int32_t q = 1; q < len; ++q) {
+    const int32_t v = at(q);
     int32_t r = q - 1;
-    while (r >= a && idx[r] > v) {
-      idx[r + 1] = idx[r];
+    while (r >= 0 && at(r) > v) {
+      at(r + 1) = at(r);
       --r;
     }
-    idx[r + 1] = v;
+    at(r + 1) = v;
   }
 }
 
@@ -546,8 +567,12 @@ __device__ __forceinline__ void op1_body(const DevState &st, int b) {
   const bool s1 = st.op1_rule == 0 ? ((c2 < c1) || (c2 == c1 && g2 < g1))
                                     : ((c2 == 0.0f) != (c1 == 0.0f) ? c2 == 0.0f : g2 < g1);
   const bool s2 = g1 < g2;
-  st.FCN[0][i] = s1 ? o2 : o1;
-  st.FCN[1][i] = s2 ? o1 : o2;
+  // the CV lane's sign bit tells k_select which population's offspring row this is
+  float4 n1 = s1 ? o2 : o1, n2 = s2 ? o1 : o2;
+  n1.w = s1 ? -fabsf(n1.w) : fabsf(n1.w);
+  n2.w = s2 ? -fabsf(n2.w) : fabsf(n2.w);
+  st.FCN[0][i] = n1;
+  st.FCN[1][i] = n2;
   st.src[i] = static_cast<uint8_t>((s1 ? 1u : 0u) | (s2 ? 2u : 0u));
 }
 
@@ -566,13 +591,17 @@ __global__ __launch_bounds__(kBlock) void k_op1(DevState st) {
 // the slot they overwrite.
 // A group of lps lanes decides one slot (lps = t_p / 4 rounded up to a power of
 // two, at most 64: about four reverse-list entries per lane). Lane g takes
-// entries g, g + lps, ... of the slot's list, four at a time with independent
-// loads (index, then candidate F/CV), and keeps its lexicographic minimum of
-// (CV, g, index). The group minimum follows from DPP moves inside 16-lane rows
-// (quad swaps, half-row mirror, row mirror) and lane permutes beyond. That
-// minimum qualifies exactly when some candidate qualifies, since qualifying
-// means being below the parent in the same order; a minimum over a total order
-// does not depend on how the candidates were split among lanes.
+// entries g, g + lps, ... of the slot's padded list head, four at a time with
+// independent loads (index, then candidate F/CV), then its share of the tail
+// (lists longer than t_p), and keeps its lexicographic minimum of (CV, g,
+// index). No load waits on another beyond index -> candidate: the head needs no
+// offset, and OP1's choice of population rides in the sign of the candidate's
+// CV. The group minimum follows from DPP moves inside 16-lane rows (quad swaps,
+// half-row mirror, row mirror) and lane permutes beyond, and the lane that
+// holds the winner writes its F/CV from registers. That minimum qualifies
+// exactly when some candidate qualifies, since qualifying means being below the
+// parent in the same order; a minimum over a total order does not depend on how
+// the candidates were split among lanes.
 // ----------------------------------------------------------------------------
 struct SelKey {
   float c, g;
@@ -623,51 +652,64 @@ __device__ __forceinline__ void select_body(const DevState &st, int L) {
   if (threadIdx.x == 0) s_cnt = 0;
   __syncthreads();
   const bool live = j < st.n;
+  // keys carry i2 = 2 i + (OP1 source bit of i): the same order as i, and the
+  // winner's row follows without another load
   SelKey best{__builtin_huge_valf(), __builtin_huge_valf(), 0x7FFFFFFF};
+  float4 bestf = make_float4(0, 0, 0, 0);  // F/CV of this lane's best candidate
   float4 w = make_float4(0, 0, 0, 0), par = make_float4(0, 0, 0, 0);
   float z[M];
   load_z<M>(st.zkey, z);
+  auto consider = [&](int32_t i, float4 c) {
+    const uint32_t bit = __float_as_uint(c.w) >> 31;  // set: the other population's offspring
+    c.w = fabsf(c.w);
+    const SelKey k{(p == 0) ? nan_inf(c.w) : 0.0f, aggregate<M>(c, w, z, st.agg, st.theta),
+                   static_cast<int>((static_cast<uint32_t>(i) << 1) | bit)};
+    if (sel_less(k, best)) {
+      best = k;
+      bestf = c;
+    }
+  };
   if (live) {
+    const int t = st.t[p];
     w = st.W[j];
     par = st.FC[p][j];
-    const int q0 = st.roff[p][j], q1 = st.roff[p][j + 1];
-    const int32_t *rl = st.ridx[p];
+    const int32_t *head = st.rhead[p] + static_cast<size_t>(j) * t;
+    const int32_t ta = st.rtoff[p][j], tb = st.rtoff[p][j + 1];
     const float4 *cand = st.FCN[p];
-    for (int q = q0 + g; q < q1; q += 4 * lps) {
+    for (int q0 = g; q0 < t; q0 += 4 * lps) {  // one pass unless t > 4 lps = 256
       int ii[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        const int qq = q + u * lps;
-        ii[u] = qq < q1 ? rl[qq] : -1;
+        const int q = q0 + u * lps;
+        ii[u] = q < t ? head[q] : -1;
       }
       float4 cc[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) cc[u] = ii[u] >= 0 ? cand[ii[u]] : make_float4(0, 0, 0, 0);
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        if (ii[u] >= 0) {
-          const SelKey k{(p == 0) ? nan_inf(cc[u].w) : 0.0f,
-                         aggregate<M>(cc[u], w, z, st.agg, st.theta), ii[u]};
-          if (sel_less(k, best)) best = k;
-        }
-      }
+      for (int u = 0; u < 4; ++u)
+        if (ii[u] >= 0) consider(ii[u], cc[u]);
+    }
+    for (int q = ta + g; q < tb; q += lps) {
+      const int32_t i = st.rtail[p][q];
+      consider(i, cand[i]);
     }
   }
+  const SelKey mine = best;
   sel_group_min(best, lps);
-  if (live && g == 0) {
+  if (live) {
     const float pc = (p == 0) ? nan_inf(par.w) : 0.0f;
     const float pg = aggregate<M>(par, w, z, st.agg, st.theta);
     const bool win = best.i != 0x7FFFFFFF && (best.c < pc || (best.c == pc && best.g < pg));
-    if (st.win[p]) st.win[p][j] = win ? best.i : -1;
-    if (win) {
-      const float4 fnew = st.FCN[p][best.i];
-      const uint32_t sb = st.src[best.i];
-      st.FC[p][j] = fnew;
-      const int sp = p ^ static_cast<int>((sb >> p) & 1u);
+    const int bi = best.i >> 1;
+    if (!win && g == 0 && st.win[p]) st.win[p][j] = -1;
+    if (win && mine.i == best.i) {  // the one lane that holds the winner
+      if (st.win[p]) st.win[p][j] = bi;
+      st.FC[p][j] = bestf;
+      const int sp = p ^ (best.i & 1);
       const int slot = atomicAdd(&s_cnt, 1);
       s_dst[slot] = j;
-      s_srcrow[slot] =
-          reinterpret_cast<const float4 *>(st.XO[sp] + static_cast<size_t>(best.i) * st.stride);
+      s_srcrow[slot] = reinterpret_cast<const float4 *>(st.XO[sp] + static_cast<size_t>(bi) * st.stride);
     }
   }
   __syncthreads();
@@ -841,14 +883,24 @@ hipError_t launch_tables(int32_t m, int32_t n, int32_t H, const int2 *offs, int3
   return hipGetLastError();
 }
 
-hipError_t launch_reverse(int32_t n, int32_t t, const int32_t *B, int32_t *off, int32_t *cursor,
-                          int32_t *idx, hipStream_t s) {
+hipError_t launch_reverse_count(int32_t n, int32_t t, const int32_t *B, int32_t *cursor,
+                                int32_t *toff, hipStream_t s) {
   const int64_t nt = static_cast<int64_t>(n) * t;
   const unsigned grid = static_cast<unsigned>((nt + kBlock - 1) / kBlock);
-  hipLaunchKernelGGL(k_rev_count, dim3(grid), dim3(kBlock), 0, s, nt, B, off);
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, s, off, n + 1);
-  hipLaunchKernelGGL(k_rev_fill, dim3(grid), dim3(kBlock), 0, s, nt, t, B, off, cursor, idx);
-  hipLaunchKernelGGL(k_rev_sort, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, n, off, idx);
+  hipLaunchKernelGGL(k_rev_count, dim3(grid), dim3(kBlock), 0, s, nt, B, cursor);
+  hipLaunchKernelGGL(k_rev_excess, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, n, t,
+                     static_cast<const int32_t *>(cursor), toff);
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, s, toff, n + 1);
+  return hipGetLastError();
+}
+
+hipError_t launch_reverse_fill(int32_t n, int32_t t, const int32_t *B, const int32_t *toff,
+                               int32_t *cursor, int32_t *head, int32_t *tail, hipStream_t s) {
+  const int64_t nt = static_cast<int64_t>(n) * t;
+  const unsigned grid = static_cast<unsigned>((nt + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL(k_rev_fill, dim3(grid), dim3(kBlock), 0, s, nt, t, B, toff, cursor, head, tail);
+  hipLaunchKernelGGL(k_rev_sort, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, n, t, toff,
+                     head, tail);
   return hipGetLastError();
 }
 

@@ -77,6 +77,31 @@ def _diag(label, S, Xo, Fo, CVo, dbg, ok):
     np.savez(os.path.join(out, "diag_%s.npz" % name), **keep)
 
 
+def _diag_decision(label, p, slots, S, Xo, Fo, CVo, z, g_win, g_sw, dbg):
+    """On a robust-decision mismatch, print the competing keys and keep the
+    generation's inputs for a replay on the CPU (GMPEA_DIAG_DIR)."""
+    for j in slots[:5]:
+        gi, oi = int(g_win[j]), int(dbg["win"][p][j])
+        _log("%s p=%d slot %d: gpu winner %d, oracle winner %d" % (label, p, j, gi, oi))
+        for who, i in (("gpu", gi), ("oracle", oi)):
+            if i < 0:
+                continue
+            sp = p ^ int(g_sw[i])
+            _log("  %s cand %d src %d: gpu F %s CV %.9g | ref F %s CV %.9g | op1 gpu %d ref %d" % (
+                who, i, sp, Fo[sp][i], CVo[sp][i], dbg["Fo"][sp][i], dbg["CVo"][sp][i],
+                int(g_sw[i]), int(dbg["op1"][p][i])))
+        _log("  parent F %s CV %.9g" % (S["F"][p][j], S["CV"][p][j]))
+    out = os.environ.get("GMPEA_DIAG_DIR")
+    if out:
+        os.makedirs(out, exist_ok=True)
+        name = "".join(ch if ch.isalnum() else "_" for ch in label)
+        np.savez(os.path.join(out, "decision_%s_p%d.npz" % (name, p)), slots=slots,
+                 X0=S["X"][0], X1=S["X"][1], z_pre=S["z"], gen=np.array([S["gen"]]),
+                 Xo0=Xo[0], Xo1=Xo[1], Fo0=Fo[0], Fo1=Fo[1], CVo0=CVo[0], CVo1=CVo[1], z=z,
+                 g_win=g_win, g_sw=g_sw, o_win=dbg["win"][p], o_op1=dbg["op1"],
+                 o_Xo=dbg["Xo"], o_Fo=dbg["Fo"], o_CVo=dbg["CVo"])
+
+
 def _teacher_forced(gp, o, gens, label):
     """Run `gens` teacher-forced generations, each checked in two stages.
 
@@ -128,7 +153,11 @@ def _teacher_forced(gp, o, gens, label):
             assert bad.size == 0, (label, "win fp32", p, np.nonzero(wr)[0][bad[:5]])
             # FP64 decisions marked robust agree as well
             wr64 = dbg["win_rob"][p].astype(bool)
-            assert np.array_equal(g_win[wr64], dbg["win"][p][wr64]), (label, "win fp64", p)
+            bad64 = np.nonzero(wr64 & (g_win != dbg["win"][p]))[0]
+            if bad64.size:
+                _diag_decision(label, p, bad64, S, Xo, Fo, CVo, z, g_win, g_sw, dbg)
+            assert bad64.size == 0, (label, "win fp64", p, bad64[:5], g_win[bad64[:5]],
+                                     dbg["win"][p][bad64[:5]])
             # every decision is a valid one, and replaced rows are exact copies
             X, F, CV = gp.read("X", p), gp.read("F", p), gp.read("CV", p)
             B = o.B[p]
