@@ -43,7 +43,10 @@ struct DevState {
   int32_t sel_blocks0, sel_blocks1;  // k_select blocks of each population
   int32_t agg;
   float theta;
+  // X_p holds two planes of rows x stride floats: generation g's population in
+  // plane g & 1; replacement writes every row of the other plane.
   float *X[2], *XO[2];
+  int64_t plane;             // floats per plane
   float4 *FC[2], *FCO[2], *FCN[2];
   float4 *W;                 // unit direction (PBI) or raw weight (Tchebycheff)
   const int32_t *B[2];       // n x t_p
@@ -56,7 +59,8 @@ struct DevState {
   uint8_t *src;              // OP1 switches: bit p set = population p took the other's offspring
                              // (also carried in the sign of FCN's CV, for k_select)
   uint32_t *zkey;            // ideal point as order-preserving keys (atomic min)
-  uint32_t *gen;             // generations completed
+  uint32_t *gen;             // generations completed (k_op1 advances it: from then on
+                             // it names the generation being finished)
   unsigned long long *repl;  // replaced-slot counters per population
   int32_t *mate[2];          // optional record of parent rows (n x 2)
   int32_t *win[2];           // optional record of winners (n)

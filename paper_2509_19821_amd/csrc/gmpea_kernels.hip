@@ -228,7 +228,7 @@ __global__ __launch_bounds__(kBlock) void k_init(DevState st) {
 #pragma unroll
   for (int k = 0; k < M; ++k) zv[k] = __builtin_huge_valf();
   if (i < st.n) {
-    float *row = st.X[p] + static_cast<size_t>(i) * st.stride;
+    float *row = st.X[p] + static_cast<size_t>(i) * st.stride;  // plane 0: generation 0
     EvalAcc e{0.0f, 0.0f, 0.0f};
     uint4 w = make_uint4(0, 0, 0, 0);
     for (int l = 0; l < st.stride; ++l) {
@@ -422,8 +422,10 @@ __device__ __forceinline__ void vary_body(const DevState &st, int L, int G) {
   const int p = L >= half ? 1 : 0;
   const int g = threadIdx.x & (LPO - 1);
   const int i = (L - p * half) * kPer + threadIdx.x / LPO;
-  const uint32_t k = *st.gen + 1u;
+  const uint32_t gk = *st.gen;
+  const uint32_t k = gk + 1u;
   const uint32_t tagp = (p << 16);
+  const float *Xc = st.X[p] + static_cast<size_t>(gk & 1u) * st.plane;
   float zv[M];
 #pragma unroll
   for (int q = 0; q < M; ++q) zv[q] = __builtin_huge_valf();
@@ -445,8 +447,8 @@ __device__ __forceinline__ void vary_body(const DevState &st, int L, int G) {
       st.mate[p][2 * i + 1] = pb;
     }
     const bool cross = static_cast<uint64_t>(w.z) < st.tpc;
-    const float4 *ra = reinterpret_cast<const float4 *>(st.X[p] + static_cast<size_t>(pa) * st.stride);
-    const float4 *rb = reinterpret_cast<const float4 *>(st.X[p] + static_cast<size_t>(pb) * st.stride);
+    const float4 *ra = reinterpret_cast<const float4 *>(Xc + static_cast<size_t>(pa) * st.stride);
+    const float4 *rb = reinterpret_cast<const float4 *>(Xc + static_cast<size_t>(pb) * st.stride);
     float4 *ro = reinterpret_cast<float4 *>(st.XO[p] + static_cast<size_t>(i) * st.stride);
     const float4 *lb4 = reinterpret_cast<const float4 *>(st.prob.lb);
     const float4 *ub4 = reinterpret_cast<const float4 *>(st.prob.ub);
@@ -454,7 +456,7 @@ __device__ __forceinline__ void vary_body(const DevState &st, int L, int G) {
     const uint32_t tagv = (kTagVar << 24) | tagp;
     const int nq = st.stride >> 2;
     const bool de = st.op == 1;
-    const float4 *rx = reinterpret_cast<const float4 *>(st.X[p] + static_cast<size_t>(i) * st.stride);
+    const float4 *rx = reinterpret_cast<const float4 *>(Xc + static_cast<size_t>(i) * st.stride);
     for (int q = g; q < nq; q += LPO) {
       const int l0 = q << 2;
       const float4 va = ra[q], vb = rb[q], lo = lb4[q], hi = ub4[q], is = is4[q];
@@ -557,6 +559,9 @@ __device__ __forceinline__ void load_z(const uint32_t *zkey, float (&z)[M]) {
 template <int M>
 __device__ __forceinline__ void op1_body(const DevState &st, int b) {
   const int i = b * kBlock + threadIdx.x;
+  // the generation counter advances here: k_vary of this generation has read it,
+  // and k_select (next launch) reads the advanced value to pick the planes
+  if (b == 0 && threadIdx.x == 0) st.gen[0] = st.gen[0] + 1u;
   if (i >= st.n) return;
   float z[M];
   load_z<M>(st.zkey, z);
@@ -643,15 +648,21 @@ __device__ __forceinline__ void sel_group_min(SelKey &best, int lps) {
 template <int M>
 __device__ __forceinline__ void select_body(const DevState &st, int L) {
   __shared__ int s_cnt;
-  __shared__ int s_dst[kBlock];
   __shared__ const float4 *s_srcrow[kBlock];
   const int p = L >= st.sel_blocks0 ? 1 : 0;
   const int lps = st.lps[p];
   const int g = threadIdx.x & (lps - 1);
-  const int j = (L - p * st.sel_blocks0) * (kBlock / lps) + threadIdx.x / lps;
+  const int per = kBlock / lps;  // slots of this block
+  const int j0 = (L - p * st.sel_blocks0) * per;
+  const int j = j0 + threadIdx.x / lps;
   if (threadIdx.x == 0) s_cnt = 0;
   __syncthreads();
   const bool live = j < st.n;
+  // k_op1 has advanced the counter to g + 1 for generation g: parents are in
+  // plane g & 1, the next population goes to plane (g + 1) & 1
+  const uint32_t gn = *st.gen;
+  const float *Xc = st.X[p] + static_cast<size_t>((gn + 1u) & 1u) * st.plane;
+  float *Xn = st.X[p] + static_cast<size_t>(gn & 1u) * st.plane;
   // keys carry i2 = 2 i + (OP1 source bit of i): the same order as i, and the
   // winner's row follows without another load
   SelKey best{__builtin_huge_valf(), __builtin_huge_valf(), 0x7FFFFFFF};
@@ -702,31 +713,29 @@ __device__ __forceinline__ void select_body(const DevState &st, int L) {
     const float pg = aggregate<M>(par, w, z, st.agg, st.theta);
     const bool win = best.i != 0x7FFFFFFF && (best.c < pc || (best.c == pc && best.g < pg));
     const int bi = best.i >> 1;
-    if (!win && g == 0 && st.win[p]) st.win[p][j] = -1;
+    if (!win && g == 0) {  // the parent stays
+      if (st.win[p]) st.win[p][j] = -1;
+      s_srcrow[j - j0] = reinterpret_cast<const float4 *>(Xc + static_cast<size_t>(j) * st.stride);
+    }
     if (win && mine.i == best.i) {  // the one lane that holds the winner
       if (st.win[p]) st.win[p][j] = bi;
       st.FC[p][j] = bestf;
       const int sp = p ^ (best.i & 1);
-      const int slot = atomicAdd(&s_cnt, 1);
-      s_dst[slot] = j;
-      s_srcrow[slot] = reinterpret_cast<const float4 *>(st.XO[sp] + static_cast<size_t>(bi) * st.stride);
+      atomicAdd(&s_cnt, 1);
+      s_srcrow[j - j0] = reinterpret_cast<const float4 *>(st.XO[sp] + static_cast<size_t>(bi) * st.stride);
     }
   }
   __syncthreads();
-  const int n = s_cnt;
-  if (n > 0) {
-    const int nq = st.stride >> 2;
-    float4 *base = reinterpret_cast<float4 *>(st.X[p]);
-    for (int f = threadIdx.x; f < n * nq; f += kBlock) {
-      const int r = f / nq, c = f - r * nq;
-      base[static_cast<size_t>(s_dst[r]) * nq + c] = s_srcrow[r][c];
-    }
-    if (threadIdx.x == 0) atomicAdd(&st.repl[p], static_cast<unsigned long long>(n));
+  // every row of the block's slots goes to the next plane: consecutive slots'
+  // rows are consecutive in memory, so the block writes whole cache lines
+  const int rows = min(per, st.n - j0);
+  const int nq = st.stride >> 2;
+  float4 *dst = reinterpret_cast<float4 *>(Xn + static_cast<size_t>(j0) * st.stride);
+  for (int f = threadIdx.x; f < rows * nq; f += kBlock) {
+    const int r = f / nq, c = f - r * nq;
+    dst[f] = s_srcrow[r][c];
   }
-  if (L == 0 && threadIdx.x == 0) {
-    // generations completed; next read by the following generation's k_vary
-    st.gen[0] = st.gen[0] + 1u;
-  }
+  if (threadIdx.x == 0 && s_cnt > 0) atomicAdd(&st.repl[p], static_cast<unsigned long long>(s_cnt));
 }
 
 template <int M>
@@ -829,7 +838,7 @@ __global__ __launch_bounds__(kBlock) void k_gather(DevState st, int pop, const i
   const int r = blockIdx.x;
   if (r >= count) return;
   const int row = idx[r];
-  const float *srcx = st.X[pop] + static_cast<size_t>(row) * st.stride;
+  const float *srcx = st.X[pop] + static_cast<size_t>(*st.gen & 1u) * st.plane + static_cast<size_t>(row) * st.stride;
   for (int l = threadIdx.x; l < st.d; l += blockDim.x) x[static_cast<size_t>(r) * st.d + l] = srcx[l];
   if (threadIdx.x == 0) fc[r] = st.FC[pop][row];
 }
