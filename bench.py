@@ -46,13 +46,15 @@ def bytes_model(n, m, d, t, rho):
       op1:    both offspring F/CV read (2 (m + 1)), weight (m), both new
               offspring F/CV written (2 (m + 1)) -- per subproblem
       select: parent F/CV (m + 1), weight (m), reverse list (t_p entries),
-              candidate F/CV once per offspring (m + 1); winners: offspring row
-              read + parent row write (2 d) and F/CV write (m + 1), times rho_p"""
+              candidate F/CV once per offspring (m + 1), the slot's replacement
+              record (1); winners' F/CV written (m + 1) times rho_p
+      rows:   winners' rows: offspring row read + slot row write (2 d), times rho_p"""
     vary = sum(n * 4 * (2 * d + (m + 1) + 2) for _ in range(2))
     op1 = n * 4 * (4 * (m + 1) + m)
-    select = sum(n * 4 * ((m + 1) + m + t[p] + (m + 1)) + rho[p] * n * 4 * (2 * d + (m + 1))
+    select = sum(n * 4 * ((m + 1) + m + t[p] + (m + 1) + 1) + rho[p] * n * 4 * (m + 1)
                  for p in range(2))
-    return {"vary": vary, "op1": op1, "select": select}
+    rows = sum(rho[p] * n * 4 * 2 * d for p in range(2))
+    return {"vary": vary, "op1": op1, "select": select, "rows": rows}
 
 
 def kernel_hash():

@@ -230,7 +230,8 @@ const char *gmpea_last_error(void);
 /* Run n_gen generations one launch at a time with HIP events recorded on the
  * handle's stream around every kernel, and return each kernel's mean duration in
  * milliseconds: ms[0] variation + evaluation + ideal point, ms[1] offspring
- * cooperation (OP1), ms[2] neighbour replacement (OP2 + OP3). The generations
+ * cooperation (OP1), ms[2] neighbour replacement decisions (OP2 + OP3), ms[3]
+ * the replaced rows' copies (ms holds 4 floats). The generations
  * are real (the state advances). Synchronises. */
 gmpea_status gmpea_profile(gmpea_t h, int32_t n_gen, float *ms);
 

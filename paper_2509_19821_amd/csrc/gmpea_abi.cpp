@@ -366,7 +366,6 @@ gmpea_status gmpea_init(const gmpea_problem *P, const gmpea_config *C, const gmp
   dp.g_scale = d > 1 ? static_cast<float>(9.0 / (d - 1)) : 0.0f;
 
   const size_t rows = static_cast<size_t>(st.nblk) * kBlock;
-  st.plane = static_cast<int64_t>(rows) * st.stride;
   float *lb = nullptr, *ub = nullptr, *inv_span = nullptr;
   int2 *d_offs = nullptr;
   uint32_t *d_flag = nullptr;
@@ -375,7 +374,8 @@ gmpea_status gmpea_init(const gmpea_problem *P, const gmpea_config *C, const gmp
     ub = c.take<float>(st.stride);
     inv_span = c.take<float>(st.stride);
     for (int p = 0; p < 2; ++p) {
-      st.X[p] = c.take<float>(2 * rows * st.stride);
+      st.X[p] = c.take<float>(rows * st.stride);
+      st.rsrc[p] = c.take<int32_t>(rows);
       st.XO[p] = c.take<float>(rows * st.stride);
       st.FC[p] = c.take<float4>(rows);
       st.FCO[p] = c.take<float4>(rows);
@@ -429,7 +429,7 @@ gmpea_status gmpea_init(const gmpea_problem *P, const gmpea_config *C, const gmp
   cp(d_offs, offs.data(), offs.size() * sizeof(int32_t));
   zero(d_flag, 0, 4 * sizeof(uint32_t));
   for (int p = 0; p < 2; ++p) {
-    zero(st.X[p], 0, 2 * rows * st.stride * sizeof(float));
+    zero(st.X[p], 0, rows * st.stride * sizeof(float));
     zero(st.XO[p], 0, rows * st.stride * sizeof(float));
     zero(st.FC[p], 0, rows * sizeof(float4));
     zero(st.FCO[p], 0, rows * sizeof(float4));
@@ -662,13 +662,7 @@ gmpea_status gmpea_read(gmpea_t h, int32_t buffer, int32_t pop, void *host, int6
     case GMPEA_BUF_X:
     case GMPEA_BUF_XOFF: {
       if (!need(n * d)) return fail(GMPEA_EINVAL, "gmpea_read: count must be N * d");
-      const float *src = st.XO[pop];
-      if (buffer == GMPEA_BUF_X) {
-        uint32_t g = 0;
-        gmpea_status s = d2h(h, &g, st.gen, 1, "gmpea_read");
-        if (s != GMPEA_OK) return s;
-        src = st.X[pop] + static_cast<size_t>(g & 1u) * st.plane;
-      }
+      const float *src = buffer == GMPEA_BUF_X ? st.X[pop] : st.XO[pop];
       hipError_t e = hipMemcpy2DAsync(host, d * sizeof(float), src, st.stride * sizeof(float),
                                       d * sizeof(float), n, hipMemcpyDeviceToHost, h->stream);
       if (e != hipSuccess) return hip_fail(e, "gmpea_read");
@@ -751,11 +745,7 @@ gmpea_status gmpea_write(gmpea_t h, int32_t buffer, int32_t pop, const void *hos
   switch (buffer) {
     case GMPEA_BUF_X: {
       if (count != n * d) return fail(GMPEA_EINVAL, "gmpea_write: count must be N * d");
-      uint32_t g = 0;
-      gmpea_status s = d2h(h, &g, st.gen, 1, "gmpea_write");
-      if (s != GMPEA_OK) return s;
-      hipError_t e = hipMemcpy2DAsync(st.X[pop] + static_cast<size_t>(g & 1u) * st.plane,
-                                      st.stride * sizeof(float), host, d * sizeof(float),
+      hipError_t e = hipMemcpy2DAsync(st.X[pop], st.stride * sizeof(float), host, d * sizeof(float),
                                       d * sizeof(float), n, hipMemcpyHostToDevice, h->stream);
       if (e != hipSuccess) return hip_fail(e, "gmpea_write");
       return sync(h, "gmpea_write");
@@ -790,19 +780,6 @@ gmpea_status gmpea_write(gmpea_t h, int32_t buffer, int32_t pop, const void *hos
       const int64_t g = *static_cast<const int64_t *>(host);
       if (g < 0 || g > 0xFFFFFFFFll) return fail(GMPEA_EINVAL, "gmpea_write: generation out of range");
       const uint32_t g32 = static_cast<uint32_t>(g);
-      uint32_t old = 0;
-      gmpea_status s = d2h(h, &old, st.gen, 1, "gmpea_write");
-      if (s != GMPEA_OK) return s;
-      if ((old & 1u) != (g32 & 1u)) {
-        // the population lives in plane gen & 1: move it along with the parity
-        for (int q = 0; q < 2; ++q) {
-          const float *from = st.X[q] + static_cast<size_t>(old & 1u) * st.plane;
-          float *to = st.X[q] + static_cast<size_t>(g32 & 1u) * st.plane;
-          hipError_t e = hipMemcpyAsync(to, from, st.plane * sizeof(float), hipMemcpyDeviceToDevice,
-                                        h->stream);
-          if (e != hipSuccess) return hip_fail(e, "gmpea_write");
-        }
-      }
       return h2d(h, st.gen, &g32, 1, "gmpea_write");
     }
     default:
@@ -826,7 +803,7 @@ gmpea_status gmpea_profile(gmpea_t h, int32_t n_gen, float *ms) {
   hipError_t e = hipSuccess;
   for (; made <= kPhases && e == hipSuccess; ++made) e = hipEventCreate(&ev[made]);
   if (e != hipSuccess) --made;
-  double acc[kPhases] = {0.0, 0.0, 0.0};
+  double acc[kPhases] = {0.0, 0.0, 0.0, 0.0};
   for (int32_t g = 0; g < n_gen && e == hipSuccess; ++g) {
     e = hipEventRecord(ev[0], h->stream);
     for (int ph = 0; ph < kPhases && e == hipSuccess; ++ph) {
@@ -908,9 +885,9 @@ struct gmpea_pool_s {
   // device tables
   DevState *d_states = nullptr;
   int32_t state_cap = 0;
-  int2 *d_work[kPhases] = {nullptr, nullptr, nullptr};
-  int32_t work_cap[kPhases] = {0, 0, 0};
-  int32_t nwork[kPhases] = {0, 0, 0};
+  int2 *d_work[kPhases] = {nullptr, nullptr, nullptr, nullptr};
+  int32_t work_cap[kPhases] = {0, 0, 0, 0};
+  int32_t nwork[kPhases] = {0, 0, 0, 0};
   bool dirty = true;
   // launch policy (the autotuner may change both; results do not depend on them)
   int32_t schedule = 0;  // 0: instance blocks grouped per XCD, 1: linear
@@ -1032,7 +1009,8 @@ gmpea_status pool_table(gmpea_pool_s *q, T **ptr, int32_t *cap, int32_t need) {
 int32_t phase_blocks(const DevState &st, int phase) {
   if (phase == 0) return vary_blocks_of(st.n, vary_lanes_of(st.stride));
   if (phase == 1) return st.nblk;
-  return st.sel_blocks0 + st.sel_blocks1;
+  if (phase == 2) return st.sel_blocks0 + st.sel_blocks1;
+  return rows_blocks_of(st.n, st.stride);
 }
 
 // Work list of one phase. Schedule 0 keeps each instance's consecutive blocks

@@ -43,10 +43,8 @@ struct DevState {
   int32_t sel_blocks0, sel_blocks1;  // k_select blocks of each population
   int32_t agg;
   float theta;
-  // X_p holds two planes of rows x stride floats: generation g's population in
-  // plane g & 1; replacement writes every row of the other plane.
   float *X[2], *XO[2];
-  int64_t plane;             // floats per plane
+  int32_t *rsrc[2];          // replacement of slot j: -1 kept, else (population << 30) | offspring row
   float4 *FC[2], *FCO[2], *FCN[2];
   float4 *W;                 // unit direction (PBI) or raw weight (Tchebycheff)
   const int32_t *B[2];       // n x t_p
@@ -59,8 +57,7 @@ struct DevState {
   uint8_t *src;              // OP1 switches: bit p set = population p took the other's offspring
                              // (also carried in the sign of FCN's CV, for k_select)
   uint32_t *zkey;            // ideal point as order-preserving keys (atomic min)
-  uint32_t *gen;             // generations completed (k_op1 advances it: from then on
-                             // it names the generation being finished)
+  uint32_t *gen;             // generations completed (k_op1 advances it once k_vary has read it)
   unsigned long long *repl;  // replaced-slot counters per population
   int32_t *mate[2];          // optional record of parent rows (n x 2)
   int32_t *win[2];           // optional record of winners (n)
@@ -92,8 +89,13 @@ __host__ __device__ inline int vary_blocks_of(int n, int lanes) {
 // Launchers (gmpea_kernels.hip). Each enqueues on `s` and returns the launch status.
 hipError_t launch_init(const DevState &st, hipStream_t s);
 // A generation is kPhases launches: 0 variation + evaluation + ideal point,
-// 1 offspring cooperation, 2 neighbour replacement.
-constexpr int kPhases = 3;
+// 1 offspring cooperation, 2 neighbour replacement decisions, 3 row copies.
+constexpr int kPhases = 4;
+// k_rows blocks of one instance (float4 elements of both populations' rows).
+__host__ __device__ inline int rows_blocks_of(int n, int stride) {
+  const long long e = 2LL * n * (stride >> 2);
+  return static_cast<int>((e + kBlock - 1) / kBlock);
+}
 hipError_t launch_phase(const DevState &st, int phase, hipStream_t s);
 hipError_t launch_generation(const DevState &st, hipStream_t s);
 // One phase of a batched generation over a pool: work[b] = (instance, block).

@@ -228,7 +228,7 @@ __global__ __launch_bounds__(kBlock) void k_init(DevState st) {
 #pragma unroll
   for (int k = 0; k < M; ++k) zv[k] = __builtin_huge_valf();
   if (i < st.n) {
-    float *row = st.X[p] + static_cast<size_t>(i) * st.stride;  // plane 0: generation 0
+    float *row = st.X[p] + static_cast<size_t>(i) * st.stride;
     EvalAcc e{0.0f, 0.0f, 0.0f};
     uint4 w = make_uint4(0, 0, 0, 0);
     for (int l = 0; l < st.stride; ++l) {
@@ -422,10 +422,9 @@ __device__ __forceinline__ void vary_body(const DevState &st, int L, int G) {
   const int p = L >= half ? 1 : 0;
   const int g = threadIdx.x & (LPO - 1);
   const int i = (L - p * half) * kPer + threadIdx.x / LPO;
-  const uint32_t gk = *st.gen;
-  const uint32_t k = gk + 1u;
+  const uint32_t k = *st.gen + 1u;
   const uint32_t tagp = (p << 16);
-  const float *Xc = st.X[p] + static_cast<size_t>(gk & 1u) * st.plane;
+  const float *Xc = st.X[p];
   float zv[M];
 #pragma unroll
   for (int q = 0; q < M; ++q) zv[q] = __builtin_huge_valf();
@@ -559,8 +558,7 @@ __device__ __forceinline__ void load_z(const uint32_t *zkey, float (&z)[M]) {
 template <int M>
 __device__ __forceinline__ void op1_body(const DevState &st, int b) {
   const int i = b * kBlock + threadIdx.x;
-  // the generation counter advances here: k_vary of this generation has read it,
-  // and k_select (next launch) reads the advanced value to pick the planes
+  // the generation counter advances here, once k_vary of this generation has read it
   if (b == 0 && threadIdx.x == 0) st.gen[0] = st.gen[0] + 1u;
   if (i >= st.n) return;
   float z[M];
@@ -648,21 +646,13 @@ __device__ __forceinline__ void sel_group_min(SelKey &best, int lps) {
 template <int M>
 __device__ __forceinline__ void select_body(const DevState &st, int L) {
   __shared__ int s_cnt;
-  __shared__ const float4 *s_srcrow[kBlock];
   const int p = L >= st.sel_blocks0 ? 1 : 0;
   const int lps = st.lps[p];
   const int g = threadIdx.x & (lps - 1);
-  const int per = kBlock / lps;  // slots of this block
-  const int j0 = (L - p * st.sel_blocks0) * per;
-  const int j = j0 + threadIdx.x / lps;
+  const int j = (L - p * st.sel_blocks0) * (kBlock / lps) + threadIdx.x / lps;
   if (threadIdx.x == 0) s_cnt = 0;
   __syncthreads();
   const bool live = j < st.n;
-  // k_op1 has advanced the counter to g + 1 for generation g: parents are in
-  // plane g & 1, the next population goes to plane (g + 1) & 1
-  const uint32_t gn = *st.gen;
-  const float *Xc = st.X[p] + static_cast<size_t>((gn + 1u) & 1u) * st.plane;
-  float *Xn = st.X[p] + static_cast<size_t>(gn & 1u) * st.plane;
   // keys carry i2 = 2 i + (OP1 source bit of i): the same order as i, and the
   // winner's row follows without another load
   SelKey best{__builtin_huge_valf(), __builtin_huge_valf(), 0x7FFFFFFF};
@@ -715,27 +705,60 @@ __device__ __forceinline__ void select_body(const DevState &st, int L) {
     const int bi = best.i >> 1;
     if (!win && g == 0) {  // the parent stays
       if (st.win[p]) st.win[p][j] = -1;
-      s_srcrow[j - j0] = reinterpret_cast<const float4 *>(Xc + static_cast<size_t>(j) * st.stride);
+      st.rsrc[p][j] = -1;
     }
     if (win && mine.i == best.i) {  // the one lane that holds the winner
       if (st.win[p]) st.win[p][j] = bi;
       st.FC[p][j] = bestf;
-      const int sp = p ^ (best.i & 1);
+      st.rsrc[p][j] = ((p ^ (best.i & 1)) << 30) | bi;
       atomicAdd(&s_cnt, 1);
-      s_srcrow[j - j0] = reinterpret_cast<const float4 *>(st.XO[sp] + static_cast<size_t>(bi) * st.stride);
     }
   }
   __syncthreads();
-  // every row of the block's slots goes to the next plane: consecutive slots'
-  // rows are consecutive in memory, so the block writes whole cache lines
-  const int rows = min(per, st.n - j0);
-  const int nq = st.stride >> 2;
-  float4 *dst = reinterpret_cast<float4 *>(Xn + static_cast<size_t>(j0) * st.stride);
-  for (int f = threadIdx.x; f < rows * nq; f += kBlock) {
-    const int r = f / nq, c = f - r * nq;
-    dst[f] = s_srcrow[r][c];
-  }
   if (threadIdx.x == 0 && s_cnt > 0) atomicAdd(&st.repl[p], static_cast<unsigned long long>(s_cnt));
+}
+
+// ----------------------------------------------------------------------------
+// k_rows: the row copies of the replacement, one float4 of a population row per
+// thread, streaming over both populations. A replaced slot takes its winning
+// offspring row. Rows are not aligned to 128-byte lines, so a line may hold
+// parts of a replaced row and of a kept one; the kept bytes of such a line are
+// written back unchanged, so that no line leaves the L2 partially written (a
+// partial line costs a read-modify-write at the memory). All reads of X for the
+// generation happened in earlier launches, and no kept byte changes value.
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ void rows_body(const DevState &st, int64_t e) {
+  const int nq = st.stride >> 2;
+  const int64_t per_pop = static_cast<int64_t>(st.n) * nq;
+  if (e >= 2 * per_pop) return;
+  const int p = e >= per_pop ? 1 : 0;
+  const int64_t el = e - p * per_pop;
+  const int r = static_cast<int>(el / nq);
+  const int c = static_cast<int>(el - static_cast<int64_t>(r) * nq);
+  const int32_t *rs = st.rsrc[p];
+  float4 *x = reinterpret_cast<float4 *>(st.X[p] + static_cast<size_t>(r) * st.stride) + c;
+  const int32_t ds = rs[r];
+  if (ds >= 0) {
+    const float *src = st.XO[ds >> 30] + static_cast<size_t>(ds & 0x3FFFFFFF) * st.stride;
+    *x = reinterpret_cast<const float4 *>(src)[c];
+    return;
+  }
+  // kept row: is another row of this element's 128-byte line replaced?
+  const int64_t f0 = (static_cast<int64_t>(r) * st.stride + 4 * c) & ~static_cast<int64_t>(31);
+  const int r0 = static_cast<int>(f0 / st.stride);
+  const int r1 = min(st.n - 1, static_cast<int>((f0 + 31) / st.stride));
+  bool mixed = false;
+  for (int q = r0; q <= r1; ++q) mixed = mixed || (q != r && rs[q] >= 0);
+  if (mixed) {
+    float4 v = *x;
+    // an opaque register use keeps the compiler from dropping the rewrite
+    asm volatile("" : "+v"(v.x), "+v"(v.y), "+v"(v.z), "+v"(v.w));
+    *x = v;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_rows(DevState st) {
+  rows_body(st, static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x);
 }
 
 template <int M>
@@ -795,6 +818,13 @@ __global__ __launch_bounds__(kBlock) void k_select_batch(const DevState *__restr
     select_body<3>(st, wi.y);
 }
 
+__global__ __launch_bounds__(kBlock) void k_rows_batch(const DevState *__restrict__ S,
+                                                      const int2 *__restrict__ work) {
+  const int2 wi = work[blockIdx.x];
+  if (wi.x < 0) return;
+  rows_body(S[wi.x], static_cast<int64_t>(wi.y) * kBlock + threadIdx.x);
+}
+
 // ----------------------------------------------------------------------------
 // Front: feasible rows of population `pop` that no feasible row dominates
 // (Eq. (5)); candidates staged through LDS tiles.
@@ -838,7 +868,7 @@ __global__ __launch_bounds__(kBlock) void k_gather(DevState st, int pop, const i
   const int r = blockIdx.x;
   if (r >= count) return;
   const int row = idx[r];
-  const float *srcx = st.X[pop] + static_cast<size_t>(*st.gen & 1u) * st.plane + static_cast<size_t>(row) * st.stride;
+  const float *srcx = st.X[pop] + static_cast<size_t>(row) * st.stride;
   for (int l = threadIdx.x; l < st.d; l += blockDim.x) x[static_cast<size_t>(r) * st.d + l] = srcx[l];
   if (threadIdx.x == 0) fc[r] = st.FC[pop][row];
 }
@@ -939,8 +969,10 @@ hipError_t launch_phase(const DevState &st, int phase, hipStream_t s) {
     }
   } else if (phase == 1) {
     GMPEA_DISPATCH_M(k_op1, st.nblk, s, st);
-  } else {
+  } else if (phase == 2) {
     GMPEA_DISPATCH_M(k_select, st.sel_blocks0 + st.sel_blocks1, s, st);
+  } else {
+    hipLaunchKernelGGL(k_rows, dim3(rows_blocks_of(st.n, st.stride)), dim3(kBlock), 0, s, st);
   }
   return hipGetLastError();
 }
@@ -952,8 +984,10 @@ hipError_t launch_batch_phase(const DevState *states, const int2 *work, int nwor
     hipLaunchKernelGGL(k_vary_batch, dim3(nwork), dim3(kBlock), 0, s, states, work);
   else if (phase == 1)
     hipLaunchKernelGGL(k_op1_batch, dim3(nwork), dim3(kBlock), 0, s, states, work);
-  else
+  else if (phase == 2)
     hipLaunchKernelGGL(k_select_batch, dim3(nwork), dim3(kBlock), 0, s, states, work);
+  else
+    hipLaunchKernelGGL(k_rows_batch, dim3(nwork), dim3(kBlock), 0, s, states, work);
   return hipGetLastError();
 }
 

@@ -35,7 +35,7 @@ EXPORTS = ["gmpea_init", "gmpea_step", "gmpea_run", "gmpea_front", "gmpea_get_in
            "gmpea_philox", "gmpea_copy", "gmpea_pool_create", "gmpea_pool_admit",
            "gmpea_pool_step", "gmpea_pool_tune", "gmpea_pool_handle", "gmpea_pool_release",
            "gmpea_pool_query", "gmpea_pool_sync", "gmpea_pool_destroy", "gmpea_lattice"]
-PHASES = ("vary", "op1", "select")
+PHASES = ("vary", "op1", "select", "rows")
 
 
 class GmpeaError(RuntimeError):
@@ -289,7 +289,7 @@ class Gmpea:
     def profile(self, n_gen: int) -> dict:
         """Mean per-kernel durations (ms) over n_gen generations, HIP events on
         the handle's stream."""
-        ms = np.zeros(3, dtype=np.float32)
+        ms = np.zeros(len(PHASES), dtype=np.float32)  # the library writes one mean per phase
         _check(lib().gmpea_profile(self._h, int(n_gen), ms.ctypes.data))
         return dict(zip(PHASES, (float(v) for v in ms)))
 
