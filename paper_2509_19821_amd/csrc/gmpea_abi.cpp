@@ -390,7 +390,7 @@ gmpea_status gmpea_init(const gmpea_problem *P, const gmpea_config *C, const gmp
     st.src = c.take<uint8_t>(rows);
     st.zkey = c.take<uint32_t>(4);
     st.gen = c.take<uint32_t>(4);
-    st.repl = c.take<unsigned long long>(2);
+    st.repl = c.take<unsigned long long>(2 * kReplLanes);
     d_offs = c.take<int2>(noffs);
     d_flag = c.take<uint32_t>(4);
   };
@@ -444,7 +444,7 @@ gmpea_status gmpea_init(const gmpea_problem *P, const gmpea_config *C, const gmp
   zero(st.src, 0, rows);
   zero(st.zkey, 0xFF, 4 * sizeof(uint32_t));
   zero(st.gen, 0, 4 * sizeof(uint32_t));
-  zero(st.repl, 0, 2 * sizeof(unsigned long long));
+  zero(st.repl, 0, 2 * kReplLanes * sizeof(unsigned long long));
   // reference vectors and neighbourhoods on the device
   if (e == hipSuccess)
     e = launch_tables(m, N, H, d_offs, noffs, t1, t2, C->agg, st.W, const_cast<int32_t *>(st.B[0]),
@@ -627,11 +627,11 @@ gmpea_status gmpea_get_info(gmpea_t h, gmpea_info *info) {
   if (!info) return fail(GMPEA_EINVAL, "gmpea_get_info: info is NULL");
   const DevState &st = h->st;
   uint32_t gen = 0, zk[4];
-  unsigned long long rep[2];
+  unsigned long long rep[2 * kReplLanes];
   std::vector<float4> fc(st.n);
   gmpea_status s = d2h(h, &gen, st.gen, 1, "gmpea_get_info");
   if (s == GMPEA_OK) s = d2h(h, zk, st.zkey, 4, "gmpea_get_info");
-  if (s == GMPEA_OK) s = d2h(h, rep, st.repl, 2, "gmpea_get_info");
+  if (s == GMPEA_OK) s = d2h(h, rep, st.repl, 2 * kReplLanes, "gmpea_get_info");
   if (s == GMPEA_OK) s = d2h(h, fc.data(), st.FC[0], st.n, "gmpea_get_info");
   if (s != GMPEA_OK) return s;
   info->n = st.n;
@@ -642,8 +642,11 @@ gmpea_status gmpea_get_info(gmpea_t h, gmpea_info *info) {
   info->H = h->H;
   info->generation = gen;
   for (int a = 0; a < GMPEA_MAX_M; ++a) info->z[a] = a < st.m ? key_float(zk[a]) : 0.0f;
-  info->replaced[0] = static_cast<int64_t>(rep[0]);
-  info->replaced[1] = static_cast<int64_t>(rep[1]);
+  for (int p = 0; p < 2; ++p) {
+    unsigned long long tot = 0;
+    for (int q = 0; q < kReplLanes; ++q) tot += rep[p * kReplLanes + q];
+    info->replaced[p] = static_cast<int64_t>(tot);
+  }
   int64_t feas = 0;
   for (int32_t i = 0; i < st.n; ++i) feas += fc[i].w == 0.0f;
   info->feasible_frac = static_cast<double>(feas) / st.n;

@@ -15,6 +15,9 @@ namespace gmpea {
 constexpr int kMaxM = 3;
 constexpr int kMaxRing = 8;
 constexpr int kBlock = 256;  // threads per block of the per-subproblem kernels
+// Replacement counters are spread over this many words per population: one
+// word updated by every block serialises those atomics at one L2 channel.
+constexpr int kReplLanes = 64;
 
 // Stream tags of the counter RNG (top byte of counter word 3).
 constexpr uint32_t kTagInit = 1u;
@@ -58,7 +61,7 @@ struct DevState {
                              // (also carried in the sign of FCN's CV, for k_select)
   uint32_t *zkey;            // ideal point as order-preserving keys (atomic min)
   uint32_t *gen;             // generations completed (k_op1 advances it once k_vary has read it)
-  unsigned long long *repl;  // replaced-slot counters per population
+  unsigned long long *repl;  // replaced-slot counters: kReplLanes per population, summed on read
   int32_t *mate[2];          // optional record of parent rows (n x 2)
   int32_t *win[2];           // optional record of winners (n)
   uint32_t key0, key1;       // RNG key

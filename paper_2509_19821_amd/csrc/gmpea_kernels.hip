@@ -715,7 +715,8 @@ __device__ __forceinline__ void select_body(const DevState &st, int L) {
     }
   }
   __syncthreads();
-  if (threadIdx.x == 0 && s_cnt > 0) atomicAdd(&st.repl[p], static_cast<unsigned long long>(s_cnt));
+  if (threadIdx.x == 0 && s_cnt > 0)
+    atomicAdd(&st.repl[p * kReplLanes + (L & (kReplLanes - 1))], static_cast<unsigned long long>(s_cnt));
 }
 
 // ----------------------------------------------------------------------------
