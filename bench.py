@@ -213,6 +213,7 @@ def main():
     n, m, d = gp.n, gp.m, gp.d
 
     gp.step(args.warmup)
+    gp.step(0)  # capture the replay graph outside the timed region (no generations)
     gp.sync()
     log("bench: warmup done")
     r0 = gp.info()["replaced"]

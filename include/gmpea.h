@@ -186,7 +186,10 @@ gmpea_status gmpea_init(const gmpea_problem *problem, const gmpea_config *config
                         const gmpea_allocator *allocator, void *hip_stream, gmpea_t *out);
 
 /* Enqueue n_gen generations (Alg. 1 loop body) on the handle's stream and
- * return without waiting. n_gen = 0 is a no-op. Errors: EINVAL (n_gen < 0), EHIP. */
+ * return without waiting. Runs of 64 generations replay one captured hipGraph
+ * (the environment variable GMPEA_GRAPH_CHUNK sets another length, below 2 none);
+ * n_gen = 0 launches nothing but captures that graph ahead of time, so a timed
+ * region need not include the capture. Errors: EINVAL (n_gen < 0), EHIP. */
 gmpea_status gmpea_step(gmpea_t h, int32_t n_gen);
 
 /* Run up to max_gen generations, stopping at the first generation boundary at

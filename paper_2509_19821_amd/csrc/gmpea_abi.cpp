@@ -51,7 +51,7 @@ struct gmpea_s {
   // graph replay of `gchunk` generations
   hipGraphExec_t gexec = nullptr;
   int32_t gchunk = 0;
-  int32_t graph_chunk_cfg = 16;
+  int32_t graph_chunk_cfg = 64;
 };
 
 namespace {
@@ -208,6 +208,7 @@ gmpea_status build_graph(gmpea_s *h, int32_t chunk) {
 
 gmpea_status enqueue(gmpea_s *h, int32_t n) {
   const int32_t G = h->graph_chunk_cfg;
+  if (n == 0 && G >= 2) return build_graph(h, G);  // prepare the replay, launch nothing
   if (G >= 2 && n >= G) {
     gmpea_status s = build_graph(h, G);
     if (s != GMPEA_OK) return s;
