@@ -79,28 +79,39 @@ __device__ __forceinline__ float powpos(float x, float e) {
 // ----------------------------------------------------------------------------
 __device__ __forceinline__ float pm1(float c, uint32_t wB, float lo, float hi, float inv_span,
                                      const DevState &st) {
+  // u = wB / tpm. Every coefficient of the mutation step (2u, 1 - 2u, 2(1 - u),
+  // 2(u - 1/2)) comes from an exact integer numerator over tpm, and 1 - delta
+  // from the distance to the far bound: in FP32, 1 - u itself cancels
+  // catastrophically as u -> 1 and val^(1/(eta+1)) magnifies that error. Both
+  // halves of the mutation share one pair of powers (selects, no branch), so a
+  // wave whose lanes fall in different halves evaluates them once.
+  if (st.tpm <= 0x80000000ull) {
+    // pm <= 1/2: every numerator fits 32 bits
+    const uint32_t T = static_cast<uint32_t>(st.tpm);
+    if (wB < T) {
+      const bool low = 2u * wB < T;  // u < 1/2
+      const uint32_t na = low ? 2u * wB : 2u * (T - wB);
+      const uint32_t nb = low ? T - 2u * wB : 2u * wB - T;
+      const float a = static_cast<float>(na) * st.inv_tpm;
+      const float b = static_cast<float>(nb) * st.inv_tpm;
+      const float xy = (low ? (hi - c) : (c - lo)) * inv_span;
+      const float t = powpos(a + b * powpos(xy, st.pm_p), st.pm_e);
+      const float dq = low ? t - 1.0f : 1.0f - t;
+      c = fminf(fmaxf(c + dq * (hi - lo), lo), hi);
+    }
+    return c;
+  }
   const uint64_t w = wB;
   if (w < st.tpm) {
-    // u = wB / tpm. Every coefficient of the mutation step (2u, 1 - 2u, 2(1 - u),
-    // 2(u - 1/2)) comes from an exact integer numerator over tpm, and 1 - delta
-    // from the distance to the far bound: in FP32, 1 - u itself cancels
-    // catastrophically as u -> 1 and val^(1/(eta+1)) magnifies that error.
-    const float span = hi - lo;
-    float dq;
-    if (2u * w < st.tpm) {
-      const float u2 = static_cast<float>(2u * w) * st.inv_tpm;
-      const float om = static_cast<float>(st.tpm - 2u * w) * st.inv_tpm;
-      const float xy = (hi - c) * inv_span;
-      const float val = u2 + om * powpos(xy, st.pm_p);
-      dq = powpos(val, st.pm_e) - 1.0f;
-    } else {
-      const float a2 = static_cast<float>(2u * (st.tpm - w)) * st.inv_tpm;
-      const float b2 = static_cast<float>(2u * w - st.tpm) * st.inv_tpm;
-      const float xy = (c - lo) * inv_span;
-      const float val = a2 + b2 * powpos(xy, st.pm_p);
-      dq = 1.0f - powpos(val, st.pm_e);
-    }
-    c = fminf(fmaxf(c + dq * span, lo), hi);
+    const bool low = 2u * w < st.tpm;
+    const uint64_t na = low ? 2u * w : 2u * (st.tpm - w);
+    const uint64_t nb = low ? st.tpm - 2u * w : 2u * w - st.tpm;
+    const float a = static_cast<float>(na) * st.inv_tpm;
+    const float b = static_cast<float>(nb) * st.inv_tpm;
+    const float xy = (low ? (hi - c) : (c - lo)) * inv_span;
+    const float t = powpos(a + b * powpos(xy, st.pm_p), st.pm_e);
+    const float dq = low ? t - 1.0f : 1.0f - t;
+    c = fminf(fmaxf(c + dq * (hi - lo), lo), hi);
   }
   return c;
 }
@@ -110,8 +121,9 @@ __device__ __forceinline__ float vary1(float a, float b, uint32_t wA, uint32_t w
   float c = a;
   if (cross && (wA & 1u)) {
     const float u = u24(wA);
-    float beta = (u <= 0.5f) ? powpos(2.0f * u, st.sbx_e) : powpos(2.0f * (1.0f - u), -st.sbx_e);
-    if (wA & 2u) beta = -beta;
+    const bool low = u <= 0.5f;  // one power for both halves of the spread
+    const float beta0 = powpos(low ? 2.0f * u : 2.0f * (1.0f - u), low ? st.sbx_e : -st.sbx_e);
+    const float beta = (wA & 2u) ? -beta0 : beta0;
     c = 0.5f * ((a + b) + beta * (a - b));
   }
   c = fminf(fmaxf(c, lo), hi);
