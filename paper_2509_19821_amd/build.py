@@ -27,7 +27,10 @@ def flags() -> list:
     return ["--offload-arch=" + ARCH, "-O3", "-fPIC", "-std=c++17", "-Wall",
             "-I" + os.path.join(ROOT, "include"), "-I" + CSRC,
             # keep packed-FP32 instructions out of the generated code
-            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            # no implicit multiply-add fusion: the kernels write fmaf where they
+            # want one, so results do not depend on the inlining context
+            "-ffp-contract=off"]
 
 
 def build(verbose: bool = False, jobs: int = 3) -> str:

@@ -25,6 +25,11 @@
 
 #include "gmpea_internal.hpp"
 
+// Floating-point contraction is off for this file (build flag -ffp-contract=off)
+// and every fused multiply-add is written out as fmaf: the compiler may not
+// fuse an expression in one kernel and leave it unfused in another, so a device
+// function gives bitwise-equal results in the plain and the batched kernels.
+
 namespace gmpea {
 
 // ----------------------------------------------------------------------------
@@ -95,9 +100,9 @@ __device__ __forceinline__ float pm1(float c, uint32_t wB, float lo, float hi, f
       const float a = static_cast<float>(na) * st.inv_tpm;
       const float b = static_cast<float>(nb) * st.inv_tpm;
       const float xy = (low ? (hi - c) : (c - lo)) * inv_span;
-      const float t = powpos(a + b * powpos(xy, st.pm_p), st.pm_e);
+      const float t = powpos(fmaf(b, powpos(xy, st.pm_p), a), st.pm_e);
       const float dq = low ? t - 1.0f : 1.0f - t;
-      c = fminf(fmaxf(c + dq * (hi - lo), lo), hi);
+      c = fminf(fmaxf(fmaf(dq, hi - lo, c), lo), hi);
     }
     return c;
   }
@@ -109,9 +114,9 @@ __device__ __forceinline__ float pm1(float c, uint32_t wB, float lo, float hi, f
     const float a = static_cast<float>(na) * st.inv_tpm;
     const float b = static_cast<float>(nb) * st.inv_tpm;
     const float xy = (low ? (hi - c) : (c - lo)) * inv_span;
-    const float t = powpos(a + b * powpos(xy, st.pm_p), st.pm_e);
+    const float t = powpos(fmaf(b, powpos(xy, st.pm_p), a), st.pm_e);
     const float dq = low ? t - 1.0f : 1.0f - t;
-    c = fminf(fmaxf(c + dq * (hi - lo), lo), hi);
+    c = fminf(fmaxf(fmaf(dq, hi - lo, c), lo), hi);
   }
   return c;
 }
@@ -124,7 +129,7 @@ __device__ __forceinline__ float vary1(float a, float b, uint32_t wA, uint32_t w
     const bool low = u <= 0.5f;  // one power for both halves of the spread
     const float beta0 = powpos(low ? 2.0f * u : 2.0f * (1.0f - u), low ? st.sbx_e : -st.sbx_e);
     const float beta = (wA & 2u) ? -beta0 : beta0;
-    c = 0.5f * ((a + b) + beta * (a - b));
+    c = 0.5f * fmaf(beta, a - b, a + b);
   }
   c = fminf(fmaxf(c, lo), hi);
   return pm1(c, wB, lo, hi, inv_span, st);
@@ -132,7 +137,7 @@ __device__ __forceinline__ float vary1(float a, float b, uint32_t wA, uint32_t w
 
 __device__ __forceinline__ float vary1_de(float x, float a, float b, uint32_t wB, float lo, float hi,
                                           float inv_span, const DevState &st) {
-  const float c = fminf(fmaxf(x + st.de_f * (a - b), lo), hi);
+  const float c = fminf(fmaxf(fmaf(st.de_f, a - b, x), lo), hi);
   return pm1(c, wB, lo, hi, inv_span, st);
 }
 
@@ -149,7 +154,7 @@ __device__ __forceinline__ void eval_add(EvalAcc &e, int l, float x) {
   if (FAM == 0) {
     if (l >= 1) e.s += x;
   } else {
-    if (l >= M - 1) e.s += (x - 0.5f) * (x - 0.5f);
+    if (l >= M - 1) e.s = fmaf(x - 0.5f, x - 0.5f, e.s);
   }
 }
 
@@ -158,7 +163,7 @@ template <int M, int FAM>
 __device__ __forceinline__ float4 eval_finish(const EvalAcc &e, const DevProblem &P) {
   float f[3] = {0.0f, 0.0f, 0.0f};
   if (FAM == 0) {
-    const float g = 1.0f + P.g_scale * e.s;
+    const float g = fmaf(P.g_scale, e.s, 1.0f);
     f[0] = e.x0;
     f[1] = g * (1.0f - sqrtf(e.x0 / g));
   } else {
@@ -182,7 +187,7 @@ __device__ __forceinline__ float4 eval_finish(const EvalAcc &e, const DevProblem
 #pragma unroll
     for (int k = 0; k < M; ++k) {
       const float df = f[k] - P.ring_c[j * M + k];
-      q += df * df;
+      q = fmaf(df, df, q);
     }
     const float c = P.ring_r2[j] - q;
     cv += (c > 0.0f) ? c : 0.0f;
@@ -250,7 +255,7 @@ __global__ __launch_bounds__(kBlock) void k_init(DevState st) {
           w = philox10(make_uint4(l >> 2, i, 0u, (kTagInit << 24) | (p << 16)), st.key0, st.key1);
         const uint32_t word = (l & 3) == 0 ? w.x : (l & 3) == 1 ? w.y : (l & 3) == 2 ? w.z : w.w;
         const float lo = st.prob.lb[l], hi = st.prob.ub[l];
-        x = lo + (hi - lo) * u24(word);
+        x = fmaf(hi - lo, u24(word), lo);
         eval_add<M, FAM>(e, l, x);
       }
       row[l] = x;
@@ -541,13 +546,13 @@ __device__ __forceinline__ float aggregate(float4 f, float4 w, const float (&z)[
   } else {
     float dot = 0.0f;
 #pragma unroll
-    for (int k = 0; k < M; ++k) dot += df[k] * ww[k];
+    for (int k = 0; k < M; ++k) dot = fmaf(df[k], ww[k], dot);
     const float d1 = fabsf(dot);
     float d2 = 0.0f;
 #pragma unroll
     for (int k = 0; k < M; ++k) {
       const float e = df[k] - d1 * ww[k];
-      d2 += e * e;
+      d2 = fmaf(e, e, d2);
     }
     g = d1 + theta * sqrtf(d2);
   }
