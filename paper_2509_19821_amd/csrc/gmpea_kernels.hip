@@ -738,12 +738,11 @@ __device__ __forceinline__ void select_body(const DevState &st, int L) {
 
 // ----------------------------------------------------------------------------
 // k_rows: the row copies of the replacement, one float4 of a population row per
-// thread, streaming over both populations. A replaced slot takes its winning
-// offspring row. Rows are not aligned to 128-byte lines, so a line may hold
-// parts of a replaced row and of a kept one; the kept bytes of such a line are
-// written back unchanged, so that no line leaves the L2 partially written (a
-// partial line costs a read-modify-write at the memory). All reads of X for the
-// generation happened in earlier launches, and no kept byte changes value.
+// thread, streaming over both populations in place: a replaced slot takes its
+// winning offspring row. All reads of X for the generation happened in earlier
+// launches. (Rows are not aligned to 128-byte lines; writing the kept bytes of
+// shared lines back as well, so that no line is left partially written, was
+// measured slower: partial lines cost nothing extra here.)
 // ----------------------------------------------------------------------------
 __device__ __forceinline__ void rows_body(const DevState &st, int64_t e) {
   const int nq = st.stride >> 2;
@@ -753,26 +752,11 @@ __device__ __forceinline__ void rows_body(const DevState &st, int64_t e) {
   const int64_t el = e - p * per_pop;
   const int r = static_cast<int>(el / nq);
   const int c = static_cast<int>(el - static_cast<int64_t>(r) * nq);
-  const int32_t *rs = st.rsrc[p];
-  float4 *x = reinterpret_cast<float4 *>(st.X[p] + static_cast<size_t>(r) * st.stride) + c;
-  const int32_t ds = rs[r];
-  if (ds >= 0) {
-    const float *src = st.XO[ds >> 30] + static_cast<size_t>(ds & 0x3FFFFFFF) * st.stride;
-    *x = reinterpret_cast<const float4 *>(src)[c];
-    return;
-  }
-  // kept row: is another row of this element's 128-byte line replaced?
-  const int64_t f0 = (static_cast<int64_t>(r) * st.stride + 4 * c) & ~static_cast<int64_t>(31);
-  const int r0 = static_cast<int>(f0 / st.stride);
-  const int r1 = min(st.n - 1, static_cast<int>((f0 + 31) / st.stride));
-  bool mixed = false;
-  for (int q = r0; q <= r1; ++q) mixed = mixed || (q != r && rs[q] >= 0);
-  if (mixed) {
-    float4 v = *x;
-    // an opaque register use keeps the compiler from dropping the rewrite
-    asm volatile("" : "+v"(v.x), "+v"(v.y), "+v"(v.z), "+v"(v.w));
-    *x = v;
-  }
+  const int32_t ds = st.rsrc[p][r];
+  if (ds < 0) return;
+  const float *src = st.XO[ds >> 30] + static_cast<size_t>(ds & 0x3FFFFFFF) * st.stride;
+  reinterpret_cast<float4 *>(st.X[p] + static_cast<size_t>(r) * st.stride)[c] =
+      reinterpret_cast<const float4 *>(src)[c];
 }
 
 __global__ __launch_bounds__(kBlock) void k_rows(DevState st) {
