@@ -82,47 +82,37 @@ __device__ __forceinline__ float powpos(float x, float e) {
 // wB < tpm, then SBX (one child kept; per-variable crossing bit, sign bit,
 // 24-bit uniform) or DE (x + F (a - b), every variable) in front of it.
 // ----------------------------------------------------------------------------
-__device__ __forceinline__ float pm1(float c, uint32_t wB, float lo, float hi, float inv_span,
-                                     const DevState &st) {
-  // u = wB / tpm. Every coefficient of the mutation step (2u, 1 - 2u, 2(1 - u),
-  // 2(u - 1/2)) comes from an exact integer numerator over tpm, and 1 - delta
-  // from the distance to the far bound: in FP32, 1 - u itself cancels
-  // catastrophically as u -> 1 and val^(1/(eta+1)) magnifies that error. Both
-  // halves of the mutation share one pair of powers (selects, no branch), so a
-  // wave whose lanes fall in different halves evaluates them once.
-  if (st.tpm <= 0x80000000ull) {
-    // pm <= 1/2: every numerator fits 32 bits
-    const uint32_t T = static_cast<uint32_t>(st.tpm);
-    if (wB < T) {
-      const bool low = 2u * wB < T;  // u < 1/2
-      const uint32_t na = low ? 2u * wB : 2u * (T - wB);
-      const uint32_t nb = low ? T - 2u * wB : 2u * wB - T;
-      const float a = static_cast<float>(na) * st.inv_tpm;
-      const float b = static_cast<float>(nb) * st.inv_tpm;
-      const float xy = (low ? (hi - c) : (c - lo)) * inv_span;
-      const float t = powpos(fmaf(b, powpos(xy, st.pm_p), a), st.pm_e);
-      const float dq = low ? t - 1.0f : 1.0f - t;
-      c = fminf(fmaxf(fmaf(dq, hi - lo, c), lo), hi);
-    }
-    return c;
+__device__ __forceinline__ float pm1(float c, uint32_t w, uint64_t T, float invT, float lo, float hi,
+                                     float inv_span, const DevState &st) {
+  // Called with w < T: u = w / T. Every coefficient of the mutation step (2u,
+  // 1 - 2u, 2(1 - u), 2(u - 1/2)) comes from an exact integer numerator over T,
+  // and 1 - delta from the distance to the far bound: in FP32, 1 - u itself
+  // cancels catastrophically as u -> 1 and val^(1/(eta+1)) magnifies that
+  // error. Both halves of the mutation share one pair of powers (selects, no
+  // branch).
+  float a, b;
+  bool low;
+  if (T <= 0x80000000ull) {  // every numerator fits 32 bits
+    const uint32_t T32 = static_cast<uint32_t>(T);
+    low = 2u * w < T32;  // u < 1/2
+    a = static_cast<float>(low ? 2u * w : 2u * (T32 - w)) * invT;
+    b = static_cast<float>(low ? T32 - 2u * w : 2u * w - T32) * invT;
+  } else {
+    const uint64_t w64 = w;
+    low = 2u * w64 < T;
+    a = static_cast<float>(low ? 2u * w64 : 2u * (T - w64)) * invT;
+    b = static_cast<float>(low ? T - 2u * w64 : 2u * w64 - T) * invT;
   }
-  const uint64_t w = wB;
-  if (w < st.tpm) {
-    const bool low = 2u * w < st.tpm;
-    const uint64_t na = low ? 2u * w : 2u * (st.tpm - w);
-    const uint64_t nb = low ? st.tpm - 2u * w : 2u * w - st.tpm;
-    const float a = static_cast<float>(na) * st.inv_tpm;
-    const float b = static_cast<float>(nb) * st.inv_tpm;
-    const float xy = (low ? (hi - c) : (c - lo)) * inv_span;
-    const float t = powpos(fmaf(b, powpos(xy, st.pm_p), a), st.pm_e);
-    const float dq = low ? t - 1.0f : 1.0f - t;
-    c = fminf(fmaxf(fmaf(dq, hi - lo, c), lo), hi);
-  }
-  return c;
+  const float xy = (low ? (hi - c) : (c - lo)) * inv_span;
+  const float t = powpos(fmaf(b, powpos(xy, st.pm_p), a), st.pm_e);
+  const float dq = low ? t - 1.0f : 1.0f - t;
+  return __builtin_amdgcn_fmed3f(fmaf(dq, hi - lo, c), lo, hi);
 }
 
-__device__ __forceinline__ float vary1(float a, float b, uint32_t wA, uint32_t wB, float lo, float hi,
-                                       float inv_span, bool cross, const DevState &st) {
+// SBX of one variable (one child kept; crossing bit 0, sign bit 1, 24-bit
+// uniform in bits 8..31), clipped to the box.
+__device__ __forceinline__ float sbx1(float a, float b, uint32_t wA, float lo, float hi, bool cross,
+                                      const DevState &st) {
   float c = a;
   if (cross && (wA & 1u)) {
     const float u = u24(wA);
@@ -131,14 +121,13 @@ __device__ __forceinline__ float vary1(float a, float b, uint32_t wA, uint32_t w
     const float beta = (wA & 2u) ? -beta0 : beta0;
     c = 0.5f * fmaf(beta, a - b, a + b);
   }
-  c = fminf(fmaxf(c, lo), hi);
-  return pm1(c, wB, lo, hi, inv_span, st);
+  return __builtin_amdgcn_fmed3f(c, lo, hi);
 }
 
-__device__ __forceinline__ float vary1_de(float x, float a, float b, uint32_t wB, float lo, float hi,
-                                          float inv_span, const DevState &st) {
-  const float c = fminf(fmaxf(fmaf(st.de_f, a - b, x), lo), hi);
-  return pm1(c, wB, lo, hi, inv_span, st);
+// DE mutant of one variable (crossover rate 1), clipped to the box.
+__device__ __forceinline__ float de1(float x, float a, float b, float lo, float hi,
+                                     const DevState &st) {
+  return __builtin_amdgcn_fmed3f(fmaf(st.de_f, a - b, x), lo, hi);
 }
 
 // Running sums of the evaluation, filled variable by variable.
@@ -155,6 +144,19 @@ __device__ __forceinline__ void eval_add(EvalAcc &e, int l, float x) {
     if (l >= 1) e.s += x;
   } else {
     if (l >= M - 1) e.s = fmaf(x - 0.5f, x - 0.5f, e.s);
+  }
+}
+
+// Replace variable l's contribution old by new (a mutation applied after the
+// variable was first added).
+template <int M, int FAM>
+__device__ __forceinline__ void eval_fix(EvalAcc &e, int l, float old, float nw) {
+  if (l == 0) e.x0 = nw;
+  if (l == 1) e.x1 = nw;
+  if (FAM == 0) {
+    if (l >= 1) e.s += nw - old;
+  } else {
+    if (l >= M - 1) e.s += fmaf(nw - 0.5f, nw - 0.5f, -((old - 0.5f) * (old - 0.5f)));
   }
 }
 
@@ -424,8 +426,11 @@ __global__ __launch_bounds__(kBlock) void k_rev_sort(int32_t n, int32_t t, const
 // Draws (the paper fixes no RNG; this counter layout is the library's): Philox
 // counter (c0, i, k, tag << 24 | p << 16) for offspring i of population p in
 // generation k. The MATE block (c0 = 0) gives the two neighbourhood positions
-// and the per-offspring crossing draw; VAR block c0 = l >> 1 gives (wA, wB) for
-// variables l and l + 1.
+// and the per-offspring crossing draw; VAR block c0 = q gives one word per
+// variable of chunk q (variables 4q .. 4q + 3): SBX's bits, and in bits 2..7
+// a 24-bit value for the chunk's mutation test; the PMX block c0 = q decides,
+// for a chunk that has a mutation, which of its variables mutate and with
+// which uniform.
 // A group of LPO consecutive lanes builds one offspring: lane g of the group
 // takes the float4 chunks g, g + LPO, ... of the row, so with LPO = 8 the group
 // reads each parent row and writes the offspring row as whole 128-byte lines.
@@ -470,34 +475,78 @@ __device__ __forceinline__ void vary_body(const DevState &st, int L, int G) {
     const float4 *ub4 = reinterpret_cast<const float4 *>(st.prob.ub);
     const float4 *is4 = reinterpret_cast<const float4 *>(st.prob.inv_span);
     const uint32_t tagv = (kTagVar << 24) | tagp;
+    const uint32_t tagm = (kTagPmx << 24) | tagp;
     const int nq = st.stride >> 2;
     const bool de = st.op == 1;
     const float4 *rx = reinterpret_cast<const float4 *>(Xc + static_cast<size_t>(i) * st.stride);
-    for (int q = g; q < nq; q += LPO) {
+    // Mutations are sampled per chunk of four variables: the spare bits of the
+    // chunk's variation words decide whether any variable mutates; the rare
+    // chunks that do are finished in a second pass over a bit mask, so a wave
+    // does not evaluate the mutation while most of its lanes have none.
+    uint32_t flagged = 0;
+    auto finish = [&](uint32_t mask, int it0) {
+      while (mask) {
+        const int bit = __builtin_ctz(mask);
+        mask &= mask - 1u;
+        const int q = g + (it0 + bit) * LPO;
+        const int l0 = q << 2;
+        const int r = min(4, st.d - l0);
+        const uint4 wm4 = philox10(make_uint4(q, i, k, tagm), st.key0, st.key1);
+        const uint32_t wm[4] = {wm4.x, wm4.y, wm4.z, wm4.w};
+        float4 o = ro[q];
+        float ov[4] = {o.x, o.y, o.z, o.w};
+        const float4 lo = lb4[q], hi = ub4[q], is = is4[q];
+        const float lov[4] = {lo.x, lo.y, lo.z, lo.w}, hiv[4] = {hi.x, hi.y, hi.z, hi.w};
+        const float isv[4] = {is.x, is.y, is.z, is.w};
+        bool any = false;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          if (u < r) {
+            const uint64_t T = any ? st.tpm : st.tfirst[r - u];
+            const float invT = any ? st.inv_tpm : st.inv_tfirst[r - u];
+            if (static_cast<uint64_t>(wm[u]) < T) {
+              const float nv = pm1(ov[u], wm[u], T, invT, lov[u], hiv[u], isv[u], st);
+              eval_fix<M, FAM>(e, l0 + u, ov[u], nv);
+              ov[u] = nv;
+              any = true;
+            }
+          }
+        }
+        ro[q] = make_float4(ov[0], ov[1], ov[2], ov[3]);
+      }
+    };
+    int it = 0;
+    for (int q = g; q < nq; q += LPO, ++it) {
       const int l0 = q << 2;
-      const float4 va = ra[q], vb = rb[q], lo = lb4[q], hi = ub4[q], is = is4[q];
-      const uint4 r0 = philox10(make_uint4(2 * q, i, k, tagv), st.key0, st.key1);
-      uint4 r1w = make_uint4(0, 0, 0, 0);
-      if (l0 + 2 < st.d) r1w = philox10(make_uint4(2 * q + 1, i, k, tagv), st.key0, st.key1);
+      const float4 va = ra[q], vb = rb[q], lo = lb4[q], hi = ub4[q];
+      const uint4 w4 = philox10(make_uint4(q, i, k, tagv), st.key0, st.key1);
       float4 o = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
       if (de) {
         const float4 vx = rx[q];
-        o.x = vary1_de(vx.x, va.x, vb.x, r0.y, lo.x, hi.x, is.x, st);
-        if (l0 + 1 < st.d) o.y = vary1_de(vx.y, va.y, vb.y, r0.w, lo.y, hi.y, is.y, st);
-        if (l0 + 2 < st.d) o.z = vary1_de(vx.z, va.z, vb.z, r1w.y, lo.z, hi.z, is.z, st);
-        if (l0 + 3 < st.d) o.w = vary1_de(vx.w, va.w, vb.w, r1w.w, lo.w, hi.w, is.w, st);
+        o.x = de1(vx.x, va.x, vb.x, lo.x, hi.x, st);
+        if (l0 + 1 < st.d) o.y = de1(vx.y, va.y, vb.y, lo.y, hi.y, st);
+        if (l0 + 2 < st.d) o.z = de1(vx.z, va.z, vb.z, lo.z, hi.z, st);
+        if (l0 + 3 < st.d) o.w = de1(vx.w, va.w, vb.w, lo.w, hi.w, st);
       } else {
-        o.x = vary1(va.x, vb.x, r0.x, r0.y, lo.x, hi.x, is.x, cross, st);
-        if (l0 + 1 < st.d) o.y = vary1(va.y, vb.y, r0.z, r0.w, lo.y, hi.y, is.y, cross, st);
-        if (l0 + 2 < st.d) o.z = vary1(va.z, vb.z, r1w.x, r1w.y, lo.z, hi.z, is.z, cross, st);
-        if (l0 + 3 < st.d) o.w = vary1(va.w, vb.w, r1w.z, r1w.w, lo.w, hi.w, is.w, cross, st);
+        o.x = sbx1(va.x, vb.x, w4.x, lo.x, hi.x, cross, st);
+        if (l0 + 1 < st.d) o.y = sbx1(va.y, vb.y, w4.y, lo.y, hi.y, cross, st);
+        if (l0 + 2 < st.d) o.z = sbx1(va.z, vb.z, w4.z, lo.z, hi.z, cross, st);
+        if (l0 + 3 < st.d) o.w = sbx1(va.w, vb.w, w4.w, lo.w, hi.w, cross, st);
       }
       eval_add<M, FAM>(e, l0, o.x);
       if (l0 + 1 < st.d) eval_add<M, FAM>(e, l0 + 1, o.y);
       if (l0 + 2 < st.d) eval_add<M, FAM>(e, l0 + 2, o.z);
       if (l0 + 3 < st.d) eval_add<M, FAM>(e, l0 + 3, o.w);
       ro[q] = o;
+      const uint32_t A = ((w4.x >> 2) & 63u) | (((w4.y >> 2) & 63u) << 6) |
+                         (((w4.z >> 2) & 63u) << 12) | (((w4.w >> 2) & 63u) << 18);
+      if (A < st.tany[min(4, st.d - l0)]) flagged |= 1u << (it & 31);
+      if ((it & 31) == 31) {
+        finish(flagged, it - 31);
+        flagged = 0;
+      }
     }
+    finish(flagged, it & ~31);
   }
   // Group reduction: the sums over the group's chunks, and x1, x2 from chunk 0
   // (lane g = 0). Every lane of a wave takes part (no lane has left early).
