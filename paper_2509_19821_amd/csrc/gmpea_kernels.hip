@@ -147,19 +147,6 @@ __device__ __forceinline__ void eval_add(EvalAcc &e, int l, float x) {
   }
 }
 
-// Replace variable l's contribution old by new (a mutation applied after the
-// variable was first added).
-template <int M, int FAM>
-__device__ __forceinline__ void eval_fix(EvalAcc &e, int l, float old, float nw) {
-  if (l == 0) e.x0 = nw;
-  if (l == 1) e.x1 = nw;
-  if (FAM == 0) {
-    if (l >= 1) e.s += nw - old;
-  } else {
-    if (l >= M - 1) e.s += fmaf(nw - 0.5f, nw - 0.5f, -((old - 0.5f) * (old - 0.5f)));
-  }
-}
-
 // F and CV from the sums (Eqs. (1)-(3)); returns (f0, f1, f2, cv).
 template <int M, int FAM>
 __device__ __forceinline__ float4 eval_finish(const EvalAcc &e, const DevProblem &P) {
@@ -484,7 +471,9 @@ __device__ __forceinline__ void vary_body(const DevState &st, int L, int G) {
     // chunks that do are finished in a second pass over a bit mask, so a wave
     // does not evaluate the mutation while most of its lanes have none.
     uint32_t flagged = 0;
+    bool dirty = false;  // this lane's chunks changed after their first evaluation
     auto finish = [&](uint32_t mask, int it0) {
+      dirty = dirty || mask != 0u;
       while (mask) {
         const int bit = __builtin_ctz(mask);
         mask &= mask - 1u;
@@ -505,9 +494,7 @@ __device__ __forceinline__ void vary_body(const DevState &st, int L, int G) {
             const uint64_t T = any ? st.tpm : st.tfirst[r - u];
             const float invT = any ? st.inv_tpm : st.inv_tfirst[r - u];
             if (static_cast<uint64_t>(wm[u]) < T) {
-              const float nv = pm1(ov[u], wm[u], T, invT, lov[u], hiv[u], isv[u], st);
-              eval_fix<M, FAM>(e, l0 + u, ov[u], nv);
-              ov[u] = nv;
+              ov[u] = pm1(ov[u], wm[u], T, invT, lov[u], hiv[u], isv[u], st);
               any = true;
             }
           }
@@ -547,6 +534,19 @@ __device__ __forceinline__ void vary_body(const DevState &st, int L, int G) {
       }
     }
     finish(flagged, it & ~31);
+    if (dirty) {
+      // F must be a function of the final x alone (copies of an individual must
+      // evaluate bitwise equal): re-add this lane's chunks in the same order
+      e = EvalAcc{0.0f, 0.0f, 0.0f};
+      for (int q = g; q < nq; q += LPO) {
+        const int l0 = q << 2;
+        const float4 o = ro[q];
+        eval_add<M, FAM>(e, l0, o.x);
+        if (l0 + 1 < st.d) eval_add<M, FAM>(e, l0 + 1, o.y);
+        if (l0 + 2 < st.d) eval_add<M, FAM>(e, l0 + 2, o.z);
+        if (l0 + 3 < st.d) eval_add<M, FAM>(e, l0 + 3, o.w);
+      }
+    }
   }
   // Group reduction: the sums over the group's chunks, and x1, x2 from chunk 0
   // (lane g = 0). Every lane of a wave takes part (no lane has left early).

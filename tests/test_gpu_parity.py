@@ -170,6 +170,18 @@ def _teacher_forced(gp, o, gens, label):
                 sp = p ^ int(g_sw[i])
                 assert np.array_equal(X[j], Xo[sp][i]), (label, "copied row", p, j)
                 assert np.array_equal(F[j], Fo[sp][i]) and CV[j] == CVo[sp][i], (label, "copied F/CV")
+            # F and CV are functions of x alone: bitwise-equal rows evaluate equal
+            allx = np.concatenate([X, Xo[0], Xo[1]])
+            allfc = np.concatenate([np.column_stack([F, CV]), np.column_stack([Fo[0], CVo[0]]),
+                                    np.column_stack([Fo[1], CVo[1]])])
+            _, inv = np.unique(allx.view(np.dtype((np.void, allx.dtype.itemsize * allx.shape[1]))),
+                               return_inverse=True)
+            first = {}
+            for r_, key_ in enumerate(inv.ravel()):
+                if key_ in first:
+                    assert np.array_equal(allfc[r_], allfc[first[key_]]), (label, "F of equal x", p)
+                else:
+                    first[key_] = r_
             amb32 += int((~wr).sum())
             amb64 += int((~wr64).sum())
             slots += N
