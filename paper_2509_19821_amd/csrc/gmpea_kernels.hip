@@ -230,32 +230,79 @@ __global__ __launch_bounds__(kBlock) void k_init(DevState st) {
   const int L = xcd_tile(blockIdx.x, gridDim.x);
   const int p = L >= st.nblk ? 1 : 0;
   const int i = (L - p * st.nblk) * kBlock + threadIdx.x;
+  if (i >= st.n) return;
+  float *row = st.X[p] + static_cast<size_t>(i) * st.stride;
+  uint4 w = make_uint4(0, 0, 0, 0);
+  for (int l = 0; l < st.stride; ++l) {
+    float x = 0.0f;
+    if (l < st.d) {
+      if ((l & 3) == 0)
+        w = philox10(make_uint4(l >> 2, i, 0u, (kTagInit << 24) | (p << 16)), st.key0, st.key1);
+      const uint32_t word = (l & 3) == 0 ? w.x : (l & 3) == 1 ? w.y : (l & 3) == 2 ? w.z : w.w;
+      const float lo = st.prob.lb[l], hi = st.prob.ub[l];
+      x = fmaf(hi - lo, u24(word), lo);
+    }
+    row[l] = x;
+  }
+}
+
+// Evaluation of a population row by a group of LPO lanes: lane g adds chunks
+// g, g + LPO, ... in order, then a butterfly combines the lanes. k_vary adds
+// its offspring in exactly this order, so F and CV are a function of x alone:
+// an offspring that copies an individual evaluates bitwise equal to it.
+template <int M, int FAM, int LPO>
+__device__ __forceinline__ EvalAcc eval_row(const DevState &st, const float4 *row, int g, bool live) {
+  EvalAcc e{0.0f, 0.0f, 0.0f};
+  if (live) {
+    const int nq = st.stride >> 2;
+    for (int q = g; q < nq; q += LPO) {
+      const int l0 = q << 2;
+      const float4 o = row[q];
+      eval_add<M, FAM>(e, l0, o.x);
+      if (l0 + 1 < st.d) eval_add<M, FAM>(e, l0 + 1, o.y);
+      if (l0 + 2 < st.d) eval_add<M, FAM>(e, l0 + 2, o.z);
+      if (l0 + 3 < st.d) eval_add<M, FAM>(e, l0 + 3, o.w);
+    }
+  }
+  return e;
+}
+
+// Group reduction of the sums (every lane of the wave takes part), then F/CV
+// and the ideal point's block minimum.
+template <int M, int FAM, int LPO>
+__device__ __forceinline__ void eval_group(const DevState &st, EvalAcc e, int g, bool live,
+                                           float4 *out) {
   float zv[M];
 #pragma unroll
-  for (int k = 0; k < M; ++k) zv[k] = __builtin_huge_valf();
-  if (i < st.n) {
-    float *row = st.X[p] + static_cast<size_t>(i) * st.stride;
-    EvalAcc e{0.0f, 0.0f, 0.0f};
-    uint4 w = make_uint4(0, 0, 0, 0);
-    for (int l = 0; l < st.stride; ++l) {
-      float x = 0.0f;
-      if (l < st.d) {
-        if ((l & 3) == 0)
-          w = philox10(make_uint4(l >> 2, i, 0u, (kTagInit << 24) | (p << 16)), st.key0, st.key1);
-        const uint32_t word = (l & 3) == 0 ? w.x : (l & 3) == 1 ? w.y : (l & 3) == 2 ? w.z : w.w;
-        const float lo = st.prob.lb[l], hi = st.prob.ub[l];
-        x = fmaf(hi - lo, u24(word), lo);
-        eval_add<M, FAM>(e, l, x);
-      }
-      row[l] = x;
-    }
+  for (int q = 0; q < M; ++q) zv[q] = __builtin_huge_valf();
+#pragma unroll
+  for (int o = 1; o < LPO; o <<= 1) e.s += __shfl_xor(e.s, o);
+  const int base = (threadIdx.x & 63) & ~(LPO - 1);
+  e.x0 = __shfl(e.x0, base);
+  e.x1 = __shfl(e.x1, base);
+  if (live && g == 0) {
     const float4 fc = eval_finish<M, FAM>(e, st.prob);
-    st.FC[p][i] = fc;
+    *out = fc;
     zv[0] = fc.x;
     if (M > 1) zv[1] = fc.y;
     if (M > 2) zv[M - 1] = fc.z;
   }
   block_zmin<M>(zv, st.zkey);
+}
+
+// Initial evaluation (Alg. 1): F, CV and the ideal point of both populations.
+template <int M, int FAM, int LPO>
+__global__ __launch_bounds__(kBlock) void k_eval(DevState st) {
+  constexpr int kPer = kBlock / LPO;
+  const int L = xcd_tile(blockIdx.x, gridDim.x);
+  const int half = gridDim.x >> 1;
+  const int p = L >= half ? 1 : 0;
+  const int g = threadIdx.x & (LPO - 1);
+  const int i = (L - p * half) * kPer + threadIdx.x / LPO;
+  const bool live = i < st.n;
+  const float4 *row = reinterpret_cast<const float4 *>(st.X[p] + static_cast<size_t>(live ? i : 0) * st.stride);
+  const EvalAcc e = eval_row<M, FAM, LPO>(st, row, g, live);
+  eval_group<M, FAM, LPO>(st, e, g, live, &st.FC[p][live ? i : 0]);
 }
 
 // ----------------------------------------------------------------------------
@@ -434,9 +481,6 @@ __device__ __forceinline__ void vary_body(const DevState &st, int L, int G) {
   const uint32_t k = *st.gen + 1u;
   const uint32_t tagp = (p << 16);
   const float *Xc = st.X[p];
-  float zv[M];
-#pragma unroll
-  for (int q = 0; q < M; ++q) zv[q] = __builtin_huge_valf();
   const bool live = i < st.n;
   EvalAcc e{0.0f, 0.0f, 0.0f};
   if (live) {
@@ -534,35 +578,12 @@ __device__ __forceinline__ void vary_body(const DevState &st, int L, int G) {
       }
     }
     finish(flagged, it & ~31);
-    if (dirty) {
-      // F must be a function of the final x alone (copies of an individual must
-      // evaluate bitwise equal): re-add this lane's chunks in the same order
-      e = EvalAcc{0.0f, 0.0f, 0.0f};
-      for (int q = g; q < nq; q += LPO) {
-        const int l0 = q << 2;
-        const float4 o = ro[q];
-        eval_add<M, FAM>(e, l0, o.x);
-        if (l0 + 1 < st.d) eval_add<M, FAM>(e, l0 + 1, o.y);
-        if (l0 + 2 < st.d) eval_add<M, FAM>(e, l0 + 2, o.z);
-        if (l0 + 3 < st.d) eval_add<M, FAM>(e, l0 + 3, o.w);
-      }
-    }
+    // F must be a function of the final x alone (copies of an individual must
+    // evaluate bitwise equal): a lane whose chunks changed re-adds them in order
+    if (dirty) e = eval_row<M, FAM, LPO>(st, ro, g, true);
   }
-  // Group reduction: the sums over the group's chunks, and x1, x2 from chunk 0
-  // (lane g = 0). Every lane of a wave takes part (no lane has left early).
-#pragma unroll
-  for (int o = 1; o < LPO; o <<= 1) e.s += __shfl_xor(e.s, o);
-  const int base = (threadIdx.x & 63) & ~(LPO - 1);
-  e.x0 = __shfl(e.x0, base);
-  e.x1 = __shfl(e.x1, base);
-  if (live && g == 0) {
-    const float4 fc = eval_finish<M, FAM>(e, st.prob);
-    st.FCO[p][i] = fc;
-    zv[0] = fc.x;
-    if (M > 1) zv[1] = fc.y;
-    if (M > 2) zv[M - 1] = fc.z;
-  }
-  block_zmin<M>(zv, st.zkey);
+  // the sums over the group's chunks (and x1, x2 from chunk 0) -> F, CV, z
+  eval_group<M, FAM, LPO>(st, e, g, live, &st.FCO[p][live ? i : 0]);
 }
 
 template <int M, int FAM, int LPO>
@@ -994,8 +1015,27 @@ hipError_t launch_reverse_fill(int32_t n, int32_t t, const int32_t *B, const int
   return hipGetLastError();
 }
 
+template <int LPO>
+static void launch_eval_lpo(const DevState &st, hipStream_t s) {
+  const int grid = vary_blocks_of(st.n, LPO);
+  if (st.m == 2 && st.prob.family == 0)
+    hipLaunchKernelGGL((k_eval<2, 0, LPO>), dim3(grid), dim3(kBlock), 0, s, st);
+  else if (st.m == 2)
+    hipLaunchKernelGGL((k_eval<2, 1, LPO>), dim3(grid), dim3(kBlock), 0, s, st);
+  else
+    hipLaunchKernelGGL((k_eval<3, 1, LPO>), dim3(grid), dim3(kBlock), 0, s, st);
+}
+
 hipError_t launch_init(const DevState &st, hipStream_t s) {
   GMPEA_DISPATCH_MF(k_init, 2 * st.nblk, st, s);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  switch (vary_lanes_of(st.stride)) {
+    case 8: launch_eval_lpo<8>(st, s); break;
+    case 4: launch_eval_lpo<4>(st, s); break;
+    case 2: launch_eval_lpo<2>(st, s); break;
+    default: launch_eval_lpo<1>(st, s); break;
+  }
   return hipGetLastError();
 }
 
