@@ -510,44 +510,12 @@ __device__ __forceinline__ void vary_body(const DevState &st, int L, int G) {
     const int nq = st.stride >> 2;
     const bool de = st.op == 1;
     const float4 *rx = reinterpret_cast<const float4 *>(Xc + static_cast<size_t>(i) * st.stride);
+    bool flag_out = false;  // chunk_var's verdict: the chunk holds a mutation
     // Mutations are sampled per chunk of four variables: the spare bits of the
     // chunk's variation words decide whether any variable mutates; the rare
     // chunks that do are finished in a second pass over a bit mask, so a wave
     // does not evaluate the mutation while most of its lanes have none.
-    uint32_t flagged = 0;
-    bool dirty = false;  // this lane's chunks changed after their first evaluation
-    auto finish = [&](uint32_t mask, int it0) {
-      dirty = dirty || mask != 0u;
-      while (mask) {
-        const int bit = __builtin_ctz(mask);
-        mask &= mask - 1u;
-        const int q = g + (it0 + bit) * LPO;
-        const int l0 = q << 2;
-        const int r = min(4, st.d - l0);
-        const uint4 wm4 = philox10(make_uint4(q, i, k, tagm), st.key0, st.key1);
-        const uint32_t wm[4] = {wm4.x, wm4.y, wm4.z, wm4.w};
-        float4 o = ro[q];
-        float ov[4] = {o.x, o.y, o.z, o.w};
-        const float4 lo = lb4[q], hi = ub4[q], is = is4[q];
-        const float lov[4] = {lo.x, lo.y, lo.z, lo.w}, hiv[4] = {hi.x, hi.y, hi.z, hi.w};
-        const float isv[4] = {is.x, is.y, is.z, is.w};
-        bool any = false;
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          if (u < r) {
-            const uint64_t T = any ? st.tpm : st.tfirst[r - u];
-            const float invT = any ? st.inv_tpm : st.inv_tfirst[r - u];
-            if (static_cast<uint64_t>(wm[u]) < T) {
-              ov[u] = pm1(ov[u], wm[u], T, invT, lov[u], hiv[u], isv[u], st);
-              any = true;
-            }
-          }
-        }
-        ro[q] = make_float4(ov[0], ov[1], ov[2], ov[3]);
-      }
-    };
-    int it = 0;
-    for (int q = g; q < nq; q += LPO, ++it) {
+    auto chunk_var = [&](int q) -> float4 {
       const int l0 = q << 2;
       const float4 va = ra[q], vb = rb[q], lo = lb4[q], hi = ub4[q];
       const uint4 w4 = philox10(make_uint4(q, i, k, tagv), st.key0, st.key1);
@@ -564,23 +532,102 @@ __device__ __forceinline__ void vary_body(const DevState &st, int L, int G) {
         if (l0 + 2 < st.d) o.z = sbx1(va.z, vb.z, w4.z, lo.z, hi.z, cross, st);
         if (l0 + 3 < st.d) o.w = sbx1(va.w, vb.w, w4.w, lo.w, hi.w, cross, st);
       }
-      eval_add<M, FAM>(e, l0, o.x);
-      if (l0 + 1 < st.d) eval_add<M, FAM>(e, l0 + 1, o.y);
-      if (l0 + 2 < st.d) eval_add<M, FAM>(e, l0 + 2, o.z);
-      if (l0 + 3 < st.d) eval_add<M, FAM>(e, l0 + 3, o.w);
-      ro[q] = o;
       const uint32_t A = ((w4.x >> 2) & 63u) | (((w4.y >> 2) & 63u) << 6) |
                          (((w4.z >> 2) & 63u) << 12) | (((w4.w >> 2) & 63u) << 18);
-      if (A < st.tany[min(4, st.d - l0)]) flagged |= 1u << (it & 31);
-      if ((it & 31) == 31) {
-        finish(flagged, it - 31);
-        flagged = 0;
+      flag_out = A < st.tany[min(4, st.d - l0)];
+      return o;
+    };
+    auto chunk_mut = [&](int q, float4 o) -> float4 {
+      const int l0 = q << 2;
+      const int r = min(4, st.d - l0);
+      const uint4 wm4 = philox10(make_uint4(q, i, k, tagm), st.key0, st.key1);
+      const uint32_t wm[4] = {wm4.x, wm4.y, wm4.z, wm4.w};
+      float ov[4] = {o.x, o.y, o.z, o.w};
+      const float4 lo = lb4[q], hi = ub4[q], is = is4[q];
+      const float lov[4] = {lo.x, lo.y, lo.z, lo.w}, hiv[4] = {hi.x, hi.y, hi.z, hi.w};
+      const float isv[4] = {is.x, is.y, is.z, is.w};
+      bool any = false;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (u < r) {
+          const uint64_t T = any ? st.tpm : st.tfirst[r - u];
+          const float invT = any ? st.inv_tpm : st.inv_tfirst[r - u];
+          if (static_cast<uint64_t>(wm[u]) < T) {
+            ov[u] = pm1(ov[u], wm[u], T, invT, lov[u], hiv[u], isv[u], st);
+            any = true;
+          }
+        }
       }
+      return make_float4(ov[0], ov[1], ov[2], ov[3]);
+    };
+    if (nq <= 4 * LPO) {
+      // up to four chunks per lane: they stay in registers until final (four
+      // named values, not an array, so that a dynamic pick cannot send them to
+      // scratch memory)
+      const float4 zero4 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      float4 k0 = zero4, k1 = zero4, k2 = zero4, k3 = zero4;
+      uint32_t flagged = 0;
+      if (g < nq) {
+        k0 = chunk_var(g);
+        flagged |= flag_out ? 1u : 0u;
+      }
+      if (g + LPO < nq) {
+        k1 = chunk_var(g + LPO);
+        flagged |= flag_out ? 2u : 0u;
+      }
+      if (g + 2 * LPO < nq) {
+        k2 = chunk_var(g + 2 * LPO);
+        flagged |= flag_out ? 4u : 0u;
+      }
+      if (g + 3 * LPO < nq) {
+        k3 = chunk_var(g + 3 * LPO);
+        flagged |= flag_out ? 8u : 0u;
+      }
+      while (flagged) {
+        const int it = __builtin_ctz(flagged);
+        flagged &= flagged - 1u;
+        float4 o = k0;
+        if (it == 1) o = k1;
+        if (it == 2) o = k2;
+        if (it == 3) o = k3;
+        const float4 nw = chunk_mut(g + it * LPO, o);
+        if (it == 0) k0 = nw;
+        if (it == 1) k1 = nw;
+        if (it == 2) k2 = nw;
+        if (it == 3) k3 = nw;
+      }
+      auto store_add = [&](int q, float4 o) {
+        const int l0 = q << 2;
+        ro[q] = o;
+        eval_add<M, FAM>(e, l0, o.x);
+        if (l0 + 1 < st.d) eval_add<M, FAM>(e, l0 + 1, o.y);
+        if (l0 + 2 < st.d) eval_add<M, FAM>(e, l0 + 2, o.z);
+        if (l0 + 3 < st.d) eval_add<M, FAM>(e, l0 + 3, o.w);
+      };
+      if (g < nq) store_add(g, k0);
+      if (g + LPO < nq) store_add(g + LPO, k1);
+      if (g + 2 * LPO < nq) store_add(g + 2 * LPO, k2);
+      if (g + 3 * LPO < nq) store_add(g + 3 * LPO, k3);
+    } else {
+      // long rows: each chunk is written once, a flagged one again after its
+      // mutation, and the sums are taken from the final row in the same order
+      uint32_t flagged = 0;
+      int it = 0;
+      for (int q = g; q < nq; q += LPO, ++it) {
+        ro[q] = chunk_var(q);
+        flagged |= flag_out ? (1u << (it & 31)) : 0u;
+        if ((it & 31) == 31 || q + LPO >= nq) {
+          const int it0 = it & ~31;
+          while (flagged) {
+            const int bit = __builtin_ctz(flagged);
+            flagged &= flagged - 1u;
+            const int qq = g + (it0 + bit) * LPO;
+            ro[qq] = chunk_mut(qq, ro[qq]);
+          }
+        }
+      }
+      e = eval_row<M, FAM, LPO>(st, ro, g, true);
     }
-    finish(flagged, it & ~31);
-    // F must be a function of the final x alone (copies of an individual must
-    // evaluate bitwise equal): a lane whose chunks changed re-adds them in order
-    if (dirty) e = eval_row<M, FAM, LPO>(st, ro, g, true);
   }
   // the sums over the group's chunks (and x1, x2 from chunk 0) -> F, CV, z
   eval_group<M, FAM, LPO>(st, e, g, live, &st.FCO[p][live ? i : 0]);

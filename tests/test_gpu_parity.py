@@ -308,6 +308,21 @@ def test_generation_equality_and_wide_rows(G):
             gp.close()
 
 
+@pytest.mark.parametrize("d,op", [(200, 0), (1100, 0), (1100, 1)])
+def test_generation_long_rows(G, d, op):
+    """Rows longer than four chunks per lane (d > 128) take the kernel's
+    long-row path; d = 1100 also crosses its 32-chunk mutation flush."""
+    prob = ci.make_problem(ci.FAMILY_SPHERE, 3, d, 2, True, False, 8)
+    cfg = ci.method_config(120, 10, 8, op=op)
+    gp, o = _pair(prob, cfg)
+    try:
+        gp.step(2)
+        frac = _teacher_forced(gp, o, 2, "long rows d=%d op=%d" % (d, op))
+        assert frac < 0.005
+    finally:
+        gp.close()
+
+
 def test_generation_odd_shapes(G):
     """Unit neighbourhoods, d = 7 (ragged rows), m = 2 sphere family, pc < 1."""
     prob = ci.make_problem(ci.FAMILY_SPHERE, 2, 7, 3, True, False, 3)
