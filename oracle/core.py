@@ -49,8 +49,7 @@ class Cfg(ctypes.Structure):
                 ("tpm", ctypes.c_uint64), ("tpc", ctypes.c_uint64),
                 ("key", ctypes.c_uint32 * 2), ("n_eq", ctypes.c_int32), ("eq_tol", ctypes.c_double),
                 ("f32", ctypes.c_int32), ("op", ctypes.c_int32), ("de_f", ctypes.c_double),
-                ("op1_rule", ctypes.c_int32), ("tany", ctypes.c_uint32 * 5),
-                ("tfirst", ctypes.c_uint64 * 5)]
+                ("op1_rule", ctypes.c_int32)]
 
 
 def lib():
@@ -82,7 +81,6 @@ def lib():
             L.orc_mate.argtypes = [u32, u32, i32, vp, vp]
             L.orc_de_dim.argtypes = [ctypes.c_double] * 6 + [u32, ctypes.c_uint64, ctypes.c_double]
             L.orc_de_dim.restype = ctypes.c_double
-            L.orc_pm_chunk.argtypes = [vp, vp, i32, u32, u32, u32, u32, vp, vp]
             L.orc_select.argtypes = [vp] * 18
             L.orc_reproduce.argtypes = [vp, vp, u32, vp, vp, vp, vp, vp, vp, vp]
             L.orc_ideal.argtypes = [i64, i32, vp, vp]
@@ -202,22 +200,6 @@ def de_dim(xi: float, a: float, b: float, F: float, lo: float, hi: float, wB: in
                                   int(wB) & 0xFFFFFFFF, int(tpm), float(eta_m)))
 
 
-def pm_chunk(dv: dict, key, v, r: int, c: int, i: int, k: int, p: int):
-    """R8 chunk-level mutation sampling for one chunk: (PMX words, thresholds
-    used, 0 for variables left unmutated)."""
-    holder = Cfg()
-    holder.tpm = dv["tpm"]
-    holder.key = (ctypes.c_uint32 * 2)(*key)
-    holder.tany = (ctypes.c_uint32 * 5)(*dv["tany"])
-    holder.tfirst = (ctypes.c_uint64 * 5)(*dv["tfirst"])
-    vv = np.ascontiguousarray(v, dtype=np.uint32)
-    wm = np.zeros(4, dtype=np.uint32)
-    mut = np.zeros(4, dtype=np.uint64)
-    lib().orc_pm_chunk(ctypes.byref(holder), _p(vv), int(r), int(c), int(i), int(k), int(p),
-                       _p(wm), _p(mut))
-    return wm, mut
-
-
 def mate(w0: int, w1: int, t: int):
     r1 = np.zeros(1, dtype=np.int32)
     r2 = np.zeros(1, dtype=np.int32)
@@ -252,23 +234,12 @@ def derive(prob: dict, cfg: dict) -> dict:
         raise ValueError("neighbourhood sizes must satisfy 1 <= t <= N_eff")
     pm = float(cfg["pm"]) if cfg["pm"] > 0 else 1.0 / d
     seed = int(cfg["seed"]) & 0xFFFFFFFFFFFFFFFF
-    # R8 chunk thresholds: P(a chunk of r variables holds a mutation) and the
-    # conditional first-mutation probabilities, in FP64 by repeated products
-    tany, tfirst = [0] * 5, [0] * 5
-    for r in range(1, 5):
-        q = 1.0
-        for _ in range(r):
-            q *= (1.0 - pm)
-        p0 = 1.0 - q
-        tany[r] = int(np.floor(p0 * 16777216.0))
-        tfirst[r] = 4294967296 if r == 1 else (int(np.floor(pm / p0 * 4294967296.0)) if p0 > 0 else 0)
     return {"m": m, "d": d, "H": H, "N": N, "t": (t1, t2),
             "tpm": int(np.floor(pm * 4294967296.0)), "tpc": int(np.floor(float(cfg["pc"]) * 4294967296.0)),
             "key": (seed & 0xFFFFFFFF, seed >> 32), "agg": int(cfg["agg"]),
             "theta": float(cfg["theta"]), "eta_c": float(cfg["eta_c"]),
             "eta_m": float(cfg["eta_m"]), "op": int(cfg.get("op", 0)),
-            "de_f": float(cfg.get("de_f", 0.0)) or 0.5, "op1_rule": int(cfg.get("op1_rule", 0)),
-            "tany": tany, "tfirst": tfirst}
+            "de_f": float(cfg.get("de_f", 0.0)) or 0.5, "op1_rule": int(cfg.get("op1_rule", 0))}
 
 
 class Oracle:
@@ -289,8 +260,7 @@ class Oracle:
                         (ctypes.c_void_p * 2)(_p(self.B[0]), _p(self.B[1])), _p(self.W),
                         dv["agg"], dv["theta"], dv["eta_c"], dv["eta_m"], dv["tpm"], dv["tpc"],
                         (ctypes.c_uint32 * 2)(*dv["key"]), int(prob["n_eq"]),
-                        float(prob["eq_tol"]), 0, dv["op"], dv["de_f"], dv["op1_rule"],
-                        (ctypes.c_uint32 * 5)(*dv["tany"]), (ctypes.c_uint64 * 5)(*dv["tfirst"]))
+                        float(prob["eq_tol"]), 0, dv["op"], dv["de_f"], dv["op1_rule"])
         self.gen = 0
         if init:
             X = [self.init_x(0), self.init_x(1)]

@@ -36,7 +36,6 @@
 #define ORC_TAG_INIT 1u
 #define ORC_TAG_MATE 2u
 #define ORC_TAG_VAR 3u
-#define ORC_TAG_PMX 4u
 
 void orc_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
   uint32_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
@@ -302,8 +301,7 @@ static double orc_clip(double v, double lo, double hi) {
 
 /* R8: bounded polynomial mutation of y in [lo, hi] when wB < tpm (integer test,
  * bit-exact on both sides); given that, wB is uniform on [0, tpm) and the
- * conditional uniform is u = wB / tpm in the working precision. The generation
- * calls it with the threshold its chunk-level sampling uses (orc_reproduce). */
+ * conditional uniform is u = wB / tpm in the working precision. */
 double orc_pm_dim(double y, double lo, double hi, uint32_t wB, uint64_t tpm, double eta_m) {
   if ((uint64_t)wB >= tpm) return y;
   double u = (double)wB / (double)tpm;
@@ -367,8 +365,6 @@ typedef struct {
   double de_f;   /* DE scale factor F */
   int32_t op1_rule; /* population 1's OP1 test: 0 the pseudocode's FPR, 1 the prose's
                        feasibility-first rule (R27) */
-  uint32_t tany[5];  /* R8: floor(2^24 (1 - (1 - pm)^r)), r = 1..4 variables in a chunk */
-  uint64_t tfirst[5]; /* R8: floor(2^32 pm / (1 - (1 - pm)^s)), s = 2..4; tfirst[1] = 2^32 */
 } orc_cfg;
 
 #define ORC_OP_SBX 0
@@ -716,42 +712,9 @@ void orc_select(const orc_cfg *C, const double *X0, const double *X1, const doub
   }
 }
 
-/* R8: which variables of a chunk (variables 4c .. 4c + r - 1, r <= 4) the
- * polynomial mutation touches, each independently with probability pm, drawn
- * in two steps. First a 24-bit value A made of bits 2..7 of the chunk's four
- * variation words decides whether any variable mutates: A < tany[r], with
- * probability 1 - (1 - pm)^r. Only then is the chunk's PMX block drawn, and
- * its word u decides variable u given the outcome so far: while no earlier
- * variable of the chunk mutated, with probability pm / (1 - (1 - pm)^s) for
- * the s variables left (1 for the last), afterwards with probability pm. The
- * product of these conditionals is the independent Bernoulli(pm) law. A
- * mutating variable takes u = word / threshold as its uniform (the
- * conditional uniform of R8). mut[u] receives the threshold used, or 0. */
-void orc_pm_chunk(const orc_cfg *C, const uint32_t v[4], int32_t r, uint32_t c, uint32_t i,
-                  uint32_t k, uint32_t p, uint32_t wm[4], uint64_t mut[4]) {
-  for (int u = 0; u < 4; ++u) {
-    wm[u] = 0;
-    mut[u] = 0;
-  }
-  uint32_t A = 0;
-  for (int u = 0; u < 4; ++u) A |= ((v[u] >> 2) & 63u) << (6 * u);
-  if (A >= C->tany[r]) return;
-  orc_draw(c, i, k, ORC_TAG_PMX, p, C->key, wm);
-  int any = 0;
-  for (int u = 0; u < r; ++u) {
-    uint64_t T = any ? C->tpm : C->tfirst[r - u];
-    if ((uint64_t)wm[u] < T) {
-      mut[u] = T;
-      any = 1;
-    }
-  }
-}
-
 /* Offspring of one generation (Alg. 1 reproduction + evaluation): each
  * population mates inside its own neighbourhood (R6), SBX then PM (R7, R8) or
- * DE then PM (R26), then objectives and constraints. The variation words come
- * one per variable from the VAR block of its chunk of four (R7). Outputs
- * population-major; mate may be NULL. */
+ * DE then PM (R26), then objectives and constraints. Outputs population-major; mate may be NULL. */
 void orc_reproduce(const orc_problem *P, const orc_cfg *C, uint32_t k, const double *X0,
                    const double *X1, double *Xo, double *Fo, double *CVo, double *CMo,
                    int32_t *mate) {
@@ -775,27 +738,18 @@ void orc_reproduce(const orc_problem *P, const orc_cfg *C, uint32_t k, const dou
       const double *a = X[p] + (size_t)pa * d, *b = X[p] + (size_t)pb * d;
       const double *xi = X[p] + (size_t)i * d;
       double *c = Xo + (size_t)p * nd + (size_t)i * d;
-      for (int32_t l0 = 0; l0 < d; l0 += 4) {
-        const uint32_t ch = (uint32_t)(l0 >> 2);
-        const int32_t r = (d - l0) < 4 ? (d - l0) : 4;
-        uint32_t wm[4];
-        uint64_t mut[4];
-        orc_draw(ch, (uint32_t)i, k, ORC_TAG_VAR, (uint32_t)p, C->key, v);
-        orc_pm_chunk(C, v, r, ch, (uint32_t)i, k, (uint32_t)p, wm, mut);
-        for (int32_t u = 0; u < r; ++u) {
-          const int32_t l = l0 + u;
-          const uint32_t wA = v[u];
-          double y;
-          if (C->op == ORC_OP_DE) {
-            y = orc_clip(xi[l] + C->de_f * (a[l] - b[l]), P->lb[l], P->ub[l]);
-          } else {
-            double sib;
-            y = a[l];
-            if (cross) orc_sbx_dim(a[l], b[l], wA, C->eta_c, &y, &sib);
-            y = orc_clip(y, P->lb[l], P->ub[l]);
-          }
-          c[l] = mut[u] ? orc_pm_dim(y, P->lb[l], P->ub[l], wm[u], mut[u], C->eta_m) : y;
+      for (int32_t l = 0; l < d; ++l) {
+        if ((l & 1) == 0)
+          orc_draw((uint32_t)(l >> 1), (uint32_t)i, k, ORC_TAG_VAR, (uint32_t)p, C->key, v);
+        uint32_t wA = v[2 * (l & 1)], wB = v[2 * (l & 1) + 1];
+        if (C->op == ORC_OP_DE) {
+          c[l] = orc_de_dim(xi[l], a[l], b[l], C->de_f, P->lb[l], P->ub[l], wB, C->tpm, C->eta_m);
+          continue;
         }
+        double ch = a[l], sib;
+        if (cross) orc_sbx_dim(a[l], b[l], wA, C->eta_c, &ch, &sib);
+        ch = orc_clip(ch, P->lb[l], P->ub[l]);
+        c[l] = orc_pm_dim(ch, P->lb[l], P->ub[l], wB, C->tpm, C->eta_m);
       }
       double *f = Fo + ((size_t)p * N + i) * m;
       orc_objectives(P, c, f);

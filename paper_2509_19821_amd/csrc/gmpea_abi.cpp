@@ -345,22 +345,6 @@ gmpea_status gmpea_init(const gmpea_problem *P, const gmpea_config *C, const gmp
   st.tpm = static_cast<uint64_t>(std::floor(pm * 4294967296.0));
   st.tpc = static_cast<uint64_t>(std::floor(pc * 4294967296.0));
   st.inv_tpm = st.tpm > 0 ? static_cast<float>(1.0 / static_cast<double>(st.tpm)) : 0.0f;
-  // chunk-level mutation sampling: P(a chunk of r variables holds a mutation)
-  // and the first mutation's conditional probability with s variables left
-  for (int r = 0; r < 5; ++r) {
-    st.tany[r] = 0;
-    st.tfirst[r] = 0;
-    st.inv_tfirst[r] = 0.0f;
-  }
-  for (int r = 1; r <= 4; ++r) {
-    double q = 1.0;
-    for (int j = 0; j < r; ++j) q *= (1.0 - pm);
-    const double p0 = 1.0 - q;
-    st.tany[r] = static_cast<uint32_t>(std::floor(p0 * 16777216.0));
-    st.tfirst[r] = r == 1 ? (uint64_t(1) << 32)
-                          : (p0 > 0 ? static_cast<uint64_t>(std::floor(pm / p0 * 4294967296.0)) : 0);
-    st.inv_tfirst[r] = st.tfirst[r] > 0 ? static_cast<float>(1.0 / static_cast<double>(st.tfirst[r])) : 0.0f;
-  }
   st.op = C->op;
   st.op1_rule = C->op1_rule;
   st.de_f = static_cast<float>(C->de_f > 0 ? C->de_f : 0.5);

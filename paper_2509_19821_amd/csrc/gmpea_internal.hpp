@@ -23,7 +23,6 @@ constexpr int kReplLanes = 64;
 constexpr uint32_t kTagInit = 1u;
 constexpr uint32_t kTagMate = 2u;
 constexpr uint32_t kTagVar = 3u;
-constexpr uint32_t kTagPmx = 4u;
 
 // Problem constants in the device precision, passed by value to every kernel
 // that evaluates F and CV.
@@ -68,9 +67,6 @@ struct DevState {
   uint32_t key0, key1;       // RNG key
   uint64_t tpm, tpc;         // mutation / crossover thresholds floor(p 2^32)
   float inv_tpm;             // 1 / tpm
-  uint32_t tany[5];          // floor(2^24 (1 - (1 - pm)^r)): some variable of an r-chunk mutates
-  uint64_t tfirst[5];        // floor(2^32 pm / (1 - (1 - pm)^s)): first mutation, s variables left
-  float inv_tfirst[5];       // 1 / tfirst
   float sbx_e;               // 1 / (eta_c + 1)
   float pm_p, pm_e;          // eta_m + 1, 1 / (eta_m + 1)
   int32_t op;                // 0: SBX then PM, 1: DE then PM

@@ -460,11 +460,8 @@ __global__ __launch_bounds__(kBlock) void k_rev_sort(int32_t n, int32_t t, const
 // Draws (the paper fixes no RNG; this counter layout is the library's): Philox
 // counter (c0, i, k, tag << 24 | p << 16) for offspring i of population p in
 // generation k. The MATE block (c0 = 0) gives the two neighbourhood positions
-// and the per-offspring crossing draw; VAR block c0 = q gives one word per
-// variable of chunk q (variables 4q .. 4q + 3): SBX's bits, and in bits 2..7
-// a 24-bit value for the chunk's mutation test; the PMX block c0 = q decides,
-// for a chunk that has a mutation, which of its variables mutate and with
-// which uniform.
+// and the per-offspring crossing draw; VAR block c0 = l >> 1 gives (wA, wB) for
+// variables l and l + 1: SBX's bits in wA, the mutation test and uniform in wB.
 // A group of LPO consecutive lanes builds one offspring: lane g of the group
 // takes the float4 chunks g, g + LPO, ... of the row, so with LPO = 8 the group
 // reads each parent row and writes the offspring row as whole 128-byte lines.
@@ -506,127 +503,43 @@ __device__ __forceinline__ void vary_body(const DevState &st, int L, int G) {
     const float4 *ub4 = reinterpret_cast<const float4 *>(st.prob.ub);
     const float4 *is4 = reinterpret_cast<const float4 *>(st.prob.inv_span);
     const uint32_t tagv = (kTagVar << 24) | tagp;
-    const uint32_t tagm = (kTagPmx << 24) | tagp;
     const int nq = st.stride >> 2;
     const bool de = st.op == 1;
     const float4 *rx = reinterpret_cast<const float4 *>(Xc + static_cast<size_t>(i) * st.stride);
-    bool flag_out = false;  // chunk_var's verdict: the chunk holds a mutation
-    // Mutations are sampled per chunk of four variables: the spare bits of the
-    // chunk's variation words decide whether any variable mutates; the rare
-    // chunks that do are finished in a second pass over a bit mask, so a wave
-    // does not evaluate the mutation while most of its lanes have none.
-    auto chunk_var = [&](int q) -> float4 {
+    const uint64_t T = st.tpm;
+    for (int q = g; q < nq; q += LPO) {
       const int l0 = q << 2;
-      const float4 va = ra[q], vb = rb[q], lo = lb4[q], hi = ub4[q];
-      const uint4 w4 = philox10(make_uint4(q, i, k, tagv), st.key0, st.key1);
+      const float4 va = ra[q], vb = rb[q], lo = lb4[q], hi = ub4[q], is = is4[q];
+      const uint4 r0 = philox10(make_uint4(2 * q, i, k, tagv), st.key0, st.key1);
+      uint4 r1w = make_uint4(0, 0, 0, 0);
+      if (l0 + 2 < st.d) r1w = philox10(make_uint4(2 * q + 1, i, k, tagv), st.key0, st.key1);
       float4 o = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
       if (de) {
         const float4 vx = rx[q];
         o.x = de1(vx.x, va.x, vb.x, lo.x, hi.x, st);
-        if (l0 + 1 < st.d) o.y = de1(vx.y, va.y, vb.y, lo.y, hi.y, st);
-        if (l0 + 2 < st.d) o.z = de1(vx.z, va.z, vb.z, lo.z, hi.z, st);
-        if (l0 + 3 < st.d) o.w = de1(vx.w, va.w, vb.w, lo.w, hi.w, st);
+        o.y = de1(vx.y, va.y, vb.y, lo.y, hi.y, st);
+        o.z = de1(vx.z, va.z, vb.z, lo.z, hi.z, st);
+        o.w = de1(vx.w, va.w, vb.w, lo.w, hi.w, st);
       } else {
-        o.x = sbx1(va.x, vb.x, w4.x, lo.x, hi.x, cross, st);
-        if (l0 + 1 < st.d) o.y = sbx1(va.y, vb.y, w4.y, lo.y, hi.y, cross, st);
-        if (l0 + 2 < st.d) o.z = sbx1(va.z, vb.z, w4.z, lo.z, hi.z, cross, st);
-        if (l0 + 3 < st.d) o.w = sbx1(va.w, vb.w, w4.w, lo.w, hi.w, cross, st);
+        o.x = sbx1(va.x, vb.x, r0.x, lo.x, hi.x, cross, st);
+        o.y = sbx1(va.y, vb.y, r0.z, lo.y, hi.y, cross, st);
+        o.z = sbx1(va.z, vb.z, r1w.x, lo.z, hi.z, cross, st);
+        o.w = sbx1(va.w, vb.w, r1w.z, lo.w, hi.w, cross, st);
       }
-      const uint32_t A = ((w4.x >> 2) & 63u) | (((w4.y >> 2) & 63u) << 6) |
-                         (((w4.z >> 2) & 63u) << 12) | (((w4.w >> 2) & 63u) << 18);
-      flag_out = A < st.tany[min(4, st.d - l0)];
-      return o;
-    };
-    auto chunk_mut = [&](int q, float4 o) -> float4 {
-      const int l0 = q << 2;
-      const int r = min(4, st.d - l0);
-      const uint4 wm4 = philox10(make_uint4(q, i, k, tagm), st.key0, st.key1);
-      const uint32_t wm[4] = {wm4.x, wm4.y, wm4.z, wm4.w};
-      float ov[4] = {o.x, o.y, o.z, o.w};
-      const float4 lo = lb4[q], hi = ub4[q], is = is4[q];
-      const float lov[4] = {lo.x, lo.y, lo.z, lo.w}, hiv[4] = {hi.x, hi.y, hi.z, hi.w};
-      const float isv[4] = {is.x, is.y, is.z, is.w};
-      bool any = false;
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        if (u < r) {
-          const uint64_t T = any ? st.tpm : st.tfirst[r - u];
-          const float invT = any ? st.inv_tpm : st.inv_tfirst[r - u];
-          if (static_cast<uint64_t>(wm[u]) < T) {
-            ov[u] = pm1(ov[u], wm[u], T, invT, lov[u], hiv[u], isv[u], st);
-            any = true;
-          }
-        }
-      }
-      return make_float4(ov[0], ov[1], ov[2], ov[3]);
-    };
-    if (nq <= 4 * LPO) {
-      // up to four chunks per lane: they stay in registers until final (four
-      // named values, not an array, so that a dynamic pick cannot send them to
-      // scratch memory)
-      const float4 zero4 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-      float4 k0 = zero4, k1 = zero4, k2 = zero4, k3 = zero4;
-      uint32_t flagged = 0;
-      if (g < nq) {
-        k0 = chunk_var(g);
-        flagged |= flag_out ? 1u : 0u;
-      }
-      if (g + LPO < nq) {
-        k1 = chunk_var(g + LPO);
-        flagged |= flag_out ? 2u : 0u;
-      }
-      if (g + 2 * LPO < nq) {
-        k2 = chunk_var(g + 2 * LPO);
-        flagged |= flag_out ? 4u : 0u;
-      }
-      if (g + 3 * LPO < nq) {
-        k3 = chunk_var(g + 3 * LPO);
-        flagged |= flag_out ? 8u : 0u;
-      }
-      while (flagged) {
-        const int it = __builtin_ctz(flagged);
-        flagged &= flagged - 1u;
-        float4 o = k0;
-        if (it == 1) o = k1;
-        if (it == 2) o = k2;
-        if (it == 3) o = k3;
-        const float4 nw = chunk_mut(g + it * LPO, o);
-        if (it == 0) k0 = nw;
-        if (it == 1) k1 = nw;
-        if (it == 2) k2 = nw;
-        if (it == 3) k3 = nw;
-      }
-      auto store_add = [&](int q, float4 o) {
-        const int l0 = q << 2;
-        ro[q] = o;
-        eval_add<M, FAM>(e, l0, o.x);
-        if (l0 + 1 < st.d) eval_add<M, FAM>(e, l0 + 1, o.y);
-        if (l0 + 2 < st.d) eval_add<M, FAM>(e, l0 + 2, o.z);
-        if (l0 + 3 < st.d) eval_add<M, FAM>(e, l0 + 3, o.w);
-      };
-      if (g < nq) store_add(g, k0);
-      if (g + LPO < nq) store_add(g + LPO, k1);
-      if (g + 2 * LPO < nq) store_add(g + 2 * LPO, k2);
-      if (g + 3 * LPO < nq) store_add(g + 3 * LPO, k3);
-    } else {
-      // long rows: each chunk is written once, a flagged one again after its
-      // mutation, and the sums are taken from the final row in the same order
-      uint32_t flagged = 0;
-      int it = 0;
-      for (int q = g; q < nq; q += LPO, ++it) {
-        ro[q] = chunk_var(q);
-        flagged |= flag_out ? (1u << (it & 31)) : 0u;
-        if ((it & 31) == 31 || q + LPO >= nq) {
-          const int it0 = it & ~31;
-          while (flagged) {
-            const int bit = __builtin_ctz(flagged);
-            flagged &= flagged - 1u;
-            const int qq = g + (it0 + bit) * LPO;
-            ro[qq] = chunk_mut(qq, ro[qq]);
-          }
-        }
-      }
-      e = eval_row<M, FAM, LPO>(st, ro, g, true);
+      // polynomial mutation of each variable whose word wB falls below tpm
+      if (r0.y < T) o.x = pm1(o.x, r0.y, T, st.inv_tpm, lo.x, hi.x, is.x, st);
+      if (l0 + 1 < st.d && r0.w < T) o.y = pm1(o.y, r0.w, T, st.inv_tpm, lo.y, hi.y, is.y, st);
+      if (l0 + 2 < st.d && r1w.y < T) o.z = pm1(o.z, r1w.y, T, st.inv_tpm, lo.z, hi.z, is.z, st);
+      if (l0 + 3 < st.d && r1w.w < T) o.w = pm1(o.w, r1w.w, T, st.inv_tpm, lo.w, hi.w, is.w, st);
+      // padding variables (beyond d) stay 0
+      if (l0 + 1 >= st.d) o.y = 0.0f;
+      if (l0 + 2 >= st.d) o.z = 0.0f;
+      if (l0 + 3 >= st.d) o.w = 0.0f;
+      eval_add<M, FAM>(e, l0, o.x);
+      if (l0 + 1 < st.d) eval_add<M, FAM>(e, l0 + 1, o.y);
+      if (l0 + 2 < st.d) eval_add<M, FAM>(e, l0 + 2, o.z);
+      if (l0 + 3 < st.d) eval_add<M, FAM>(e, l0 + 3, o.w);
+      ro[q] = o;
     }
   }
   // the sums over the group's chunks (and x1, x2 from chunk 0) -> F, CV, z

@@ -11,21 +11,7 @@ import cmop_inputs as ci
 from oracle import core
 from oracle.dense_alg2 import dense_select
 
-TAG_INIT, TAG_MATE, TAG_VAR, TAG_PMX = 1, 2, 3, 4
-
-
-def _chunk_thresholds(pm):
-    """R8 thresholds: P(any of r variables mutates) on 24 bits, and the
-    conditional probability of a first mutation with s variables left on 32
-    bits, from FP64 repeated products."""
-    tany, tfirst = [0] * 5, [0] * 5
-    for r in range(1, 5):
-        q = 1.0
-        for _ in range(r):
-            q *= 1.0 - pm
-        tany[r] = math.floor((1.0 - q) * 2.0**24)
-        tfirst[r] = 2**32 if r == 1 else math.floor(pm / (1.0 - q) * 2.0**32)
-    return tany, tfirst
+TAG_INIT, TAG_MATE, TAG_VAR = 1, 2, 3
 
 
 def _words(key, c0, i, k, tag, pop):
@@ -68,8 +54,6 @@ def _python_offspring(o, k):
     prob, dv, N, d, m = o.prob, o.dv, o.N, o.d, o.m
     key = dv["key"]
     eta_c, eta_m, tpm = dv["eta_c"], dv["eta_m"], dv["tpm"]
-    pm = 1.0 / d  # the workloads use the default pm = 1/d
-    tany, tfirst = _chunk_thresholds(pm)
     lb, ub = prob["lb"], prob["ub"]
     Xo = np.empty((2, N, d))
     Fo = np.empty((2, N, m))
@@ -83,23 +67,9 @@ def _python_offspring(o, k):
             if t > 1 and r2 >= r1:
                 r2 += 1
             a, b = o.X[p][o.B[p][i, r1]], o.X[p][o.B[p][i, r2]]
-            # which variables mutate: chunk-level test, then sequential conditionals
-            mut = {}
-            for l0 in range(0, d, 4):
-                v = _words(key, l0 >> 2, i, k, TAG_VAR, p)
-                r = min(4, d - l0)
-                A = sum(((v[u] >> 2) & 63) << (6 * u) for u in range(4))
-                if A < tany[r]:
-                    wm = _words(key, l0 >> 2, i, k, TAG_PMX, p)
-                    seen = False
-                    for u in range(r):
-                        T = tpm if seen else tfirst[r - u]
-                        if wm[u] < T:
-                            mut[l0 + u] = (wm[u], T)
-                            seen = True
             for l in range(d):
-                v = _words(key, l >> 2, i, k, TAG_VAR, p)
-                wA = v[l & 3]
+                v = _words(key, l >> 1, i, k, TAG_VAR, p)
+                wA, wB = v[2 * (l & 1)], v[2 * (l & 1) + 1]
                 c = a[l]
                 if wA & 1:  # crossed: beta from the SBX spread distribution
                     u = (wA >> 8) / 2.0**24
@@ -108,9 +78,8 @@ def _python_offspring(o, k):
                         beta = -beta
                     c = (1 + beta) / 2 * a[l] + (1 - beta) / 2 * b[l]
                 c = min(max(c, lb[l]), ub[l])
-                if l in mut:
-                    wB, T = mut[l]
-                    u = wB / T
+                if wB < tpm:
+                    u = wB / tpm
                     span = ub[l] - lb[l]
                     if u < 0.5:
                         dq = (2 * u + (1 - 2 * u) * (1 - (c - lb[l]) / span) ** (eta_m + 1)) ** (1 / (eta_m + 1)) - 1

@@ -300,64 +300,11 @@ def test_de_generation_wiring(oracle_core):
         for i in range(N):
             a, b = dbg["mate"][p][i]
             for l in range(d):
-                c0 = l >> 2
-                ctr = np.array([c0, i, o.gen, (3 << 24) | (p << 16)], dtype=np.uint32)
-                v = oracle_core.philox(ctr[None, :], key)[0]
-                _, mut = oracle_core.pm_chunk(dv, key, v, min(4, d - 4 * c0), c0, i, o.gen, p)
-                if mut[l & 3]:
+                ctr = np.array([l >> 1, i, o.gen, (3 << 24) | (p << 16)], dtype=np.uint32)
+                wB = int(oracle_core.philox(ctr[None, :], key)[0][2 * (l & 1) + 1])
+                if wB < dv["tpm"]:
                     continue
                 want = min(1.0, max(0.0, X[p][i, l] + 0.5 * (X[p][a, l] - X[p][b, l])))
                 assert dbg["Xo"][p][i, l] == pytest.approx(want, abs=1e-15)
                 checked += 1
     assert checked > 0.8 * 2 * N * d  # pm = 1/d mutates about one variable in d
-
-
-# ---------------------------------------------- chunk-level PM sampling ----
-# R8: which variables mutate is drawn per chunk of up to four variables; the
-# law must be independent Bernoulli(pm) per variable, and a mutating variable's
-# uniform must be uniform on [0, 1).
-
-def _chunk_draws(oracle_core, pm, r, n):
-    from oracle import core
-    prob = ci.make_problem(ci.FAMILY_SPHERE, 3, 8, 0, False, False, 0)
-    dv = core.derive(prob, dict(ci.method_config(10, 4, 0), pm=pm))
-    key = np.array(dv["key"], dtype=np.uint32)
-    rng = np.random.default_rng(int(pm * 1e6) + r)
-    V = rng.integers(0, 2**32, size=(n, 4), dtype=np.uint64).astype(np.uint32)
-    M = np.zeros((n, 4), dtype=bool)
-    U = []
-    for q in range(n):
-        wm, mut = core.pm_chunk(dv, key, V[q], r, q, 7, 3, 0)
-        for u in range(4):
-            if mut[u]:
-                M[q, u] = True
-                U.append(float(wm[u]) / float(mut[u]))
-    return M, np.array(U)
-
-
-@pytest.mark.parametrize("pm,r", [(0.1, 4), (0.25, 3), (0.1, 1), (0.5, 2)])
-def test_chunk_mutation_law_is_independent_bernoulli(oracle_core, pm, r):
-    n = 40000
-    M, U = _chunk_draws(oracle_core, pm, r, n)
-    assert not M[:, r:].any()                      # nothing past the chunk's end
-    for u in range(r):                             # marginal rate pm
-        assert abs(M[:, u].mean() - pm) < 5 * math.sqrt(pm * (1 - pm) / n)
-    for u in range(r):                             # pairwise independence
-        for v in range(u + 1, r):
-            both = (M[:, u] & M[:, v]).mean()
-            assert abs(both - pm * pm) < 5 * math.sqrt(pm * pm * (1 - pm * pm) / n)
-    counts = np.bincount(M[:, :r].sum(1), minlength=r + 1)   # Binomial(r, pm) counts
-    expect = np.array([math.comb(r, k) * pm**k * (1 - pm)**(r - k) for k in range(r + 1)]) * n
-    keep = expect > 5
-    assert stats.chisquare(counts[keep], expect[keep] * counts[keep].sum() / expect[keep].sum()).pvalue > 1e-4
-    assert stats.kstest(U, "uniform").pvalue > 1e-4  # the mutation's conditional uniform
-
-
-def test_chunk_mutation_extremes(oracle_core):
-    """pm = 1 mutates every variable; pm = 0 none."""
-    M, _ = _chunk_draws(oracle_core, 1.0, 4, 200)
-    assert M.all()
-    from oracle import core
-    prob = ci.make_problem(ci.FAMILY_SPHERE, 3, 8, 0, False, False, 0)
-    dv = core.derive(prob, dict(ci.method_config(10, 4, 0), pm=1e-300))
-    assert dv["tany"][4] == 0   # effectively zero: no chunk is ever flagged
