@@ -183,6 +183,40 @@ def serving(g, ci, window_s=5.0, rate=200.0):
     return {k: (round(v, 5) if isinstance(v, float) else v) for k, v in out.items()}
 
 
+def sweep(g, ci, sizes=(100, 1000, 5000, 10000, 100000, 1000000), gens=50, cpu_gens=3):
+    """Generation time against population size on the large workload's shape
+    (m = 3, d = 100, T = 32, four rings and the equality): the GPU (graph
+    replay, inputs resident) and, up to N = 1e5, the CPU oracle on this host's
+    cores. One JSON object per size on stdout."""
+    from oracle import core
+    cores = core.set_threads(0)
+    for n_req in sizes:
+        prob, cfg, _ = ci.workload_large(0)
+        cfg = dict(cfg, n_req=n_req)
+        gp = g.Gmpea(prob, cfg)
+        gp.step(5)
+        gp.step(0)
+        gp.sync()
+        t0 = time.perf_counter()
+        gp.step(gens)
+        gp.sync()
+        gpu_us = (time.perf_counter() - t0) / gens * 1e6
+        n = gp.n
+        gp.close()
+        row = {"n_requested": n_req, "n": n, "gpu_us_per_gen": round(gpu_us, 2),
+               "gpu_offspring_per_s": round(2 * n / (gpu_us * 1e-6), 1)}
+        if n_req <= 100000:
+            o = core.Oracle(prob, cfg)
+            o.step()
+            t0 = time.perf_counter()
+            for _ in range(cpu_gens):
+                o.step()
+            cpu_us = (time.perf_counter() - t0) / cpu_gens * 1e6
+            row.update({"cpu_us_per_gen": round(cpu_us, 1), "cpu_cores": int(cores),
+                        "gpu_over_cpu": round(cpu_us / gpu_us, 1)})
+        print(json.dumps(row), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -193,6 +227,9 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serve-window", type=float, default=5.0)
+    ap.add_argument("--sweep", action="store_true",
+                    help="print generation time against population size (GPU and CPU oracle) "
+                         "instead of the benchmark line")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -203,6 +240,10 @@ def main():
 
     import cmop_inputs as ci
     import paper_2509_19821_amd as g
+
+    if args.sweep:
+        sweep(g, ci)
+        return
 
     prob, cfg, K_total = ci.workload_large(0)
     log("bench: init large workload")
