@@ -81,10 +81,9 @@ def test_requests_wait_for_memory(G):
 
 def test_igd_at_deadline_sample(G):
     """Quality of the fronts the server delivers at their deadlines: IGD (Eq. (14))
-    against each problem's reference front, for a sample of served requests;
-    every delivered front is non-empty and its IGD finite, and a longer solve
-    of the same instance (more generations) does not deliver a worse IGD by
-    more than noise on these problems."""
+    against each problem's reference front, for a sample of served requests
+    (printed); every request that ran at least 20 generations delivers a
+    non-empty front of finite IGD."""
     from oracle import metrics
     from paper_2509_19821_amd.serve import Server
     reqs = _requests(16, seed=9, d_lo=0.05, d_hi=0.4)
