@@ -36,21 +36,14 @@ namespace gmpea {
 // Counter RNG: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).
 // ----------------------------------------------------------------------------
 // Each round's two 32 x 32 -> 64-bit products are written as 64-bit multiplies
-// so that each becomes one v_mad_u64_u32 (high and low words together), and
-// each three-way XOR with the (wave-uniform) round key is one v_xor3_b32.
-__device__ __forceinline__ uint32_t xor3_key(uint32_t a, uint32_t b, uint32_t key) {
-  uint32_t r;
-  asm("v_xor3_b32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "s"(key));
-  return r;
-}
-
+// so that each becomes one v_mad_u64_u32 (high and low words together).
 __device__ __forceinline__ uint4 philox10(uint4 c, uint32_t k0, uint32_t k1) {
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
     const uint64_t p0 = static_cast<uint64_t>(0xD2511F53u) * c.x;
     const uint64_t p1 = static_cast<uint64_t>(0xCD9E8D57u) * c.z;
-    c = make_uint4(xor3_key(static_cast<uint32_t>(p1 >> 32), c.y, k0), static_cast<uint32_t>(p1),
-                   xor3_key(static_cast<uint32_t>(p0 >> 32), c.w, k1), static_cast<uint32_t>(p0));
+    c = make_uint4(static_cast<uint32_t>(p1 >> 32) ^ c.y ^ k0, static_cast<uint32_t>(p1),
+                   static_cast<uint32_t>(p0 >> 32) ^ c.w ^ k1, static_cast<uint32_t>(p0));
     k0 += 0x9E3779B9u;
     k1 += 0xBB67AE85u;
   }
