@@ -62,14 +62,16 @@ def make_problem(family: int, m: int, d: int, n_ring: int, linear: bool, equalit
 def method_config(n_req: int, T: int, seed: int, agg: int = 0, theta: float = 5.0,
                   t1: int = 0, t2: int = 0, eta_c: float = 20.0, eta_m: float = 20.0,
                   pc: float = 1.0, pm: float = 0.0, op: int = 0, de_f: float = 0.5,
-                  op1_rule: int = 0) -> dict:
+                  op1_rule: int = 0, h_outer: int = 0, h_inner: int = 0) -> dict:
     """Raw method parameters (the paper's settings: theta = 5, eta = 20, pc = 1,
     pm = 1/d written as 0, t1 = T/2 and t2 = 2T written as 0; op 0 = SBX, op 1 =
-    DE with F = 0.5 and CR = 1)."""
+    DE with F = 0.5 and CR = 1). h_outer > 0 gives the reference set's layer
+    divisions explicitly (h_inner > 0 adds an inner layer) instead of n_req."""
     return {"n_req": int(n_req), "T": int(T), "t1": int(t1), "t2": int(t2), "agg": int(agg),
             "theta": float(theta), "eta_c": float(eta_c), "eta_m": float(eta_m),
             "pc": float(pc), "pm": float(pm), "seed": int(seed), "op": int(op),
-            "de_f": float(de_f), "op1_rule": int(op1_rule)}
+            "de_f": float(de_f), "op1_rule": int(op1_rule), "h_outer": int(h_outer),
+            "h_inner": int(h_inner)}
 
 
 # --------------------------------------------------------------------------
@@ -96,7 +98,32 @@ def workload_large(seed: int = 0):
     return prob, method_config(100000, 32, seed), 200
 
 
-WORKLOADS = {"small": workload_small, "medium": workload_medium, "large": workload_large}
+def workload_many5(seed: int = 0):
+    """Five objectives (sphere family), d = 14, one layer of N = 210 (H = 6),
+    T = 20, three rings + linear bound, 300 generations."""
+    prob = make_problem(FAMILY_SPHERE, 5, 14, 3, True, False, seed)
+    return prob, method_config(210, 20, seed), 300
+
+
+def workload_many8(seed: int = 0):
+    """Eight objectives (sphere family), d = 17, two layers (H = 3 and 2:
+    120 + 36 = 156 vectors), T = 20, two rings + linear bound, 300 generations."""
+    prob = make_problem(FAMILY_SPHERE, 8, 17, 2, True, False, seed)
+    return prob, method_config(156, 20, seed, h_outer=3, h_inner=2), 300
+
+
+def workload_many_large(seed: int = 0, m: int = 8):
+    """Many-objective throughput shape: m objectives (sphere family), d = 100,
+    two layers of about 1e5 vectors per population (m = 5: H = 35 and 22,
+    82,251 + 14,950; m = 8: H = 13 and 10, 77,520 + 19,448), T = 32, four rings
+    + linear bound, 200 generations."""
+    layers = {5: (35, 22), 8: (13, 10)}[m]
+    prob = make_problem(FAMILY_SPHERE, m, 100, 4, True, False, seed)
+    return prob, method_config(2, 32, seed, h_outer=layers[0], h_inner=layers[1]), 200
+
+
+WORKLOADS = {"small": workload_small, "medium": workload_medium, "large": workload_large,
+             "many5": workload_many5, "many8": workload_many8}
 
 
 def batch_instances(count: int = 256, master_seed: int = 0, n_lo: int = 100,

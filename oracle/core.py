@@ -133,6 +133,24 @@ def dd_lattice(m: int, H: int) -> np.ndarray:
     return K
 
 
+def reference_set(m: int, H1: int, H2: int = 0):
+    """Reference vectors W (FP64, N x m) and the same vectors as integer
+    coordinates on a common denominator (exact neighbour distances).
+    One layer (H2 = 0): the Das-Dennis lattice k / H1 of Alg. 1's input, with
+    integer coordinates k. Two layers (reading R28, for many objectives): the
+    boundary lattice k / H1 followed by the lattice k / H2 moved halfway to the
+    centroid, (k / H2 + 1 / m) / 2, each in lexicographic order; on the
+    denominator 2 m H1 H2 these are 2 m H2 k and m H1 k + H1 H2."""
+    K1 = dd_lattice(m, H1).astype(np.int64)
+    if H2 <= 0:
+        return K1.astype(np.float64) / float(H1), K1.astype(np.int32)
+    K2 = dd_lattice(m, H2).astype(np.int64)
+    W = np.vstack([K1.astype(np.float64) / float(H1),
+                   (K2.astype(np.float64) / float(H2) + 1.0 / m) * 0.5])
+    Ks = np.vstack([K1 * (2 * m * H2), K2 * (m * H1) + H1 * H2])
+    return W, Ks.astype(np.int32)
+
+
 def knn(K: np.ndarray, t: int) -> np.ndarray:
     K = np.ascontiguousarray(K, dtype=np.int32)
     B = np.empty((K.shape[0], t), dtype=np.int32)
@@ -225,8 +243,15 @@ def derive(prob: dict, cfg: dict) -> dict:
     t1 = T/2 and t2 = 2T follow the parameter settings unless overridden;
     pm = 0 means 1/d; thresholds are floor(p 2^32) (R8); key = seed words (R5)."""
     m, d = int(prob["m"]), int(prob["d"])
-    H = dd_H(m, int(cfg["n_req"]))
-    N = dd_count(m, H)
+    H1, H2 = int(cfg.get("h_outer", 0)), int(cfg.get("h_inner", 0))
+    if H2 > 0 and H1 <= 0:
+        raise ValueError("an inner layer needs an outer one")
+    if H1 > 0:  # the layers are given (R28)
+        H = H1
+        N = dd_count(m, H1) + (dd_count(m, H2) if H2 > 0 else 0)
+    else:
+        H, H2 = dd_H(m, int(cfg["n_req"])), 0
+        N = dd_count(m, H)
     T = int(cfg["T"])
     t1 = int(cfg["t1"]) if cfg["t1"] > 0 else T // 2
     t2 = int(cfg["t2"]) if cfg["t2"] > 0 else 2 * T
@@ -234,7 +259,7 @@ def derive(prob: dict, cfg: dict) -> dict:
         raise ValueError("neighbourhood sizes must satisfy 1 <= t <= N_eff")
     pm = float(cfg["pm"]) if cfg["pm"] > 0 else 1.0 / d
     seed = int(cfg["seed"]) & 0xFFFFFFFFFFFFFFFF
-    return {"m": m, "d": d, "H": H, "N": N, "t": (t1, t2),
+    return {"m": m, "d": d, "H": H, "H2": H2, "N": N, "t": (t1, t2),
             "tpm": int(np.floor(pm * 4294967296.0)), "tpc": int(np.floor(float(cfg["pc"]) * 4294967296.0)),
             "key": (seed & 0xFFFFFFFF, seed >> 32), "agg": int(cfg["agg"]),
             "theta": float(cfg["theta"]), "eta_c": float(cfg["eta_c"]),
@@ -252,8 +277,7 @@ class Oracle:
         dv = derive(prob, cfg)
         self.dv = dv
         self.m, self.d, self.N = dv["m"], dv["d"], dv["N"]
-        self.K = dd_lattice(self.m, dv["H"])
-        self.W = self.K.astype(np.float64) / float(dv["H"])
+        self.W, self.K = reference_set(self.m, dv["H"], dv["H2"])
         self.B = [knn(self.K, dv["t"][0]), knn(self.K, dv["t"][1])]
         self.key = np.array(dv["key"], dtype=np.uint32)
         self._cfg = Cfg(self.m, self.d, self.N, (ctypes.c_int32 * 2)(*dv["t"]),
