@@ -30,7 +30,9 @@ if ROOT not in sys.path:
 
 METRIC = "offspring evaluated+selected/sec (FP32) and % HBM roofline; batched vs plain speedup at equal IGD"
 HBM_PEAK_GBS = 8000.0
-KERNEL_SRC = os.path.join(ROOT, "paper_2509_19821_amd", "csrc", "gmpea_kernels.hip")
+KERNEL_SRC = [os.path.join(ROOT, "paper_2509_19821_amd", "csrc", f)
+              for f in ("gmpea_device.hpp", "gmpea_kernels.hip", "gmpea_kernels_wide.hip",
+                        "gmpea_internal.hpp")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_large.json")
 
 
@@ -58,8 +60,13 @@ def bytes_model(n, m, d, t, rho):
 
 
 def kernel_hash():
-    with open(KERNEL_SRC, "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
+    """sha256[:16] over the kernel sources (device code, both instantiation
+    units, the shared declarations), in that order."""
+    h = hashlib.sha256()
+    for path in KERNEL_SRC:
+        with open(path, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic(kernel):

@@ -16,7 +16,9 @@
  *    (hipMalloc when none is given).
  *  - The device computes in FP32; FP64 problem constants are rounded once.
  *  - Population rows are in ascending subproblem order. Subproblem i is the
- *    i-th Das-Dennis reference vector in lexicographic order.
+ *    i-th reference vector: the Das-Dennis lattice in lexicographic order, or
+ *    for a two-layer set (gmpea_config.h_outer / h_inner) the outer layer's
+ *    lattice followed by the inner layer's.
  *  - A handle is used by one host thread at a time; separate handles are
  *    independent and may share a stream.
  */
@@ -54,8 +56,10 @@ enum { GMPEA_OP_SBX = 0, GMPEA_OP_DE = 1 };
 /* Problem families (objective functions of the synthetic CMOPs). */
 enum {
   GMPEA_FAMILY_CURVE = 0, /* m = 2: f1 = x1, g = 1 + 9 mean(x2..xd), f2 = g (1 - sqrt(f1/g)) */
-  GMPEA_FAMILY_SPHERE = 1 /* m in {2, 3}: F = (1 + g) s(angles pi x_l / 2, l < m),
-                             g = sum_{l >= m} (x_l - 0.5)^2; s is the unit sphere octant */
+  GMPEA_FAMILY_SPHERE = 1 /* 2 <= m <= GMPEA_MAX_M, d >= m - 1: with angles
+                             th_l = pi x_l / 2 (l < m - 1) and g = sum_{l >= m-1}
+                             (x_l - 0.5)^2 (0-based l), f_k = (1 + g) prod_{j <
+                             m-1-k} cos th_j, times sin th_{m-1-k} for k > 0 */
 };
 
 /* Aggregation (Eq. (7) and its Tchebycheff alternative named beside it). */
@@ -79,7 +83,7 @@ enum {
  *                         (before OP1), same layouts; read only
  *   Z      m      float   ideal point (shared by both populations); pop ignored
  *   GEN    1      int64   generations completed; pop ignored
- *   W      N x m  float   reference vectors (read only; pop ignored)
+ *   W      N x m  float   reference vectors, the raw weights (read only; pop ignored)
  *   B      N x t  int32   neighbourhood of population `pop` (read only)
  *   MATE   N x 2  int32   last generation's parent rows of population `pop`
  *   OP1    N      uint8   1 if population `pop`'s new offspring i came from the
@@ -103,7 +107,7 @@ enum {
   GMPEA_BUF_WIN = 12
 };
 
-#define GMPEA_MAX_M 3     /* objectives supported by this build */
+#define GMPEA_MAX_M 8     /* objectives supported by this build */
 #define GMPEA_MAX_RING 8  /* ring constraints supported by this build */
 
 /* A CMOP instance (Eq. (1)): minimise F(x) over the box [lb, ub]^d subject to
@@ -128,7 +132,8 @@ typedef struct {
  * the paper's default where one exists. */
 typedef struct {
   int32_t n_req;   /* requested reference vectors per population; the library uses
-                      the smallest Das-Dennis count N >= n_req (needs n_req >= 2) */
+                      the smallest Das-Dennis count N >= n_req (needs n_req >= 2
+                      unless h_outer is set) */
   int32_t T;       /* base neighbourhood size: t1 = T/2, t2 = 2T unless set below */
   int32_t t1, t2;  /* population 1 (small) and population 2 (large) neighbourhoods */
   int32_t agg;     /* GMPEA_AGG_PBI (default) or GMPEA_AGG_TCHE */
@@ -147,6 +152,16 @@ typedef struct {
                        GMPEA_OP1_FPR (Alg. 2: lower CV, then lower aggregation) or
                        GMPEA_OP1_FEASIBLE_FIRST (its prose: a feasible offspring
                        wins, otherwise the lower aggregation) */
+  int32_t h_outer;  /* > 0: the reference set is given by layers instead of n_req
+                       (the paper names many objectives as future work and fixes
+                       no set for them): the Das-Dennis lattice k / h_outer ... */
+  int32_t h_inner;  /* ... followed, when > 0, by the lattice k / h_inner moved
+                       halfway to the centroid, (k / h_inner + 1 / m) / 2. Then
+                       N = C(h_outer + m - 1, m - 1) + C(h_inner + m - 1, m - 1)
+                       and neighbourhoods use exact distances of the vectors as
+                       integers over 2 m h_outer h_inner. Building them is a
+                       host search of O(N^2 m) (threaded): about a second at
+                       N = 1e5. */
 } gmpea_config;
 
 enum { GMPEA_OP1_FPR = 0, GMPEA_OP1_FEASIBLE_FIRST = 1 };
@@ -164,7 +179,8 @@ typedef struct {
   int32_t n;          /* N, rows per population */
   int32_t m, d;
   int32_t t1, t2;
-  int32_t H;          /* Das-Dennis divisions */
+  int32_t H;          /* Das-Dennis divisions (of the outer layer) */
+  int32_t H2;         /* inner layer's divisions, 0 for one layer */
   int64_t generation; /* generations completed */
   float z[GMPEA_MAX_M];
   int64_t replaced[2];   /* parent slots replaced, summed over all generations */
@@ -180,8 +196,11 @@ typedef struct {
  * enqueued on that stream; the call returns once the handle is ready.
  * The HIP runtime in the process must be at least as new as the HIP toolchain
  * the library was built with; otherwise EUNSUPPORTED (nothing is launched).
+ * With m > 3 the F/CV records and W rows take two or three float4 instead of
+ * one, and the generation runs kernels instantiated for that m.
  * Errors: EINVAL (bad sizes: m, d < 2 for the curve family, lb >= ub, t > N,
- * n_ring out of range, ...), EUNSUPPORTED (m > GMPEA_MAX_M), ENOMEM, EHIP. */
+ * n_ring out of range, h_inner without h_outer, ...), EUNSUPPORTED
+ * (m > GMPEA_MAX_M), ENOMEM, EHIP. */
 gmpea_status gmpea_init(const gmpea_problem *problem, const gmpea_config *config,
                         const gmpea_allocator *allocator, void *hip_stream, gmpea_t *out);
 
@@ -260,6 +279,19 @@ gmpea_status gmpea_philox(const uint32_t *ctr, int64_t n, uint64_t seed, uint32_
  * is given. */
 gmpea_status gmpea_lattice(int32_t m, int32_t n_req, int32_t t, int32_t cap_rows, int32_t *K,
                            int32_t *B, int32_t *H_out, int32_t *n_out);
+
+/* The layered reference set of gmpea_config.h_outer / h_inner (many
+ * objectives) and its neighbourhoods, on the host with no GPU work, as
+ * gmpea_init builds them. K (N x m, caller-owned; may be NULL): the vectors as
+ * integers over the denominator 2 m h_outer h_inner (h_outer for one layer),
+ * the outer layer's rows first, each layer in ascending lexicographic order.
+ * B (N x t; may be NULL): for each row the t rows nearest by exact squared
+ * distance, ties by ascending index (a row is first in its own list unless an
+ * earlier row holds the same vector). *n_out (may be NULL) receives N. EINVAL
+ * for m outside [2, GMPEA_MAX_M], h_outer < 1, h_inner < 0 or t outside
+ * [1, N]; ECAPACITY (with *n_out set) when cap_rows < N and K or B is given. */
+gmpea_status gmpea_reference_set(int32_t m, int32_t h_outer, int32_t h_inner, int32_t t,
+                                 int32_t cap_rows, int32_t *K, int32_t *B, int32_t *n_out);
 
 /* ---------------------------------------------------------------------------
  * Pools: many independent instances (uneven N, d, m, constraint counts) stay

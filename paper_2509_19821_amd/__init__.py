@@ -8,4 +8,4 @@ in the library's kernels. Importing fails loudly when the library is not built
 """
 from .gmpea import (AGG_PBI, AGG_TCHE, BUF, FAMILY_CURVE, FAMILY_SPHERE, FRONT_FEASIBLE_ND,  # noqa: F401
                     FRONT_POP1, FRONT_POP2, OP_DE, OP_SBX, DeviceBuffer, Gmpea, GmpeaError, Pool, copy,
-                    device_count, lattice, lib, lib_path, philox)
+                    device_count, lattice, lib, lib_path, philox, reference_set)

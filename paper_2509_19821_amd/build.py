@@ -12,7 +12,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OUT_DIR = os.path.join(PKG, "_build")
 LIB = os.path.join(OUT_DIR, "libgmpea.so")
-SOURCES = ["gmpea_kernels.hip", "gmpea_abi.cpp", "lattice.cpp"]
+SOURCES = ["gmpea_kernels.hip", "gmpea_kernels_wide.hip", "gmpea_abi.cpp", "lattice.cpp"]
 ARCH = "gfx950"
 
 

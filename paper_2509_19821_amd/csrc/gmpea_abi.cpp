@@ -39,7 +39,7 @@ struct gmpea_s {
   hipStream_t stream = nullptr;
   bool own_stream = false;
   DevState st{};
-  int32_t H = 0;
+  int32_t H = 0, H2 = 0;  // reference-set divisions (outer, inner; H2 = 0: one layer)
   bool record = false;
   std::vector<std::pair<void *, size_t>> allocs;
   size_t bytes = 0;
@@ -161,8 +161,14 @@ gmpea_status validate(const gmpea_problem *P, const gmpea_config *C) {
     for (int32_t l = 0; l < P->d; ++l)
       if (!(P->lb[l] < P->ub[l]) || !std::isfinite(P->lb[l]) || !std::isfinite(P->ub[l]))
         return fail(GMPEA_EINVAL, "gmpea_init: need finite lb < ub in every variable");
-  if (C->n_req < 2) return fail(GMPEA_EINVAL, "gmpea_init: n_req must be at least 2");
-  if (C->n_req > (1 << 26)) return fail(GMPEA_EUNSUPPORTED, "gmpea_init: n_req too large");
+  if (C->h_outer < 0 || C->h_inner < 0) return fail(GMPEA_EINVAL, "gmpea_init: negative layer divisions");
+  if (C->h_inner > 0 && C->h_outer == 0)
+    return fail(GMPEA_EINVAL, "gmpea_init: an inner layer (h_inner) needs an outer one (h_outer)");
+  if (C->h_outer == 0 && C->n_req < 2) return fail(GMPEA_EINVAL, "gmpea_init: n_req must be at least 2");
+  if (C->h_outer == 0 && C->n_req > (1 << 26))
+    return fail(GMPEA_EUNSUPPORTED, "gmpea_init: n_req too large");
+  if (C->h_outer > 4096 || C->h_inner > 4096)
+    return fail(GMPEA_EUNSUPPORTED, "gmpea_init: layer divisions too large");
   if (C->agg != GMPEA_AGG_PBI && C->agg != GMPEA_AGG_TCHE)
     return fail(GMPEA_EINVAL, "gmpea_init: unknown aggregation");
   if (C->T < 0 || C->t1 < 0 || C->t2 < 0) return fail(GMPEA_EINVAL, "gmpea_init: negative size");
@@ -278,9 +284,17 @@ gmpea_status gmpea_init(const gmpea_problem *P, const gmpea_config *C, const gmp
   if (A && (!A->alloc || !A->free)) return fail(GMPEA_EINVAL, "gmpea_init: incomplete allocator");
 
   const int32_t m = P->m, d = P->d;
-  const int32_t H = dd_divisions(m, C->n_req);
-  const int64_t n64 = dd_count(m, H);
+  const bool layered = C->h_outer > 0;
+  const int32_t H = layered ? C->h_outer : dd_divisions(m, C->n_req);
+  const int32_t H2 = layered ? C->h_inner : 0;
+  // counts grow fast with m: compare in floating point before any exact count
+  const double approx = std::exp(std::lgamma(H + m) - std::lgamma(m) - std::lgamma(H + 1.0)) +
+                        (H2 > 0 ? std::exp(std::lgamma(H2 + m) - std::lgamma(m) - std::lgamma(H2 + 1.0)) : 0.0);
+  if (approx > double(1 << 27)) return fail(GMPEA_EUNSUPPORTED, "gmpea_init: population too large");
+  const int64_t n64 = refset_count(m, H, H2);
   if (n64 > (1 << 27)) return fail(GMPEA_EUNSUPPORTED, "gmpea_init: population too large");
+  if (H2 > 0 && int64_t(2) * m * H * H2 * std::max(H, H2) >= (int64_t(1) << 31))
+    return fail(GMPEA_EUNSUPPORTED, "gmpea_init: layer divisions too large for exact distances");
   const int32_t N = static_cast<int32_t>(n64);
   const int32_t T = C->T;
   const int32_t t1 = C->t1 > 0 ? C->t1 : T / 2;
@@ -310,12 +324,15 @@ gmpea_status gmpea_init(const gmpea_problem *P, const gmpea_config *C, const gmp
     h->own_stream = true;
   }
   h->H = H;
+  h->H2 = H2;
   h->record = C->record != 0;
 
-  // ---- neighbourhood offsets (host, a few KB); the tables are built on the device ----
+  // ---- neighbourhood offsets (host, a few KB) when the device builds the tables:
+  // one Das-Dennis layer with m <= 3; otherwise the host builds them ----
   const int32_t ts[2] = {t1, t2};
+  const bool dev_tables = m <= 3 && H2 == 0;
   std::vector<int32_t> offs;
-  neighbour_offsets(m, H, std::max(t1, t2), offs);
+  if (dev_tables) neighbour_offsets(m, H, std::max(t1, t2), offs);
   const int32_t noffs = static_cast<int32_t>(offs.size() / 2);
 
   // ---- device state ----
@@ -324,6 +341,7 @@ gmpea_status gmpea_init(const gmpea_problem *P, const gmpea_config *C, const gmp
   st.m = m;
   st.d = d;
   st.stride = (d + 3) & ~3;
+  st.rq = rec_quads(m);
   st.nblk = (N + kBlock - 1) / kBlock;
   st.t[0] = t1;
   st.t[1] = t2;
@@ -378,18 +396,18 @@ gmpea_status gmpea_init(const gmpea_problem *P, const gmpea_config *C, const gmp
       st.X[p] = c.take<float>(rows * st.stride);
       st.rsrc[p] = c.take<int32_t>(rows);
       st.XO[p] = c.take<float>(rows * st.stride);
-      st.FC[p] = c.take<float4>(rows);
-      st.FCO[p] = c.take<float4>(rows);
-      st.FCN[p] = c.take<float4>(rows);
+      st.FC[p] = c.take<float4>(rows * st.rq);
+      st.FCO[p] = c.take<float4>(rows * st.rq);
+      st.FCN[p] = c.take<float4>(rows * st.rq);
       st.B[p] = c.take<int32_t>(static_cast<size_t>(N) * ts[p]);
       st.rhead[p] = c.take<int32_t>(static_cast<size_t>(N) * ts[p]);
       st.rtoff[p] = c.take<int32_t>(static_cast<size_t>(N) + 1);
       st.mate[p] = h->record ? c.take<int32_t>(rows * 2) : nullptr;
       st.win[p] = h->record ? c.take<int32_t>(rows) : nullptr;
     }
-    st.W = c.take<float4>(rows);
+    st.W = c.take<float4>(rows * st.rq);
     st.src = c.take<uint8_t>(rows);
-    st.zkey = c.take<uint32_t>(4);
+    st.zkey = c.take<uint32_t>(kMaxM);
     st.gen = c.take<uint32_t>(4);
     st.repl = c.take<unsigned long long>(2 * kReplLanes);
     d_offs = c.take<int2>(noffs);
@@ -427,14 +445,14 @@ gmpea_status gmpea_init(const gmpea_problem *P, const gmpea_config *C, const gmp
   cp(lb, lbf.data(), st.stride * sizeof(float));
   cp(ub, ubf.data(), st.stride * sizeof(float));
   cp(inv_span, isf.data(), st.stride * sizeof(float));
-  cp(d_offs, offs.data(), offs.size() * sizeof(int32_t));
+  if (noffs > 0) cp(d_offs, offs.data(), offs.size() * sizeof(int32_t));
   zero(d_flag, 0, 4 * sizeof(uint32_t));
   for (int p = 0; p < 2; ++p) {
     zero(st.X[p], 0, rows * st.stride * sizeof(float));
     zero(st.XO[p], 0, rows * st.stride * sizeof(float));
-    zero(st.FC[p], 0, rows * sizeof(float4));
-    zero(st.FCO[p], 0, rows * sizeof(float4));
-    zero(st.FCN[p], 0, rows * sizeof(float4));
+    zero(st.FC[p], 0, rows * st.rq * sizeof(float4));
+    zero(st.FCO[p], 0, rows * st.rq * sizeof(float4));
+    zero(st.FCN[p], 0, rows * st.rq * sizeof(float4));
     zero(const_cast<int32_t *>(st.rtoff[p]), 0, (static_cast<size_t>(N) + 1) * sizeof(int32_t));
     zero(const_cast<int32_t *>(st.rhead[p]), 0xFF, static_cast<size_t>(N) * ts[p] * sizeof(int32_t));
     if (h->record) {
@@ -443,16 +461,41 @@ gmpea_status gmpea_init(const gmpea_problem *P, const gmpea_config *C, const gmp
     }
   }
   zero(st.src, 0, rows);
-  zero(st.zkey, 0xFF, 4 * sizeof(uint32_t));
+  zero(st.zkey, 0xFF, kMaxM * sizeof(uint32_t));
   zero(st.gen, 0, 4 * sizeof(uint32_t));
   zero(st.repl, 0, 2 * kReplLanes * sizeof(unsigned long long));
-  // reference vectors and neighbourhoods on the device
-  if (e == hipSuccess)
-    e = launch_tables(m, N, H, d_offs, noffs, t1, t2, C->agg, st.W, const_cast<int32_t *>(st.B[0]),
-                      const_cast<int32_t *>(st.B[1]), d_flag, h->stream);
+  // reference vectors and neighbourhoods: on the device for one Das-Dennis layer
+  // with m <= 3, else on the host (W rounded once from FP64, rq float4 per row)
   uint32_t incomplete = 0;
-  if (e == hipSuccess) e = hipMemcpyAsync(&incomplete, d_flag, sizeof(uint32_t), hipMemcpyDeviceToHost, h->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (dev_tables) {
+    if (e == hipSuccess)
+      e = launch_tables(m, N, H, d_offs, noffs, t1, t2, C->agg, st.W, const_cast<int32_t *>(st.B[0]),
+                        const_cast<int32_t *>(st.B[1]), d_flag, h->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(&incomplete, d_flag, sizeof(uint32_t), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  } else if (e == hipSuccess) {
+    std::vector<int32_t> K, Bh;
+    std::vector<double> Wd;
+    refset(m, H, H2, K, &Wd);
+    std::vector<float> Wf(static_cast<size_t>(N) * st.rq * 4, 0.0f);
+    for (int32_t i = 0; i < N; ++i) {
+      double nrm = 0.0;
+      for (int32_t a = 0; a < m; ++a) nrm += Wd[static_cast<size_t>(i) * m + a] * Wd[static_cast<size_t>(i) * m + a];
+      nrm = std::sqrt(nrm);
+      for (int32_t a = 0; a < m; ++a) {
+        const double w = Wd[static_cast<size_t>(i) * m + a];
+        Wf[static_cast<size_t>(i) * st.rq * 4 + a] = static_cast<float>(C->agg == GMPEA_AGG_PBI ? w / nrm : w);
+      }
+    }
+    e = hipMemcpyAsync(st.W, Wf.data(), Wf.size() * sizeof(float), hipMemcpyHostToDevice, h->stream);
+    for (int p = 0; p < 2 && e == hipSuccess; ++p) {
+      refset_neighbours(K, m, H, H2, ts[p], Bh);
+      e = hipMemcpyAsync(const_cast<int32_t *>(st.B[p]), Bh.data(), Bh.size() * sizeof(int32_t),
+                         hipMemcpyHostToDevice, h->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);  // Wf is read before it goes
+  }
   if (e == hipSuccess && incomplete) {
     // some row (near a lattice corner) needs neighbours beyond the offset list:
     // the host's exact search provides both tables
@@ -497,7 +540,7 @@ gmpea_status gmpea_init(const gmpea_problem *P, const gmpea_config *C, const gmp
       e = launch_reverse_fill(N, ts[p], st.B[p], st.rtoff[p], cursor, const_cast<int32_t *>(st.rhead[p]),
                               const_cast<int32_t *>(st.rtail[p]), h->stream);
   }
-  zero(st.FCO[0], 0, rows * sizeof(float4));
+  zero(st.FCO[0], 0, rows * st.rq * sizeof(float4));
   if (e == hipSuccess) e = launch_init(st, h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) {
@@ -565,7 +608,7 @@ gmpea_status gmpea_front(gmpea_t h, int32_t what, int32_t capacity, float *x, fl
       h->f_keep = c.take<uint8_t>(st.n);
       h->f_idx = c.take<int32_t>(st.n);
       h->f_x = c.take<float>(static_cast<size_t>(st.n) * st.d);
-      h->f_fc = c.take<float4>(st.n);
+      h->f_fc = c.take<float4>(static_cast<size_t>(st.n) * st.rq);
     };
     Carve sizing;
     layout(sizing);
@@ -609,15 +652,16 @@ gmpea_status gmpea_front(gmpea_t h, int32_t what, int32_t capacity, float *x, fl
   }
   if (s == GMPEA_OK && x) s = d2h(h, x, dx, static_cast<size_t>(cnt) * st.d, "gmpea_front");
   if (s == GMPEA_OK) {
-    hfc.resize(cnt);
-    s = d2h(h, hfc.data(), dfc, cnt, "gmpea_front");
+    hfc.resize(static_cast<size_t>(cnt) * st.rq);
+    s = d2h(h, hfc.data(), dfc, hfc.size(), "gmpea_front");
   }
   if (s == GMPEA_OK) {
+    const float *v = reinterpret_cast<const float *>(hfc.data());
+    const size_t rw = static_cast<size_t>(st.rq) * 4;
     for (int32_t r = 0; r < cnt; ++r) {
-      const float v[4] = {hfc[r].x, hfc[r].y, hfc[r].z, hfc[r].w};
       if (f)
-        for (int32_t a = 0; a < st.m; ++a) f[static_cast<size_t>(r) * st.m + a] = v[a];
-      if (cv) cv[r] = v[3];
+        for (int32_t a = 0; a < st.m; ++a) f[static_cast<size_t>(r) * st.m + a] = v[r * rw + a];
+      if (cv) cv[r] = v[r * rw + rw - 1];
     }
   }
   return s;
@@ -627,13 +671,13 @@ gmpea_status gmpea_get_info(gmpea_t h, gmpea_info *info) {
   if (!valid(h)) return fail(GMPEA_ESTATE, "gmpea_get_info: invalid handle");
   if (!info) return fail(GMPEA_EINVAL, "gmpea_get_info: info is NULL");
   const DevState &st = h->st;
-  uint32_t gen = 0, zk[4];
+  uint32_t gen = 0, zk[kMaxM];
   unsigned long long rep[2 * kReplLanes];
-  std::vector<float4> fc(st.n);
+  std::vector<float4> fc(static_cast<size_t>(st.n) * st.rq);
   gmpea_status s = d2h(h, &gen, st.gen, 1, "gmpea_get_info");
-  if (s == GMPEA_OK) s = d2h(h, zk, st.zkey, 4, "gmpea_get_info");
+  if (s == GMPEA_OK) s = d2h(h, zk, st.zkey, kMaxM, "gmpea_get_info");
   if (s == GMPEA_OK) s = d2h(h, rep, st.repl, 2 * kReplLanes, "gmpea_get_info");
-  if (s == GMPEA_OK) s = d2h(h, fc.data(), st.FC[0], st.n, "gmpea_get_info");
+  if (s == GMPEA_OK) s = d2h(h, fc.data(), st.FC[0], fc.size(), "gmpea_get_info");
   if (s != GMPEA_OK) return s;
   info->n = st.n;
   info->m = st.m;
@@ -641,6 +685,7 @@ gmpea_status gmpea_get_info(gmpea_t h, gmpea_info *info) {
   info->t1 = st.t[0];
   info->t2 = st.t[1];
   info->H = h->H;
+  info->H2 = h->H2;
   info->generation = gen;
   for (int a = 0; a < GMPEA_MAX_M; ++a) info->z[a] = a < st.m ? key_float(zk[a]) : 0.0f;
   for (int p = 0; p < 2; ++p) {
@@ -649,7 +694,7 @@ gmpea_status gmpea_get_info(gmpea_t h, gmpea_info *info) {
     info->replaced[p] = static_cast<int64_t>(tot);
   }
   int64_t feas = 0;
-  for (int32_t i = 0; i < st.n; ++i) feas += fc[i].w == 0.0f;
+  for (int32_t i = 0; i < st.n; ++i) feas += fc[static_cast<size_t>(i) * st.rq + st.rq - 1].w == 0.0f;
   info->feasible_frac = static_cast<double>(feas) / st.n;
   info->device_bytes = h->bytes;
   return GMPEA_OK;
@@ -678,24 +723,24 @@ gmpea_status gmpea_read(gmpea_t h, int32_t buffer, int32_t pop, void *host, int6
     case GMPEA_BUF_CVOFF: {
       const bool isf = buffer == GMPEA_BUF_F || buffer == GMPEA_BUF_FOFF;
       if (!need(isf ? n * m : n)) return fail(GMPEA_EINVAL, "gmpea_read: wrong count");
-      std::vector<float4> fc(n);
+      const int64_t rw = int64_t(st.rq) * 4;
+      std::vector<float> fc(static_cast<size_t>(n * rw));
       const float4 *src = (buffer == GMPEA_BUF_F || buffer == GMPEA_BUF_CV) ? st.FC[pop] : st.FCO[pop];
-      gmpea_status s = d2h(h, fc.data(), src, n, "gmpea_read");
+      gmpea_status s = d2h(h, fc.data(), src, fc.size(), "gmpea_read");
       if (s != GMPEA_OK) return s;
       float *o = static_cast<float *>(host);
       for (int64_t i = 0; i < n; ++i) {
-        const float v[4] = {fc[i].x, fc[i].y, fc[i].z, fc[i].w};
         if (isf)
-          for (int64_t a = 0; a < m; ++a) o[i * m + a] = v[a];
+          for (int64_t a = 0; a < m; ++a) o[i * m + a] = fc[i * rw + a];
         else
-          o[i] = v[3];
+          o[i] = fc[i * rw + rw - 1];
       }
       return GMPEA_OK;
     }
     case GMPEA_BUF_Z: {
       if (!need(m)) return fail(GMPEA_EINVAL, "gmpea_read: count must be m");
-      uint32_t zk[4];
-      gmpea_status s = d2h(h, zk, st.zkey, 4, "gmpea_read");
+      uint32_t zk[kMaxM];
+      gmpea_status s = d2h(h, zk, st.zkey, kMaxM, "gmpea_read");
       if (s != GMPEA_OK) return s;
       for (int64_t a = 0; a < m; ++a) static_cast<float *>(host)[a] = key_float(zk[a]);
       return GMPEA_OK;
@@ -710,9 +755,9 @@ gmpea_status gmpea_read(gmpea_t h, int32_t buffer, int32_t pop, void *host, int6
     case GMPEA_BUF_W: {
       if (!need(n * m)) return fail(GMPEA_EINVAL, "gmpea_read: count must be N * m");
       std::vector<int32_t> K;
-      dd_lattice(static_cast<int32_t>(m), h->H, K);
-      for (size_t q = 0; q < K.size(); ++q)
-        static_cast<float *>(host)[q] = static_cast<float>(static_cast<double>(K[q]) / h->H);
+      std::vector<double> Wd;
+      refset(static_cast<int32_t>(m), h->H, h->H2, K, &Wd);
+      for (size_t q = 0; q < Wd.size(); ++q) static_cast<float *>(host)[q] = static_cast<float>(Wd[q]);
       return GMPEA_OK;
     }
     case GMPEA_BUF_B: {
@@ -758,26 +803,25 @@ gmpea_status gmpea_write(gmpea_t h, int32_t buffer, int32_t pop, const void *hos
     case GMPEA_BUF_CV: {
       const bool isf = buffer == GMPEA_BUF_F;
       if (count != (isf ? n * m : n)) return fail(GMPEA_EINVAL, "gmpea_write: wrong count");
-      std::vector<float4> fc(n);
-      gmpea_status s = d2h(h, fc.data(), st.FC[pop], n, "gmpea_write");
+      const int64_t rw = int64_t(st.rq) * 4;
+      std::vector<float> fc(static_cast<size_t>(n * rw));
+      gmpea_status s = d2h(h, fc.data(), st.FC[pop], fc.size(), "gmpea_write");
       if (s != GMPEA_OK) return s;
       const float *in = static_cast<const float *>(host);
       for (int64_t i = 0; i < n; ++i) {
-        if (isf) {
-          fc[i].x = in[i * m];
-          fc[i].y = in[i * m + 1];
-          fc[i].z = m > 2 ? in[i * m + 2] : 0.0f;
-        } else {
-          fc[i].w = in[i];
-        }
+        if (isf)
+          for (int64_t a = 0; a < m; ++a) fc[i * rw + a] = in[i * m + a];
+        else
+          fc[i * rw + rw - 1] = in[i];
       }
-      return h2d(h, st.FC[pop], fc.data(), n, "gmpea_write");
+      return h2d(h, st.FC[pop], fc.data(), fc.size(), "gmpea_write");
     }
     case GMPEA_BUF_Z: {
       if (count != m) return fail(GMPEA_EINVAL, "gmpea_write: count must be m");
-      uint32_t zk[4] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu};
+      uint32_t zk[kMaxM];
+      for (int a = 0; a < kMaxM; ++a) zk[a] = 0xFFFFFFFFu;
       for (int64_t a = 0; a < m; ++a) zk[a] = float_key(static_cast<const float *>(host)[a]);
-      return h2d(h, st.zkey, zk, 4, "gmpea_write");
+      return h2d(h, st.zkey, zk, kMaxM, "gmpea_write");
     }
     case GMPEA_BUF_GEN: {
       if (count != 1) return fail(GMPEA_EINVAL, "gmpea_write: count must be 1");
@@ -889,9 +933,11 @@ struct gmpea_pool_s {
   // device tables
   DevState *d_states = nullptr;
   int32_t state_cap = 0;
-  int2 *d_work[kPhases] = {nullptr, nullptr, nullptr, nullptr};
-  int32_t work_cap[kPhases] = {0, 0, 0, 0};
-  int32_t nwork[kPhases] = {0, 0, 0, 0};
+  // work lists per phase: [0] instances with m <= 3 (every instance in the row
+  // copies, which do not depend on m), [1] instances with m > 3
+  int2 *d_work[2][kPhases] = {};
+  int32_t work_cap[2][kPhases] = {};
+  int32_t nwork[2][kPhases] = {};
   bool dirty = true;
   // launch policy (the autotuner may change both; results do not depend on them)
   int32_t schedule = 0;  // 0: instance blocks grouped per XCD, 1: linear
@@ -1021,12 +1067,13 @@ int32_t phase_blocks(const DevState &st, int phase) {
 // on one XCD (instances placed largest first on the least-loaded XCD, large
 // ones split into contiguous runs) so neighbouring subproblems share an L2;
 // the hardware deals block b to XCD b mod 8, hence the interleaving at the end.
-void build_work(const gmpea_pool_s *q, int phase, int schedule, std::vector<int2> &out) {
+// cls 0: instances with m <= 3 (every instance for the row copies), 1: m > 3.
+void build_work(const gmpea_pool_s *q, int phase, int schedule, int cls, std::vector<int2> &out) {
   out.clear();
   std::vector<std::pair<int32_t, int32_t>> inst;  // (blocks, slot)
   int64_t total = 0;
   for (int32_t s = 0; s < static_cast<int32_t>(q->slots.size()); ++s)
-    if (q->slots[s]) {
+    if (q->slots[s] && (phase == 3 ? cls == 0 : (q->slots[s]->st.m > 3) == (cls == 1))) {
       inst.emplace_back(phase_blocks(q->slots[s]->st, phase), s);
       total += inst.back().first;
     }
@@ -1076,16 +1123,18 @@ gmpea_status pool_rebuild(gmpea_pool_s *q) {
     if (q->slots[k]) host[k] = q->slots[k]->st;
   hipError_t e = hipMemcpyAsync(q->d_states, host.data(), sizeof(DevState) * host.size(),
                                 hipMemcpyHostToDevice, q->stream);
-  std::vector<int2> w;
-  for (int ph = 0; ph < kPhases && e == hipSuccess; ++ph) {
-    build_work(q, ph, q->schedule, w);
-    s = pool_table(q, &q->d_work[ph], &q->work_cap[ph], std::max<int32_t>(1, static_cast<int32_t>(w.size())));
-    if (s != GMPEA_OK) return s;
-    q->nwork[ph] = static_cast<int32_t>(w.size());
-    if (!w.empty())
-      e = hipMemcpyAsync(q->d_work[ph], w.data(), sizeof(int2) * w.size(), hipMemcpyHostToDevice,
-                         q->stream);
-  }
+  std::vector<int2> w[2][kPhases];  // kept until the copies below have finished
+  for (int c = 0; c < 2; ++c)
+    for (int ph = 0; ph < kPhases && e == hipSuccess; ++ph) {
+      build_work(q, ph, q->schedule, c, w[c][ph]);
+      s = pool_table(q, &q->d_work[c][ph], &q->work_cap[c][ph],
+                     std::max<int32_t>(1, static_cast<int32_t>(w[c][ph].size())));
+      if (s != GMPEA_OK) return s;
+      q->nwork[c][ph] = static_cast<int32_t>(w[c][ph].size());
+      if (!w[c][ph].empty())
+        e = hipMemcpyAsync(q->d_work[c][ph], w[c][ph].data(), sizeof(int2) * w[c][ph].size(),
+                           hipMemcpyHostToDevice, q->stream);
+    }
   if (e == hipSuccess) e = hipStreamSynchronize(q->stream);
   if (e != hipSuccess) return hip_fail(e, "pool rebuild");
   q->dirty = false;
@@ -1094,8 +1143,10 @@ gmpea_status pool_rebuild(gmpea_pool_s *q) {
 
 hipError_t pool_generation(const gmpea_pool_s *q, hipStream_t s) {
   for (int ph = 0; ph < kPhases; ++ph) {
-    hipError_t e = launch_batch_phase(q->d_states, q->d_work[ph], q->nwork[ph], ph, s);
-    if (e != hipSuccess) return e;
+    for (int c = 0; c < 2; ++c) {
+      hipError_t e = launch_batch_phase(q->d_states, q->d_work[c][ph], q->nwork[c][ph], ph, c == 1, s);
+      if (e != hipSuccess) return e;
+    }
   }
   return hipSuccess;
 }
@@ -1103,7 +1154,7 @@ hipError_t pool_generation(const gmpea_pool_s *q, hipStream_t s) {
 gmpea_status pool_enqueue(gmpea_pool_s *q, int32_t n) {
   gmpea_status s = pool_rebuild(q);
   if (s != GMPEA_OK) return s;
-  if (q->nwork[0] == 0) return GMPEA_OK;
+  if (q->nwork[0][3] == 0) return GMPEA_OK;  // no instance
   const int32_t G = q->chunk;
   if (G >= 2 && n >= G) {
     if (!q->gexec || q->gchunk != G) {
@@ -1164,11 +1215,36 @@ gmpea_status gmpea_lattice(int32_t m, int32_t n_req, int32_t t, int32_t cap_rows
     dd_lattice(m, H, KK);
     if (K) std::memcpy(K, KK.data(), KK.size() * sizeof(int32_t));
     if (B) {
-      lattice_knn(KK, m, H, t, BB);
+      refset_neighbours(KK, m, H, 0, t, BB);
       std::memcpy(B, BB.data(), BB.size() * sizeof(int32_t));
     }
   } catch (const std::bad_alloc &) {
     return fail(GMPEA_ENOMEM, "gmpea_lattice: host memory");
+  }
+  return GMPEA_OK;
+}
+
+gmpea_status gmpea_reference_set(int32_t m, int32_t h_outer, int32_t h_inner, int32_t t,
+                                 int32_t cap_rows, int32_t *K, int32_t *B, int32_t *n_out) {
+  if (m < 2 || m > GMPEA_MAX_M) return fail(GMPEA_EINVAL, "gmpea_reference_set: m out of range");
+  if (h_outer < 1 || h_inner < 0 || h_outer > 4096 || h_inner > 4096)
+    return fail(GMPEA_EINVAL, "gmpea_reference_set: layer divisions out of range");
+  const int64_t n = refset_count(m, h_outer, h_inner);
+  if (n > (int64_t(1) << 27)) return fail(GMPEA_EUNSUPPORTED, "gmpea_reference_set: set too large");
+  if (t < 1 || t > n) return fail(GMPEA_EINVAL, "gmpea_reference_set: t must lie in [1, N]");
+  if (n_out) *n_out = static_cast<int32_t>(n);
+  if (!K && !B) return GMPEA_OK;
+  if (cap_rows < n) return fail(GMPEA_ECAPACITY, "gmpea_reference_set: cap_rows below N");
+  try {
+    std::vector<int32_t> KK, BB;
+    refset(m, h_outer, h_inner, KK, nullptr);
+    if (K) std::memcpy(K, KK.data(), KK.size() * sizeof(int32_t));
+    if (B) {
+      refset_neighbours(KK, m, h_outer, h_inner, t, BB);
+      std::memcpy(B, BB.data(), BB.size() * sizeof(int32_t));
+    }
+  } catch (const std::bad_alloc &) {
+    return fail(GMPEA_ENOMEM, "gmpea_reference_set: host memory");
   }
   return GMPEA_OK;
 }
@@ -1333,7 +1409,8 @@ void gmpea_pool_destroy(gmpea_pool_t q) {
   if (q->gexec) (void)hipGraphExecDestroy(q->gexec);
   if (q->d_states) pool_raw_free(q, q->d_states);
   for (int ph = 0; ph < kPhases; ++ph)
-    if (q->d_work[ph]) pool_raw_free(q, q->d_work[ph]);
+    for (int c = 0; c < 2; ++c)
+      if (q->d_work[c][ph]) pool_raw_free(q, q->d_work[c][ph]);
   pool_arena_destroy(q);
   if (q->own_stream) (void)hipStreamDestroy(q->stream);
   delete q;

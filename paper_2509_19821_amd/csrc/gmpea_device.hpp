@@ -1,0 +1,778 @@
+// Device code of the GMPEA generation shared by the kernel translation units:
+// gmpea_kernels.hip instantiates it for m <= 3 (one float4 per F/CV record),
+// gmpea_kernels_wide.hip for 4 <= m <= 8. Every function is templated on the
+// objective count M, so each instantiation holds only the registers its m needs.
+#pragma once
+
+#include "gmpea_internal.hpp"
+
+namespace gmpea {
+
+// ----------------------------------------------------------------------------
+// Counter RNG: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).
+// ----------------------------------------------------------------------------
+// Each round's two 32 x 32 -> 64-bit products are written as 64-bit multiplies
+// so that each becomes one v_mad_u64_u32 (high and low words together).
+__device__ __forceinline__ uint4 philox10(uint4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t p0 = static_cast<uint64_t>(0xD2511F53u) * c.x;
+    const uint64_t p1 = static_cast<uint64_t>(0xCD9E8D57u) * c.z;
+    c = make_uint4(static_cast<uint32_t>(p1 >> 32) ^ c.y ^ k0, static_cast<uint32_t>(p1),
+                   static_cast<uint32_t>(p0 >> 32) ^ c.w ^ k1, static_cast<uint32_t>(p0));
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return c;
+}
+
+__device__ __forceinline__ float u24(uint32_t w) {
+  return static_cast<float>(w >> 8) * (1.0f / 16777216.0f);
+}
+
+__device__ __forceinline__ uint32_t fkey(float f) {
+  const uint32_t b = __float_as_uint(f);
+  return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+__device__ __forceinline__ float keyf(uint32_t k) {
+  return __uint_as_float((k & 0x80000000u) ? (k & 0x7FFFFFFFu) : ~k);
+}
+
+__device__ __forceinline__ float nan_inf(float v) { return (v != v) ? __builtin_huge_valf() : v; }
+
+// Block index -> tile such that each XCD receives a contiguous run of tiles.
+__device__ __forceinline__ int xcd_tile(int b, int G) {
+  const int x = b & 7, q = G >> 3, r = G & 7;
+  return x * q + min(x, r) + (b >> 3);
+}
+
+// x^e for x >= 0 with the hardware log2/exp2 (about 1 ulp each). Every base
+// used here is either exactly 0 (giving 0 for e > 0) or a normal number; a
+// result below the normal range flushes to 0, which no caller can tell apart.
+__device__ __forceinline__ float powpos(float x, float e) {
+  return __builtin_amdgcn_exp2f(e * __builtin_amdgcn_logf(x));
+}
+
+// ----------------------------------------------------------------------------
+// Variation of one variable. Bounded polynomial mutation of c in [lo, hi] when
+// wB < tpm, then SBX (one child kept; per-variable crossing bit, sign bit,
+// 24-bit uniform) or DE (x + F (a - b), every variable) in front of it.
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ float pm1(float c, uint32_t w, uint64_t T, float invT, float lo, float hi,
+                                     float inv_span, const DevState &st) {
+  // Called with w < T: u = w / T. Every coefficient of the mutation step (2u,
+  // 1 - 2u, 2(1 - u), 2(u - 1/2)) comes from an exact integer numerator over T,
+  // and 1 - delta from the distance to the far bound: in FP32, 1 - u itself
+  // cancels catastrophically as u -> 1 and val^(1/(eta+1)) magnifies that
+  // error. Both halves of the mutation share one pair of powers (selects, no
+  // branch).
+  float a, b;
+  bool low;
+  if (T <= 0x80000000ull) {  // every numerator fits 32 bits
+    const uint32_t T32 = static_cast<uint32_t>(T);
+    low = 2u * w < T32;  // u < 1/2
+    a = static_cast<float>(low ? 2u * w : 2u * (T32 - w)) * invT;
+    b = static_cast<float>(low ? T32 - 2u * w : 2u * w - T32) * invT;
+  } else {
+    const uint64_t w64 = w;
+    low = 2u * w64 < T;
+    a = static_cast<float>(low ? 2u * w64 : 2u * (T - w64)) * invT;
+    b = static_cast<float>(low ? T - 2u * w64 : 2u * w64 - T) * invT;
+  }
+  const float xy = (low ? (hi - c) : (c - lo)) * inv_span;
+  const float t = powpos(fmaf(b, powpos(xy, st.pm_p), a), st.pm_e);
+  const float dq = low ? t - 1.0f : 1.0f - t;
+  return __builtin_amdgcn_fmed3f(fmaf(dq, hi - lo, c), lo, hi);
+}
+
+// SBX of one variable (one child kept; crossing bit 0, sign bit 1, 24-bit
+// uniform in bits 8..31), clipped to the box.
+__device__ __forceinline__ float sbx1(float a, float b, uint32_t wA, float lo, float hi, bool cross,
+                                      const DevState &st) {
+  float c = a;
+  if (cross && (wA & 1u)) {
+    const float u = u24(wA);
+    const bool low = u <= 0.5f;  // one power for both halves of the spread
+    const float beta0 = powpos(low ? 2.0f * u : 2.0f * (1.0f - u), low ? st.sbx_e : -st.sbx_e);
+    const float beta = (wA & 2u) ? -beta0 : beta0;
+    c = 0.5f * fmaf(beta, a - b, a + b);
+  }
+  return __builtin_amdgcn_fmed3f(c, lo, hi);
+}
+
+// DE mutant of one variable (crossover rate 1), clipped to the box.
+__device__ __forceinline__ float de1(float x, float a, float b, float lo, float hi,
+                                     const DevState &st) {
+  return __builtin_amdgcn_fmed3f(fmaf(st.de_f, a - b, x), lo, hi);
+}
+
+// F/CV record of one individual in registers: objectives f_0 .. f_{M-1} from
+// the first lane, CV in the last lane (kCv), unused lanes 0; rec_quads(M) float4.
+template <int M>
+struct Rec {
+  static constexpr int Q = rec_quads(M);
+  static constexpr int kCv = 4 * Q - 1;
+  float v[4 * Q];
+};
+
+template <int M>
+__device__ __forceinline__ Rec<M> rec_load(const float4 *base, int j) {
+  Rec<M> r;
+  const float4 *p = base + static_cast<size_t>(j) * Rec<M>::Q;
+#pragma unroll
+  for (int a = 0; a < Rec<M>::Q; ++a) {
+    const float4 t = p[a];
+    r.v[4 * a] = t.x;
+    r.v[4 * a + 1] = t.y;
+    r.v[4 * a + 2] = t.z;
+    r.v[4 * a + 3] = t.w;
+  }
+  return r;
+}
+
+template <int M>
+__device__ __forceinline__ void rec_store(float4 *base, int j, const Rec<M> &r) {
+  float4 *p = base + static_cast<size_t>(j) * Rec<M>::Q;
+#pragma unroll
+  for (int a = 0; a < Rec<M>::Q; ++a)
+    p[a] = make_float4(r.v[4 * a], r.v[4 * a + 1], r.v[4 * a + 2], r.v[4 * a + 3]);
+}
+
+template <int M>
+__device__ __forceinline__ Rec<M> rec_zero() {
+  Rec<M> r;
+#pragma unroll
+  for (int k = 0; k < 4 * Rec<M>::Q; ++k) r.v[k] = 0.0f;
+  return r;
+}
+
+// Running sums of the evaluation, filled chunk by chunk, and the leading
+// variables the objectives and the equality read: x1, x2 in lead for m <= 3.
+// For m > 3 the first kLeadChunks float4 chunks (through the last angle
+// variable x_{m-1}) go to the group's LDS slot instead (lead_slots): held in
+// registers, a chunk chosen by a run-time index sends the accumulator to
+// scratch memory.
+template <int M>
+struct EvalAcc {
+  static constexpr int kLeadChunks = M <= 3 ? 0 : (M + 2) / 4;
+  float s;  // curve: sum x_2..x_d; sphere: sum over non-angle variables of (x - 0.5)^2
+  float lead[2];
+};
+
+// LDS slots of the leading chunks for m > 3: two float4 per lane group (at
+// most kBlock groups per block).
+template <int M>
+__device__ __forceinline__ float4 *lead_slots(int group) {
+  __shared__ float4 slots[kBlock * 2];
+  return slots + 2 * group;
+}
+
+// Component k (0..3) of a float4; k is a constant wherever this is called.
+__device__ __forceinline__ float f4_at(const float4 &v, int k) {
+  return k == 0 ? v.x : k == 1 ? v.y : k == 2 ? v.z : v.w;
+}
+
+template <int M, int FAM>
+__device__ __forceinline__ void eval_add(EvalAcc<M> &e, int l, float x) {
+  if (l == 0) e.lead[0] = x;
+  if (l == 1) e.lead[1] = x;
+  if (FAM == 0) {
+    if (l >= 1) e.s += x;
+  } else {
+    if (l >= M - 1) e.s = fmaf(x - 0.5f, x - 0.5f, e.s);
+  }
+}
+
+// Adds chunk q (variables 4q .. 4q + 3, those below d) in variable order; for
+// m > 3 a leading chunk is also stored to the group's slot.
+template <int M, int FAM>
+__device__ __forceinline__ void eval_chunk(EvalAcc<M> &e, int q, float4 o, int d, float4 *slot) {
+  const int l0 = q << 2;
+  if constexpr (M <= 3) {
+    eval_add<M, FAM>(e, l0, o.x);
+    if (l0 + 1 < d) eval_add<M, FAM>(e, l0 + 1, o.y);
+    if (l0 + 2 < d) eval_add<M, FAM>(e, l0 + 2, o.z);
+    if (l0 + 3 < d) eval_add<M, FAM>(e, l0 + 3, o.w);
+  } else {  // the sphere family: keep the leading chunks, sum the rest
+    if (q < EvalAcc<M>::kLeadChunks) slot[q] = o;
+    const float xs[4] = {o.x, o.y, o.z, o.w};
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (l0 + k >= M - 1 && l0 + k < d) e.s = fmaf(xs[k] - 0.5f, xs[k] - 0.5f, e.s);
+  }
+}
+
+// F and CV from the sums (Eqs. (1)-(3)); c0, c1: the leading chunks for m > 3.
+template <int M, int FAM>
+__device__ __forceinline__ Rec<M> eval_finish(const EvalAcc<M> &e, float4 c0, float4 c1,
+                                              const DevProblem &P) {
+  float f[M > 3 ? M : 3];
+#pragma unroll
+  for (int k = 0; k < (M > 3 ? M : 3); ++k) f[k] = 0.0f;
+  if (FAM == 0) {
+    const float g = fmaf(P.g_scale, e.s, 1.0f);
+    f[0] = e.lead[0];
+    f[1] = g * (1.0f - sqrtf(e.lead[0] / g));
+  } else if constexpr (M <= 3) {
+    const float r = 1.0f + e.s;
+    float s0, c0;
+    sincospif(0.5f * e.lead[0], &s0, &c0);
+    if (M == 2) {
+      f[0] = r * c0;
+      f[1] = r * s0;
+    } else {
+      float s1, c1;
+      sincospif(0.5f * e.lead[1], &s1, &c1);
+      f[0] = r * c0 * c1;
+      f[1] = r * c0 * s1;
+      f[2] = r * s0;
+    }
+  } else {
+    // f_k = (1 + g) prod_{j < M-1-k} cos(theta_j), times sin(theta_{M-1-k}) for
+    // k > 0: with the running product P_j = (1 + g) cos(theta_0) .. cos(theta_{j-1})
+    // (multiplied left to right), f_{M-1-j} = P_j sin(theta_j) and f_0 = P_{M-1}
+    float P = 1.0f + e.s;
+#pragma unroll
+    for (int j = 0; j < M - 1; ++j) {
+      float sj, cj;
+      sincospif(0.5f * (j < 4 ? f4_at(c0, j) : f4_at(c1, j - 4)), &sj, &cj);
+      f[M - 1 - j] = P * sj;
+      P = P * cj;
+    }
+    f[0] = P;
+  }
+  float cv = 0.0f;
+  for (int j = 0; j < P.n_ring; ++j) {
+    float q = 0.0f;
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+      const float df = f[k] - P.ring_c[j * M + k];
+      q = fmaf(df, df, q);
+    }
+    const float c = P.ring_r2[j] - q;
+    cv += (c > 0.0f) ? c : 0.0f;
+  }
+  if (P.has_sum_lower) {
+    float sum = 0.0f;
+#pragma unroll
+    for (int k = 0; k < M; ++k) sum += f[k];
+    const float c = P.sum_lower - sum;
+    cv += (c > 0.0f) ? c : 0.0f;
+  }
+  if (P.n_eq) {
+    const float x0 = M <= 3 ? e.lead[0] : c0.x, x1 = M <= 3 ? e.lead[1] : c0.y;
+    const float c = fabsf(x0 + x1 - 1.0f) - P.eq_tol;
+    cv += (c > 0.0f) ? c : 0.0f;
+  }
+  Rec<M> out = rec_zero<M>();
+#pragma unroll
+  for (int k = 0; k < (M > 3 ? M : 3); ++k) out.v[k] = f[k];
+  out.v[Rec<M>::kCv] = cv;
+  return out;
+}
+
+// Block-wide minimum of each objective, then one atomic per objective when the
+// block's value can lower the ideal point. NaN never lowers it.
+template <int M>
+__device__ __forceinline__ void block_zmin(float (&v)[M], uint32_t *zkey) {
+  __shared__ float red[M][kBlock / 64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < M; ++k) {
+    float x = v[k];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x = fminf(x, __shfl_xor(x, o));
+    if (lane == 0) red[k][wv] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x < M) {
+    const int k = threadIdx.x;
+    float x = red[k][0];
+#pragma unroll
+    for (int w = 1; w < kBlock / 64; ++w) x = fminf(x, red[k][w]);
+    if (x == x) {
+      const uint32_t kk = fkey(x);
+      if (kk < __atomic_load_n(&zkey[k], __ATOMIC_RELAXED)) atomicMin(&zkey[k], kk);
+    }
+  }
+}
+
+// Evaluation of a population row by a group of LPO lanes: lane g adds chunks
+// g, g + LPO, ... in order, then a butterfly combines the lanes. k_vary adds
+// its offspring in exactly this order, so F and CV are a function of x alone:
+// an offspring that copies an individual evaluates bitwise equal to it.
+template <int M, int FAM, int LPO>
+__device__ __forceinline__ EvalAcc<M> eval_row(const DevState &st, const float4 *row, int g,
+                                               bool live, float4 *slot) {
+  EvalAcc<M> e{};
+  if (live) {
+    const int nq = st.stride >> 2;
+    for (int q = g; q < nq; q += LPO) eval_chunk<M, FAM>(e, q, row[q], st.d, slot);
+  }
+  return e;
+}
+
+// Group reduction of the sums (every thread of the block takes part), then
+// F/CV and the ideal point's block minimum. The leading variables come from the
+// lanes that added their chunks (m <= 3: lane 0's registers; m > 3: the
+// group's LDS slot).
+template <int M, int FAM, int LPO>
+__device__ __forceinline__ void eval_group(const DevState &st, EvalAcc<M> e, int g, bool live,
+                                           float4 *out, int j, const float4 *slot) {
+  float zv[M];
+#pragma unroll
+  for (int q = 0; q < M; ++q) zv[q] = __builtin_huge_valf();
+#pragma unroll
+  for (int o = 1; o < LPO; o <<= 1) e.s += __shfl_xor(e.s, o);
+  const int base = (threadIdx.x & 63) & ~(LPO - 1);
+  if constexpr (M <= 3) {
+    e.lead[0] = __shfl(e.lead[0], base);
+    e.lead[1] = __shfl(e.lead[1], base);
+  } else {
+    __syncthreads();  // the slots' stores are visible to the finishing lane
+  }
+  if (live && g == 0) {
+    float4 c0 = make_float4(0, 0, 0, 0), c1 = c0;
+    if constexpr (M > 3) {
+      c0 = slot[0];
+      if (EvalAcc<M>::kLeadChunks > 1) c1 = slot[1];
+    }
+    const Rec<M> fc = eval_finish<M, FAM>(e, c0, c1, st.prob);
+    rec_store<M>(out, j, fc);
+#pragma unroll
+    for (int k = 0; k < M; ++k) zv[k] = fc.v[k];
+  }
+  block_zmin<M>(zv, st.zkey);
+}
+
+// Initial evaluation (Alg. 1): F, CV and the ideal point of both populations.
+template <int M, int FAM, int LPO>
+__global__ __launch_bounds__(kBlock) void k_eval(DevState st) {
+  constexpr int kPer = kBlock / LPO;
+  const int L = xcd_tile(blockIdx.x, gridDim.x);
+  const int half = gridDim.x >> 1;
+  const int p = L >= half ? 1 : 0;
+  const int g = threadIdx.x & (LPO - 1);
+  const int i = (L - p * half) * kPer + threadIdx.x / LPO;
+  const bool live = i < st.n;
+  const float4 *row = reinterpret_cast<const float4 *>(st.X[p] + static_cast<size_t>(live ? i : 0) * st.stride);
+  float4 *slot = M > 3 ? lead_slots<M>(threadIdx.x / LPO) : nullptr;
+  const EvalAcc<M> e = eval_row<M, FAM, LPO>(st, row, g, live, slot);
+  eval_group<M, FAM, LPO>(st, e, g, live, st.FC[p], live ? i : 0, slot);
+}
+
+// ----------------------------------------------------------------------------
+// k_vary: reproduction (SBX or DE, then PM) + evaluation + ideal-point update.
+// Draws (the paper fixes no RNG; this counter layout is the library's): Philox
+// counter (c0, i, k, tag << 24 | p << 16) for offspring i of population p in
+// generation k. The MATE block (c0 = 0) gives the two neighbourhood positions
+// and the per-offspring crossing draw; VAR block c0 = l >> 1 gives (wA, wB) for
+// variables l and l + 1: SBX's bits in wA, the mutation test and uniform in wB.
+// A group of LPO consecutive lanes builds one offspring: lane g of the group
+// takes the float4 chunks g, g + LPO, ... of the row, so with LPO = 8 the group
+// reads each parent row and writes the offspring row as whole 128-byte lines.
+// The group shares the mating draw (each lane computes it; the cost is one
+// Philox block either way) and reduces the evaluation sums with butterflies.
+// ----------------------------------------------------------------------------
+template <int M, int FAM, int LPO>
+__device__ __forceinline__ void vary_body(const DevState &st, int L, int G) {
+  constexpr int kPer = kBlock / LPO;  // offspring per block
+  const int half = G >> 1;            // blocks per population
+  const int p = L >= half ? 1 : 0;
+  const int g = threadIdx.x & (LPO - 1);
+  const int i = (L - p * half) * kPer + threadIdx.x / LPO;
+  const uint32_t k = *st.gen + 1u;
+  const uint32_t tagp = (p << 16);
+  const float *Xc = st.X[p];
+  const bool live = i < st.n;
+  EvalAcc<M> e{};
+  float4 *slot = M > 3 ? lead_slots<M>(threadIdx.x / LPO) : nullptr;
+  if (live) {
+    const int t = st.t[p];
+    const uint4 w = philox10(make_uint4(0u, i, k, (kTagMate << 24) | tagp), st.key0, st.key1);
+    const uint32_t r1 = __umulhi(w.x, static_cast<uint32_t>(t));
+    uint32_t r2 = r1;
+    if (t > 1) {
+      r2 = __umulhi(w.y, static_cast<uint32_t>(t - 1));
+      r2 += (r2 >= r1) ? 1u : 0u;
+    }
+    const int32_t *Bi = st.B[p] + static_cast<size_t>(i) * t;
+    const int pa = Bi[r1], pb = Bi[r2];
+    if (st.mate[p] && g == 0) {
+      st.mate[p][2 * i] = pa;
+      st.mate[p][2 * i + 1] = pb;
+    }
+    const bool cross = static_cast<uint64_t>(w.z) < st.tpc;
+    const float4 *ra = reinterpret_cast<const float4 *>(Xc + static_cast<size_t>(pa) * st.stride);
+    const float4 *rb = reinterpret_cast<const float4 *>(Xc + static_cast<size_t>(pb) * st.stride);
+    float4 *ro = reinterpret_cast<float4 *>(st.XO[p] + static_cast<size_t>(i) * st.stride);
+    const float4 *lb4 = reinterpret_cast<const float4 *>(st.prob.lb);
+    const float4 *ub4 = reinterpret_cast<const float4 *>(st.prob.ub);
+    const float4 *is4 = reinterpret_cast<const float4 *>(st.prob.inv_span);
+    const uint32_t tagv = (kTagVar << 24) | tagp;
+    const int nq = st.stride >> 2;
+    const bool de = st.op == 1;
+    const float4 *rx = reinterpret_cast<const float4 *>(Xc + static_cast<size_t>(i) * st.stride);
+    const uint64_t T = st.tpm;
+    for (int q = g; q < nq; q += LPO) {
+      const int l0 = q << 2;
+      const float4 va = ra[q], vb = rb[q], lo = lb4[q], hi = ub4[q], is = is4[q];
+      const uint4 r0 = philox10(make_uint4(2 * q, i, k, tagv), st.key0, st.key1);
+      uint4 r1w = make_uint4(0, 0, 0, 0);
+      if (l0 + 2 < st.d) r1w = philox10(make_uint4(2 * q + 1, i, k, tagv), st.key0, st.key1);
+      float4 o = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      if (de) {
+        const float4 vx = rx[q];
+        o.x = de1(vx.x, va.x, vb.x, lo.x, hi.x, st);
+        o.y = de1(vx.y, va.y, vb.y, lo.y, hi.y, st);
+        o.z = de1(vx.z, va.z, vb.z, lo.z, hi.z, st);
+        o.w = de1(vx.w, va.w, vb.w, lo.w, hi.w, st);
+      } else {
+        o.x = sbx1(va.x, vb.x, r0.x, lo.x, hi.x, cross, st);
+        o.y = sbx1(va.y, vb.y, r0.z, lo.y, hi.y, cross, st);
+        o.z = sbx1(va.z, vb.z, r1w.x, lo.z, hi.z, cross, st);
+        o.w = sbx1(va.w, vb.w, r1w.z, lo.w, hi.w, cross, st);
+      }
+      // polynomial mutation of each variable whose word wB falls below tpm
+      if (r0.y < T) o.x = pm1(o.x, r0.y, T, st.inv_tpm, lo.x, hi.x, is.x, st);
+      if (l0 + 1 < st.d && r0.w < T) o.y = pm1(o.y, r0.w, T, st.inv_tpm, lo.y, hi.y, is.y, st);
+      if (l0 + 2 < st.d && r1w.y < T) o.z = pm1(o.z, r1w.y, T, st.inv_tpm, lo.z, hi.z, is.z, st);
+      if (l0 + 3 < st.d && r1w.w < T) o.w = pm1(o.w, r1w.w, T, st.inv_tpm, lo.w, hi.w, is.w, st);
+      // padding variables (beyond d) stay 0
+      if (l0 + 1 >= st.d) o.y = 0.0f;
+      if (l0 + 2 >= st.d) o.z = 0.0f;
+      if (l0 + 3 >= st.d) o.w = 0.0f;
+      eval_chunk<M, FAM>(e, q, o, st.d, slot);
+      ro[q] = o;
+    }
+  }
+  // the sums over the group's chunks (and the leading variables) -> F, CV, z
+  eval_group<M, FAM, LPO>(st, e, g, live, st.FCO[p], live ? i : 0, slot);
+}
+
+template <int M, int FAM, int LPO>
+__global__ __launch_bounds__(kBlock) void k_vary(DevState st) {
+  vary_body<M, FAM, LPO>(st, xcd_tile(blockIdx.x, gridDim.x), gridDim.x);
+}
+
+// ----------------------------------------------------------------------------
+// Aggregation. PBI (Eq. (7)) with the unit direction u = w / ||w|| stored in W:
+// d1 = |(F - z) . u|, d2 = ||F - z - d1 u||, g = d1 + theta d2. Tchebycheff:
+// max_k w_k |f_k - z_k| with the raw weight stored in W. NaN reads as +inf.
+// ----------------------------------------------------------------------------
+template <int M>
+__device__ __forceinline__ float aggregate(const Rec<M> &f, const Rec<M> &w, const float (&z)[M],
+                                           int agg, float theta) {
+  float df[M], ww[M];
+#pragma unroll
+  for (int k = 0; k < M; ++k) {
+    df[k] = f.v[k] - z[k];
+    ww[k] = w.v[k];
+  }
+  float g;
+  if (agg == 1) {
+    // fmaxf drops NaN operands, so a NaN term is tracked on the side
+    g = -__builtin_huge_valf();
+    bool nan = false;
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+      const float v = ww[k] * fabsf(df[k]);
+      nan = nan || (v != v);
+      g = fmaxf(g, v);
+    }
+    if (nan) g = __builtin_huge_valf();
+  } else {
+    float dot = 0.0f;
+#pragma unroll
+    for (int k = 0; k < M; ++k) dot = fmaf(df[k], ww[k], dot);
+    const float d1 = fabsf(dot);
+    float d2 = 0.0f;
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+      const float e = df[k] - d1 * ww[k];
+      d2 = fmaf(e, e, d2);
+    }
+    g = d1 + theta * sqrtf(d2);
+  }
+  return nan_inf(g);
+}
+
+template <int M>
+__device__ __forceinline__ void load_z(const uint32_t *zkey, float (&z)[M]) {
+#pragma unroll
+  for (int k = 0; k < M; ++k) z[k] = keyf(zkey[k]);
+}
+
+// ----------------------------------------------------------------------------
+// k_op1: offspring cooperation (Alg. 2 OP1, Eq. (11)) at w_i.
+// Population 1 takes off2_i if it is better by the feasibility priority rule
+// (Eq. (8)), or, as a variant, by the prose's feasibility-first rule (a feasible
+// offspring wins; otherwise the lower aggregation); population 2 takes off1_i
+// if its aggregation is lower.
+// ----------------------------------------------------------------------------
+template <int M>
+__device__ __forceinline__ void op1_body(const DevState &st, int b) {
+  const int i = b * kBlock + threadIdx.x;
+  // the generation counter advances here, once k_vary of this generation has read it
+  if (b == 0 && threadIdx.x == 0) st.gen[0] = st.gen[0] + 1u;
+  if (i >= st.n) return;
+  float z[M];
+  load_z<M>(st.zkey, z);
+  constexpr int kCv = Rec<M>::kCv;
+  const Rec<M> o1 = rec_load<M>(st.FCO[0], i), o2 = rec_load<M>(st.FCO[1], i);
+  const Rec<M> w = rec_load<M>(st.W, i);
+  const float g1 = aggregate<M>(o1, w, z, st.agg, st.theta);
+  const float g2 = aggregate<M>(o2, w, z, st.agg, st.theta);
+  const float c1 = nan_inf(o1.v[kCv]), c2 = nan_inf(o2.v[kCv]);
+  const bool s1 = st.op1_rule == 0 ? ((c2 < c1) || (c2 == c1 && g2 < g1))
+                                    : ((c2 == 0.0f) != (c1 == 0.0f) ? c2 == 0.0f : g2 < g1);
+  const bool s2 = g1 < g2;
+  // the CV lane's sign bit tells k_select which population's offspring row this is
+  Rec<M> n1 = s1 ? o2 : o1, n2 = s2 ? o1 : o2;
+  n1.v[kCv] = s1 ? -fabsf(n1.v[kCv]) : fabsf(n1.v[kCv]);
+  n2.v[kCv] = s2 ? -fabsf(n2.v[kCv]) : fabsf(n2.v[kCv]);
+  rec_store<M>(st.FCN[0], i, n1);
+  rec_store<M>(st.FCN[1], i, n2);
+  st.src[i] = static_cast<uint8_t>((s1 ? 1u : 0u) | (s2 ? 2u : 0u));
+}
+
+template <int M>
+__global__ __launch_bounds__(kBlock) void k_op1(DevState st) {
+  op1_body<M>(st, blockIdx.x);
+}
+
+// ----------------------------------------------------------------------------
+// k_select: OP2 + OP3 (Eqs. (12)-(13)) as a pull over parent slot j of
+// population p. Offspring i qualifies iff j is in B_p(i) and its new offspring
+// is strictly better than parent j at w_j (population 1: lower CV, or equal CV
+// and lower aggregation; population 2: lower aggregation). The winner is the
+// lexicographic minimum over the qualifiers with the first index on ties; every
+// decision uses generation-k parents, and replacements land after all reads of
+// the slot they overwrite.
+// A group of lps lanes decides one slot (lps = t_p / 4 rounded up to a power of
+// two, at most 64: about four reverse-list entries per lane). Lane g takes
+// entries g, g + lps, ... of the slot's padded list head, four at a time with
+// independent loads (index, then candidate F/CV), then its share of the tail
+// (lists longer than t_p), and keeps its lexicographic minimum of (CV, g,
+// index). No load waits on another beyond index -> candidate: the head needs no
+// offset, and OP1's choice of population rides in the sign of the candidate's
+// CV. The group minimum follows from DPP moves inside 16-lane rows (quad swaps,
+// half-row mirror, row mirror) and lane permutes beyond, and the lane that
+// holds the winner writes its F/CV from registers. That minimum qualifies
+// exactly when some candidate qualifies, since qualifying means being below the
+// parent in the same order; a minimum over a total order does not depend on how
+// the candidates were split among lanes.
+// ----------------------------------------------------------------------------
+struct SelKey {
+  float c, g;
+  int i;
+};
+
+__device__ __forceinline__ bool sel_less(const SelKey &a, const SelKey &b) {
+  return a.c < b.c || (a.c == b.c && (a.g < b.g || (a.g == b.g && a.i < b.i)));
+}
+
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int v) {
+  return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, false);
+}
+
+template <int CTRL>
+__device__ __forceinline__ void sel_step_dpp(SelKey &best) {
+  const SelKey o{__int_as_float(dpp_i<CTRL>(__float_as_int(best.c))),
+                 __int_as_float(dpp_i<CTRL>(__float_as_int(best.g))), dpp_i<CTRL>(best.i)};
+  if (sel_less(o, best)) best = o;
+}
+
+__device__ __forceinline__ void sel_step_xor(SelKey &best, int o) {
+  const SelKey k{__shfl_xor(best.c, o), __shfl_xor(best.g, o), __shfl_xor(best.i, o)};
+  if (sel_less(k, best)) best = k;
+}
+
+// Minimum over each aligned group of lps lanes, left in every lane of the group.
+// Every lane of the wave must be active.
+__device__ __forceinline__ void sel_group_min(SelKey &best, int lps) {
+  if (lps > 1) sel_step_dpp<0xB1>(best);   // quad_perm [1, 0, 3, 2]
+  if (lps > 2) sel_step_dpp<0x4E>(best);   // quad_perm [2, 3, 0, 1]
+  if (lps > 4) sel_step_dpp<0x141>(best);  // row_half_mirror: quad q <-> the other quad of its 8
+  if (lps > 8) sel_step_dpp<0x140>(best);  // row_mirror: half-row <-> the other half of its 16
+  if (lps > 16) sel_step_xor(best, 16);
+  if (lps > 32) sel_step_xor(best, 32);
+}
+
+template <int M>
+__device__ __forceinline__ void select_body(const DevState &st, int L) {
+  __shared__ int s_cnt;
+  const int p = L >= st.sel_blocks0 ? 1 : 0;
+  const int lps = st.lps[p];
+  const int g = threadIdx.x & (lps - 1);
+  const int j = (L - p * st.sel_blocks0) * (kBlock / lps) + threadIdx.x / lps;
+  if (threadIdx.x == 0) s_cnt = 0;
+  __syncthreads();
+  const bool live = j < st.n;
+  // keys carry i2 = 2 i + (OP1 source bit of i): the same order as i, and the
+  // winner's row follows without another load
+  constexpr int kCv = Rec<M>::kCv;
+  SelKey best{__builtin_huge_valf(), __builtin_huge_valf(), 0x7FFFFFFF};
+  Rec<M> bestf = rec_zero<M>();  // F/CV of this lane's best candidate
+  Rec<M> w = rec_zero<M>(), par = rec_zero<M>();
+  float z[M];
+  load_z<M>(st.zkey, z);
+  // m <= 3: the lane keeps its best candidate's record in registers and writes
+  // it if it wins; m > 3: only the key, and the winner's record is read again
+  // (records of two or three float4 would cost a select per float per candidate)
+  auto consider = [&](int32_t i, Rec<M> c) {
+    const uint32_t bit = __float_as_uint(c.v[kCv]) >> 31;  // set: the other population's offspring
+    c.v[kCv] = fabsf(c.v[kCv]);
+    const SelKey k{(p == 0) ? nan_inf(c.v[kCv]) : 0.0f, aggregate<M>(c, w, z, st.agg, st.theta),
+                   static_cast<int>((static_cast<uint32_t>(i) << 1) | bit)};
+    if (sel_less(k, best)) {
+      best = k;
+      if constexpr (M <= 3) bestf = c;
+    }
+  };
+  if (live) {
+    const int t = st.t[p];
+    w = rec_load<M>(st.W, j);
+    par = rec_load<M>(st.FC[p], j);
+    const int32_t *head = st.rhead[p] + static_cast<size_t>(j) * t;
+    const int32_t ta = st.rtoff[p][j], tb = st.rtoff[p][j + 1];
+    const float4 *cand = st.FCN[p];
+    for (int q0 = g; q0 < t; q0 += 4 * lps) {  // one pass unless t > 4 lps = 256
+      int ii[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int q = q0 + u * lps;
+        ii[u] = q < t ? head[q] : -1;
+      }
+      Rec<M> cc[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) cc[u] = ii[u] >= 0 ? rec_load<M>(cand, ii[u]) : rec_zero<M>();
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (ii[u] >= 0) consider(ii[u], cc[u]);
+    }
+    for (int q = ta + g; q < tb; q += lps) {
+      const int32_t i = st.rtail[p][q];
+      consider(i, rec_load<M>(cand, i));
+    }
+  }
+  const SelKey mine = best;
+  sel_group_min(best, lps);
+  if (live) {
+    const float pc = (p == 0) ? nan_inf(par.v[kCv]) : 0.0f;
+    const float pg = aggregate<M>(par, w, z, st.agg, st.theta);
+    const bool win = best.i != 0x7FFFFFFF && (best.c < pc || (best.c == pc && best.g < pg));
+    const int bi = best.i >> 1;
+    if (!win && g == 0) {  // the parent stays
+      if (st.win[p]) st.win[p][j] = -1;
+      st.rsrc[p][j] = -1;
+    }
+    // the lane that holds the winner (m <= 3), the group's first lane (m > 3)
+    if (win && (M <= 3 ? mine.i == best.i : g == 0)) {
+      if (st.win[p]) st.win[p][j] = bi;
+      if constexpr (M > 3) {
+        bestf = rec_load<M>(st.FCN[p], bi);
+        bestf.v[kCv] = fabsf(bestf.v[kCv]);
+      }
+      rec_store<M>(st.FC[p], j, bestf);
+      st.rsrc[p][j] = ((p ^ (best.i & 1)) << 30) | bi;
+      atomicAdd(&s_cnt, 1);
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0 && s_cnt > 0)
+    atomicAdd(&st.repl[p * kReplLanes + (L & (kReplLanes - 1))], static_cast<unsigned long long>(s_cnt));
+}
+
+// ----------------------------------------------------------------------------
+// k_rows: the row copies of the replacement, one float4 of a population row per
+// thread, streaming over both populations in place: a replaced slot takes its
+// winning offspring row. All reads of X for the generation happened in earlier
+// launches. (Rows are not aligned to 128-byte lines; writing the kept bytes of
+// shared lines back as well, so that no line is left partially written, was
+// measured slower: partial lines cost nothing extra here.)
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ void rows_body(const DevState &st, int64_t e) {
+  const int nq = st.stride >> 2;
+  const int64_t per_pop = static_cast<int64_t>(st.n) * nq;
+  if (e >= 2 * per_pop) return;
+  const int p = e >= per_pop ? 1 : 0;
+  const int64_t el = e - p * per_pop;
+  const int r = static_cast<int>(el / nq);
+  const int c = static_cast<int>(el - static_cast<int64_t>(r) * nq);
+  const int32_t ds = st.rsrc[p][r];
+  if (ds < 0) return;
+  const float *src = st.XO[ds >> 30] + static_cast<size_t>(ds & 0x3FFFFFFF) * st.stride;
+  reinterpret_cast<float4 *>(st.X[p] + static_cast<size_t>(r) * st.stride)[c] =
+      reinterpret_cast<const float4 *>(src)[c];
+}
+
+template <int M>
+__global__ __launch_bounds__(kBlock) void k_select(DevState st) {
+  select_body<M>(st, xcd_tile(blockIdx.x, gridDim.x));
+}
+
+// ----------------------------------------------------------------------------
+// Batched generations: one launch per phase covers every instance of a pool.
+// Block b runs work item work[b] = (instance, block of that instance's plain
+// launch), on the instance's state in S; padding items (instance -1) idle.
+// Each item runs the very device function, template and lane grouping of the
+// plain launch, so every instance computes bit-identically to running alone.
+// ----------------------------------------------------------------------------
+template <int M, int FAM>
+__device__ __forceinline__ void vary_any_lanes(const DevState &st, int L) {
+  switch (vary_lanes_of(st.stride)) {
+    case 8: vary_body<M, FAM, 8>(st, L, vary_blocks_of(st.n, 8)); break;
+    case 4: vary_body<M, FAM, 4>(st, L, vary_blocks_of(st.n, 4)); break;
+    case 2: vary_body<M, FAM, 2>(st, L, vary_blocks_of(st.n, 2)); break;
+    default: vary_body<M, FAM, 1>(st, L, vary_blocks_of(st.n, 1)); break;
+  }
+}
+
+// ----------------------------------------------------------------------------
+// Front: feasible rows of population `pop` that no feasible row dominates
+// (Eq. (5)); candidates staged through LDS tiles.
+// ----------------------------------------------------------------------------
+template <int M>
+__global__ __launch_bounds__(kBlock) void k_front(DevState st, int pop, uint8_t *keep) {
+  constexpr int Q = Rec<M>::Q, kCv = Rec<M>::kCv;
+  __shared__ float4 tile[kBlock * Q];
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  Rec<M> me = rec_zero<M>();
+  bool alive = false;
+  if (i < st.n) {
+    me = rec_load<M>(st.FC[pop], i);
+    alive = (me.v[kCv] == 0.0f);
+  }
+  for (int t0 = 0; t0 < st.n; t0 += kBlock) {
+    if (!__syncthreads_or(alive)) break;
+    const int jj = t0 + threadIdx.x;
+    Rec<M> r = rec_zero<M>();
+    if (jj < st.n) r = rec_load<M>(st.FC[pop], jj);
+    else r.v[kCv] = 1.0f;  // never dominates
+    rec_store<M>(tile, threadIdx.x, r);
+    __syncthreads();
+    const int lim = min(kBlock, st.n - t0);
+    if (alive) {
+      for (int q = 0; q < lim; ++q) {
+        const Rec<M> o = rec_load<M>(tile, q);
+        if (o.v[kCv] != 0.0f) continue;
+        bool le = true, lt = false;
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+          le = le && o.v[k] <= me.v[k];
+          lt = lt || o.v[k] < me.v[k];
+        }
+        if (le && lt) {
+          alive = false;
+          break;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (i < st.n) keep[i] = alive ? 1 : 0;
+}
+
+}  // namespace gmpea

@@ -1,6 +1,7 @@
 // Internal declarations of the GMPEA HIP library: kernel argument blocks and
-// launchers shared by the kernels (gmpea_kernels.hip) and the host runtime
-// (gmpea_abi.cpp, lattice.cpp). Not part of the public ABI.
+// launchers shared by the kernels (gmpea_kernels.hip for m <= 3,
+// gmpea_kernels_wide.hip for m > 3) and the host runtime (gmpea_abi.cpp,
+// lattice.cpp). Not part of the public ABI.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -12,7 +13,7 @@
 
 namespace gmpea {
 
-constexpr int kMaxM = 3;
+constexpr int kMaxM = 8;
 constexpr int kMaxRing = 8;
 constexpr int kBlock = 256;  // threads per block of the per-subproblem kernels
 // Replacement counters are spread over this many words per population: one
@@ -36,11 +37,17 @@ struct DevProblem {
   const float *inv_span;           // device, 1 / (ub - lb), stride each
 };
 
+// float4 words per F/CV record and per reference-vector row: one (f0, f1, f2,
+// cv) up to three objectives, else enough for m objectives and the CV.
+__host__ __device__ constexpr int rec_quads(int m) { return m <= 3 ? 1 : (m + 4) / 4; }
+
 // Device state of one instance. Rows of X are `stride` floats (d rounded up to a
 // multiple of 4 so that every row starts 16-byte aligned); F and CV of one
-// individual share a float4 (f0, f1, f2, cv) with unused objective lanes 0.
+// individual share a record of rq = rec_quads(m) float4: objectives from the
+// first lane, CV in the last lane, unused lanes 0. W rows have the same width.
 struct DevState {
   int32_t n, m, d, stride, nblk;  // nblk: blocks of kBlock rows per population
+  int32_t rq;                      // float4 per F/CV record and per W row
   int32_t t[2];
   int32_t lps[2];                  // lanes per slot in k_select (power of two <= 64)
   int32_t sel_blocks0, sel_blocks1;  // k_select blocks of each population
@@ -102,8 +109,16 @@ __host__ __device__ inline int rows_blocks_of(int n, int stride) {
 hipError_t launch_phase(const DevState &st, int phase, hipStream_t s);
 hipError_t launch_generation(const DevState &st, hipStream_t s);
 // One phase of a batched generation over a pool: work[b] = (instance, block).
+// wide: the work list holds instances with m > 3 (their kernels are separate so
+// that the m <= 3 kernels keep their register budget); phase 3 takes any m.
 hipError_t launch_batch_phase(const DevState *states, const int2 *work, int nwork, int phase,
-                              hipStream_t s);
+                              bool wide, hipStream_t s);
+// The m > 3 launchers (gmpea_kernels_wide.hip).
+hipError_t launch_init_eval_wide(const DevState &st, hipStream_t s);
+hipError_t launch_phase_wide(const DevState &st, int phase, hipStream_t s);
+hipError_t launch_batch_phase_wide(const DevState *states, const int2 *work, int nwork, int phase,
+                                   hipStream_t s);
+hipError_t launch_front_flags_wide(const DevState &st, int pop, uint8_t *keep, hipStream_t s);
 hipError_t launch_front_flags(const DevState &st, int pop, uint8_t *keep, hipStream_t s);
 hipError_t launch_gather(const DevState &st, int pop, const int32_t *idx, int32_t count,
                          float *x, float4 *fc, hipStream_t s);
@@ -137,6 +152,18 @@ void reverse_lists(const std::vector<int32_t> &B, int32_t n, int32_t t, std::vec
 // (squared lattice distance, lexicographic order), enough for t neighbours of
 // interior points; the device builds neighbourhoods by walking this list.
 void neighbour_offsets(int32_t m, int32_t H, int32_t t, std::vector<int32_t> &d);
+// Two-layer reference set (H2 > 0): the lattice k / H1, then the lattice k / H2
+// moved halfway to the centroid, (k / H2 + 1 / m) / 2. K receives the rows as
+// integers on the denominator 2 m H1 H2 (H1 for one layer) and W, if given, the
+// FP64 vectors. refset_knn: the t nearest rows of each row by exact squared
+// distance of those integers, ties by index (brute force, threaded).
+int64_t refset_count(int32_t m, int32_t H1, int32_t H2);
+void refset(int32_t m, int32_t H1, int32_t H2, std::vector<int32_t> &K, std::vector<double> *W);
+void refset_knn(const std::vector<int32_t> &K, int32_t m, int32_t t, std::vector<int32_t> &B);
+// Neighbourhoods of the reference set refset(m, H1, H2) built: the offset walk
+// for one layer with m <= 3, else the brute force.
+void refset_neighbours(const std::vector<int32_t> &K, int32_t m, int32_t H1, int32_t H2, int32_t t,
+                       std::vector<int32_t> &B);
 
 // Device construction of the initialisation tables (gmpea_kernels.hip).
 // W and both neighbourhoods from the offset list; *incomplete becomes nonzero

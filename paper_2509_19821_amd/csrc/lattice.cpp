@@ -21,6 +21,12 @@
 // and grows R until the t-th nearest found lies within distance R. Every lattice
 // point within distance R lies inside the box, so neither method can miss a
 // closer point (or an equal-distance point with a smaller index).
+//
+// Two-layer sets (many objectives): the lattice above with H1 divisions, then a
+// lattice with H2 divisions moved halfway to the centroid. Both layers become
+// integer points on the common denominator 2 m H1 H2, and the neighbourhoods
+// come from a brute-force search over exact squared distances (O(N^2 m) over
+// host threads; such sets hold a few thousand to about 1e5 vectors).
 #include <algorithm>
 #include <cmath>
 #include <thread>
@@ -239,6 +245,72 @@ void lattice_knn(const std::vector<int32_t> &K, int32_t m, int32_t H, int32_t t,
     pool.emplace_back([&, lo, hi] { knn_rows(K, m, H, t, offs, lo, hi, B); });
   }
   for (auto &th : pool) th.join();
+}
+
+int64_t refset_count(int32_t m, int32_t H1, int32_t H2) {
+  return dd_count(m, H1) + (H2 > 0 ? dd_count(m, H2) : 0);
+}
+
+void refset(int32_t m, int32_t H1, int32_t H2, std::vector<int32_t> &K, std::vector<double> *W) {
+  std::vector<int32_t> K1, K2;
+  dd_lattice(m, H1, K1);
+  if (H2 > 0) dd_lattice(m, H2, K2);
+  const size_t n1 = K1.size() / m, n2 = K2.size() / m;
+  K.assign((n1 + n2) * m, 0);
+  if (W) W->assign((n1 + n2) * m, 0.0);
+  // outer layer: k / H1, on the denominator 2 m H1 H2 (H1 alone for one layer)
+  const int32_t so = H2 > 0 ? 2 * m * H2 : 1;
+  for (size_t q = 0; q < n1 * m; ++q) {
+    K[q] = K1[q] * so;
+    if (W) (*W)[q] = static_cast<double>(K1[q]) / H1;
+  }
+  // inner layer: (k / H2 + 1 / m) / 2 = (m H1 k + H1 H2) / (2 m H1 H2)
+  for (size_t q = 0; q < n2 * m; ++q) {
+    K[n1 * m + q] = m * H1 * K2[q] + H1 * H2;
+    if (W) (*W)[n1 * m + q] = (static_cast<double>(K2[q]) / H2 + 1.0 / m) * 0.5;
+  }
+}
+
+void refset_knn(const std::vector<int32_t> &K, int32_t m, int32_t t, std::vector<int32_t> &B) {
+  const int64_t n = static_cast<int64_t>(K.size()) / m;
+  B.assign(static_cast<size_t>(n) * t, 0);
+  auto rows = [&](int64_t lo, int64_t hi) {
+    std::vector<Cand> best;  // the t smallest (distance, index) so far, sorted
+    for (int64_t i = lo; i < hi; ++i) {
+      best.clear();
+      const int32_t *ki = &K[i * m];
+      for (int64_t j = 0; j < n; ++j) {
+        const int32_t *kj = &K[j * m];
+        int64_t dist = 0;
+        for (int32_t a = 0; a < m; ++a) {
+          const int64_t df = int64_t(ki[a]) - kj[a];
+          dist += df * df;
+        }
+        const Cand c{dist, static_cast<int32_t>(j)};
+        if (static_cast<int32_t>(best.size()) == t) {
+          if (!(c < best.back())) continue;
+          best.pop_back();
+        }
+        best.insert(std::upper_bound(best.begin(), best.end(), c), c);
+      }
+      for (int32_t r = 0; r < t; ++r) B[i * t + r] = best[r].idx;
+    }
+  };
+  unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  if (n * n < (1 << 22)) nt = 1;
+  std::vector<std::thread> pool;
+  for (unsigned w = 0; w < nt; ++w)
+    pool.emplace_back(rows, n * w / nt, n * (w + 1) / nt);
+  for (auto &th : pool) th.join();
+}
+
+void refset_neighbours(const std::vector<int32_t> &K, int32_t m, int32_t H1, int32_t H2, int32_t t,
+                       std::vector<int32_t> &B) {
+  // the offset walk enumerates boxes in m - 1 dimensions: cheap for m <= 3 only
+  if (H2 == 0 && m <= 3)
+    lattice_knn(K, m, H1, t, B);
+  else
+    refset_knn(K, m, t, B);
 }
 
 void reverse_lists(const std::vector<int32_t> &B, int32_t n, int32_t t, std::vector<int32_t> &off,

@@ -34,7 +34,8 @@ EXPORTS = ["gmpea_init", "gmpea_step", "gmpea_run", "gmpea_front", "gmpea_get_in
            "gmpea_write", "gmpea_destroy", "gmpea_last_error", "gmpea_sync", "gmpea_profile",
            "gmpea_philox", "gmpea_copy", "gmpea_pool_create", "gmpea_pool_admit",
            "gmpea_pool_step", "gmpea_pool_tune", "gmpea_pool_handle", "gmpea_pool_release",
-           "gmpea_pool_query", "gmpea_pool_sync", "gmpea_pool_destroy", "gmpea_lattice"]
+           "gmpea_pool_query", "gmpea_pool_sync", "gmpea_pool_destroy", "gmpea_lattice",
+           "gmpea_reference_set"]
 PHASES = ("vary", "op1", "select", "rows")
 
 
@@ -57,8 +58,11 @@ class Config(ctypes.Structure):
                 ("t2", ctypes.c_int32), ("agg", ctypes.c_int32), ("theta", ctypes.c_double),
                 ("eta_c", ctypes.c_double), ("eta_m", ctypes.c_double), ("pc", ctypes.c_double),
                 ("pm", ctypes.c_double), ("seed", ctypes.c_uint64), ("record", ctypes.c_int32),
-                ("op", ctypes.c_int32), ("de_f", ctypes.c_double), ("op1_rule", ctypes.c_int32)]
+                ("op", ctypes.c_int32), ("de_f", ctypes.c_double), ("op1_rule", ctypes.c_int32),
+                ("h_outer", ctypes.c_int32), ("h_inner", ctypes.c_int32)]
 
+
+MAX_M = 8  # GMPEA_MAX_M
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
 FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
@@ -71,7 +75,7 @@ class Allocator(ctypes.Structure):
 class Info(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("m", ctypes.c_int32), ("d", ctypes.c_int32),
                 ("t1", ctypes.c_int32), ("t2", ctypes.c_int32), ("H", ctypes.c_int32),
-                ("generation", ctypes.c_int64), ("z", ctypes.c_float * 3),
+                ("H2", ctypes.c_int32), ("generation", ctypes.c_int64), ("z", ctypes.c_float * MAX_M),
                 ("replaced", ctypes.c_int64 * 2), ("feasible_frac", ctypes.c_double),
                 ("device_bytes", ctypes.c_size_t)]
 
@@ -149,6 +153,7 @@ def lib():
         L.gmpea_pool_destroy.restype = None
         L.gmpea_lattice.argtypes = [i32, i32, i32, i32, vp, vp, ctypes.POINTER(i32),
                                     ctypes.POINTER(i32)]
+        L.gmpea_reference_set.argtypes = [i32, i32, i32, i32, i32, vp, vp, ctypes.POINTER(i32)]
         for name in EXPORTS:
             if name not in ("gmpea_destroy", "gmpea_last_error", "gmpea_pool_destroy"):
                 getattr(L, name).restype = ctypes.c_int
@@ -296,7 +301,7 @@ class Gmpea:
     def info(self) -> dict:
         inf = Info()
         _check(lib().gmpea_get_info(self._h, ctypes.byref(inf)))
-        return {"n": inf.n, "m": inf.m, "d": inf.d, "t1": inf.t1, "t2": inf.t2, "H": inf.H,
+        return {"n": inf.n, "m": inf.m, "d": inf.d, "t1": inf.t1, "t2": inf.t2, "H": inf.H, "H2": inf.H2,
                 "generation": int(inf.generation), "z": np.array(inf.z[:inf.m], dtype=np.float32),
                 "replaced": (int(inf.replaced[0]), int(inf.replaced[1])),
                 "feasible_frac": float(inf.feasible_frac), "device_bytes": int(inf.device_bytes)}
@@ -360,6 +365,19 @@ def lattice(m: int, n_req: int, t: int):
     return int(H.value), K, B
 
 
+def reference_set(m: int, h_outer: int, h_inner: int, t: int):
+    """(K, B) of gmpea_reference_set: the layered reference set as integers over
+    2 m h_outer h_inner (N x m) and the t nearest rows of each (N x t), on the host."""
+    n = ctypes.c_int32(0)
+    _check(lib().gmpea_reference_set(int(m), int(h_outer), int(h_inner), int(t), 0, None, None,
+                                     ctypes.byref(n)))
+    K = np.empty((n.value, int(m)), dtype=np.int32)
+    B = np.empty((n.value, int(t)), dtype=np.int32)
+    _check(lib().gmpea_reference_set(int(m), int(h_outer), int(h_inner), int(t), n.value,
+                                     K.ctypes.data, B.ctypes.data, ctypes.byref(n)))
+    return K, B
+
+
 def _structs(problem: dict, config: dict, record: bool = False):
     m, d = int(problem["m"]), int(problem["d"])
     nr = int(np.asarray(problem["ring_radius"]).size)
@@ -375,7 +393,8 @@ def _structs(problem: dict, config: dict, record: bool = False):
                int(c.get("agg", 0)), float(c.get("theta", 0.0)), float(c.get("eta_c", 0.0)),
                float(c.get("eta_m", 0.0)), float(c.get("pc", 0.0)), float(c.get("pm", 0.0)),
                int(c["seed"]) & 0xFFFFFFFFFFFFFFFF, 1 if (record or c.get("record", 0)) else 0,
-               int(c.get("op", 0)), float(c.get("de_f", 0.0)), int(c.get("op1_rule", 0)))
+               int(c.get("op", 0)), float(c.get("de_f", 0.0)), int(c.get("op1_rule", 0)),
+               int(c.get("h_outer", 0)), int(c.get("h_inner", 0)))
     return P, C, keep
 
 

@@ -55,7 +55,8 @@ def _init(glib, prob, cfg):
                   prob["has_sum_lower"], prob["sum_lower"], prob["n_eq"], prob["eq_tol"])
     C = G.Config(cfg["n_req"], cfg["T"], cfg["t1"], cfg["t2"], cfg["agg"], cfg["theta"],
                  cfg["eta_c"], cfg["eta_m"], cfg["pc"], cfg["pm"], cfg["seed"], 0,
-                 cfg.get("op", 0), cfg.get("de_f", 0.0), cfg.get("op1_rule", 0))
+                 cfg.get("op", 0), cfg.get("de_f", 0.0), cfg.get("op1_rule", 0),
+                 cfg.get("h_outer", 0), cfg.get("h_inner", 0))
     h = ctypes.c_void_p()
     st = L.gmpea_init(ctypes.byref(P), ctypes.byref(C), None, None, ctypes.byref(h))
     return st, L.gmpea_last_error().decode()
@@ -66,7 +67,11 @@ def _init(glib, prob, cfg):
     (lambda p, c: c.update(t1=101), -1),                     # t1 > N
     (lambda p, c: c.update(n_req=1), -1),                    # fewer than two subproblems
     (lambda p, c: p.update(ub=np.zeros(10)), -1),            # lb >= ub
-    (lambda p, c: p.update(m=4), -6),                        # beyond the objectives supported
+    (lambda p, c: p.update(m=9), -6),                        # beyond the objectives supported
+    (lambda p, c: p.update(m=4), -1),                        # the curve family has two
+    (lambda p, c: p.update(family=1, m=8, d=6), -1),         # sphere: d below m - 1
+    (lambda p, c: c.update(h_inner=2), -1),                  # inner layer without an outer one
+    (lambda p, c: c.update(h_outer=-1), -1),                 # negative divisions
     (lambda p, c: p.update(family=7), -1),                   # unknown family
     (lambda p, c: c.update(agg=5), -1),                      # unknown aggregation
     (lambda p, c: c.update(pm=1.5), -1),                     # probability above 1
@@ -139,10 +144,44 @@ def test_host_lattice_matches_bruteforce(glib, m, n_req, t):
 def test_host_lattice_rejects_invalid(glib):
     from paper_2509_19821_amd import gmpea as G
     with pytest.raises(G.GmpeaError):
-        glib.lattice(4, 100, 10)
+        glib.lattice(9, 100, 10)
     with pytest.raises(G.GmpeaError):
         glib.lattice(2, 100, 101)
     H, n = ctypes.c_int32(0), ctypes.c_int32(0)
     K = np.empty((2, 2), dtype=np.int32)
     st = G.lib().gmpea_lattice(2, 100, 3, 2, K.ctypes.data, None, ctypes.byref(H), ctypes.byref(n))
     assert st == -4 and n.value == 100 and H.value == 99
+
+
+@pytest.mark.parametrize("m,n_req,t", [(4, 200, 20), (5, 210, 20), (8, 120, 40), (6, 500, 10)])
+def test_host_lattice_many_objectives(glib, m, n_req, t):
+    """Single-layer lattices for m > 3 (the offset walk in m - 1 leading
+    coordinates) against the oracle's brute force."""
+    from oracle import core
+    H, K, B = glib.lattice(m, n_req, t)
+    Ko = core.dd_lattice(m, H)
+    assert np.array_equal(K, Ko)
+    assert np.array_equal(B, core.knn(Ko, t))
+
+
+@pytest.mark.parametrize("m,h1,h2,t", [(8, 3, 2, 20), (5, 4, 2, 16), (4, 6, 3, 30), (2, 4, 2, 3),
+                                       (6, 3, 0, 12), (3, 12, 6, 40)])
+def test_host_reference_set_matches_oracle(glib, m, h1, h2, t):
+    """The library's layered reference set (R28) and its brute-force neighbourhoods
+    equal the oracle's, integer coordinates included."""
+    from oracle import core
+    K, B = glib.reference_set(m, h1, h2, t)
+    _, Ko = core.reference_set(m, h1, h2)
+    assert np.array_equal(K, Ko)
+    assert np.array_equal(B, core.knn(Ko, t))
+
+
+def test_host_reference_set_rejects_invalid(glib):
+    from paper_2509_19821_amd import gmpea as G
+    for args in ((9, 3, 2, 5), (4, 0, 2, 5), (4, 3, -1, 5), (4, 3, 2, 1000)):
+        with pytest.raises(G.GmpeaError):
+            glib.reference_set(*args)
+    n = ctypes.c_int32(0)
+    K = np.empty((2, 8), dtype=np.int32)
+    st = G.lib().gmpea_reference_set(8, 3, 2, 5, 2, K.ctypes.data, None, ctypes.byref(n))
+    assert st == -4 and n.value == 156

@@ -121,3 +121,32 @@ def test_pool_front_and_empty_steps(G):
         assert pool.instance(s).read("GEN")[0] == 20
     finally:
         pool.close()
+
+
+def test_batched_mixed_objectives_equal_alone(G):
+    """A pool holding m = 2 .. 8: the m > 3 instances run in their own batched
+    kernels (the row copies are shared by all), and every instance still equals
+    its run alone, bit for bit."""
+    S = ci.FAMILY_SPHERE
+    mix = [ci.workload_small(13)[:2], ci.workload_many5(14)[:2], ci.workload_many8(15)[:2],
+           (ci.make_problem(S, 6, 33, 2, True, False, 16),
+            ci.method_config(2, 10, 16, op=1, h_outer=5, h_inner=3)),
+           (ci.make_problem(S, 3, 40, 2, True, False, 17), ci.method_config(900, 12, 17)),
+           (ci.make_problem(S, 4, 9, 1, False, False, 18), ci.method_config(400, 8, 18, agg=1))]
+    gens = 21  # one graph replay of 16 plus eager generations
+    pool = G.Pool(4 << 30)
+    try:
+        slots = [pool.admit(p, c) for p, c in mix]
+        pool.step(gens)
+        pool.sync()
+        for (p, c), s in zip(mix, slots):
+            _same(pool.instance(s).state(), _alone(G, p, c, gens))
+        # releasing the wide instances leaves a pool of m <= 3 only, and back
+        pool.release(slots[1])
+        pool.release(slots[2])
+        pool.step(3)
+        pool.sync()
+        _same(pool.instance(slots[0]).state(), _alone(G, *mix[0], gens + 3))
+        _same(pool.instance(slots[3]).state(), _alone(G, *mix[3], gens + 3))
+    finally:
+        pool.close()
