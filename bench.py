@@ -169,14 +169,23 @@ def batched_vs_plain(g, ci, count=256, gens=300):
             "graph_chunk": q["chunk"]}
 
 
-def serving(g, ci, window_s=5.0, rate=200.0):
+def serving(g, ci, window_s=5.0, rate=200.0, quality_every=16):
     """Poisson arrivals at `rate` per second over `window_s`, deadlines
     log-uniform in [10 ms, 1 s], problems from the batched-instance
-    distribution; continuous batching over one pool."""
+    distribution; continuous batching over one pool. Every `quality_every`-th
+    request carries a reference front (built before the window opens), so its
+    IGD and HV at the deadline are measured on the device before delivery."""
+    from paper_2509_19821_amd import fronts
     from paper_2509_19821_amd.serve import Request, Server, summarize
     arr = ci.serve_arrivals(rate=rate, window_s=window_s, master_seed=0)
     inst = ci.batch_instances(count=len(arr), master_seed=1)
-    reqs = [Request(k, p, c, dl, t) for k, ((t, dl), (p, c)) in enumerate(zip(arr, inst))]
+    reqs = []
+    for k, ((t, dl), (p, c)) in enumerate(zip(arr, inst)):
+        ref = hvp = None
+        if quality_every and k % quality_every == 0:
+            ref = fronts.reference_front(p, n=800)
+            hvp = 1.1 * ref.max(0)  # the HV reference point 1.1 x the front's maximum
+        reqs.append(Request(k, p, c, dl, t, reference=ref, hv_point=hvp))
     srv = Server(200 << 30, keep_fronts=False)
     try:
         t0 = time.perf_counter()

@@ -226,6 +226,27 @@ gmpea_status gmpea_run(gmpea_t h, int32_t max_gen, double time_limit_s, int32_t 
 gmpea_status gmpea_front(gmpea_t h, int32_t what, int32_t capacity, float *x, float *f,
                          float *cv, int32_t *idx, int32_t *count);
 
+/* Quality of the current front on the device: the feasible non-dominated rows
+ * of population 1 (as GMPEA_FRONT_FEASIBLE_ND), measured by IGD (Eq. (14)) and
+ * HV (Eq. (15)) without copying the front to the host. Synchronises.
+ *  igd (may be NULL): mean over the n_ref reference points ref (n_ref x m,
+ *    host, row-major) of the Euclidean distance to the nearest front point;
+ *    distances in FP32, their sum in FP64 in a fixed order (reproducible).
+ *  hv (may be NULL): Monte Carlo estimate of the volume weakly dominated by the
+ *    front and bounded by hv_point (m host floats): hv_samples points uniform
+ *    in the box from the front's per-objective minimum to hv_point, drawn from
+ *    the library's Philox4x32-10 keyed by hv_seed (sample s takes blocks
+ *    (s mod 2^32, s >> 32, 0 and 1, 4 << 24), words in objective order, u as
+ *    in the method's draws); hv = box volume x covered share. Its standard
+ *    error is box volume x sqrt(p (1 - p) / hv_samples).
+ *  front_count (may be NULL): the front's row count. An empty front gives
+ *    igd = +inf and hv = 0.
+ * Errors: ESTATE, EINVAL (igd without ref or n_ref < 1; hv without hv_point,
+ * a non-finite hv_point or hv_samples outside [1, 2^34]), ENOMEM, EHIP. */
+gmpea_status gmpea_quality(gmpea_t h, const float *ref, int32_t n_ref, const float *hv_point,
+                           int64_t hv_samples, uint64_t hv_seed, double *igd, double *hv,
+                           int32_t *front_count);
+
 /* Wait until every generation enqueued on the handle's stream has finished. */
 gmpea_status gmpea_sync(gmpea_t h);
 

@@ -86,6 +86,41 @@ def hv_inclusion_exclusion(P: np.ndarray, r: np.ndarray) -> float:
     return tot
 
 
+def hv_mc(P: np.ndarray, r: np.ndarray, samples: int, seed: int = 0, chunk: int = 1 << 16) -> float:
+    """Monte Carlo HV (Eq. (15)) with the library's sampling rule, in FP64:
+    sample s is uniform in the box from P's per-objective minimum to r, its
+    coordinates u_k = (w_k >> 8) 2^-24 from Philox4x32-10 keyed by seed with
+    counters (s mod 2^32, s >> 32, b, 4 << 24), b = 0 for objectives 1..4 and
+    b = 1 for 5..8; a sample counts when some row of P is <= it in every
+    objective. Returns box volume x covered share."""
+    P = np.asarray(P, dtype=np.float64)
+    r = np.asarray(r, dtype=np.float64)
+    if P.shape[0] == 0:
+        return 0.0
+    m = P.shape[1]
+    lo = P.min(0)
+    vol = float(np.prod(np.clip(r - lo, 0.0, None)))
+    if not vol > 0:
+        return 0.0
+    key = np.array([seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF], dtype=np.uint32)
+    hits = 0
+    for s0 in range(0, samples, chunk):
+        s = np.arange(s0, min(samples, s0 + chunk), dtype=np.uint64)
+        words = []
+        for b in range(2 if m > 4 else 1):
+            ctr = np.stack([s & 0xFFFFFFFF, s >> 32, np.full_like(s, b),
+                            np.full_like(s, 4 << 24)], 1).astype(np.uint32)
+            words.append(core.philox(ctr, key))
+        w = np.concatenate(words, 1)[:, :m].astype(np.float64)
+        u = np.floor(w / 256.0) * 2.0 ** -24
+        X = lo + u * (r - lo)
+        covered = np.zeros(X.shape[0], dtype=bool)
+        for q0 in range(0, P.shape[0], 256):
+            covered |= np.any(np.all(P[None, q0:q0 + 256, :] <= X[:, None, :], axis=2), axis=1)
+        hits += int(covered.sum())
+    return vol * hits / samples
+
+
 def _feasible_objective(prob: dict, F: np.ndarray, tol: float = 1e-9) -> np.ndarray:
     """Objective-space constraints (rings, linear bound) satisfied within tol."""
     ok = np.ones(F.shape[0], dtype=bool)

@@ -5,6 +5,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdlib>
+#include <limits>
 #include <map>
 #include <mutex>
 #include <string>
@@ -48,6 +49,14 @@ struct gmpea_s {
   int32_t *f_idx = nullptr;
   float *f_x = nullptr;
   float4 *f_fc = nullptr;
+  // gmpea_quality scratch (reference points, IGD partial sums, HV box and
+  // counter), grown on demand
+  float *q_ref = nullptr;
+  size_t q_ref_cap = 0;
+  double *q_part = nullptr;
+  size_t q_part_cap = 0;
+  float *q_box = nullptr;                // lo[kMaxM], hi[kMaxM]
+  unsigned long long *q_hits = nullptr;
   // graph replay of `gchunk` generations
   hipGraphExec_t gexec = nullptr;
   int32_t gchunk = 0;
@@ -262,6 +271,73 @@ gmpea_status check_runtime(const char *who) {
                     std::to_string(HIP_VERSION_MAJOR) + "." + std::to_string(HIP_VERSION_MINOR) +
                     " toolchain this library was built with; load it in a process whose HIP "
                     "runtime is the toolchain's (or newer)");
+  return GMPEA_OK;
+}
+
+gmpea_status front_scratch(gmpea_s *h, const char *who) {
+  if (h->f_keep) return GMPEA_OK;
+  const DevState &st = h->st;
+  auto layout = [&](Carve &c) {
+    h->f_keep = c.take<uint8_t>(st.n);
+    h->f_idx = c.take<int32_t>(st.n);
+    h->f_x = c.take<float>(static_cast<size_t>(st.n) * st.d);
+    h->f_fc = c.take<float4>(static_cast<size_t>(st.n) * st.rq);
+  };
+  Carve sizing;
+  layout(sizing);
+  Carve carve;
+  carve.base = static_cast<char *>(dev_alloc(h, sizing.off));
+  if (!carve.base) {
+    h->f_keep = nullptr;
+    return fail(GMPEA_ENOMEM, std::string(who) + ": scratch allocation failed");
+  }
+  layout(carve);
+  return GMPEA_OK;
+}
+
+// Row indices (ascending) of a front selector: the feasible non-dominated rows
+// of population 1 (flags on the device), or every row of a population.
+gmpea_status front_rows(gmpea_s *h, int32_t what, std::vector<int32_t> &rows, const char *who) {
+  gmpea_status s = front_scratch(h, who);
+  if (s != GMPEA_OK) return s;
+  const DevState &st = h->st;
+  rows.clear();
+  if (what == GMPEA_FRONT_FEASIBLE_ND) {
+    hipError_t e = launch_front_flags(st, 0, h->f_keep, h->stream);
+    std::vector<uint8_t> hk(st.n);
+    s = e == hipSuccess ? d2h(h, hk.data(), h->f_keep, st.n, who) : hip_fail(e, who);
+    if (s != GMPEA_OK) return s;
+    for (int32_t i = 0; i < st.n; ++i)
+      if (hk[i]) rows.push_back(i);
+  } else {
+    s = sync(h, who);
+    if (s != GMPEA_OK) return s;
+    rows.resize(st.n);
+    for (int32_t i = 0; i < st.n; ++i) rows[i] = i;
+  }
+  return GMPEA_OK;
+}
+
+// Rows (non-empty) of population `pop` gathered into the scratch: X to f_x,
+// F/CV records to f_fc.
+gmpea_status front_gather(gmpea_s *h, int pop, const std::vector<int32_t> &rows, const char *who) {
+  const int32_t cnt = static_cast<int32_t>(rows.size());
+  gmpea_status s = h2d(h, h->f_idx, rows.data(), cnt, who);
+  if (s != GMPEA_OK) return s;
+  hipError_t e = launch_gather(h->st, pop, h->f_idx, cnt, h->f_x, h->f_fc, h->stream);
+  if (e != hipSuccess) return hip_fail(e, who);
+  return GMPEA_OK;
+}
+
+// Device buffer of at least `need` elements, regrown through the handle's
+// allocator (contents are not kept).
+template <class T>
+gmpea_status grow(gmpea_s *h, T **buf, size_t *cap, size_t need, const char *who) {
+  if (*buf && *cap >= need) return GMPEA_OK;
+  if (*buf) dev_free(h, *buf);
+  *buf = static_cast<T *>(dev_alloc(h, std::max<size_t>(need, 1) * sizeof(T)));
+  *cap = *buf ? need : 0;
+  if (!*buf) return fail(GMPEA_ENOMEM, std::string(who) + ": scratch allocation failed");
   return GMPEA_OK;
 }
 
@@ -603,53 +679,18 @@ gmpea_status gmpea_front(gmpea_t h, int32_t what, int32_t capacity, float *x, fl
   if (capacity < 0) return fail(GMPEA_EINVAL, "gmpea_front: negative capacity");
   const DevState &st = h->st;
   const int pop = what == GMPEA_FRONT_POP2 ? 1 : 0;
-  if (!h->f_keep) {
-    auto layout = [&](Carve &c) {
-      h->f_keep = c.take<uint8_t>(st.n);
-      h->f_idx = c.take<int32_t>(st.n);
-      h->f_x = c.take<float>(static_cast<size_t>(st.n) * st.d);
-      h->f_fc = c.take<float4>(static_cast<size_t>(st.n) * st.rq);
-    };
-    Carve sizing;
-    layout(sizing);
-    Carve carve;
-    carve.base = static_cast<char *>(dev_alloc(h, sizing.off));
-    if (!carve.base) {
-      h->f_keep = nullptr;
-      return fail(GMPEA_ENOMEM, "gmpea_front: scratch allocation failed");
-    }
-    layout(carve);
-  }
   std::vector<int32_t> rows;
-  if (what == GMPEA_FRONT_FEASIBLE_ND) {
-    hipError_t e = launch_front_flags(st, pop, h->f_keep, h->stream);
-    std::vector<uint8_t> hk(st.n);
-    gmpea_status s =
-        e == hipSuccess ? d2h(h, hk.data(), h->f_keep, st.n, "gmpea_front") : hip_fail(e, "gmpea_front");
-    if (s != GMPEA_OK) return s;
-    for (int32_t i = 0; i < st.n; ++i)
-      if (hk[i]) rows.push_back(i);
-  } else {
-    gmpea_status s = sync(h, "gmpea_front");
-    if (s != GMPEA_OK) return s;
-    rows.resize(st.n);
-    for (int32_t i = 0; i < st.n; ++i) rows[i] = i;
-  }
+  gmpea_status s = front_rows(h, what, rows, "gmpea_front");
+  if (s != GMPEA_OK) return s;
   const int32_t cnt = static_cast<int32_t>(rows.size());
   *count = cnt;
   if (cnt > capacity) return fail(GMPEA_ECAPACITY, "gmpea_front: capacity below the row count");
   if (cnt == 0) return GMPEA_OK;
   if (idx) std::copy(rows.begin(), rows.end(), idx);
-  int32_t *didx = h->f_idx;
   float *dx = h->f_x;
   float4 *dfc = h->f_fc;
-  gmpea_status s = GMPEA_OK;
   std::vector<float4> hfc;
-  if (s == GMPEA_OK) s = h2d(h, didx, rows.data(), cnt, "gmpea_front");
-  if (s == GMPEA_OK) {
-    hipError_t e = launch_gather(st, pop, didx, cnt, dx, dfc, h->stream);
-    if (e != hipSuccess) s = hip_fail(e, "gmpea_front gather");
-  }
+  s = front_gather(h, pop, rows, "gmpea_front");
   if (s == GMPEA_OK && x) s = d2h(h, x, dx, static_cast<size_t>(cnt) * st.d, "gmpea_front");
   if (s == GMPEA_OK) {
     hfc.resize(static_cast<size_t>(cnt) * st.rq);
@@ -697,6 +738,89 @@ gmpea_status gmpea_get_info(gmpea_t h, gmpea_info *info) {
   for (int32_t i = 0; i < st.n; ++i) feas += fc[static_cast<size_t>(i) * st.rq + st.rq - 1].w == 0.0f;
   info->feasible_frac = static_cast<double>(feas) / st.n;
   info->device_bytes = h->bytes;
+  return GMPEA_OK;
+}
+
+gmpea_status gmpea_quality(gmpea_t h, const float *ref, int32_t n_ref, const float *hv_point,
+                           int64_t hv_samples, uint64_t hv_seed, double *igd, double *hv,
+                           int32_t *front_count) {
+  const char *who = "gmpea_quality";
+  if (!valid(h)) return fail(GMPEA_ESTATE, "gmpea_quality: invalid handle");
+  if (igd && (!ref || n_ref < 1)) return fail(GMPEA_EINVAL, "gmpea_quality: IGD needs ref and n_ref >= 1");
+  if (hv && (!hv_point || hv_samples < 1 || hv_samples > (int64_t(1) << 34)))
+    return fail(GMPEA_EINVAL, "gmpea_quality: HV needs hv_point and 1 <= hv_samples <= 2^34");
+  const DevState &st = h->st;
+  const int32_t m = st.m;
+  if (hv)
+    for (int32_t k = 0; k < m; ++k)
+      if (!std::isfinite(hv_point[k])) return fail(GMPEA_EINVAL, "gmpea_quality: hv_point must be finite");
+  std::vector<int32_t> rows;
+  gmpea_status s = front_rows(h, GMPEA_FRONT_FEASIBLE_ND, rows, who);
+  if (s != GMPEA_OK) return s;
+  const int32_t cnt = static_cast<int32_t>(rows.size());
+  if (front_count) *front_count = cnt;
+  if (cnt == 0) {  // no feasible row: no point is covered
+    if (igd) *igd = std::numeric_limits<double>::infinity();
+    if (hv) *hv = 0.0;
+    return GMPEA_OK;
+  }
+  s = front_gather(h, 0, rows, who);
+  if (s != GMPEA_OK) return s;
+  if (igd) {
+    const int32_t blocks_max = (n_ref + kBlock - 1) / kBlock;
+    s = grow(h, &h->q_ref, &h->q_ref_cap, static_cast<size_t>(n_ref) * m, who);
+    if (s == GMPEA_OK) s = grow(h, &h->q_part, &h->q_part_cap, static_cast<size_t>(blocks_max), who);
+    if (s == GMPEA_OK) s = h2d(h, h->q_ref, ref, static_cast<size_t>(n_ref) * m, who);
+    if (s != GMPEA_OK) return s;
+    int32_t blocks = 0;
+    hipError_t e = launch_igd(h->q_ref, n_ref, m, h->f_fc, cnt, st.rq, h->q_part, &blocks, h->stream);
+    if (e != hipSuccess) return hip_fail(e, who);
+    std::vector<double> part(static_cast<size_t>(blocks));
+    s = d2h(h, part.data(), h->q_part, part.size(), who);
+    if (s != GMPEA_OK) return s;
+    double sum = 0.0;
+    for (double v : part) sum += v;  // fixed order: the result is reproducible
+    *igd = sum / n_ref;
+  }
+  if (hv) {
+    // the box from the front's per-objective minimum to the reference point
+    // holds every dominated point below the reference point
+    std::vector<float> recs(static_cast<size_t>(cnt) * st.rq * 4);
+    s = d2h(h, recs.data(), h->f_fc, recs.size(), who);
+    if (s != GMPEA_OK) return s;
+    float box[2 * kMaxM];
+    double vol = 1.0;
+    for (int32_t k = 0; k < m; ++k) {
+      float lo = recs[k];
+      for (int32_t r = 1; r < cnt; ++r) lo = std::min(lo, recs[static_cast<size_t>(r) * st.rq * 4 + k]);
+      box[k] = lo;
+      box[kMaxM + k] = hv_point[k];
+      vol *= std::max(0.0, static_cast<double>(hv_point[k]) - static_cast<double>(lo));
+    }
+    if (!(vol > 0.0)) {
+      *hv = 0.0;
+      return GMPEA_OK;
+    }
+    if (!h->q_box) {
+      void *p = dev_alloc(h, 2 * kMaxM * sizeof(float) + 256);
+      if (!p) return fail(GMPEA_ENOMEM, "gmpea_quality: scratch allocation failed");
+      h->q_box = static_cast<float *>(p);
+      h->q_hits = reinterpret_cast<unsigned long long *>(static_cast<char *>(p) + 2 * kMaxM * sizeof(float) + 128);
+    }
+    const unsigned long long zero = 0;
+    s = h2d(h, h->q_box, box, 2 * kMaxM, who);
+    if (s == GMPEA_OK) s = h2d(h, h->q_hits, &zero, 1, who);
+    if (s != GMPEA_OK) return s;
+    hipError_t e = launch_hv(hv_samples, m, h->q_box, h->q_box + kMaxM,
+                             static_cast<uint32_t>(hv_seed & 0xFFFFFFFFull),
+                             static_cast<uint32_t>(hv_seed >> 32), h->f_fc, cnt, st.rq, h->q_hits,
+                             h->stream);
+    if (e != hipSuccess) return hip_fail(e, who);
+    unsigned long long hits = 0;
+    s = d2h(h, &hits, h->q_hits, 1, who);
+    if (s != GMPEA_OK) return s;
+    *hv = vol * static_cast<double>(hits) / static_cast<double>(hv_samples);
+  }
   return GMPEA_OK;
 }
 

@@ -24,6 +24,7 @@ constexpr int kReplLanes = 64;
 constexpr uint32_t kTagInit = 1u;
 constexpr uint32_t kTagMate = 2u;
 constexpr uint32_t kTagVar = 3u;
+constexpr uint32_t kTagHv = 4u;  // Monte Carlo samples of the hypervolume (not the method's)
 
 // Problem constants in the device precision, passed by value to every kernel
 // that evaluates F and CV.
@@ -123,6 +124,16 @@ hipError_t launch_front_flags(const DevState &st, int pop, uint8_t *keep, hipStr
 hipError_t launch_gather(const DevState &st, int pop, const int32_t *idx, int32_t count,
                          float *x, float4 *fc, hipStream_t s);
 hipError_t launch_copy(const void *src, void *dst, int64_t n16, hipStream_t s);
+// Front quality (Eqs. (14)-(15)) of `count` front records (rq float4 each).
+// IGD: partial[b] receives the sum over block b's reference points of the
+// distance to the nearest front point (n_ref x m reference rows, row-major).
+// HV: *hits (zero on entry) receives how many of samples [0, n) drawn uniformly
+// in the box [lo, hi] are weakly dominated by some front point.
+hipError_t launch_igd(const float *ref, int32_t n_ref, int32_t m, const float4 *front, int32_t count,
+                      int32_t rq, double *partial, int32_t *blocks, hipStream_t s);
+hipError_t launch_hv(int64_t n, int32_t m, const float *lo, const float *hi, uint32_t k0, uint32_t k1,
+                     const float4 *front, int32_t count, int32_t rq, unsigned long long *hits,
+                     hipStream_t s);
 hipError_t launch_philox(const uint32_t *ctr, int64_t n, uint32_t k0, uint32_t k1, uint32_t *out,
                          hipStream_t s);
 

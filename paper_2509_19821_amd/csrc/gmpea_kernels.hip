@@ -270,6 +270,95 @@ __global__ __launch_bounds__(kBlock) void k_gather(DevState st, int pop, const i
     fc[static_cast<size_t>(r) * st.rq + threadIdx.x] = st.FC[pop][static_cast<size_t>(row) * st.rq + threadIdx.x];
 }
 
+// ----------------------------------------------------------------------------
+// Front quality (Eqs. (14)-(15)), for results delivered at a deadline.
+// The front's objectives are staged through LDS tiles of kBlock points; m and
+// the record width are run-time values (one kernel serves every m).
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ void stage_front(float *tile, const float4 *front, int count, int rq,
+                                            int m, int t0) {
+  const int jj = t0 + threadIdx.x;
+  if (jj < count) {
+    const float *rec = reinterpret_cast<const float *>(front + static_cast<size_t>(jj) * rq);
+    for (int k = 0; k < m; ++k) tile[threadIdx.x * kMaxM + k] = rec[k];
+  }
+}
+
+// IGD: one thread per reference point; the block's sum of nearest distances
+// (FP64) goes to partial[blockIdx.x].
+__global__ __launch_bounds__(kBlock) void k_igd(const float *__restrict__ ref, int32_t n_ref,
+                                                int32_t m, const float4 *__restrict__ front,
+                                                int32_t count, int32_t rq, double *partial) {
+  __shared__ float tile[kBlock * kMaxM];
+  __shared__ double red[kBlock / 64];
+  const int r = blockIdx.x * kBlock + threadIdx.x;
+  float v[kMaxM];
+#pragma unroll
+  for (int k = 0; k < kMaxM; ++k) v[k] = (r < n_ref && k < m) ? ref[static_cast<size_t>(r) * m + k] : 0.0f;
+  float best = __builtin_huge_valf();
+  for (int t0 = 0; t0 < count; t0 += kBlock) {
+    stage_front(tile, front, count, rq, m, t0);
+    __syncthreads();
+    const int lim = min(kBlock, count - t0);
+    for (int q = 0; q < lim; ++q) {
+      float d2 = 0.0f;
+#pragma unroll
+      for (int k = 0; k < kMaxM; ++k)
+        if (k < m) {
+          const float df = v[k] - tile[q * kMaxM + k];
+          d2 = fmaf(df, df, d2);
+        }
+      best = fminf(best, d2);
+    }
+    __syncthreads();
+  }
+  double x = (r < n_ref) ? static_cast<double>(sqrtf(best)) : 0.0;
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double sum = 0.0;
+    for (int w = 0; w < kBlock / 64; ++w) sum += red[w];
+    partial[blockIdx.x] = sum;
+  }
+}
+
+// HV by Monte Carlo: one thread per sample, drawn from the counter RNG (tag
+// kTagHv, counter (sample low word, sample high word, block, tag << 24)) in the
+// box [lo, hi]; a sample counts when some front point is <= it in every
+// objective. Tiles stop once every sample of the block is dominated.
+__global__ __launch_bounds__(kBlock) void k_hv(int64_t n, int32_t m, const float *__restrict__ lo,
+                                               const float *__restrict__ hi, uint32_t k0, uint32_t k1,
+                                               const float4 *__restrict__ front, int32_t count,
+                                               int32_t rq, unsigned long long *hits) {
+  __shared__ float tile[kBlock * kMaxM];
+  const int64_t sidx = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  float x[kMaxM];
+  const uint32_t c0 = static_cast<uint32_t>(sidx), c1 = static_cast<uint32_t>(sidx >> 32);
+  const uint4 wa = philox10(make_uint4(c0, c1, 0u, kTagHv << 24), k0, k1);
+  const uint4 wb = m > 4 ? philox10(make_uint4(c0, c1, 1u, kTagHv << 24), k0, k1) : make_uint4(0, 0, 0, 0);
+  const uint32_t w[8] = {wa.x, wa.y, wa.z, wa.w, wb.x, wb.y, wb.z, wb.w};
+#pragma unroll
+  for (int k = 0; k < kMaxM; ++k) x[k] = k < m ? fmaf(hi[k] - lo[k], u24(w[k]), lo[k]) : 0.0f;
+  bool dom = sidx >= n;  // samples past the end count as done (and are not counted)
+  for (int t0 = 0; t0 < count; t0 += kBlock) {
+    if (__syncthreads_and(dom)) break;
+    stage_front(tile, front, count, rq, m, t0);
+    __syncthreads();
+    const int lim = min(kBlock, count - t0);
+    for (int q = 0; q < lim && !dom; ++q) {
+      bool le = true;
+#pragma unroll
+      for (int k = 0; k < kMaxM; ++k)
+        if (k < m) le = le && tile[q * kMaxM + k] <= x[k];
+      dom = le;
+    }
+    __syncthreads();
+  }
+  const int c = __syncthreads_count(dom && sidx < n);
+  if (threadIdx.x == 0 && c > 0) atomicAdd(hits, static_cast<unsigned long long>(c));
+}
+
 __global__ __launch_bounds__(kBlock) void k_philox(const uint4 *ctr, int64_t n, uint32_t k0,
                                                    uint32_t k1, uint4 *out) {
   const int64_t q = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
@@ -426,6 +515,25 @@ hipError_t launch_copy(const void *src, void *dst, int64_t n16, hipStream_t s) {
   const int64_t blocks = std::min<int64_t>((n16 + kBlock - 1) / kBlock, 256 * 16);
   hipLaunchKernelGGL(k_copy, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, s,
                      static_cast<const uint4 *>(src), static_cast<uint4 *>(dst), n16);
+  return hipGetLastError();
+}
+
+hipError_t launch_igd(const float *ref, int32_t n_ref, int32_t m, const float4 *front, int32_t count,
+                      int32_t rq, double *partial, int32_t *blocks, hipStream_t s) {
+  const int grid = (n_ref + kBlock - 1) / kBlock;
+  *blocks = grid;
+  if (grid == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_igd, dim3(grid), dim3(kBlock), 0, s, ref, n_ref, m, front, count, rq, partial);
+  return hipGetLastError();
+}
+
+hipError_t launch_hv(int64_t n, int32_t m, const float *lo, const float *hi, uint32_t k0, uint32_t k1,
+                     const float4 *front, int32_t count, int32_t rq, unsigned long long *hits,
+                     hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int64_t grid = (n + kBlock - 1) / kBlock;
+  hipLaunchKernelGGL(k_hv, dim3(static_cast<unsigned>(grid)), dim3(kBlock), 0, s, n, m, lo, hi, k0, k1,
+                     front, count, rq, hits);
   return hipGetLastError();
 }
 

@@ -35,7 +35,7 @@ EXPORTS = ["gmpea_init", "gmpea_step", "gmpea_run", "gmpea_front", "gmpea_get_in
            "gmpea_philox", "gmpea_copy", "gmpea_pool_create", "gmpea_pool_admit",
            "gmpea_pool_step", "gmpea_pool_tune", "gmpea_pool_handle", "gmpea_pool_release",
            "gmpea_pool_query", "gmpea_pool_sync", "gmpea_pool_destroy", "gmpea_lattice",
-           "gmpea_reference_set"]
+           "gmpea_reference_set", "gmpea_quality"]
 PHASES = ("vary", "op1", "select", "rows")
 
 
@@ -154,6 +154,7 @@ def lib():
         L.gmpea_lattice.argtypes = [i32, i32, i32, i32, vp, vp, ctypes.POINTER(i32),
                                     ctypes.POINTER(i32)]
         L.gmpea_reference_set.argtypes = [i32, i32, i32, i32, i32, vp, vp, ctypes.POINTER(i32)]
+        L.gmpea_quality.argtypes = [vp, vp, i32, vp, i64, ctypes.c_uint64, vp, vp, vp]
         for name in EXPORTS:
             if name not in ("gmpea_destroy", "gmpea_last_error", "gmpea_pool_destroy"):
                 getattr(L, name).restype = ctypes.c_int
@@ -290,6 +291,22 @@ class Gmpea:
                                  cv.ctypes.data, idx.ctypes.data, ctypes.byref(cnt)))
         k = int(cnt.value)
         return {"x": x[:k].copy(), "f": f[:k].copy(), "cv": cv[:k].copy(), "idx": idx[:k].copy()}
+
+    def quality(self, ref=None, hv_point=None, hv_samples: int = 1 << 20, hv_seed: int = 0) -> dict:
+        """gmpea_quality: IGD against the reference points `ref` (n x m) and the
+        Monte Carlo HV below `hv_point`, both computed on the device from the
+        feasible non-dominated rows of population 1 (either may be None)."""
+        igd, hv, cnt = ctypes.c_double(0.0), ctypes.c_double(0.0), ctypes.c_int32(0)
+        r = None if ref is None else np.ascontiguousarray(ref, dtype=np.float32).reshape(-1, self.m)
+        hp = None if hv_point is None else np.ascontiguousarray(hv_point, dtype=np.float32).reshape(self.m)
+        _check(lib().gmpea_quality(self._h, None if r is None else r.ctypes.data,
+                                   0 if r is None else r.shape[0],
+                                   None if hp is None else hp.ctypes.data, int(hv_samples),
+                                   int(hv_seed) & 0xFFFFFFFFFFFFFFFF,
+                                   None if r is None else ctypes.byref(igd),
+                                   None if hp is None else ctypes.byref(hv), ctypes.byref(cnt)))
+        return {"igd": None if r is None else float(igd.value),
+                "hv": None if hp is None else float(hv.value), "front_count": int(cnt.value)}
 
     def profile(self, n_gen: int) -> dict:
         """Mean per-kernel durations (ms) over n_gen generations, HIP events on

@@ -11,7 +11,10 @@ time limit outputs its current set), takes its feasible non-dominated front
 
 Each delivered result records how many generations the solve received, so it
 can be reproduced exactly: an instance advanced alone for that many generations
-computes the same front bit for bit.
+computes the same front bit for bit. A request that carries a reference front
+(and optionally an HV reference point) also gets the front's IGD (Eq. (14))
+and Monte Carlo HV (Eq. (15)) at its deadline, computed on the device before
+the slot is freed.
 """
 from __future__ import annotations
 
@@ -31,6 +34,8 @@ class Request:
     config: dict
     deadline_s: float          # time allowed after arrival
     arrival: float = 0.0       # wall-clock arrival (seconds since the server started)
+    reference: np.ndarray | None = field(default=None, repr=False)  # IGD reference front (k x m)
+    hv_point: np.ndarray | None = field(default=None, repr=False)   # HV reference point (m)
 
 
 @dataclass
@@ -44,6 +49,8 @@ class Result:
     n: int
     front_f: np.ndarray = field(repr=False)
     front_x: np.ndarray = field(repr=False)
+    igd: float | None = None   # at the deadline, on the device (requests with a reference front)
+    hv: float | None = None
 
     @property
     def latency(self):
@@ -57,7 +64,8 @@ class Result:
 class Server:
     """Single-threaded serving loop on one GPU (one pool, one stream)."""
 
-    def __init__(self, budget_bytes: int, clock=time.perf_counter, keep_fronts: bool = True):
+    def __init__(self, budget_bytes: int, clock=time.perf_counter, keep_fronts: bool = True,
+                 hv_samples: int = 1 << 18):
         self.pool = Pool(budget_bytes)
         self.clock = clock
         self.t0 = None
@@ -67,6 +75,7 @@ class Server:
         self.offspring = 0     # offspring evaluated and selected so far
         self.steps = 0
         self.keep_fronts = keep_fronts
+        self.hv_samples = hv_samples
         self.host_s = {"admit": 0.0, "step": 0.0, "harvest": 0.0}  # wall time per activity
 
     def now(self) -> float:
@@ -98,10 +107,14 @@ class Server:
                 fr = inst.front()
                 gens = int(inst.read("GEN")[0])
                 delivered = self.now()
+                q = {"igd": None, "hv": None}
+                if req.reference is not None or req.hv_point is not None:
+                    q = inst.quality(req.reference, req.hv_point, hv_samples=self.hv_samples)
                 self.results.append(Result(req.rid, req.arrival, admitted, delivered,
                                            req.arrival + req.deadline_s, gens, n,
                                            fr["f"] if self.keep_fronts else fr["f"][:0],
-                                           fr["x"] if self.keep_fronts else fr["x"][:0]))
+                                           fr["x"] if self.keep_fronts else fr["x"][:0],
+                                           q["igd"], q["hv"]))
                 self.pool.release(slot)
                 del self.active[slot]
 
@@ -158,4 +171,14 @@ def summarize(results, wall_s: float, offspring: int, host_s: dict | None = None
             "mean_generations": float(np.mean([r.generations for r in results])) if results else 0,
             "offspring_per_s": offspring / wall_s if wall_s > 0 else None,
             "wall_s": wall_s,
-            "host_s": dict(host_s) if host_s else None}
+            "host_s": dict(host_s) if host_s else None,
+            "igd_at_deadline": _stats([r.igd for r in results if r.igd is not None]),
+            "hv_at_deadline": _stats([r.hv for r in results if r.hv is not None])}
+
+
+def _stats(v):
+    if not v:
+        return None
+    a = np.asarray(v, dtype=np.float64)
+    return {"count": int(a.size), "median": float(np.median(a)), "mean": float(np.mean(a)),
+            "p90": float(np.percentile(a, 90))}

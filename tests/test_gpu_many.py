@@ -103,3 +103,43 @@ def test_many_front_and_checkpoint(G):
         assert np.array_equal(got["F"][p], ref["F"][p])
         assert np.array_equal(got["CV"][p], ref["CV"][p])
     assert np.array_equal(got["z"], ref["z"])
+
+
+def test_quality_on_device(G):
+    """gmpea_quality against the oracle's metrics on the device's own front:
+    IGD (FP32 distances, FP64 sum) within 1e-5 relative; the Monte Carlo HV
+    equal to the oracle's estimate from the same samples within 2e-3 relative
+    (FP32 against FP64 sample coordinates can flip a boundary sample), and
+    within five standard errors of the exact HV for m = 3."""
+    from oracle import metrics
+    for which, steps in (("medium", 60), ("many5", 40), ("many8", 40)):
+        prob, cfg, _ = ci.WORKLOADS[which](2)
+        _log("quality: %s" % which)
+        gp = G.Gmpea(prob, cfg)
+        try:
+            gp.step(steps)
+            F = gp.front()["f"].astype(np.float64)
+            m = prob["m"]
+            if m == 3:
+                ref = metrics.reference_front(prob, density=60)
+            else:
+                W, _ = core.reference_set(m, 6 if m == 5 else 3, 0 if m == 5 else 2)
+                ref = W / np.linalg.norm(W, axis=1, keepdims=True)
+            r = (1.1 * np.max(F, axis=0)).astype(np.float32)
+            S = 1 << 20
+            q = gp.quality(ref, r, hv_samples=S, hv_seed=5)
+            assert q["front_count"] == F.shape[0] > 0
+            want = metrics.igd(ref.astype(np.float32).astype(np.float64), F)
+            assert abs(q["igd"] - want) <= 1e-5 * want, (which, q["igd"], want)
+            mc = metrics.hv_mc(F, r.astype(np.float64), S, seed=5)
+            assert abs(q["hv"] - mc) <= 2e-3 * mc, (which, q["hv"], mc)
+            if m == 3:
+                exact = metrics.hv(F, r.astype(np.float64))
+                vol = float(np.prod(r.astype(np.float64) - F.min(0)))
+                p = exact / vol
+                assert abs(q["hv"] - exact) <= 5 * vol * np.sqrt(p * (1 - p) / S)
+            # reproducible: the same call gives the same numbers
+            q2 = gp.quality(ref, r, hv_samples=S, hv_seed=5)
+            assert q2 == q
+        finally:
+            gp.close()

@@ -83,11 +83,20 @@ def test_igd_at_deadline_sample(G):
     """Quality of the fronts the server delivers at their deadlines: IGD (Eq. (14))
     against each problem's reference front, for a sample of served requests
     (printed); every request that ran at least 20 generations delivers a
-    non-empty front of finite IGD."""
+    non-empty front of finite IGD. The server measures IGD and the Monte Carlo
+    HV on the device at the deadline; both must match the oracle's metrics on
+    the delivered front (IGD within 1e-5 relative, HV within 2e-3 of the
+    oracle's estimate from the same samples)."""
     from oracle import metrics
     from paper_2509_19821_amd.serve import Server
     reqs = _requests(16, seed=9, d_lo=0.05, d_hi=0.4)
-    srv = Server(4 << 30)
+    refs = {}
+    for q in reqs[:8]:
+        ref = metrics.reference_front(q.problem, density=60).astype(np.float32)
+        refs[q.rid] = ref
+        q.reference = ref
+        q.hv_point = (1.1 * ref.max(0)).astype(np.float32)
+    srv = Server(4 << 30, hv_samples=1 << 18)
     try:
         res = srv.run(reqs)
     finally:
@@ -95,9 +104,16 @@ def test_igd_at_deadline_sample(G):
     rows = []
     for r in sorted(res, key=lambda x: x.rid)[:8]:
         q = reqs[r.rid]
-        ref = metrics.reference_front(q.problem, density=60)
-        v = metrics.igd(ref, r.front_f.astype(np.float64)) if len(r.front_f) else float("inf")
+        ref = refs[r.rid].astype(np.float64)
+        F = r.front_f.astype(np.float64)
+        v = metrics.igd(ref, F) if len(F) else float("inf")
         rows.append((r.rid, r.n, r.generations, v))
-        print("request %d: N=%d, %d generations by its deadline, IGD %.5f" % (r.rid, r.n, r.generations, v),
-              flush=True)
+        print("request %d: N=%d, %d generations by its deadline, IGD %.5f (device %.5f), HV device %.5f"
+              % (r.rid, r.n, r.generations, v, r.igd, r.hv), flush=True)
+        if len(F):
+            assert abs(r.igd - v) <= 1e-5 * v, (r.rid, r.igd, v)
+            mc = metrics.hv_mc(F, q.hv_point.astype(np.float64), 1 << 18, seed=0)
+            assert abs(r.hv - mc) <= 2e-3 * mc + 1e-12, (r.rid, r.hv, mc)
+        else:
+            assert r.igd == float("inf") and r.hv == 0.0
     assert all(np.isfinite(v) for (_, _, gens, v) in rows if gens >= 20)

@@ -85,3 +85,36 @@ def test_reference_front_sphere_problem():
     assert ref.shape[0] > 200
     assert np.all(np.linalg.norm(ref, axis=1) >= 1 - 1e-9)
     assert np.all(ref.sum(1) >= prob["sum_lower"] - 1e-9)
+
+
+@pytest.mark.parametrize("m,n", [(2, 30), (3, 40)])
+def test_hv_monte_carlo_against_exact(m, n):
+    """The Monte Carlo HV (the library's sampling rule) agrees with the exact
+    sweep within five standard errors."""
+    rng = np.random.default_rng(40 + m)
+    P = rng.dirichlet(np.ones(m), size=n)
+    r = np.full(m, 1.1)
+    S = 1 << 16
+    est = metrics.hv_mc(P, r, S, seed=7)
+    exact = metrics.hv(P, r)
+    vol = float(np.prod(r - P.min(0)))
+    p = exact / vol
+    assert abs(est - exact) <= 5 * vol * np.sqrt(p * (1 - p) / S)
+
+
+@pytest.mark.parametrize("m", [5, 8])
+def test_hv_monte_carlo_many_objectives(m):
+    """m > 3: against inclusion-exclusion on tiny fronts, within five standard
+    errors; a single point gives exactly the box (every sample is covered)."""
+    rng = np.random.default_rng(50 + m)
+    r = np.full(m, 1.2)
+    P = rng.uniform(0.2, 0.9, (5, m))
+    S = 1 << 15
+    est = metrics.hv_mc(P, r, S, seed=3)
+    exact = metrics.hv_inclusion_exclusion(P, r)
+    vol = float(np.prod(r - P.min(0)))
+    p = exact / vol
+    assert abs(est - exact) <= 5 * vol * np.sqrt(p * (1 - p) / S)
+    one = P[:1]
+    assert metrics.hv_mc(one, r, 1000, seed=1) == pytest.approx(float(np.prod(r - one[0])), rel=1e-12)
+    assert metrics.hv_mc(np.full((1, m), 2.0), r, 100) == 0.0
