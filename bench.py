@@ -233,6 +233,58 @@ def sweep(g, ci, sizes=(100, 1000, 5000, 10000, 100000, 1000000), gens=50, cpu_g
         print(json.dumps(row), flush=True)
 
 
+def many(g, ci, gens=50, cpu_gens=3):
+    """Many objectives (m = 5 and 8) on the many-objective throughput shape
+    (d = 100, two layers of about 1e5 reference vectors, T = 32): GPU time per
+    generation (graph replay, inputs resident), per-kernel times and k_vary's
+    algorithmic bandwidth; then the GPU and the CPU oracle on a layered set of
+    about 2,000 vectors (the oracle's brute-force tables make 1e5 too slow
+    for a bounded run). One JSON object per row on stdout."""
+    from oracle import core
+    cores = core.set_threads(0)
+    for m in (5, 8):
+        prob, cfg, _ = ci.workload_many_large(0, m)
+        t0 = time.perf_counter()
+        gp = g.Gmpea(prob, cfg)
+        init_s = time.perf_counter() - t0
+        gp.step(5)
+        gp.step(0)
+        gp.sync()
+        t0 = time.perf_counter()
+        gp.step(gens)
+        gp.sync()
+        us = (time.perf_counter() - t0) / gens * 1e6
+        prof = gp.profile(10)
+        n, d, rq = gp.n, prob["d"], (m + 4) // 4
+        vary_bytes = 2 * n * (4 * 2 * d + 16 * rq + 8)
+        print(json.dumps({"m": m, "n": n, "d": d, "layers": [cfg["h_outer"], cfg["h_inner"]],
+                          "init_s": round(init_s, 2), "gpu_us_per_gen": round(us, 2),
+                          "gpu_offspring_per_s": round(2 * n / (us * 1e-6), 1),
+                          "per_kernel_ms": {k: round(v, 5) for k, v in prof.items()},
+                          "vary_gbs": round(vary_bytes / (prof["vary"] * 1e-3) / 1e9, 1)}), flush=True)
+        gp.close()
+        small = dict(cfg, h_outer={5: 10, 8: 6}[m], h_inner={5: 6, 8: 4}[m])
+        gp = g.Gmpea(prob, small)
+        gp.step(5)
+        gp.step(0)
+        gp.sync()
+        t0 = time.perf_counter()
+        gp.step(gens)
+        gp.sync()
+        us = (time.perf_counter() - t0) / gens * 1e6
+        n = gp.n
+        gp.close()
+        o = core.Oracle(prob, small)
+        o.step()
+        t0 = time.perf_counter()
+        for _ in range(cpu_gens):
+            o.step()
+        cpu_us = (time.perf_counter() - t0) / cpu_gens * 1e6
+        print(json.dumps({"m": m, "n": n, "d": d, "layers": [small["h_outer"], small["h_inner"]],
+                          "gpu_us_per_gen": round(us, 2), "cpu_us_per_gen": round(cpu_us, 1),
+                          "cpu_cores": int(cores), "gpu_over_cpu": round(cpu_us / us, 1)}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -245,6 +297,9 @@ def main():
     ap.add_argument("--serve-window", type=float, default=5.0)
     ap.add_argument("--sweep", action="store_true",
                     help="print generation time against population size (GPU and CPU oracle) "
+                         "instead of the benchmark line")
+    ap.add_argument("--many", action="store_true",
+                    help="print many-objective (m = 5, 8) generation times (GPU and CPU oracle) "
                          "instead of the benchmark line")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -259,6 +314,9 @@ def main():
 
     if args.sweep:
         sweep(g, ci)
+        return
+    if args.many:
+        many(g, ci)
         return
 
     prob, cfg, K_total = ci.workload_large(0)

@@ -564,9 +564,16 @@ gmpea_status gmpea_init(const gmpea_problem *P, const gmpea_config *C, const gmp
       }
     }
     e = hipMemcpyAsync(st.W, Wf.data(), Wf.size() * sizeof(float), hipMemcpyHostToDevice, h->stream);
+    // one search for the larger neighbourhood: the smaller one is its prefix,
+    // since both lists are in (distance, index) order
+    const int32_t tmax = std::max(t1, t2);
+    refset_neighbours(K, m, H, H2, tmax, Bh);
+    std::vector<int32_t> Bp;
     for (int p = 0; p < 2 && e == hipSuccess; ++p) {
-      refset_neighbours(K, m, H, H2, ts[p], Bh);
-      e = hipMemcpyAsync(const_cast<int32_t *>(st.B[p]), Bh.data(), Bh.size() * sizeof(int32_t),
+      Bp.resize(static_cast<size_t>(N) * ts[p]);
+      for (int32_t i = 0; i < N; ++i)
+        std::copy_n(&Bh[static_cast<size_t>(i) * tmax], ts[p], &Bp[static_cast<size_t>(i) * ts[p]]);
+      e = hipMemcpyAsync(const_cast<int32_t *>(st.B[p]), Bp.data(), Bp.size() * sizeof(int32_t),
                          hipMemcpyHostToDevice, h->stream);
       if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     }
