@@ -1191,7 +1191,7 @@ int32_t phase_blocks(const DevState &st, int phase) {
   if (phase == 0) return vary_blocks_of(st.n, vary_lanes_of(st.stride));
   if (phase == 1) return st.nblk;
   if (phase == 2) return st.sel_blocks0 + st.sel_blocks1;
-  return rows_blocks_of(st.n, st.stride);
+  return rows_blocks_of(st.n, st.stride, kRowsIterBatch);
 }
 
 // Work list of one phase. Schedule 0 keeps each instance's consecutive blocks

@@ -551,7 +551,8 @@ __global__ __launch_bounds__(kBlock) void k_op1(DevState st) {
 // the slot they overwrite.
 // A group of lps lanes decides one slot (lps = t_p / 4 rounded up to a power of
 // two, at most 64: about four reverse-list entries per lane). Lane g takes
-// entries g, g + lps, ... of the slot's padded list head, four at a time with
+// four entries of the slot's padded list head at a time (entries 4g .. 4g + 3
+// in one 16-byte load when t_p is a multiple of 4, else g, g + lps, ...) with
 // independent loads (index, then candidate F/CV), then its share of the tail
 // (lists longer than t_p), and keeps its lexicographic minimum of (CV, g,
 // index). No load waits on another beyond index -> candidate: the head needs no
@@ -638,19 +639,33 @@ __device__ __forceinline__ void select_body(const DevState &st, int L) {
     const int32_t *head = st.rhead[p] + static_cast<size_t>(j) * t;
     const int32_t ta = st.rtoff[p][j], tb = st.rtoff[p][j + 1];
     const float4 *cand = st.FCN[p];
-    for (int q0 = g; q0 < t; q0 += 4 * lps) {  // one pass unless t > 4 lps = 256
-      int ii[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int q = q0 + u * lps;
-        ii[u] = q < t ? head[q] : -1;
-      }
+    auto take4 = [&](const int (&ii)[4]) {  // four independent candidate loads, then the keys
       Rec<M> cc[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) cc[u] = ii[u] >= 0 ? rec_load<M>(cand, ii[u]) : rec_zero<M>();
 #pragma unroll
       for (int u = 0; u < 4; ++u)
         if (ii[u] >= 0) consider(ii[u], cc[u]);
+    };
+    if ((t & 3) == 0) {
+      // lane g takes entries 4g .. 4g + 3 (one 16-byte load; head rows are
+      // 16-byte aligned when t is a multiple of 4); the minimum does not
+      // depend on how the entries are dealt to lanes
+      for (int q0 = 4 * g; q0 < t; q0 += 4 * lps) {
+        const int4 v = *reinterpret_cast<const int4 *>(head + q0);
+        const int ii[4] = {v.x, v.y, v.z, v.w};
+        take4(ii);
+      }
+    } else {
+      for (int q0 = g; q0 < t; q0 += 4 * lps) {  // one pass unless t > 4 lps = 256
+        int ii[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int q = q0 + u * lps;
+          ii[u] = q < t ? head[q] : -1;
+        }
+        take4(ii);
+      }
     }
     for (int q = ta + g; q < tb; q += lps) {
       const int32_t i = st.rtail[p][q];

@@ -102,10 +102,15 @@ hipError_t launch_init(const DevState &st, hipStream_t s);
 // A generation is kPhases launches: 0 variation + evaluation + ideal point,
 // 1 offspring cooperation, 2 neighbour replacement decisions, 3 row copies.
 constexpr int kPhases = 4;
-// k_rows blocks of one instance (float4 elements of both populations' rows).
-__host__ __device__ inline int rows_blocks_of(int n, int stride) {
+// Row copies: a block copies `iters` runs of kBlock float4 elements of both
+// populations' rows: one run in the plain launch, kRowsIterBatch in a batched
+// one, where each work item must also cover fetching its item and instance
+// state (the copies do not depend on how they are split).
+constexpr int kRowsIterBatch = 4;
+__host__ __device__ inline int rows_blocks_of(int n, int stride, int iters = 1) {
   const long long e = 2LL * n * (stride >> 2);
-  return static_cast<int>((e + kBlock - 1) / kBlock);
+  const long long per = static_cast<long long>(kBlock) * iters;
+  return static_cast<int>((e + per - 1) / per);
 }
 hipError_t launch_phase(const DevState &st, int phase, hipStream_t s);
 hipError_t launch_generation(const DevState &st, hipStream_t s);

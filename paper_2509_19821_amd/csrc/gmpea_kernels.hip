@@ -256,7 +256,10 @@ __global__ __launch_bounds__(kBlock) void k_rows_batch(const DevState *__restric
                                                       const int2 *__restrict__ work) {
   const int2 wi = work[blockIdx.x];
   if (wi.x < 0) return;
-  rows_body(S[wi.x], static_cast<int64_t>(wi.y) * kBlock + threadIdx.x);
+  const DevState &st = S[wi.x];
+  const int64_t e0 = static_cast<int64_t>(wi.y) * kRowsIterBatch * kBlock + threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < kRowsIterBatch; ++k) rows_body(st, e0 + static_cast<int64_t>(k) * kBlock);
 }
 
 __global__ __launch_bounds__(kBlock) void k_gather(DevState st, int pop, const int32_t *idx,
