@@ -747,12 +747,23 @@ __device__ __forceinline__ void vary_any_lanes(const DevState &st, int L) {
 
 // ----------------------------------------------------------------------------
 // Front: feasible rows of population `pop` that no feasible row dominates
-// (Eq. (5)); candidates staged through LDS tiles.
+// (Eq. (5)). k_front_init sets keep[i] = (row i is feasible); k_front then
+// clears keep[i] when some feasible row dominates row i. Its grid is (row tile,
+// column chunk): each block checks its kBlock rows against one chunk of
+// candidate rows staged through LDS tiles, so a population of a few thousand
+// rows still spreads over the whole chip; several blocks may clear the same
+// flag, all with the same value.
 // ----------------------------------------------------------------------------
 template <int M>
-__global__ __launch_bounds__(kBlock) void k_front(DevState st, int pop, uint8_t *keep) {
-  constexpr int Q = Rec<M>::Q, kCv = Rec<M>::kCv;
-  __shared__ float4 tile[kBlock * Q];
+__global__ __launch_bounds__(kBlock) void k_front_init(DevState st, int pop, uint8_t *keep) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i < st.n) keep[i] = rec_load<M>(st.FC[pop], i).v[Rec<M>::kCv] == 0.0f ? 1 : 0;
+}
+
+template <int M>
+__global__ __launch_bounds__(kBlock) void k_front(DevState st, int pop, uint8_t *keep, int chunk) {
+  constexpr int kCv = Rec<M>::kCv;
+  __shared__ float4 tile[kBlock * Rec<M>::Q];
   const int i = blockIdx.x * kBlock + threadIdx.x;
   Rec<M> me = rec_zero<M>();
   bool alive = false;
@@ -760,15 +771,16 @@ __global__ __launch_bounds__(kBlock) void k_front(DevState st, int pop, uint8_t 
     me = rec_load<M>(st.FC[pop], i);
     alive = (me.v[kCv] == 0.0f);
   }
-  for (int t0 = 0; t0 < st.n; t0 += kBlock) {
+  const int c0 = blockIdx.y * chunk, c1 = min(st.n, c0 + chunk);
+  for (int t0 = c0; t0 < c1; t0 += kBlock) {
     if (!__syncthreads_or(alive)) break;
     const int jj = t0 + threadIdx.x;
     Rec<M> r = rec_zero<M>();
-    if (jj < st.n) r = rec_load<M>(st.FC[pop], jj);
+    if (jj < c1) r = rec_load<M>(st.FC[pop], jj);
     else r.v[kCv] = 1.0f;  // never dominates
     rec_store<M>(tile, threadIdx.x, r);
     __syncthreads();
-    const int lim = min(kBlock, st.n - t0);
+    const int lim = min(kBlock, c1 - t0);
     if (alive) {
       for (int q = 0; q < lim; ++q) {
         const Rec<M> o = rec_load<M>(tile, q);
@@ -781,13 +793,22 @@ __global__ __launch_bounds__(kBlock) void k_front(DevState st, int pop, uint8_t 
         }
         if (le && lt) {
           alive = false;
+          keep[i] = 0;
           break;
         }
       }
     }
     __syncthreads();
   }
-  if (i < st.n) keep[i] = alive ? 1 : 0;
+}
+
+// Column chunks of k_front: enough blocks to fill the chip, chunks of whole tiles.
+__host__ __device__ inline int front_chunk(int n) {
+  const int tiles = (n + kBlock - 1) / kBlock;
+  const int want = (2048 + tiles - 1) / tiles;  // about 2048 blocks in all
+  const int chunks = want < tiles ? want : tiles;
+  const int per = (tiles + chunks - 1) / chunks;
+  return per * kBlock;
 }
 
 }  // namespace gmpea

@@ -502,7 +502,13 @@ hipError_t launch_generation(const DevState &st, hipStream_t s) {
 
 hipError_t launch_front_flags(const DevState &st, int pop, uint8_t *keep, hipStream_t s) {
   if (st.m > 3) return launch_front_flags_wide(st, pop, keep, s);
-  GMPEA_DISPATCH_M(k_front, st.nblk, s, st, pop, keep);
+  const int chunk = front_chunk(st.n);
+  const dim3 grid(st.nblk, (st.n + chunk - 1) / chunk);
+  GMPEA_DISPATCH_M(k_front_init, st.nblk, s, st, pop, keep);
+  if (st.m == 2)
+    hipLaunchKernelGGL((k_front<2>), grid, dim3(kBlock), 0, s, st, pop, keep, chunk);
+  else
+    hipLaunchKernelGGL((k_front<3>), grid, dim3(kBlock), 0, s, st, pop, keep, chunk);
   return hipGetLastError();
 }
 

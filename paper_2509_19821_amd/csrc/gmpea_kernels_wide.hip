@@ -133,7 +133,10 @@ hipError_t launch_batch_phase_wide(const DevState *states, const int2 *work, int
 hipError_t launch_front_flags_wide(const DevState &st, int pop, uint8_t *keep, hipStream_t s) {
   with_wide_m(st.m, [&](auto mc) {
     constexpr int M = decltype(mc)::value;
-    hipLaunchKernelGGL((k_front<M>), dim3(st.nblk), dim3(kBlock), 0, s, st, pop, keep);
+    const int chunk = front_chunk(st.n);
+    hipLaunchKernelGGL((k_front_init<M>), dim3(st.nblk), dim3(kBlock), 0, s, st, pop, keep);
+    hipLaunchKernelGGL((k_front<M>), dim3(st.nblk, (st.n + chunk - 1) / chunk), dim3(kBlock), 0, s, st,
+                       pop, keep, chunk);
   });
   return hipGetLastError();
 }

@@ -279,16 +279,18 @@ class Gmpea:
         _check(lib().gmpea_run(self._h, int(max_gen), float(time_limit_s), ctypes.byref(done)))
         return int(done.value)
 
-    def front(self, what: int = FRONT_FEASIBLE_ND) -> dict:
+    def front(self, what: int = FRONT_FEASIBLE_ND, with_x: bool = True) -> dict:
+        """Rows of a front selector; with_x=False leaves the decision vectors
+        on the device (the returned "x" is empty)."""
         # one call with room for the whole population (the front is a subset)
         cnt = ctypes.c_int32(0)
         n = self.n
-        x = np.empty((n, self.d), dtype=np.float32)
+        x = np.empty((n if with_x else 0, self.d), dtype=np.float32)
         f = np.empty((n, self.m), dtype=np.float32)
         cv = np.empty(n, dtype=np.float32)
         idx = np.empty(n, dtype=np.int32)
-        _check(lib().gmpea_front(self._h, int(what), n, x.ctypes.data, f.ctypes.data,
-                                 cv.ctypes.data, idx.ctypes.data, ctypes.byref(cnt)))
+        _check(lib().gmpea_front(self._h, int(what), n, x.ctypes.data if with_x else None,
+                                 f.ctypes.data, cv.ctypes.data, idx.ctypes.data, ctypes.byref(cnt)))
         k = int(cnt.value)
         return {"x": x[:k].copy(), "f": f[:k].copy(), "cv": cv[:k].copy(), "idx": idx[:k].copy()}
 

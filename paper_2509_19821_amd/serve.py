@@ -104,7 +104,7 @@ class Server:
             req, admitted, n = self.active[slot]
             if force or t >= req.arrival + req.deadline_s:
                 inst = self.pool.instance(slot)
-                fr = inst.front()
+                fr = inst.front(with_x=self.keep_fronts)
                 gens = int(inst.read("GEN")[0])
                 delivered = self.now()
                 q = {"igd": None, "hv": None}
@@ -113,7 +113,7 @@ class Server:
                 self.results.append(Result(req.rid, req.arrival, admitted, delivered,
                                            req.arrival + req.deadline_s, gens, n,
                                            fr["f"] if self.keep_fronts else fr["f"][:0],
-                                           fr["x"] if self.keep_fronts else fr["x"][:0],
+                                           fr["x"],
                                            q["igd"], q["hv"]))
                 self.pool.release(slot)
                 del self.active[slot]

@@ -378,6 +378,28 @@ def test_front_matches_bruteforce(G):
         gp.close()
 
 
+@pytest.mark.parametrize("m,n_req,d", [(3, 5100, 12), (2, 20000, 8)])
+def test_front_chunked_grid(G, m, n_req, d):
+    """The front kernel's (row tile, column chunk) grid at sizes with many
+    chunks and a ragged last tile, against the oracle's filter on the device's
+    values."""
+    import paper_2509_19821_amd as g
+    fam = ci.FAMILY_SPHERE if m == 3 else ci.FAMILY_CURVE
+    prob = ci.make_problem(fam, m, d, 3, m == 3, False, 31)
+    gp = g.Gmpea(prob, ci.method_config(n_req, 10, 31))
+    try:
+        gp.step(30)
+        fr = gp.front(with_x=False)
+        F = gp.read("F", 0).astype(np.float64)
+        CV = gp.read("CV", 0).astype(np.float64)
+        keep = core.front_mask(F, CV)
+        assert gp.n % 256 != 0
+        assert np.array_equal(fr["idx"], np.nonzero(keep)[0])
+        assert fr["x"].shape == (0, d)
+    finally:
+        gp.close()
+
+
 def test_graph_replay_equals_eager(G):
     import paper_2509_19821_amd as g
     prob, cfg, _ = ci.workload_medium(3)
