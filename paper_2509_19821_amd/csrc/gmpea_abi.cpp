@@ -564,18 +564,37 @@ gmpea_status gmpea_init(const gmpea_problem *P, const gmpea_config *C, const gmp
       }
     }
     e = hipMemcpyAsync(st.W, Wf.data(), Wf.size() * sizeof(float), hipMemcpyHostToDevice, h->stream);
-    // one search for the larger neighbourhood: the smaller one is its prefix,
-    // since both lists are in (distance, index) order
     const int32_t tmax = std::max(t1, t2);
-    refset_neighbours(K, m, H, H2, tmax, Bh);
-    std::vector<int32_t> Bp;
-    for (int p = 0; p < 2 && e == hipSuccess; ++p) {
-      Bp.resize(static_cast<size_t>(N) * ts[p]);
-      for (int32_t i = 0; i < N; ++i)
-        std::copy_n(&Bh[static_cast<size_t>(i) * tmax], ts[p], &Bp[static_cast<size_t>(i) * ts[p]]);
-      e = hipMemcpyAsync(const_cast<int32_t *>(st.B[p]), Bp.data(), Bp.size() * sizeof(int32_t),
-                         hipMemcpyHostToDevice, h->stream);
+    if (tmax <= kKnnMaxTHost && e == hipSuccess) {
+      // exact search on the device (one block per row); every coordinate lies
+      // in [0, S] with S = 2 m H1 H2 (H1 for one layer) and the rows sum to S,
+      // so no squared distance exceeds 2 S^2
+      const uint64_t S = H2 > 0 ? uint64_t(2) * m * H * H2 : uint64_t(H);
+      int32_t *dK = static_cast<int32_t *>(dev_alloc(h, K.size() * sizeof(int32_t)));
+      if (!dK) {
+        release_all(h);
+        delete h;
+        return fail(GMPEA_ENOMEM, "gmpea_init: device allocation failed");
+      }
+      e = hipMemcpyAsync(dK, K.data(), K.size() * sizeof(int32_t), hipMemcpyHostToDevice, h->stream);
+      if (e == hipSuccess)
+        e = launch_knn(dK, N, m, 2 * S * S, t1, t2, const_cast<int32_t *>(st.B[0]),
+                       const_cast<int32_t *>(st.B[1]), h->stream);
       if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+      dev_free(h, dK);
+    } else {
+      // one host search for the larger neighbourhood: the smaller one is its
+      // prefix, since both lists are in (distance, index) order
+      refset_neighbours(K, m, H, H2, tmax, Bh);
+      std::vector<int32_t> Bp;
+      for (int p = 0; p < 2 && e == hipSuccess; ++p) {
+        Bp.resize(static_cast<size_t>(N) * ts[p]);
+        for (int32_t i = 0; i < N; ++i)
+          std::copy_n(&Bh[static_cast<size_t>(i) * tmax], ts[p], &Bp[static_cast<size_t>(i) * ts[p]]);
+        e = hipMemcpyAsync(const_cast<int32_t *>(st.B[p]), Bp.data(), Bp.size() * sizeof(int32_t),
+                           hipMemcpyHostToDevice, h->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+      }
     }
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);  // Wf is read before it goes
   }

@@ -129,6 +129,13 @@ hipError_t launch_front_flags(const DevState &st, int pop, uint8_t *keep, hipStr
 hipError_t launch_gather(const DevState &st, int pop, const int32_t *idx, int32_t count,
                          float *x, float4 *fc, hipStream_t s);
 hipError_t launch_copy(const void *src, void *dst, int64_t n16, hipStream_t s);
+// Neighbourhoods of n rows of integer coordinates K (n x m, device): B1 (n x t1)
+// and B2 (n x t2) receive each row's nearest rows by exact squared distance,
+// ties by index. max_dist bounds every squared distance (it sets the digits of
+// the radix select). max(t1, t2) must not exceed kKnnMaxTHost.
+constexpr int kKnnMaxTHost = 256;
+hipError_t launch_knn(const int32_t *K, int32_t n, int32_t m, uint64_t max_dist, int32_t t1, int32_t t2,
+                      int32_t *B1, int32_t *B2, hipStream_t s);
 // Front quality (Eqs. (14)-(15)) of `count` front records (rq float4 each).
 // IGD: partial[b] receives the sum over block b's reference points of the
 // distance to the nearest front point (n_ref x m reference rows, row-major).

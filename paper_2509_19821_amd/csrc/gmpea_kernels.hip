@@ -274,6 +274,117 @@ __global__ __launch_bounds__(kBlock) void k_gather(DevState st, int pop, const i
 }
 
 // ----------------------------------------------------------------------------
+// Neighbourhoods of an arbitrary reference set given as integer coordinates
+// (layered sets, m > 3): row i's t nearest rows by exact squared distance, ties
+// by index, one block per row. A radix select over the distance's digits (8
+// bits at a time from the top, each pass a 256-bin LDS histogram of the
+// distances that share the digits found so far) finds the t-th smallest
+// distance D and how many rows at distance D are needed; the rows below D are
+// gathered, the needed rows at D are taken in index order (contiguous index
+// ranges per thread and a scan of their counts), and the t rows are placed by
+// their rank in (distance, index) order. B1 receives the first t1 of them and
+// B2 the first t2 (t = max(t1, t2) <= kKnnMaxT).
+// ----------------------------------------------------------------------------
+constexpr int kKnnMaxT = 256;
+
+__global__ __launch_bounds__(kBlock) void k_knn(const int32_t *__restrict__ K, int32_t n, int32_t m,
+                                               int32_t bits, int32_t t1, int32_t t2,
+                                               int32_t *__restrict__ B1, int32_t *__restrict__ B2) {
+  __shared__ int32_t ki[kMaxM];
+  __shared__ uint32_t hist[256];
+  __shared__ uint64_t s_prefix;
+  __shared__ int32_t s_need, s_nsel;
+  __shared__ uint64_t sel_d[kKnnMaxT];
+  __shared__ int32_t sel_j[kKnnMaxT];
+  __shared__ int32_t scan[kBlock];
+  const int i = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int t = max(t1, t2);
+  if (tid < m) ki[tid] = K[static_cast<size_t>(i) * m + tid];
+  if (tid == 0) {
+    s_prefix = 0;
+    s_need = t;
+    s_nsel = 0;
+  }
+  __syncthreads();
+  auto dist = [&](int j) -> uint64_t {
+    const int32_t *kj = K + static_cast<size_t>(j) * m;
+    int64_t d = 0;
+    for (int a = 0; a < m; ++a) {
+      const int64_t df = static_cast<int64_t>(kj[a]) - ki[a];
+      d += df * df;
+    }
+    return static_cast<uint64_t>(d);
+  };
+  // digits [lo, hi) from the top bit of the largest distance down: the first
+  // pass already spreads the distances over the 256 bins
+  for (int hi = bits; hi > 0; hi -= 8) {
+    const int lo = hi > 8 ? hi - 8 : 0;
+    hist[tid] = 0;
+    __syncthreads();
+    const uint64_t above = hi >= 64 ? 0ull : (~0ull << hi);
+    const uint64_t pre = s_prefix;
+    const uint64_t dmask = (1ull << (hi - lo)) - 1ull;
+    for (int j = tid; j < n; j += kBlock) {
+      const uint64_t d = dist(j);
+      if ((d & above) == pre) atomicAdd(&hist[(d >> lo) & dmask], 1u);
+    }
+    __syncthreads();
+    if (tid == 0) {
+      int32_t cum = 0;
+      for (int b = 0; b < 256; ++b) {
+        const int32_t h = static_cast<int32_t>(hist[b]);
+        if (cum + h >= s_need) {
+          s_prefix = pre | (static_cast<uint64_t>(b) << lo);
+          s_need -= cum;
+          break;
+        }
+        cum += h;
+      }
+    }
+    __syncthreads();
+  }
+  const uint64_t D = s_prefix;
+  const int32_t need = s_need;  // rows at distance D to take; t - need lie below D
+  for (int j = tid; j < n; j += kBlock) {
+    const uint64_t d = dist(j);
+    if (d < D) {
+      const int k = atomicAdd(&s_nsel, 1);
+      sel_d[k] = d;
+      sel_j[k] = j;
+    }
+  }
+  const int per = (n + kBlock - 1) / kBlock;
+  const int lo = min(n, tid * per), hi = min(n, lo + per);
+  int32_t cnt = 0;
+  for (int j = lo; j < hi; ++j) cnt += dist(j) == D;
+  scan[tid] = cnt;
+  __syncthreads();
+  for (int o = 1; o < kBlock; o <<= 1) {  // inclusive scan of the tie counts
+    const int32_t v = tid >= o ? scan[tid - o] : 0;
+    __syncthreads();
+    scan[tid] += v;
+    __syncthreads();
+  }
+  int32_t rank = scan[tid] - cnt;
+  for (int j = lo; j < hi && rank < need; ++j)
+    if (dist(j) == D) {
+      sel_d[t - need + rank] = D;
+      sel_j[t - need + rank] = j;
+      ++rank;
+    }
+  __syncthreads();
+  if (tid < t) {  // place entry tid by its rank in (distance, index) order
+    const uint64_t d = sel_d[tid];
+    const int32_t j = sel_j[tid];
+    int r = 0;
+    for (int q = 0; q < t; ++q) r += (sel_d[q] < d) || (sel_d[q] == d && sel_j[q] < j);
+    if (r < t1) B1[static_cast<size_t>(i) * t1 + r] = j;
+    if (r < t2) B2[static_cast<size_t>(i) * t2 + r] = j;
+  }
+}
+
+// ----------------------------------------------------------------------------
 // Front quality (Eqs. (14)-(15)), for results delivered at a deadline.
 // The front's objectives are staged through LDS tiles of kBlock points; m and
 // the record width are run-time values (one kernel serves every m).
@@ -524,6 +635,16 @@ hipError_t launch_copy(const void *src, void *dst, int64_t n16, hipStream_t s) {
   const int64_t blocks = std::min<int64_t>((n16 + kBlock - 1) / kBlock, 256 * 16);
   hipLaunchKernelGGL(k_copy, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, s,
                      static_cast<const uint4 *>(src), static_cast<uint4 *>(dst), n16);
+  return hipGetLastError();
+}
+
+hipError_t launch_knn(const int32_t *K, int32_t n, int32_t m, uint64_t max_dist, int32_t t1, int32_t t2,
+                      int32_t *B1, int32_t *B2, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  if (std::max(t1, t2) > kKnnMaxT) return hipErrorInvalidValue;
+  int32_t bits = 1;  // every distance is below 2^bits
+  while (bits < 63 && (max_dist >> bits) != 0) ++bits;
+  hipLaunchKernelGGL(k_knn, dim3(n), dim3(kBlock), 0, s, K, n, m, bits, t1, t2, B1, B2);
   return hipGetLastError();
 }
 

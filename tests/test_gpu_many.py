@@ -143,3 +143,20 @@ def test_quality_on_device(G):
             assert q2 == q
         finally:
             gp.close()
+
+
+@pytest.mark.parametrize("m,h1,h2,T", [(8, 8, 6, 20), (4, 40, 0, 32), (6, 7, 4, 128)])
+def test_device_neighbourhoods_match_host(G, m, h1, h2, T):
+    """The device's exact neighbour search (radix select per row) against the
+    host's brute force at thousands of rows: both neighbourhoods equal, the
+    smaller one the prefix of the larger (t up to 256)."""
+    prob = ci.make_problem(ci.FAMILY_SPHERE, m, m + 5, 1, False, False, 41)
+    cfg = ci.method_config(2, T, 41, h_outer=h1, h_inner=h2)
+    gp = G.Gmpea(prob, cfg, record=False)
+    try:
+        t1, t2 = gp.t
+        _, Bh = G.reference_set(m, h1, h2, max(t1, t2))
+        assert np.array_equal(gp.read("B", 0), Bh[:, :t1])
+        assert np.array_equal(gp.read("B", 1), Bh[:, :t2])
+    finally:
+        gp.close()
