@@ -193,7 +193,7 @@ def serving(g, ci, window_s=5.0, rate=200.0, quality_every=16):
         wall = time.perf_counter() - t0
         out = summarize(res, wall, srv.offspring, srv.host_s)
         out["host_s"] = {k: round(v, 3) for k, v in out["host_s"].items()}
-        out.update({"window_s": window_s, "rate_per_s": rate, "batched_steps": srv.steps})
+        out.update({"window_s": window_s, "rate_per_s": rate, "batched_generations": srv.steps})
     finally:
         srv.close()
     return {k: (round(v, 5) if isinstance(v, float) else v) for k, v in out.items()}

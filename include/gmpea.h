@@ -253,6 +253,11 @@ gmpea_status gmpea_sync(gmpea_t h);
 /* Sizes, generation count, ideal point and counters (synchronises). */
 gmpea_status gmpea_get_info(gmpea_t h, gmpea_info *info);
 
+/* Sizes of an instance (any output may be NULL): N per population, m, d and
+ * the two neighbourhood sizes. Host-side only: no device access and no wait,
+ * so it may be called while generations are in flight. */
+gmpea_status gmpea_shape(gmpea_t h, int32_t *n, int32_t *m, int32_t *d, int32_t *t1, int32_t *t2);
+
 /* Copy a buffer (see GMPEA_BUF_*) to host memory of `count` elements of its
  * host type; count must equal the buffer's element count. Synchronises. */
 gmpea_status gmpea_read(gmpea_t h, int32_t buffer, int32_t pop, void *host, int64_t count);
@@ -332,7 +337,9 @@ gmpea_status gmpea_pool_create(size_t budget_bytes, const gmpea_allocator *alloc
                                void *hip_stream, gmpea_pool_t *out);
 
 /* Initialise an instance inside the pool (as gmpea_init) and return its slot.
- * ENOMEM when its footprint does not fit the remaining budget (nothing is kept). */
+ * The initialisation runs on a stream of the pool's own, so generations already
+ * enqueued keep running; the instance then uses the pool's stream. ENOMEM when
+ * its footprint does not fit the remaining budget (nothing is kept). */
 gmpea_status gmpea_pool_admit(gmpea_pool_t pool, const gmpea_problem *problem,
                               const gmpea_config *config, int32_t *slot);
 

@@ -850,6 +850,17 @@ gmpea_status gmpea_quality(gmpea_t h, const float *ref, int32_t n_ref, const flo
   return GMPEA_OK;
 }
 
+gmpea_status gmpea_shape(gmpea_t h, int32_t *n, int32_t *m, int32_t *d, int32_t *t1, int32_t *t2) {
+  if (!valid(h)) return fail(GMPEA_ESTATE, "gmpea_shape: invalid handle");
+  const DevState &st = h->st;
+  if (n) *n = st.n;
+  if (m) *m = st.m;
+  if (d) *d = st.d;
+  if (t1) *t1 = st.t[0];
+  if (t2) *t2 = st.t[1];
+  return GMPEA_OK;
+}
+
 gmpea_status gmpea_read(gmpea_t h, int32_t buffer, int32_t pop, void *host, int64_t count) {
   if (!valid(h)) return fail(GMPEA_ESTATE, "gmpea_read: invalid handle");
   if (!host) return fail(GMPEA_EINVAL, "gmpea_read: host is NULL");
@@ -1077,6 +1088,7 @@ struct gmpea_pool_s {
   gmpea_allocator hook{};  // arena-backed hook handed to every instance
   hipStream_t stream = nullptr;
   bool own_stream = false;
+  hipStream_t init_stream = nullptr;  // admissions initialise here, beside generations in flight
   size_t budget = 0;
   PoolArena arena;
   std::vector<gmpea_t> slots;  // nullptr = free
@@ -1426,6 +1438,14 @@ gmpea_status gmpea_pool_create(size_t budget_bytes, const gmpea_allocator *A, vo
     q->own_stream = true;
   }
   {
+    hipError_t e = hipStreamCreateWithFlags(&q->init_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      if (q->own_stream) (void)hipStreamDestroy(q->stream);
+      delete q;
+      return hip_fail(e, "gmpea_pool_create: stream");
+    }
+  }
+  {
     std::lock_guard<std::mutex> lk(g_pool_mu);
     g_pools.insert(q);
   }
@@ -1438,10 +1458,15 @@ gmpea_status gmpea_pool_admit(gmpea_pool_t q, const gmpea_problem *P, const gmpe
   if (!pool_valid(q)) return fail(GMPEA_ESTATE, "gmpea_pool_admit: invalid pool");
   if (!slot) return fail(GMPEA_EINVAL, "gmpea_pool_admit: slot is NULL");
   gmpea_t h = nullptr;
-  gmpea_status s = gmpea_init(P, C, &q->hook, q->stream, &h);
+  // initialise on the pool's side stream: the generations enqueued on the pool
+  // stream keep running meanwhile (the new instance's memory is fresh: freed
+  // blocks are recycled only after the pool's work on them has finished), and
+  // gmpea_init returns once its own work is done
+  gmpea_status s = gmpea_init(P, C, &q->hook, q->init_stream, &h);
   if (s == GMPEA_ENOMEM)
     return fail(GMPEA_ENOMEM, "gmpea_pool_admit: the instance does not fit the pool's budget");
   if (s != GMPEA_OK) return s;
+  h->stream = q->stream;  // every later operation runs in order with the pool's generations
   int32_t k = 0;
   while (k < static_cast<int32_t>(q->slots.size()) && q->slots[k]) ++k;
   if (k == static_cast<int32_t>(q->slots.size())) q->slots.push_back(nullptr);
@@ -1562,6 +1587,7 @@ void gmpea_pool_destroy(gmpea_pool_t q) {
     for (int c = 0; c < 2; ++c)
       if (q->d_work[c][ph]) pool_raw_free(q, q->d_work[c][ph]);
   pool_arena_destroy(q);
+  if (q->init_stream) (void)hipStreamDestroy(q->init_stream);
   if (q->own_stream) (void)hipStreamDestroy(q->stream);
   delete q;
 }

@@ -35,7 +35,7 @@ EXPORTS = ["gmpea_init", "gmpea_step", "gmpea_run", "gmpea_front", "gmpea_get_in
            "gmpea_philox", "gmpea_copy", "gmpea_pool_create", "gmpea_pool_admit",
            "gmpea_pool_step", "gmpea_pool_tune", "gmpea_pool_handle", "gmpea_pool_release",
            "gmpea_pool_query", "gmpea_pool_sync", "gmpea_pool_destroy", "gmpea_lattice",
-           "gmpea_reference_set", "gmpea_quality"]
+           "gmpea_reference_set", "gmpea_quality", "gmpea_shape"]
 PHASES = ("vary", "op1", "select", "rows")
 
 
@@ -155,6 +155,7 @@ def lib():
                                     ctypes.POINTER(i32)]
         L.gmpea_reference_set.argtypes = [i32, i32, i32, i32, i32, vp, vp, ctypes.POINTER(i32)]
         L.gmpea_quality.argtypes = [vp, vp, i32, vp, i64, ctypes.c_uint64, vp, vp, vp]
+        L.gmpea_shape.argtypes = [vp] + [ctypes.POINTER(i32)] * 5
         for name in EXPORTS:
             if name not in ("gmpea_destroy", "gmpea_last_error", "gmpea_pool_destroy"):
                 getattr(L, name).restype = ctypes.c_int
@@ -222,9 +223,10 @@ class Gmpea:
         self._describe()
 
     def _describe(self):
-        inf = self.info()
-        self.n, self.m, self.d = inf["n"], inf["m"], inf["d"]
-        self.t = (inf["t1"], inf["t2"])
+        v = [ctypes.c_int32(0) for _ in range(5)]
+        _check(lib().gmpea_shape(self._h, *[ctypes.byref(x) for x in v]))  # no device access
+        self.n, self.m, self.d = v[0].value, v[1].value, v[2].value
+        self.t = (v[3].value, v[4].value)
 
     @classmethod
     def _borrow(cls, handle, keep):

@@ -3,9 +3,10 @@
 Requests (a CMOP, method parameters and a deadline) arrive over time. A request
 is admitted into the pool as soon as its device-memory footprint fits the
 budget; until then it waits in arrival order. Every loop iteration advances all
-resident solves by one batched generation (one launch per phase for all of
-them). When a solve's deadline has passed, the loop stops it at that
-generation boundary, as in the paper's fixed-time protocol (a run reaching its
+resident solves by a few batched generations (one launch per phase for all of
+them, per generation): as many as are expected to fit before the earliest
+deadline among them, at most max_chunk, at least one. When a solve's deadline
+has passed, the loop stops it at that generation boundary, as in the paper's fixed-time protocol (a run reaching its
 time limit outputs its current set), takes its feasible non-dominated front
 (population 1) and frees its slot for waiting requests.
 
@@ -65,7 +66,7 @@ class Server:
     """Single-threaded serving loop on one GPU (one pool, one stream)."""
 
     def __init__(self, budget_bytes: int, clock=time.perf_counter, keep_fronts: bool = True,
-                 hv_samples: int = 1 << 18):
+                 hv_samples: int = 1 << 18, max_chunk: int = 8):
         self.pool = Pool(budget_bytes)
         self.clock = clock
         self.t0 = None
@@ -76,6 +77,8 @@ class Server:
         self.steps = 0
         self.keep_fronts = keep_fronts
         self.hv_samples = hv_samples
+        self.max_chunk = max(1, int(max_chunk))
+        self.gen_s = None      # running estimate of one batched generation's duration
         self.host_s = {"admit": 0.0, "step": 0.0, "harvest": 0.0}  # wall time per activity
 
     def now(self) -> float:
@@ -118,23 +121,38 @@ class Server:
                 self.pool.release(slot)
                 del self.active[slot]
 
+    def _chunk(self) -> int:
+        """Generations for this step: those expected to end before the earliest
+        resident deadline (one generation's duration estimated from the last
+        steps), within [1, max_chunk]."""
+        if self.gen_s is None or self.max_chunk == 1:
+            return 1
+        now = self.now()
+        left = min(req.arrival + req.deadline_s for (req, _, _) in self.active.values()) - now
+        return int(min(self.max_chunk, max(1, left // self.gen_s)))
+
     def step(self):
-        """Advance every resident solve one generation, admit what fits while the
-        GPU works (new solves join from the next generation on), then deliver
-        the solves whose deadline has passed."""
+        """Advance every resident solve by one or more generations, admit what
+        fits while the GPU works (new solves join from the next step on), then
+        deliver the solves whose deadline has passed."""
         c = self.clock
         t0 = c()
         stepped = bool(self.active)
+        k = 0
         if stepped:
-            self.pool.step(1)
-            self.steps += 1
-            self.offspring += sum(2 * n for (_, _, n) in self.active.values())
+            k = self._chunk()
+            self.pool.step(k)
+            self.steps += k
+            self.offspring += k * sum(2 * n for (_, _, n) in self.active.values())
         t1 = c()
         self._admit()
         t2 = c()
         if stepped:
             self.pool.sync()
         t3 = c()
+        if stepped:  # per generation, admission included: what a step really costs
+            per = (t3 - t0) / k
+            self.gen_s = per if self.gen_s is None else 0.8 * self.gen_s + 0.2 * per
         self._harvest()
         t4 = c()
         self.host_s["step"] += (t1 - t0) + (t3 - t2)
