@@ -424,7 +424,7 @@ gmpea_status gmpea_init(const gmpea_problem *P, const gmpea_config *C, const gmp
   for (int p = 0; p < 2; ++p) {
     // lanes per slot in k_select: about four reverse-list entries per lane
     int l = 1;
-    while (4 * l < st.t[p] && l < 64) l <<= 1;
+    while (kSelPerLane * l < st.t[p] && l < 64) l <<= 1;
     st.lps[p] = l;
   }
   st.sel_blocks0 = (N + kBlock / st.lps[0] - 1) / (kBlock / st.lps[0]);

@@ -647,14 +647,28 @@ __device__ __forceinline__ void select_body(const DevState &st, int L) {
       for (int u = 0; u < 4; ++u)
         if (ii[u] >= 0) consider(ii[u], cc[u]);
     };
-    if ((t & 3) == 0) {
-      // lane g takes entries 4g .. 4g + 3 (one 16-byte load; head rows are
-      // 16-byte aligned when t is a multiple of 4); the minimum does not
-      // depend on how the entries are dealt to lanes
-      for (int q0 = 4 * g; q0 < t; q0 += 4 * lps) {
-        const int4 v = *reinterpret_cast<const int4 *>(head + q0);
-        const int ii[4] = {v.x, v.y, v.z, v.w};
-        take4(ii);
+    constexpr int K = kSelPerLane;
+    if ((t & (K - 1)) == 0) {
+      // lane g takes entries K g .. K g + K - 1 (16-byte loads; head rows are
+      // 16-byte aligned when t is a multiple of 4), all K candidate loads in
+      // flight together; the minimum does not depend on how the entries are
+      // dealt to lanes
+      for (int q0 = K * g; q0 < t; q0 += K * lps) {
+        int ii[K];
+#pragma unroll
+        for (int h4 = 0; h4 < K / 4; ++h4) {
+          const int4 v = *reinterpret_cast<const int4 *>(head + q0 + 4 * h4);
+          ii[4 * h4] = v.x;
+          ii[4 * h4 + 1] = v.y;
+          ii[4 * h4 + 2] = v.z;
+          ii[4 * h4 + 3] = v.w;
+        }
+        Rec<M> cc[K];
+#pragma unroll
+        for (int u = 0; u < K; ++u) cc[u] = ii[u] >= 0 ? rec_load<M>(cand, ii[u]) : rec_zero<M>();
+#pragma unroll
+        for (int u = 0; u < K; ++u)
+          if (ii[u] >= 0) consider(ii[u], cc[u]);
       }
     } else {
       for (int q0 = g; q0 < t; q0 += 4 * lps) {  // one pass unless t > 4 lps = 256

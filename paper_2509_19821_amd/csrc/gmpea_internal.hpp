@@ -16,6 +16,9 @@ namespace gmpea {
 constexpr int kMaxM = 8;
 constexpr int kMaxRing = 8;
 constexpr int kBlock = 256;  // threads per block of the per-subproblem kernels
+// Reverse-list entries a k_select lane takes at a time (its lanes per slot are
+// t_p / kSelPerLane rounded up to a power of two, at most 64).
+constexpr int kSelPerLane = 8;
 // Replacement counters are spread over this many words per population: one
 // word updated by every block serialises those atomics at one L2 channel.
 constexpr int kReplLanes = 64;
