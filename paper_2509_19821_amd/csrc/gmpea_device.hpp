@@ -549,11 +549,11 @@ __global__ __launch_bounds__(kBlock) void k_op1(DevState st) {
 // lexicographic minimum over the qualifiers with the first index on ties; every
 // decision uses generation-k parents, and replacements land after all reads of
 // the slot they overwrite.
-// A group of lps lanes decides one slot (lps = t_p / 4 rounded up to a power of
-// two, at most 64: about four reverse-list entries per lane). Lane g takes
-// four entries of the slot's padded list head at a time (entries 4g .. 4g + 3
-// in one 16-byte load when t_p is a multiple of 4, else g, g + lps, ...) with
-// independent loads (index, then candidate F/CV), then its share of the tail
+// A group of lps lanes decides one slot (lps = t_p / kSelPerLane rounded up to
+// a power of two, at most 64). When t_p is a multiple of kSelPerLane, lane g
+// takes entries K g .. K g + K - 1 of the slot's padded list head (K =
+// kSelPerLane, 16-byte index loads), else entries g, g + lps, ... four at a
+// time, with independent loads (index, then candidate F/CV), then its share of the tail
 // (lists longer than t_p), and keeps its lexicographic minimum of (CV, g,
 // index). No load waits on another beyond index -> candidate: the head needs no
 // offset, and OP1's choice of population rides in the sign of the candidate's
