@@ -369,8 +369,9 @@ __global__ __launch_bounds__(kBlock) void k_eval(DevState st) {
 // and the per-offspring crossing draw; VAR block c0 = l >> 1 gives (wA, wB) for
 // variables l and l + 1: SBX's bits in wA, the mutation test and uniform in wB.
 // A group of LPO consecutive lanes builds one offspring: lane g of the group
-// takes the float4 chunks g, g + LPO, ... of the row, so with LPO = 8 the group
-// reads each parent row and writes the offspring row as whole 128-byte lines.
+// takes the float4 chunks g, g + LPO, ... of the row, so each group step reads
+// and writes LPO * 16 contiguous bytes of a row (whole 128-byte lines at
+// LPO = 8); LPO comes from vary_lanes_of.
 // The group shares the mating draw (each lane computes it; the cost is one
 // Philox block either way) and reduces the evaluation sums with butterflies.
 // ----------------------------------------------------------------------------

@@ -89,10 +89,11 @@ struct DevState {
 // Launch geometry shared by host and device (plain and batched launches must
 // agree on it, since it fixes the lane grouping and so the rounding order).
 // Lanes per offspring in k_vary: enough that each lane keeps two to four float4
-// chunks of the row.
+// chunks of the row, except the widest rows (d > 92), where four lanes of six
+// or seven chunks each measured faster than eight.
 __host__ __device__ inline int vary_lanes_of(int stride) {
   const int nq = stride >> 2;
-  return nq >= 16 ? 8 : nq >= 6 ? 4 : nq >= 3 ? 2 : 1;
+  return nq >= 24 ? 4 : nq >= 16 ? 8 : nq >= 6 ? 4 : nq >= 3 ? 2 : 1;
 }
 // k_vary blocks of one instance (both populations).
 __host__ __device__ inline int vary_blocks_of(int n, int lanes) {
