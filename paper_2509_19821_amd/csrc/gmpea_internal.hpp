@@ -106,11 +106,13 @@ hipError_t launch_init(const DevState &st, hipStream_t s);
 // A generation is kPhases launches: 0 variation + evaluation + ideal point,
 // 1 offspring cooperation, 2 neighbour replacement decisions, 3 row copies.
 constexpr int kPhases = 4;
-// Row copies: a block copies `iters` runs of kBlock float4 elements of both
-// populations' rows: one run in the plain launch, kRowsIterBatch in a batched
-// one, where each work item must also cover fetching its item and instance
-// state (the copies do not depend on how they are split).
+// Row copies: a batched work item copies kRowsIterBatch runs of kBlock float4
+// elements of both populations' rows (each item also fetches its entry and
+// instance state); the plain launch strides a grid of at most kRowsGrid blocks
+// (eight per CU) over the elements, which saves the dispatch of one block per
+// run. The copies do not depend on how they are split.
 constexpr int kRowsIterBatch = 4;
+constexpr int kRowsGrid = 2048;
 __host__ __device__ inline int rows_blocks_of(int n, int stride, int iters = 1) {
   const long long e = 2LL * n * (stride >> 2);
   const long long per = static_cast<long long>(kBlock) * iters;

@@ -214,7 +214,10 @@ __global__ __launch_bounds__(kBlock) void k_rev_sort(int32_t n, int32_t t, const
 }
 
 __global__ __launch_bounds__(kBlock) void k_rows(DevState st) {
-  rows_body(st, static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x);
+  const int64_t total = 2LL * st.n * (st.stride >> 2);
+  const int64_t step = static_cast<int64_t>(gridDim.x) * kBlock;
+  for (int64_t e = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; e < total; e += step)
+    rows_body(st, e);
 }
 
 __global__ __launch_bounds__(kBlock) void k_vary_batch(const DevState *__restrict__ S,
@@ -583,7 +586,8 @@ hipError_t launch_phase(const DevState &st, int phase, hipStream_t s) {
   } else if (phase == 2) {
     GMPEA_DISPATCH_M(k_select, st.sel_blocks0 + st.sel_blocks1, s, st);
   } else {
-    hipLaunchKernelGGL(k_rows, dim3(rows_blocks_of(st.n, st.stride)), dim3(kBlock), 0, s, st);
+    hipLaunchKernelGGL(k_rows, dim3(std::min(rows_blocks_of(st.n, st.stride), kRowsGrid)), dim3(kBlock), 0, s,
+                       st);
   }
   return hipGetLastError();
 }
