@@ -66,8 +66,10 @@ class Server:
     """Single-threaded serving loop on one GPU (one pool, one stream)."""
 
     def __init__(self, budget_bytes: int, clock=time.perf_counter, keep_fronts: bool = True,
-                 hv_samples: int = 1 << 18, max_chunk: int = 8):
-        self.pool = Pool(budget_bytes)
+                 hv_samples: int = 1 << 18, max_chunk: int = 8, pool=None):
+        # pool: any object with Pool's try_admit / instance / step / sync /
+        # release / close (the scheduling is tested on the host with a stand-in)
+        self.pool = pool if pool is not None else Pool(budget_bytes)
         self.clock = clock
         self.t0 = None
         self.waiting = collections.deque()
