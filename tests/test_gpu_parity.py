@@ -343,6 +343,27 @@ def test_generation_odd_shapes(G):
         gp.close()
 
 
+@pytest.mark.parametrize("family,m,d,n_req,t1,t2", [
+    (ci.FAMILY_CURVE, 2, 2, 2, 1, 2),    # the smallest lattice (H = 1), one chunk per row
+    (ci.FAMILY_SPHERE, 2, 1, 2, 2, 2),   # one variable: no distance term g
+    (ci.FAMILY_SPHERE, 3, 2, 3, 1, 3),   # m = 3 with only the angles, every slot sees all
+])
+def test_generation_smallest_shapes(G, family, m, d, n_req, t1, t2):
+    """The smallest instances the boundary accepts, unconstrained (CV = 0
+    throughout, so population 1's rule reduces to population 2's): a single
+    partly used tile and chunk, neighbourhoods up to the whole population."""
+    prob = ci.make_problem(family, m, d, 0, False, False, 7)
+    cfg = ci.method_config(n_req, 2, 7, t1=t1, t2=t2)
+    gp, o = _pair(prob, cfg)
+    try:
+        assert gp.n == n_req
+        gp.step(3)
+        _teacher_forced(gp, o, 3, "smallest m=%d d=%d" % (m, d))
+        assert np.all(gp.read("CV", 0) == 0) and np.all(gp.read("CV", 1) == 0)
+    finally:
+        gp.close()
+
+
 def test_generation_full_size_large(G):
     """One teacher-forced generation of the large workload at full size
     (N = 100,128 per population, d = 100, t1 = 16, t2 = 64) in the launch
