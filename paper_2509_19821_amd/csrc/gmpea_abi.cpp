@@ -422,9 +422,9 @@ gmpea_status gmpea_init(const gmpea_problem *P, const gmpea_config *C, const gmp
   st.t[0] = t1;
   st.t[1] = t2;
   for (int p = 0; p < 2; ++p) {
-    // lanes per slot in k_select: about four reverse-list entries per lane
+    // lanes per slot in k_select: sel_per_lane reverse-list entries per lane
     int l = 1;
-    while (kSelPerLane * l < st.t[p] && l < 64) l <<= 1;
+    while (sel_per_lane(st.rq) * l < st.t[p] && l < 64) l <<= 1;
     st.lps[p] = l;
   }
   st.sel_blocks0 = (N + kBlock / st.lps[0] - 1) / (kBlock / st.lps[0]);

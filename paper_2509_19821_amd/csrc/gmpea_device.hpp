@@ -550,10 +550,10 @@ __global__ __launch_bounds__(kBlock) void k_op1(DevState st) {
 // lexicographic minimum over the qualifiers with the first index on ties; every
 // decision uses generation-k parents, and replacements land after all reads of
 // the slot they overwrite.
-// A group of lps lanes decides one slot (lps = t_p / kSelPerLane rounded up to
-// a power of two, at most 64). When t_p is a multiple of kSelPerLane, lane g
+// A group of lps lanes decides one slot (lps = t_p / sel_per_lane rounded up to
+// a power of two, at most 64). When t_p is a multiple of sel_per_lane, lane g
 // takes entries K g .. K g + K - 1 of the slot's padded list head (K =
-// kSelPerLane, 16-byte index loads), else entries g, g + lps, ... four at a
+// sel_per_lane, 16-byte index loads), else entries g, g + lps, ... four at a
 // time, with independent loads (index, then candidate F/CV), then its share of the tail
 // (lists longer than t_p), and keeps its lexicographic minimum of (CV, g,
 // index). No load waits on another beyond index -> candidate: the head needs no
@@ -648,7 +648,7 @@ __device__ __forceinline__ void select_body(const DevState &st, int L) {
       for (int u = 0; u < 4; ++u)
         if (ii[u] >= 0) consider(ii[u], cc[u]);
     };
-    constexpr int K = kSelPerLane;
+    constexpr int K = sel_per_lane(Rec<M>::Q);
     if ((t & (K - 1)) == 0) {
       // lane g takes entries K g .. K g + K - 1 (16-byte loads; head rows are
       // 16-byte aligned when t is a multiple of 4), all K candidate loads in

@@ -16,9 +16,11 @@ namespace gmpea {
 constexpr int kMaxM = 8;
 constexpr int kMaxRing = 8;
 constexpr int kBlock = 256;  // threads per block of the per-subproblem kernels
-// Reverse-list entries a k_select lane takes at a time (its lanes per slot are
-// t_p / kSelPerLane rounded up to a power of two, at most 64).
-constexpr int kSelPerLane = 8;
+// Reverse-list entries a k_select lane takes at a time, by the float4 count of
+// an F/CV record: eight one-float4 records, four wider ones (their loads in
+// flight take the registers). A slot's lanes are t_p / that count rounded up to
+// a power of two, at most 64.
+__host__ __device__ constexpr int sel_per_lane(int rq) { return rq == 1 ? 8 : 4; }
 // Replacement counters are spread over this many words per population: one
 // word updated by every block serialises those atomics at one L2 channel.
 constexpr int kReplLanes = 64;
