@@ -304,7 +304,7 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build runs each instance on a single "
+        print("bench.py measures one GPU only: each instance runs on a single "
               "MI355X (instances shard across GPUs without communication); run with --gpus 1",
               file=sys.stderr)
         sys.exit(2)

@@ -42,7 +42,7 @@ typedef enum {
   GMPEA_EHIP = -3,        /* a HIP runtime call failed */
   GMPEA_ECAPACITY = -4,   /* an output buffer is too small; *count holds the need */
   GMPEA_ESTATE = -5,      /* handle destroyed or not in a usable state */
-  GMPEA_EUNSUPPORTED = -6 /* valid request outside what this build implements */
+  GMPEA_EUNSUPPORTED = -6 /* valid request outside what the library implements */
 } gmpea_status;
 
 /* Reproduction operators (the experimental settings name both). GMPEA_OP_DE
@@ -107,8 +107,8 @@ enum {
   GMPEA_BUF_WIN = 12
 };
 
-#define GMPEA_MAX_M 8     /* objectives supported by this build */
-#define GMPEA_MAX_RING 8  /* ring constraints supported by this build */
+#define GMPEA_MAX_M 8     /* objectives the library supports */
+#define GMPEA_MAX_RING 8  /* ring constraints the library supports */
 
 /* A CMOP instance (Eq. (1)): minimise F(x) over the box [lb, ub]^d subject to
  *   ring:     r_j^2 - ||F(x) - a_j||^2 <= 0          (j < n_ring)
