@@ -104,7 +104,18 @@ def cpu_baseline(target_s=12.0):
             "kind": "oracle",
             "sample": "large-workload shape (m=3, d=100, T=32, 4 rings + equality) at N=%d per "
                       "population, %d generations after one warm-up, FP64, OpenMP over "
-                      "subproblems" % (o.N, gens)}
+                      "subproblems on %s" % (o.N, gens, _cpu_model())}
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "an unidentified CPU"
 
 
 def copy_probe(g, nbytes=512 << 20, reps=5):
