@@ -3,7 +3,8 @@
 A plain, slow, obviously-correct FP64 implementation of what one GMPEA
 generation computes (Alg. 1 loop body and Alg. 2 of arXiv 2509.19821), plus
 the quality indicators of Eqs. (14)-(15). Only ``tests/``, the package smoke
-check and the CPU-baseline leg of ``bench.py`` may import it. The product path
+check and the CPU legs of ``bench.py`` (the ``cpu_baseline`` object and the
+CPU columns of ``--sweep`` and ``--many``) may import it. The product path
 (the HIP library and its binding) never imports, links or calls anything here,
 and this package shares no code with it; the only module both sides use is
 ``cmop_inputs`` (seeded problem constants, no method arithmetic).

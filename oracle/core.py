@@ -1,7 +1,8 @@
 """ctypes front end of the FP64 C oracle (gmpea_oracle.c).
 
-TEST INFRASTRUCTURE ONLY: imported by tests, the smoke check and the CPU
-baseline of the benchmark; never by the product path.
+TEST INFRASTRUCTURE ONLY: imported by tests, the smoke check and the CPU legs
+of the benchmark (its baseline and the CPU columns of its sweeps); never by
+the product path.
 """
 from __future__ import annotations
 
