@@ -12,14 +12,19 @@ namespace gmpea {
 // Counter RNG: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).
 // ----------------------------------------------------------------------------
 // Each round's two 32 x 32 -> 64-bit products are written as 64-bit multiplies
-// so that each becomes one v_mad_u64_u32 (high and low words together).
+// so that each becomes one v_mad_u64_u32 (high and low words together), and
+// each three-way XOR with the round key is one gfx950 v_bitop3_b32 (truth
+// table 0x96) instead of two v_xor_b32.
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+  return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
 __device__ __forceinline__ uint4 philox10(uint4 c, uint32_t k0, uint32_t k1) {
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
     const uint64_t p0 = static_cast<uint64_t>(0xD2511F53u) * c.x;
     const uint64_t p1 = static_cast<uint64_t>(0xCD9E8D57u) * c.z;
-    c = make_uint4(static_cast<uint32_t>(p1 >> 32) ^ c.y ^ k0, static_cast<uint32_t>(p1),
-                   static_cast<uint32_t>(p0 >> 32) ^ c.w ^ k1, static_cast<uint32_t>(p0));
+    c = make_uint4(xor3(static_cast<uint32_t>(p1 >> 32), c.y, k0), static_cast<uint32_t>(p1),
+                   xor3(static_cast<uint32_t>(p0 >> 32), c.w, k1), static_cast<uint32_t>(p0));
     k0 += 0x9E3779B9u;
     k1 += 0xBB67AE85u;
   }
