@@ -364,6 +364,27 @@ def test_generation_smallest_shapes(G, family, m, d, n_req, t1, t2):
         gp.close()
 
 
+@pytest.mark.parametrize("pm", [0.75, 0.05])
+def test_generation_operator_parameters(G, pm):
+    """Non-default operators and box: bounds other than [0, 1] per variable
+    (the clip and the mutation's span), eta_c = 2, eta_m = 5, pc = 0.6,
+    theta = 2, and a mutation rate above 1/2, whose threshold floor(pm 2^32)
+    needs the 64-bit numerators of the mutation step, beside one below it."""
+    d = 20
+    lb = np.linspace(-1.0, -0.2, d)
+    ub = np.linspace(0.5, 3.0, d)
+    prob = ci.make_problem(ci.FAMILY_SPHERE, 3, d, 2, True, False, 11, lb=lb, ub=ub)
+    cfg = ci.method_config(300, 10, 11, theta=2.0, eta_c=2.0, eta_m=5.0, pc=0.6, pm=pm)
+    gp, o = _pair(prob, cfg)
+    try:
+        gp.step(2)
+        _teacher_forced(gp, o, 2, "operators pm=%g" % pm)
+        X = gp.read("X", 0)
+        assert np.all(X >= lb.astype(np.float32)) and np.all(X <= ub.astype(np.float32))
+    finally:
+        gp.close()
+
+
 def test_generation_full_size_large(G):
     """One teacher-forced generation of the large workload at full size
     (N = 100,128 per population, d = 100, t1 = 16, t2 = 64) in the launch
