@@ -124,15 +124,19 @@ def test_pool_front_and_empty_steps(G):
 
 
 def test_batched_mixed_objectives_equal_alone(G):
-    """A pool holding m = 2 .. 8: the m > 3 instances run in their own batched
-    kernels (the row copies are shared by all), and every instance still equals
-    its run alone, bit for bit."""
+    """A pool holding m = 2 .. 8, SBX and DE, PBI and Tchebycheff: the m > 3
+    instances run in their own batched kernels (the row copies are shared by
+    all), and every instance still equals its run alone, bit for bit."""
     S = ci.FAMILY_SPHERE
     mix = [ci.workload_small(13)[:2], ci.workload_many5(14)[:2], ci.workload_many8(15)[:2],
            (ci.make_problem(S, 6, 33, 2, True, False, 16),
             ci.method_config(2, 10, 16, op=1, h_outer=5, h_inner=3)),
            (ci.make_problem(S, 3, 40, 2, True, False, 17), ci.method_config(900, 12, 17)),
-           (ci.make_problem(S, 4, 9, 1, False, False, 18), ci.method_config(400, 8, 18, agg=1))]
+           (ci.make_problem(S, 4, 9, 1, False, False, 18), ci.method_config(400, 8, 18, agg=1)),
+           # m <= 3 with DE, and with Tchebycheff, a high mutation rate and eta_c = 3
+           (ci.make_problem(S, 3, 25, 2, True, False, 19), ci.method_config(500, 10, 19, op=1)),
+           (ci.make_problem(ci.FAMILY_CURVE, 2, 11, 1, False, False, 20),
+            ci.method_config(200, 10, 20, agg=1, pm=0.75, eta_c=3.0))]
     gens = 21  # one graph replay of 16 plus eager generations
     pool = G.Pool(4 << 30)
     try:
