@@ -34,6 +34,14 @@ KERNEL_SRC = [os.path.join(ROOT, "paper_2509_19821_amd", "csrc", f)
               for f in ("gmpea_device.hpp", "gmpea_kernels.hip", "gmpea_kernels_wide.hip",
                         "gmpea_internal.hpp")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_large.json")
+VALU_FILE = os.path.join(ROOT, "profiles", "valu_large.json")
+# Vector-ALU issue ceiling: 256 CUs x 4 SIMDs, each SIMD issuing one wave64
+# VALU instruction every 4 cycles (16 lanes per cycle) at 2.4 GHz, i.e.
+# 39.3e12 lane-operations per second for single-issue 32-bit operations. (The
+# chip's 157.3 TFLOP/s FP32 figure counts an FMA as two operations and packed
+# dual FP32 issue, which this build keeps off.)
+SIMDS, CLOCK_HZ, CYCLES_PER_VALU = 1024, 2.4e9, 4
+ALU_PEAK_LANE_OPS = SIMDS * 16 * CLOCK_HZ
 
 
 def log(msg):
@@ -83,28 +91,53 @@ def measured_traffic(kernel):
     return None if k is None else k.get("bytes_per_launch")
 
 
-def cpu_baseline(target_s=12.0):
+def measured_valu(kernel):
+    """SQ_INSTS_VALU (wave-level VALU instructions) per launch from a committed
+    rocprofv3 --pmc run, only if taken on the kernel source as it is now."""
+    try:
+        with open(VALU_FILE) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_src_sha256_16") != kernel_hash():
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("valu_insts_per_launch")
+
+
+def cpu_baseline(target_s=12.0, single_s=10.0):
     """The oracle as it stands, on the large workload's shape at a bounded
-    population (N = 50,086 per population), timed over whole generations."""
+    population (N = 50,086 per population), timed over whole generations: once
+    with OpenMP over subproblems on every host core, once on one thread."""
     import cmop_inputs as ci
     from oracle import core
     prob, cfg, _ = ci.workload_large(0)
     cfg = dict(cfg, n_req=50000)
-    cores = core.set_threads(0)
-    o = core.Oracle(prob, cfg)
-    o.step()  # first generation off the clock
-    gens, t0 = 0, time.perf_counter()
-    while True:
-        o.step()
-        gens += 1
-        el = time.perf_counter() - t0
-        if el >= target_s or gens >= 200:
-            break
-    return {"value": 2.0 * o.N * gens / el, "unit": "offspring/s", "cores": int(cores),
-            "kind": "oracle",
-            "sample": "large-workload shape (m=3, d=100, T=32, 4 rings + equality) at N=%d per "
-                      "population, %d generations after one warm-up, FP64, OpenMP over "
-                      "subproblems on %s" % (o.N, gens, _cpu_model())}
+
+    def timed(threads, budget_s, max_gens):
+        cores = core.set_threads(threads)
+        o = core.Oracle(prob, cfg)
+        o.step()  # first generation off the clock
+        gens, t0 = 0, time.perf_counter()
+        while True:
+            o.step()
+            gens += 1
+            el = time.perf_counter() - t0
+            if el >= budget_s or gens >= max_gens:
+                break
+        return 2.0 * o.N * gens / el, int(cores), o.N, gens
+
+    all_cores = core.set_threads(0)
+    v, cores, n, gens = timed(all_cores, target_s, 200)
+    v1, _, _, gens1 = timed(1, single_s, 50)
+    core.set_threads(all_cores)
+    shape = "large-workload shape (m=3, d=100, T=32, 4 rings + equality) at N=%d per population" % n
+    return {"value": v, "unit": "offspring/s", "cores": cores, "kind": "oracle",
+            "sample": "%s, %d generations after one warm-up, FP64, OpenMP over subproblems on %s"
+                      % (shape, gens, _cpu_model()),
+            "single_thread": {"value": v1, "cores": 1,
+                              "sample": "%s, %d generations after one warm-up, FP64, one thread"
+                                        % (shape, gens1)}}
 
 
 def _cpu_model():
@@ -119,19 +152,23 @@ def _cpu_model():
 
 
 def copy_probe(g, nbytes=512 << 20, reps=5):
-    """Bandwidth of the library's streaming copy kernel (read + write bytes per
-    second, best of `reps`); also the reference launch for counter calibration."""
+    """Attainable copy bandwidth (read + write bytes per second, fastest of
+    `reps`, HIP events) of four copy forms: the library's strided copy kernel
+    (also the counter calibration launch), a one-pass copy with four 16-byte
+    words per thread, the same with non-temporal accesses, and the runtime's
+    hipMemcpyAsync."""
     src, dst = g.DeviceBuffer(nbytes), g.DeviceBuffer(nbytes)
+    out = {}
     try:
-        best = float("inf")
-        for _ in range(reps):
-            t0 = time.perf_counter()
-            g.copy(src.ptr.value, dst.ptr.value, nbytes)
-            best = min(best, time.perf_counter() - t0)
+        g.copy(src.ptr.value, dst.ptr.value, nbytes)
+        for name, mode in (("strided_kernel", g.COPY_STRIDED), ("wide_kernel", g.COPY_WIDE),
+                           ("wide_nontemporal", g.COPY_WIDE_NT), ("hipMemcpyAsync", g.COPY_RUNTIME)):
+            ms = g.copy_probe(src.ptr.value, dst.ptr.value, nbytes, mode, reps)
+            out[name] = round(2.0 * nbytes / (ms * 1e-3) / 1e9, 1)
     finally:
         src.free()
         dst.free()
-    return 2.0 * nbytes / best / 1e9
+    return out
 
 
 def batched_vs_plain(g, ci, count=256, gens=300):
@@ -305,7 +342,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
-    ap.add_argument("--serve-window", type=float, default=5.0)
+    ap.add_argument("--serve-window", type=float, default=60.0)
+    ap.add_argument("--n-req", type=int, default=0,
+                    help="reference vectors requested per population for the main line "
+                         "(default: the large workload's 100,000)")
     ap.add_argument("--sweep", action="store_true",
                     help="print generation time against population size (GPU and CPU oracle) "
                          "instead of the benchmark line")
@@ -331,6 +371,8 @@ def main():
         return
 
     prob, cfg, K_total = ci.workload_large(0)
+    if args.n_req > 0:
+        cfg = dict(cfg, n_req=args.n_req)
     log("bench: init large workload")
     t0 = time.perf_counter()
     gp = g.Gmpea(prob, cfg)
@@ -361,15 +403,27 @@ def main():
     traffic = measured_traffic(dom)
     log("bench: per-kernel ms %s; model bytes %s" % (ms, model))
     gen_bytes = sum(model.values())
-    copy_gbs = copy_probe(g)
-    log("bench: streaming copy %.0f GB/s" % copy_gbs)
-    roof = {"bound": "hbm", "kernel": "k_" + dom, "achieved": round(achieved, 1),
-            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": traffic, "algorithmic_bytes_per_launch": int(model[dom]),
-            "avg_launch_ms": round(ms[dom], 5),
+    copies = copy_probe(g)
+    log("bench: copy bandwidth %s GB/s" % copies)
+    hbm = {"achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(achieved / HBM_PEAK_GBS, 4)}
+    valu = measured_valu(dom)
+    alu = None
+    if valu is not None:
+        # lane-operations per second: wave64 instructions x 64 lanes over the launch
+        lane_ops = valu * 64 / (ms[dom] * 1e-3)
+        alu = {"achieved": round(lane_ops / 1e12, 2), "peak": round(ALU_PEAK_LANE_OPS / 1e12, 2),
+               "unit": "T VALU lane-ops/s", "frac": round(lane_ops / ALU_PEAK_LANE_OPS, 4),
+               "valu_insts_per_launch": int(valu)}
+    bind = alu if (alu is not None and alu["frac"] > hbm["frac"]) else hbm
+    roof = {"bound": "alu" if bind is alu else "hbm", "kernel": "k_" + dom,
+            "achieved": bind["achieved"], "peak": bind["peak"], "unit": bind["unit"],
+            "frac": bind["frac"], "traffic": traffic,
+            "algorithmic_bytes_per_launch": int(model[dom]), "avg_launch_ms": round(ms[dom], 5),
+            "hbm": hbm, "alu": alu,
             "per_kernel_ms": {k: round(v, 5) for k, v in ms.items()},
             "generation_gbs": round(gen_bytes / (sum(ms.values()) * 1e-3) / 1e9, 1),
-            "copy_probe_gbs": round(copy_gbs, 1),
+            "copy_probe_gbs": copies,
             "rho": [round(r, 4) for r in rho]}
     gp.close()
 

@@ -379,6 +379,23 @@ void gmpea_pool_destroy(gmpea_pool_t pool);
  * hip_stream (NULL: legacy default) and synchronises. */
 gmpea_status gmpea_copy(const void *src, void *dst, size_t bytes, void *hip_stream);
 
+/* Copy forms timed by gmpea_copy_probe. */
+enum {
+  GMPEA_COPY_STRIDED = 0, /* gmpea_copy's kernel: at most 4,096 blocks striding, 16 B per step */
+  GMPEA_COPY_WIDE = 1,    /* one pass, four 16-byte words per thread, loads before stores */
+  GMPEA_COPY_WIDE_NT = 2, /* the same with non-temporal loads and stores */
+  GMPEA_COPY_RUNTIME = 3  /* the HIP runtime's hipMemcpyAsync device to device */
+};
+
+/* Attainable device-memory bandwidth, for the roofline's measured ceiling:
+ * times `reps` copies (after one untimed) of `bytes` (a multiple of 16, > 0;
+ * both pointers 16-byte aligned device memory, not overlapping) in one of the
+ * forms above with HIP events on hip_stream (NULL: legacy default); *ms
+ * receives the fastest copy's time in milliseconds (bandwidth = 2 bytes / time).
+ * EINVAL for bad arguments or mode; EHIP for a runtime failure. Synchronises. */
+gmpea_status gmpea_copy_probe(const void *src, void *dst, size_t bytes, int32_t mode,
+                              int32_t reps, void *hip_stream, float *ms);
+
 #ifdef __cplusplus
 }
 #endif

@@ -132,7 +132,33 @@ def _feasible_objective(prob: dict, F: np.ndarray, tol: float = 1e-9) -> np.ndar
     return ok
 
 
+def nd_mask_2d(F: np.ndarray) -> np.ndarray:
+    """Non-dominated rows of a two-objective set (Eq. (4): q dominates p iff
+    q <= p in both objectives and q < p in one), equal rows all kept, by a
+    sweep in (f1, f2) order instead of all pairs: p is dominated iff some row
+    with a smaller f1 has f2 <= p's f2, or a row with the same f1 has a
+    smaller f2."""
+    F = np.asarray(F, dtype=np.float64)
+    n = F.shape[0]
+    keep = np.zeros(n, dtype=bool)
+    if n == 0:
+        return keep
+    order = np.lexsort((F[:, 1], F[:, 0]))
+    f1, f2 = F[order, 0], F[order, 1]
+    # groups of equal f1 (each sorted by f2, so its first row has the least f2)
+    start = np.concatenate([[True], f1[1:] != f1[:-1]])
+    grp = np.cumsum(start) - 1
+    gmin = f2[start]
+    # smallest f2 among rows with a strictly smaller f1: the running minimum
+    # over the earlier groups
+    before = np.concatenate([[np.inf], np.minimum.accumulate(gmin)[:-1]])
+    keep[order] = ~((before[grp] <= f2) | (gmin[grp] < f2))
+    return keep
+
+
 def _nd(F: np.ndarray) -> np.ndarray:
+    if F.shape[1] == 2:
+        return F[nd_mask_2d(F)]
     keep = core.front_mask(F, np.zeros(F.shape[0]))
     return F[keep]
 

@@ -1045,6 +1045,46 @@ gmpea_status gmpea_copy(const void *src, void *dst, size_t bytes, void *hip_stre
   return GMPEA_OK;
 }
 
+gmpea_status gmpea_copy_probe(const void *src, void *dst, size_t bytes, int32_t mode,
+                              int32_t reps, void *hip_stream, float *ms) {
+  if (bytes % 16 != 0 || bytes == 0 || !src || !dst || !ms || reps < 1 ||
+      (reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) % 16 != 0)
+    return fail(GMPEA_EINVAL, "gmpea_copy_probe: need 16-byte aligned pointers and size, reps >= 1");
+  if (mode < GMPEA_COPY_STRIDED || mode > GMPEA_COPY_RUNTIME)
+    return fail(GMPEA_EINVAL, "gmpea_copy_probe: unknown mode");
+  gmpea_status st = check_runtime("gmpea_copy_probe");
+  if (st != GMPEA_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  const int64_t n16 = static_cast<int64_t>(bytes / 16);
+  auto one = [&]() -> hipError_t {
+    switch (mode) {
+      case GMPEA_COPY_STRIDED: return launch_copy(src, dst, n16, s);
+      case GMPEA_COPY_WIDE: return launch_copy4(src, dst, n16, false, s);
+      case GMPEA_COPY_WIDE_NT: return launch_copy4(src, dst, n16, true, s);
+      default: return hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s);
+    }
+  };
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e == hipSuccess) e = one();  // warm-up
+  float best = 0.0f;
+  for (int32_t r = 0; r < reps && e == hipSuccess; ++r) {
+    e = hipEventRecord(e0, s);
+    if (e == hipSuccess) e = one();
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float t = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+    if (e == hipSuccess && (r == 0 || t < best)) best = t;
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (e != hipSuccess) return hip_fail(e, "gmpea_copy_probe");
+  *ms = best;
+  return GMPEA_OK;
+}
+
 gmpea_status gmpea_philox(const uint32_t *ctr, int64_t n, uint64_t seed, uint32_t *out,
                           void *hip_stream) {
   if (n < 0 || (n > 0 && (!ctr || !out))) return fail(GMPEA_EINVAL, "gmpea_philox: bad arguments");

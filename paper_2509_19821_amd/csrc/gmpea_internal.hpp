@@ -137,6 +137,8 @@ hipError_t launch_front_flags(const DevState &st, int pop, uint8_t *keep, hipStr
 hipError_t launch_gather(const DevState &st, int pop, const int32_t *idx, int32_t count,
                          float *x, float4 *fc, hipStream_t s);
 hipError_t launch_copy(const void *src, void *dst, int64_t n16, hipStream_t s);
+// One-pass copy, four 16-byte words per thread (optionally non-temporal).
+hipError_t launch_copy4(const void *src, void *dst, int64_t n16, bool nontemporal, hipStream_t s);
 // Neighbourhoods of n rows of integer coordinates K (n x m, device): B1 (n x t1)
 // and B2 (n x t2) receive each row's nearest rows by exact squared distance,
 // ties by index. max_dist bounds every squared distance (it sets the digits of

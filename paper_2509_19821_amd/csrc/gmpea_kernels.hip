@@ -491,6 +491,33 @@ __global__ __launch_bounds__(kBlock) void k_copy(const uint4 *__restrict__ src,
     dst[q] = src[q];
 }
 
+// The same copy with four independent 16-byte words per thread in flight (all
+// four loads issued before the stores) and one pass over the buffer: a second
+// reading of the attainable copy bandwidth. kNt selects non-temporal loads and
+// stores (streamed past the caches).
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+template <bool kNt>
+__global__ __launch_bounds__(kBlock) void k_copy4(const u32x4 *__restrict__ src,
+                                                  u32x4 *__restrict__ dst, int64_t n16) {
+  const int64_t base = static_cast<int64_t>(blockIdx.x) * (4 * kBlock) + threadIdx.x;
+  u32x4 v[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int64_t q = base + u * kBlock;
+    if (q < n16) v[u] = kNt ? __builtin_nontemporal_load(src + q) : src[q];
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int64_t q = base + u * kBlock;
+    if (q < n16) {
+      if (kNt)
+        __builtin_nontemporal_store(v[u], dst + q);
+      else
+        dst[q] = v[u];
+    }
+  }
+}
+
 // ----------------------------------------------------------------------------
 // Launchers
 // ----------------------------------------------------------------------------
@@ -639,6 +666,19 @@ hipError_t launch_copy(const void *src, void *dst, int64_t n16, hipStream_t s) {
   const int64_t blocks = std::min<int64_t>((n16 + kBlock - 1) / kBlock, 256 * 16);
   hipLaunchKernelGGL(k_copy, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, s,
                      static_cast<const uint4 *>(src), static_cast<uint4 *>(dst), n16);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy4(const void *src, void *dst, int64_t n16, bool nontemporal, hipStream_t s) {
+  if (n16 <= 0) return hipSuccess;
+  const int64_t blocks = (n16 + 4 * kBlock - 1) / (4 * kBlock);
+  if (blocks > 0x7FFFFFFF) return hipErrorInvalidValue;
+  if (nontemporal)
+    hipLaunchKernelGGL(k_copy4<true>, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, s,
+                       static_cast<const u32x4 *>(src), static_cast<u32x4 *>(dst), n16);
+  else
+    hipLaunchKernelGGL(k_copy4<false>, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, s,
+                       static_cast<const u32x4 *>(src), static_cast<u32x4 *>(dst), n16);
   return hipGetLastError();
 }
 

@@ -35,7 +35,8 @@ EXPORTS = ["gmpea_init", "gmpea_step", "gmpea_run", "gmpea_front", "gmpea_get_in
            "gmpea_philox", "gmpea_copy", "gmpea_pool_create", "gmpea_pool_admit",
            "gmpea_pool_step", "gmpea_pool_tune", "gmpea_pool_handle", "gmpea_pool_release",
            "gmpea_pool_query", "gmpea_pool_sync", "gmpea_pool_destroy", "gmpea_lattice",
-           "gmpea_reference_set", "gmpea_quality", "gmpea_shape"]
+           "gmpea_reference_set", "gmpea_quality", "gmpea_shape", "gmpea_copy_probe"]
+COPY_STRIDED, COPY_WIDE, COPY_WIDE_NT, COPY_RUNTIME = 0, 1, 2, 3
 PHASES = ("vary", "op1", "select", "rows")
 
 
@@ -137,6 +138,8 @@ def lib():
         L.gmpea_profile.argtypes = [vp, i32, vp]
         L.gmpea_sync.argtypes = [vp]
         L.gmpea_copy.argtypes = [vp, vp, ctypes.c_size_t, vp]
+        L.gmpea_copy_probe.argtypes = [vp, vp, ctypes.c_size_t, i32, i32, vp,
+                                       ctypes.POINTER(ctypes.c_float)]
         L.gmpea_pool_create.argtypes = [ctypes.c_size_t, ctypes.POINTER(Allocator), vp,
                                         ctypes.POINTER(vp)]
         L.gmpea_pool_admit.argtypes = [vp, ctypes.POINTER(Problem), ctypes.POINTER(Config),
@@ -365,6 +368,16 @@ def copy(src_dev_ptr: int, dst_dev_ptr: int, nbytes: int, stream: int = 0):
     """The library's streaming copy kernel (bandwidth reference)."""
     _check(lib().gmpea_copy(ctypes.c_void_p(src_dev_ptr), ctypes.c_void_p(dst_dev_ptr), int(nbytes),
                             ctypes.c_void_p(stream) if stream else None))
+
+
+def copy_probe(src_dev_ptr: int, dst_dev_ptr: int, nbytes: int, mode: int, reps: int = 5,
+               stream: int = 0) -> float:
+    """Fastest of `reps` timed copies (milliseconds) in one of the COPY_* forms."""
+    ms = ctypes.c_float(0.0)
+    _check(lib().gmpea_copy_probe(ctypes.c_void_p(src_dev_ptr), ctypes.c_void_p(dst_dev_ptr),
+                                  int(nbytes), int(mode), int(reps),
+                                  ctypes.c_void_p(stream) if stream else None, ctypes.byref(ms)))
+    return float(ms.value)
 
 
 def philox(ctr_dev_ptr: int, n: int, seed: int, out_dev_ptr: int, stream: int = 0):

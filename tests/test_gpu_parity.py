@@ -102,7 +102,135 @@ def _diag_decision(label, p, slots, S, Xo, Fo, CVo, z, g_win, g_sw, dbg):
                  o_Xo=dbg["Xo"], o_Fo=dbg["Fo"], o_CVo=dbg["CVo"])
 
 
-def _teacher_forced(gp, o, gens, label):
+def _rev_lists(B):
+    """Reverse neighbourhoods rev(j) = {i : j in B(i)}, ascending: CSR (off, idx)."""
+    N, t = B.shape
+    j = B.reshape(-1).astype(np.int64)
+    i = np.repeat(np.arange(N, dtype=np.int64), t)
+    order = np.lexsort((i, j))
+    off = np.zeros(N + 1, dtype=np.int64)
+    np.add.at(off, j + 1, 1)
+    return np.cumsum(off), i[order]
+
+
+def _unchecked_valid(p, slots, S, Fo, CVo, z, g_win, g_sw, o, agg, theta):
+    """Slots the FP32 comparison leaves unchecked still hold a valid outcome
+    within the FP32 bound of reading R24 (margins 2e-6 (max(|a|, |b|) +
+    max(1, |F|, |z|)) on g, 1e-6 max(1, |a|, |b|) on CV), keys from the
+    device's own FP32 values: a kept parent has no candidate clearly better than
+    it, and a chosen winner is neither clearly worse than the parent nor than
+    any other candidate of the slot (Alg. 2 OP2/OP3, Eq. (8))."""
+    from oracle.dense_alg2 import agg_rows
+    off, idx = _rev_lists(o.B[p])
+    W = o.W
+    zz = z.astype(np.float64)
+    for j in slots:
+        cand = idx[off[j]:off[j + 1]]
+        src = p ^ g_sw[cand].astype(np.int64)
+        Fc = np.stack([Fo[s_][i] for s_, i in zip(src, cand)]).astype(np.float64)
+        Cc = np.array([CVo[s_][i] for s_, i in zip(src, cand)], dtype=np.float64)
+        Fpj = S["F"][p][j].astype(np.float64)[None, :]
+        allF = np.vstack([Fpj, Fc])
+        g = agg_rows(agg, theta, allF, np.repeat(W[j:j + 1], len(allF), 0), zz)
+        c = np.concatenate([[float(S["CV"][p][j])], Cc]) if p == 0 else np.zeros(len(allF))
+        fs = max(1.0, float(np.max(np.abs(allF))), float(np.max(np.abs(zz))))
+
+        def clearly_less(a, b):
+            bc = 1e-6 * max(1.0, abs(c[a]), abs(c[b]))
+            bg = 2e-6 * (max(abs(g[a]), abs(g[b])) + fs)
+            if c[a] < c[b] - bc:
+                return True
+            return abs(c[a] - c[b]) <= bc and g[a] < g[b] - bg
+
+        w = int(g_win[j])
+        if w < 0:
+            assert not any(clearly_less(q, 0) for q in range(1, len(allF))), ("kept parent", p, j)
+        else:
+            q = 1 + int(np.nonzero(cand == w)[0][0])
+            assert not clearly_less(0, q), ("winner worse than parent", p, j, w)
+            assert not any(clearly_less(r, q) for r in range(1, len(allF)) if r != q), (
+                "winner not minimal", p, j, w)
+
+
+def _tf_check(gp, o, S, dbg, label, stats):
+    """Checks of one teacher-forced generation (see _teacher_forced)."""
+    N = o.N
+    Xo = [gp.read("XOFF", p) for p in range(2)]
+    Fo = [gp.read("FOFF", p) for p in range(2)]
+    CVo = [gp.read("CVOFF", p) for p in range(2)]
+    _diag(label, S=S, Xo=Xo, Fo=Fo, CVo=CVo, dbg=dbg, ok=all(
+        _err(a[p], dbg[k][p]) <= TOL for a, k in ((Xo, "Xo"), (Fo, "Fo"), (CVo, "CVo"))
+        for p in range(2)))
+    for p in range(2):
+        assert np.array_equal(gp.read("MATE", p), dbg["mate"][p]), (label, "mate", p)
+        assert _err(Xo[p], dbg["Xo"][p]) <= TOL, (label, "Xo", p)
+        assert _err(Fo[p], dbg["Fo"][p]) <= TOL, (label, "Fo", p)
+        assert _err(CVo[p], dbg["CVo"][p]) <= TOL, (label, "CVo", p)
+    z = gp.read("Z")
+    assert _err(z, o.z) <= TOL, (label, "z")
+    allF = np.concatenate([S["z"][None, :], Fo[0], Fo[1]])
+    assert np.array_equal(z, np.nanmin(allF, axis=0)), (label, "z is the FP32 minimum")
+    # stage 2: selection on the GPU's inputs, decisions in FP32
+    zeros = [np.zeros(N), np.zeros(N)]
+    sw, swr, win, winr = o.select(S["X"], S["F"], S["CV"], zeros, np.concatenate(Xo),
+                                  np.concatenate(Fo), np.concatenate(CVo), np.zeros(2 * N),
+                                  z.astype(np.float64), f32=True)
+    for p in range(2):
+        g_sw = gp.read("OP1", p)
+        g_win = gp.read("WIN", p)
+        r = swr[p].astype(bool)
+        assert np.array_equal(g_sw[r], sw[p][r]), (label, "op1 fp32", p)
+        wr = winr[p].astype(bool)
+        bad = np.nonzero(g_win[wr] != win[p][wr])[0]
+        assert bad.size == 0, (label, "win fp32", p, np.nonzero(wr)[0][bad[:5]])
+        # FP64 decisions marked robust agree as well
+        wr64 = dbg["win_rob"][p].astype(bool)
+        bad64 = np.nonzero(wr64 & (g_win != dbg["win"][p]))[0]
+        if bad64.size:
+            _diag_decision(label, p, bad64, S, Xo, Fo, CVo, z, g_win, g_sw, dbg)
+        assert bad64.size == 0, (label, "win fp64", p, bad64[:5], g_win[bad64[:5]],
+                                 dbg["win"][p][bad64[:5]])
+        # every decision is a valid one, and replaced rows are exact copies
+        X, F, CV = gp.read("X", p), gp.read("F", p), gp.read("CV", p)
+        B = o.B[p]
+        for j in range(N):
+            i = g_win[j]
+            if i < 0:
+                assert np.array_equal(X[j], S["X"][p][j]), (label, "kept row", p, j)
+                continue
+            assert j in B[i], (label, "invalid winner", p, j, i)
+            sp = p ^ int(g_sw[i])
+            assert np.array_equal(X[j], Xo[sp][i]), (label, "copied row", p, j)
+            assert np.array_equal(F[j], Fo[sp][i]) and CV[j] == CVo[sp][i], (label, "copied F/CV")
+        # the slots the FP32 comparison cannot check still hold a valid outcome
+        _unchecked_valid(p, np.nonzero(~wr)[0], S, Fo, CVo, z, g_win, g_sw, o,
+                         o.dv["agg"], o.dv["theta"])
+        # F and CV are functions of x alone: bitwise-equal rows evaluate equal
+        allx = np.concatenate([X, Xo[0], Xo[1]])
+        allfc = np.concatenate([np.column_stack([F, CV]), np.column_stack([Fo[0], CVo[0]]),
+                                np.column_stack([Fo[1], CVo[1]])])
+        _, inv = np.unique(allx.view(np.dtype((np.void, allx.dtype.itemsize * allx.shape[1]))),
+                           return_inverse=True)
+        first = {}
+        for r_, key_ in enumerate(inv.ravel()):
+            if key_ in first:
+                assert np.array_equal(allfc[r_], allfc[first[key_]]), (label, "F of equal x", p)
+            else:
+                first[key_] = r_
+        stats["amb32"] += int((~wr).sum())
+        stats["amb64"] += int((~wr64).sum())
+        stats["slots"] += N
+
+
+def _tf_summary(label, stats):
+    frac = stats["amb32"] / max(1, stats["slots"])
+    rob64 = 1.0 - stats["amb64"] / max(1, stats["slots"])
+    _log("%s: unchecked slots %d of %d in FP32 (%.4f%%); FP64-robust share %.2f%%"
+         % (label, stats["amb32"], stats["slots"], 100 * frac, 100 * rob64))
+    return frac, rob64
+
+
+def _teacher_forced(gp, o, gens, label, rob64_floor=0.5):
     """Run `gens` teacher-forced generations, each checked in two stages.
 
     Stage 1 (reproduction + evaluation): the FP64 oracle recomputes generation
@@ -113,81 +241,21 @@ def _teacher_forced(gp, o, gens, label):
     FP32 parents, offspring and ideal point with its aggregation evaluated in
     FP32, the kernel's precision (the paper fixes none); OP1 switches and
     winners must be identical except where the two FP32 evaluations could
-    round a near-tie differently, and each replaced row must be a bitwise copy
-    of the winning offspring row. Returns the share of stage-2 slots that were
-    not checkable."""
-    amb32, amb64, slots = 0, 0, 0
+    round a near-tie differently, each replaced row must be a bitwise copy of
+    the winning offspring row, and every slot left unchecked must still hold
+    a valid outcome within the FP32 bound. Asserts that the share of slots
+    whose FP64 decision is robust (and so compared with the FP64 oracle's own
+    decision) is at least rob64_floor, and returns the share of stage-2 slots
+    that were not checkable."""
+    stats = {"amb32": 0, "amb64": 0, "slots": 0}
     for _ in range(gens):
         S = gp.state()
         o.set_state(S["X"][0], S["X"][1], S["z"].astype(np.float64), gen=S["gen"])
         gp.step(1)
         dbg = o.step(debug=True)
-        N = o.N
-        Xo = [gp.read("XOFF", p) for p in range(2)]
-        Fo = [gp.read("FOFF", p) for p in range(2)]
-        CVo = [gp.read("CVOFF", p) for p in range(2)]
-        _diag(label, S=S, Xo=Xo, Fo=Fo, CVo=CVo, dbg=dbg, ok=all(
-            _err(a[p], dbg[k][p]) <= TOL for a, k in ((Xo, "Xo"), (Fo, "Fo"), (CVo, "CVo"))
-            for p in range(2)))
-        for p in range(2):
-            assert np.array_equal(gp.read("MATE", p), dbg["mate"][p]), (label, "mate", p)
-            assert _err(Xo[p], dbg["Xo"][p]) <= TOL, (label, "Xo", p)
-            assert _err(Fo[p], dbg["Fo"][p]) <= TOL, (label, "Fo", p)
-            assert _err(CVo[p], dbg["CVo"][p]) <= TOL, (label, "CVo", p)
-        z = gp.read("Z")
-        assert _err(z, o.z) <= TOL, (label, "z")
-        allF = np.concatenate([S["z"][None, :], Fo[0], Fo[1]])
-        assert np.array_equal(z, np.nanmin(allF, axis=0)), (label, "z is the FP32 minimum")
-        # stage 2: selection on the GPU's inputs, decisions in FP32
-        zeros = [np.zeros(N), np.zeros(N)]
-        sw, swr, win, winr = o.select(S["X"], S["F"], S["CV"], zeros, np.concatenate(Xo),
-                                      np.concatenate(Fo), np.concatenate(CVo), np.zeros(2 * N),
-                                      z.astype(np.float64), f32=True)
-        for p in range(2):
-            g_sw = gp.read("OP1", p)
-            g_win = gp.read("WIN", p)
-            r = swr[p].astype(bool)
-            assert np.array_equal(g_sw[r], sw[p][r]), (label, "op1 fp32", p)
-            wr = winr[p].astype(bool)
-            bad = np.nonzero(g_win[wr] != win[p][wr])[0]
-            assert bad.size == 0, (label, "win fp32", p, np.nonzero(wr)[0][bad[:5]])
-            # FP64 decisions marked robust agree as well
-            wr64 = dbg["win_rob"][p].astype(bool)
-            bad64 = np.nonzero(wr64 & (g_win != dbg["win"][p]))[0]
-            if bad64.size:
-                _diag_decision(label, p, bad64, S, Xo, Fo, CVo, z, g_win, g_sw, dbg)
-            assert bad64.size == 0, (label, "win fp64", p, bad64[:5], g_win[bad64[:5]],
-                                     dbg["win"][p][bad64[:5]])
-            # every decision is a valid one, and replaced rows are exact copies
-            X, F, CV = gp.read("X", p), gp.read("F", p), gp.read("CV", p)
-            B = o.B[p]
-            for j in range(N):
-                i = g_win[j]
-                if i < 0:
-                    assert np.array_equal(X[j], S["X"][p][j]), (label, "kept row", p, j)
-                    continue
-                assert j in B[i], (label, "invalid winner", p, j, i)
-                sp = p ^ int(g_sw[i])
-                assert np.array_equal(X[j], Xo[sp][i]), (label, "copied row", p, j)
-                assert np.array_equal(F[j], Fo[sp][i]) and CV[j] == CVo[sp][i], (label, "copied F/CV")
-            # F and CV are functions of x alone: bitwise-equal rows evaluate equal
-            allx = np.concatenate([X, Xo[0], Xo[1]])
-            allfc = np.concatenate([np.column_stack([F, CV]), np.column_stack([Fo[0], CVo[0]]),
-                                    np.column_stack([Fo[1], CVo[1]])])
-            _, inv = np.unique(allx.view(np.dtype((np.void, allx.dtype.itemsize * allx.shape[1]))),
-                               return_inverse=True)
-            first = {}
-            for r_, key_ in enumerate(inv.ravel()):
-                if key_ in first:
-                    assert np.array_equal(allfc[r_], allfc[first[key_]]), (label, "F of equal x", p)
-                else:
-                    first[key_] = r_
-            amb32 += int((~wr).sum())
-            amb64 += int((~wr64).sum())
-            slots += N
-    frac = amb32 / max(1, slots)
-    _log("%s: unchecked slots %d of %d in FP32 (%.4f%%); FP64-robust share %.2f%%"
-         % (label, amb32, slots, 100 * frac, 100 * (1 - amb64 / max(1, slots))))
+        _tf_check(gp, o, S, dbg, label, stats)
+    frac, rob64 = _tf_summary(label, stats)
+    assert rob64 >= rob64_floor, (label, "FP64-robust share", rob64, rob64_floor)
     return frac
 
 
@@ -330,7 +398,7 @@ def test_generation_odd_shapes(G):
     gp, o = _pair(prob, cfg)
     try:
         gp.step(2)
-        _teacher_forced(gp, o, 2, "unit neighbourhoods")
+        assert _teacher_forced(gp, o, 2, "unit neighbourhoods") < 0.005
     finally:
         gp.close()
     prob = ci.make_problem(ci.FAMILY_CURVE, 2, 7, 1, False, False, 4)
@@ -338,7 +406,7 @@ def test_generation_odd_shapes(G):
     gp, o = _pair(prob, cfg)
     try:
         gp.step(2)
-        _teacher_forced(gp, o, 1, "full neighbourhood")
+        assert _teacher_forced(gp, o, 1, "full neighbourhood") < 0.005
     finally:
         gp.close()
 
@@ -358,7 +426,7 @@ def test_generation_smallest_shapes(G, family, m, d, n_req, t1, t2):
     try:
         assert gp.n == n_req
         gp.step(3)
-        _teacher_forced(gp, o, 3, "smallest m=%d d=%d" % (m, d))
+        assert _teacher_forced(gp, o, 3, "smallest m=%d d=%d" % (m, d)) < 0.005
         assert np.all(gp.read("CV", 0) == 0) and np.all(gp.read("CV", 1) == 0)
     finally:
         gp.close()
@@ -378,7 +446,7 @@ def test_generation_operator_parameters(G, pm):
     gp, o = _pair(prob, cfg)
     try:
         gp.step(2)
-        _teacher_forced(gp, o, 2, "operators pm=%g" % pm)
+        assert _teacher_forced(gp, o, 2, "operators pm=%g" % pm) < 0.005
         X = gp.read("X", 0)
         assert np.all(X >= lb.astype(np.float32)) and np.all(X <= ub.astype(np.float32))
     finally:
@@ -562,3 +630,49 @@ def test_generation_nan_constraint_constant(G):
         assert np.all(np.isfinite(gp.read("CV", 0)))
     finally:
         gp.close()
+
+
+def test_pool_teacher_forced(G):
+    """Instances advanced by batched pool generations (one launch per phase for
+    all of them) checked against the FP64 oracle exactly as plain instances
+    are: the oracle runs each instance's generation from the pool's pre-state.
+    The mix covers both record widths' batched kernels (m = 2, 3 and a
+    five-objective layered set), both aggregations, DE, the equality, ragged
+    rows and tiles."""
+    import paper_2509_19821_amd as g
+    mix = [("pool small", ci.workload_small(8)[:2]),
+           ("pool sphere DE", (ci.make_problem(ci.FAMILY_SPHERE, 3, 30, 3, True, False, 12),
+                               ci.method_config(400, 10, 12, op=1))),
+           ("pool curve tche d23", (ci.make_problem(ci.FAMILY_CURVE, 2, 23, 4, False, False, 13),
+                                    ci.method_config(700, 10, 13, agg=1))),
+           ("pool d100 equality", (ci.make_problem(ci.FAMILY_SPHERE, 3, 100, 4, False, True, 14,
+                                                   eq_tol=1e-4), ci.method_config(1500, 32, 14))),
+           ("pool m5 layers", (ci.make_problem(ci.FAMILY_SPHERE, 5, 30, 3, True, False, 15),
+                               ci.method_config(2, 12, 15, h_outer=8, h_inner=5)))]
+    pool = g.Pool(8 << 30)
+    try:
+        pairs = []
+        for label, (prob, cfg) in mix:
+            s = pool.admit(prob, cfg, record=True)
+            o = core.Oracle(prob, cfg, init=False)
+            pairs.append((label, pool.instance(s), o, {"amb32": 0, "amb64": 0, "slots": 0}))
+            assert pairs[-1][1].n == o.N
+        pool.step(3)
+        pool.sync()
+        for _ in range(2):
+            pre = []
+            for label, gp, o, _ in pairs:
+                S = gp.state()
+                o.set_state(S["X"][0], S["X"][1], S["z"].astype(np.float64), gen=S["gen"])
+                pre.append(S)
+            pool.step(1)
+            pool.sync()
+            for (label, gp, o, stats), S in zip(pairs, pre):
+                dbg = o.step(debug=True)
+                _tf_check(gp, o, S, dbg, label, stats)
+        for label, gp, o, stats in pairs:
+            frac, rob64 = _tf_summary(label, stats)
+            assert frac < 0.005, (label, frac)
+            assert rob64 >= 0.5, (label, rob64)
+    finally:
+        pool.close()

@@ -37,6 +37,18 @@ def test_front_two_objective_sweep():
     assert np.array_equal(keep, want)
 
 
+@pytest.mark.parametrize("grid", [True, False])
+def test_two_objective_filter_against_dominance_matrix(grid):
+    """The sweep filter used for two-objective reference fronts keeps exactly
+    the rows no other row dominates (duplicates and equal-f1 groups included)."""
+    rng = np.random.default_rng(11 if grid else 12)
+    for trial in range(60):
+        n = int(rng.integers(1, 400))
+        F = (rng.integers(0, 9, (n, 2)) / 8.0) if grid else rng.uniform(0, 1, (n, 2))
+        want = _nd_matrix(F, np.zeros(n))
+        assert np.array_equal(metrics.nd_mask_2d(F), want), trial
+
+
 def test_front_keeps_duplicates_and_drops_infeasible():
     F = np.array([[0.1, 0.9], [0.1, 0.9], [0.5, 0.5], [0.05, 0.05]])
     CV = np.array([0.0, 0.0, 0.0, 0.3])

@@ -1,0 +1,444 @@
+"""Pin of the oracle's robustness classifier (reading R24) and of its FP32
+decision mode, against perturbations of the arithmetic it claims to cover.
+
+The oracle marks each OP1 switch (Alg. 2 OP1, Eq. (11)) and each slot's
+OP2/OP3 outcome (Eqs. (12)-(13), with the feasibility priority rule of
+Eq. (8)) as robust or not. "Robust in FP64" claims: a device that evaluates
+the same generation in FP32 takes the same decision. "Robust in FP32 mode"
+claims: any FP32 evaluation of the aggregation on the given FP32 operands
+(fused or unfused multiply-adds, either summation order, the unit direction
+rounded once or computed in FP32) takes the same decision.
+
+This test re-derives every decision with a plain pull written here from
+Alg. 2 (lexicographic minimum over the reverse neighbourhood, first index on
+ties), in perturbed FP32 worlds:
+  - offspring decision vectors rounded to FP32 and moved by a few ulps (a
+    function of the value for SBX, so exact copies stay copies; per element
+    for DE, whose offspring are recomputed in every variable);
+  - F and CV either rounded from FP64 or evaluated in FP32 from the FP32
+    vectors (own evaluation of the two families, sums in either order);
+  - the ideal point as the FP32 minimum;
+  - the aggregation in FP32 with and without fused multiply-adds, sums
+    forward and backward, the unit direction rounded once or built in FP32.
+Every decision the oracle marks robust must come out the same in every
+world; the worlds must also flip some unmarked decisions, or they would not
+test anything. The states are real generations (evolved populations with
+copies, forced CV ties, equality-boundary rows, DE's exact FP64 ties at
+F = 1/2)."""
+import numpy as np
+import pytest
+
+import cmop_inputs as ci
+from oracle import core
+
+F32 = np.float32
+
+
+# --------------------------------------------------------------------------
+# FP32 worlds
+# --------------------------------------------------------------------------
+
+def _ulp_shift(x32, k):
+    """x moved by k ulps (k an int array), within [0, inf) bit patterns."""
+    b = x32.view(np.int32).astype(np.int64) + k
+    b = np.clip(b, 0, 0x7F7FFFFF)
+    return b.astype(np.int32).view(np.float32)
+
+
+def _perturb_x(X64, lb, ub, mode, amp, rng, exact):
+    """FP32 copy of offspring vectors moved by up to `amp` ulps. Values at a
+    bound stay exact (the clip is exact in both precisions), and so do the
+    elements flagged in `exact`: values copied from a parent (an uncrossed SBX
+    variable, or a crossed one whose parents agree; DE's own variable when the
+    two picks agree), which FP32 reproduces bit for bit."""
+    x = X64.astype(F32)
+    if amp == 0:
+        return x
+    if mode == "value":  # a function of the value: equal inputs stay equal
+        h = x.view(np.uint32).astype(np.uint64)
+        h = (h * np.uint64(0x9E3779B1)) & np.uint64(0xFFFFFFFF)
+        k = (h % np.uint64(2 * amp + 1)).astype(np.int64) - amp
+    else:
+        k = rng.integers(-amp, amp + 1, size=x.shape)
+    neg = x < 0
+    y = np.where(neg, -_ulp_shift(-x, k), _ulp_shift(np.abs(x), k))
+    lo, hi = lb.astype(F32), ub.astype(F32)
+    y = np.clip(y, lo, hi)
+    at_bound = (x == lo) | (x == hi) | exact
+    return np.where(at_bound, x, y).astype(F32)
+
+
+def _fsum(terms, reverse):
+    """FP32 sum of the columns of terms (n x k) in one order."""
+    cols = list(range(terms.shape[1]))
+    if reverse:
+        cols = cols[::-1]
+    s = np.zeros(terms.shape[0], dtype=F32)
+    for c in cols:
+        s = (s + terms[:, c]).astype(F32)
+    return s
+
+
+def _eval32(prob, X, reverse):
+    """Objectives and CV (Eqs. (1)-(3)) of FP32 rows X in FP32 arithmetic."""
+    m, d = prob["m"], prob["d"]
+    X = X.astype(F32)
+    n = X.shape[0]
+    F = np.zeros((n, m), dtype=F32)
+    if prob["family"] == ci.FAMILY_CURVE:
+        s = _fsum(X[:, 1:], reverse)
+        g = (F32(1.0) + F32(9.0 / (d - 1)) * s).astype(F32)
+        F[:, 0] = X[:, 0]
+        F[:, 1] = g * (F32(1.0) - np.sqrt(X[:, 0] / g))
+    else:
+        dx = (X[:, m - 1:] - F32(0.5)).astype(F32)
+        r = (F32(1.0) + _fsum((dx * dx).astype(F32), reverse)).astype(F32)
+        th = (F32(np.pi / 2) * X[:, :m - 1]).astype(F32)
+        c, s_ = np.cos(th).astype(F32), np.sin(th).astype(F32)
+        for k in range(m):
+            v = r.copy()
+            for j in range(m - 1 - k):
+                v = (v * c[:, j]).astype(F32)
+            if k > 0:
+                v = (v * s_[:, m - 1 - k]).astype(F32)
+            F[:, k] = v
+    cv = np.zeros(n, dtype=F32)
+    cen = np.asarray(prob["ring_center"]).reshape(-1, m).astype(F32)
+    r2 = (np.asarray(prob["ring_radius"]).reshape(-1) ** 2).astype(F32)
+    for a, rr in zip(cen, r2):
+        q = _fsum(((F - a) * (F - a)).astype(F32), reverse)
+        cv = (cv + np.maximum(rr - q, F32(0))).astype(F32)
+    if prob["has_sum_lower"]:
+        cv = (cv + np.maximum(F32(prob["sum_lower"]) - _fsum(F, reverse), F32(0))).astype(F32)
+    if prob["n_eq"]:
+        h = (np.abs((X[:, 0] + X[:, 1]).astype(F32) - F32(1.0)) - F32(prob["eq_tol"])).astype(F32)
+        cv = (cv + np.maximum(h, F32(0))).astype(F32)
+    return F, cv
+
+
+def _fma(a, b, c):
+    """FP32 fused multiply-add: the exact product in FP64, one rounding."""
+    return (a.astype(np.float64) * b.astype(np.float64) + c.astype(np.float64)).astype(F32)
+
+
+def _agg32(kind, theta, F, W, z, fma, reverse, unit32):
+    """Aggregation of FP32 rows F at weights W (FP64 reference vectors) in FP32."""
+    F = F.astype(F32)
+    z = z.astype(F32)
+    diff = (F - z).astype(F32)
+    m = F.shape[1]
+    if kind == 1:
+        g = np.max((W.astype(F32) * np.abs(diff)).astype(F32), axis=1)
+        return np.where(np.isnan(g), np.inf, g.astype(np.float64))
+    if unit32:
+        W32 = W.astype(F32)
+        nrm = np.sqrt(_fsum((W32 * W32).astype(F32), False)).astype(F32)
+        u = (W32 / nrm[:, None]).astype(F32)
+    else:
+        u = (W / np.linalg.norm(W, axis=1, keepdims=True)).astype(F32)
+    order = range(m - 1, -1, -1) if reverse else range(m)
+    dot = np.zeros(F.shape[0], dtype=F32)
+    for k in order:
+        dot = _fma(diff[:, k], u[:, k], dot) if fma else (dot + (diff[:, k] * u[:, k]).astype(F32)).astype(F32)
+    d1 = np.abs(dot)
+    d2 = np.zeros(F.shape[0], dtype=F32)
+    for k in order:
+        e = (diff[:, k] - (d1 * u[:, k]).astype(F32)).astype(F32)
+        d2 = _fma(e, e, d2) if fma else (d2 + (e * e).astype(F32)).astype(F32)
+    g = (d1 + (F32(theta) * np.sqrt(d2)).astype(F32)).astype(F32)
+    return np.where(np.isnan(g), np.inf, g.astype(np.float64))
+
+
+def _inf(a):
+    a = np.asarray(a, dtype=np.float64).copy()
+    a[np.isnan(a)] = np.inf
+    return a
+
+
+def _decide(o, cfg, F, CV, Fo, CVo, z, agg_fn):
+    """OP1 switches and OP2/OP3 winners by a plain pull (Alg. 2): F[p], CV[p]
+    parents; Fo[p], CVo[p] offspring of population p; agg_fn(F, W, z) -> g."""
+    N, W, B = o.N, o.W, o.B
+    rule = cfg.get("op1_rule", 0)
+    g1 = agg_fn(Fo[0], W, z)
+    g2 = agg_fn(Fo[1], W, z)
+    c1, c2 = _inf(CVo[0]), _inf(CVo[1])
+    if rule == 0:
+        s1 = (c2 < c1) | ((c2 == c1) & (g2 < g1))
+    else:
+        f1, f2 = c1 == 0, c2 == 0
+        s1 = np.where(f1 != f2, f2, g2 < g1)
+    s2 = g1 < g2
+    sw = np.stack([s1, s2]).astype(np.uint8)
+    newF = [np.where(s1[:, None], Fo[1], Fo[0]), np.where(s2[:, None], Fo[0], Fo[1])]
+    newCV = [np.where(s1, c2, c1), np.where(s2, c1, c2)]
+    win = np.full((2, N), -1, dtype=np.int32)
+    for p in range(2):
+        t = B[p].shape[1]
+        rev = [[] for _ in range(N)]
+        for i in range(N):
+            for j in B[p][i]:
+                rev[j].append(i)
+        for j in range(N):
+            cand = np.array(sorted(rev[j]), dtype=np.int64)
+            wj = np.repeat(W[j:j + 1], len(cand) + 1, 0)
+            Fs = np.vstack([F[p][j:j + 1], newF[p][cand]])
+            gs = agg_fn(Fs, wj, z)
+            if p == 0:
+                cs = np.concatenate([[_inf(CV[0][j:j + 1])[0]], newCV[0][cand]])
+            else:
+                cs = np.zeros(len(cand) + 1)
+            best_c, best_g, bi = cs[0], gs[0], -1
+            for q, i in enumerate(cand, start=1):
+                if cs[q] < best_c or (cs[q] == best_c and gs[q] < best_g):
+                    best_c, best_g, bi = cs[q], gs[q], int(i)
+            win[p, j] = bi
+        del t
+    return sw, win
+
+
+AGG_VARIANTS = [dict(fma=f, reverse=r, unit32=u) for f in (False, True) for r in (False, True)
+                for u in (False, True)]
+
+
+def _states(prob, cfg, warm, gens, rng, eq_edge=False):
+    """Teacher-forced states: the oracle evolved `warm` generations, then each
+    of `gens` generations is started from FP32-rounded parents and an FP32 ideal
+    point (as the device holds them)."""
+    o = core.Oracle(prob, cfg)
+    o.run(warm)
+    out = []
+    for _ in range(gens):
+        X = [o.X[p].astype(F32) for p in range(2)]
+        if eq_edge:  # rows on the equality's tolerance boundary, and swapped pairs
+            tol = prob["eq_tol"]
+            for p in range(2):
+                rows = rng.choice(o.N, size=o.N // 8, replace=False)
+                for q, i in enumerate(rows):
+                    a = F32(rng.uniform(0.1, 0.9))
+                    off = [tol * (1 + 1e-3), tol * (1 - 1e-3), -tol * (1 + 1e-3), 0.0, tol * 3][q % 5]
+                    X[p][i, 0] = a
+                    X[p][i, 1] = F32(1.0 - a + off)
+                    if q % 7 == 0:
+                        X[p][i, 0], X[p][i, 1] = X[p][i, 1], X[p][i, 0]
+        zpre = np.minimum(o.F[0].min(0), o.F[1].min(0)).astype(F32)
+        o.set_state(X[0], X[1], zpre.astype(np.float64), gen=o.gen)
+        dbg = o.step(debug=True)
+        out.append((X, zpre, dbg, o))
+        o = _clone(o, prob, cfg)
+    return out
+
+
+def _clone(o, prob, cfg):
+    c = core.Oracle(prob, cfg, init=False)
+    c.set_state(o.X[0], o.X[1], o.z, gen=o.gen)
+    return c
+
+
+def _check_world(o, prob, cfg, X, zpre, dbg, rng, counts):
+    kind, theta = int(cfg["agg"]), float(cfg["theta"])
+    N = o.N
+    de = int(cfg.get("op", 0)) == 1
+    lb, ub = np.asarray(prob["lb"]), np.asarray(prob["ub"])
+    worlds = []
+    for amp in (0, 4, 16):
+        for how in ("round", "eval_fwd", "eval_rev"):
+            worlds.append((amp, how))
+    for amp, how in worlds:
+        if how == "round" and amp:
+            continue
+        Xo = [_perturb_x(dbg["Xo"][p], lb, ub, "random" if de else "value", amp, rng,
+                         _copied(dbg["Xo"][p], X[p], dbg["mate"][p], de, dbg.get("src", [None, None])[p]))
+              for p in range(2)]
+        if how == "round":
+            Fo = [dbg["Fo"][p].astype(F32) for p in range(2)]
+            CVo = [dbg["CVo"][p].astype(F32) for p in range(2)]
+            Fp = [o_F.astype(F32) for o_F in _parent_f64(o, prob, X)[0]]
+            CVp = [c.astype(F32) for c in _parent_f64(o, prob, X)[1]]
+        else:
+            rev = how == "eval_rev"
+            FC = [_eval32(prob, Xo[p], rev) for p in range(2)]
+            Fo = [FC[p][0] for p in range(2)]
+            CVo = [FC[p][1] for p in range(2)]
+            PC = [_eval32(prob, X[p], rev) for p in range(2)]
+            Fp = [PC[p][0] for p in range(2)]
+            CVp = [PC[p][1] for p in range(2)]
+        allF = np.vstack([zpre[None, :], Fo[0], Fo[1]])
+        z = np.nanmin(allF, axis=0).astype(F32)
+        for av in AGG_VARIANTS[::3] if amp else AGG_VARIANTS:
+            fn = lambda F_, W_, z_, av=av: _agg32(kind, theta, F_, W_, z_, **av)  # noqa: E731
+            sw, win = _decide(o, cfg, Fp, CVp, Fo, CVo, z, fn)
+            r = dbg["op1_rob"].astype(bool)
+            bad = np.nonzero(r & (sw != dbg["op1"]))
+            assert bad[0].size == 0, ("op1 robust but flipped", amp, how, av, bad)
+            wr = dbg["win_rob"].astype(bool)
+            badw = np.nonzero(wr & (win != dbg["win"]))
+            assert badw[0].size == 0, ("winner robust but changed", amp, how, av, badw,
+                                       win[badw][:4], dbg["win"][badw][:4])
+            counts["robust"] += int(wr.sum()) + int(r.sum())
+            counts["total"] += 2 * wr.size
+            counts["flipped_unmarked"] += int((~wr & (win != dbg["win"])).sum() +
+                                              (~r & (sw != dbg["op1"])).sum())
+        # the FP32 decision mode on this world's FP32 values
+        _check_f32_mode(o, cfg, X, Xo, Fp, CVp, Fo, CVo, z, counts)
+        if amp == 0 and how == "eval_fwd":
+            # FP32 near ties: offspring whose FP32 objectives are a neighbouring
+            # parent's with one objective moved by one ulp
+            Fo2 = [f.copy() for f in Fo]
+            CVo2 = [c.copy() for c in CVo]
+            for p in range(2):
+                for i in rng.choice(N, size=N // 5, replace=False):
+                    j = int(o.B[p][i][rng.integers(o.B[p].shape[1])])
+                    f = Fp[p][j].copy()
+                    k = int(rng.integers(o.m))
+                    f[k] = np.nextafter(f[k], F32(np.inf) if rng.random() < 0.5 else F32(-np.inf))
+                    Fo2[p][i] = f
+                    CVo2[p][i] = CVp[p][j]
+            _check_f32_mode(o, cfg, X, Xo, Fp, CVp, Fo2, CVo2, z, counts)
+
+
+def _check_f32_mode(o, cfg, X, Xo, Fp, CVp, Fo, CVo, z, counts):
+    """The oracle's FP32 decision mode on these FP32 values: every decision it
+    marks robust holds under every FP32 evaluation of the aggregation."""
+    kind, theta = int(cfg["agg"]), float(cfg["theta"])
+    N = o.N
+    zeros = [np.zeros(N), np.zeros(N)]
+    sw32, swr32, win32, winr32 = o.select(
+        [X[0].astype(np.float64), X[1].astype(np.float64)],
+        [Fp[0].astype(np.float64), Fp[1].astype(np.float64)],
+        [CVp[0].astype(np.float64), CVp[1].astype(np.float64)], zeros,
+        np.concatenate([Xo[0], Xo[1]]).astype(np.float64),
+        np.concatenate([Fo[0], Fo[1]]).astype(np.float64),
+        np.concatenate([CVo[0], CVo[1]]).astype(np.float64), np.zeros(2 * N),
+        z.astype(np.float64), f32=True)
+    for av in AGG_VARIANTS:
+        fn = lambda F_, W_, z_, av=av: _agg32(kind, theta, F_, W_, z_, **av)  # noqa: E731
+        sw, win = _decide(o, cfg, Fp, CVp, Fo, CVo, z, fn)
+        r = swr32.astype(bool)
+        assert not np.any(r & (sw != sw32)), ("fp32 op1 robust but flipped", av)
+        wr = winr32.astype(bool)
+        badw = np.nonzero(wr & (win != win32))
+        assert badw[0].size == 0, ("fp32 winner robust but changed", av, badw)
+        counts["robust32"] += int(wr.sum())
+        counts["total32"] += wr.size
+        counts["flipped_unmarked32"] += int((~wr & (win != win32)).sum() + (~r & (sw != sw32)).sum())
+
+
+def _copied(Xo, X, mate, de, src=None):
+    """Offspring elements equal to a parent's element: the two mating picks'
+    for SBX (which copies or averages equal values), the own row's for DE;
+    for planted rows (src >= 0), the elements whose FP32 rounding equals the
+    source parent's (a device would hold an exact copy there)."""
+    X = X.astype(np.float64)
+    if de:
+        out = Xo == X
+    else:
+        out = (Xo == X[mate[:, 0]]) | (Xo == X[mate[:, 1]])
+    if src is not None:
+        rows = np.nonzero(src >= 0)[0]
+        out[rows] = Xo[rows].astype(F32) == X[src[rows]].astype(F32)
+    return out
+
+
+def _planted(o, prob, X, zpre, dbg, rng, frac=0.2):
+    """The same generation with a share of the offspring replaced by near
+    copies of a neighbouring parent: one variable moved by about 1e-12
+    relative, below half an FP32 ulp. In FP64 such an offspring is strictly
+    better or worse than its source; in FP32 it is an exact copy and ties.
+    Decisions and their robustness come from the oracle's FP64 selection."""
+    N, d, m = o.N, o.d, o.m
+    Xo = dbg["Xo"].copy()
+    src = [np.full(N, -1, dtype=np.int64) for _ in range(2)]
+    lb, ub = np.asarray(prob["lb"]), np.asarray(prob["ub"])
+    for p in range(2):
+        for i in rng.choice(N, size=max(1, int(frac * N)), replace=False):
+            j = int(o.B[p][i][rng.integers(o.B[p].shape[1])])
+            y = X[p][j].astype(np.float64).copy()
+            l = int(rng.integers(d))
+            step = max(abs(y[l]), 1e-3) * 2.0 ** -40
+            y[l] = min(ub[l], max(lb[l], y[l] + (step if rng.random() < 0.5 else -step)))
+            Xo[p][i] = y
+            src[p][i] = j
+    Fo, CVo, CMo = core.evaluate(prob, Xo.reshape(-1, d))
+    Xp = [X[p].astype(np.float64) for p in range(2)]
+    FP = [core.evaluate(prob, Xp[p]) for p in range(2)]
+    z = np.fmin(zpre.astype(np.float64), np.nanmin(Fo, axis=0))
+    sw, swr, win, winr = o.select(Xp, [FP[0][0], FP[1][0]], [FP[0][1], FP[1][1]],
+                                  [FP[0][2], FP[1][2]], Xo.reshape(-1, d), Fo, CVo, CMo, z)
+    return {"Xo": Xo, "Fo": Fo.reshape(2, N, m), "CVo": CVo.reshape(2, N), "op1": sw,
+            "op1_rob": swr, "win": win, "win_rob": winr, "mate": dbg["mate"], "src": src}
+
+
+def _parent_f64(o, prob, X):
+    F, CV = [], []
+    for p in range(2):
+        f, cv, _ = core.evaluate(prob, X[p].astype(np.float64))
+        F.append(f)
+        CV.append(cv)
+    return F, CV
+
+
+CASES = [
+    # (label, problem, method config, warm generations, generations, eq_edge)
+    ("curve m=2 PBI (converged: copies, CV ties)",
+     lambda: ci.make_problem(ci.FAMILY_CURVE, 2, 10, 2, False, False, 0),
+     lambda: ci.method_config(100, 20, 0), 40, 2, False),
+    ("curve m=2 PBI (early)",
+     lambda: ci.make_problem(ci.FAMILY_CURVE, 2, 10, 2, False, False, 1),
+     lambda: ci.method_config(100, 20, 1), 2, 2, False),
+    ("sphere m=3 PBI rings + linear",
+     lambda: ci.make_problem(ci.FAMILY_SPHERE, 3, 12, 3, True, False, 2),
+     lambda: ci.method_config(120, 10, 2), 15, 2, False),
+    ("sphere m=3 Tchebycheff rings + linear",
+     lambda: ci.make_problem(ci.FAMILY_SPHERE, 3, 12, 3, True, False, 3),
+     lambda: ci.method_config(120, 10, 3, agg=1), 15, 2, False),
+    ("sphere m=3 equality boundary rows (tol 1e-4)",
+     lambda: ci.make_problem(ci.FAMILY_SPHERE, 3, 20, 2, False, True, 4, eq_tol=1e-4),
+     lambda: ci.method_config(120, 10, 4), 10, 2, True),
+    ("curve m=2 DE (F = 1/2 exact ties)",
+     lambda: ci.make_problem(ci.FAMILY_CURVE, 2, 10, 2, False, False, 5),
+     lambda: ci.method_config(100, 20, 5, op=1), 30, 2, False),
+    ("sphere m=3 DE + OP1 feasibility-first",
+     lambda: ci.make_problem(ci.FAMILY_SPHERE, 3, 12, 3, True, False, 6),
+     lambda: ci.method_config(120, 10, 6, op=1, op1_rule=1), 15, 2, False),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_robust_decisions_survive_fp32_worlds(case):
+    label, mkp, mkc, warm, gens, eq_edge = case
+    prob, cfg = mkp(), mkc()
+    rng = np.random.default_rng(abs(hash(label)) % (2**32))
+    counts = dict.fromkeys(["robust", "total", "flipped_unmarked", "robust32", "total32",
+                            "flipped_unmarked32"], 0)
+    for X, zpre, dbg, o in _states(prob, cfg, warm, gens, np.random.default_rng(7), eq_edge):
+        _check_world(o, prob, cfg, X, zpre, dbg, rng, counts)
+    print(label, counts)
+    planted = dict.fromkeys(counts, 0)
+    for X, zpre, dbg, o in _states(prob, cfg, warm, 1, np.random.default_rng(8), eq_edge):
+        _check_world(o, prob, cfg, X, zpre, _planted(o, prob, X, zpre, dbg, rng), rng, planted)
+    print(label, "planted near copies", planted)
+    # the classifier is not vacuous: most decisions are checkable in both modes
+    assert counts["robust"] > 0.5 * counts["total"], counts
+    assert counts["robust32"] > 0.9 * counts["total32"], counts
+
+
+def test_worlds_flip_some_unmarked_decisions():
+    """The perturbed worlds have teeth: on states with planted near copies
+    (ties in FP32, strict in FP64) they change decisions that the classifier
+    leaves unmarked, in both populations and for OP1, so a classifier that
+    marked those robust would fail the test above."""
+    flipped = 0
+    for case in (CASES[0], CASES[2], CASES[5]):
+        label, mkp, mkc, warm, gens, eq_edge = case
+        prob, cfg = mkp(), mkc()
+        counts = dict.fromkeys(["robust", "total", "flipped_unmarked", "robust32", "total32",
+                                "flipped_unmarked32"], 0)
+        rng = np.random.default_rng(3)
+        for X, zpre, dbg, o in _states(prob, cfg, warm, 1, np.random.default_rng(8), eq_edge):
+            _check_world(o, prob, cfg, X, zpre, _planted(o, prob, X, zpre, dbg, rng), rng, counts)
+        assert counts["flipped_unmarked"] > 0, (label, counts)
+        flipped += counts["flipped_unmarked"]
+        if cfg["agg"] == 0:  # PBI: FP32 one-ulp near ties flip under some evaluation
+            assert counts["flipped_unmarked32"] > 0, (label, counts)
+    assert flipped > 0

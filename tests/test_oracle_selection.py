@@ -161,52 +161,6 @@ def test_ideal_point_is_running_minimum():
         assert np.array_equal(o.z, seen)
 
 
-def _dense_f32(F, CV, Fo, CVo, W, z, B, kind):
-    """The dense transcription fed FP32 operands with its aggregation in FP32."""
-    import oracle.dense_alg2 as D
-    orig = D.agg_rows
-
-    def agg32(kind_, theta, Fr, Wr, zr):
-        Fr = np.atleast_2d(Fr).astype(np.float32)
-        Wr = np.atleast_2d(Wr)
-        zr = np.asarray(zr).astype(np.float32)
-        if kind_ == 1:
-            return np.max(Wr.astype(np.float32) * np.abs(Fr - zr), axis=1).astype(np.float64)
-        u = (Wr / np.linalg.norm(Wr, axis=1, keepdims=True)).astype(np.float32)
-        diff = Fr - zr
-        d1 = np.abs(np.sum(diff * u, axis=1, dtype=np.float32))
-        e = diff - d1[:, None] * u
-        d2 = np.sqrt(np.sum(e * e, axis=1, dtype=np.float32))
-        return (d1 + np.float32(theta) * d2).astype(np.float64)
-
-    D.agg_rows = agg32
-    try:
-        return D.dense_select(F, CV, Fo, CVo, W, z, B, kind=kind, theta=5.0)
-    finally:
-        D.agg_rows = orig
-
-
-@pytest.mark.parametrize("m,kind", [(2, 0), (3, 0), (3, 1)])
-def test_fp32_decisions_equal_dense_alg2_in_fp32(m, kind):
-    """The FP32 decision mode (used to compare with the device) takes the same
-    decisions as the dense transcription evaluated in FP32, wherever it marks
-    them robust; its CV comparisons are exact."""
-    o = _tiny_oracle(m, 28 if m == 3 else 24, 8, kind)
-    rng = np.random.default_rng(200 + m + 10 * kind)
-    for trial in range(10):
-        F, CV, CM, Fo, CVo, CMo, z, X, Xo = _random_state(o, rng)
-        F = [f.astype(np.float32).astype(np.float64) for f in F]
-        CV = [c.astype(np.float32).astype(np.float64) for c in CV]
-        Fo = Fo.astype(np.float32).astype(np.float64)
-        CVo = CVo.astype(np.float32).astype(np.float64)
-        z = z.astype(np.float32).astype(np.float64)
-        sw, swr, win, winr = o.select(X, F, CV, CM, Xo, Fo, CVo, CMo, z, f32=True)
-        dsw, dwin = _dense_f32(F, CV, Fo.reshape(2, o.N, m), CVo.reshape(2, o.N), o.W, z, o.B, kind)
-        assert np.array_equal(sw[swr.astype(bool)], dsw[swr.astype(bool)]), trial
-        assert np.array_equal(win[winr.astype(bool)], dwin[winr.astype(bool)]), trial
-        assert winr.mean() > 0.9
-
-
 def _op1_oracle(rule):
     fam = ci.FAMILY_CURVE
     prob = ci.make_problem(fam, 2, 6, 2, False, False, 0)
