@@ -281,6 +281,47 @@ def sweep(g, ci, sizes=(100, 1000, 5000, 10000, 100000, 1000000), gens=50, cpu_g
         print(json.dumps(row), flush=True)
 
 
+def shapes(g, ci, seconds=4.0):
+    """GPU against the CPU oracle at the three plain workload shapes: small
+    (m = 2, d = 10, N = 100), medium (m = 3, d = 30, N = 1,035) and large
+    (m = 3, d = 100, N = 100,128). GPU: generations in graph replay, inputs
+    resident. CPU: the oracle on one thread and with OpenMP on every host core,
+    whole generations for about `seconds` each (at least two). One JSON object
+    per shape on stdout."""
+    from oracle import core
+    all_cores = core.set_threads(0)
+    for name in ("small", "medium", "large"):
+        prob, cfg, _ = ci.WORKLOADS[name](0)
+        gp = g.Gmpea(prob, cfg)
+        gens = 1000 if name != "large" else 200
+        gp.step(5)
+        gp.step(0)
+        gp.sync()
+        t0 = time.perf_counter()
+        gp.step(gens)
+        gp.sync()
+        gpu_us = (time.perf_counter() - t0) / gens * 1e6
+        n = gp.n
+        gp.close()
+        row = {"workload": name, "m": prob["m"], "d": prob["d"], "n": n,
+               "gpu_us_per_gen": round(gpu_us, 2),
+               "gpu_offspring_per_s": round(2 * n / (gpu_us * 1e-6), 1)}
+        for label, threads in (("cpu_1thread", 1), ("cpu_all_cores", all_cores)):
+            core.set_threads(threads)
+            o = core.Oracle(prob, cfg)
+            o.step()
+            k, t0 = 0, time.perf_counter()
+            while k < 2 or time.perf_counter() - t0 < seconds:
+                o.step()
+                k += 1
+            us = (time.perf_counter() - t0) / k * 1e6
+            row[label] = {"us_per_gen": round(us, 1), "threads": int(threads), "generations": k,
+                          "gpu_speedup": round(us / gpu_us, 1)}
+        core.set_threads(all_cores)
+        row["cpu_model"] = _cpu_model()
+        print(json.dumps(row), flush=True)
+
+
 def many(g, ci, gens=50, cpu_gens=3):
     """Many objectives (m = 5 and 8) on the many-objective throughput shape
     (d = 100, two layers of about 1e5 reference vectors, T = 32): GPU time per
@@ -349,6 +390,9 @@ def main():
     ap.add_argument("--sweep", action="store_true",
                     help="print generation time against population size (GPU and CPU oracle) "
                          "instead of the benchmark line")
+    ap.add_argument("--shapes", action="store_true",
+                    help="print GPU against CPU oracle (one thread and all cores) at the small, "
+                         "medium and large workload shapes instead of the benchmark line")
     ap.add_argument("--many", action="store_true",
                     help="print many-objective (m = 5, 8) generation times (GPU and CPU oracle) "
                          "instead of the benchmark line")
@@ -368,6 +412,9 @@ def main():
         return
     if args.many:
         many(g, ci)
+        return
+    if args.shapes:
+        shapes(g, ci)
         return
 
     prob, cfg, K_total = ci.workload_large(0)

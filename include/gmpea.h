@@ -198,6 +198,9 @@ typedef struct {
  * the library was built with; otherwise EUNSUPPORTED (nothing is launched).
  * With m > 3 the F/CV records and W rows take two or three float4 instead of
  * one, and the generation runs kernels instantiated for that m.
+ * Every device buffer the handle will use is allocated here, including the
+ * scratch of gmpea_front and gmpea_quality, so no later call on the handle
+ * allocates device memory (a pool's admission reserves the whole footprint).
  * Errors: EINVAL (bad sizes: m, d < 2 for the curve family, lb >= ub, t > N,
  * n_ring out of range, h_inner without h_outer, ...), EUNSUPPORTED
  * (m > GMPEA_MAX_M), ENOMEM, EHIP. */
@@ -212,7 +215,8 @@ gmpea_status gmpea_init(const gmpea_problem *problem, const gmpea_config *config
 gmpea_status gmpea_step(gmpea_t h, int32_t n_gen);
 
 /* Run up to max_gen generations, stopping at the first generation boundary at
- * or after time_limit_s seconds of wall time (the paper's fixed-time protocol;
+ * or after time_limit_s seconds of wall time (the fixed-time comparison of the
+ * experimental setup, Sec. IV-C, used for the runtime analysis of Sec. V-B;
  * <= 0 means no limit), then synchronise. *gens_done (may be NULL) receives the
  * generations run by this call. A limit already reached runs none. */
 gmpea_status gmpea_run(gmpea_t h, int32_t max_gen, double time_limit_s, int32_t *gens_done);
@@ -225,6 +229,7 @@ gmpea_status gmpea_run(gmpea_t h, int32_t max_gen, double time_limit_s, int32_t 
  * if it exceeds capacity nothing is copied and ECAPACITY is returned. */
 gmpea_status gmpea_front(gmpea_t h, int32_t what, int32_t capacity, float *x, float *f,
                          float *cv, int32_t *idx, int32_t *count);
+
 
 /* Quality of the current front on the device: the feasible non-dominated rows
  * of population 1 (as GMPEA_FRONT_FEASIBLE_ND), measured by IGD (Eq. (14)) and

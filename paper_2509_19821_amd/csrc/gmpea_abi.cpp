@@ -44,17 +44,18 @@ struct gmpea_s {
   bool record = false;
   std::vector<std::pair<void *, size_t>> allocs;
   size_t bytes = 0;
-  // gmpea_front scratch (flags, row list, gathered rows), allocated on first use
+  int device = 0;  // the device current at gmpea_init (the handle's memory and stream)
+  // gmpea_front / gmpea_quality scratch, part of the allocation made at
+  // gmpea_init so that delivering a front never allocates: flags and row list
+  // (n each), gathered F/CV records (n), gathered decision vectors (kFrontRows
+  // rows at a time), reference points (kQualityRefs at a time) and their IGD
+  // partial sums, the HV box and hit counter
   uint8_t *f_keep = nullptr;
   int32_t *f_idx = nullptr;
   float *f_x = nullptr;
   float4 *f_fc = nullptr;
-  // gmpea_quality scratch (reference points, IGD partial sums, HV box and
-  // counter), grown on demand
   float *q_ref = nullptr;
-  size_t q_ref_cap = 0;
   double *q_part = nullptr;
-  size_t q_part_cap = 0;
   float *q_box = nullptr;                // lo[kMaxM], hi[kMaxM]
   unsigned long long *q_hits = nullptr;
   // graph replay of `gchunk` generations
@@ -64,6 +65,12 @@ struct gmpea_s {
 };
 
 namespace {
+
+// Decision vectors gathered per pass of gmpea_front, and reference points per
+// IGD launch of gmpea_quality (a multiple of kBlock, so the per-block partial
+// sums come out in the same order as one launch over every point).
+constexpr int32_t kFrontRows = 4096;
+constexpr int32_t kQualityRefs = 16 * kBlock;
 
 void *dev_alloc(gmpea_s *h, size_t bytes) {
   void *p = nullptr;
@@ -274,38 +281,32 @@ gmpea_status check_runtime(const char *who) {
   return GMPEA_OK;
 }
 
-gmpea_status front_scratch(gmpea_s *h, const char *who) {
-  if (h->f_keep) return GMPEA_OK;
-  const DevState &st = h->st;
-  auto layout = [&](Carve &c) {
-    h->f_keep = c.take<uint8_t>(st.n);
-    h->f_idx = c.take<int32_t>(st.n);
-    h->f_x = c.take<float>(static_cast<size_t>(st.n) * st.d);
-    h->f_fc = c.take<float4>(static_cast<size_t>(st.n) * st.rq);
-  };
-  Carve sizing;
-  layout(sizing);
-  Carve carve;
-  carve.base = static_cast<char *>(dev_alloc(h, sizing.off));
-  if (!carve.base) {
-    h->f_keep = nullptr;
-    return fail(GMPEA_ENOMEM, std::string(who) + ": scratch allocation failed");
-  }
-  layout(carve);
-  return GMPEA_OK;
+// Device buffers one front extraction works in: the handle's own (carved at
+// gmpea_init).
+struct FrontBufs {
+  uint8_t *keep;   // n flags
+  int32_t *idx;    // n row indices
+  float4 *fc;      // n F/CV records
+  float *x;        // x_rows decision vectors
+  int32_t x_rows;
+};
+
+FrontBufs handle_bufs(gmpea_s *h) {
+  return FrontBufs{h->f_keep, h->f_idx, h->f_fc, h->f_x, std::min(kFrontRows, h->st.n)};
 }
 
 // Row indices (ascending) of a front selector: the feasible non-dominated rows
 // of population 1 (flags on the device), or every row of a population.
-gmpea_status front_rows(gmpea_s *h, int32_t what, std::vector<int32_t> &rows, const char *who) {
-  gmpea_status s = front_scratch(h, who);
-  if (s != GMPEA_OK) return s;
+gmpea_status front_rows(gmpea_s *h, const FrontBufs &b, int32_t what, std::vector<int32_t> &rows,
+                        const char *who) {
   const DevState &st = h->st;
   rows.clear();
+  gmpea_status s = GMPEA_OK;
   if (what == GMPEA_FRONT_FEASIBLE_ND) {
-    hipError_t e = launch_front_flags(st, 0, h->f_keep, h->stream);
+    hipError_t e = st.m > 3 ? launch_front_flags_wide(st, 0, b.keep, h->stream)
+                            : launch_front_flags(st, 0, b.keep, h->stream);
     std::vector<uint8_t> hk(st.n);
-    s = e == hipSuccess ? d2h(h, hk.data(), h->f_keep, st.n, who) : hip_fail(e, who);
+    s = e == hipSuccess ? d2h(h, hk.data(), b.keep, st.n, who) : hip_fail(e, who);
     if (s != GMPEA_OK) return s;
     for (int32_t i = 0; i < st.n; ++i)
       if (hk[i]) rows.push_back(i);
@@ -318,27 +319,54 @@ gmpea_status front_rows(gmpea_s *h, int32_t what, std::vector<int32_t> &rows, co
   return GMPEA_OK;
 }
 
-// Rows (non-empty) of population `pop` gathered into the scratch: X to f_x,
-// F/CV records to f_fc.
-gmpea_status front_gather(gmpea_s *h, int pop, const std::vector<int32_t> &rows, const char *who) {
+// The F/CV records of `rows` (non-empty) of population `pop` gathered into
+// b.fc, in row order; the row list stays in b.idx.
+gmpea_status front_gather_fc(gmpea_s *h, const FrontBufs &b, int pop, const std::vector<int32_t> &rows,
+                             const char *who) {
   const int32_t cnt = static_cast<int32_t>(rows.size());
-  gmpea_status s = h2d(h, h->f_idx, rows.data(), cnt, who);
+  gmpea_status s = h2d(h, b.idx, rows.data(), cnt, who);
   if (s != GMPEA_OK) return s;
-  hipError_t e = launch_gather(h->st, pop, h->f_idx, cnt, h->f_x, h->f_fc, h->stream);
+  hipError_t e = launch_gather(h->st, pop, b.idx, cnt, nullptr, b.fc, h->stream);
   if (e != hipSuccess) return hip_fail(e, who);
   return GMPEA_OK;
 }
 
-// Device buffer of at least `need` elements, regrown through the handle's
-// allocator (contents are not kept).
-template <class T>
-gmpea_status grow(gmpea_s *h, T **buf, size_t *cap, size_t need, const char *who) {
-  if (*buf && *cap >= need) return GMPEA_OK;
-  if (*buf) dev_free(h, *buf);
-  *buf = static_cast<T *>(dev_alloc(h, std::max<size_t>(need, 1) * sizeof(T)));
-  *cap = *buf ? need : 0;
-  if (!*buf) return fail(GMPEA_ENOMEM, std::string(who) + ": scratch allocation failed");
-  return GMPEA_OK;
+// Front extraction into a buffer set.
+gmpea_status front_impl(gmpea_s *h, const FrontBufs &b, int32_t what, int32_t capacity, float *x,
+                        float *f, float *cv, int32_t *idx, int32_t *count, const char *who) {
+  const DevState &st = h->st;
+  const int pop = what == GMPEA_FRONT_POP2 ? 1 : 0;
+  std::vector<int32_t> rows;
+  gmpea_status s = front_rows(h, b, what, rows, who);
+  if (s != GMPEA_OK) return s;
+  const int32_t cnt = static_cast<int32_t>(rows.size());
+  *count = cnt;
+  if (cnt > capacity) return fail(GMPEA_ECAPACITY, std::string(who) + ": capacity below the row count");
+  if (cnt == 0) return GMPEA_OK;
+  if (idx) std::copy(rows.begin(), rows.end(), idx);
+  s = front_gather_fc(h, b, pop, rows, who);
+  // decision vectors in passes of b.x_rows rows
+  for (int32_t r0 = 0; x && s == GMPEA_OK && r0 < cnt; r0 += b.x_rows) {
+    const int32_t c = std::min(b.x_rows, cnt - r0);
+    hipError_t e = launch_gather(st, pop, b.idx + r0, c, b.x, nullptr, h->stream);
+    if (e != hipSuccess) return hip_fail(e, who);
+    s = d2h(h, x + static_cast<size_t>(r0) * st.d, b.x, static_cast<size_t>(c) * st.d, who);
+  }
+  std::vector<float4> hfc;
+  if (s == GMPEA_OK) {
+    hfc.resize(static_cast<size_t>(cnt) * st.rq);
+    s = d2h(h, hfc.data(), b.fc, hfc.size(), who);
+  }
+  if (s == GMPEA_OK) {
+    const float *v = reinterpret_cast<const float *>(hfc.data());
+    const size_t rw = static_cast<size_t>(st.rq) * 4;
+    for (int32_t r = 0; r < cnt; ++r) {
+      if (f)
+        for (int32_t a = 0; a < st.m; ++a) f[static_cast<size_t>(r) * st.m + a] = v[r * rw + a];
+      if (cv) cv[r] = v[r * rw + rw - 1];
+    }
+  }
+  return s;
 }
 
 }  // namespace
@@ -402,6 +430,8 @@ gmpea_status gmpea_init(const gmpea_problem *P, const gmpea_config *C, const gmp
   h->H = H;
   h->H2 = H2;
   h->record = C->record != 0;
+  (void)hipGetDevice(&h->device);
+  }
 
   // ---- neighbourhood offsets (host, a few KB) when the device builds the tables:
   // one Das-Dennis layer with m <= 3; otherwise the host builds them ----
@@ -488,6 +518,15 @@ gmpea_status gmpea_init(const gmpea_problem *P, const gmpea_config *C, const gmp
     st.repl = c.take<unsigned long long>(2 * kReplLanes);
     d_offs = c.take<int2>(noffs);
     d_flag = c.take<uint32_t>(4);
+    // delivery scratch (gmpea_front, gmpea_quality)
+    h->f_keep = c.take<uint8_t>(static_cast<size_t>(N));
+    h->f_idx = c.take<int32_t>(static_cast<size_t>(N));
+    h->f_fc = c.take<float4>(static_cast<size_t>(N) * st.rq);
+    h->f_x = c.take<float>(static_cast<size_t>(std::min(kFrontRows, N)) * d);
+    h->q_ref = c.take<float>(static_cast<size_t>(kQualityRefs) * m);
+    h->q_part = c.take<double>(kQualityRefs / kBlock);
+    h->q_box = c.take<float>(2 * kMaxM);
+    h->q_hits = c.take<unsigned long long>(1);
   };
   Carve sizing;
   layout(sizing);
@@ -703,35 +742,7 @@ gmpea_status gmpea_front(gmpea_t h, int32_t what, int32_t capacity, float *x, fl
   if (what != GMPEA_FRONT_FEASIBLE_ND && what != GMPEA_FRONT_POP1 && what != GMPEA_FRONT_POP2)
     return fail(GMPEA_EINVAL, "gmpea_front: unknown selector");
   if (capacity < 0) return fail(GMPEA_EINVAL, "gmpea_front: negative capacity");
-  const DevState &st = h->st;
-  const int pop = what == GMPEA_FRONT_POP2 ? 1 : 0;
-  std::vector<int32_t> rows;
-  gmpea_status s = front_rows(h, what, rows, "gmpea_front");
-  if (s != GMPEA_OK) return s;
-  const int32_t cnt = static_cast<int32_t>(rows.size());
-  *count = cnt;
-  if (cnt > capacity) return fail(GMPEA_ECAPACITY, "gmpea_front: capacity below the row count");
-  if (cnt == 0) return GMPEA_OK;
-  if (idx) std::copy(rows.begin(), rows.end(), idx);
-  float *dx = h->f_x;
-  float4 *dfc = h->f_fc;
-  std::vector<float4> hfc;
-  s = front_gather(h, pop, rows, "gmpea_front");
-  if (s == GMPEA_OK && x) s = d2h(h, x, dx, static_cast<size_t>(cnt) * st.d, "gmpea_front");
-  if (s == GMPEA_OK) {
-    hfc.resize(static_cast<size_t>(cnt) * st.rq);
-    s = d2h(h, hfc.data(), dfc, hfc.size(), "gmpea_front");
-  }
-  if (s == GMPEA_OK) {
-    const float *v = reinterpret_cast<const float *>(hfc.data());
-    const size_t rw = static_cast<size_t>(st.rq) * 4;
-    for (int32_t r = 0; r < cnt; ++r) {
-      if (f)
-        for (int32_t a = 0; a < st.m; ++a) f[static_cast<size_t>(r) * st.m + a] = v[r * rw + a];
-      if (cv) cv[r] = v[r * rw + rw - 1];
-    }
-  }
-  return s;
+  return front_impl(h, handle_bufs(h), what, capacity, x, f, cv, idx, count, "gmpea_front");
 }
 
 gmpea_status gmpea_get_info(gmpea_t h, gmpea_info *info) {
@@ -780,8 +791,9 @@ gmpea_status gmpea_quality(gmpea_t h, const float *ref, int32_t n_ref, const flo
   if (hv)
     for (int32_t k = 0; k < m; ++k)
       if (!std::isfinite(hv_point[k])) return fail(GMPEA_EINVAL, "gmpea_quality: hv_point must be finite");
+  const FrontBufs b = handle_bufs(h);
   std::vector<int32_t> rows;
-  gmpea_status s = front_rows(h, GMPEA_FRONT_FEASIBLE_ND, rows, who);
+  gmpea_status s = front_rows(h, b, GMPEA_FRONT_FEASIBLE_ND, rows, who);
   if (s != GMPEA_OK) return s;
   const int32_t cnt = static_cast<int32_t>(rows.size());
   if (front_count) *front_count = cnt;
@@ -790,22 +802,24 @@ gmpea_status gmpea_quality(gmpea_t h, const float *ref, int32_t n_ref, const flo
     if (hv) *hv = 0.0;
     return GMPEA_OK;
   }
-  s = front_gather(h, 0, rows, who);
+  s = front_gather_fc(h, b, 0, rows, who);
   if (s != GMPEA_OK) return s;
   if (igd) {
-    const int32_t blocks_max = (n_ref + kBlock - 1) / kBlock;
-    s = grow(h, &h->q_ref, &h->q_ref_cap, static_cast<size_t>(n_ref) * m, who);
-    if (s == GMPEA_OK) s = grow(h, &h->q_part, &h->q_part_cap, static_cast<size_t>(blocks_max), who);
-    if (s == GMPEA_OK) s = h2d(h, h->q_ref, ref, static_cast<size_t>(n_ref) * m, who);
-    if (s != GMPEA_OK) return s;
-    int32_t blocks = 0;
-    hipError_t e = launch_igd(h->q_ref, n_ref, m, h->f_fc, cnt, st.rq, h->q_part, &blocks, h->stream);
-    if (e != hipSuccess) return hip_fail(e, who);
-    std::vector<double> part(static_cast<size_t>(blocks));
-    s = d2h(h, part.data(), h->q_part, part.size(), who);
-    if (s != GMPEA_OK) return s;
+    // reference points kQualityRefs at a time; the per-block sums are added in
+    // block order, the order one launch over every point would give
     double sum = 0.0;
-    for (double v : part) sum += v;  // fixed order: the result is reproducible
+    std::vector<double> part(kQualityRefs / kBlock);
+    for (int32_t r0 = 0; r0 < n_ref && s == GMPEA_OK; r0 += kQualityRefs) {
+      const int32_t c = std::min(kQualityRefs, n_ref - r0);
+      s = h2d(h, h->q_ref, ref + static_cast<size_t>(r0) * m, static_cast<size_t>(c) * m, who);
+      if (s != GMPEA_OK) return s;
+      int32_t blocks = 0;
+      hipError_t e = launch_igd(h->q_ref, c, m, h->f_fc, cnt, st.rq, h->q_part, &blocks, h->stream);
+      if (e != hipSuccess) return hip_fail(e, who);
+      s = d2h(h, part.data(), h->q_part, static_cast<size_t>(blocks), who);
+      for (int32_t q = 0; q < blocks && s == GMPEA_OK; ++q) sum += part[q];
+    }
+    if (s != GMPEA_OK) return s;
     *igd = sum / n_ref;
   }
   if (hv) {
@@ -826,12 +840,6 @@ gmpea_status gmpea_quality(gmpea_t h, const float *ref, int32_t n_ref, const flo
     if (!(vol > 0.0)) {
       *hv = 0.0;
       return GMPEA_OK;
-    }
-    if (!h->q_box) {
-      void *p = dev_alloc(h, 2 * kMaxM * sizeof(float) + 256);
-      if (!p) return fail(GMPEA_ENOMEM, "gmpea_quality: scratch allocation failed");
-      h->q_box = static_cast<float *>(p);
-      h->q_hits = reinterpret_cast<unsigned long long *>(static_cast<char *>(p) + 2 * kMaxM * sizeof(float) + 128);
     }
     const unsigned long long zero = 0;
     s = h2d(h, h->q_box, box, 2 * kMaxM, who);

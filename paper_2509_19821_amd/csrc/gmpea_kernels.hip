@@ -265,14 +265,18 @@ __global__ __launch_bounds__(kBlock) void k_rows_batch(const DevState *__restric
   for (int k = 0; k < kRowsIterBatch; ++k) rows_body(st, e0 + static_cast<int64_t>(k) * kBlock);
 }
 
+// Rows idx[0 .. count) of population `pop`: decision vectors to x (count x d)
+// and F/CV records to fc (count x rq); either output may be null.
 __global__ __launch_bounds__(kBlock) void k_gather(DevState st, int pop, const int32_t *idx,
                                                    int32_t count, float *x, float4 *fc) {
   const int r = blockIdx.x;
   if (r >= count) return;
   const int row = idx[r];
-  const float *srcx = st.X[pop] + static_cast<size_t>(row) * st.stride;
-  for (int l = threadIdx.x; l < st.d; l += blockDim.x) x[static_cast<size_t>(r) * st.d + l] = srcx[l];
-  if (threadIdx.x < st.rq)
+  if (x) {
+    const float *srcx = st.X[pop] + static_cast<size_t>(row) * st.stride;
+    for (int l = threadIdx.x; l < st.d; l += blockDim.x) x[static_cast<size_t>(r) * st.d + l] = srcx[l];
+  }
+  if (fc && threadIdx.x < st.rq)
     fc[static_cast<size_t>(r) * st.rq + threadIdx.x] = st.FC[pop][static_cast<size_t>(row) * st.rq + threadIdx.x];
 }
 

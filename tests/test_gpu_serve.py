@@ -117,3 +117,41 @@ def test_igd_at_deadline_sample(G):
         else:
             assert r.igd == float("inf") and r.hv == 0.0
     assert all(np.isfinite(v) for (_, _, gens, v) in rows if gens >= 20)
+
+
+def test_delivery_in_a_full_pool(G):
+    """A pool whose budget is exactly two instances' footprint plus the pool's
+    own tables: deliveries (front and device quality at each deadline)
+    allocate nothing beyond what admission reserved, so every request is
+    delivered with its IGD and HV while the pool stays full."""
+    from oracle import metrics
+    from paper_2509_19821_amd.serve import Request, Server
+    prob, cfg, _ = ci.workload_medium(2)
+    probe = G.Pool(1 << 30)
+    try:  # two instances and the pool's own device tables (state array, work lists)
+        probe.admit(prob, cfg)
+        probe.admit(prob, dict(cfg, seed=99))
+        probe.step(1)
+        probe.sync()
+        full = probe.query()["used_bytes"]
+    finally:
+        probe.close()
+    ref = metrics.reference_front(prob, density=40).astype(np.float32)
+    hvp = (1.1 * ref.max(0)).astype(np.float32)
+    reqs = [Request(k, prob, dict(cfg, seed=k), 0.02, 0.0, reference=ref, hv_point=hvp)
+            for k in range(6)]
+    srv = Server(full, hv_samples=1 << 16)
+    peak = 0
+    try:
+        for r in reqs:
+            srv.submit(r)
+        srv.now()
+        while srv.waiting or srv.active:
+            srv.step()
+            peak = max(peak, len(srv.active))
+            assert srv.pool.query()["used_bytes"] <= full
+    finally:
+        srv.close()
+    assert peak == 2
+    assert sorted(r.rid for r in srv.results) == list(range(6))
+    assert all(r.igd is not None and r.hv is not None for r in srv.results)
