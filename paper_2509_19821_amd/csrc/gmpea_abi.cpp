@@ -431,7 +431,6 @@ gmpea_status gmpea_init(const gmpea_problem *P, const gmpea_config *C, const gmp
   h->H2 = H2;
   h->record = C->record != 0;
   (void)hipGetDevice(&h->device);
-  }
 
   // ---- neighbourhood offsets (host, a few KB) when the device builds the tables:
   // one Das-Dennis layer with m <= 3; otherwise the host builds them ----
