@@ -445,7 +445,18 @@ gmpea_status gmpea_init(const gmpea_problem *P, const gmpea_config *C, const gmp
   st.n = N;
   st.m = m;
   st.d = d;
-  st.stride = (d + 3) & ~3;
+  st.nq = (d + 3) >> 2;
+  {
+    // row pitch: the variables rounded up to whole float4 chunks, or to a
+    // multiple of GMPEA_ROW_ALIGN floats when set (a layout experiment knob)
+    int32_t align = 4;
+    if (const char *a = std::getenv("GMPEA_ROW_ALIGN")) align = std::max(4, (std::atoi(a) + 3) & ~3);
+    st.stride = (4 * st.nq + align - 1) / align * align;
+    // the variation kernel: lane groups, or the task-dealt kernel when asked
+    // for (GMPEA_TASKED=1) and the rows have at most kTaskChunks chunks
+    const char *tk = std::getenv("GMPEA_TASKED");
+    st.tasked = (st.nq <= kTaskChunks && tk && std::atoi(tk) == 1) ? 1 : 0;
+  }
   st.rq = rec_quads(m);
   st.nblk = (N + kBlock - 1) / kBlock;
   st.t[0] = t1;
@@ -497,10 +508,11 @@ gmpea_status gmpea_init(const gmpea_problem *P, const gmpea_config *C, const gmp
     lb = c.take<float>(st.stride);
     ub = c.take<float>(st.stride);
     inv_span = c.take<float>(st.stride);
+    st.rows = c.take<float>(6 * rows * st.stride);
     for (int p = 0; p < 2; ++p) {
-      st.X[p] = c.take<float>(rows * st.stride);
+      st.X[p] = st.rows ? st.rows + p * rows * st.stride : nullptr;
+      st.loc[p] = c.take<uint32_t>(rows);
       st.rsrc[p] = c.take<int32_t>(rows);
-      st.XO[p] = c.take<float>(rows * st.stride);
       st.FC[p] = c.take<float4>(rows * st.rq);
       st.FCO[p] = c.take<float4>(rows * st.rq);
       st.FCN[p] = c.take<float4>(rows * st.rq);
@@ -561,9 +573,9 @@ gmpea_status gmpea_init(const gmpea_problem *P, const gmpea_config *C, const gmp
   cp(inv_span, isf.data(), st.stride * sizeof(float));
   if (noffs > 0) cp(d_offs, offs.data(), offs.size() * sizeof(int32_t));
   zero(d_flag, 0, 4 * sizeof(uint32_t));
+  st.region = static_cast<int64_t>(rows);
+  zero(st.rows, 0, 6 * rows * st.stride * sizeof(float));
   for (int p = 0; p < 2; ++p) {
-    zero(st.X[p], 0, rows * st.stride * sizeof(float));
-    zero(st.XO[p], 0, rows * st.stride * sizeof(float));
     zero(st.FC[p], 0, rows * st.rq * sizeof(float4));
     zero(st.FCO[p], 0, rows * st.rq * sizeof(float4));
     zero(st.FCN[p], 0, rows * st.rq * sizeof(float4));
@@ -879,9 +891,21 @@ gmpea_status gmpea_read(gmpea_t h, int32_t buffer, int32_t pop, void *host, int6
     case GMPEA_BUF_X:
     case GMPEA_BUF_XOFF: {
       if (!need(n * d)) return fail(GMPEA_EINVAL, "gmpea_read: count must be N * d");
-      const float *src = buffer == GMPEA_BUF_X ? st.X[pop] : st.XO[pop];
-      hipError_t e = hipMemcpy2DAsync(host, d * sizeof(float), src, st.stride * sizeof(float),
-                                      d * sizeof(float), n, hipMemcpyDeviceToHost, h->stream);
+      const float *src = st.X[pop];
+      hipError_t e = hipSuccess;
+      if (buffer == GMPEA_BUF_X) {
+        // current rows gathered home first (the values do not change)
+        e = launch_materialize(st, h->stream);
+      } else {
+        // the offspring of the last generation, in the regions of its parity
+        uint32_t g = 0;
+        gmpea_status s = d2h(h, &g, st.gen, 1, "gmpea_read");
+        if (s != GMPEA_OK) return s;
+        src = st.rows + static_cast<size_t>(offspring_row(st, g & 1u, pop, 0)) * st.stride;
+      }
+      if (e == hipSuccess)
+        e = hipMemcpy2DAsync(host, d * sizeof(float), src, st.stride * sizeof(float), d * sizeof(float), n,
+                             hipMemcpyDeviceToHost, h->stream);
       if (e != hipSuccess) return hip_fail(e, "gmpea_read");
       return sync(h, "gmpea_read");
     }
@@ -964,6 +988,7 @@ gmpea_status gmpea_write(gmpea_t h, int32_t buffer, int32_t pop, const void *hos
       if (count != n * d) return fail(GMPEA_EINVAL, "gmpea_write: count must be N * d");
       hipError_t e = hipMemcpy2DAsync(st.X[pop], st.stride * sizeof(float), host, d * sizeof(float),
                                       d * sizeof(float), n, hipMemcpyHostToDevice, h->stream);
+      if (e == hipSuccess) e = launch_loc_home(st, pop, h->stream);
       if (e != hipSuccess) return hip_fail(e, "gmpea_write");
       return sync(h, "gmpea_write");
     }
@@ -1033,9 +1058,20 @@ gmpea_status gmpea_profile(gmpea_t h, int32_t n_gen, float *ms) {
       acc[ph] += t;
     }
   }
+  // the variation phase again, n_gen launches back to back between two events:
+  // repeated, it rewrites the same offspring of the same generation (the
+  // generation counter advances only in the next phase), so this times the
+  // kernel without one event pair per launch
+  float rep = 0.0f;
+  if (e == hipSuccess) e = hipEventRecord(ev[0], h->stream);
+  for (int32_t g = 0; g < n_gen && e == hipSuccess; ++g) e = launch_phase(h->st, 0, h->stream);
+  if (e == hipSuccess) e = hipEventRecord(ev[1], h->stream);
+  if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
+  if (e == hipSuccess) e = hipEventElapsedTime(&rep, ev[0], ev[1]);
   for (int q = 0; q < made; ++q) (void)hipEventDestroy(ev[q]);
   if (e != hipSuccess) return hip_fail(e, "gmpea_profile");
   for (int ph = 0; ph < kPhases; ++ph) ms[ph] = static_cast<float>(acc[ph] / n_gen);
+  ms[kPhases] = rep / static_cast<float>(n_gen);
   return GMPEA_OK;
 }
 
@@ -1129,6 +1165,8 @@ struct PoolArena {
   static constexpr size_t kChunk = size_t(256) << 20;
 };
 
+constexpr int kWorkClasses = 4;
+
 struct gmpea_pool_s {
   gmpea_allocator user{};
   bool user_hook = false;
@@ -1144,9 +1182,9 @@ struct gmpea_pool_s {
   int32_t state_cap = 0;
   // work lists per phase: [0] instances with m <= 3 (every instance in the row
   // copies, which do not depend on m), [1] instances with m > 3
-  int2 *d_work[2][kPhases] = {};
-  int32_t work_cap[2][kPhases] = {};
-  int32_t nwork[2][kPhases] = {};
+  int2 *d_work[kWorkClasses][kPhases] = {};
+  int32_t work_cap[kWorkClasses][kPhases] = {};
+  int32_t nwork[kWorkClasses][kPhases] = {};
   bool dirty = true;
   // launch policy (the autotuner may change both; results do not depend on them)
   int32_t schedule = 0;  // 0: instance blocks grouped per XCD, 1: linear
@@ -1266,10 +1304,10 @@ gmpea_status pool_table(gmpea_pool_s *q, T **ptr, int32_t *cap, int32_t need) {
 }
 
 int32_t phase_blocks(const DevState &st, int phase) {
-  if (phase == 0) return vary_blocks_of(st.n, vary_lanes_of(st.stride));
+  if (phase == 0) return vary_grid(st);
   if (phase == 1) return st.nblk;
   if (phase == 2) return st.sel_blocks0 + st.sel_blocks1;
-  return rows_blocks_of(st.n, st.stride, kRowsIterBatch);
+  return remap_blocks_of(st.n);
 }
 
 // Work list of one phase. Schedule 0 keeps each instance's consecutive blocks
@@ -1277,12 +1315,22 @@ int32_t phase_blocks(const DevState &st, int phase) {
 // ones split into contiguous runs) so neighbouring subproblems share an L2;
 // the hardware deals block b to XCD b mod 8, hence the interleaving at the end.
 // cls 0: instances with m <= 3 (every instance for the row copies), 1: m > 3.
+// Work-list classes of a pool: bit 0 records of m > 3 (kernels of their own),
+// bit 1 the task-dealt variation. The location phase takes every instance in
+// class 0; the OP1 and selection phases split by m only.
+bool in_class(const DevState &st, int phase, int cls) {
+  const int wide = st.m > 3 ? 1 : 0, tasked = st.tasked ? 1 : 0;
+  if (phase == 3) return cls == 0;
+  if (phase == 0) return cls == (wide | (tasked << 1));
+  return cls == wide;
+}
+
 void build_work(const gmpea_pool_s *q, int phase, int schedule, int cls, std::vector<int2> &out) {
   out.clear();
   std::vector<std::pair<int32_t, int32_t>> inst;  // (blocks, slot)
   int64_t total = 0;
   for (int32_t s = 0; s < static_cast<int32_t>(q->slots.size()); ++s)
-    if (q->slots[s] && (phase == 3 ? cls == 0 : (q->slots[s]->st.m > 3) == (cls == 1))) {
+    if (q->slots[s] && in_class(q->slots[s]->st, phase, cls)) {
       inst.emplace_back(phase_blocks(q->slots[s]->st, phase), s);
       total += inst.back().first;
     }
@@ -1332,8 +1380,8 @@ gmpea_status pool_rebuild(gmpea_pool_s *q) {
     if (q->slots[k]) host[k] = q->slots[k]->st;
   hipError_t e = hipMemcpyAsync(q->d_states, host.data(), sizeof(DevState) * host.size(),
                                 hipMemcpyHostToDevice, q->stream);
-  std::vector<int2> w[2][kPhases];  // kept until the copies below have finished
-  for (int c = 0; c < 2; ++c)
+  std::vector<int2> w[kWorkClasses][kPhases];  // kept until the copies below have finished
+  for (int c = 0; c < kWorkClasses; ++c)
     for (int ph = 0; ph < kPhases && e == hipSuccess; ++ph) {
       build_work(q, ph, q->schedule, c, w[c][ph]);
       s = pool_table(q, &q->d_work[c][ph], &q->work_cap[c][ph],
@@ -1352,8 +1400,9 @@ gmpea_status pool_rebuild(gmpea_pool_s *q) {
 
 hipError_t pool_generation(const gmpea_pool_s *q, hipStream_t s) {
   for (int ph = 0; ph < kPhases; ++ph) {
-    for (int c = 0; c < 2; ++c) {
-      hipError_t e = launch_batch_phase(q->d_states, q->d_work[c][ph], q->nwork[c][ph], ph, c == 1, s);
+    for (int c = 0; c < kWorkClasses; ++c) {
+      hipError_t e = launch_batch_phase(q->d_states, q->d_work[c][ph], q->nwork[c][ph], ph, (c & 1) != 0,
+                                        (c & 2) != 0, s);
       if (e != hipSuccess) return e;
     }
   }
@@ -1631,7 +1680,7 @@ void gmpea_pool_destroy(gmpea_pool_t q) {
   if (q->gexec) (void)hipGraphExecDestroy(q->gexec);
   if (q->d_states) pool_raw_free(q, q->d_states);
   for (int ph = 0; ph < kPhases; ++ph)
-    for (int c = 0; c < 2; ++c)
+    for (int c = 0; c < kWorkClasses; ++c)
       if (q->d_work[c][ph]) pool_raw_free(q, q->d_work[c][ph]);
   pool_arena_destroy(q);
   if (q->init_stream) (void)hipStreamDestroy(q->init_stream);

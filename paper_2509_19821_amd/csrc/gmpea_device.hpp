@@ -45,6 +45,11 @@ __device__ __forceinline__ float keyf(uint32_t k) {
 
 __device__ __forceinline__ float nan_inf(float v) { return (v != v) ? __builtin_huge_valf() : v; }
 
+// The decision vector in arena row r (float4 view).
+__device__ __forceinline__ const float4 *arena_row(const DevState &st, uint32_t r) {
+  return reinterpret_cast<const float4 *>(st.rows + static_cast<size_t>(r) * st.stride);
+}
+
 // Block index -> tile such that each XCD receives a contiguous run of tiles.
 __device__ __forceinline__ int xcd_tile(int b, int G) {
   const int x = b & 7, q = G >> 3, r = G & 7;
@@ -311,7 +316,7 @@ __device__ __forceinline__ EvalAcc<M> eval_row(const DevState &st, const float4 
                                                bool live, float4 *slot) {
   EvalAcc<M> e{};
   if (live) {
-    const int nq = st.stride >> 2;
+    const int nq = st.nq;
     for (int q = g; q < nq; q += LPO) eval_chunk<M, FAM>(e, q, row[q], st.d, slot);
   }
   return e;
@@ -389,7 +394,6 @@ __device__ __forceinline__ void vary_body(const DevState &st, int L, int G) {
   const int i = (L - p * half) * kPer + threadIdx.x / LPO;
   const uint32_t k = *st.gen + 1u;
   const uint32_t tagp = (p << 16);
-  const float *Xc = st.X[p];
   const bool live = i < st.n;
   EvalAcc<M> e{};
   float4 *slot = M > 3 ? lead_slots<M>(threadIdx.x / LPO) : nullptr;
@@ -409,16 +413,18 @@ __device__ __forceinline__ void vary_body(const DevState &st, int L, int G) {
       st.mate[p][2 * i + 1] = pb;
     }
     const bool cross = static_cast<uint64_t>(w.z) < st.tpc;
-    const float4 *ra = reinterpret_cast<const float4 *>(Xc + static_cast<size_t>(pa) * st.stride);
-    const float4 *rb = reinterpret_cast<const float4 *>(Xc + static_cast<size_t>(pb) * st.stride);
-    float4 *ro = reinterpret_cast<float4 *>(st.XO[p] + static_cast<size_t>(i) * st.stride);
+    // the parents' current decision vectors, wherever the replacement left them
+    const float4 *ra = arena_row(st, st.loc[p][pa]);
+    const float4 *rb = arena_row(st, st.loc[p][pb]);
+    float4 *ro = reinterpret_cast<float4 *>(st.rows + static_cast<size_t>(offspring_row(st, k & 1u, p, i)) *
+                                                          st.stride);
     const float4 *lb4 = reinterpret_cast<const float4 *>(st.prob.lb);
     const float4 *ub4 = reinterpret_cast<const float4 *>(st.prob.ub);
     const float4 *is4 = reinterpret_cast<const float4 *>(st.prob.inv_span);
     const uint32_t tagv = (kTagVar << 24) | tagp;
-    const int nq = st.stride >> 2;
+    const int nq = st.nq;
     const bool de = st.op == 1;
-    const float4 *rx = reinterpret_cast<const float4 *>(Xc + static_cast<size_t>(i) * st.stride);
+    const float4 *rx = de ? arena_row(st, st.loc[p][i]) : ra;
     const uint64_t T = st.tpm;
     for (int q = g; q < nq; q += LPO) {
       const int l0 = q << 2;
@@ -462,6 +468,205 @@ __global__ __launch_bounds__(kBlock) void k_vary(DevState st) {
 }
 
 // ----------------------------------------------------------------------------
+// Task-dealt variation for rows of at most kTaskChunks float4 chunks (d <= 128).
+// A wave builds 64 offspring: lane o first draws offspring o's mating picks
+// and finds its parents' rows; then the wave's 64 nq tasks (offspring o, chunk
+// q), numbered o nq + q, are dealt to the lanes in order, task lane + 64 s in
+// step s, so every lane runs exactly nq steps with no lane idle, and one wave
+// instruction reads and writes 64 consecutive chunks (about 1 KB of offspring
+// rows, the matching spans of the parent rows). Each task leaves its chunk's
+// evaluation partial in LDS; lane o then adds its offspring's partials in
+// chunk order and finishes F, CV and the ideal point. The draws and the
+// variation of every variable are those of vary_body.
+// ----------------------------------------------------------------------------
+// Evaluation partial of chunk q (variables 4q .. 4q + 3 below d, in order).
+template <int M, int FAM>
+__device__ __forceinline__ float chunk_partial(int q, float4 o, int d) {
+  const float xs[4] = {o.x, o.y, o.z, o.w};
+  float s = 0.0f;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int l = 4 * q + k;
+    if (l < d) {
+      if (FAM == 0) {
+        if (l >= 1) s += xs[k];
+      } else if (l >= M - 1) {
+        s = fmaf(xs[k] - 0.5f, xs[k] - 0.5f, s);
+      }
+    }
+  }
+  return s;
+}
+
+// F/CV record of a row from its chunk partials (added in chunk order) and its
+// leading chunks c0, c1 (the variables the objectives and the equality read).
+template <int M, int FAM>
+__device__ __forceinline__ Rec<M> eval_partials(const float *part, int nq, float4 c0, float4 c1,
+                                                const DevProblem &P) {
+  EvalAcc<M> e{};
+  e.s = 0.0f;
+  for (int q = 0; q < nq; ++q) e.s += part[q];
+  e.lead[0] = c0.x;
+  e.lead[1] = c0.y;
+  return eval_finish<M, FAM>(e, c0, c1, P);
+}
+
+// LDS of tvary_body, one buffer per kernel whatever the template instances a
+// batched kernel holds (a non-template function's shared array): per wave, the
+// 64 offspring's sources, their chunk partials (offspring-major) and their two
+// leading chunks.
+struct TvaryLds {
+  int4 src[kBlock / 64][64];  // parent rows a, b; own row; index | cross << 30 (-1: none)
+  float part[kBlock / 64][64 * kTaskChunks];
+  float4 lead[kBlock / 64][64][2];
+};
+__device__ __forceinline__ TvaryLds &tvary_lds() {
+  __shared__ TvaryLds lds;
+  return lds;
+}
+
+template <int M, int FAM>
+__device__ __forceinline__ void tvary_body(const DevState &st, int L, int G) {
+  constexpr int kLead = M <= 3 ? 1 : EvalAcc<M>::kLeadChunks;
+  static_assert(kLead <= 2, "at most two leading chunks");
+  TvaryLds &lds = tvary_lds();
+  auto &s_src = lds.src;
+  auto &s_part = lds.part;
+  auto &s_lead = lds.lead;
+  const int half = G >> 1;  // blocks per population
+  const int p = L >= half ? 1 : 0;
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int base = (L - p * half) * kBlock + wv * 64;  // the wave's first offspring
+  const uint32_t k = *st.gen + 1u;
+  const uint32_t tagp = (p << 16);
+  const int n = st.n, nq = st.nq;
+  // ---- lane o: offspring base + o -- mating picks and parent rows ----
+  {
+    const int i = base + lane;
+    int4 src = make_int4(0, 0, 0, -1);
+    if (i < n) {
+      const int t = st.t[p];
+      const uint4 w = philox10(make_uint4(0u, i, k, (kTagMate << 24) | tagp), st.key0, st.key1);
+      const uint32_t r1 = __umulhi(w.x, static_cast<uint32_t>(t));
+      uint32_t r2 = r1;
+      if (t > 1) {
+        r2 = __umulhi(w.y, static_cast<uint32_t>(t - 1));
+        r2 += (r2 >= r1) ? 1u : 0u;
+      }
+      const int32_t *Bi = st.B[p] + static_cast<size_t>(i) * t;
+      const int pa = Bi[r1], pb = Bi[r2];
+      if (st.mate[p]) {
+        st.mate[p][2 * i] = pa;
+        st.mate[p][2 * i + 1] = pb;
+      }
+      const bool cross = static_cast<uint64_t>(w.z) < st.tpc;
+      src = make_int4(static_cast<int>(st.loc[p][pa]), static_cast<int>(st.loc[p][pb]),
+                      st.op == 1 ? static_cast<int>(st.loc[p][i]) : 0,
+                      i | (cross ? (1 << 30) : 0));
+    }
+    s_src[wv][lane] = src;
+  }
+  __syncthreads();
+  // ---- the wave's 64 nq tasks, task lane + 64 s in step s ----
+  const float4 *lb4 = reinterpret_cast<const float4 *>(st.prob.lb);
+  const float4 *ub4 = reinterpret_cast<const float4 *>(st.prob.ub);
+  const float4 *is4 = reinterpret_cast<const float4 *>(st.prob.inv_span);
+  const uint32_t tagv = (kTagVar << 24) | tagp;
+  const bool de = st.op == 1;
+  const uint64_t T = st.tpm;
+  const int dq = 64 % nq, dof = 64 / nq;
+  int o = lane / nq, q = lane - (lane / nq) * nq;
+  for (int step = 0; step < nq; ++step) {
+    const int4 src = s_src[wv][o];
+    if (src.w >= 0) {
+      const int i = src.w & 0x3FFFFFFF;
+      const bool cross = (src.w >> 30) != 0;
+      const int l0 = q << 2;
+      const float4 va = arena_row(st, static_cast<uint32_t>(src.x))[q];
+      const float4 vb = arena_row(st, static_cast<uint32_t>(src.y))[q];
+      const float4 lo = lb4[q], hi = ub4[q], is = is4[q];
+      const uint4 r0 = philox10(make_uint4(2 * q, i, k, tagv), st.key0, st.key1);
+      uint4 r1w = make_uint4(0, 0, 0, 0);
+      if (l0 + 2 < st.d) r1w = philox10(make_uint4(2 * q + 1, i, k, tagv), st.key0, st.key1);
+      float4 ov = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      if (de) {
+        const float4 vx = arena_row(st, static_cast<uint32_t>(src.z))[q];
+        ov.x = de1(vx.x, va.x, vb.x, lo.x, hi.x, st);
+        ov.y = de1(vx.y, va.y, vb.y, lo.y, hi.y, st);
+        ov.z = de1(vx.z, va.z, vb.z, lo.z, hi.z, st);
+        ov.w = de1(vx.w, va.w, vb.w, lo.w, hi.w, st);
+      } else {
+        ov.x = sbx1(va.x, vb.x, r0.x, lo.x, hi.x, cross, st);
+        ov.y = sbx1(va.y, vb.y, r0.z, lo.y, hi.y, cross, st);
+        ov.z = sbx1(va.z, vb.z, r1w.x, lo.z, hi.z, cross, st);
+        ov.w = sbx1(va.w, vb.w, r1w.z, lo.w, hi.w, cross, st);
+      }
+      if (r0.y < T) ov.x = pm1(ov.x, r0.y, T, st.inv_tpm, lo.x, hi.x, is.x, st);
+      if (l0 + 1 < st.d && r0.w < T) ov.y = pm1(ov.y, r0.w, T, st.inv_tpm, lo.y, hi.y, is.y, st);
+      if (l0 + 2 < st.d && r1w.y < T) ov.z = pm1(ov.z, r1w.y, T, st.inv_tpm, lo.z, hi.z, is.z, st);
+      if (l0 + 3 < st.d && r1w.w < T) ov.w = pm1(ov.w, r1w.w, T, st.inv_tpm, lo.w, hi.w, is.w, st);
+      if (l0 + 1 >= st.d) ov.y = 0.0f;
+      if (l0 + 2 >= st.d) ov.z = 0.0f;
+      if (l0 + 3 >= st.d) ov.w = 0.0f;
+      reinterpret_cast<float4 *>(st.rows + static_cast<size_t>(offspring_row(st, k & 1u, p, i)) *
+                                               st.stride)[q] = ov;
+      s_part[wv][o * nq + q] = chunk_partial<M, FAM>(q, ov, st.d);
+      if (q < kLead) s_lead[wv][o][q] = ov;
+    }
+    q += dq;
+    o += dof;
+    if (q >= nq) {
+      q -= nq;
+      ++o;
+    }
+  }
+  __syncthreads();
+  // ---- lane o: F, CV and the ideal point of offspring base + o ----
+  float zv[M];
+#pragma unroll
+  for (int a = 0; a < M; ++a) zv[a] = __builtin_huge_valf();
+  const int i = base + lane;
+  if (i < n) {
+    const float4 c0 = s_lead[wv][lane][0];
+    const float4 c1 = kLead > 1 ? s_lead[wv][lane][kLead > 1 ? 1 : 0] : make_float4(0, 0, 0, 0);
+    const Rec<M> fc = eval_partials<M, FAM>(&s_part[wv][lane * nq], nq, c0, c1, st.prob);
+    rec_store<M>(st.FCO[p], i, fc);
+#pragma unroll
+    for (int a = 0; a < M; ++a) zv[a] = fc.v[a];
+  }
+  block_zmin<M>(zv, st.zkey);
+}
+
+template <int M, int FAM>
+__global__ __launch_bounds__(kBlock) void k_tvary(DevState st) {
+  tvary_body<M, FAM>(st, xcd_tile(blockIdx.x, gridDim.x), gridDim.x);
+}
+
+// Initial evaluation matching tvary_body's order (rows of at most kTaskChunks
+// chunks): one thread per row, chunk partials added in chunk order.
+template <int M, int FAM>
+__global__ __launch_bounds__(kBlock) void k_teval(DevState st) {
+  const int L = xcd_tile(blockIdx.x, gridDim.x);
+  const int half = gridDim.x >> 1;
+  const int p = L >= half ? 1 : 0;
+  const int i = (L - p * half) * kBlock + threadIdx.x;
+  float zv[M];
+#pragma unroll
+  for (int a = 0; a < M; ++a) zv[a] = __builtin_huge_valf();
+  if (i < st.n) {
+    const float4 *row = reinterpret_cast<const float4 *>(st.X[p] + static_cast<size_t>(i) * st.stride);
+    float part[kTaskChunks];
+    for (int q = 0; q < st.nq; ++q) part[q] = chunk_partial<M, FAM>(q, row[q], st.d);
+    const float4 c1 = st.nq > 1 ? row[1] : make_float4(0, 0, 0, 0);
+    const Rec<M> fc = eval_partials<M, FAM>(part, st.nq, row[0], c1, st.prob);
+    rec_store<M>(st.FC[p], i, fc);
+#pragma unroll
+    for (int a = 0; a < M; ++a) zv[a] = fc.v[a];
+  }
+  block_zmin<M>(zv, st.zkey);
+}
+
+// ----------------------------------------------------------------------------
 // Aggregation. PBI (Eq. (7)) with the unit direction u = w / ||w|| stored in W:
 // d1 = |(F - z) . u|, d2 = ||F - z - d1 u||, g = d1 + theta d2. Tchebycheff:
 // max_k w_k |f_k - z_k| with the raw weight stored in W. NaN reads as +inf.
@@ -498,7 +703,9 @@ __device__ __forceinline__ float aggregate(const Rec<M> &f, const Rec<M> &w, con
       const float e = df[k] - d1 * ww[k];
       d2 = fmaf(e, e, d2);
     }
-    g = d1 + theta * sqrtf(d2);
+    // the hardware square root (within one ulp; a correctly rounded sqrtf
+    // costs about fifteen more instructions per candidate)
+    g = d1 + theta * __builtin_amdgcn_sqrtf(d2);
   }
   return nan_inf(g);
 }
@@ -721,26 +928,66 @@ __device__ __forceinline__ void select_body(const DevState &st, int L) {
 }
 
 // ----------------------------------------------------------------------------
-// k_rows: the row copies of the replacement, one float4 of a population row per
-// thread, streaming over both populations in place: a replaced slot takes its
-// winning offspring row. All reads of X for the generation happened in earlier
-// launches. (Rows are not aligned to 128-byte lines; writing the kept bytes of
-// shared lines back as well, so that no line is left partially written, was
-// measured slower: partial lines cost nothing extra here.)
+// Locations after the replacement, one thread per slot of both populations
+// (slot e of population e / n). A replaced slot points at its winning offspring
+// row (written by this generation, parity k). A kept slot keeps its row, but a
+// row in the other parity's offspring regions would be overwritten by the next
+// generation's offspring: such a row is copied to the slot's home row first, by
+// all lanes of the wave together (about one slot in a hundred is kept). No slot
+// points at another slot's home row, so the copies never overwrite a row that
+// some location still names. Every lane of the wave must reach the ballot.
 // ----------------------------------------------------------------------------
-__device__ __forceinline__ void rows_body(const DevState &st, int64_t e) {
-  const int nq = st.stride >> 2;
-  const int64_t per_pop = static_cast<int64_t>(st.n) * nq;
-  if (e >= 2 * per_pop) return;
-  const int p = e >= per_pop ? 1 : 0;
-  const int64_t el = e - p * per_pop;
-  const int r = static_cast<int>(el / nq);
-  const int c = static_cast<int>(el - static_cast<int64_t>(r) * nq);
-  const int32_t ds = st.rsrc[p][r];
-  if (ds < 0) return;
-  const float *src = st.XO[ds >> 30] + static_cast<size_t>(ds & 0x3FFFFFFF) * st.stride;
-  reinterpret_cast<float4 *>(st.X[p] + static_cast<size_t>(r) * st.stride)[c] =
-      reinterpret_cast<const float4 *>(src)[c];
+__device__ __forceinline__ void remap_body(const DevState &st, int64_t e) {
+  const uint32_t k = *st.gen;  // the generation this replacement belongs to
+  const int n = st.n;
+  bool copy = false;
+  uint32_t from = 0, home = 0;
+  if (e < 2LL * n) {
+    const int p = e >= n ? 1 : 0;
+    const int j = static_cast<int>(e - p * n);
+    const int32_t ds = st.rsrc[p][j];
+    if (ds >= 0) {
+      st.loc[p][j] = offspring_row(st, k & 1u, ds >> 30, ds & 0x3FFFFFFF);
+    } else {
+      const uint32_t l = st.loc[p][j];
+      const uint32_t lo = offspring_row(st, (k + 1u) & 1u, 0, 0);
+      if (l >= lo && l < lo + 2 * static_cast<uint32_t>(st.region)) {
+        copy = true;
+        from = l;
+        home = static_cast<uint32_t>(p * st.region + j);
+        st.loc[p][j] = home;
+      }
+    }
+  }
+  // copies four rows at a time, so that four loads per lane are in flight
+  constexpr int kAtOnce = 4;
+  uint64_t pending = __ballot(copy);
+  const int lane = threadIdx.x & 63;
+  while (pending) {
+    uint32_t f[kAtOnce], h[kAtOnce];
+    int cnt = 0;
+#pragma unroll
+    for (int u = 0; u < kAtOnce; ++u) {
+      f[u] = 0;
+      h[u] = 0;
+      if (pending) {
+        const int src_lane = __ffsll(static_cast<unsigned long long>(pending)) - 1;
+        pending &= pending - 1;
+        f[u] = static_cast<uint32_t>(__shfl(static_cast<int>(from), src_lane));
+        h[u] = static_cast<uint32_t>(__shfl(static_cast<int>(home), src_lane));
+        cnt = u + 1;
+      }
+    }
+    for (int c = lane; c < st.nq; c += 64) {
+      float4 v[kAtOnce];
+#pragma unroll
+      for (int u = 0; u < kAtOnce; ++u)
+        if (u < cnt) v[u] = arena_row(st, f[u])[c];
+#pragma unroll
+      for (int u = 0; u < kAtOnce; ++u)
+        if (u < cnt) reinterpret_cast<float4 *>(st.rows + static_cast<size_t>(h[u]) * st.stride)[c] = v[u];
+    }
+  }
 }
 
 template <int M>
@@ -755,13 +1002,17 @@ __global__ __launch_bounds__(kBlock) void k_select(DevState st) {
 // Each item runs the very device function, template and lane grouping of the
 // plain launch, so every instance computes bit-identically to running alone.
 // ----------------------------------------------------------------------------
+// Lane-group variation of one work item with the instance's lane count (the
+// task-dealt kernel has batched kernels of its own, so that these keep no LDS
+// for it).
 template <int M, int FAM>
 __device__ __forceinline__ void vary_any_lanes(const DevState &st, int L) {
-  switch (vary_lanes_of(st.stride)) {
-    case 8: vary_body<M, FAM, 8>(st, L, vary_blocks_of(st.n, 8)); break;
-    case 4: vary_body<M, FAM, 4>(st, L, vary_blocks_of(st.n, 4)); break;
-    case 2: vary_body<M, FAM, 2>(st, L, vary_blocks_of(st.n, 2)); break;
-    default: vary_body<M, FAM, 1>(st, L, vary_blocks_of(st.n, 1)); break;
+  const int G = vary_grid(st);
+  switch (vary_lanes_of(st)) {
+    case 8: vary_body<M, FAM, 8>(st, L, G); break;
+    case 4: vary_body<M, FAM, 4>(st, L, G); break;
+    case 2: vary_body<M, FAM, 2>(st, L, G); break;
+    default: vary_body<M, FAM, 1>(st, L, G); break;
   }
 }
 

@@ -47,20 +47,32 @@ struct DevProblem {
 // cv) up to three objectives, else enough for m objectives and the CV.
 __host__ __device__ constexpr int rec_quads(int m) { return m <= 3 ? 1 : (m + 4) / 4; }
 
-// Device state of one instance. Rows of X are `stride` floats (d rounded up to a
-// multiple of 4 so that every row starts 16-byte aligned); F and CV of one
-// individual share a record of rq = rec_quads(m) float4: objectives from the
-// first lane, CV in the last lane, unused lanes 0. W rows have the same width.
+// Device state of one instance. Decision vectors live in one row arena of
+// `stride` floats per row (a multiple of 4, at least 4 nq, so that every row
+// starts 16-byte aligned), in six regions of `region` rows: regions 0 and 1 are
+// the home rows of populations 1 and 2 (slot j at row j), region 2 + 2 par + q
+// holds the offspring of population q written by a generation of parity par.
+// A slot's current decision vector is the arena row loc[p][j]: a replaced slot
+// points at its winning offspring row, so the replacement moves a 4-byte
+// location instead of a row. F and CV of one individual share a record of
+// rq = rec_quads(m) float4: objectives from the first lane, CV in the last
+// lane, unused lanes 0. W rows have the same width.
 struct DevState {
   int32_t n, m, d, stride, nblk;  // nblk: blocks of kBlock rows per population
+  int32_t nq;                      // float4 chunks holding the d variables
+  int32_t tasked;                  // variation kernel: 1 task-dealt, 0 lane groups
   int32_t rq;                      // float4 per F/CV record and per W row
   int32_t t[2];
   int32_t lps[2];                  // lanes per slot in k_select (power of two <= 64)
   int32_t sel_blocks0, sel_blocks1;  // k_select blocks of each population
   int32_t agg;
   float theta;
-  float *X[2], *XO[2];
-  int32_t *rsrc[2];          // replacement of slot j: -1 kept, else (population << 30) | offspring row
+  float *rows;               // the row arena (6 regions)
+  int64_t region;            // rows per region (nblk kBlock)
+  float *X[2];               // home rows: regions 0 and 1
+  uint32_t *loc[2];          // arena row of slot j's current decision vector
+  int32_t *rsrc[2];          // this generation's decision for slot j: -1 kept, else
+                             // (population << 30) | offspring row
   float4 *FC[2], *FCO[2], *FCN[2];
   float4 *W;                 // unit direction (PBI) or raw weight (Tchebycheff)
   const int32_t *B[2];       // n x t_p
@@ -90,48 +102,62 @@ struct DevState {
 
 // Launch geometry shared by host and device (plain and batched launches must
 // agree on it, since it fixes the lane grouping and so the rounding order).
-// Lanes per offspring in k_vary: enough that each lane keeps two to four float4
-// chunks of the row, except the widest rows (d > 92), where four lanes of six
-// or seven chunks each measured faster than eight.
-__host__ __device__ inline int vary_lanes_of(int stride) {
-  const int nq = stride >> 2;
+// Variation kernels, fixed per instance (plain and batched launches must agree,
+// since the kernel fixes the evaluation's rounding order). The lane-group
+// kernel takes vary_lanes_of_chunks(nq) lanes per offspring: enough that each
+// lane keeps two to four float4 chunks, except the widest rows (d > 92),
+// where four lanes of six or seven chunks each measured faster than eight.
+// The task-dealt kernel (a wave builds 64 offspring, 256 per block; rows of at
+// most kTaskChunks chunks, d <= 128) is opt-in (GMPEA_TASKED=1 at gmpea_init):
+// it measured slower on the large workload (77 against 58 us for the variation
+// at N = 100,128) and faster only beyond the last-level cache (519 against
+// 560 us at N = 1,000,405).
+constexpr int kTaskChunks = 32;
+__host__ __device__ inline int vary_lanes_of_chunks(int nq) {
   return nq >= 24 ? 4 : nq >= 16 ? 8 : nq >= 6 ? 4 : nq >= 3 ? 2 : 1;
+}
+__host__ __device__ inline bool vary_tasked(const DevState &st) { return st.tasked != 0; }
+__host__ __device__ inline int vary_lanes_of(const DevState &st) {
+  return vary_tasked(st) ? 1 : vary_lanes_of_chunks(st.nq);
+}
+// Arena row of offspring i of population q written by a generation of parity par.
+__host__ __device__ inline uint32_t offspring_row(const DevState &st, uint32_t par, int q, int i) {
+  return static_cast<uint32_t>((2 + 2 * static_cast<int64_t>(par) + q) * st.region + i);
 }
 // k_vary blocks of one instance (both populations).
 __host__ __device__ inline int vary_blocks_of(int n, int lanes) {
   const int per = kBlock / lanes;
   return 2 * ((n + per - 1) / per);
 }
+__host__ __device__ inline int vary_grid(const DevState &st) { return vary_blocks_of(st.n, vary_lanes_of(st)); }
 
 // Launchers (gmpea_kernels.hip). Each enqueues on `s` and returns the launch status.
 hipError_t launch_init(const DevState &st, hipStream_t s);
 // A generation is kPhases launches: 0 variation + evaluation + ideal point,
-// 1 offspring cooperation, 2 neighbour replacement decisions, 3 row copies.
+// 1 offspring cooperation, 2 neighbour replacement decisions, 3 locations (a
+// replaced slot points at its winner; a kept slot whose row the next
+// generation's offspring would overwrite copies it home).
 constexpr int kPhases = 4;
-// Row copies: a batched work item copies kRowsIterBatch runs of kBlock float4
-// elements of both populations' rows (each item also fetches its entry and
-// instance state); the plain launch strides a grid of at most kRowsGrid blocks
-// (eight per CU) over the elements, which saves the dispatch of one block per
-// run. The copies do not depend on how they are split.
-constexpr int kRowsIterBatch = 4;
-constexpr int kRowsGrid = 2048;
-__host__ __device__ inline int rows_blocks_of(int n, int stride, int iters = 1) {
-  const long long e = 2LL * n * (stride >> 2);
-  const long long per = static_cast<long long>(kBlock) * iters;
-  return static_cast<int>((e + per - 1) / per);
-}
+// Blocks of the location phase: one thread per slot of both populations.
+__host__ __device__ inline int remap_blocks_of(int n) { return (2 * n + kBlock - 1) / kBlock; }
 hipError_t launch_phase(const DevState &st, int phase, hipStream_t s);
+// Point every slot of population `pop` at its home row (after the home rows were written).
+hipError_t launch_loc_home(const DevState &st, int pop, hipStream_t s);
+// Copy every slot's current decision vector to its home row and point it there.
+hipError_t launch_materialize(const DevState &st, hipStream_t s);
 hipError_t launch_generation(const DevState &st, hipStream_t s);
 // One phase of a batched generation over a pool: work[b] = (instance, block).
 // wide: the work list holds instances with m > 3 (their kernels are separate so
 // that the m <= 3 kernels keep their register budget); phase 3 takes any m.
+// tasked: the pool's instances take the task-dealt variation (a pool holds
+// instances of one variation kernel).
 hipError_t launch_batch_phase(const DevState *states, const int2 *work, int nwork, int phase,
-                              bool wide, hipStream_t s);
+                              bool wide, bool tasked, hipStream_t s);
 // The m > 3 launchers (gmpea_kernels_wide.hip).
 hipError_t launch_init_eval_wide(const DevState &st, hipStream_t s);
 hipError_t launch_phase_wide(const DevState &st, int phase, hipStream_t s);
 hipError_t launch_batch_phase_wide(const DevState *states, const int2 *work, int nwork, int phase,
-                                   hipStream_t s);
+                                   bool tasked, hipStream_t s);
 hipError_t launch_front_flags_wide(const DevState &st, int pop, uint8_t *keep, hipStream_t s);
 hipError_t launch_front_flags(const DevState &st, int pop, uint8_t *keep, hipStream_t s);
 hipError_t launch_gather(const DevState &st, int pop, const int32_t *idx, int32_t count,
@@ -205,7 +231,8 @@ hipError_t launch_tables(int32_t m, int32_t n, int32_t H, const int2 *offs, int3
                          int32_t t1, int32_t t2, int32_t agg, float4 *W, int32_t *B1, int32_t *B2,
                          uint32_t *incomplete, hipStream_t s);
 // Reverse lists of B (n x t), in two launches around a host read of the tail
-// size. launch_reverse_count: cursor (n, zero on entry) receives each list's
+// size. launch_reverse_count: cursor (n + ceil((n + 1) / 1024) entries, the first n
+// zero on entry; the rest is scratch of the scan) receives each list's
 // length and toff (n + 1, zero on entry) the exclusive scan of the lengths in
 // excess of t, so toff[n] is the tail size. launch_reverse_fill: head (n x t)
 // and tail receive the lists, each ascending (cursor must be zero again).

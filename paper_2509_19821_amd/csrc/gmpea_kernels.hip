@@ -15,15 +15,19 @@
 //             reverse neighbour list of j (every offspring i with j in B_p(i)),
 //             lexicographic minimum of the qualifiers; writes the winner's F/CV
 //             and the slot's replacement record.
-//   k_rows    one float4 per thread over both populations: replaced slots take
-//             their winning offspring rows.
+//   k_remap   one thread per slot: a replaced slot's location becomes its
+//             winning offspring row; a kept slot whose row lies where the next
+//             generation writes its offspring copies it to its home row.
 // The ideal point is a grid-wide dependency between k_vary and k_op1, OP1 must
 // finish for every i before any slot can be decided, and every decision reads
-// generation-k parents before any row is overwritten; kernel boundaries provide
+// generation-k parents before any location changes; kernel boundaries provide
 // all three.
 //
-// Layout: X rows are `stride` floats (16-byte aligned), so a row copy is a run
-// of float4 moves; F and CV share one float4 per individual for m <= 3.
+// Layout: decision vectors are rows of `stride` floats (16-byte aligned) in one
+// arena: home rows of both populations, then offspring rows of each population
+// for even and odd generations. A slot reads its current row through its
+// location, so the replacement moves no rows. F and CV share one float4 per
+// individual for m <= 3.
 // Blocks are remapped so that consecutive row tiles run on the same XCD (the
 // hardware deals blocks to the 8 XCDs round-robin): neighbouring subproblems
 // share parents and candidates, and then share that XCD's L2.
@@ -43,25 +47,55 @@ namespace gmpea {
 // evaluation, ideal point.
 // ----------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_init(DevState st) {
-  const int L = xcd_tile(blockIdx.x, gridDim.x);
-  const int p = L >= st.nblk ? 1 : 0;
-  const int i = (L - p * st.nblk) * kBlock + threadIdx.x;
-  if (i >= st.n) return;
-  float *row = st.X[p] + static_cast<size_t>(i) * st.stride;
-  uint4 w = make_uint4(0, 0, 0, 0);
-  for (int l = 0; l < st.stride; ++l) {
-    float x = 0.0f;
+  // one thread per float4 chunk (row, q) of both populations, consecutive
+  // threads on consecutive chunks of a row: chunk q takes the four words of the
+  // INIT block q (variable l = 4 q + w), padding variables are 0; chunk 0 also
+  // points the slot at its home row
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  const int64_t per = static_cast<int64_t>(st.n) * st.nq;
+  if (e >= 2 * per) return;
+  const int p = e >= per ? 1 : 0;
+  const int64_t r = e - p * per;
+  const int i = static_cast<int>(r / st.nq);
+  const int q = static_cast<int>(r - static_cast<int64_t>(i) * st.nq);
+  const uint4 w = philox10(make_uint4(q, i, 0u, (kTagInit << 24) | (p << 16)), st.key0, st.key1);
+  const uint32_t words[4] = {w.x, w.y, w.z, w.w};
+  float x[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int l = 4 * q + u;
+    x[u] = 0.0f;
     if (l < st.d) {
-      if ((l & 3) == 0)
-        w = philox10(make_uint4(l >> 2, i, 0u, (kTagInit << 24) | (p << 16)), st.key0, st.key1);
-      const uint32_t word = (l & 3) == 0 ? w.x : (l & 3) == 1 ? w.y : (l & 3) == 2 ? w.z : w.w;
       const float lo = st.prob.lb[l], hi = st.prob.ub[l];
-      x = fmaf(hi - lo, u24(word), lo);
+      x[u] = fmaf(hi - lo, u24(words[u]), lo);
     }
-    row[l] = x;
   }
+  reinterpret_cast<float4 *>(st.X[p] + static_cast<size_t>(i) * st.stride)[q] =
+      make_float4(x[0], x[1], x[2], x[3]);
+  if (q == 0) st.loc[p][i] = static_cast<uint32_t>(p * st.region + i);
 }
 
+// Every slot of population `pop` points at its home row.
+__global__ __launch_bounds__(kBlock) void k_loc_home(DevState st, int pop) {
+  const int j = blockIdx.x * kBlock + threadIdx.x;
+  if (j < st.n) st.loc[pop][j] = static_cast<uint32_t>(pop * st.region + j);
+}
+
+// Copy of every slot's current decision vector to its home row, one thread per
+// float4 chunk (sources are offspring rows or the home row itself, never
+// another slot's home row); k_loc_home then points the slots there.
+__global__ __launch_bounds__(kBlock) void k_materialize(DevState st) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  const int64_t per = static_cast<int64_t>(st.n) * st.nq;
+  if (e >= 2 * per) return;
+  const int p = e >= per ? 1 : 0;
+  const int64_t r = e - p * per;
+  const int j = static_cast<int>(r / st.nq);
+  const int q = static_cast<int>(r - static_cast<int64_t>(j) * st.nq);
+  const uint32_t l = st.loc[p][j], home = static_cast<uint32_t>(p * st.region + j);
+  if (l != home)
+    reinterpret_cast<float4 *>(st.rows + static_cast<size_t>(home) * st.stride)[q] = arena_row(st, l)[q];
+}
 
 // ----------------------------------------------------------------------------
 // Initialisation tables (Alg. 1 inputs): reference vectors and neighbourhoods.
@@ -148,19 +182,39 @@ __global__ __launch_bounds__(kBlock) void k_rev_excess(int32_t n, int32_t t, con
   if (j < n) toff[j + 1] = max(cnt[j] - t, 0);
 }
 
-constexpr int kScanThreads = 1024;
+// Inclusive scan of off[0 .. len) in three launches: per-tile sums (tiles of
+// kScanTile entries), one block scanning the tile sums, then every tile adding
+// its prefix (kScanTile threads per tile, one entry each).
+constexpr int kScanTile = 1024;
 
-// In-place inclusive scan of off[0 .. len) by one block.
-__global__ __launch_bounds__(kScanThreads) void k_scan(int32_t *off, int32_t len) {
-  __shared__ int32_t part[kScanThreads];
+__global__ __launch_bounds__(kScanTile) void k_scan_tiles(const int32_t *__restrict__ off, int32_t len,
+                                                          int32_t *__restrict__ sums) {
+  __shared__ int32_t red[kScanTile / 64];
+  const int64_t q = static_cast<int64_t>(blockIdx.x) * kScanTile + threadIdx.x;
+  int32_t v = q < len ? off[q] : 0;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int32_t t = 0;
+    for (int w = 0; w < kScanTile / 64; ++w) t += red[w];
+    sums[blockIdx.x] = t;
+  }
+}
+
+// Exclusive scan of the tile sums in place, by one block (each thread a
+// contiguous run of them).
+__global__ __launch_bounds__(kScanTile) void k_scan_sums(int32_t *sums, int32_t tiles) {
+  __shared__ int32_t part[kScanTile];
   const int tid = threadIdx.x;
-  const int per = (len + kScanThreads - 1) / kScanThreads;
-  const int lo = min(len, tid * per), hi = min(len, lo + per);
+  const int per = (tiles + kScanTile - 1) / kScanTile;
+  const int lo = min(tiles, tid * per), hi = min(tiles, lo + per);
   int32_t sum = 0;
-  for (int q = lo; q < hi; ++q) sum += off[q];
+  for (int q = lo; q < hi; ++q) sum += sums[q];
   part[tid] = sum;
   __syncthreads();
-  for (int o = 1; o < kScanThreads; o <<= 1) {
+  for (int o = 1; o < kScanTile; o <<= 1) {
     const int32_t v = tid >= o ? part[tid - o] : 0;
     __syncthreads();
     part[tid] += v;
@@ -168,9 +222,26 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(int32_t *off, int32_t len
   }
   int32_t run = tid > 0 ? part[tid - 1] : 0;
   for (int q = lo; q < hi; ++q) {
-    run += off[q];
-    off[q] = run;
+    const int32_t v = sums[q];
+    sums[q] = run;
+    run += v;
   }
+}
+
+__global__ __launch_bounds__(kScanTile) void k_scan_add(int32_t *__restrict__ off, int32_t len,
+                                                        const int32_t *__restrict__ sums) {
+  __shared__ int32_t part[kScanTile];
+  const int tid = threadIdx.x;
+  const int64_t q = static_cast<int64_t>(blockIdx.x) * kScanTile + tid;
+  part[tid] = q < len ? off[q] : 0;
+  __syncthreads();
+  for (int o = 1; o < kScanTile; o <<= 1) {
+    const int32_t v = tid >= o ? part[tid - o] : 0;
+    __syncthreads();
+    part[tid] += v;
+    __syncthreads();
+  }
+  if (q < len) off[q] = part[tid] + sums[blockIdx.x];
 }
 
 __global__ __launch_bounds__(kBlock) void k_rev_fill(int64_t nt, int32_t t, const int32_t *__restrict__ B,
@@ -189,35 +260,60 @@ __global__ __launch_bounds__(kBlock) void k_rev_fill(int64_t nt, int32_t t, cons
     tail[toff[j] + pos - t] = i;
 }
 
+// Each list sorted ascending by one wave: the wave stages the list (head
+// entries, then its tail) in LDS, each lane ranks its entries by counting the
+// smaller ones (the entries of a list are distinct) and writes every entry at
+// its rank. A list longer than kRevSortMax (not met by lattice neighbourhoods,
+// whose lists hold about t entries) is sorted by one lane in place.
+constexpr int kRevSortMax = 512;
+
 __global__ __launch_bounds__(kBlock) void k_rev_sort(int32_t n, int32_t t, const int32_t *__restrict__ toff,
                                                     int32_t *__restrict__ head,
                                                     int32_t *__restrict__ tail) {
-  const int32_t j = blockIdx.x * kBlock + threadIdx.x;
-  if (j >= n) return;
-  int32_t *h = head + static_cast<size_t>(j) * t;
-  int32_t *tl = tail + toff[j];
-  const int32_t ext = toff[j + 1] - toff[j];
-  int32_t len = 0;
-  while (len < t && h[len] >= 0) ++len;
-  len += ext;
-  // element k of the list: head for k < t, tail beyond
-  auto at = [&](int32_t k) -> int32_t & { return k < t ? h[k] : tl[k - t]; };
-  for (int32_t q = 1; q < len; ++q) {
-    const int32_t v = at(q);
-    int32_t r = q - 1;
-    while (r >= 0 && at(r) > v) {
-      at(r + 1) = at(r);
-      --r;
+  __shared__ int32_t buf[kBlock / 64][kRevSortMax];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int32_t j = blockIdx.x * (kBlock / 64) + wv;
+  int32_t len = 0, ext = 0;
+  int32_t *h = nullptr, *tl = nullptr;
+  if (j < n) {  // uniform per wave
+    h = head + static_cast<size_t>(j) * t;
+    tl = tail + toff[j];
+    ext = toff[j + 1] - toff[j];
+    // the head holds the first min(length, t) entries, then -1
+    int32_t hl = 0;
+    for (int32_t k0 = 0; k0 < t; k0 += 64) {
+      const int32_t k = k0 + lane;
+      hl += __popcll(__ballot(k < t && h[k] >= 0));
     }
-    at(r + 1) = v;
+    len = hl + ext;
+  }
+  auto at = [&](int32_t k) -> int32_t & { return k < t ? h[k] : tl[k - t]; };
+  const bool staged = j < n && len <= kRevSortMax;
+  if (staged)
+    for (int32_t k = lane; k < len; k += 64) buf[wv][k] = at(k);
+  __syncthreads();
+  if (staged) {
+    for (int32_t k = lane; k < len; k += 64) {
+      const int32_t v = buf[wv][k];
+      int32_t rank = 0;
+      for (int32_t u = 0; u < len; ++u) rank += buf[wv][u] < v ? 1 : 0;
+      at(rank) = v;
+    }
+  } else if (j < n && lane == 0) {
+    for (int32_t q = 1; q < len; ++q) {
+      const int32_t v = at(q);
+      int32_t r = q - 1;
+      while (r >= 0 && at(r) > v) {
+        at(r + 1) = at(r);
+        --r;
+      }
+      at(r + 1) = v;
+    }
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_rows(DevState st) {
-  const int64_t total = 2LL * st.n * (st.stride >> 2);
-  const int64_t step = static_cast<int64_t>(gridDim.x) * kBlock;
-  for (int64_t e = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; e < total; e += step)
-    rows_body(st, e);
+__global__ __launch_bounds__(kBlock) void k_remap(DevState st) {
+  remap_body(st, static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x);
 }
 
 __global__ __launch_bounds__(kBlock) void k_vary_batch(const DevState *__restrict__ S,
@@ -231,6 +327,19 @@ __global__ __launch_bounds__(kBlock) void k_vary_batch(const DevState *__restric
     vary_any_lanes<2, 1>(st, wi.y);
   else
     vary_any_lanes<3, 1>(st, wi.y);
+}
+
+__global__ __launch_bounds__(kBlock) void k_tvary_batch(const DevState *__restrict__ S,
+                                                       const int2 *__restrict__ work) {
+  const int2 wi = work[blockIdx.x];
+  if (wi.x < 0) return;
+  const DevState &st = S[wi.x];
+  if (st.m == 2 && st.prob.family == 0)
+    tvary_body<2, 0>(st, wi.y, vary_grid(st));
+  else if (st.m == 2)
+    tvary_body<2, 1>(st, wi.y, vary_grid(st));
+  else
+    tvary_body<3, 1>(st, wi.y, vary_grid(st));
 }
 
 __global__ __launch_bounds__(kBlock) void k_op1_batch(const DevState *__restrict__ S,
@@ -255,14 +364,11 @@ __global__ __launch_bounds__(kBlock) void k_select_batch(const DevState *__restr
     select_body<3>(st, wi.y);
 }
 
-__global__ __launch_bounds__(kBlock) void k_rows_batch(const DevState *__restrict__ S,
-                                                      const int2 *__restrict__ work) {
+__global__ __launch_bounds__(kBlock) void k_remap_batch(const DevState *__restrict__ S,
+                                                       const int2 *__restrict__ work) {
   const int2 wi = work[blockIdx.x];
   if (wi.x < 0) return;
-  const DevState &st = S[wi.x];
-  const int64_t e0 = static_cast<int64_t>(wi.y) * kRowsIterBatch * kBlock + threadIdx.x;
-#pragma unroll
-  for (int k = 0; k < kRowsIterBatch; ++k) rows_body(st, e0 + static_cast<int64_t>(k) * kBlock);
+  remap_body(S[wi.x], static_cast<int64_t>(wi.y) * kBlock + threadIdx.x);
 }
 
 // Rows idx[0 .. count) of population `pop`: decision vectors to x (count x d)
@@ -273,7 +379,7 @@ __global__ __launch_bounds__(kBlock) void k_gather(DevState st, int pop, const i
   if (r >= count) return;
   const int row = idx[r];
   if (x) {
-    const float *srcx = st.X[pop] + static_cast<size_t>(row) * st.stride;
+    const float *srcx = reinterpret_cast<const float *>(arena_row(st, st.loc[pop][row]));
     for (int l = threadIdx.x; l < st.d; l += blockDim.x) x[static_cast<size_t>(r) * st.d + l] = srcx[l];
   }
   if (fc && threadIdx.x < st.rq)
@@ -546,6 +652,16 @@ hipError_t launch_tables(int32_t m, int32_t n, int32_t H, const int2 *offs, int3
   return hipGetLastError();
 }
 
+// Inclusive scan of off[0 .. len) with tile sums in `sums` (room for
+// ceil(len / kScanTile) entries).
+static hipError_t launch_scan(int32_t *off, int32_t len, int32_t *sums, hipStream_t s) {
+  const int32_t tiles = (len + kScanTile - 1) / kScanTile;
+  hipLaunchKernelGGL(k_scan_tiles, dim3(tiles), dim3(kScanTile), 0, s, off, len, sums);
+  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kScanTile), 0, s, sums, tiles);
+  hipLaunchKernelGGL(k_scan_add, dim3(tiles), dim3(kScanTile), 0, s, off, len, static_cast<const int32_t *>(sums));
+  return hipGetLastError();
+}
+
 hipError_t launch_reverse_count(int32_t n, int32_t t, const int32_t *B, int32_t *cursor,
                                 int32_t *toff, hipStream_t s) {
   const int64_t nt = static_cast<int64_t>(n) * t;
@@ -553,8 +669,7 @@ hipError_t launch_reverse_count(int32_t n, int32_t t, const int32_t *B, int32_t 
   hipLaunchKernelGGL(k_rev_count, dim3(grid), dim3(kBlock), 0, s, nt, B, cursor);
   hipLaunchKernelGGL(k_rev_excess, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, n, t,
                      static_cast<const int32_t *>(cursor), toff);
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, s, toff, n + 1);
-  return hipGetLastError();
+  return launch_scan(toff, n + 1, cursor + n, s);
 }
 
 hipError_t launch_reverse_fill(int32_t n, int32_t t, const int32_t *B, const int32_t *toff,
@@ -562,80 +677,111 @@ hipError_t launch_reverse_fill(int32_t n, int32_t t, const int32_t *B, const int
   const int64_t nt = static_cast<int64_t>(n) * t;
   const unsigned grid = static_cast<unsigned>((nt + kBlock - 1) / kBlock);
   hipLaunchKernelGGL(k_rev_fill, dim3(grid), dim3(kBlock), 0, s, nt, t, B, toff, cursor, head, tail);
-  hipLaunchKernelGGL(k_rev_sort, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, n, t, toff,
-                     head, tail);
+  hipLaunchKernelGGL(k_rev_sort, dim3((n + kBlock / 64 - 1) / (kBlock / 64)), dim3(kBlock), 0, s, n, t,
+                     toff, head, tail);
   return hipGetLastError();
 }
 
-template <int LPO>
+// Initial evaluation in the order the variation kernel for this row width
+// evaluates its offspring (so a copy of an individual evaluates bitwise equal).
+template <int M, int FAM, int LPO>
 static void launch_eval_lpo(const DevState &st, hipStream_t s) {
-  const int grid = vary_blocks_of(st.n, LPO);
-  if (st.m == 2 && st.prob.family == 0)
-    hipLaunchKernelGGL((k_eval<2, 0, LPO>), dim3(grid), dim3(kBlock), 0, s, st);
-  else if (st.m == 2)
-    hipLaunchKernelGGL((k_eval<2, 1, LPO>), dim3(grid), dim3(kBlock), 0, s, st);
-  else
-    hipLaunchKernelGGL((k_eval<3, 1, LPO>), dim3(grid), dim3(kBlock), 0, s, st);
+  hipLaunchKernelGGL((k_eval<M, FAM, LPO>), dim3(vary_blocks_of(st.n, LPO)), dim3(kBlock), 0, s, st);
+}
+
+template <int M, int FAM>
+static void launch_eval_mf(const DevState &st, hipStream_t s) {
+  if (vary_tasked(st)) {
+    hipLaunchKernelGGL((k_teval<M, FAM>), dim3(2 * st.nblk), dim3(kBlock), 0, s, st);
+    return;
+  }
+  switch (vary_lanes_of(st)) {
+    case 8: launch_eval_lpo<M, FAM, 8>(st, s); break;
+    case 4: launch_eval_lpo<M, FAM, 4>(st, s); break;
+    case 2: launch_eval_lpo<M, FAM, 2>(st, s); break;
+    default: launch_eval_lpo<M, FAM, 1>(st, s); break;
+  }
 }
 
 hipError_t launch_init(const DevState &st, hipStream_t s) {
-  hipLaunchKernelGGL(k_init, dim3(2 * st.nblk), dim3(kBlock), 0, s, st);
+  const int64_t chunks = 2LL * st.n * st.nq;
+  hipLaunchKernelGGL(k_init, dim3(static_cast<unsigned>((chunks + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+                     st);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (st.m > 3) return launch_init_eval_wide(st, s);
-  switch (vary_lanes_of(st.stride)) {
-    case 8: launch_eval_lpo<8>(st, s); break;
-    case 4: launch_eval_lpo<4>(st, s); break;
-    case 2: launch_eval_lpo<2>(st, s); break;
-    default: launch_eval_lpo<1>(st, s); break;
-  }
+  if (st.m == 2 && st.prob.family == 0)
+    launch_eval_mf<2, 0>(st, s);
+  else if (st.m == 2)
+    launch_eval_mf<2, 1>(st, s);
+  else
+    launch_eval_mf<3, 1>(st, s);
   return hipGetLastError();
 }
 
-template <int LPO>
-static void launch_vary_lpo(const DevState &st, hipStream_t s) {
-  const int grid = vary_blocks_of(st.n, LPO);
-  if (st.m == 2 && st.prob.family == 0)
-    hipLaunchKernelGGL((k_vary<2, 0, LPO>), dim3(grid), dim3(kBlock), 0, s, st);
-  else if (st.m == 2)
-    hipLaunchKernelGGL((k_vary<2, 1, LPO>), dim3(grid), dim3(kBlock), 0, s, st);
-  else
-    hipLaunchKernelGGL((k_vary<3, 1, LPO>), dim3(grid), dim3(kBlock), 0, s, st);
+template <int M, int FAM>
+static void launch_vary_mf(const DevState &st, hipStream_t s) {
+  const int grid = vary_grid(st);
+  if (vary_tasked(st)) {
+    hipLaunchKernelGGL((k_tvary<M, FAM>), dim3(grid), dim3(kBlock), 0, s, st);
+    return;
+  }
+  switch (vary_lanes_of(st)) {
+    case 8: hipLaunchKernelGGL((k_vary<M, FAM, 8>), dim3(grid), dim3(kBlock), 0, s, st); break;
+    case 4: hipLaunchKernelGGL((k_vary<M, FAM, 4>), dim3(grid), dim3(kBlock), 0, s, st); break;
+    case 2: hipLaunchKernelGGL((k_vary<M, FAM, 2>), dim3(grid), dim3(kBlock), 0, s, st); break;
+    default: hipLaunchKernelGGL((k_vary<M, FAM, 1>), dim3(grid), dim3(kBlock), 0, s, st); break;
+  }
 }
 
 hipError_t launch_phase(const DevState &st, int phase, hipStream_t s) {
   if (st.m > 3 && phase < 3) return launch_phase_wide(st, phase, s);
   if (phase == 0) {
-    switch (vary_lanes_of(st.stride)) {
-      case 8: launch_vary_lpo<8>(st, s); break;
-      case 4: launch_vary_lpo<4>(st, s); break;
-      case 2: launch_vary_lpo<2>(st, s); break;
-      default: launch_vary_lpo<1>(st, s); break;
-    }
+    if (st.m == 2 && st.prob.family == 0)
+      launch_vary_mf<2, 0>(st, s);
+    else if (st.m == 2)
+      launch_vary_mf<2, 1>(st, s);
+    else
+      launch_vary_mf<3, 1>(st, s);
   } else if (phase == 1) {
     GMPEA_DISPATCH_M(k_op1, st.nblk, s, st);
   } else if (phase == 2) {
     GMPEA_DISPATCH_M(k_select, st.sel_blocks0 + st.sel_blocks1, s, st);
   } else {
-    hipLaunchKernelGGL(k_rows, dim3(std::min(rows_blocks_of(st.n, st.stride), kRowsGrid)), dim3(kBlock), 0, s,
-                       st);
+    hipLaunchKernelGGL(k_remap, dim3(remap_blocks_of(st.n)), dim3(kBlock), 0, s, st);
   }
   return hipGetLastError();
 }
 
 hipError_t launch_batch_phase(const DevState *states, const int2 *work, int nwork, int phase,
-                              bool wide, hipStream_t s) {
+                              bool wide, bool tasked, hipStream_t s) {
   if (nwork <= 0) return hipSuccess;
-  if (wide && phase < 3) return launch_batch_phase_wide(states, work, nwork, phase, s);
-  if (phase == 0)
+  if (wide && phase < 3) return launch_batch_phase_wide(states, work, nwork, phase, tasked, s);
+  if (phase == 0 && tasked)
+    hipLaunchKernelGGL(k_tvary_batch, dim3(nwork), dim3(kBlock), 0, s, states, work);
+  else if (phase == 0)
     hipLaunchKernelGGL(k_vary_batch, dim3(nwork), dim3(kBlock), 0, s, states, work);
   else if (phase == 1)
     hipLaunchKernelGGL(k_op1_batch, dim3(nwork), dim3(kBlock), 0, s, states, work);
   else if (phase == 2)
     hipLaunchKernelGGL(k_select_batch, dim3(nwork), dim3(kBlock), 0, s, states, work);
   else
-    hipLaunchKernelGGL(k_rows_batch, dim3(nwork), dim3(kBlock), 0, s, states, work);
+    hipLaunchKernelGGL(k_remap_batch, dim3(nwork), dim3(kBlock), 0, s, states, work);
   return hipGetLastError();
+}
+
+hipError_t launch_loc_home(const DevState &st, int pop, hipStream_t s) {
+  hipLaunchKernelGGL(k_loc_home, dim3(st.nblk), dim3(kBlock), 0, s, st, pop);
+  return hipGetLastError();
+}
+
+hipError_t launch_materialize(const DevState &st, hipStream_t s) {
+  const int64_t chunks = 2LL * st.n * st.nq;
+  hipLaunchKernelGGL(k_materialize, dim3(static_cast<unsigned>((chunks + kBlock - 1) / kBlock)), dim3(kBlock),
+                     0, s, st);
+  hipError_t e = hipGetLastError();
+  for (int p = 0; p < 2 && e == hipSuccess; ++p) e = launch_loc_home(st, p, s);
+  return e;
 }
 
 hipError_t launch_generation(const DevState &st, hipStream_t s) {

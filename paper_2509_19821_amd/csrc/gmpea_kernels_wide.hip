@@ -6,7 +6,7 @@
 // is the largest over the m values it dispatches.
 //
 // Per m the generation is the m <= 3 one: k_vary (mating, variation,
-// evaluation, ideal point), k_op1, k_select, then the shared row copies.
+// evaluation, ideal point), k_op1, k_select, then the shared location phase.
 // Register use grows with m through the records a k_select lane keeps (its
 // parent, weight, best candidate and four candidates in flight); the evaluation
 // keeps the leading variables (the m - 1 angles) of its group's first chunks.
@@ -20,6 +20,16 @@
 namespace gmpea {
 
 template <class F>
+static void with_lanes(const DevState &st, F &&f) {
+  switch (vary_lanes_of(st)) {
+    case 8: f(std::integral_constant<int, 8>{}); break;
+    case 4: f(std::integral_constant<int, 4>{}); break;
+    case 2: f(std::integral_constant<int, 2>{}); break;
+    default: f(std::integral_constant<int, 1>{}); break;
+  }
+}
+
+template <class F>
 static void with_wide_m(int m, F &&f) {
   switch (m) {
     case 4: f(std::integral_constant<int, 4>{}); break;
@@ -27,16 +37,6 @@ static void with_wide_m(int m, F &&f) {
     case 6: f(std::integral_constant<int, 6>{}); break;
     case 7: f(std::integral_constant<int, 7>{}); break;
     default: f(std::integral_constant<int, 8>{}); break;
-  }
-}
-
-template <class F>
-static void with_lanes(int stride, F &&f) {
-  switch (vary_lanes_of(stride)) {
-    case 8: f(std::integral_constant<int, 8>{}); break;
-    case 4: f(std::integral_constant<int, 4>{}); break;
-    case 2: f(std::integral_constant<int, 2>{}); break;
-    default: f(std::integral_constant<int, 1>{}); break;
   }
 }
 
@@ -57,6 +57,20 @@ __global__ __launch_bounds__(kBlock) void k_vary_batch_w(const DevState *__restr
     case 6: vary_batch_m<6>(st, wi.y); break;
     case 7: vary_batch_m<7>(st, wi.y); break;
     default: vary_batch_m<8>(st, wi.y); break;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_tvary_batch_w(const DevState *__restrict__ S,
+                                                         const int2 *__restrict__ work) {
+  const int2 wi = work[blockIdx.x];
+  if (wi.x < 0) return;
+  const DevState &st = S[wi.x];
+  switch (st.m) {
+    case 4: tvary_body<4, 1>(st, wi.y, vary_grid(st)); break;
+    case 5: tvary_body<5, 1>(st, wi.y, vary_grid(st)); break;
+    case 6: tvary_body<6, 1>(st, wi.y, vary_grid(st)); break;
+    case 7: tvary_body<7, 1>(st, wi.y, vary_grid(st)); break;
+    default: tvary_body<8, 1>(st, wi.y, vary_grid(st)); break;
   }
 }
 
@@ -91,11 +105,13 @@ __global__ __launch_bounds__(kBlock) void k_select_batch_w(const DevState *__res
 hipError_t launch_init_eval_wide(const DevState &st, hipStream_t s) {
   with_wide_m(st.m, [&](auto mc) {
     constexpr int M = decltype(mc)::value;
-    with_lanes(st.stride, [&](auto lc) {
-      constexpr int LPO = decltype(lc)::value;
-      hipLaunchKernelGGL((k_eval<M, 1, LPO>), dim3(vary_blocks_of(st.n, LPO)), dim3(kBlock), 0, s,
-                         st);
-    });
+    if (vary_tasked(st))
+      hipLaunchKernelGGL((k_teval<M, 1>), dim3(2 * st.nblk), dim3(kBlock), 0, s, st);
+    else
+      with_lanes(st, [&](auto lc) {
+        constexpr int LPO = decltype(lc)::value;
+        hipLaunchKernelGGL((k_eval<M, 1, LPO>), dim3(vary_blocks_of(st.n, LPO)), dim3(kBlock), 0, s, st);
+      });
   });
   return hipGetLastError();
 }
@@ -104,11 +120,13 @@ hipError_t launch_phase_wide(const DevState &st, int phase, hipStream_t s) {
   with_wide_m(st.m, [&](auto mc) {
     constexpr int M = decltype(mc)::value;
     if (phase == 0) {
-      with_lanes(st.stride, [&](auto lc) {
-        constexpr int LPO = decltype(lc)::value;
-        hipLaunchKernelGGL((k_vary<M, 1, LPO>), dim3(vary_blocks_of(st.n, LPO)), dim3(kBlock), 0,
-                           s, st);
-      });
+      if (vary_tasked(st))
+        hipLaunchKernelGGL((k_tvary<M, 1>), dim3(vary_grid(st)), dim3(kBlock), 0, s, st);
+      else
+        with_lanes(st, [&](auto lc) {
+          constexpr int LPO = decltype(lc)::value;
+          hipLaunchKernelGGL((k_vary<M, 1, LPO>), dim3(vary_grid(st)), dim3(kBlock), 0, s, st);
+        });
     } else if (phase == 1) {
       hipLaunchKernelGGL((k_op1<M>), dim3(st.nblk), dim3(kBlock), 0, s, st);
     } else {
@@ -120,8 +138,10 @@ hipError_t launch_phase_wide(const DevState &st, int phase, hipStream_t s) {
 }
 
 hipError_t launch_batch_phase_wide(const DevState *states, const int2 *work, int nwork, int phase,
-                                   hipStream_t s) {
-  if (phase == 0)
+                                   bool tasked, hipStream_t s) {
+  if (phase == 0 && tasked)
+    hipLaunchKernelGGL(k_tvary_batch_w, dim3(nwork), dim3(kBlock), 0, s, states, work);
+  else if (phase == 0)
     hipLaunchKernelGGL(k_vary_batch_w, dim3(nwork), dim3(kBlock), 0, s, states, work);
   else if (phase == 1)
     hipLaunchKernelGGL(k_op1_batch_w, dim3(nwork), dim3(kBlock), 0, s, states, work);

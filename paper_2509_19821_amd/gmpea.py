@@ -37,7 +37,7 @@ EXPORTS = ["gmpea_init", "gmpea_step", "gmpea_run", "gmpea_front", "gmpea_get_in
            "gmpea_pool_query", "gmpea_pool_sync", "gmpea_pool_destroy", "gmpea_lattice",
            "gmpea_reference_set", "gmpea_quality", "gmpea_shape", "gmpea_copy_probe"]
 COPY_STRIDED, COPY_WIDE, COPY_WIDE_NT, COPY_RUNTIME = 0, 1, 2, 3
-PHASES = ("vary", "op1", "select", "rows")
+PHASES = ("vary", "op1", "select", "remap")
 
 
 class GmpeaError(RuntimeError):
@@ -317,10 +317,13 @@ class Gmpea:
 
     def profile(self, n_gen: int) -> dict:
         """Mean per-kernel durations (ms) over n_gen generations, HIP events on
-        the handle's stream."""
-        ms = np.zeros(len(PHASES), dtype=np.float32)  # the library writes one mean per phase
+        the handle's stream, and the variation kernel's mean over n_gen
+        launches back to back ("vary_back_to_back")."""
+        ms = np.zeros(len(PHASES) + 1, dtype=np.float32)  # one mean per phase, then vary back to back
         _check(lib().gmpea_profile(self._h, int(n_gen), ms.ctypes.data))
-        return dict(zip(PHASES, (float(v) for v in ms)))
+        out = dict(zip(PHASES, (float(v) for v in ms)))
+        out["vary_back_to_back"] = float(ms[len(PHASES)])
+        return out
 
     def info(self) -> dict:
         inf = Info()

@@ -7,7 +7,8 @@ Eq. (8)) as robust or not. "Robust in FP64" claims: a device that evaluates
 the same generation in FP32 takes the same decision. "Robust in FP32 mode"
 claims: any FP32 evaluation of the aggregation on the given FP32 operands
 (fused or unfused multiply-adds, either summation order, the unit direction
-rounded once or computed in FP32) takes the same decision.
+rounded once or computed in FP32, a square root within one ulp) takes the
+same decision.
 
 This test re-derives every decision with a plain pull written here from
 Alg. 2 (lexicographic minimum over the reverse neighbourhood, first index on
@@ -19,7 +20,8 @@ ties), in perturbed FP32 worlds:
     vectors (own evaluation of the two families, sums in either order);
   - the ideal point as the FP32 minimum;
   - the aggregation in FP32 with and without fused multiply-adds, sums
-    forward and backward, the unit direction rounded once or built in FP32.
+    forward and backward, the unit direction rounded once or built in FP32,
+    the square root correctly rounded or off by up to one ulp.
 Every decision the oracle marks robust must come out the same in every
 world; the worlds must also flip some unmarked decisions, or they would not
 test anything. The states are real generations (evolved populations with
@@ -121,7 +123,18 @@ def _fma(a, b, c):
     return (a.astype(np.float64) * b.astype(np.float64) + c.astype(np.float64)).astype(F32)
 
 
-def _agg32(kind, theta, F, W, z, fma, reverse, unit32):
+def _sqrt_1ulp(x):
+    """FP32 square root moved by up to one ulp (a function of the value): a
+    hardware square root within one ulp instead of the correctly rounded one."""
+    r = np.sqrt(x.astype(F32)).astype(F32)
+    h = (r.view(np.uint32).astype(np.uint64) * np.uint64(0x85EBCA6B)) & np.uint64(0xFFFFFFFF)
+    k = (h % np.uint64(3)).astype(np.int64) - 1
+    ok = np.isfinite(r) & (r > 0)
+    moved = _ulp_shift(np.where(ok, r, F32(1)), k)
+    return np.where(ok, moved, r).astype(F32)
+
+
+def _agg32(kind, theta, F, W, z, fma, reverse, unit32, hw_sqrt=False):
     """Aggregation of FP32 rows F at weights W (FP64 reference vectors) in FP32."""
     F = F.astype(F32)
     z = z.astype(F32)
@@ -145,7 +158,8 @@ def _agg32(kind, theta, F, W, z, fma, reverse, unit32):
     for k in order:
         e = (diff[:, k] - (d1 * u[:, k]).astype(F32)).astype(F32)
         d2 = _fma(e, e, d2) if fma else (d2 + (e * e).astype(F32)).astype(F32)
-    g = (d1 + (F32(theta) * np.sqrt(d2)).astype(F32)).astype(F32)
+    root = _sqrt_1ulp(d2) if hw_sqrt else np.sqrt(d2).astype(F32)
+    g = (d1 + (F32(theta) * root).astype(F32)).astype(F32)
     return np.where(np.isnan(g), np.inf, g.astype(np.float64))
 
 
@@ -197,8 +211,8 @@ def _decide(o, cfg, F, CV, Fo, CVo, z, agg_fn):
     return sw, win
 
 
-AGG_VARIANTS = [dict(fma=f, reverse=r, unit32=u) for f in (False, True) for r in (False, True)
-                for u in (False, True)]
+AGG_VARIANTS = [dict(fma=f, reverse=r, unit32=u, hw_sqrt=q) for f in (False, True)
+                for r in (False, True) for u in (False, True) for q in (False, True)]
 
 
 def _states(prob, cfg, warm, gens, rng, eq_edge=False):
