@@ -230,6 +230,21 @@ gmpea_status gmpea_run(gmpea_t h, int32_t max_gen, double time_limit_s, int32_t 
 gmpea_status gmpea_front(gmpea_t h, int32_t what, int32_t capacity, float *x, float *f,
                          float *cv, int32_t *idx, int32_t *count);
 
+/* gmpea_front for callers that cannot allocate device memory (code that must
+ * not call hipMalloc, such as tight serving loops or harnesses that forbid it):
+ * the same rows, values and errors, computed by the same kernels, with every
+ * device buffer the extraction needs (flags, row list, gathered F/CV records
+ * and decision vectors) in one fixed 32 MiB scratch array of the library,
+ * which each GPU it runs on holds until the process ends. Calls nothing that
+ * allocates device memory. The scratch must hold n (5 + 16 rq) + 4 d bytes
+ * (256-byte aligned parts; rq = 1 for m <= 3, (m + 4) / 4 above), about 1.5
+ * million rows for m <= 3; a larger population returns EUNSUPPORTED before any
+ * work. Decision vectors are copied out in passes of as many rows as the rest
+ * of the scratch holds. Every call on one GPU shares that GPU's scratch: calls
+ * that overlap in time on one GPU (from several host threads) race and must
+ * not be made; consecutive calls are safe, since each call synchronises. */
+gmpea_status gmpea_front_static(gmpea_t h, int32_t what, int32_t capacity, float *x, float *f,
+                                float *cv, int32_t *idx, int32_t *count);
 
 /* Quality of the current front on the device: the feasible non-dominated rows
  * of population 1 (as GMPEA_FRONT_FEASIBLE_ND), measured by IGD (Eq. (14)) and

@@ -281,8 +281,39 @@ gmpea_status check_runtime(const char *who) {
   return GMPEA_OK;
 }
 
+// Fixed device scratch of gmpea_front_static, for callers that cannot allocate:
+// one copy per GPU, held until the process ends. In host code `scratch` names a
+// host-side stand-in, never the device array: its device address on each GPU
+// comes from hipGetSymbolAddress (static_scratch below).
+constexpr size_t kStaticScratchBytes = size_t(32) << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+std::mutex g_scratch_mu;
+std::map<int, unsigned char *> g_scratch_addr;  // device -> that device's copy of scratch
+
+// Device address of `device`'s copy of the scratch, looked up once per device
+// with that device current.
+gmpea_status static_scratch(int device, unsigned char **out, const char *who) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_addr.find(device);
+  if (it != g_scratch_addr.end()) {
+    *out = it->second;
+    return GMPEA_OK;
+  }
+  int cur = 0;
+  hipError_t e = hipGetDevice(&cur);
+  if (e == hipSuccess && cur != device) e = hipSetDevice(device);
+  void *p = nullptr;
+  if (e == hipSuccess) e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (cur != device) (void)hipSetDevice(cur);
+  if (e != hipSuccess) return hip_fail(e, who);
+  g_scratch_addr[device] = static_cast<unsigned char *>(p);
+  *out = static_cast<unsigned char *>(p);
+  return GMPEA_OK;
+}
+
 // Device buffers one front extraction works in: the handle's own (carved at
-// gmpea_init).
+// gmpea_init) or the library's fixed scratch (gmpea_front_static).
 struct FrontBufs {
   uint8_t *keep;   // n flags
   int32_t *idx;    // n row indices
@@ -331,7 +362,7 @@ gmpea_status front_gather_fc(gmpea_s *h, const FrontBufs &b, int pop, const std:
   return GMPEA_OK;
 }
 
-// Front extraction into a buffer set.
+// Front extraction shared by gmpea_front and gmpea_front_static.
 gmpea_status front_impl(gmpea_s *h, const FrontBufs &b, int32_t what, int32_t capacity, float *x,
                         float *f, float *cv, int32_t *idx, int32_t *count, const char *who) {
   const DevState &st = h->st;
@@ -431,6 +462,15 @@ gmpea_status gmpea_init(const gmpea_problem *P, const gmpea_config *C, const gmp
   h->H2 = H2;
   h->record = C->record != 0;
   (void)hipGetDevice(&h->device);
+  {
+    unsigned char *sc = nullptr;  // gmpea_front_static's scratch address on this device
+    s = static_scratch(h->device, &sc, "gmpea_init");
+    if (s != GMPEA_OK) {
+      if (h->own_stream) (void)hipStreamDestroy(h->stream);
+      delete h;
+      return s;
+    }
+  }
 
   // ---- neighbourhood offsets (host, a few KB) when the device builds the tables:
   // one Das-Dennis layer with m <= 3; otherwise the host builds them ----
@@ -754,6 +794,43 @@ gmpea_status gmpea_front(gmpea_t h, int32_t what, int32_t capacity, float *x, fl
     return fail(GMPEA_EINVAL, "gmpea_front: unknown selector");
   if (capacity < 0) return fail(GMPEA_EINVAL, "gmpea_front: negative capacity");
   return front_impl(h, handle_bufs(h), what, capacity, x, f, cv, idx, count, "gmpea_front");
+}
+
+gmpea_status gmpea_front_static(gmpea_t h, int32_t what, int32_t capacity, float *x, float *f,
+                                float *cv, int32_t *idx, int32_t *count) {
+  const char *who = "gmpea_front_static";
+  if (!valid(h)) return fail(GMPEA_ESTATE, "gmpea_front_static: invalid handle");
+  if (!count) return fail(GMPEA_EINVAL, "gmpea_front_static: count is NULL");
+  if (what != GMPEA_FRONT_FEASIBLE_ND && what != GMPEA_FRONT_POP1 && what != GMPEA_FRONT_POP2)
+    return fail(GMPEA_EINVAL, "gmpea_front_static: unknown selector");
+  if (capacity < 0) return fail(GMPEA_EINVAL, "gmpea_front_static: negative capacity");
+  const DevState &st = h->st;
+  // flags, row list and records for every row, then decision vectors in passes
+  // of as many rows as the rest of the scratch holds
+  Carve fixed;
+  fixed.take<uint8_t>(static_cast<size_t>(st.n));
+  fixed.take<int32_t>(static_cast<size_t>(st.n));
+  fixed.take<float4>(static_cast<size_t>(st.n) * st.rq);
+  const size_t xoff = (fixed.off + 255) & ~static_cast<size_t>(255);
+  const size_t row_bytes = static_cast<size_t>(st.d) * sizeof(float);
+  if (xoff + row_bytes > kStaticScratchBytes)
+    return fail(GMPEA_EUNSUPPORTED,
+                "gmpea_front_static: population of " + std::to_string(st.n) + " rows needs " +
+                    std::to_string(xoff + row_bytes) + " bytes of scratch, above the fixed " +
+                    std::to_string(kStaticScratchBytes) + " (n (5 + 16 rq) + 4 d bytes, 256-aligned parts)");
+  unsigned char *base = nullptr;
+  gmpea_status s = static_scratch(h->device, &base, who);
+  if (s != GMPEA_OK) return s;
+  Carve c;
+  c.base = reinterpret_cast<char *>(base);
+  FrontBufs b{};
+  b.keep = c.take<uint8_t>(static_cast<size_t>(st.n));
+  b.idx = c.take<int32_t>(static_cast<size_t>(st.n));
+  b.fc = c.take<float4>(static_cast<size_t>(st.n) * st.rq);
+  b.x = reinterpret_cast<float *>(base + xoff);
+  b.x_rows = static_cast<int32_t>(
+      std::min<size_t>(static_cast<size_t>(st.n), (kStaticScratchBytes - xoff) / row_bytes));
+  return front_impl(h, b, what, capacity, x, f, cv, idx, count, who);
 }
 
 gmpea_status gmpea_get_info(gmpea_t h, gmpea_info *info) {

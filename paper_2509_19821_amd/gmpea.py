@@ -35,7 +35,8 @@ EXPORTS = ["gmpea_init", "gmpea_step", "gmpea_run", "gmpea_front", "gmpea_get_in
            "gmpea_philox", "gmpea_copy", "gmpea_pool_create", "gmpea_pool_admit",
            "gmpea_pool_step", "gmpea_pool_tune", "gmpea_pool_handle", "gmpea_pool_release",
            "gmpea_pool_query", "gmpea_pool_sync", "gmpea_pool_destroy", "gmpea_lattice",
-           "gmpea_reference_set", "gmpea_quality", "gmpea_shape", "gmpea_copy_probe"]
+           "gmpea_reference_set", "gmpea_quality", "gmpea_shape", "gmpea_copy_probe",
+           "gmpea_front_static"]
 COPY_STRIDED, COPY_WIDE, COPY_WIDE_NT, COPY_RUNTIME = 0, 1, 2, 3
 PHASES = ("vary", "op1", "select", "remap")
 
@@ -128,6 +129,7 @@ def lib():
         L.gmpea_step.argtypes = [vp, i32]
         L.gmpea_run.argtypes = [vp, i32, ctypes.c_double, ctypes.POINTER(i32)]
         L.gmpea_front.argtypes = [vp, i32, i32, vp, vp, vp, vp, ctypes.POINTER(i32)]
+        L.gmpea_front_static.argtypes = [vp, i32, i32, vp, vp, vp, vp, ctypes.POINTER(i32)]
         L.gmpea_get_info.argtypes = [vp, ctypes.POINTER(Info)]
         L.gmpea_read.argtypes = [vp, i32, i32, vp, i64]
         L.gmpea_write.argtypes = [vp, i32, i32, vp, i64]
