@@ -370,7 +370,8 @@ gmpea_status gmpea_pool_admit(gmpea_pool_t pool, const gmpea_problem *problem,
 gmpea_status gmpea_pool_step(gmpea_pool_t pool, int32_t n_gen);
 
 /* Run n_gen batched generations while choosing the launch schedule (instance
- * blocks grouped per XCD or in order) and the graph chunk length by timing the
+ * blocks grouped per XCD or in order) and the launch form (hipGraph replays of
+ * 16 or 64 generations, or one launch per phase without a graph) by timing the
  * first generations; the choice stays for later steps. Results do not depend
  * on it. *gens_done (may be NULL) receives the generations run. Synchronises. */
 gmpea_status gmpea_pool_tune(gmpea_pool_t pool, int32_t n_gen, int32_t *gens_done);

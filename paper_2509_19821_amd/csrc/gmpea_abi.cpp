@@ -1661,7 +1661,9 @@ gmpea_status gmpea_pool_tune(gmpea_pool_t q, int32_t n_gen, int32_t *gens_done) 
   // Each candidate (schedule, chunk) runs real generations, timed with events;
   // the fastest per generation is kept. The state advances by the generations
   // run, whatever the choice, and results do not depend on it.
-  const int32_t cand[4][2] = {{0, 16}, {1, 16}, {0, 64}, {1, 64}};
+  // (schedule, chunk, generations timed): chunk 0 launches every generation
+  // eagerly, without a graph
+  const int32_t cand[6][3] = {{0, 16, 16}, {1, 16, 16}, {0, 0, 16}, {1, 0, 16}, {0, 64, 64}, {1, 64, 64}};
   hipEvent_t a, b;
   if (hipEventCreate(&a) != hipSuccess) return fail(GMPEA_EHIP, "gmpea_pool_tune: event");
   if (hipEventCreate(&b) != hipSuccess) {
@@ -1672,8 +1674,8 @@ gmpea_status gmpea_pool_tune(gmpea_pool_t q, int32_t n_gen, int32_t *gens_done) 
   float best = 1e30f;
   int32_t bs = q->schedule, bc = q->chunk;
   gmpea_status s = GMPEA_OK;
-  for (int c = 0; c < 4 && s == GMPEA_OK; ++c) {
-    const int32_t gens = cand[c][1];
+  for (int c = 0; c < 6 && s == GMPEA_OK; ++c) {
+    const int32_t gens = cand[c][2];
     if (done + 2 * gens > n_gen) break;
     if (q->schedule != cand[c][0]) q->dirty = true;
     q->schedule = cand[c][0];
