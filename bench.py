@@ -512,6 +512,24 @@ def main():
             "rho": [round(r, 4) for r in rho]}
     gp.close()
 
+    # the whole solve (200 generations from a fresh instance, initialisation
+    # excluded): replacements thin out as the populations converge, and the
+    # generation's cost follows
+    gs = g.Gmpea(prob, cfg)
+    gs.step(0)
+    gs.sync()
+    t0 = time.perf_counter()
+    gs.step(K_total)
+    gs.sync()
+    el_s = time.perf_counter() - t0
+    rep = gs.info()["replaced"]
+    gs.close()
+    solve = {"generations": K_total, "ms_per_generation": round(1e3 * el_s / K_total, 5),
+             "offspring_per_s": round(2.0 * n * K_total / el_s, 1),
+             "rho_mean": [round(rep[p] / (n * K_total), 4) for p in range(2)]}
+    log("bench: full solve %d generations %.1f us/gen, rho %s" % (K_total, 1e6 * el_s / K_total,
+                                                                 solve["rho_mean"]))
+
     out = {"metric": METRIC, "value": round(value, 1), "unit": "offspring/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": round(1e3 * el / args.steps, 5), "higher_is_better": True,
@@ -520,7 +538,7 @@ def main():
                                   "T=32 (t1=16, t2=64), 4 rings + equality x1+x2=1 (tol 1e-4), "
                                   "%d generations in the full solve" % (n, K_total),
                       "global_batch": 2 * n, "parallelism": "single GPU"},
-           "roofline": roof}
+           "roofline": roof, "full_solve": solve}
     if not args.no_batched:
         log("bench: batched instances")
         out["batched"] = batched_vs_plain(g, ci)

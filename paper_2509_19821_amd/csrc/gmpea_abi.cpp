@@ -541,6 +541,8 @@ gmpea_status gmpea_init(const gmpea_problem *P, const gmpea_config *C, const gmp
   dp.g_scale = d > 1 ? static_cast<float>(9.0 / (d - 1)) : 0.0f;
 
   const size_t rows = static_cast<size_t>(st.nblk) * kBlock;
+  const int32_t tail_cap[2] = {static_cast<int32_t>(static_cast<int64_t>(N) * t1 / 8 + 256),
+                               static_cast<int32_t>(static_cast<int64_t>(N) * t2 / 8 + 256)};
   float *lb = nullptr, *ub = nullptr, *inv_span = nullptr;
   int2 *d_offs = nullptr;
   uint32_t *d_flag = nullptr;
@@ -569,6 +571,9 @@ gmpea_status gmpea_init(const gmpea_problem *P, const gmpea_config *C, const gmp
     st.repl = c.take<unsigned long long>(2 * kReplLanes);
     d_offs = c.take<int2>(noffs);
     d_flag = c.take<uint32_t>(4);
+    // reverse-list tails with room for an eighth of the entries (lattice
+    // neighbourhoods put well under 1 % there); a larger tail is rebuilt exactly
+    for (int p = 0; p < 2; ++p) st.rtail[p] = c.take<int32_t>(tail_cap[p]);
     // delivery scratch (gmpea_front, gmpea_quality)
     h->f_keep = c.take<uint8_t>(static_cast<size_t>(N));
     h->f_idx = c.take<int32_t>(static_cast<size_t>(N));
@@ -632,13 +637,11 @@ gmpea_status gmpea_init(const gmpea_problem *P, const gmpea_config *C, const gmp
   zero(st.repl, 0, 2 * kReplLanes * sizeof(unsigned long long));
   // reference vectors and neighbourhoods: on the device for one Das-Dennis layer
   // with m <= 3, else on the host (W rounded once from FP64, rq float4 per row)
-  uint32_t incomplete = 0;
   if (dev_tables) {
+    // the flag that some row's offset walk came up short is read at the end
     if (e == hipSuccess)
       e = launch_tables(m, N, H, d_offs, noffs, t1, t2, C->agg, st.W, const_cast<int32_t *>(st.B[0]),
                         const_cast<int32_t *>(st.B[1]), d_flag, h->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(&incomplete, d_flag, sizeof(uint32_t), hipMemcpyDeviceToHost, h->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   } else if (e == hipSuccess) {
     std::vector<int32_t> K, Bh;
     std::vector<double> Wd;
@@ -688,9 +691,32 @@ gmpea_status gmpea_init(const gmpea_problem *P, const gmpea_config *C, const gmp
     }
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);  // Wf is read before it goes
   }
-  if (e == hipSuccess && incomplete) {
+  // reverse lists (the offspring buffer serves as the zeroed cursor array),
+  // into the tails carved above
+  int32_t *cursor = reinterpret_cast<int32_t *>(st.FCO[0]);
+  auto reverse_lists = [&](const int32_t *cap) {
+    for (int p = 0; p < 2; ++p) {
+      zero(cursor, 0, static_cast<size_t>(N) * sizeof(int32_t));
+      zero(const_cast<int32_t *>(st.rtoff[p]), 0, (static_cast<size_t>(N) + 1) * sizeof(int32_t));
+      zero(const_cast<int32_t *>(st.rhead[p]), 0xFF, static_cast<size_t>(N) * ts[p] * sizeof(int32_t));
+      if (e == hipSuccess)
+        e = launch_reverse_count(N, ts[p], st.B[p], cursor, const_cast<int32_t *>(st.rtoff[p]), h->stream);
+      zero(cursor, 0, static_cast<size_t>(N) * sizeof(int32_t));
+      if (e == hipSuccess)
+        e = launch_reverse_fill(N, ts[p], st.B[p], st.rtoff[p], cursor, const_cast<int32_t *>(st.rhead[p]),
+                                const_cast<int32_t *>(st.rtail[p]), cap[p], d_flag + 1 + p, h->stream);
+    }
+  };
+  reverse_lists(tail_cap);
+  zero(st.FCO[0], 0, rows * st.rq * sizeof(float4));
+  if (e == hipSuccess) e = launch_init(st, h->stream);
+  // one wait for everything above: the tables' and the tails' flags
+  uint32_t flags[4] = {0, 0, 0, 0};
+  if (e == hipSuccess) e = hipMemcpyAsync(flags, d_flag, sizeof(flags), hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e == hipSuccess && flags[0]) {
     // some row (near a lattice corner) needs neighbours beyond the offset list:
-    // the host's exact search provides both tables
+    // the host's exact search provides both tables, then the lists again
     std::vector<int32_t> K, Bh;
     dd_lattice(m, H, K);
     for (int p = 0; p < 2 && e == hipSuccess; ++p) {
@@ -699,42 +725,35 @@ gmpea_status gmpea_init(const gmpea_problem *P, const gmpea_config *C, const gmp
                          hipMemcpyHostToDevice, h->stream);
       if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     }
+    zero(d_flag, 0, 4 * sizeof(uint32_t));
+    reverse_lists(tail_cap);
+    if (e == hipSuccess) e = hipMemcpyAsync(flags, d_flag, sizeof(flags), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   }
-  // reverse lists (the offspring buffer serves as the zeroed cursor array); the
-  // tail, sized by the count pass, gets an allocation of its own
-  int32_t *cursor = reinterpret_cast<int32_t *>(st.FCO[0]);
-  int32_t tail_n[2] = {0, 0};
-  for (int p = 0; p < 2; ++p) {
-    zero(cursor, 0, static_cast<size_t>(N) * sizeof(int32_t));
-    if (e == hipSuccess)
-      e = launch_reverse_count(N, ts[p], st.B[p], cursor, const_cast<int32_t *>(st.rtoff[p]), h->stream);
-    if (e == hipSuccess)
+  if (e == hipSuccess && (flags[1] || flags[2])) {
+    // a tail beyond its room: tails of the exact sizes (toff[N] after the count)
+    int32_t tail_n[2] = {0, 0};
+    for (int p = 0; p < 2 && e == hipSuccess; ++p)
       e = hipMemcpyAsync(&tail_n[p], st.rtoff[p] + N, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream);
-  }
-  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-  if (e == hipSuccess) {
-    Carve sizing;
-    sizing.take<int32_t>(static_cast<size_t>(tail_n[0]));
-    sizing.take<int32_t>(static_cast<size_t>(tail_n[1]));
-    Carve carve;
-    carve.base = static_cast<char *>(dev_alloc(h, sizing.off));
-    if (!carve.base) {
-      release_all(h);
-      delete h;
-      return fail(GMPEA_ENOMEM, "gmpea_init: device allocation failed");
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e == hipSuccess) {
+      Carve sizing;
+      sizing.take<int32_t>(static_cast<size_t>(tail_n[0]));
+      sizing.take<int32_t>(static_cast<size_t>(tail_n[1]));
+      Carve carve;
+      carve.base = static_cast<char *>(dev_alloc(h, sizing.off));
+      if (!carve.base) {
+        release_all(h);
+        delete h;
+        return fail(GMPEA_ENOMEM, "gmpea_init: device allocation failed");
+      }
+      st.rtail[0] = carve.take<int32_t>(static_cast<size_t>(tail_n[0]));
+      st.rtail[1] = carve.take<int32_t>(static_cast<size_t>(tail_n[1]));
+      zero(d_flag, 0, 4 * sizeof(uint32_t));
+      reverse_lists(tail_n);
+      if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     }
-    st.rtail[0] = carve.take<int32_t>(static_cast<size_t>(tail_n[0]));
-    st.rtail[1] = carve.take<int32_t>(static_cast<size_t>(tail_n[1]));
   }
-  for (int p = 0; p < 2; ++p) {
-    zero(cursor, 0, static_cast<size_t>(N) * sizeof(int32_t));
-    if (e == hipSuccess)
-      e = launch_reverse_fill(N, ts[p], st.B[p], st.rtoff[p], cursor, const_cast<int32_t *>(st.rhead[p]),
-                              const_cast<int32_t *>(st.rtail[p]), h->stream);
-  }
-  zero(st.FCO[0], 0, rows * st.rq * sizeof(float4));
-  if (e == hipSuccess) e = launch_init(st, h->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) {
     gmpea_status r = hip_fail(e, "gmpea_init");
     release_all(h);

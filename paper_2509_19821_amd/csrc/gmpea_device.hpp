@@ -959,33 +959,27 @@ __device__ __forceinline__ void remap_body(const DevState &st, int64_t e) {
       }
     }
   }
-  // copies four rows at a time, so that four loads per lane are in flight
-  constexpr int kAtOnce = 4;
+  // the wave's lanes form groups of gw lanes (a power of two covering the row's
+  // chunks, at most 64), and each group copies one pending row at a time, so
+  // several rows move at once
+  int gw = 1;
+  while (gw < st.nq && gw < 64) gw <<= 1;
+  const int lane = threadIdx.x & 63, groups = 64 / gw, grp = lane / gw, gl = lane % gw;
   uint64_t pending = __ballot(copy);
-  const int lane = threadIdx.x & 63;
   while (pending) {
-    uint32_t f[kAtOnce], h[kAtOnce];
-    int cnt = 0;
-#pragma unroll
-    for (int u = 0; u < kAtOnce; ++u) {
-      f[u] = 0;
-      h[u] = 0;
-      if (pending) {
-        const int src_lane = __ffsll(static_cast<unsigned long long>(pending)) - 1;
-        pending &= pending - 1;
-        f[u] = static_cast<uint32_t>(__shfl(static_cast<int>(from), src_lane));
-        h[u] = static_cast<uint32_t>(__shfl(static_cast<int>(home), src_lane));
-        cnt = u + 1;
-      }
+    int src_lane = -1;
+    for (int g = 0; g < groups && pending; ++g) {
+      const int b = __ffsll(static_cast<unsigned long long>(pending)) - 1;
+      pending &= pending - 1;
+      if (g == grp) src_lane = b;
     }
-    for (int c = lane; c < st.nq; c += 64) {
-      float4 v[kAtOnce];
-#pragma unroll
-      for (int u = 0; u < kAtOnce; ++u)
-        if (u < cnt) v[u] = arena_row(st, f[u])[c];
-#pragma unroll
-      for (int u = 0; u < kAtOnce; ++u)
-        if (u < cnt) reinterpret_cast<float4 *>(st.rows + static_cast<size_t>(h[u]) * st.stride)[c] = v[u];
+    const int sl = src_lane >= 0 ? src_lane : 0;
+    const uint32_t f = static_cast<uint32_t>(__shfl(static_cast<int>(from), sl));
+    const uint32_t h = static_cast<uint32_t>(__shfl(static_cast<int>(home), sl));
+    if (src_lane >= 0) {
+      const float4 *src = arena_row(st, f);
+      float4 *dst = reinterpret_cast<float4 *>(st.rows + static_cast<size_t>(h) * st.stride);
+      for (int c = gl; c < st.nq; c += gw) dst[c] = src[c];
     }
   }
 }

@@ -230,15 +230,17 @@ void refset_neighbours(const std::vector<int32_t> &K, int32_t m, int32_t H1, int
 hipError_t launch_tables(int32_t m, int32_t n, int32_t H, const int2 *offs, int32_t noffs,
                          int32_t t1, int32_t t2, int32_t agg, float4 *W, int32_t *B1, int32_t *B2,
                          uint32_t *incomplete, hipStream_t s);
-// Reverse lists of B (n x t), in two launches around a host read of the tail
-// size. launch_reverse_count: cursor (n + ceil((n + 1) / 1024) entries, the first n
-// zero on entry; the rest is scratch of the scan) receives each list's
-// length and toff (n + 1, zero on entry) the exclusive scan of the lengths in
-// excess of t, so toff[n] is the tail size. launch_reverse_fill: head (n x t)
-// and tail receive the lists, each ascending (cursor must be zero again).
+// Reverse lists of B (n x t). launch_reverse_count: cursor (n + ceil((n + 1) /
+// 1024) entries, the first n zero on entry; the rest is scratch of the scan)
+// receives each list's length and toff (n + 1, zero on entry) the exclusive
+// scan of the lengths in excess of t, so toff[n] is the tail size.
+// launch_reverse_fill: head (n x t) and tail (cap entries) receive the lists,
+// each ascending (cursor must be zero again); when the tail needs more than cap
+// entries, *overflow becomes nonzero and the lists are incomplete.
 hipError_t launch_reverse_count(int32_t n, int32_t t, const int32_t *B, int32_t *cursor,
                                 int32_t *toff, hipStream_t s);
 hipError_t launch_reverse_fill(int32_t n, int32_t t, const int32_t *B, const int32_t *toff,
-                               int32_t *cursor, int32_t *head, int32_t *tail, hipStream_t s);
+                               int32_t *cursor, int32_t *head, int32_t *tail, int32_t cap,
+                               uint32_t *overflow, hipStream_t s);
 
 }  // namespace gmpea

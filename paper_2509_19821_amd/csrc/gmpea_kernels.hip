@@ -244,20 +244,29 @@ __global__ __launch_bounds__(kScanTile) void k_scan_add(int32_t *__restrict__ of
   if (q < len) off[q] = part[tid] + sums[blockIdx.x];
 }
 
+// Scatter of the reverse lists: entries past a list's first t go to the tail,
+// which holds `cap` entries; an entry beyond it is dropped and *overflow set
+// (the caller then rebuilds with an exact tail).
 __global__ __launch_bounds__(kBlock) void k_rev_fill(int64_t nt, int32_t t, const int32_t *__restrict__ B,
                                                     const int32_t *__restrict__ toff,
                                                     int32_t *__restrict__ cursor,
                                                     int32_t *__restrict__ head,
-                                                    int32_t *__restrict__ tail) {
+                                                    int32_t *__restrict__ tail, int32_t cap,
+                                                    uint32_t *__restrict__ overflow) {
   const int64_t q = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
   if (q >= nt) return;
   const int32_t j = B[q];
   const int32_t pos = atomicAdd(&cursor[j], 1);
   const int32_t i = static_cast<int32_t>(q / t);
-  if (pos < t)
+  if (pos < t) {
     head[static_cast<size_t>(j) * t + pos] = i;
-  else
-    tail[toff[j] + pos - t] = i;
+  } else {
+    const int32_t at = toff[j] + pos - t;
+    if (at < cap)
+      tail[at] = i;
+    else
+      atomicOr(overflow, 1u);
+  }
 }
 
 // Each list sorted ascending by one wave: the wave stages the list (head
@@ -269,10 +278,13 @@ constexpr int kRevSortMax = 512;
 
 __global__ __launch_bounds__(kBlock) void k_rev_sort(int32_t n, int32_t t, const int32_t *__restrict__ toff,
                                                     int32_t *__restrict__ head,
-                                                    int32_t *__restrict__ tail) {
+                                                    int32_t *__restrict__ tail, int32_t cap) {
   __shared__ int32_t buf[kBlock / 64][kRevSortMax];
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int32_t j = blockIdx.x * (kBlock / 64) + wv;
+  int32_t j = blockIdx.x * (kBlock / 64) + wv;
+  // a list whose tail lies beyond the tail's room was not filled completely
+  // (the caller rebuilds): left as it is
+  if (j < n && toff[j + 1] > cap) j = n;
   int32_t len = 0, ext = 0;
   int32_t *h = nullptr, *tl = nullptr;
   if (j < n) {  // uniform per wave
@@ -673,12 +685,14 @@ hipError_t launch_reverse_count(int32_t n, int32_t t, const int32_t *B, int32_t 
 }
 
 hipError_t launch_reverse_fill(int32_t n, int32_t t, const int32_t *B, const int32_t *toff,
-                               int32_t *cursor, int32_t *head, int32_t *tail, hipStream_t s) {
+                               int32_t *cursor, int32_t *head, int32_t *tail, int32_t cap,
+                               uint32_t *overflow, hipStream_t s) {
   const int64_t nt = static_cast<int64_t>(n) * t;
   const unsigned grid = static_cast<unsigned>((nt + kBlock - 1) / kBlock);
-  hipLaunchKernelGGL(k_rev_fill, dim3(grid), dim3(kBlock), 0, s, nt, t, B, toff, cursor, head, tail);
+  hipLaunchKernelGGL(k_rev_fill, dim3(grid), dim3(kBlock), 0, s, nt, t, B, toff, cursor, head, tail, cap,
+                     overflow);
   hipLaunchKernelGGL(k_rev_sort, dim3((n + kBlock / 64 - 1) / (kBlock / 64)), dim3(kBlock), 0, s, n, t,
-                     toff, head, tail);
+                     toff, head, tail, cap);
   return hipGetLastError();
 }
 

@@ -70,7 +70,7 @@ def test_tuning_does_not_change_results(G):
         done = pool.tune(200)
         assert done == 200
         q = pool.query()
-        assert q["schedule"] in (0, 1) and q["chunk"] in (16, 64)
+        assert q["schedule"] in (0, 1) and q["chunk"] in (0, 16, 64)
         for (p, c), s in zip(mix, slots):
             _same(pool.instance(s).state(), _alone(G, p, c, 200))
     finally:
