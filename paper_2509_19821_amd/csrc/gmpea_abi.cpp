@@ -727,6 +727,7 @@ gmpea_status gmpea_init(const gmpea_problem *P, const gmpea_config *C, const gmp
     }
     zero(d_flag, 0, 4 * sizeof(uint32_t));
     reverse_lists(tail_cap);
+    zero(st.FCO[0], 0, rows * st.rq * sizeof(float4));  // the cursor again
     if (e == hipSuccess) e = hipMemcpyAsync(flags, d_flag, sizeof(flags), hipMemcpyDeviceToHost, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   }
@@ -751,6 +752,7 @@ gmpea_status gmpea_init(const gmpea_problem *P, const gmpea_config *C, const gmp
       st.rtail[1] = carve.take<int32_t>(static_cast<size_t>(tail_n[1]));
       zero(d_flag, 0, 4 * sizeof(uint32_t));
       reverse_lists(tail_n);
+      zero(st.FCO[0], 0, rows * st.rq * sizeof(float4));
       if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     }
   }

@@ -164,16 +164,28 @@ __global__ __launch_bounds__(kBlock) void k_tables(int32_t n, int32_t H, const i
     if (c < t2) B2[static_cast<size_t>(i) * t2 + c] = rank;
     ++c;
   }
-  if (c < tmax) atomicOr(incomplete, 1u);
+  if (c < tmax) {
+    // a walk that came up short: the row's remaining entries name the row
+    // itself, so that every entry is a valid index until the host's exact
+    // search replaces both tables
+    atomicOr(incomplete, 1u);
+    for (; c < tmax; ++c) {
+      if (c < t1) B1[static_cast<size_t>(i) * t1 + c] = i;
+      if (c < t2) B2[static_cast<size_t>(i) * t2 + c] = i;
+    }
+  }
 }
 
 // Reverse lists: lengths, the scan of their excess over t, a scatter into the
 // padded head and the tail, and a per-list insertion sort (lists hold about t
 // entries) so that every list is ascending.
-__global__ __launch_bounds__(kBlock) void k_rev_count(int64_t nt, const int32_t *__restrict__ B,
+// (an entry outside [0, n) is skipped by the count and the scatter alike)
+__global__ __launch_bounds__(kBlock) void k_rev_count(int64_t nt, int32_t n, const int32_t *__restrict__ B,
                                                      int32_t *__restrict__ cnt) {
   const int64_t q = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
-  if (q < nt) atomicAdd(&cnt[B[q]], 1);
+  if (q >= nt) return;
+  const int32_t j = B[q];
+  if (j >= 0 && j < n) atomicAdd(&cnt[j], 1);
 }
 
 __global__ __launch_bounds__(kBlock) void k_rev_excess(int32_t n, int32_t t, const int32_t *__restrict__ cnt,
@@ -256,6 +268,7 @@ __global__ __launch_bounds__(kBlock) void k_rev_fill(int64_t nt, int32_t t, cons
   const int64_t q = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
   if (q >= nt) return;
   const int32_t j = B[q];
+  if (j < 0 || j >= static_cast<int32_t>(nt / t)) return;
   const int32_t pos = atomicAdd(&cursor[j], 1);
   const int32_t i = static_cast<int32_t>(q / t);
   if (pos < t) {
@@ -678,7 +691,7 @@ hipError_t launch_reverse_count(int32_t n, int32_t t, const int32_t *B, int32_t 
                                 int32_t *toff, hipStream_t s) {
   const int64_t nt = static_cast<int64_t>(n) * t;
   const unsigned grid = static_cast<unsigned>((nt + kBlock - 1) / kBlock);
-  hipLaunchKernelGGL(k_rev_count, dim3(grid), dim3(kBlock), 0, s, nt, B, cursor);
+  hipLaunchKernelGGL(k_rev_count, dim3(grid), dim3(kBlock), 0, s, nt, n, B, cursor);
   hipLaunchKernelGGL(k_rev_excess, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, n, t,
                      static_cast<const int32_t *>(cursor), toff);
   return launch_scan(toff, n + 1, cursor + n, s);
