@@ -16,7 +16,11 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "gmpea_oracle.c")
 _OUT_DIR = os.path.join(_HERE, "_build")
-_SO = os.path.join(_OUT_DIR, "libgmpea_oracle.so")
+# GMPEA_ORACLE_LIBRARY names another build of the oracle (a sanitizer build),
+# used as it is
+_SO_ENV = os.environ.get("GMPEA_ORACLE_LIBRARY")
+_DEFAULT_SO = os.path.join(_OUT_DIR, "libgmpea_oracle.so")
+_SO = _SO_ENV or _DEFAULT_SO
 _lock = threading.Lock()
 _lib = None
 
@@ -24,13 +28,13 @@ _lib = None
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc (-O2, OpenMP). Always rebuilds when force."""
     os.makedirs(_OUT_DIR, exist_ok=True)
-    if force or not os.path.exists(_SO):
-        tmp = _SO + ".tmp%d" % os.getpid()
+    if force or not os.path.exists(_DEFAULT_SO):
+        tmp = _DEFAULT_SO + ".tmp%d" % os.getpid()
         cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11", "-Wall", "-o", tmp,
                _SRC, "-lm"]
         subprocess.run(cmd, check=True)
-        os.replace(tmp, _SO)
-    return _SO
+        os.replace(tmp, _DEFAULT_SO)
+    return _DEFAULT_SO
 
 
 class Problem(ctypes.Structure):
@@ -57,7 +61,7 @@ def lib():
     global _lib
     with _lock:
         if _lib is None:
-            if not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
+            if not _SO_ENV and (not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC)):
                 build(force=True)
             L = ctypes.CDLL(_SO)
             vp, i32, i64, u32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32

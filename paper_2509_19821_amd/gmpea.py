@@ -18,8 +18,10 @@ import sys
 import numpy as np
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_PKG, "_build", "libgmpea.so")
-_BUILD_INFO = os.path.join(_PKG, "_build", "build_info.json")
+# GMPEA_LIBRARY names another build of the library (a debug or host-sanitizer
+# build); by default the in-tree one
+_LIB_PATH = os.environ.get("GMPEA_LIBRARY") or os.path.join(_PKG, "_build", "libgmpea.so")
+_BUILD_INFO = os.path.join(os.path.dirname(_LIB_PATH), "build_info.json")
 
 FAMILY_CURVE, FAMILY_SPHERE = 0, 1
 OP_SBX, OP_DE = 0, 1
@@ -208,16 +210,22 @@ class Gmpea:
              or a torch.cuda.Stream.
     use_torch_allocator: take device memory from PyTorch's caching allocator
              instead of hipMalloc.
+    allocator: an Allocator (device memory hook) instead of hipMalloc; its
+             callbacks must stay alive until the instance is closed.
     """
 
     def __init__(self, problem: dict, config: dict, stream=None, use_torch_allocator=False,
-                 record: bool = False):
+                 record: bool = False, allocator=None):
         L = lib()
         self._h = None
         self._owned = True
         self._prob, self._cfg, self._keep = _structs(problem, config, record)
         self._alloc = None
-        if use_torch_allocator:
+        if allocator is not None and use_torch_allocator:
+            raise ValueError("give allocator or use_torch_allocator, not both")
+        if allocator is not None:
+            self._alloc = allocator
+        elif use_torch_allocator:
             self._alloc, self._cb = _torch_allocator()
         self.stream = self._stream_handle(stream)
         h = ctypes.c_void_p()

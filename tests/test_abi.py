@@ -40,7 +40,7 @@ def test_library_exports_every_declared_symbol(glib):
         assert hasattr(L, name), name
 
 
-def _init(glib, prob, cfg):
+def _init(glib, prob, cfg, allocator=None):
     """Call gmpea_init directly; validation errors return before any HIP call."""
     from paper_2509_19821_amd import gmpea as G
     L = G.lib()
@@ -58,7 +58,10 @@ def _init(glib, prob, cfg):
                  cfg.get("op", 0), cfg.get("de_f", 0.0), cfg.get("op1_rule", 0),
                  cfg.get("h_outer", 0), cfg.get("h_inner", 0))
     h = ctypes.c_void_p()
-    st = L.gmpea_init(ctypes.byref(P), ctypes.byref(C), None, None, ctypes.byref(h))
+    st = L.gmpea_init(ctypes.byref(P), ctypes.byref(C), ctypes.byref(allocator) if allocator else None,
+                      None, ctypes.byref(h))
+    if st == 0:
+        L.gmpea_destroy(h)
     return st, L.gmpea_last_error().decode()
 
 
@@ -86,6 +89,46 @@ def test_init_rejects_invalid_input(glib, mutate, code):
     st, msg = _init(glib, prob, cfg)
     assert st == code, msg
     assert msg
+
+
+class _CountingHook:
+    """An allocator hook that hands out nothing (NULL), counting its calls."""
+
+    def __init__(self, G):
+        self.calls = 0
+        self.freed = 0
+        self.fa = G.ALLOC_FN(self._alloc)
+        self.ff = G.FREE_FN(self._free)
+        self.al = G.Allocator(self.fa, self.ff, None)
+
+    def _alloc(self, nbytes, ctx):
+        self.calls += 1
+        return None
+
+    def _free(self, ptr, ctx):
+        self.freed += 1
+
+
+def test_allocator_hook_is_checked_before_use(glib):
+    """An allocator without both callbacks is refused; invalid input is
+    refused before the hook is called; with a hook that returns NULL, init
+    fails with ENOMEM (or with EHIP where no device is visible, before any
+    allocation) and frees nothing it was not given."""
+    from paper_2509_19821_amd import gmpea as G
+    prob, cfg, _ = ci.workload_small(0)
+    hook = _CountingHook(G)
+    half = G.Allocator(hook.fa, G.FREE_FN(), None)
+    st, msg = _init(glib, prob, cfg, allocator=half)
+    assert st == -1 and "allocator" in msg
+    bad = dict(cfg, t1=101)
+    st, msg = _init(glib, prob, bad, allocator=hook.al)
+    assert st == -1 and hook.calls == 0 and hook.freed == 0
+    st, msg = _init(glib, prob, cfg, allocator=hook.al)
+    if G.device_count() == 0:
+        assert st in (-2, -3), msg  # ENOMEM, or EHIP: no device for the stream or scratch
+    else:
+        assert st == -2 and hook.calls == 1, msg
+    assert hook.freed == 0  # NULL is never handed back
 
 
 def test_calls_on_dead_handles_are_rejected(glib):
