@@ -492,10 +492,12 @@ gmpea_status gmpea_init(const gmpea_problem *P, const gmpea_config *C, const gmp
     int32_t align = 4;
     if (const char *a = std::getenv("GMPEA_ROW_ALIGN")) align = std::max(4, (std::atoi(a) + 3) & ~3);
     st.stride = (4 * st.nq + align - 1) / align * align;
-    // the variation kernel: lane groups, or the task-dealt kernel when asked
-    // for (GMPEA_TASKED=1) and the rows have at most kTaskChunks chunks
+    // the variation kernel: task-dealt for rows of at most kTaskChunks chunks
+    // (d <= 128), lane groups for longer rows; GMPEA_TASKED=0 takes lane groups
+    // for every width (a comparison knob: the kernel fixes the evaluation's
+    // rounding order, so runs to be compared bitwise must agree on it)
     const char *tk = std::getenv("GMPEA_TASKED");
-    st.tasked = (st.nq <= kTaskChunks && tk && std::atoi(tk) == 1) ? 1 : 0;
+    st.tasked = (st.nq <= kTaskChunks && !(tk && std::atoi(tk) == 0)) ? 1 : 0;
   }
   st.rq = rec_quads(m);
   st.nblk = (N + kBlock - 1) / kBlock;

@@ -4,6 +4,8 @@
 // objective count M, so each instantiation holds only the registers its m needs.
 #pragma once
 
+#include <type_traits>
+
 #include "gmpea_internal.hpp"
 
 namespace gmpea {
@@ -469,15 +471,16 @@ __global__ __launch_bounds__(kBlock) void k_vary(DevState st) {
 
 // ----------------------------------------------------------------------------
 // Task-dealt variation for rows of at most kTaskChunks float4 chunks (d <= 128).
-// A wave builds 64 offspring: lane o first draws offspring o's mating picks
-// and finds its parents' rows; then the wave's 64 nq tasks (offspring o, chunk
-// q), numbered o nq + q, are dealt to the lanes in order, task lane + 64 s in
-// step s, so every lane runs exactly nq steps with no lane idle, and one wave
-// instruction reads and writes 64 consecutive chunks (about 1 KB of offspring
-// rows, the matching spans of the parent rows). Each task leaves its chunk's
-// evaluation partial in LDS; lane o then adds its offspring's partials in
-// chunk order and finishes F, CV and the ideal point. The draws and the
-// variation of every variable are those of vary_body.
+// A wave builds kTaskOff offspring: lane o < kTaskOff first draws offspring o's
+// mating picks and finds its parents' rows; then the wave's kTaskOff nq tasks
+// (offspring o, chunk q), numbered o nq + q, are dealt to the lanes in order,
+// task lane + 64 s in step s, so one wave instruction reads and writes 64
+// consecutive chunks (about 1 KB of offspring rows, the matching spans of the
+// parent rows) and no lane idles before the last step. Each task leaves its
+// chunk's evaluation partial in LDS; lane o then adds its offspring's partials
+// in chunk order and finishes F, CV and the ideal point. The draws and the
+// variation of every variable are those of vary_body. kTaskOff = 32 keeps the
+// LDS per wave near 5 KB, so LDS allows eight waves per SIMD.
 // ----------------------------------------------------------------------------
 // Evaluation partial of chunk q (variables 4q .. 4q + 3 below d, in order).
 template <int M, int FAM>
@@ -512,36 +515,45 @@ __device__ __forceinline__ Rec<M> eval_partials(const float *part, int nq, float
 }
 
 // LDS of tvary_body, one buffer per kernel whatever the template instances a
-// batched kernel holds (a non-template function's shared array): per wave, the
-// 64 offspring's sources, their chunk partials (offspring-major) and their two
-// leading chunks.
+// batched kernel holds (a non-template function's shared array; m <= 3 and
+// m > 3 never share a kernel): per wave, the kTaskOff offspring's sources, their
+// chunk partials (offspring-major) and their leading variables (x1, x2 for
+// m <= 3; the first two chunks for m > 3).
+template <bool W>
 struct TvaryLds {
-  int4 src[kBlock / 64][64];  // parent rows a, b; own row; index | cross << 30 (-1: none)
-  float part[kBlock / 64][64 * kTaskChunks];
-  float4 lead[kBlock / 64][64][2];
+  int4 src[kBlock / 64][kTaskOff];  // parent rows a, b; own row; index | cross << 30 (-1: none)
+  float part[kBlock / 64][kTaskOff * kTaskChunks];
+  typename std::conditional<W, float4[kBlock / 64][kTaskOff][2], float2[kBlock / 64][kTaskOff]>::type lead;
 };
-__device__ __forceinline__ TvaryLds &tvary_lds() {
-  __shared__ TvaryLds lds;
+__device__ __forceinline__ TvaryLds<false> &tvary_lds_narrow() {
+  __shared__ TvaryLds<false> lds;
+  return lds;
+}
+__device__ __forceinline__ TvaryLds<true> &tvary_lds_wide() {
+  __shared__ TvaryLds<true> lds;
   return lds;
 }
 
 template <int M, int FAM>
 __device__ __forceinline__ void tvary_body(const DevState &st, int L, int G) {
-  constexpr int kLead = M <= 3 ? 1 : EvalAcc<M>::kLeadChunks;
+  constexpr bool kWide = M > 3;
+  constexpr int kLead = kWide ? EvalAcc<M>::kLeadChunks : 1;
   static_assert(kLead <= 2, "at most two leading chunks");
-  TvaryLds &lds = tvary_lds();
+  auto &lds = [] () -> auto & {
+    if constexpr (kWide) return tvary_lds_wide();
+    else return tvary_lds_narrow();
+  }();
   auto &s_src = lds.src;
   auto &s_part = lds.part;
-  auto &s_lead = lds.lead;
   const int half = G >> 1;  // blocks per population
   const int p = L >= half ? 1 : 0;
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int base = (L - p * half) * kBlock + wv * 64;  // the wave's first offspring
+  const int base = (L - p * half) * (kBlock / 64 * kTaskOff) + wv * kTaskOff;  // the wave's first offspring
   const uint32_t k = *st.gen + 1u;
   const uint32_t tagp = (p << 16);
   const int n = st.n, nq = st.nq;
   // ---- lane o: offspring base + o -- mating picks and parent rows ----
-  {
+  if (lane < kTaskOff) {
     const int i = base + lane;
     int4 src = make_int4(0, 0, 0, -1);
     if (i < n) {
@@ -567,17 +579,18 @@ __device__ __forceinline__ void tvary_body(const DevState &st, int L, int G) {
     s_src[wv][lane] = src;
   }
   __syncthreads();
-  // ---- the wave's 64 nq tasks, task lane + 64 s in step s ----
+  // ---- the wave's kTaskOff nq tasks, task lane + 64 s in step s ----
   const float4 *lb4 = reinterpret_cast<const float4 *>(st.prob.lb);
   const float4 *ub4 = reinterpret_cast<const float4 *>(st.prob.ub);
   const float4 *is4 = reinterpret_cast<const float4 *>(st.prob.inv_span);
   const uint32_t tagv = (kTagVar << 24) | tagp;
   const bool de = st.op == 1;
   const uint64_t T = st.tpm;
+  const int tasks = kTaskOff * nq, steps = (tasks + 63) >> 6;
   const int dq = 64 % nq, dof = 64 / nq;
   int o = lane / nq, q = lane - (lane / nq) * nq;
-  for (int step = 0; step < nq; ++step) {
-    const int4 src = s_src[wv][o];
+  for (int step = 0; step < steps; ++step) {
+    const int4 src = o < kTaskOff ? s_src[wv][o] : make_int4(0, 0, 0, -1);
     if (src.w >= 0) {
       const int i = src.w & 0x3FFFFFFF;
       const bool cross = (src.w >> 30) != 0;
@@ -611,7 +624,11 @@ __device__ __forceinline__ void tvary_body(const DevState &st, int L, int G) {
       reinterpret_cast<float4 *>(st.rows + static_cast<size_t>(offspring_row(st, k & 1u, p, i)) *
                                                st.stride)[q] = ov;
       s_part[wv][o * nq + q] = chunk_partial<M, FAM>(q, ov, st.d);
-      if (q < kLead) s_lead[wv][o][q] = ov;
+      if constexpr (kWide) {
+        if (q < kLead) lds.lead[wv][o][q] = ov;
+      } else {
+        if (q == 0) lds.lead[wv][o] = make_float2(ov.x, ov.y);
+      }
     }
     q += dq;
     o += dof;
@@ -626,9 +643,15 @@ __device__ __forceinline__ void tvary_body(const DevState &st, int L, int G) {
 #pragma unroll
   for (int a = 0; a < M; ++a) zv[a] = __builtin_huge_valf();
   const int i = base + lane;
-  if (i < n) {
-    const float4 c0 = s_lead[wv][lane][0];
-    const float4 c1 = kLead > 1 ? s_lead[wv][lane][kLead > 1 ? 1 : 0] : make_float4(0, 0, 0, 0);
+  if (lane < kTaskOff && i < n) {
+    float4 c0, c1 = make_float4(0, 0, 0, 0);
+    if constexpr (kWide) {
+      c0 = lds.lead[wv][lane][0];
+      if (kLead > 1) c1 = lds.lead[wv][lane][kLead > 1 ? 1 : 0];
+    } else {
+      const float2 x12 = lds.lead[wv][lane];
+      c0 = make_float4(x12.x, x12.y, 0.0f, 0.0f);
+    }
     const Rec<M> fc = eval_partials<M, FAM>(&s_part[wv][lane * nq], nq, c0, c1, st.prob);
     rec_store<M>(st.FCO[p], i, fc);
 #pragma unroll

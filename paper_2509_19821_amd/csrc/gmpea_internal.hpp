@@ -103,16 +103,19 @@ struct DevState {
 // Launch geometry shared by host and device (plain and batched launches must
 // agree on it, since it fixes the lane grouping and so the rounding order).
 // Variation kernels, fixed per instance (plain and batched launches must agree,
-// since the kernel fixes the evaluation's rounding order). The lane-group
-// kernel takes vary_lanes_of_chunks(nq) lanes per offspring: enough that each
-// lane keeps two to four float4 chunks, except the widest rows (d > 92),
-// where four lanes of six or seven chunks each measured faster than eight.
-// The task-dealt kernel (a wave builds 64 offspring, 256 per block; rows of at
-// most kTaskChunks chunks, d <= 128) is opt-in (GMPEA_TASKED=1 at gmpea_init):
-// it measured slower on the large workload (77 against 58 us for the variation
-// at N = 100,128) and faster only beyond the last-level cache (519 against
-// 560 us at N = 1,000,405).
+// since the kernel fixes the evaluation's rounding order). Rows of at most
+// kTaskChunks chunks (d <= 128) take the task-dealt kernel (a wave builds
+// kTaskOff offspring, its lanes dealt consecutive (offspring, chunk) tasks):
+// every wave instruction moves about 1 KB of consecutive chunks, which keeps
+// the variation at the same cost whether the parents' rows are shared by many
+// slots (early generations, most slots replaced) or all distinct (later, most
+// slots kept): 60-64 us against 55-77 us for lane groups at N = 100,128, and
+// 445-454 against 536-804 us at N = 1,000,405. Longer rows take the lane-group
+// kernel, vary_lanes_of_chunks(nq) lanes per offspring: enough that each lane
+// keeps two to four float4 chunks, except the widest rows (d > 92), where four
+// lanes of six or seven chunks each measured faster than eight.
 constexpr int kTaskChunks = 32;
+constexpr int kTaskOff = 32;  // offspring per wave of the task-dealt kernel
 __host__ __device__ inline int vary_lanes_of_chunks(int nq) {
   return nq >= 24 ? 4 : nq >= 16 ? 8 : nq >= 6 ? 4 : nq >= 3 ? 2 : 1;
 }
@@ -129,7 +132,10 @@ __host__ __device__ inline int vary_blocks_of(int n, int lanes) {
   const int per = kBlock / lanes;
   return 2 * ((n + per - 1) / per);
 }
-__host__ __device__ inline int vary_grid(const DevState &st) { return vary_blocks_of(st.n, vary_lanes_of(st)); }
+// (the task-dealt kernel builds kBlock / 64 * kTaskOff offspring per block)
+__host__ __device__ inline int vary_grid(const DevState &st) {
+  return vary_tasked(st) ? vary_blocks_of(st.n, 64 / kTaskOff) : vary_blocks_of(st.n, vary_lanes_of(st));
+}
 
 // Launchers (gmpea_kernels.hip). Each enqueues on `s` and returns the launch status.
 hipError_t launch_init(const DevState &st, hipStream_t s);

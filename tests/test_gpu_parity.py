@@ -346,6 +346,26 @@ def test_generation_teacher_forced(G, which, agg, seed):
         gp.close()
 
 
+@pytest.mark.parametrize("which,op,seed", [("small", 0, 3), ("medium", 0, 4), ("medium", 1, 5)])
+def test_generation_lane_group_variation(G, which, op, seed, monkeypatch):
+    """The lane-group variation kernel (taken by rows longer than 128
+    variables) at the widths where the task-dealt kernel is the default
+    (GMPEA_TASKED=0 at init selects it): teacher-forced generations, SBX and
+    DE, and an initial evaluation that matches its summation order (copied
+    rows evaluate equal to their sources)."""
+    prob, cfg, _ = ci.WORKLOADS[which](seed)
+    cfg = dict(cfg, op=op)
+    monkeypatch.setenv("GMPEA_TASKED", "0")
+    gp, o = _pair(prob, cfg)
+    monkeypatch.delenv("GMPEA_TASKED")
+    try:
+        gp.step(3)
+        frac = _teacher_forced(gp, o, 2, "%s lane groups op=%d seed=%d" % (which, op, seed))
+        assert frac < 0.005
+    finally:
+        gp.close()
+
+
 @pytest.mark.parametrize("which,seed,rule", [("small", 4, 0), ("medium", 5, 0), ("medium", 6, 1)])
 def test_generation_teacher_forced_de(G, which, seed, rule):
     """The DE operator (CR = 1, F = 0.5, then PM) in place of SBX; also with
