@@ -56,17 +56,16 @@ def bytes_model(n, m, d, t, rho):
       op1:    both offspring F/CV read (2 (m + 1)), weight (m), both new
               offspring F/CV written (2 (m + 1)) -- per subproblem
       select: parent F/CV (m + 1), weight (m), reverse list (t_p entries),
-              candidate F/CV once per offspring (m + 1), the slot's replacement
-              record (1); winners' F/CV written (m + 1) times rho_p
-      remap:  per slot: its decision (1) and its new location (1) written; a
-              kept slot (1 - rho_p) also reads its location and, at most,
-              copies its row home (read + write, 2 d)"""
+              candidate F/CV once per offspring (m + 1); a replaced slot
+              (rho_p) writes the winner's F/CV (m + 1) and its new location
+              (1), a kept slot reads its location (1). The kernel's copies of
+              kept rows out of the next generation's offspring region are not
+              the method's bytes: they show in the measured traffic only."""
     vary = sum(n * 4 * (2 * d + (m + 1) + 2) for _ in range(2))
     op1 = n * 4 * (4 * (m + 1) + m)
-    select = sum(n * 4 * ((m + 1) + m + t[p] + (m + 1) + 1) + rho[p] * n * 4 * (m + 1)
+    select = sum(n * 4 * ((m + 1) + m + t[p] + (m + 1)) + rho[p] * n * 4 * (m + 2) + (1 - rho[p]) * n * 4
                  for p in range(2))
-    remap = sum(n * 4 * 2 + (1 - rho[p]) * n * 4 * (1 + 2 * d) for p in range(2))
-    return {"vary": vary, "op1": op1, "select": select, "remap": remap}
+    return {"vary": vary, "op1": op1, "select": select}
 
 
 def kernel_hash():

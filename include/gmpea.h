@@ -298,12 +298,12 @@ const char *gmpea_last_error(void);
 /* Run n_gen generations one launch at a time with HIP events recorded on the
  * handle's stream around every kernel, and return each kernel's mean duration in
  * milliseconds: ms[0] variation + evaluation + ideal point, ms[1] offspring
- * cooperation (OP1), ms[2] neighbour replacement decisions (OP2 + OP3), ms[3]
- * the locations after the replacement; then ms[4]: the variation kernel timed
- * over n_gen launches back to back between two events (repeated, it rewrites
- * the same offspring of the same generation), which leaves out the per-launch
- * event overhead (ms holds 5 floats). The generations are real (the state
- * advances by n_gen). Synchronises. */
+ * cooperation (OP1), ms[2] neighbour replacement decisions (OP2 + OP3) with the
+ * slots' new locations; then ms[3]: the variation kernel timed over n_gen
+ * launches back to back between two events (repeated, it rewrites the same
+ * offspring of the same generation), which leaves out the per-launch event
+ * overhead (ms holds 4 floats). The generations are real (the state advances
+ * by n_gen). Synchronises. */
 gmpea_status gmpea_profile(gmpea_t h, int32_t n_gen, float *ms);
 
 /* The counter RNG every draw of the method uses (the paper names none):

@@ -498,6 +498,15 @@ gmpea_status gmpea_init(const gmpea_problem *P, const gmpea_config *C, const gmp
     // rounding order, so runs to be compared bitwise must agree on it)
     const char *tk = std::getenv("GMPEA_TASKED");
     st.tasked = (st.nq <= kTaskChunks && !(tk && std::atoi(tk) == 0)) ? 1 : 0;
+    st.task_off = task_off_for(N);
+    // offspring generations kept in the arena (GMPEA_OFFSPRING_GENERATIONS, 2 to
+    // 16, is a layout experiment knob; results do not depend on it)
+    st.npar = kOffspringGenerations;
+    if (const char *a = std::getenv("GMPEA_OFFSPRING_GENERATIONS"))
+      st.npar = std::min(16, std::max(2, std::atoi(a)));
+    // arena rows are 32-bit indices: fewer generations for the largest populations
+    const int64_t rows_pad = int64_t((N + kBlock - 1) / kBlock) * kBlock;
+    st.npar = static_cast<int32_t>(std::max<int64_t>(2, std::min<int64_t>(st.npar, ((int64_t(1) << 32) / rows_pad - 2) / 2)));
   }
   st.rq = rec_quads(m);
   st.nblk = (N + kBlock - 1) / kBlock;
@@ -552,11 +561,10 @@ gmpea_status gmpea_init(const gmpea_problem *P, const gmpea_config *C, const gmp
     lb = c.take<float>(st.stride);
     ub = c.take<float>(st.stride);
     inv_span = c.take<float>(st.stride);
-    st.rows = c.take<float>(6 * rows * st.stride);
+    st.rows = c.take<float>((2 + 2 * static_cast<size_t>(st.npar)) * rows * st.stride);
     for (int p = 0; p < 2; ++p) {
       st.X[p] = st.rows ? st.rows + p * rows * st.stride : nullptr;
       st.loc[p] = c.take<uint32_t>(rows);
-      st.rsrc[p] = c.take<int32_t>(rows);
       st.FC[p] = c.take<float4>(rows * st.rq);
       st.FCO[p] = c.take<float4>(rows * st.rq);
       st.FCN[p] = c.take<float4>(rows * st.rq);
@@ -621,7 +629,7 @@ gmpea_status gmpea_init(const gmpea_problem *P, const gmpea_config *C, const gmp
   if (noffs > 0) cp(d_offs, offs.data(), offs.size() * sizeof(int32_t));
   zero(d_flag, 0, 4 * sizeof(uint32_t));
   st.region = static_cast<int64_t>(rows);
-  zero(st.rows, 0, 6 * rows * st.stride * sizeof(float));
+  zero(st.rows, 0, (2 + 2 * static_cast<size_t>(st.npar)) * rows * st.stride * sizeof(float));
   for (int p = 0; p < 2; ++p) {
     zero(st.FC[p], 0, rows * st.rq * sizeof(float4));
     zero(st.FCO[p], 0, rows * st.rq * sizeof(float4));
@@ -1001,7 +1009,7 @@ gmpea_status gmpea_read(gmpea_t h, int32_t buffer, int32_t pop, void *host, int6
         uint32_t g = 0;
         gmpea_status s = d2h(h, &g, st.gen, 1, "gmpea_read");
         if (s != GMPEA_OK) return s;
-        src = st.rows + static_cast<size_t>(offspring_row(st, g & 1u, pop, 0)) * st.stride;
+        src = st.rows + static_cast<size_t>(offspring_row(st, gen_slot(st, g), pop, 0)) * st.stride;
       }
       if (e == hipSuccess)
         e = hipMemcpy2DAsync(host, d * sizeof(float), src, st.stride * sizeof(float), d * sizeof(float), n,
@@ -1144,7 +1152,7 @@ gmpea_status gmpea_profile(gmpea_t h, int32_t n_gen, float *ms) {
   hipError_t e = hipSuccess;
   for (; made <= kPhases && e == hipSuccess; ++made) e = hipEventCreate(&ev[made]);
   if (e != hipSuccess) --made;
-  double acc[kPhases] = {0.0, 0.0, 0.0, 0.0};
+  double acc[kPhases] = {};
   for (int32_t g = 0; g < n_gen && e == hipSuccess; ++g) {
     e = hipEventRecord(ev[0], h->stream);
     for (int ph = 0; ph < kPhases && e == hipSuccess; ++ph) {
@@ -1280,8 +1288,7 @@ struct gmpea_pool_s {
   // device tables
   DevState *d_states = nullptr;
   int32_t state_cap = 0;
-  // work lists per phase: [0] instances with m <= 3 (every instance in the row
-  // copies, which do not depend on m), [1] instances with m > 3
+  // work lists per class (see in_class) and phase
   int2 *d_work[kWorkClasses][kPhases] = {};
   int32_t work_cap[kWorkClasses][kPhases] = {};
   int32_t nwork[kWorkClasses][kPhases] = {};
@@ -1406,21 +1413,17 @@ gmpea_status pool_table(gmpea_pool_s *q, T **ptr, int32_t *cap, int32_t need) {
 int32_t phase_blocks(const DevState &st, int phase) {
   if (phase == 0) return vary_grid(st);
   if (phase == 1) return st.nblk;
-  if (phase == 2) return st.sel_blocks0 + st.sel_blocks1;
-  return remap_blocks_of(st.n);
+  return st.sel_blocks0 + st.sel_blocks1;
 }
 
 // Work list of one phase. Schedule 0 keeps each instance's consecutive blocks
 // on one XCD (instances placed largest first on the least-loaded XCD, large
 // ones split into contiguous runs) so neighbouring subproblems share an L2;
 // the hardware deals block b to XCD b mod 8, hence the interleaving at the end.
-// cls 0: instances with m <= 3 (every instance for the row copies), 1: m > 3.
 // Work-list classes of a pool: bit 0 records of m > 3 (kernels of their own),
-// bit 1 the task-dealt variation. The location phase takes every instance in
-// class 0; the OP1 and selection phases split by m only.
+// bit 1 the task-dealt variation. The OP1 and selection phases split by m only.
 bool in_class(const DevState &st, int phase, int cls) {
   const int wide = st.m > 3 ? 1 : 0, tasked = st.tasked ? 1 : 0;
-  if (phase == 3) return cls == 0;
   if (phase == 0) return cls == (wide | (tasked << 1));
   return cls == wide;
 }
@@ -1512,7 +1515,7 @@ hipError_t pool_generation(const gmpea_pool_s *q, hipStream_t s) {
 gmpea_status pool_enqueue(gmpea_pool_s *q, int32_t n) {
   gmpea_status s = pool_rebuild(q);
   if (s != GMPEA_OK) return s;
-  if (q->nwork[0][3] == 0) return GMPEA_OK;  // no instance
+  if (q->nwork[0][1] + q->nwork[1][1] == 0) return GMPEA_OK;  // no instance (OP1 lists hold them all)
   const int32_t G = q->chunk;
   if (G >= 2 && n >= G) {
     if (!q->gexec || q->gchunk != G) {
@@ -1663,6 +1666,7 @@ gmpea_status gmpea_pool_admit(gmpea_pool_t q, const gmpea_problem *P, const gmpe
     return fail(GMPEA_ENOMEM, "gmpea_pool_admit: the instance does not fit the pool's budget");
   if (s != GMPEA_OK) return s;
   h->stream = q->stream;  // every later operation runs in order with the pool's generations
+  h->st.task_off = kTaskOff;  // batched launches fill the chip (same results, see task_off_for)
   int32_t k = 0;
   while (k < static_cast<int32_t>(q->slots.size()) && q->slots[k]) ++k;
   if (k == static_cast<int32_t>(q->slots.size())) q->slots.push_back(nullptr);

@@ -418,7 +418,7 @@ __device__ __forceinline__ void vary_body(const DevState &st, int L, int G) {
     // the parents' current decision vectors, wherever the replacement left them
     const float4 *ra = arena_row(st, st.loc[p][pa]);
     const float4 *rb = arena_row(st, st.loc[p][pb]);
-    float4 *ro = reinterpret_cast<float4 *>(st.rows + static_cast<size_t>(offspring_row(st, k & 1u, p, i)) *
+    float4 *ro = reinterpret_cast<float4 *>(st.rows + static_cast<size_t>(offspring_row(st, gen_slot(st, k), p, i)) *
                                                           st.stride);
     const float4 *lb4 = reinterpret_cast<const float4 *>(st.prob.lb);
     const float4 *ub4 = reinterpret_cast<const float4 *>(st.prob.ub);
@@ -471,16 +471,17 @@ __global__ __launch_bounds__(kBlock) void k_vary(DevState st) {
 
 // ----------------------------------------------------------------------------
 // Task-dealt variation for rows of at most kTaskChunks float4 chunks (d <= 128).
-// A wave builds kTaskOff offspring: lane o < kTaskOff first draws offspring o's
-// mating picks and finds its parents' rows; then the wave's kTaskOff nq tasks
-// (offspring o, chunk q), numbered o nq + q, are dealt to the lanes in order,
-// task lane + 64 s in step s, so one wave instruction reads and writes 64
-// consecutive chunks (about 1 KB of offspring rows, the matching spans of the
-// parent rows) and no lane idles before the last step. Each task leaves its
-// chunk's evaluation partial in LDS; lane o then adds its offspring's partials
-// in chunk order and finishes F, CV and the ideal point. The draws and the
-// variation of every variable are those of vary_body. kTaskOff = 32 keeps the
-// LDS per wave near 5 KB, so LDS allows eight waves per SIMD.
+// A wave builds `off` = st.task_off offspring: lane o < off first draws
+// offspring o's mating picks and finds its parents' rows; then the wave's
+// off nq tasks (offspring o, chunk q), numbered o nq + q, are dealt to the
+// lanes in order, task lane + 64 s in step s, so one wave instruction reads and
+// writes 64 consecutive chunks (about 1 KB of offspring rows, the matching
+// spans of the parent rows) and no lane idles before the last step. Each task
+// leaves its chunk's evaluation partial in LDS; lane o then adds its
+// offspring's partials in chunk order and finishes F, CV and the ideal point,
+// so the results do not depend on off. The draws and the variation of every
+// variable are those of vary_body. At most kTaskOff = 32 offspring per wave keep
+// the LDS per wave near 5 KB, so LDS allows eight waves per SIMD.
 // ----------------------------------------------------------------------------
 // Evaluation partial of chunk q (variables 4q .. 4q + 3 below d, in order).
 template <int M, int FAM>
@@ -548,12 +549,13 @@ __device__ __forceinline__ void tvary_body(const DevState &st, int L, int G) {
   const int half = G >> 1;  // blocks per population
   const int p = L >= half ? 1 : 0;
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int base = (L - p * half) * (kBlock / 64 * kTaskOff) + wv * kTaskOff;  // the wave's first offspring
+  const int off = st.task_off;
+  const int base = (L - p * half) * (kBlock / 64 * off) + wv * off;  // the wave's first offspring
   const uint32_t k = *st.gen + 1u;
   const uint32_t tagp = (p << 16);
   const int n = st.n, nq = st.nq;
   // ---- lane o: offspring base + o -- mating picks and parent rows ----
-  if (lane < kTaskOff) {
+  if (lane < off) {
     const int i = base + lane;
     int4 src = make_int4(0, 0, 0, -1);
     if (i < n) {
@@ -579,18 +581,18 @@ __device__ __forceinline__ void tvary_body(const DevState &st, int L, int G) {
     s_src[wv][lane] = src;
   }
   __syncthreads();
-  // ---- the wave's kTaskOff nq tasks, task lane + 64 s in step s ----
+  // ---- the wave's off nq tasks, task lane + 64 s in step s ----
   const float4 *lb4 = reinterpret_cast<const float4 *>(st.prob.lb);
   const float4 *ub4 = reinterpret_cast<const float4 *>(st.prob.ub);
   const float4 *is4 = reinterpret_cast<const float4 *>(st.prob.inv_span);
   const uint32_t tagv = (kTagVar << 24) | tagp;
   const bool de = st.op == 1;
   const uint64_t T = st.tpm;
-  const int tasks = kTaskOff * nq, steps = (tasks + 63) >> 6;
+  const int tasks = off * nq, steps = (tasks + 63) >> 6;
   const int dq = 64 % nq, dof = 64 / nq;
   int o = lane / nq, q = lane - (lane / nq) * nq;
   for (int step = 0; step < steps; ++step) {
-    const int4 src = o < kTaskOff ? s_src[wv][o] : make_int4(0, 0, 0, -1);
+    const int4 src = o < off ? s_src[wv][o] : make_int4(0, 0, 0, -1);
     if (src.w >= 0) {
       const int i = src.w & 0x3FFFFFFF;
       const bool cross = (src.w >> 30) != 0;
@@ -621,7 +623,7 @@ __device__ __forceinline__ void tvary_body(const DevState &st, int L, int G) {
       if (l0 + 1 >= st.d) ov.y = 0.0f;
       if (l0 + 2 >= st.d) ov.z = 0.0f;
       if (l0 + 3 >= st.d) ov.w = 0.0f;
-      reinterpret_cast<float4 *>(st.rows + static_cast<size_t>(offspring_row(st, k & 1u, p, i)) *
+      reinterpret_cast<float4 *>(st.rows + static_cast<size_t>(offspring_row(st, gen_slot(st, k), p, i)) *
                                                st.stride)[q] = ov;
       s_part[wv][o * nq + q] = chunk_partial<M, FAM>(q, ov, st.d);
       if constexpr (kWide) {
@@ -643,7 +645,7 @@ __device__ __forceinline__ void tvary_body(const DevState &st, int L, int G) {
 #pragma unroll
   for (int a = 0; a < M; ++a) zv[a] = __builtin_huge_valf();
   const int i = base + lane;
-  if (lane < kTaskOff && i < n) {
+  if (lane < off && i < n) {
     float4 c0, c1 = make_float4(0, 0, 0, 0);
     if constexpr (kWide) {
       c0 = lds.lead[wv][lane][0];
@@ -778,6 +780,60 @@ __global__ __launch_bounds__(kBlock) void k_op1(DevState st) {
 }
 
 // ----------------------------------------------------------------------------
+// Kept rows moved home. A kept slot keeps its row, but a row in the other
+// parity's offspring regions would be overwritten by the next generation's
+// offspring: such a row is copied to the slot's home row (`from` -> `home`,
+// arena rows) by all lanes of the wave together. The wave's pending rows are
+// ranked, their (from, home) pairs staged in LDS, and the (row, chunk) copies
+// dealt to the lanes in order, four per lane at a time with the four loads
+// issued before the stores. No slot points at another slot's home row, so the
+// copies never overwrite a row that some location still names. Every thread of
+// the block must call it (a block barrier follows the staging).
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ void wave_copy_home(const DevState &st, bool copy, uint32_t from, uint32_t home) {
+  __shared__ uint2 s_cp[kBlock / 64][64];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const uint64_t pending = __ballot(copy);
+  if (copy) s_cp[wv][__popcll(pending & ((1ull << lane) - 1ull))] = make_uint2(from, home);
+  __syncthreads();
+  if (pending == 0) return;  // uniform over the wave
+  const int np = __popcll(pending);
+  const int nq = st.nq, tasks = np * nq;
+  const int dq = 64 % nq, dr = 64 / nq;
+  int r = lane / nq, c = lane - (lane / nq) * nq;
+  // one task: load its chunk (held in v, its destination in o; o < 0: none)
+  auto fetch = [&](int t, float4 &v, int64_t &o) {
+    o = -1;
+    if (t < tasks) {
+      const uint2 fh = s_cp[wv][r];
+      v = arena_row(st, fh.x)[c];
+      o = static_cast<int64_t>(fh.y) * st.stride + 4 * c;
+    }
+    c += dq;
+    r += dr;
+    if (c >= nq) {
+      c -= nq;
+      ++r;
+    }
+  };
+  auto put = [&](const float4 &v, int64_t o) {
+    if (o >= 0) *reinterpret_cast<float4 *>(st.rows + o) = v;
+  };
+  for (int t0 = lane; t0 < tasks; t0 += 4 * 64) {
+    float4 v0, v1, v2, v3;
+    int64_t o0, o1, o2, o3;
+    fetch(t0, v0, o0);
+    fetch(t0 + 64, v1, o1);
+    fetch(t0 + 128, v2, o2);
+    fetch(t0 + 192, v3, o3);
+    put(v0, o0);
+    put(v1, o1);
+    put(v2, o2);
+    put(v3, o3);
+  }
+}
+
+// ----------------------------------------------------------------------------
 // k_select: OP2 + OP3 (Eqs. (12)-(13)) as a pull over parent slot j of
 // population p. Offspring i qualifies iff j is in B_p(i) and its new offspring
 // is strictly better than parent j at w_j (population 1: lower CV, or equal CV
@@ -799,6 +855,11 @@ __global__ __launch_bounds__(kBlock) void k_op1(DevState st) {
 // exactly when some candidate qualifies, since qualifying means being below the
 // parent in the same order; a minimum over a total order does not depend on how
 // the candidates were split among lanes.
+// The slot's location follows the decision in the same launch: a replaced slot
+// points at the winner's offspring row (written by this generation's
+// variation, parity k); a kept slot whose row lies in the other parity's
+// offspring regions has it moved home (wave_copy_home). Neither touches a row
+// or a record that another slot's decision reads.
 // ----------------------------------------------------------------------------
 struct SelKey {
   float c, g;
@@ -847,6 +908,8 @@ __device__ __forceinline__ void select_body(const DevState &st, int L) {
   if (threadIdx.x == 0) s_cnt = 0;
   __syncthreads();
   const bool live = j < st.n;
+  bool copy = false;  // a kept row this lane moves home (see wave_copy_home)
+  uint32_t from = 0, home = 0;
   // keys carry i2 = 2 i + (OP1 source bit of i): the same order as i, and the
   // winner's row follows without another load
   constexpr int kCv = Rec<M>::kCv;
@@ -929,51 +992,11 @@ __device__ __forceinline__ void select_body(const DevState &st, int L) {
     const float pg = aggregate<M>(par, w, z, st.agg, st.theta);
     const bool win = best.i != 0x7FFFFFFF && (best.c < pc || (best.c == pc && best.g < pg));
     const int bi = best.i >> 1;
-    if (!win && g == 0) {  // the parent stays
+    const uint32_t k = *st.gen;  // this generation (OP1 advanced the counter)
+    if (!win && g == 0) {  // the parent stays, and its row too unless the next offspring overwrite it
       if (st.win[p]) st.win[p][j] = -1;
-      st.rsrc[p][j] = -1;
-    }
-    // the lane that holds the winner (m <= 3), the group's first lane (m > 3)
-    if (win && (M <= 3 ? mine.i == best.i : g == 0)) {
-      if (st.win[p]) st.win[p][j] = bi;
-      if constexpr (M > 3) {
-        bestf = rec_load<M>(st.FCN[p], bi);
-        bestf.v[kCv] = fabsf(bestf.v[kCv]);
-      }
-      rec_store<M>(st.FC[p], j, bestf);
-      st.rsrc[p][j] = ((p ^ (best.i & 1)) << 30) | bi;
-      atomicAdd(&s_cnt, 1);
-    }
-  }
-  __syncthreads();
-  if (threadIdx.x == 0 && s_cnt > 0)
-    atomicAdd(&st.repl[p * kReplLanes + (L & (kReplLanes - 1))], static_cast<unsigned long long>(s_cnt));
-}
-
-// ----------------------------------------------------------------------------
-// Locations after the replacement, one thread per slot of both populations
-// (slot e of population e / n). A replaced slot points at its winning offspring
-// row (written by this generation, parity k). A kept slot keeps its row, but a
-// row in the other parity's offspring regions would be overwritten by the next
-// generation's offspring: such a row is copied to the slot's home row first, by
-// all lanes of the wave together (about one slot in a hundred is kept). No slot
-// points at another slot's home row, so the copies never overwrite a row that
-// some location still names. Every lane of the wave must reach the ballot.
-// ----------------------------------------------------------------------------
-__device__ __forceinline__ void remap_body(const DevState &st, int64_t e) {
-  const uint32_t k = *st.gen;  // the generation this replacement belongs to
-  const int n = st.n;
-  bool copy = false;
-  uint32_t from = 0, home = 0;
-  if (e < 2LL * n) {
-    const int p = e >= n ? 1 : 0;
-    const int j = static_cast<int>(e - p * n);
-    const int32_t ds = st.rsrc[p][j];
-    if (ds >= 0) {
-      st.loc[p][j] = offspring_row(st, k & 1u, ds >> 30, ds & 0x3FFFFFFF);
-    } else {
       const uint32_t l = st.loc[p][j];
-      const uint32_t lo = offspring_row(st, (k + 1u) & 1u, 0, 0);
+      const uint32_t lo = offspring_row(st, gen_slot(st, k + 1u), 0, 0);
       if (l >= lo && l < lo + 2 * static_cast<uint32_t>(st.region)) {
         copy = true;
         from = l;
@@ -981,31 +1004,25 @@ __device__ __forceinline__ void remap_body(const DevState &st, int64_t e) {
         st.loc[p][j] = home;
       }
     }
-  }
-  // the wave's lanes form groups of gw lanes (a power of two covering the row's
-  // chunks, at most 64), and each group copies one pending row at a time, so
-  // several rows move at once
-  int gw = 1;
-  while (gw < st.nq && gw < 64) gw <<= 1;
-  const int lane = threadIdx.x & 63, groups = 64 / gw, grp = lane / gw, gl = lane % gw;
-  uint64_t pending = __ballot(copy);
-  while (pending) {
-    int src_lane = -1;
-    for (int g = 0; g < groups && pending; ++g) {
-      const int b = __ffsll(static_cast<unsigned long long>(pending)) - 1;
-      pending &= pending - 1;
-      if (g == grp) src_lane = b;
-    }
-    const int sl = src_lane >= 0 ? src_lane : 0;
-    const uint32_t f = static_cast<uint32_t>(__shfl(static_cast<int>(from), sl));
-    const uint32_t h = static_cast<uint32_t>(__shfl(static_cast<int>(home), sl));
-    if (src_lane >= 0) {
-      const float4 *src = arena_row(st, f);
-      float4 *dst = reinterpret_cast<float4 *>(st.rows + static_cast<size_t>(h) * st.stride);
-      for (int c = gl; c < st.nq; c += gw) dst[c] = src[c];
+    // the lane that holds the winner (m <= 3), the group's first lane (m > 3):
+    // the slot takes the winner's F/CV and points at its offspring row
+    if (win && (M <= 3 ? mine.i == best.i : g == 0)) {
+      if (st.win[p]) st.win[p][j] = bi;
+      if constexpr (M > 3) {
+        bestf = rec_load<M>(st.FCN[p], bi);
+        bestf.v[kCv] = fabsf(bestf.v[kCv]);
+      }
+      rec_store<M>(st.FC[p], j, bestf);
+      st.loc[p][j] = offspring_row(st, gen_slot(st, k), p ^ (best.i & 1), bi);
+      atomicAdd(&s_cnt, 1);
     }
   }
+  wave_copy_home(st, copy, from, home);
+  __syncthreads();
+  if (threadIdx.x == 0 && s_cnt > 0)
+    atomicAdd(&st.repl[p * kReplLanes + (L & (kReplLanes - 1))], static_cast<unsigned long long>(s_cnt));
 }
+
 
 template <int M>
 __global__ __launch_bounds__(kBlock) void k_select(DevState st) {

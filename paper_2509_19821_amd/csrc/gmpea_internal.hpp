@@ -61,18 +61,18 @@ struct DevState {
   int32_t n, m, d, stride, nblk;  // nblk: blocks of kBlock rows per population
   int32_t nq;                      // float4 chunks holding the d variables
   int32_t tasked;                  // variation kernel: 1 task-dealt, 0 lane groups
+  int32_t task_off;                // task-dealt kernel: offspring per wave (8, 16 or 32)
   int32_t rq;                      // float4 per F/CV record and per W row
   int32_t t[2];
   int32_t lps[2];                  // lanes per slot in k_select (power of two <= 64)
   int32_t sel_blocks0, sel_blocks1;  // k_select blocks of each population
   int32_t agg;
   float theta;
-  float *rows;               // the row arena (6 regions)
+  float *rows;               // the row arena (2 + 2 npar regions)
   int64_t region;            // rows per region (nblk kBlock)
+  int32_t npar;              // generations whose offspring rows stay in the arena
   float *X[2];               // home rows: regions 0 and 1
   uint32_t *loc[2];          // arena row of slot j's current decision vector
-  int32_t *rsrc[2];          // this generation's decision for slot j: -1 kept, else
-                             // (population << 30) | offspring row
   float4 *FC[2], *FCO[2], *FCN[2];
   float4 *W;                 // unit direction (PBI) or raw weight (Tchebycheff)
   const int32_t *B[2];       // n x t_p
@@ -114,8 +114,16 @@ struct DevState {
 // kernel, vary_lanes_of_chunks(nq) lanes per offspring: enough that each lane
 // keeps two to four float4 chunks, except the widest rows (d > 92), where four
 // lanes of six or seven chunks each measured faster than eight.
+// Offspring per wave of the task-dealt kernel: at most kTaskOff (the LDS is
+// sized for it). The count changes only how the tasks are dealt, never the
+// results (each offspring's partials are added in chunk order whatever the
+// dealing), so it follows the launch: a plain launch takes fewer offspring per
+// wave when the population gives the chip few waves (shorter dependency chains
+// per wave), a pool's batched launch takes kTaskOff for every instance (the
+// pool fills the chip; fewer lanes idle in the per-offspring parts).
 constexpr int kTaskChunks = 32;
-constexpr int kTaskOff = 32;  // offspring per wave of the task-dealt kernel
+constexpr int kTaskOff = 32;
+__host__ __device__ inline int task_off_for(int n) { return n >= 65536 ? 32 : n >= 32768 ? 16 : 8; }
 __host__ __device__ inline int vary_lanes_of_chunks(int nq) {
   return nq >= 24 ? 4 : nq >= 16 ? 8 : nq >= 6 ? 4 : nq >= 3 ? 2 : 1;
 }
@@ -123,7 +131,17 @@ __host__ __device__ inline bool vary_tasked(const DevState &st) { return st.task
 __host__ __device__ inline int vary_lanes_of(const DevState &st) {
   return vary_tasked(st) ? 1 : vary_lanes_of_chunks(st.nq);
 }
-// Arena row of offspring i of population q written by a generation of parity par.
+// The arena holds the home rows of both populations, then the offspring rows
+// of the last npar generations: generation k writes its offspring into the
+// regions of slot k mod npar (one per population), so an offspring row stays
+// valid for npar generations. A kept slot whose row would be overwritten by the
+// next generation's offspring moves it home then; with npar slots that is a
+// slot replaced npar - 1 generations ago and kept since.
+constexpr int kOffspringGenerations = 8;
+__host__ __device__ inline uint32_t gen_slot(const DevState &st, uint32_t k) {
+  return k % static_cast<uint32_t>(st.npar);
+}
+// Arena row of offspring i of population q written by a generation in slot par.
 __host__ __device__ inline uint32_t offspring_row(const DevState &st, uint32_t par, int q, int i) {
   return static_cast<uint32_t>((2 + 2 * static_cast<int64_t>(par) + q) * st.region + i);
 }
@@ -132,20 +150,18 @@ __host__ __device__ inline int vary_blocks_of(int n, int lanes) {
   const int per = kBlock / lanes;
   return 2 * ((n + per - 1) / per);
 }
-// (the task-dealt kernel builds kBlock / 64 * kTaskOff offspring per block)
+// (the task-dealt kernel builds kBlock / 64 * task_off offspring per block)
 __host__ __device__ inline int vary_grid(const DevState &st) {
-  return vary_tasked(st) ? vary_blocks_of(st.n, 64 / kTaskOff) : vary_blocks_of(st.n, vary_lanes_of(st));
+  return vary_tasked(st) ? vary_blocks_of(st.n, 64 / st.task_off) : vary_blocks_of(st.n, vary_lanes_of(st));
 }
 
 // Launchers (gmpea_kernels.hip). Each enqueues on `s` and returns the launch status.
 hipError_t launch_init(const DevState &st, hipStream_t s);
 // A generation is kPhases launches: 0 variation + evaluation + ideal point,
-// 1 offspring cooperation, 2 neighbour replacement decisions, 3 locations (a
-// replaced slot points at its winner; a kept slot whose row the next
-// generation's offspring would overwrite copies it home).
-constexpr int kPhases = 4;
-// Blocks of the location phase: one thread per slot of both populations.
-__host__ __device__ inline int remap_blocks_of(int n) { return (2 * n + kBlock - 1) / kBlock; }
+// 1 offspring cooperation, 2 neighbour replacement decisions and the slots'
+// locations (a replaced slot points at its winner's offspring row; a kept slot
+// whose row the next generation's offspring would overwrite moves it home).
+constexpr int kPhases = 3;
 hipError_t launch_phase(const DevState &st, int phase, hipStream_t s);
 // Point every slot of population `pop` at its home row (after the home rows were written).
 hipError_t launch_loc_home(const DevState &st, int pop, hipStream_t s);
@@ -154,9 +170,9 @@ hipError_t launch_materialize(const DevState &st, hipStream_t s);
 hipError_t launch_generation(const DevState &st, hipStream_t s);
 // One phase of a batched generation over a pool: work[b] = (instance, block).
 // wide: the work list holds instances with m > 3 (their kernels are separate so
-// that the m <= 3 kernels keep their register budget); phase 3 takes any m.
-// tasked: the pool's instances take the task-dealt variation (a pool holds
-// instances of one variation kernel).
+// that the m <= 3 kernels keep their register budget). tasked: the work list
+// holds instances of the task-dealt variation (phase 0 only; a pool keeps one
+// work list per kernel).
 hipError_t launch_batch_phase(const DevState *states, const int2 *work, int nwork, int phase,
                               bool wide, bool tasked, hipStream_t s);
 // The m > 3 launchers (gmpea_kernels_wide.hip).

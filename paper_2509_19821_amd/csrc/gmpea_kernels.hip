@@ -14,14 +14,14 @@
 //   k_select  a lane group per parent slot (p, j): OP2 + OP3 as a pull over the
 //             reverse neighbour list of j (every offspring i with j in B_p(i)),
 //             lexicographic minimum of the qualifiers; writes the winner's F/CV
-//             and the slot's replacement record.
-//   k_remap   one thread per slot: a replaced slot's location becomes its
-//             winning offspring row; a kept slot whose row lies where the next
-//             generation writes its offspring copies it to its home row.
-// The ideal point is a grid-wide dependency between k_vary and k_op1, OP1 must
-// finish for every i before any slot can be decided, and every decision reads
-// generation-k parents before any location changes; kernel boundaries provide
-// all three.
+//             and the slot's new location (the winning offspring row), or, for
+//             a kept slot whose row lies where the next generation writes its
+//             offspring, copies that row to the slot's home row.
+// The ideal point is a grid-wide dependency between k_vary and k_op1, and OP1
+// must finish for every i before any slot can be decided; kernel boundaries
+// provide both. The decisions read only F/CV records, so a slot's new location
+// and its row copy, made in the same launch, touch nothing another decision
+// reads.
 //
 // Layout: decision vectors are rows of `stride` floats (16-byte aligned) in one
 // arena: home rows of both populations, then offspring rows of each population
@@ -337,10 +337,6 @@ __global__ __launch_bounds__(kBlock) void k_rev_sort(int32_t n, int32_t t, const
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_remap(DevState st) {
-  remap_body(st, static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x);
-}
-
 __global__ __launch_bounds__(kBlock) void k_vary_batch(const DevState *__restrict__ S,
                                                       const int2 *__restrict__ work) {
   const int2 wi = work[blockIdx.x];
@@ -387,13 +383,6 @@ __global__ __launch_bounds__(kBlock) void k_select_batch(const DevState *__restr
     select_body<2>(st, wi.y);
   else
     select_body<3>(st, wi.y);
-}
-
-__global__ __launch_bounds__(kBlock) void k_remap_batch(const DevState *__restrict__ S,
-                                                       const int2 *__restrict__ work) {
-  const int2 wi = work[blockIdx.x];
-  if (wi.x < 0) return;
-  remap_body(S[wi.x], static_cast<int64_t>(wi.y) * kBlock + threadIdx.x);
 }
 
 // Rows idx[0 .. count) of population `pop`: decision vectors to x (count x d)
@@ -762,7 +751,7 @@ static void launch_vary_mf(const DevState &st, hipStream_t s) {
 }
 
 hipError_t launch_phase(const DevState &st, int phase, hipStream_t s) {
-  if (st.m > 3 && phase < 3) return launch_phase_wide(st, phase, s);
+  if (st.m > 3) return launch_phase_wide(st, phase, s);
   if (phase == 0) {
     if (st.m == 2 && st.prob.family == 0)
       launch_vary_mf<2, 0>(st, s);
@@ -772,10 +761,8 @@ hipError_t launch_phase(const DevState &st, int phase, hipStream_t s) {
       launch_vary_mf<3, 1>(st, s);
   } else if (phase == 1) {
     GMPEA_DISPATCH_M(k_op1, st.nblk, s, st);
-  } else if (phase == 2) {
-    GMPEA_DISPATCH_M(k_select, st.sel_blocks0 + st.sel_blocks1, s, st);
   } else {
-    hipLaunchKernelGGL(k_remap, dim3(remap_blocks_of(st.n)), dim3(kBlock), 0, s, st);
+    GMPEA_DISPATCH_M(k_select, st.sel_blocks0 + st.sel_blocks1, s, st);
   }
   return hipGetLastError();
 }
@@ -783,17 +770,15 @@ hipError_t launch_phase(const DevState &st, int phase, hipStream_t s) {
 hipError_t launch_batch_phase(const DevState *states, const int2 *work, int nwork, int phase,
                               bool wide, bool tasked, hipStream_t s) {
   if (nwork <= 0) return hipSuccess;
-  if (wide && phase < 3) return launch_batch_phase_wide(states, work, nwork, phase, tasked, s);
+  if (wide) return launch_batch_phase_wide(states, work, nwork, phase, tasked, s);
   if (phase == 0 && tasked)
     hipLaunchKernelGGL(k_tvary_batch, dim3(nwork), dim3(kBlock), 0, s, states, work);
   else if (phase == 0)
     hipLaunchKernelGGL(k_vary_batch, dim3(nwork), dim3(kBlock), 0, s, states, work);
   else if (phase == 1)
     hipLaunchKernelGGL(k_op1_batch, dim3(nwork), dim3(kBlock), 0, s, states, work);
-  else if (phase == 2)
-    hipLaunchKernelGGL(k_select_batch, dim3(nwork), dim3(kBlock), 0, s, states, work);
   else
-    hipLaunchKernelGGL(k_remap_batch, dim3(nwork), dim3(kBlock), 0, s, states, work);
+    hipLaunchKernelGGL(k_select_batch, dim3(nwork), dim3(kBlock), 0, s, states, work);
   return hipGetLastError();
 }
 

@@ -6,7 +6,7 @@
 // is the largest over the m values it dispatches.
 //
 // Per m the generation is the m <= 3 one: k_vary (mating, variation,
-// evaluation, ideal point), k_op1, k_select, then the shared location phase.
+// evaluation, ideal point), k_op1, then k_select (decisions and locations).
 // Register use grows with m through the records a k_select lane keeps (its
 // parent, weight, best candidate and four candidates in flight); the evaluation
 // keeps the leading variables (the m - 1 angles) of its group's first chunks.

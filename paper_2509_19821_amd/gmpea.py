@@ -40,7 +40,7 @@ EXPORTS = ["gmpea_init", "gmpea_step", "gmpea_run", "gmpea_front", "gmpea_get_in
            "gmpea_reference_set", "gmpea_quality", "gmpea_shape", "gmpea_copy_probe",
            "gmpea_front_static"]
 COPY_STRIDED, COPY_WIDE, COPY_WIDE_NT, COPY_RUNTIME = 0, 1, 2, 3
-PHASES = ("vary", "op1", "select", "remap")
+PHASES = ("vary", "op1", "select")
 
 
 class GmpeaError(RuntimeError):
