@@ -476,19 +476,21 @@ def main():
     b2b = ms.pop("vary_back_to_back")
     model = bytes_model(n, m, d, gp.t, rho)
     dom = max(ms, key=ms.get)
+    # the variation phase's kernel: k_tvary (task-dealt) or k_vary (lane groups)
+    kname = ("tvary" if gp.info()["task_dealt"] else "vary") if dom == "vary" else dom
     # the dominant kernel's launch duration: the variation kernel launched back
     # to back between two events (it rewrites the same offspring when
     # repeated), the others one launch at a time between events
     t_dom = b2b if dom == "vary" else ms[dom]
     achieved = model[dom] / (t_dom * 1e-3) / 1e9
-    traffic = measured_traffic(dom)
+    traffic = measured_traffic(kname)
     log("bench: per-kernel ms %s; model bytes %s" % (ms, model))
     gen_bytes = sum(model.values())
     copies = copy_probe(g)
     log("bench: copy bandwidth %s GB/s" % copies)
     hbm = {"achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": round(achieved / HBM_PEAK_GBS, 4)}
-    valu = measured_valu(dom)
+    valu = measured_valu(kname)
     alu = None
     if valu is not None:
         # lane-operations per second: wave64 instructions x 64 lanes over the launch
@@ -497,7 +499,7 @@ def main():
                "unit": "T VALU lane-ops/s", "frac": round(lane_ops / ALU_PEAK_LANE_OPS, 4),
                "valu_insts_per_launch": int(valu)}
     bind = alu if (alu is not None and alu["frac"] > hbm["frac"]) else hbm
-    roof = {"bound": "alu" if bind is alu else "hbm", "kernel": "k_" + dom,
+    roof = {"bound": "alu" if bind is alu else "hbm", "kernel": "k_" + kname,
             "achieved": bind["achieved"], "peak": bind["peak"], "unit": bind["unit"],
             "frac": bind["frac"], "traffic": traffic,
             "algorithmic_bytes_per_launch": int(model[dom]), "avg_launch_ms": round(t_dom, 5),

@@ -186,6 +186,7 @@ typedef struct {
   int64_t replaced[2];   /* parent slots replaced, summed over all generations */
   double feasible_frac;  /* share of population 1 with CV = 0 */
   size_t device_bytes;   /* device memory held by the handle */
+  int32_t task_dealt;    /* variation kernel: 1 task-dealt (rows of d <= 128), 0 lane groups */
 } gmpea_info;
 
 /* Create an instance: build the reference vectors W (Das-Dennis lattice), the

@@ -894,6 +894,7 @@ gmpea_status gmpea_get_info(gmpea_t h, gmpea_info *info) {
   for (int32_t i = 0; i < st.n; ++i) feas += fc[static_cast<size_t>(i) * st.rq + st.rq - 1].w == 0.0f;
   info->feasible_frac = static_cast<double>(feas) / st.n;
   info->device_bytes = h->bytes;
+  info->task_dealt = h->st.tasked;
   return GMPEA_OK;
 }
 
