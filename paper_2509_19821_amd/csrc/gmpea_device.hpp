@@ -842,9 +842,9 @@ __device__ __forceinline__ void wave_copy_home(const DevState &st, bool copy, ui
 // decision uses generation-k parents, and replacements land after all reads of
 // the slot they overwrite.
 // A group of lps lanes decides one slot (lps = t_p / sel_per_lane rounded up to
-// a power of two, at most 64). When t_p is a multiple of sel_per_lane, lane g
-// takes entries K g .. K g + K - 1 of the slot's padded list head (K =
-// sel_per_lane, 16-byte index loads), else entries g, g + lps, ... four at a
+// a power of two, at most 64). When t_p = K lps (K = sel_per_lane), lane g
+// takes entries K g .. K g + K - 1 of the slot's padded list head (16-byte
+// index loads), else entries g, g + lps, ... (every lane busy), up to K at a
 // time, with independent loads (index, then candidate F/CV), then its share of the tail
 // (lists longer than t_p), and keeps its lexicographic minimum of (CV, g,
 // index). No load waits on another beyond index -> candidate: the head needs no
@@ -938,16 +938,8 @@ __device__ __forceinline__ void select_body(const DevState &st, int L) {
     const int32_t *head = st.rhead[p] + static_cast<size_t>(j) * t;
     const int32_t ta = st.rtoff[p][j], tb = st.rtoff[p][j + 1];
     const float4 *cand = st.FCN[p];
-    auto take4 = [&](const int (&ii)[4]) {  // four independent candidate loads, then the keys
-      Rec<M> cc[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) cc[u] = ii[u] >= 0 ? rec_load<M>(cand, ii[u]) : rec_zero<M>();
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-        if (ii[u] >= 0) consider(ii[u], cc[u]);
-    };
     constexpr int K = sel_per_lane(Rec<M>::Q);
-    if ((t & (K - 1)) == 0) {
+    if (t == K * lps) {
       // lane g takes entries K g .. K g + K - 1 (16-byte loads; head rows are
       // 16-byte aligned when t is a multiple of 4), all K candidate loads in
       // flight together; the minimum does not depend on how the entries are
@@ -970,14 +962,21 @@ __device__ __forceinline__ void select_body(const DevState &st, int L) {
           if (ii[u] >= 0) consider(ii[u], cc[u]);
       }
     } else {
-      for (int q0 = g; q0 < t; q0 += 4 * lps) {  // one pass unless t > 4 lps = 256
-        int ii[4];
+      // entries g, g + lps, ...: every lane of the group busy whatever t is
+      // (one pass unless t > K lps), up to K candidate loads in flight
+      for (int q0 = g; q0 < t; q0 += K * lps) {
+        int ii[K];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < K; ++u) {
           const int q = q0 + u * lps;
           ii[u] = q < t ? head[q] : -1;
         }
-        take4(ii);
+        Rec<M> cc[K];
+#pragma unroll
+        for (int u = 0; u < K; ++u) cc[u] = ii[u] >= 0 ? rec_load<M>(cand, ii[u]) : rec_zero<M>();
+#pragma unroll
+        for (int u = 0; u < K; ++u)
+          if (ii[u] >= 0) consider(ii[u], cc[u]);
       }
     }
     for (int q = ta + g; q < tb; q += lps) {
