@@ -187,6 +187,7 @@ typedef struct {
   double feasible_frac;  /* share of population 1 with CV = 0 */
   size_t device_bytes;   /* device memory held by the handle */
   int32_t task_dealt;    /* variation kernel: 1 task-dealt (rows of d <= 128), 0 lane groups */
+  int64_t checked_generations; /* generations whose write sets were verified (GMPEA_CHECK_WRITES=1) */
 } gmpea_info;
 
 /* Create an instance: build the reference vectors W (Das-Dennis lattice), the

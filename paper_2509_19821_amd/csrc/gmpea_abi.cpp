@@ -58,6 +58,8 @@ struct gmpea_s {
   double *q_part = nullptr;
   float *q_box = nullptr;                // lo[kMaxM], hi[kMaxM]
   unsigned long long *q_hits = nullptr;
+  // write-set check (GMPEA_CHECK_WRITES=1 at init): generations verified so far
+  int64_t checked = 0;
   // graph replay of `gchunk` generations
   hipGraphExec_t gexec = nullptr;
   int32_t gchunk = 0;
@@ -228,7 +230,48 @@ gmpea_status build_graph(gmpea_s *h, int32_t chunk) {
   return GMPEA_OK;
 }
 
+// The write-set check of one generation: each offspring row got every chunk
+// written once and each offspring record once; each parent slot got at most one
+// of a replacement (its record and location) or a move of its kept row home
+// (location and every chunk), and nothing else was written.
+gmpea_status check_write_sets(gmpea_s *h) {
+  const DevState &st = h->st;
+  const int64_t n = st.n;
+  std::vector<int32_t> c(static_cast<size_t>(8 * n));
+  hipError_t e = hipMemcpyAsync(c.data(), st.wcheck, c.size() * sizeof(int32_t), hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(st.wcheck, 0, c.size() * sizeof(int32_t), h->stream);
+  if (e != hipSuccess) return hip_fail(e, "write-set check");
+  auto at = [&](int kind, int p, int64_t j) { return c[static_cast<size_t>((2 * kind + p) * n + j)]; };
+  for (int p = 0; p < 2; ++p)
+    for (int64_t j = 0; j < n; ++j) {
+      const int32_t vr = at(0, p, j), op = at(1, p, j), rp = at(2, p, j), mv = at(3, p, j);
+      const char *what = nullptr;
+      if (vr != st.nq) what = "offspring row chunks";
+      else if (op != 1) what = "offspring record";
+      else if (rp > 1) what = "slot replacement";
+      else if (mv != 0 && mv != 1 + st.nq) what = "kept row moved home";
+      else if (rp == 1 && mv != 0) what = "slot both replaced and moved";
+      if (what)
+        return fail(GMPEA_ESTATE, "write-set check failed after generation " + std::to_string(h->checked + 1) +
+                                      ": " + what + ", population " + std::to_string(p) + ", index " +
+                                      std::to_string(j) + " (counts " + std::to_string(vr) + " " +
+                                      std::to_string(op) + " " + std::to_string(rp) + " " + std::to_string(mv) + ")");
+    }
+  ++h->checked;
+  return GMPEA_OK;
+}
+
 gmpea_status enqueue(gmpea_s *h, int32_t n) {
+  if (h->st.wcheck) {  // one generation at a time, each verified
+    for (int32_t g = 0; g < n; ++g) {
+      hipError_t e = launch_generation(h->st, h->stream);
+      if (e != hipSuccess) return hip_fail(e, "generation launch");
+      gmpea_status s = check_write_sets(h);
+      if (s != GMPEA_OK) return s;
+    }
+    return GMPEA_OK;
+  }
   const int32_t G = h->graph_chunk_cfg;
   if (n == 0 && G >= 2) return build_graph(h, G);  // prepare the replay, launch nothing
   if (G >= 2 && n >= G) {
@@ -508,6 +551,10 @@ gmpea_status gmpea_init(const gmpea_problem *P, const gmpea_config *C, const gmp
     const int64_t rows_pad = int64_t((N + kBlock - 1) / kBlock) * kBlock;
     st.npar = static_cast<int32_t>(std::max<int64_t>(2, std::min<int64_t>(st.npar, ((int64_t(1) << 32) / rows_pad - 2) / 2)));
   }
+  // the write-set check: every write of a generation counted per target and
+  // verified on the host after the generation (one generation per launch set)
+  const char *cw = std::getenv("GMPEA_CHECK_WRITES");
+  const bool check_writes = cw && std::atoi(cw) == 1;
   st.rq = rec_quads(m);
   st.nblk = (N + kBlock - 1) / kBlock;
   st.t[0] = t1;
@@ -584,6 +631,7 @@ gmpea_status gmpea_init(const gmpea_problem *P, const gmpea_config *C, const gmp
     // reverse-list tails with room for an eighth of the entries (lattice
     // neighbourhoods put well under 1 % there); a larger tail is rebuilt exactly
     for (int p = 0; p < 2; ++p) st.rtail[p] = c.take<int32_t>(tail_cap[p]);
+    st.wcheck = check_writes ? c.take<int32_t>(8 * static_cast<size_t>(N)) : nullptr;
     // delivery scratch (gmpea_front, gmpea_quality)
     h->f_keep = c.take<uint8_t>(static_cast<size_t>(N));
     h->f_idx = c.take<int32_t>(static_cast<size_t>(N));
@@ -645,6 +693,7 @@ gmpea_status gmpea_init(const gmpea_problem *P, const gmpea_config *C, const gmp
   zero(st.zkey, 0xFF, kMaxM * sizeof(uint32_t));
   zero(st.gen, 0, 4 * sizeof(uint32_t));
   zero(st.repl, 0, 2 * kReplLanes * sizeof(unsigned long long));
+  if (st.wcheck) zero(st.wcheck, 0, 8 * static_cast<size_t>(N) * sizeof(int32_t));
   // reference vectors and neighbourhoods: on the device for one Das-Dennis layer
   // with m <= 3, else on the host (W rounded once from FP64, rq float4 per row)
   if (dev_tables) {
@@ -895,6 +944,7 @@ gmpea_status gmpea_get_info(gmpea_t h, gmpea_info *info) {
   info->feasible_frac = static_cast<double>(feas) / st.n;
   info->device_bytes = h->bytes;
   info->task_dealt = h->st.tasked;
+  info->checked_generations = h->checked;
   return GMPEA_OK;
 }
 
@@ -1179,6 +1229,13 @@ gmpea_status gmpea_profile(gmpea_t h, int32_t n_gen, float *ms) {
   if (e == hipSuccess) e = hipEventElapsedTime(&rep, ev[0], ev[1]);
   for (int q = 0; q < made; ++q) (void)hipEventDestroy(ev[q]);
   if (e != hipSuccess) return hip_fail(e, "gmpea_profile");
+  // profiled generations (and the repeated variation) are not verified: the
+  // write-set counts start again from zero
+  if (h->st.wcheck) {
+    e = hipMemsetAsync(h->st.wcheck, 0, 8 * static_cast<size_t>(h->st.n) * sizeof(int32_t), h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(e, "gmpea_profile");
+  }
   for (int ph = 0; ph < kPhases; ++ph) ms[ph] = static_cast<float>(acc[ph] / n_gen);
   ms[kPhases] = rep / static_cast<float>(n_gen);
   return GMPEA_OK;
@@ -1668,6 +1725,7 @@ gmpea_status gmpea_pool_admit(gmpea_pool_t q, const gmpea_problem *P, const gmpe
   if (s != GMPEA_OK) return s;
   h->stream = q->stream;  // every later operation runs in order with the pool's generations
   h->st.task_off = kTaskOff;  // batched launches fill the chip (same results, see task_off_for)
+  h->st.wcheck = nullptr;     // the write-set check verifies plain generations only
   int32_t k = 0;
   while (k < static_cast<int32_t>(q->slots.size()) && q->slots[k]) ++k;
   if (k == static_cast<int32_t>(q->slots.size())) q->slots.push_back(nullptr);

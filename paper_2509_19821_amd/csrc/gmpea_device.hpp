@@ -458,6 +458,7 @@ __device__ __forceinline__ void vary_body(const DevState &st, int L, int G) {
       if (l0 + 3 >= st.d) o.w = 0.0f;
       eval_chunk<M, FAM>(e, q, o, st.d, slot);
       ro[q] = o;
+      note_write(st, 0, p, i);
     }
   }
   // the sums over the group's chunks (and the leading variables) -> F, CV, z
@@ -625,6 +626,7 @@ __device__ __forceinline__ void tvary_body(const DevState &st, int L, int G) {
       if (l0 + 3 >= st.d) ov.w = 0.0f;
       reinterpret_cast<float4 *>(st.rows + static_cast<size_t>(offspring_row(st, gen_slot(st, k), p, i)) *
                                                st.stride)[q] = ov;
+      note_write(st, 0, p, i);
       s_part[wv][o * nq + q] = chunk_partial<M, FAM>(q, ov, st.d);
       if constexpr (kWide) {
         if (q < kLead) lds.lead[wv][o][q] = ov;
@@ -771,6 +773,8 @@ __device__ __forceinline__ void op1_body(const DevState &st, int b) {
   n2.v[kCv] = s2 ? -fabsf(n2.v[kCv]) : fabsf(n2.v[kCv]);
   rec_store<M>(st.FCN[0], i, n1);
   rec_store<M>(st.FCN[1], i, n2);
+  note_write(st, 1, 0, i);
+  note_write(st, 1, 1, i);
   st.src[i] = static_cast<uint8_t>((s1 ? 1u : 0u) | (s2 ? 2u : 0u));
 }
 
@@ -817,7 +821,14 @@ __device__ __forceinline__ void wave_copy_home(const DevState &st, bool copy, ui
     }
   };
   auto put = [&](const float4 &v, int64_t o) {
-    if (o >= 0) *reinterpret_cast<float4 *>(st.rows + o) = v;
+    if (o >= 0) {
+      *reinterpret_cast<float4 *>(st.rows + o) = v;
+      if (st.wcheck) {  // the home row's slot: row / stride = p region + j
+        const int64_t h = o / st.stride;
+        const int hp = h >= st.region ? 1 : 0;
+        note_write(st, 3, hp, static_cast<int>(h - hp * st.region));
+      }
+    }
   };
   for (int t0 = lane; t0 < tasks; t0 += 4 * 64) {
     float4 v0, v1, v2, v3;
@@ -1001,6 +1012,7 @@ __device__ __forceinline__ void select_body(const DevState &st, int L) {
         from = l;
         home = static_cast<uint32_t>(p * st.region + j);
         st.loc[p][j] = home;
+        note_write(st, 3, p, j);
       }
     }
     // the lane that holds the winner (m <= 3), the group's first lane (m > 3):
@@ -1013,6 +1025,7 @@ __device__ __forceinline__ void select_body(const DevState &st, int L) {
       }
       rec_store<M>(st.FC[p], j, bestf);
       st.loc[p][j] = offspring_row(st, gen_slot(st, k), p ^ (best.i & 1), bi);
+      note_write(st, 2, p, j);
       atomicAdd(&s_cnt, 1);
     }
   }

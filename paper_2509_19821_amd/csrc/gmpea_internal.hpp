@@ -71,6 +71,12 @@ struct DevState {
   float *rows;               // the row arena (2 + 2 npar regions)
   int64_t region;            // rows per region (nblk kBlock)
   int32_t npar;              // generations whose offspring rows stay in the arena
+  // Write-set check (GMPEA_CHECK_WRITES=1 at init; null otherwise): per
+  // generation, counts of the writes each target received, 4 arrays of 2 n
+  // (population-major): offspring-row chunk writes (variation), offspring
+  // record writes (OP1), slot records and locations written for a replacement,
+  // and chunk copies of a kept row home plus its location (selection).
+  int32_t *wcheck;
   float *X[2];               // home rows: regions 0 and 1
   uint32_t *loc[2];          // arena row of slot j's current decision vector
   float4 *FC[2], *FCO[2], *FCN[2];
@@ -138,6 +144,10 @@ __host__ __device__ inline int vary_lanes_of(const DevState &st) {
 // next generation's offspring moves it home then; with npar slots that is a
 // slot replaced npar - 1 generations ago and kept since.
 constexpr int kOffspringGenerations = 8;
+// One write recorded by the write-set check (a no-op unless it is on).
+__device__ __forceinline__ void note_write(const DevState &st, int kind, int p, int j) {
+  if (st.wcheck) atomicAdd(&st.wcheck[(2 * static_cast<int64_t>(kind) + p) * st.n + j], 1);
+}
 __host__ __device__ inline uint32_t gen_slot(const DevState &st, uint32_t k) {
   return k % static_cast<uint32_t>(st.npar);
 }

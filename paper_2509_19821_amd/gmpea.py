@@ -81,7 +81,8 @@ class Info(ctypes.Structure):
                 ("t1", ctypes.c_int32), ("t2", ctypes.c_int32), ("H", ctypes.c_int32),
                 ("H2", ctypes.c_int32), ("generation", ctypes.c_int64), ("z", ctypes.c_float * MAX_M),
                 ("replaced", ctypes.c_int64 * 2), ("feasible_frac", ctypes.c_double),
-                ("device_bytes", ctypes.c_size_t), ("task_dealt", ctypes.c_int32)]
+                ("device_bytes", ctypes.c_size_t), ("task_dealt", ctypes.c_int32),
+                ("checked_generations", ctypes.c_int64)]
 
 
 _lib = None
@@ -342,7 +343,7 @@ class Gmpea:
                 "generation": int(inf.generation), "z": np.array(inf.z[:inf.m], dtype=np.float32),
                 "replaced": (int(inf.replaced[0]), int(inf.replaced[1])),
                 "feasible_frac": float(inf.feasible_frac), "device_bytes": int(inf.device_bytes),
-                "task_dealt": bool(inf.task_dealt)}
+                "task_dealt": bool(inf.task_dealt), "checked_generations": int(inf.checked_generations)}
 
     def _shape(self, name: str, pop: int):
         n, m, d = self.n, self.m, self.d
