@@ -925,22 +925,24 @@ __device__ __forceinline__ void select_body(const DevState &st, int L) {
   // winner's row follows without another load
   constexpr int kCv = Rec<M>::kCv;
   SelKey best{__builtin_huge_valf(), __builtin_huge_valf(), 0x7FFFFFFF};
-  Rec<M> bestf = rec_zero<M>();  // F/CV of this lane's best candidate
   Rec<M> w = rec_zero<M>(), par = rec_zero<M>();
   float z[M];
   load_z<M>(st.zkey, z);
-  // m <= 3: the lane keeps its best candidate's record in registers and writes
-  // it if it wins; m > 3: only the key, and the winner's record is read again
-  // (records of two or three float4 would cost a select per float per candidate)
+  // Each lane keeps only its best key; the winner's record is read again after
+  // the group minimum. A candidate is taken without branches: an index < 0 (the
+  // padding after a list's end, its record read from row 0) keys as
+  // (+inf, +inf, INT_MAX) and never wins, and the lexicographic compare and
+  // the update are compares and selects.
   auto consider = [&](int32_t i, Rec<M> c) {
+    const bool ok = i >= 0;
     const uint32_t bit = __float_as_uint(c.v[kCv]) >> 31;  // set: the other population's offspring
-    c.v[kCv] = fabsf(c.v[kCv]);
-    const SelKey k{(p == 0) ? nan_inf(c.v[kCv]) : 0.0f, aggregate<M>(c, w, z, st.agg, st.theta),
-                   static_cast<int>((static_cast<uint32_t>(i) << 1) | bit)};
-    if (sel_less(k, best)) {
-      best = k;
-      if constexpr (M <= 3) bestf = c;
-    }
+    const float kc = ok ? ((p == 0) ? nan_inf(fabsf(c.v[kCv])) : 0.0f) : __builtin_huge_valf();
+    const float kg = ok ? aggregate<M>(c, w, z, st.agg, st.theta) : __builtin_huge_valf();
+    const int ki = ok ? static_cast<int>((static_cast<uint32_t>(i) << 1) | bit) : 0x7FFFFFFF;
+    const bool lt = (kc < best.c) | ((kc == best.c) & ((kg < best.g) | ((kg == best.g) & (ki < best.i))));
+    best.c = lt ? kc : best.c;
+    best.g = lt ? kg : best.g;
+    best.i = lt ? ki : best.i;
   };
   if (live) {
     const int t = st.t[p];
@@ -967,10 +969,9 @@ __device__ __forceinline__ void select_body(const DevState &st, int L) {
         }
         Rec<M> cc[K];
 #pragma unroll
-        for (int u = 0; u < K; ++u) cc[u] = ii[u] >= 0 ? rec_load<M>(cand, ii[u]) : rec_zero<M>();
+        for (int u = 0; u < K; ++u) cc[u] = rec_load<M>(cand, max(ii[u], 0));
 #pragma unroll
-        for (int u = 0; u < K; ++u)
-          if (ii[u] >= 0) consider(ii[u], cc[u]);
+        for (int u = 0; u < K; ++u) consider(ii[u], cc[u]);
       }
     } else {
       // entries g, g + lps, ...: every lane of the group busy whatever t is
@@ -980,14 +981,14 @@ __device__ __forceinline__ void select_body(const DevState &st, int L) {
 #pragma unroll
         for (int u = 0; u < K; ++u) {
           const int q = q0 + u * lps;
-          ii[u] = q < t ? head[q] : -1;
+          const int v = head[min(q, t - 1)];
+          ii[u] = q < t ? v : -1;
         }
         Rec<M> cc[K];
 #pragma unroll
-        for (int u = 0; u < K; ++u) cc[u] = ii[u] >= 0 ? rec_load<M>(cand, ii[u]) : rec_zero<M>();
+        for (int u = 0; u < K; ++u) cc[u] = rec_load<M>(cand, max(ii[u], 0));
 #pragma unroll
-        for (int u = 0; u < K; ++u)
-          if (ii[u] >= 0) consider(ii[u], cc[u]);
+        for (int u = 0; u < K; ++u) consider(ii[u], cc[u]);
       }
     }
     for (int q = ta + g; q < tb; q += lps) {
@@ -995,7 +996,6 @@ __device__ __forceinline__ void select_body(const DevState &st, int L) {
       consider(i, rec_load<M>(cand, i));
     }
   }
-  const SelKey mine = best;
   sel_group_min(best, lps);
   if (live) {
     const float pc = (p == 0) ? nan_inf(par.v[kCv]) : 0.0f;
@@ -1015,14 +1015,12 @@ __device__ __forceinline__ void select_body(const DevState &st, int L) {
         note_write(st, 3, p, j);
       }
     }
-    // the lane that holds the winner (m <= 3), the group's first lane (m > 3):
-    // the slot takes the winner's F/CV and points at its offspring row
-    if (win && (M <= 3 ? mine.i == best.i : g == 0)) {
+    // the group's first lane: the slot takes the winner's F/CV and points at
+    // its offspring row
+    if (win && g == 0) {
       if (st.win[p]) st.win[p][j] = bi;
-      if constexpr (M > 3) {
-        bestf = rec_load<M>(st.FCN[p], bi);
-        bestf.v[kCv] = fabsf(bestf.v[kCv]);
-      }
+      Rec<M> bestf = rec_load<M>(st.FCN[p], bi);
+      bestf.v[kCv] = fabsf(bestf.v[kCv]);
       rec_store<M>(st.FC[p], j, bestf);
       st.loc[p][j] = offspring_row(st, gen_slot(st, k), p ^ (best.i & 1), bi);
       note_write(st, 2, p, j);
