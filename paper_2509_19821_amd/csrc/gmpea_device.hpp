@@ -1034,8 +1034,13 @@ __device__ __forceinline__ void select_body(const DevState &st, int L) {
 }
 
 
+// m <= 3: eight waves per SIMD (at most 64 VGPRs; one float4, stored before
+// the candidate loop and read after it, goes to scratch): 168-180 against
+// 180-192 us at N = 1e6, 24-26
+// against 25-27 us at N = 1e5. The batched kernel, which holds both m, lost
+// with the same bound (1.36 against 1.28 ms per pool generation).
 template <int M>
-__global__ __launch_bounds__(kBlock) void k_select(DevState st) {
+__global__ __launch_bounds__(kBlock, (M <= 3 ? 8 : 1)) void k_select(DevState st) {
   select_body<M>(st, xcd_tile(blockIdx.x, gridDim.x));
 }
 
