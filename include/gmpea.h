@@ -80,7 +80,10 @@ enum {
  *   F      N x m  float   objectives
  *   CV     N      float   total constraint violation (Eq. (3))
  *   XOFF, FOFF, CVOFF     the last generation's offspring of population `pop`
- *                         (before OP1), same layouts; read only
+ *                         (before OP1), same layouts; read only. Defined once
+ *                         this handle has run a generation (zeros before the
+ *                         first; after a write of GEN, until the next one, the
+ *                         offspring rows are unspecified)
  *   Z      m      float   ideal point (shared by both populations); pop ignored
  *   GEN    1      int64   generations completed; pop ignored
  *   W      N x m  float   reference vectors, the raw weights (read only; pop ignored)

@@ -677,7 +677,10 @@ gmpea_status gmpea_init(const gmpea_problem *P, const gmpea_config *C, const gmp
   if (noffs > 0) cp(d_offs, offs.data(), offs.size() * sizeof(int32_t));
   zero(d_flag, 0, 4 * sizeof(uint32_t));
   st.region = static_cast<int64_t>(rows);
-  zero(st.rows, 0, (2 + 2 * static_cast<size_t>(st.npar)) * rows * st.stride * sizeof(float));
+  // the home rows and the first generation slot's offspring rows (what a read
+  // of X or of the offspring returns before any generation); every other
+  // offspring row is written whole (padding included) before it is read
+  zero(st.rows, 0, 4 * rows * st.stride * sizeof(float));
   for (int p = 0; p < 2; ++p) {
     zero(st.FC[p], 0, rows * st.rq * sizeof(float4));
     zero(st.FCO[p], 0, rows * st.rq * sizeof(float4));
