@@ -541,15 +541,16 @@ gmpea_status gmpea_init(const gmpea_problem *P, const gmpea_config *C, const gmp
     // rounding order, so runs to be compared bitwise must agree on it)
     const char *tk = std::getenv("GMPEA_TASKED");
     st.tasked = (st.nq <= kTaskChunks && !(tk && std::atoi(tk) == 0)) ? 1 : 0;
-    st.task_off = task_off_for(N);
+    st.task_off = task_off_for(N, st.nq, m > 3, false);
     // offspring generations kept in the arena (GMPEA_OFFSPRING_GENERATIONS, 2 to
     // 16, is a layout experiment knob; results do not depend on it)
     st.npar = kOffspringGenerations;
     if (const char *a = std::getenv("GMPEA_OFFSPRING_GENERATIONS"))
       st.npar = std::min(16, std::max(2, std::atoi(a)));
-    // arena rows are 32-bit indices: fewer generations for the largest populations
+    // arena rows are 31-bit indices (the variation keeps a flag in bit 31):
+    // fewer generations for the largest populations
     const int64_t rows_pad = int64_t((N + kBlock - 1) / kBlock) * kBlock;
-    st.npar = static_cast<int32_t>(std::max<int64_t>(2, std::min<int64_t>(st.npar, ((int64_t(1) << 32) / rows_pad - 2) / 2)));
+    st.npar = static_cast<int32_t>(std::max<int64_t>(2, std::min<int64_t>(st.npar, ((int64_t(1) << 31) / rows_pad - 2) / 2)));
   }
   // the write-set check: every write of a generation counted per target and
   // verified on the host after the generation (one generation per launch set)
@@ -1727,7 +1728,7 @@ gmpea_status gmpea_pool_admit(gmpea_pool_t q, const gmpea_problem *P, const gmpe
     return fail(GMPEA_ENOMEM, "gmpea_pool_admit: the instance does not fit the pool's budget");
   if (s != GMPEA_OK) return s;
   h->stream = q->stream;  // every later operation runs in order with the pool's generations
-  h->st.task_off = kTaskOff;  // batched launches fill the chip (same results, see task_off_for)
+  h->st.task_off = task_off_for(h->st.n, h->st.nq, h->st.m > 3, true);  // same results, see task_off_for
   h->st.wcheck = nullptr;     // the write-set check verifies plain generations only
   int32_t k = 0;
   while (k < static_cast<int32_t>(q->slots.size()) && q->slots[k]) ++k;

@@ -481,8 +481,9 @@ __global__ __launch_bounds__(kBlock) void k_vary(DevState st) {
 // leaves its chunk's evaluation partial in LDS; lane o then adds its
 // offspring's partials in chunk order and finishes F, CV and the ideal point,
 // so the results do not depend on off. The draws and the variation of every
-// variable are those of vary_body. At most kTaskOff = 32 offspring per wave keep
-// the LDS per wave near 5 KB, so LDS allows eight waves per SIMD.
+// variable are those of vary_body. A wave's LDS (its offspring's sources, then
+// kTaskPart floats of partials and leading variables) is about 5 KB, so LDS
+// allows eight waves per SIMD.
 // ----------------------------------------------------------------------------
 // Evaluation partial of chunk q (variables 4q .. 4q + 3 below d, in order).
 template <int M, int FAM>
@@ -518,14 +519,16 @@ __device__ __forceinline__ Rec<M> eval_partials(const float *part, int nq, float
 
 // LDS of tvary_body, one buffer per kernel whatever the template instances a
 // batched kernel holds (a non-template function's shared array; m <= 3 and
-// m > 3 never share a kernel): per wave, the kTaskOff offspring's sources, their
-// chunk partials (offspring-major) and their leading variables (x1, x2 for
-// m <= 3; the first two chunks for m > 3).
+// m > 3 never share a kernel): per wave, the offspring's sources (parent rows
+// a and b, the crossing draw in a's bit 31, b < 0 for no offspring), then the
+// chunk partials (offspring-major, off nq floats) followed, for m <= 3, by each
+// offspring's x1 and x2; for m > 3 the first two chunks of each offspring.
 template <bool W>
 struct TvaryLds {
-  int4 src[kBlock / 64][kTaskOff];  // parent rows a, b; own row; index | cross << 30 (-1: none)
-  float part[kBlock / 64][kTaskOff * kTaskChunks];
-  typename std::conditional<W, float4[kBlock / 64][kTaskOff][2], float2[kBlock / 64][kTaskOff]>::type lead;
+  static constexpr int kOff = W ? kTaskOffWide : kTaskOffNarrow;
+  int2 src[kBlock / 64][kOff];
+  float part[kBlock / 64][kTaskPart];
+  typename std::conditional<W, float4[kBlock / 64][kOff][2], char[1]>::type lead;
 };
 __device__ __forceinline__ TvaryLds<false> &tvary_lds_narrow() {
   __shared__ TvaryLds<false> lds;
@@ -558,7 +561,7 @@ __device__ __forceinline__ void tvary_body(const DevState &st, int L, int G) {
   // ---- lane o: offspring base + o -- mating picks and parent rows ----
   if (lane < off) {
     const int i = base + lane;
-    int4 src = make_int4(0, 0, 0, -1);
+    int2 src = make_int2(0, -1);
     if (i < n) {
       const int t = st.t[p];
       const uint4 w = philox10(make_uint4(0u, i, k, (kTagMate << 24) | tagp), st.key0, st.key1);
@@ -575,9 +578,7 @@ __device__ __forceinline__ void tvary_body(const DevState &st, int L, int G) {
         st.mate[p][2 * i + 1] = pb;
       }
       const bool cross = static_cast<uint64_t>(w.z) < st.tpc;
-      src = make_int4(static_cast<int>(st.loc[p][pa]), static_cast<int>(st.loc[p][pb]),
-                      st.op == 1 ? static_cast<int>(st.loc[p][i]) : 0,
-                      i | (cross ? (1 << 30) : 0));
+      src = make_int2(static_cast<int>(st.loc[p][pa] | (cross ? 0x80000000u : 0u)), static_cast<int>(st.loc[p][pb]));
     }
     s_src[wv][lane] = src;
   }
@@ -593,12 +594,12 @@ __device__ __forceinline__ void tvary_body(const DevState &st, int L, int G) {
   const int dq = 64 % nq, dof = 64 / nq;
   int o = lane / nq, q = lane - (lane / nq) * nq;
   for (int step = 0; step < steps; ++step) {
-    const int4 src = o < off ? s_src[wv][o] : make_int4(0, 0, 0, -1);
-    if (src.w >= 0) {
-      const int i = src.w & 0x3FFFFFFF;
-      const bool cross = (src.w >> 30) != 0;
+    const int2 src = o < off ? s_src[wv][o] : make_int2(0, -1);
+    if (src.y >= 0) {
+      const int i = base + o;
+      const bool cross = src.x < 0;
       const int l0 = q << 2;
-      const float4 va = arena_row(st, static_cast<uint32_t>(src.x))[q];
+      const float4 va = arena_row(st, static_cast<uint32_t>(src.x) & 0x7FFFFFFFu)[q];
       const float4 vb = arena_row(st, static_cast<uint32_t>(src.y))[q];
       const float4 lo = lb4[q], hi = ub4[q], is = is4[q];
       const uint4 r0 = philox10(make_uint4(2 * q, i, k, tagv), st.key0, st.key1);
@@ -606,7 +607,7 @@ __device__ __forceinline__ void tvary_body(const DevState &st, int L, int G) {
       if (l0 + 2 < st.d) r1w = philox10(make_uint4(2 * q + 1, i, k, tagv), st.key0, st.key1);
       float4 ov = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
       if (de) {
-        const float4 vx = arena_row(st, static_cast<uint32_t>(src.z))[q];
+        const float4 vx = arena_row(st, st.loc[p][i])[q];
         ov.x = de1(vx.x, va.x, vb.x, lo.x, hi.x, st);
         ov.y = de1(vx.y, va.y, vb.y, lo.y, hi.y, st);
         ov.z = de1(vx.z, va.z, vb.z, lo.z, hi.z, st);
@@ -630,8 +631,9 @@ __device__ __forceinline__ void tvary_body(const DevState &st, int L, int G) {
       s_part[wv][o * nq + q] = chunk_partial<M, FAM>(q, ov, st.d);
       if constexpr (kWide) {
         if (q < kLead) lds.lead[wv][o][q] = ov;
-      } else {
-        if (q == 0) lds.lead[wv][o] = make_float2(ov.x, ov.y);
+      } else if (q == 0) {
+        s_part[wv][off * nq + 2 * o] = ov.x;
+        s_part[wv][off * nq + 2 * o + 1] = ov.y;
       }
     }
     q += dq;
@@ -653,8 +655,7 @@ __device__ __forceinline__ void tvary_body(const DevState &st, int L, int G) {
       c0 = lds.lead[wv][lane][0];
       if (kLead > 1) c1 = lds.lead[wv][lane][kLead > 1 ? 1 : 0];
     } else {
-      const float2 x12 = lds.lead[wv][lane];
-      c0 = make_float4(x12.x, x12.y, 0.0f, 0.0f);
+      c0 = make_float4(s_part[wv][off * nq + 2 * lane], s_part[wv][off * nq + 2 * lane + 1], 0.0f, 0.0f);
     }
     const Rec<M> fc = eval_partials<M, FAM>(&s_part[wv][lane * nq], nq, c0, c1, st.prob);
     rec_store<M>(st.FCO[p], i, fc);

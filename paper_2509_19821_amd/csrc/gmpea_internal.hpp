@@ -61,7 +61,7 @@ struct DevState {
   int32_t n, m, d, stride, nblk;  // nblk: blocks of kBlock rows per population
   int32_t nq;                      // float4 chunks holding the d variables
   int32_t tasked;                  // variation kernel: 1 task-dealt, 0 lane groups
-  int32_t task_off;                // task-dealt kernel: offspring per wave (8, 16 or 32)
+  int32_t task_off;                // task-dealt kernel: offspring per wave (8 to 64)
   int32_t rq;                      // float4 per F/CV record and per W row
   int32_t t[2];
   int32_t lps[2];                  // lanes per slot in k_select (power of two <= 64)
@@ -111,7 +111,7 @@ struct DevState {
 // Variation kernels, fixed per instance (plain and batched launches must agree,
 // since the kernel fixes the evaluation's rounding order). Rows of at most
 // kTaskChunks chunks (d <= 128) take the task-dealt kernel (a wave builds
-// kTaskOff offspring, its lanes dealt consecutive (offspring, chunk) tasks):
+// task_off offspring, its lanes dealt consecutive (offspring, chunk) tasks):
 // every wave instruction moves about 1 KB of consecutive chunks, which keeps
 // the variation at the same cost whether the parents' rows are shared by many
 // slots (early generations, most slots replaced) or all distinct (later, most
@@ -120,16 +120,30 @@ struct DevState {
 // kernel, vary_lanes_of_chunks(nq) lanes per offspring: enough that each lane
 // keeps two to four float4 chunks, except the widest rows (d > 92), where four
 // lanes of six or seven chunks each measured faster than eight.
-// Offspring per wave of the task-dealt kernel: at most kTaskOff (the LDS is
-// sized for it). The count changes only how the tasks are dealt, never the
-// results (each offspring's partials are added in chunk order whatever the
-// dealing), so it follows the launch: a plain launch takes fewer offspring per
-// wave when the population gives the chip few waves (shorter dependency chains
-// per wave), a pool's batched launch takes kTaskOff for every instance (the
-// pool fills the chip; fewer lanes idle in the per-offspring parts).
+// Offspring per wave of the task-dealt kernel. A wave's LDS holds kTaskPart
+// floats: the off nq chunk partials and, for m <= 3, the two leading variables
+// of each offspring, so off (nq + 2) <= kTaskPart (m > 3 keeps its two leading
+// chunks apart, at most kTaskOffWide offspring). The count changes only how
+// the tasks are dealt, never the results (each offspring's partials are added
+// in chunk order whatever the dealing), so it follows the launch: the most that
+// fit (full lanes in the per-offspring parts and in every step when nq <= 14)
+// for a pool's batched launches and large plain populations, fewer for small
+// plain populations (shorter dependency chains per wave when the chip has few
+// waves).
 constexpr int kTaskChunks = 32;
-constexpr int kTaskOff = 32;
-__host__ __device__ inline int task_off_for(int n) { return n >= 65536 ? 32 : n >= 32768 ? 16 : 8; }
+constexpr int kTaskPart = 1024;
+constexpr int kTaskOffNarrow = 64, kTaskOffWide = 32;
+__host__ __device__ inline int task_off_fit(int nq, bool wide) {
+  int off = wide ? kTaskOffWide : kTaskOffNarrow;
+  while (off > 8 && off * (nq + (wide ? 0 : 2)) > kTaskPart) off >>= 1;
+  return off;
+}
+__host__ __device__ inline int task_off_for(int n, int nq, bool wide, bool pooled) {
+  const int fit = task_off_fit(nq, wide);
+  if (pooled) return fit;
+  const int cap = n >= 65536 ? 64 : n >= 32768 ? 16 : 8;
+  return fit < cap ? fit : cap;
+}
 __host__ __device__ inline int vary_lanes_of_chunks(int nq) {
   return nq >= 24 ? 4 : nq >= 16 ? 8 : nq >= 6 ? 4 : nq >= 3 ? 2 : 1;
 }
