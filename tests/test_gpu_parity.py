@@ -488,6 +488,23 @@ def test_generation_full_size_large(G):
         gp.close()
 
 
+def test_generation_large_population_short_rows(G):
+    """A plain population of 65,536 or more with rows of at most 56 variables:
+    the task-dealt variation builds 64 offspring per wave (the most its LDS
+    holds), which changes the dealing and not the results; one teacher-forced
+    generation at N = 65,703, d = 40, DE for population rows read in the task."""
+    prob = ci.make_problem(ci.FAMILY_SPHERE, 3, 40, 3, True, False, 21)
+    cfg = ci.method_config(65536, 20, 21, op=1)
+    gp, o = _pair(prob, cfg)
+    try:
+        assert gp.n >= 65536
+        gp.step(2)
+        frac = _teacher_forced(gp, o, 1, "N=%d d=40 DE" % gp.n)
+        assert frac < 0.005
+    finally:
+        gp.close()
+
+
 def test_front_matches_bruteforce(G):
     prob, cfg, K = ci.workload_medium(1)
     import paper_2509_19821_amd as g
