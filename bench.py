@@ -19,6 +19,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -68,13 +69,23 @@ def bytes_model(n, m, d, t, rho):
     return {"vary": vary, "op1": op1, "select": select}
 
 
+def _code_only(text):
+    """C++ source without comments and with runs of whitespace collapsed, so
+    that a change to comments alone keeps the hash (the sources hold no string
+    literal with comment markers)."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def kernel_hash():
-    """sha256[:16] over the kernel sources (device code, both instantiation
-    units, the shared declarations), in that order."""
+    """sha256[:16] over the code of the kernel sources (device code, both
+    instantiation units, the shared declarations, in that order), comments
+    left out."""
     h = hashlib.sha256()
     for path in KERNEL_SRC:
-        with open(path, "rb") as fh:
-            h.update(fh.read())
+        with open(path, encoding="utf-8") as fh:
+            h.update(_code_only(fh.read()).encode())
     return h.hexdigest()[:16]
 
 

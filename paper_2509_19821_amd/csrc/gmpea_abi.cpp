@@ -1060,7 +1060,7 @@ gmpea_status gmpea_read(gmpea_t h, int32_t buffer, int32_t pop, void *host, int6
         // current rows gathered home first (the values do not change)
         e = launch_materialize(st, h->stream);
       } else {
-        // the offspring of the last generation, in the regions of its parity
+        // the offspring of the last generation, in the regions of its slot
         uint32_t g = 0;
         gmpea_status s = d2h(h, &g, st.gen, 1, "gmpea_read");
         if (s != GMPEA_OK) return s;

@@ -785,9 +785,9 @@ __global__ __launch_bounds__(kBlock) void k_op1(DevState st) {
 }
 
 // ----------------------------------------------------------------------------
-// Kept rows moved home. A kept slot keeps its row, but a row in the other
-// parity's offspring regions would be overwritten by the next generation's
-// offspring: such a row is copied to the slot's home row (`from` -> `home`,
+// Kept rows moved home. A kept slot keeps its row, but a row in the offspring
+// regions the next generation writes (its generation slot, gen_slot) would be
+// overwritten: such a row is copied to the slot's home row (`from` -> `home`,
 // arena rows) by all lanes of the wave together. The wave's pending rows are
 // ranked, their (from, home) pairs staged in LDS, and the (row, chunk) copies
 // dealt to the lanes in order, four per lane at a time with the four loads
@@ -869,8 +869,8 @@ __device__ __forceinline__ void wave_copy_home(const DevState &st, bool copy, ui
 // the candidates were split among lanes.
 // The slot's location follows the decision in the same launch: a replaced slot
 // points at the winner's offspring row (written by this generation's
-// variation, parity k); a kept slot whose row lies in the other parity's
-// offspring regions has it moved home (wave_copy_home). Neither touches a row
+// variation, slot gen_slot(k)); a kept slot whose row lies in the offspring
+// regions of the next generation's slot has it moved home (wave_copy_home). Neither touches a row
 // or a record that another slot's decision reads.
 // ----------------------------------------------------------------------------
 struct SelKey {

@@ -49,9 +49,10 @@ __host__ __device__ constexpr int rec_quads(int m) { return m <= 3 ? 1 : (m + 4)
 
 // Device state of one instance. Decision vectors live in one row arena of
 // `stride` floats per row (a multiple of 4, at least 4 nq, so that every row
-// starts 16-byte aligned), in six regions of `region` rows: regions 0 and 1 are
-// the home rows of populations 1 and 2 (slot j at row j), region 2 + 2 par + q
-// holds the offspring of population q written by a generation of parity par.
+// starts 16-byte aligned), in 2 + 2 npar regions of `region` rows: regions 0
+// and 1 are the home rows of populations 1 and 2 (slot j at row j), region
+// 2 + 2 s + q holds the offspring of population q written by a generation in
+// slot s = gen_slot(k).
 // A slot's current decision vector is the arena row loc[p][j]: a replaced slot
 // points at its winning offspring row, so the replacement moves a 4-byte
 // location instead of a row. F and CV of one individual share a record of
