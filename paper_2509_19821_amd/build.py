@@ -14,6 +14,7 @@ OUT_DIR = os.path.join(PKG, "_build")
 LIB = os.path.join(OUT_DIR, "libgmpea.so")
 SOURCES = ["gmpea_kernels.hip", "gmpea_kernels_wide.hip", "gmpea_abi.cpp", "lattice.cpp"]
 ARCH = "gfx950"
+LIBS = ["-lpthread", "-lrocprofiler-sdk-roctx"]  # roctx: ranges over the ABI's calls
 
 
 def hipcc() -> str:
@@ -50,7 +51,7 @@ def build(verbose: bool = False, jobs: int = 3) -> str:
     for pr in procs:
         _wait(pr)
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc(), "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs + ["-lpthread"]
+    cmd = [hipcc(), "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs + LIBS
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

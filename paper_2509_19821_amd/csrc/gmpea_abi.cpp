@@ -12,6 +12,8 @@
 #include <unordered_set>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include <hip/hip_version.h>
 
 #include "gmpea.h"
@@ -20,6 +22,15 @@
 using namespace gmpea;
 
 namespace {
+
+// A roctx range over one call of the ABI, shown by rocprofv3 --marker-trace
+// (a no-op when no tool listens).
+struct Trace {
+  explicit Trace(const char *name) { roctxRangePushA(name); }
+  ~Trace() { roctxRangePop(); }
+  Trace(const Trace &) = delete;
+  Trace &operator=(const Trace &) = delete;
+};
 
 thread_local std::string g_err;
 
@@ -456,6 +467,7 @@ gmpea_status gmpea_sync(gmpea_t h) {
 
 gmpea_status gmpea_init(const gmpea_problem *P, const gmpea_config *C, const gmpea_allocator *A,
                         void *hip_stream, gmpea_t *out) {
+  Trace trace("gmpea_init");
   if (!out) return fail(GMPEA_EINVAL, "gmpea_init: out is NULL");
   gmpea_status s = validate(P, C);
   if (s != GMPEA_OK) return s;
@@ -831,12 +843,14 @@ gmpea_status gmpea_init(const gmpea_problem *P, const gmpea_config *C, const gmp
 }
 
 gmpea_status gmpea_step(gmpea_t h, int32_t n_gen) {
+  Trace trace("gmpea_step");
   if (!valid(h)) return fail(GMPEA_ESTATE, "gmpea_step: invalid handle");
   if (n_gen < 0) return fail(GMPEA_EINVAL, "gmpea_step: n_gen < 0");
   return enqueue(h, n_gen);
 }
 
 gmpea_status gmpea_run(gmpea_t h, int32_t max_gen, double time_limit_s, int32_t *gens_done) {
+  Trace trace("gmpea_run");
   if (!valid(h)) return fail(GMPEA_ESTATE, "gmpea_run: invalid handle");
   if (max_gen < 0) return fail(GMPEA_EINVAL, "gmpea_run: max_gen < 0");
   using clk = std::chrono::steady_clock;
@@ -872,6 +886,7 @@ gmpea_status gmpea_run(gmpea_t h, int32_t max_gen, double time_limit_s, int32_t 
 
 gmpea_status gmpea_front(gmpea_t h, int32_t what, int32_t capacity, float *x, float *f, float *cv,
                          int32_t *idx, int32_t *count) {
+  Trace trace("gmpea_front");
   if (!valid(h)) return fail(GMPEA_ESTATE, "gmpea_front: invalid handle");
   if (!count) return fail(GMPEA_EINVAL, "gmpea_front: count is NULL");
   if (what != GMPEA_FRONT_FEASIBLE_ND && what != GMPEA_FRONT_POP1 && what != GMPEA_FRONT_POP2)
@@ -882,6 +897,7 @@ gmpea_status gmpea_front(gmpea_t h, int32_t what, int32_t capacity, float *x, fl
 
 gmpea_status gmpea_front_static(gmpea_t h, int32_t what, int32_t capacity, float *x, float *f,
                                 float *cv, int32_t *idx, int32_t *count) {
+  Trace trace("gmpea_front_static");
   const char *who = "gmpea_front_static";
   if (!valid(h)) return fail(GMPEA_ESTATE, "gmpea_front_static: invalid handle");
   if (!count) return fail(GMPEA_EINVAL, "gmpea_front_static: count is NULL");
@@ -955,6 +971,7 @@ gmpea_status gmpea_get_info(gmpea_t h, gmpea_info *info) {
 gmpea_status gmpea_quality(gmpea_t h, const float *ref, int32_t n_ref, const float *hv_point,
                            int64_t hv_samples, uint64_t hv_seed, double *igd, double *hv,
                            int32_t *front_count) {
+  Trace trace("gmpea_quality");
   const char *who = "gmpea_quality";
   if (!valid(h)) return fail(GMPEA_ESTATE, "gmpea_quality: invalid handle");
   if (igd && (!ref || n_ref < 1)) return fail(GMPEA_EINVAL, "gmpea_quality: IGD needs ref and n_ref >= 1");
@@ -1044,6 +1061,7 @@ gmpea_status gmpea_shape(gmpea_t h, int32_t *n, int32_t *m, int32_t *d, int32_t 
 }
 
 gmpea_status gmpea_read(gmpea_t h, int32_t buffer, int32_t pop, void *host, int64_t count) {
+  Trace trace("gmpea_read");
   if (!valid(h)) return fail(GMPEA_ESTATE, "gmpea_read: invalid handle");
   if (!host) return fail(GMPEA_EINVAL, "gmpea_read: host is NULL");
   if (pop != 0 && pop != 1) return fail(GMPEA_EINVAL, "gmpea_read: pop must be 0 or 1");
@@ -1141,6 +1159,7 @@ gmpea_status gmpea_read(gmpea_t h, int32_t buffer, int32_t pop, void *host, int6
 }
 
 gmpea_status gmpea_write(gmpea_t h, int32_t buffer, int32_t pop, const void *host, int64_t count) {
+  Trace trace("gmpea_write");
   if (!valid(h)) return fail(GMPEA_ESTATE, "gmpea_write: invalid handle");
   if (!host) return fail(GMPEA_EINVAL, "gmpea_write: host is NULL");
   if (pop != 0 && pop != 1) return fail(GMPEA_EINVAL, "gmpea_write: pop must be 0 or 1");
@@ -1716,6 +1735,7 @@ gmpea_status gmpea_pool_create(size_t budget_bytes, const gmpea_allocator *A, vo
 
 gmpea_status gmpea_pool_admit(gmpea_pool_t q, const gmpea_problem *P, const gmpea_config *C,
                               int32_t *slot) {
+  Trace trace("gmpea_pool_admit");
   if (!pool_valid(q)) return fail(GMPEA_ESTATE, "gmpea_pool_admit: invalid pool");
   if (!slot) return fail(GMPEA_EINVAL, "gmpea_pool_admit: slot is NULL");
   gmpea_t h = nullptr;
@@ -1740,12 +1760,14 @@ gmpea_status gmpea_pool_admit(gmpea_pool_t q, const gmpea_problem *P, const gmpe
 }
 
 gmpea_status gmpea_pool_step(gmpea_pool_t q, int32_t n_gen) {
+  Trace trace("gmpea_pool_step");
   if (!pool_valid(q)) return fail(GMPEA_ESTATE, "gmpea_pool_step: invalid pool");
   if (n_gen < 0) return fail(GMPEA_EINVAL, "gmpea_pool_step: n_gen < 0");
   return pool_enqueue(q, n_gen);
 }
 
 gmpea_status gmpea_pool_tune(gmpea_pool_t q, int32_t n_gen, int32_t *gens_done) {
+  Trace trace("gmpea_pool_tune");
   if (!pool_valid(q)) return fail(GMPEA_ESTATE, "gmpea_pool_tune: invalid pool");
   if (n_gen < 0) return fail(GMPEA_EINVAL, "gmpea_pool_tune: n_gen < 0");
   // Each candidate (schedule, chunk) runs real generations, timed with events;
@@ -1810,6 +1832,7 @@ gmpea_status gmpea_pool_handle(gmpea_pool_t q, int32_t slot, gmpea_t *h) {
 }
 
 gmpea_status gmpea_pool_release(gmpea_pool_t q, int32_t slot) {
+  Trace trace("gmpea_pool_release");
   if (!pool_valid(q)) return fail(GMPEA_ESTATE, "gmpea_pool_release: invalid pool");
   if (slot < 0 || slot >= static_cast<int32_t>(q->slots.size()) || !q->slots[slot])
     return fail(GMPEA_EINVAL, "gmpea_pool_release: no such slot");

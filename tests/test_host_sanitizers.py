@@ -84,7 +84,7 @@ def san(tmp_path_factory):
         objs.append(obj)
     lib = str(libdir / "libgmpea.so")
     subprocess.run([libbuild.hipcc(), "--offload-arch=" + libbuild.ARCH, "-shared", "-fPIC", "-o", lib] + objs
-                   + ["-lpthread"] + SAN_HOST[:4], check=True, capture_output=True)
+                   + libbuild.LIBS + SAN_HOST[:4], check=True, capture_output=True)
     shutil.copy(os.path.join(libbuild.OUT_DIR, "build_info.json"), str(libdir))
     return {"dir": d, "oracle": orc, "lib": lib, "gcc_rt": _gcc_runtime(), "clang_rt": _clang_runtime()}
 
