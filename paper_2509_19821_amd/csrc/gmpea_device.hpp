@@ -792,15 +792,19 @@ __global__ __launch_bounds__(kBlock) void k_op1(DevState st) {
 // ranked, their (from, home) pairs staged in LDS, and the (row, chunk) copies
 // dealt to the lanes in order, four per lane at a time with the four loads
 // issued before the stores. No slot points at another slot's home row, so the
-// copies never overwrite a row that some location still names. Every thread of
-// the block must call it (a block barrier follows the staging).
+// copies never overwrite a row that some location still names. Every lane of
+// the wave must call it. A wave reads back only what its own lanes staged, and
+// one wave's LDS accesses complete in order, so a wave-level fence stands in
+// for a block barrier and the block's other waves run on.
 // ----------------------------------------------------------------------------
 __device__ __forceinline__ void wave_copy_home(const DevState &st, bool copy, uint32_t from, uint32_t home) {
   __shared__ uint2 s_cp[kBlock / 64][64];
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const uint64_t pending = __ballot(copy);
   if (copy) s_cp[wv][__popcll(pending & ((1ull << lane) - 1ull))] = make_uint2(from, home);
-  __syncthreads();
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   if (pending == 0) return;  // uniform over the wave
   const int np = __popcll(pending);
   const int nq = st.nq, tasks = np * nq;
@@ -912,21 +916,21 @@ __device__ __forceinline__ void sel_group_min(SelKey &best, int lps) {
 
 template <int M>
 __device__ __forceinline__ void select_body(const DevState &st, int L) {
-  __shared__ int s_cnt;
+  __shared__ int s_cnt[kBlock / 64];
   const int p = L >= st.sel_blocks0 ? 1 : 0;
   const int lps = st.lps[p];
   const int g = threadIdx.x & (lps - 1);
   const int j = (L - p * st.sel_blocks0) * (kBlock / lps) + threadIdx.x / lps;
-  if (threadIdx.x == 0) s_cnt = 0;
-  __syncthreads();
   const bool live = j < st.n;
   bool copy = false;  // a kept row this lane moves home (see wave_copy_home)
+  bool wrote = false;  // this lane replaced its group's slot
   uint32_t from = 0, home = 0;
   // keys carry i2 = 2 i + (OP1 source bit of i): the same order as i, and the
   // winner's row follows without another load
   constexpr int kCv = Rec<M>::kCv;
   SelKey best{__builtin_huge_valf(), __builtin_huge_valf(), 0x7FFFFFFF};
   Rec<M> w = rec_zero<M>(), par = rec_zero<M>();
+  uint32_t loc0 = 0;
   float z[M];
   load_z<M>(st.zkey, z);
   // Each lane keeps only its best key; the winner's record is read again after
@@ -949,6 +953,7 @@ __device__ __forceinline__ void select_body(const DevState &st, int L) {
     const int t = st.t[p];
     w = rec_load<M>(st.W, j);
     par = rec_load<M>(st.FC[p], j);
+    loc0 = st.loc[p][j];
     const int32_t *head = st.rhead[p] + static_cast<size_t>(j) * t;
     const int32_t ta = st.rtoff[p][j], tb = st.rtoff[p][j + 1];
     const float4 *cand = st.FCN[p];
@@ -1006,7 +1011,7 @@ __device__ __forceinline__ void select_body(const DevState &st, int L) {
     const uint32_t k = *st.gen;  // this generation (OP1 advanced the counter)
     if (!win && g == 0) {  // the parent stays, and its row too unless the next offspring overwrite it
       if (st.win[p]) st.win[p][j] = -1;
-      const uint32_t l = st.loc[p][j];
+      const uint32_t l = loc0;
       const uint32_t lo = offspring_row(st, gen_slot(st, k + 1u), 0, 0);
       if (l >= lo && l < lo + 2 * static_cast<uint32_t>(st.region)) {
         copy = true;
@@ -1025,13 +1030,20 @@ __device__ __forceinline__ void select_body(const DevState &st, int L) {
       rec_store<M>(st.FC[p], j, bestf);
       st.loc[p][j] = offspring_row(st, gen_slot(st, k), p ^ (best.i & 1), bi);
       note_write(st, 2, p, j);
-      atomicAdd(&s_cnt, 1);
+      wrote = true;
     }
   }
   wave_copy_home(st, copy, from, home);
+  // the block's replacements: one count per wave, one barrier, one atomic
+  const uint64_t wb = __ballot(wrote);
+  if ((threadIdx.x & 63) == 0) s_cnt[threadIdx.x >> 6] = __popcll(wb);
   __syncthreads();
-  if (threadIdx.x == 0 && s_cnt > 0)
-    atomicAdd(&st.repl[p * kReplLanes + (L & (kReplLanes - 1))], static_cast<unsigned long long>(s_cnt));
+  if (threadIdx.x == 0) {
+    int c = 0;
+#pragma unroll
+    for (int q = 0; q < kBlock / 64; ++q) c += s_cnt[q];
+    if (c > 0) atomicAdd(&st.repl[p * kReplLanes + (L & (kReplLanes - 1))], static_cast<unsigned long long>(c));
+  }
 }
 
 
