@@ -378,7 +378,9 @@ gmpea_status gmpea_pool_step(gmpea_pool_t pool, int32_t n_gen);
  * blocks grouped per XCD or in order) and the launch form (hipGraph replays of
  * 16 or 64 generations, or one launch per phase without a graph) by timing the
  * first generations; the choice stays for later steps. Results do not depend
- * on it. *gens_done (may be NULL) receives the generations run. Synchronises. */
+ * on it. The candidates run back to back and are waited for once; the
+ * generations after them are enqueued asynchronously. *gens_done (may be NULL)
+ * receives the generations run or enqueued. */
 gmpea_status gmpea_pool_tune(gmpea_pool_t pool, int32_t n_gen, int32_t *gens_done);
 
 /* The handle of a slot, for gmpea_front, gmpea_read, gmpea_write,

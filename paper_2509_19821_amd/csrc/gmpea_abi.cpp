@@ -1355,6 +1355,7 @@ struct PoolArena {
 };
 
 constexpr int kWorkClasses = 4;
+constexpr int kSchedules = 2;
 
 struct gmpea_pool_s {
   gmpea_allocator user{};
@@ -1369,16 +1370,21 @@ struct gmpea_pool_s {
   // device tables
   DevState *d_states = nullptr;
   int32_t state_cap = 0;
-  // work lists per class (see in_class) and phase
-  int2 *d_work[kWorkClasses][kPhases] = {};
-  int32_t work_cap[kWorkClasses][kPhases] = {};
-  int32_t nwork[kWorkClasses][kPhases] = {};
+  // work lists per schedule, class (see in_class) and phase; both schedules'
+  // lists are on the device, so the tuner switches schedule without a wait
+  int2 *d_work[kSchedules][kWorkClasses][kPhases] = {};
+  int32_t work_cap[kSchedules][kWorkClasses][kPhases] = {};
+  int32_t nwork[kSchedules][kWorkClasses][kPhases] = {};
   bool dirty = true;
   // launch policy (the autotuner may change both; results do not depend on them)
   int32_t schedule = 0;  // 0: instance blocks grouped per XCD, 1: linear
   int32_t chunk = 16;    // generations per graph replay
-  hipGraphExec_t gexec = nullptr;
-  int32_t gchunk = 0;
+  // graphs of `chunk` generations per (schedule, chunk), until the next rebuild
+  struct Graph {
+    int32_t schedule, chunk;
+    hipGraphExec_t exec;
+  };
+  std::vector<Graph> graphs;
 };
 
 namespace {
@@ -1548,12 +1554,14 @@ void build_work(const gmpea_pool_s *q, int phase, int schedule, int cls, std::ve
     for (int x = 0; x < kX; ++x) out.push_back(j < lane[x].size() ? lane[x][j] : make_int2(-1, -1));
 }
 
+void pool_drop_graphs(gmpea_pool_s *q) {
+  for (auto &g : q->graphs) (void)hipGraphExecDestroy(g.exec);
+  q->graphs.clear();
+}
+
 gmpea_status pool_rebuild(gmpea_pool_s *q) {
   if (!q->dirty) return GMPEA_OK;
-  if (q->gexec) {
-    (void)hipGraphExecDestroy(q->gexec);
-    q->gexec = nullptr;
-  }
+  pool_drop_graphs(q);
   gmpea_status s = sync_stream(q->stream, "pool");
   if (s != GMPEA_OK) return s;
   const int32_t ns = static_cast<int32_t>(q->slots.size());
@@ -1564,18 +1572,20 @@ gmpea_status pool_rebuild(gmpea_pool_s *q) {
     if (q->slots[k]) host[k] = q->slots[k]->st;
   hipError_t e = hipMemcpyAsync(q->d_states, host.data(), sizeof(DevState) * host.size(),
                                 hipMemcpyHostToDevice, q->stream);
-  std::vector<int2> w[kWorkClasses][kPhases];  // kept until the copies below have finished
-  for (int c = 0; c < kWorkClasses; ++c)
-    for (int ph = 0; ph < kPhases && e == hipSuccess; ++ph) {
-      build_work(q, ph, q->schedule, c, w[c][ph]);
-      s = pool_table(q, &q->d_work[c][ph], &q->work_cap[c][ph],
-                     std::max<int32_t>(1, static_cast<int32_t>(w[c][ph].size())));
-      if (s != GMPEA_OK) return s;
-      q->nwork[c][ph] = static_cast<int32_t>(w[c][ph].size());
-      if (!w[c][ph].empty())
-        e = hipMemcpyAsync(q->d_work[c][ph], w[c][ph].data(), sizeof(int2) * w[c][ph].size(),
-                           hipMemcpyHostToDevice, q->stream);
-    }
+  std::vector<int2> w[kSchedules][kWorkClasses][kPhases];  // kept until the copies below have finished
+  for (int sc = 0; sc < kSchedules; ++sc)
+    for (int c = 0; c < kWorkClasses; ++c)
+      for (int ph = 0; ph < kPhases && e == hipSuccess; ++ph) {
+        std::vector<int2> &l = w[sc][c][ph];
+        build_work(q, ph, sc, c, l);
+        s = pool_table(q, &q->d_work[sc][c][ph], &q->work_cap[sc][c][ph],
+                       std::max<int32_t>(1, static_cast<int32_t>(l.size())));
+        if (s != GMPEA_OK) return s;
+        q->nwork[sc][c][ph] = static_cast<int32_t>(l.size());
+        if (!l.empty())
+          e = hipMemcpyAsync(q->d_work[sc][c][ph], l.data(), sizeof(int2) * l.size(), hipMemcpyHostToDevice,
+                             q->stream);
+      }
   if (e == hipSuccess) e = hipStreamSynchronize(q->stream);
   if (e != hipSuccess) return hip_fail(e, "pool rebuild");
   q->dirty = false;
@@ -1583,10 +1593,11 @@ gmpea_status pool_rebuild(gmpea_pool_s *q) {
 }
 
 hipError_t pool_generation(const gmpea_pool_s *q, hipStream_t s) {
+  const int sc = q->schedule;
   for (int ph = 0; ph < kPhases; ++ph) {
     for (int c = 0; c < kWorkClasses; ++c) {
-      hipError_t e = launch_batch_phase(q->d_states, q->d_work[c][ph], q->nwork[c][ph], ph, (c & 1) != 0,
-                                        (c & 2) != 0, s);
+      hipError_t e = launch_batch_phase(q->d_states, q->d_work[sc][c][ph], q->nwork[sc][c][ph], ph,
+                                        (c & 1) != 0, (c & 2) != 0, s);
       if (e != hipSuccess) return e;
     }
   }
@@ -1596,14 +1607,14 @@ hipError_t pool_generation(const gmpea_pool_s *q, hipStream_t s) {
 gmpea_status pool_enqueue(gmpea_pool_s *q, int32_t n) {
   gmpea_status s = pool_rebuild(q);
   if (s != GMPEA_OK) return s;
-  if (q->nwork[0][1] + q->nwork[1][1] == 0) return GMPEA_OK;  // no instance (OP1 lists hold them all)
+  if (q->nwork[q->schedule][0][1] + q->nwork[q->schedule][1][1] == 0)
+    return GMPEA_OK;  // no instance (OP1 lists hold them all)
   const int32_t G = q->chunk;
   if (G >= 2 && n >= G) {
-    if (!q->gexec || q->gchunk != G) {
-      if (q->gexec) {
-        (void)hipGraphExecDestroy(q->gexec);
-        q->gexec = nullptr;
-      }
+    hipGraphExec_t exec = nullptr;
+    for (const auto &g : q->graphs)
+      if (g.schedule == q->schedule && g.chunk == G) exec = g.exec;
+    if (!exec) {
       hipStream_t cap;
       hipError_t e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
       if (e != hipSuccess) return hip_fail(e, "pool graph stream");
@@ -1613,18 +1624,15 @@ gmpea_status pool_enqueue(gmpea_pool_s *q, int32_t n) {
         hipGraph_t graph = nullptr;
         hipError_t e2 = hipStreamEndCapture(cap, &graph);
         if (e == hipSuccess) e = e2;
-        if (e == hipSuccess) e = hipGraphInstantiate(&q->gexec, graph, nullptr, nullptr, 0);
+        if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
         if (graph) (void)hipGraphDestroy(graph);
       }
       (void)hipStreamDestroy(cap);
-      if (e != hipSuccess) {
-        q->gexec = nullptr;
-        return hip_fail(e, "pool graph capture");
-      }
-      q->gchunk = G;
+      if (e != hipSuccess) return hip_fail(e, "pool graph capture");
+      q->graphs.push_back({q->schedule, G, exec});
     }
     while (n >= G) {
-      hipError_t e = hipGraphLaunch(q->gexec, q->stream);
+      hipError_t e = hipGraphLaunch(exec, q->stream);
       if (e != hipSuccess) return hip_fail(e, "pool graph launch");
       n -= G;
     }
@@ -1772,47 +1780,50 @@ gmpea_status gmpea_pool_tune(gmpea_pool_t q, int32_t n_gen, int32_t *gens_done) 
   if (n_gen < 0) return fail(GMPEA_EINVAL, "gmpea_pool_tune: n_gen < 0");
   // Each candidate (schedule, chunk) runs real generations, timed with events;
   // the fastest per generation is kept. The state advances by the generations
-  // run, whatever the choice, and results do not depend on it.
+  // run, whatever the choice, and results do not depend on it. The candidates
+  // are enqueued back to back and waited for once: both schedules' work lists
+  // are on the device and graphs stay cached per (schedule, chunk), so the host
+  // builds the next candidate's graph while the device runs the previous ones.
   // (schedule, chunk, generations timed): chunk 0 launches every generation
   // eagerly, without a graph
-  const int32_t cand[6][3] = {{0, 16, 16}, {1, 16, 16}, {0, 0, 16}, {1, 0, 16}, {0, 64, 64}, {1, 64, 64}};
-  hipEvent_t a, b;
-  if (hipEventCreate(&a) != hipSuccess) return fail(GMPEA_EHIP, "gmpea_pool_tune: event");
-  if (hipEventCreate(&b) != hipSuccess) {
-    (void)hipEventDestroy(a);
-    return fail(GMPEA_EHIP, "gmpea_pool_tune: event");
-  }
-  int32_t done = 0;
-  float best = 1e30f;
-  int32_t bs = q->schedule, bc = q->chunk;
-  gmpea_status s = GMPEA_OK;
-  for (int c = 0; c < 6 && s == GMPEA_OK; ++c) {
+  constexpr int kCand = 6;
+  const int32_t cand[kCand][3] = {{0, 16, 16}, {1, 16, 16}, {0, 0, 16}, {1, 0, 16}, {0, 64, 64}, {1, 64, 64}};
+  hipEvent_t ev[2 * kCand] = {};
+  gmpea_status s = pool_rebuild(q);
+  for (int k = 0; k < 2 * kCand && s == GMPEA_OK; ++k)
+    if (hipEventCreate(&ev[k]) != hipSuccess) s = fail(GMPEA_EHIP, "gmpea_pool_tune: event");
+  int32_t done = 0, ran = 0;
+  const int32_t s0 = q->schedule, c0 = q->chunk;
+  for (int c = 0; c < kCand && s == GMPEA_OK; ++c) {
     const int32_t gens = cand[c][2];
     if (done + 2 * gens > n_gen) break;
-    if (q->schedule != cand[c][0]) q->dirty = true;
     q->schedule = cand[c][0];
     q->chunk = cand[c][1];
-    s = pool_rebuild(q);
+    s = pool_enqueue(q, gens);  // the first half also builds the graph; time the second half
     if (s != GMPEA_OK) break;
-    s = pool_enqueue(q, gens);  // first replay also builds the graph; time the second half
-    if (s != GMPEA_OK) break;
-    (void)hipEventRecord(a, q->stream);
+    (void)hipEventRecord(ev[2 * c], q->stream);
     s = pool_enqueue(q, gens);
-    (void)hipEventRecord(b, q->stream);
+    (void)hipEventRecord(ev[2 * c + 1], q->stream);
     if (s != GMPEA_OK) break;
-    (void)hipEventSynchronize(b);
-    float ms = 0.0f;
-    (void)hipEventElapsedTime(&ms, a, b);
     done += 2 * gens;
-    if (ms / gens < best) {
-      best = ms / gens;
-      bs = cand[c][0];
-      bc = cand[c][1];
+    ran = c + 1;
+  }
+  int32_t bs = s0, bc = c0;
+  if (s == GMPEA_OK && ran > 0) {
+    if (hipEventSynchronize(ev[2 * ran - 1]) != hipSuccess) s = fail(GMPEA_EHIP, "gmpea_pool_tune: wait");
+    float best = 1e30f;
+    for (int c = 0; c < ran && s == GMPEA_OK; ++c) {
+      float ms = 0.0f;
+      (void)hipEventElapsedTime(&ms, ev[2 * c], ev[2 * c + 1]);
+      if (ms / cand[c][2] < best) {
+        best = ms / cand[c][2];
+        bs = cand[c][0];
+        bc = cand[c][1];
+      }
     }
   }
-  (void)hipEventDestroy(a);
-  (void)hipEventDestroy(b);
-  if (q->schedule != bs) q->dirty = true;
+  for (int k = 0; k < 2 * kCand; ++k)
+    if (ev[k]) (void)hipEventDestroy(ev[k]);
   q->schedule = bs;
   q->chunk = bc;
   if (s == GMPEA_OK && done < n_gen) {
@@ -1869,11 +1880,12 @@ void gmpea_pool_destroy(gmpea_pool_t q) {
   (void)hipStreamSynchronize(q->stream);
   for (auto &h : q->slots)
     if (h) gmpea_destroy(h);
-  if (q->gexec) (void)hipGraphExecDestroy(q->gexec);
+  pool_drop_graphs(q);
   if (q->d_states) pool_raw_free(q, q->d_states);
-  for (int ph = 0; ph < kPhases; ++ph)
-    for (int c = 0; c < kWorkClasses; ++c)
-      if (q->d_work[c][ph]) pool_raw_free(q, q->d_work[c][ph]);
+  for (int sc = 0; sc < kSchedules; ++sc)
+    for (int ph = 0; ph < kPhases; ++ph)
+      for (int c = 0; c < kWorkClasses; ++c)
+        if (q->d_work[sc][c][ph]) pool_raw_free(q, q->d_work[sc][c][ph]);
   pool_arena_destroy(q);
   if (q->init_stream) (void)hipStreamDestroy(q->init_stream);
   if (q->own_stream) (void)hipStreamDestroy(q->stream);

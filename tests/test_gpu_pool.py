@@ -77,6 +77,25 @@ def test_tuning_does_not_change_results(G):
         pool.close()
 
 
+def test_steps_after_tuning_and_admission(G):
+    """The tuner leaves graphs cached per (schedule, chunk); later steps replay
+    them, and an admission rebuilds the work lists and drops them."""
+    mix = _mix()[:5]
+    pool = G.Pool(8 << 30)
+    try:
+        slots = [pool.admit(p, c) for p, c in mix[:4]]
+        assert pool.tune(150) == 150
+        pool.step(40)
+        pool.release(slots[3])
+        late = pool.admit(*mix[4])
+        pool.step(33)
+        for (p, c), s in zip(mix[:3], slots[:3]):
+            _same(pool.instance(s).state(), _alone(G, p, c, 223))
+        _same(pool.instance(late).state(), _alone(G, *mix[4], 33))
+    finally:
+        pool.close()
+
+
 def test_admission_by_budget_and_release(G):
     small = ci.workload_small(0)[:2]
     medium = ci.workload_medium(0)[:2]
