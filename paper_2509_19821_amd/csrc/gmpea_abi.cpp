@@ -681,8 +681,24 @@ gmpea_status gmpea_init(const gmpea_problem *P, const gmpea_config *C, const gmp
   auto cp = [&](void *dst, const void *src, size_t bytes) {
     if (e == hipSuccess) e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, h->stream);
   };
+  // buffers to clear are collected and cleared by one launch (flush); a byte
+  // other than 0 or 0xFF, an unaligned span or a full list takes hipMemsetAsync
+  FillSpans fl{};
   auto zero = [&](void *dst, int v, size_t bytes) {
-    if (e == hipSuccess) e = hipMemsetAsync(dst, v, bytes, h->stream);
+    if (e != hipSuccess || bytes == 0) return;
+    if ((v == 0 || v == 0xFF) && (reinterpret_cast<uintptr_t>(dst) & 3u) == 0 && bytes % 4 == 0 &&
+        fl.count < kMaxFillSpans) {
+      fl.p[fl.count] = static_cast<uint32_t *>(dst);
+      fl.words[fl.count] = bytes / 4;
+      fl.value[fl.count] = v ? 0xFFFFFFFFu : 0u;
+      ++fl.count;
+    } else {
+      e = hipMemsetAsync(dst, v, bytes, h->stream);
+    }
+  };
+  auto flush = [&]() {
+    if (e == hipSuccess) e = launch_fill(fl, h->stream);
+    fl.count = 0;
   };
   cp(lb, lbf.data(), st.stride * sizeof(float));
   cp(ub, ubf.data(), st.stride * sizeof(float));
@@ -710,6 +726,7 @@ gmpea_status gmpea_init(const gmpea_problem *P, const gmpea_config *C, const gmp
   zero(st.gen, 0, 4 * sizeof(uint32_t));
   zero(st.repl, 0, 2 * kReplLanes * sizeof(unsigned long long));
   if (st.wcheck) zero(st.wcheck, 0, 8 * static_cast<size_t>(N) * sizeof(int32_t));
+  flush();
   // reference vectors and neighbourhoods: on the device for one Das-Dennis layer
   // with m <= 3, else on the host (W rounded once from FP64, rq float4 per row)
   if (dev_tables) {
@@ -766,24 +783,37 @@ gmpea_status gmpea_init(const gmpea_problem *P, const gmpea_config *C, const gmp
     }
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);  // Wf is read before it goes
   }
-  // reverse lists (the offspring buffer serves as the zeroed cursor array),
-  // into the tails carved above
-  int32_t *cursor = reinterpret_cast<int32_t *>(st.FCO[0]);
+  // reverse lists into the tails carved above. The four offspring record
+  // buffers serve as the zeroed cursor arrays (one per count and fill of each
+  // population, each holding at least 4N words), so the lists need no clearing
+  // between their launches; clear_cursors zeroes the four again afterwards, and
+  // clear_lists empties the offsets and heads (with the flags) for a rebuild.
+  int32_t *const cursor[4] = {reinterpret_cast<int32_t *>(st.FCO[0]), reinterpret_cast<int32_t *>(st.FCO[1]),
+                              reinterpret_cast<int32_t *>(st.FCN[0]), reinterpret_cast<int32_t *>(st.FCN[1])};
   auto reverse_lists = [&](const int32_t *cap) {
     for (int p = 0; p < 2; ++p) {
-      zero(cursor, 0, static_cast<size_t>(N) * sizeof(int32_t));
-      zero(const_cast<int32_t *>(st.rtoff[p]), 0, (static_cast<size_t>(N) + 1) * sizeof(int32_t));
-      zero(const_cast<int32_t *>(st.rhead[p]), 0xFF, static_cast<size_t>(N) * ts[p] * sizeof(int32_t));
       if (e == hipSuccess)
-        e = launch_reverse_count(N, ts[p], st.B[p], cursor, const_cast<int32_t *>(st.rtoff[p]), h->stream);
-      zero(cursor, 0, static_cast<size_t>(N) * sizeof(int32_t));
+        e = launch_reverse_count(N, ts[p], st.B[p], cursor[2 * p], const_cast<int32_t *>(st.rtoff[p]), h->stream);
       if (e == hipSuccess)
-        e = launch_reverse_fill(N, ts[p], st.B[p], st.rtoff[p], cursor, const_cast<int32_t *>(st.rhead[p]),
-                                const_cast<int32_t *>(st.rtail[p]), cap[p], d_flag + 1 + p, h->stream);
+        e = launch_reverse_fill(N, ts[p], st.B[p], st.rtoff[p], cursor[2 * p + 1],
+                                const_cast<int32_t *>(st.rhead[p]), const_cast<int32_t *>(st.rtail[p]), cap[p],
+                                d_flag + 1 + p, h->stream);
     }
   };
+  auto clear_cursors = [&]() {
+    for (int c = 0; c < 4; ++c) zero(cursor[c], 0, rows * st.rq * sizeof(float4));
+    flush();
+  };
+  auto clear_lists = [&]() {
+    zero(d_flag, 0, 4 * sizeof(uint32_t));
+    for (int p = 0; p < 2; ++p) {
+      zero(const_cast<int32_t *>(st.rtoff[p]), 0, (static_cast<size_t>(N) + 1) * sizeof(int32_t));
+      zero(const_cast<int32_t *>(st.rhead[p]), 0xFF, static_cast<size_t>(N) * ts[p] * sizeof(int32_t));
+    }
+    flush();
+  };
   reverse_lists(tail_cap);
-  zero(st.FCO[0], 0, rows * st.rq * sizeof(float4));
+  clear_cursors();
   if (e == hipSuccess) e = launch_init(st, h->stream);
   // one wait for everything above: the tables' and the tails' flags
   uint32_t flags[4] = {0, 0, 0, 0};
@@ -800,9 +830,9 @@ gmpea_status gmpea_init(const gmpea_problem *P, const gmpea_config *C, const gmp
                          hipMemcpyHostToDevice, h->stream);
       if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     }
-    zero(d_flag, 0, 4 * sizeof(uint32_t));
+    clear_lists();
     reverse_lists(tail_cap);
-    zero(st.FCO[0], 0, rows * st.rq * sizeof(float4));  // the cursor again
+    clear_cursors();
     if (e == hipSuccess) e = hipMemcpyAsync(flags, d_flag, sizeof(flags), hipMemcpyDeviceToHost, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   }
@@ -825,9 +855,9 @@ gmpea_status gmpea_init(const gmpea_problem *P, const gmpea_config *C, const gmp
       }
       st.rtail[0] = carve.take<int32_t>(static_cast<size_t>(tail_n[0]));
       st.rtail[1] = carve.take<int32_t>(static_cast<size_t>(tail_n[1]));
-      zero(d_flag, 0, 4 * sizeof(uint32_t));
+      clear_lists();
       reverse_lists(tail_n);
-      zero(st.FCO[0], 0, rows * st.rq * sizeof(float4));
+      clear_cursors();
       if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     }
   }

@@ -290,4 +290,17 @@ hipError_t launch_reverse_fill(int32_t n, int32_t t, const int32_t *B, const int
                                int32_t *cursor, int32_t *head, int32_t *tail, int32_t cap,
                                uint32_t *overflow, hipStream_t s);
 
+// Several device spans set to a 32-bit pattern by one launch (initialisation
+// clears about twenty buffers; one hipMemsetAsync each took a launch and an
+// API call apiece). Each span is p[k] .. p[k] + words[k] (32-bit words, p[k]
+// 4-byte aligned); spans must not overlap.
+constexpr int kMaxFillSpans = 24;
+struct FillSpans {
+  uint32_t *p[kMaxFillSpans];
+  uint64_t words[kMaxFillSpans];
+  uint32_t value[kMaxFillSpans];
+  int32_t count;
+};
+hipError_t launch_fill(const FillSpans &f, hipStream_t s);
+
 }  // namespace gmpea

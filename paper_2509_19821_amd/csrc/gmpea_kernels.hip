@@ -600,6 +600,27 @@ __global__ __launch_bounds__(kBlock) void k_hv(int64_t n, int32_t m, const float
   if (threadIdx.x == 0 && c > 0) atomicAdd(hits, static_cast<unsigned long long>(c));
 }
 
+// Spans set to 32-bit patterns: a few words up to 16-byte alignment, then
+// 16-byte stores over the body, then the remaining words; every thread of the
+// grid strides over each span in turn.
+__global__ __launch_bounds__(kBlock) void k_fill(FillSpans f) {
+  const uint64_t tid = static_cast<uint64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  const uint64_t nt = static_cast<uint64_t>(gridDim.x) * kBlock;
+  for (int k = 0; k < f.count; ++k) {
+    uint32_t *p = f.p[k];
+    const uint64_t n = f.words[k];
+    const uint32_t v = f.value[k];
+    const uint64_t lead = ((16u - (reinterpret_cast<uintptr_t>(p) & 15u)) & 15u) / 4u;
+    const uint64_t h = lead < n ? lead : n;
+    if (tid < h) p[tid] = v;
+    uint4 *p4 = reinterpret_cast<uint4 *>(p + h);
+    const uint64_t n4 = (n - h) / 4;
+    const uint4 v4 = make_uint4(v, v, v, v);
+    for (uint64_t i = tid; i < n4; i += nt) p4[i] = v4;
+    for (uint64_t i = h + 4 * n4 + tid; i < n; i += nt) p[i] = v;
+  }
+}
+
 __global__ __launch_bounds__(kBlock) void k_philox(const uint4 *ctr, int64_t n, uint32_t k0,
                                                    uint32_t k1, uint4 *out) {
   const int64_t q = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
@@ -717,6 +738,21 @@ static void launch_eval_mf(const DevState &st, hipStream_t s) {
     case 2: launch_eval_lpo<M, FAM, 2>(st, s); break;
     default: launch_eval_lpo<M, FAM, 1>(st, s); break;
   }
+}
+
+hipError_t launch_fill(const FillSpans &f, hipStream_t s) {
+  if (f.count <= 0) return hipSuccess;
+  if (f.count > kMaxFillSpans) return hipErrorInvalidValue;
+  uint64_t words = 0;
+  for (int k = 0; k < f.count; ++k) {
+    if (f.words[k] > 0 && (reinterpret_cast<uintptr_t>(f.p[k]) & 3u) != 0) return hipErrorInvalidValue;
+    words += f.words[k];
+  }
+  if (words == 0) return hipSuccess;
+  const uint64_t want = (words / 4 + kBlock - 1) / kBlock;
+  const unsigned grid = static_cast<unsigned>(want < 1 ? 1 : (want > 4096 ? 4096 : want));
+  hipLaunchKernelGGL(k_fill, dim3(grid), dim3(kBlock), 0, s, f);
+  return hipGetLastError();
 }
 
 hipError_t launch_init(const DevState &st, hipStream_t s) {
