@@ -360,7 +360,11 @@ gmpea_status gmpea_reference_set(int32_t m, int32_t h_outer, int32_t h_inner, in
  * up to 256 MiB from the allocator hook (or hipMalloc) as instances are
  * admitted, carved into blocks, and recycled when instances are released; the
  * chunks are returned only by gmpea_pool_destroy. hip_stream: the stream every
- * instance of the pool uses, or NULL for one the pool owns. */
+ * instance of the pool uses, or NULL for one the pool owns. The pool also holds
+ * a pinned host buffer (4 MiB, more for very large pools) that stages its work
+ * lists, and at creation copies it once into a transient 4 MiB device block
+ * (from the hook, if one is given) so that the copy path is set up before the
+ * first generation. */
 gmpea_status gmpea_pool_create(size_t budget_bytes, const gmpea_allocator *allocator,
                                void *hip_stream, gmpea_pool_t *out);
 

@@ -5,6 +5,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdlib>
+#include <cstring>
 #include <limits>
 #include <map>
 #include <mutex>
@@ -1415,6 +1416,10 @@ struct gmpea_pool_s {
     hipGraphExec_t exec;
   };
   std::vector<Graph> graphs;
+  // pinned staging of the state array and work lists: their uploads are then
+  // asynchronous, and the stream is idle whenever a rebuild refills it
+  char *stage = nullptr;
+  size_t stage_cap = 0;
 };
 
 namespace {
@@ -1591,32 +1596,53 @@ void pool_drop_graphs(gmpea_pool_s *q) {
 
 gmpea_status pool_rebuild(gmpea_pool_s *q) {
   if (!q->dirty) return GMPEA_OK;
+  Trace trace("pool_rebuild");
   pool_drop_graphs(q);
   gmpea_status s = sync_stream(q->stream, "pool");
   if (s != GMPEA_OK) return s;
   const int32_t ns = static_cast<int32_t>(q->slots.size());
   s = pool_table(q, &q->d_states, &q->state_cap, std::max(ns, 1));
   if (s != GMPEA_OK) return s;
-  std::vector<DevState> host(static_cast<size_t>(std::max(ns, 1)));
-  for (int32_t k = 0; k < ns; ++k)
-    if (q->slots[k]) host[k] = q->slots[k]->st;
-  hipError_t e = hipMemcpyAsync(q->d_states, host.data(), sizeof(DevState) * host.size(),
-                                hipMemcpyHostToDevice, q->stream);
-  std::vector<int2> w[kSchedules][kWorkClasses][kPhases];  // kept until the copies below have finished
+  const size_t nst = static_cast<size_t>(std::max(ns, 1));
+  std::vector<int2> w[kSchedules][kWorkClasses][kPhases];
+  size_t bytes = sizeof(DevState) * nst;
   for (int sc = 0; sc < kSchedules; ++sc)
     for (int c = 0; c < kWorkClasses; ++c)
-      for (int ph = 0; ph < kPhases && e == hipSuccess; ++ph) {
+      for (int ph = 0; ph < kPhases; ++ph) {
         std::vector<int2> &l = w[sc][c][ph];
         build_work(q, ph, sc, c, l);
         s = pool_table(q, &q->d_work[sc][c][ph], &q->work_cap[sc][c][ph],
                        std::max<int32_t>(1, static_cast<int32_t>(l.size())));
         if (s != GMPEA_OK) return s;
         q->nwork[sc][c][ph] = static_cast<int32_t>(l.size());
-        if (!l.empty())
-          e = hipMemcpyAsync(q->d_work[sc][c][ph], l.data(), sizeof(int2) * l.size(), hipMemcpyHostToDevice,
-                             q->stream);
+        bytes += sizeof(int2) * l.size();
       }
-  if (e == hipSuccess) e = hipStreamSynchronize(q->stream);
+  if (bytes > q->stage_cap) {  // the stream is idle (synchronised above)
+    const size_t cap = std::max(bytes, 2 * q->stage_cap) + (size_t(1) << 16);
+    if (q->stage) (void)hipHostFree(q->stage);
+    q->stage = nullptr;
+    q->stage_cap = 0;
+    if (hipHostMalloc(reinterpret_cast<void **>(&q->stage), cap, hipHostMallocDefault) != hipSuccess) {
+      q->stage = nullptr;
+      return fail(GMPEA_ENOMEM, "pool rebuild: pinned staging");
+    }
+    q->stage_cap = cap;
+  }
+  // stage everything, then upload in stream order ahead of the next generations
+  size_t off = sizeof(DevState) * nst;
+  DevState *hs = reinterpret_cast<DevState *>(q->stage);
+  for (size_t k = 0; k < nst; ++k) hs[k] = (static_cast<int32_t>(k) < ns && q->slots[k]) ? q->slots[k]->st : DevState{};
+  hipError_t e = hipMemcpyAsync(q->d_states, hs, sizeof(DevState) * nst, hipMemcpyHostToDevice, q->stream);
+  for (int sc = 0; sc < kSchedules; ++sc)
+    for (int c = 0; c < kWorkClasses; ++c)
+      for (int ph = 0; ph < kPhases && e == hipSuccess; ++ph) {
+        const std::vector<int2> &l = w[sc][c][ph];
+        if (l.empty()) continue;
+        std::memcpy(q->stage + off, l.data(), sizeof(int2) * l.size());
+        e = hipMemcpyAsync(q->d_work[sc][c][ph], q->stage + off, sizeof(int2) * l.size(), hipMemcpyHostToDevice,
+                           q->stream);
+        off += sizeof(int2) * l.size();
+      }
   if (e != hipSuccess) return hip_fail(e, "pool rebuild");
   q->dirty = false;
   return GMPEA_OK;
@@ -1645,6 +1671,7 @@ gmpea_status pool_enqueue(gmpea_pool_s *q, int32_t n) {
     for (const auto &g : q->graphs)
       if (g.schedule == q->schedule && g.chunk == G) exec = g.exec;
     if (!exec) {
+      Trace trace("pool_graph_capture");
       hipStream_t cap;
       hipError_t e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
       if (e != hipSuccess) return hip_fail(e, "pool graph stream");
@@ -1763,6 +1790,25 @@ gmpea_status gmpea_pool_create(size_t budget_bytes, const gmpea_allocator *A, vo
       return hip_fail(e, "gmpea_pool_create: stream");
     }
   }
+  // Pinned staging for the work-list uploads, and one upload from it now: the
+  // first large host-to-device copy in a process took about 7 ms of set-up
+  // (measured; copies after it took microseconds), which belongs to the
+  // pool's creation rather than to its first batched generations. A failure
+  // here only leaves the staging to the first rebuild.
+  {
+    constexpr size_t kStage = size_t(4) << 20;
+    if (hipHostMalloc(reinterpret_cast<void **>(&q->stage), kStage, hipHostMallocDefault) == hipSuccess) {
+      q->stage_cap = kStage;
+      std::memset(q->stage, 0, kStage);
+      if (void *d = pool_chunk_alloc(q, kStage)) {
+        if (hipMemcpyAsync(d, q->stage, kStage, hipMemcpyHostToDevice, q->stream) == hipSuccess)
+          (void)hipStreamSynchronize(q->stream);
+        pool_chunk_free(q, d);
+      }
+    } else {
+      q->stage = nullptr;
+    }
+  }
   {
     std::lock_guard<std::mutex> lk(g_pool_mu);
     g_pools.insert(q);
@@ -1815,9 +1861,9 @@ gmpea_status gmpea_pool_tune(gmpea_pool_t q, int32_t n_gen, int32_t *gens_done) 
   // are on the device and graphs stay cached per (schedule, chunk), so the host
   // builds the next candidate's graph while the device runs the previous ones.
   // (schedule, chunk, generations timed): chunk 0 launches every generation
-  // eagerly, without a graph
+  // eagerly, without a graph; those come first, so the device starts at once
   constexpr int kCand = 6;
-  const int32_t cand[kCand][3] = {{0, 16, 16}, {1, 16, 16}, {0, 0, 16}, {1, 0, 16}, {0, 64, 64}, {1, 64, 64}};
+  const int32_t cand[kCand][3] = {{0, 0, 16}, {1, 0, 16}, {0, 16, 16}, {1, 16, 16}, {0, 64, 64}, {1, 64, 64}};
   hipEvent_t ev[2 * kCand] = {};
   gmpea_status s = pool_rebuild(q);
   for (int k = 0; k < 2 * kCand && s == GMPEA_OK; ++k)
@@ -1911,6 +1957,7 @@ void gmpea_pool_destroy(gmpea_pool_t q) {
   for (auto &h : q->slots)
     if (h) gmpea_destroy(h);
   pool_drop_graphs(q);
+  if (q->stage) (void)hipHostFree(q->stage);
   if (q->d_states) pool_raw_free(q, q->d_states);
   for (int sc = 0; sc < kSchedules; ++sc)
     for (int ph = 0; ph < kPhases; ++ph)
