@@ -225,7 +225,7 @@ def batched_vs_plain(g, ci, count=256, gens=300):
             "speedup": round(plain_s / batched_s, 2),
             "batched_offspring_per_s": round(offspring / batched_s, 1),
             "final_fronts_identical": bool(same), "device_bytes": int(q["used_bytes"]),
-            "schedule": "xcd-grouped" if q["schedule"] == 0 else "linear",
+            "schedule": "xcd-grouped op1/select" if q["schedule"] == 0 else "linear",
             "graph_chunk": q["chunk"]}
 
 

@@ -396,7 +396,8 @@ gmpea_status gmpea_pool_handle(gmpea_pool_t pool, int32_t slot, gmpea_t *handle)
 gmpea_status gmpea_pool_release(gmpea_pool_t pool, int32_t slot);
 
 /* Active instances, device bytes in use and the budget, and the launch policy
- * (schedule 0: grouped per XCD, 1: in order; graph chunk length). Any output
+ * (schedule 0: OP1 and selection blocks grouped per XCD, variation blocks
+ * in order; 1: every phase in order; graph chunk length). Any output
  * may be NULL. */
 gmpea_status gmpea_pool_query(gmpea_pool_t pool, int32_t *active, size_t *used_bytes,
                               size_t *budget_bytes, int32_t *schedule, int32_t *chunk);

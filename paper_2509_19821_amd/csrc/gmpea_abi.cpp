@@ -1538,10 +1538,13 @@ int32_t phase_blocks(const DevState &st, int phase) {
   return st.sel_blocks0 + st.sel_blocks1;
 }
 
-// Work list of one phase. Schedule 0 keeps each instance's consecutive blocks
-// on one XCD (instances placed largest first on the least-loaded XCD, large
-// ones split into contiguous runs) so neighbouring subproblems share an L2;
-// the hardware deals block b to XCD b mod 8, hence the interleaving at the end.
+// Work list of one phase. Schedule 0 keeps each instance's consecutive OP1 and
+// selection blocks on one XCD (instances placed largest first on the
+// least-loaded XCD, large ones split into contiguous runs) so neighbouring
+// subproblems share an L2; the hardware deals block b to XCD b mod 8, hence
+// the interleaving at the end. Its variation blocks go in plain order (the
+// variation is bound by VALU issue, and measured about 1 % faster so), as do
+// every phase's blocks under schedule 1.
 // Work-list classes of a pool: bit 0 records of m > 3 (kernels of their own),
 // bit 1 the task-dealt variation. The OP1 and selection phases split by m only.
 bool in_class(const DevState &st, int phase, int cls) {
@@ -1559,7 +1562,7 @@ void build_work(const gmpea_pool_s *q, int phase, int schedule, int cls, std::ve
       inst.emplace_back(phase_blocks(q->slots[s]->st, phase), s);
       total += inst.back().first;
     }
-  if (schedule == 1) {
+  if (schedule == 1 || phase == 0) {
     for (auto &e : inst)
       for (int32_t b = 0; b < e.first; ++b) out.push_back(make_int2(e.second, b));
     return;
