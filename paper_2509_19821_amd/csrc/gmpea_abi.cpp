@@ -1545,11 +1545,13 @@ int32_t phase_blocks(const DevState &st, int phase) {
 // the interleaving at the end. Its variation blocks go in plain order (the
 // variation is bound by VALU issue, and measured about 1 % faster so), as do
 // every phase's blocks under schedule 1.
-// Work-list classes of a pool: bit 0 records of m > 3 (kernels of their own),
-// bit 1 the task-dealt variation. The OP1 and selection phases split by m only.
+// Work-list classes of a pool: bit 0 records of m > 3 (kernels of their own);
+// bit 1 the task-dealt variation in phase 0, and m = 2 in the selection phase
+// (a selection kernel per m for m <= 3). OP1 splits at m > 3 only.
 bool in_class(const DevState &st, int phase, int cls) {
   const int wide = st.m > 3 ? 1 : 0, tasked = st.tasked ? 1 : 0;
   if (phase == 0) return cls == (wide | (tasked << 1));
+  if (phase == 2) return cls == (wide | (!wide && st.m == 2 ? 2 : 0));
   return cls == wide;
 }
 

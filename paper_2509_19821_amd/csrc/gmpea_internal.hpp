@@ -195,11 +195,12 @@ hipError_t launch_materialize(const DevState &st, hipStream_t s);
 hipError_t launch_generation(const DevState &st, hipStream_t s);
 // One phase of a batched generation over a pool: work[b] = (instance, block).
 // wide: the work list holds instances with m > 3 (their kernels are separate so
-// that the m <= 3 kernels keep their register budget). tasked: the work list
-// holds instances of the task-dealt variation (phase 0 only; a pool keeps one
-// work list per kernel).
+// that the m <= 3 kernels keep their register budget). sub: in phase 0, the
+// work list holds instances of the task-dealt variation; in phase 2 with m <= 3,
+// instances with m = 2 (the selection has a kernel per m); unused otherwise. A
+// pool keeps one work list per kernel.
 hipError_t launch_batch_phase(const DevState *states, const int2 *work, int nwork, int phase,
-                              bool wide, bool tasked, hipStream_t s);
+                              bool wide, bool sub, hipStream_t s);
 // The m > 3 launchers (gmpea_kernels_wide.hip).
 hipError_t launch_init_eval_wide(const DevState &st, hipStream_t s);
 hipError_t launch_phase_wide(const DevState &st, int phase, hipStream_t s);

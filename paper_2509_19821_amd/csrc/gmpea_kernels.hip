@@ -374,15 +374,15 @@ __global__ __launch_bounds__(kBlock) void k_op1_batch(const DevState *__restrict
     op1_body<3>(st, wi.y);
 }
 
+// One kernel per m: each holds only its own registers (m = 2 fits eight waves
+// per SIMD, a kernel holding both m kept seven), at one more launch per
+// generation when a pool mixes m = 2 and m = 3.
+template <int M>
 __global__ __launch_bounds__(kBlock) void k_select_batch(const DevState *__restrict__ S,
                                                         const int2 *__restrict__ work) {
   const int2 wi = work[blockIdx.x];
   if (wi.x < 0) return;
-  const DevState &st = S[wi.x];
-  if (st.m == 2)
-    select_body<2>(st, wi.y);
-  else
-    select_body<3>(st, wi.y);
+  select_body<M>(S[wi.x], wi.y);
 }
 
 // Rows idx[0 .. count) of population `pop`: decision vectors to x (count x d)
@@ -804,17 +804,19 @@ hipError_t launch_phase(const DevState &st, int phase, hipStream_t s) {
 }
 
 hipError_t launch_batch_phase(const DevState *states, const int2 *work, int nwork, int phase,
-                              bool wide, bool tasked, hipStream_t s) {
+                              bool wide, bool sub, hipStream_t s) {
   if (nwork <= 0) return hipSuccess;
-  if (wide) return launch_batch_phase_wide(states, work, nwork, phase, tasked, s);
-  if (phase == 0 && tasked)
+  if (wide) return launch_batch_phase_wide(states, work, nwork, phase, sub, s);
+  if (phase == 0 && sub)
     hipLaunchKernelGGL(k_tvary_batch, dim3(nwork), dim3(kBlock), 0, s, states, work);
   else if (phase == 0)
     hipLaunchKernelGGL(k_vary_batch, dim3(nwork), dim3(kBlock), 0, s, states, work);
   else if (phase == 1)
     hipLaunchKernelGGL(k_op1_batch, dim3(nwork), dim3(kBlock), 0, s, states, work);
+  else if (sub)
+    hipLaunchKernelGGL(k_select_batch<2>, dim3(nwork), dim3(kBlock), 0, s, states, work);
   else
-    hipLaunchKernelGGL(k_select_batch, dim3(nwork), dim3(kBlock), 0, s, states, work);
+    hipLaunchKernelGGL(k_select_batch<3>, dim3(nwork), dim3(kBlock), 0, s, states, work);
   return hipGetLastError();
 }
 
